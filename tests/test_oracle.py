@@ -1,0 +1,409 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Nothing here compares the oracle with itself: each test checks it against a
+printed value (Example 1), a second construction (numpy library routines,
+the paper's own walk, itertools enumeration), a closed form, or an invariant
+the paper states.
+"""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import pmp_inputs as gi
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "example1.json")
+
+
+@pytest.fixture(scope="module")
+def ex1():
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+# ---------------------------------------------------------------- Example 1
+def test_example1_full_tables_match_print(ex1):
+    d = np.array(ex1["C"], np.int32)
+    pi, de, _ = oracle.tables(d, ex1["p"], ncols=ex1["m"])
+    assert (pi + 1).tolist() == ex1["Pi"]
+    assert de.tolist() == ex1["Delta"]
+
+
+def test_example1_truncated_tables_match_print(ex1):
+    d = np.array(ex1["C"], np.int32)
+    pi, de, ds = oracle.tables(d, ex1["p"])
+    assert (pi + 1).tolist() == ex1["Pi_truncated"]
+    assert de.tolist() == ex1["Delta_truncated"]
+    assert pi.size == ex1["entries"] == ex1["n"] * (ex1["m"] - ex1["p"] + 1)
+    assert (np.cumsum(de, axis=1) == ds).all()
+
+
+def _poly(terms, closed):
+    total = 0
+    for coef, mono in terms:
+        total += coef * all(j in closed for j in mono)
+    return total
+
+
+def test_example1_objective_equals_printed_polynomial(ex1):
+    d = np.array(ex1["C"], np.int32)
+    m, p = ex1["m"], ex1["p"]
+    pi, de, _ = oracle.tables(d, p)
+    for open_set in itertools.combinations(range(m), p):
+        closed = {j + 1 for j in range(m) if j not in open_set}
+        want = _poly(ex1["reduced_polynomial"]["terms"], closed)
+        mask = gi.pack_masks([list(open_set)], m)
+        assert oracle.objective(d, mask, p)[0] == want
+        assert oracle.bc_eval(pi, de, mask, m)[0][0] == want
+
+
+def test_example1_optimum(ex1):
+    d = np.array(ex1["C"], np.int32)
+    cost, mask, count = oracle.exhaustive(d, ex1["p"])
+    # least value of the printed polynomial over the six open pairs: {1,4}
+    vals = {}
+    for s in itertools.combinations(range(ex1["m"]), ex1["p"]):
+        closed = {j + 1 for j in range(ex1["m"]) if j not in s}
+        vals[s] = _poly(ex1["reduced_polynomial"]["terms"], closed)
+    assert cost == min(vals.values()) == 35
+    assert count == math.comb(ex1["m"], ex1["p"])
+    assert gi.unpack_masks(mask[None, :], ex1["m"])[0].nonzero()[0].tolist() == [0, 3]
+
+
+# ------------------------------------------------------------------- tables
+@pytest.mark.parametrize("kind,n,m,p,seed", [
+    ("graph", 60, 60, 7, 1), ("graph", 100, 100, 5, 2), ("euclid", 80, 80, 9, 3),
+    ("rect", 37, 150, 20, 4), ("ties", 50, 70, 3, 5)])
+def test_tables_match_numpy_stable_argsort(kind, n, m, p, seed):
+    d = _instance(kind, n, m, seed)
+    a = oracle.tables(d, p)
+    b = oracle.tables_numpy(d, p)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+
+
+def _instance(kind, n, m, seed):
+    if kind == "graph":
+        return gi.graph_instance(n, 2 * n, seed)
+    if kind == "euclid":
+        return gi.euclid_instance(n, seed)
+    rng = np.random.default_rng(seed)
+    if kind == "ties":
+        return rng.integers(0, 4, size=(n, m)).astype(np.int32)
+    return rng.integers(0, 1000, size=(n, m)).astype(np.int32)
+
+
+def test_tables_invariants():
+    d = gi.graph_instance(90, 180, 7)
+    n, m = d.shape
+    pi, de, ds = oracle.tables(d, 1, ncols=m)
+    assert (de[:, 1:] >= 0).all()
+    for row in pi:
+        assert len(set(row.tolist())) == m
+    # the gaps of a full row telescope to the row's largest distance
+    assert (de.sum(axis=1) == d.max(axis=1)).all()
+    assert (ds == np.take_along_axis(d, pi, axis=1)).all()
+
+
+# ------------------------------------------------ objective vs paper's walk
+@pytest.mark.parametrize("kind,n,m,p,seed", [
+    ("graph", 100, 100, 5, 0), ("graph", 120, 120, 30, 1), ("euclid", 90, 90, 10, 2),
+    ("rect", 40, 130, 64, 3), ("ties", 60, 65, 1, 4), ("ties", 30, 64, 63, 5)])
+def test_identity_direct_min_equals_bc(kind, n, m, p, seed):
+    """Eq. (4)-(6): B_C(z) = f_C(x); also the scan lengths agree."""
+    d = _instance(kind, n, m, seed)
+    masks = gi.random_population(40, m, p, seed)
+    pi, de, _ = oracle.tables(d, p)
+    c1, s1 = oracle.objective(d, masks, p, scan=True)
+    c2, s2 = oracle.bc_eval(pi, de, masks, m)
+    np.testing.assert_array_equal(c1, c2)
+    np.testing.assert_array_equal(s1, s2)
+    assert (s1 >= n).all() and (s1 <= n * (m - p + 1)).all()
+
+
+def test_truncation_is_exact():
+    """Terms past column m-p+1 vanish when p facilities are open."""
+    d = gi.euclid_instance(70, 11)
+    m, p = 70, 12
+    masks = gi.random_population(50, m, p, 11)
+    full = oracle.tables(d, p, ncols=m)
+    trunc = oracle.tables(d, p)
+    a, _ = oracle.bc_eval(full[0], full[1], masks, m)
+    b, _ = oracle.bc_eval(trunc[0], trunc[1], masks, m)
+    np.testing.assert_array_equal(a, b)
+
+
+def test_truncated_walk_overruns_with_fewer_than_p_open():
+    d = gi.euclid_instance(30, 1)
+    m, p = 30, 6
+    pi, de, _ = oracle.tables(d, p)
+    # one open facility, the farthest one of client 0: its truncated row
+    # never reaches it
+    full_pi, _, _ = oracle.tables(d, p, ncols=m)
+    j = int(full_pi[0, -1])
+    mask = gi.pack_masks([[j]], m)
+    with pytest.raises(oracle.OracleError):
+        oracle.bc_eval(pi, de, mask, m)
+    with pytest.raises(oracle.OracleError):
+        oracle.objective(d, mask, p)
+
+
+def test_expected_scan_length_closed_form():
+    """For a uniform p-subset the serving facility's position is the least
+    of p uniform positions among m: E[s*] = (m+1)/(p+1)."""
+    m, p, n, P = 400, 19, 400, 200
+    d = gi.euclid_instance(n, 21)
+    masks = gi.random_population(P, m, p, 21)
+    _, st = oracle.objective(d, masks, p, scan=True)
+    mean = st.sum() / (n * P)
+    expect = (m + 1) / (p + 1)
+    # std of one s* is about expect; n*P samples, though clients correlate
+    assert abs(mean - expect) < 0.05 * expect
+
+
+# --------------------------------------------------------------- exhaustive
+@pytest.mark.parametrize("n,m,p,seed", [(9, 9, 3, 0), (12, 10, 4, 1), (7, 11, 1, 2),
+                                        (8, 9, 8, 3)])
+def test_exhaustive_matches_itertools(n, m, p, seed):
+    rng = np.random.default_rng(seed)
+    d = rng.integers(0, 9, size=(n, m)).astype(np.int32)
+    best, mask, count = oracle.exhaustive(d, p)
+    costs = []
+    for s in itertools.combinations(range(m), p):
+        costs.append(int(d[:, list(s)].min(axis=1).sum()))
+    assert count == len(costs) == math.comb(m, p)
+    assert best == min(costs)
+    first = list(itertools.combinations(range(m), p))[int(np.argmin(costs))]
+    assert gi.unpack_masks(mask[None, :], m)[0].nonzero()[0].tolist() == list(first)
+
+
+def test_exhaustive_g20_is_min_of_all_subsets():
+    d = gi.graph_instance(20, 40, 0)
+    best, mask, count = oracle.exhaustive(d, 4)
+    allsets = gi.pack_masks([list(s) for s in itertools.combinations(range(20), 4)], 20)
+    costs = oracle.objective(d, allsets, 4)
+    assert count == 4845 == len(costs)
+    assert best == costs.min()
+
+
+# ------------------------------------------------------------------- Philox
+def _numpy_block(ctr, key):
+    """numpy's Philox advances the counter before its first block."""
+    c = int(ctr[0]) | (int(ctr[1]) << 64) | (int(ctr[2]) << 128) | (int(ctr[3]) << 192)
+    c = (c - 1) % (1 << 256)
+    words = [(c >> (64 * k)) & ((1 << 64) - 1) for k in range(4)]
+    # uint64 arrays: numpy converts Python-int lists through float
+    g = np.random.Philox(counter=np.array(words, dtype=np.uint64),
+                         key=np.array([int(key[0]), int(key[1])], dtype=np.uint64))
+    return g.random_raw(4).astype(np.uint64)
+
+
+def test_philox_matches_numpy():
+    rng = np.random.default_rng(5)
+    for _ in range(50):
+        ctr = rng.integers(0, 2**63, size=4, dtype=np.uint64) * 2 + rng.integers(0, 2, 4).astype(np.uint64)
+        key = rng.integers(0, 2**63, size=2, dtype=np.uint64)
+        np.testing.assert_array_equal(oracle.philox(ctr, key), _numpy_block(ctr, key))
+    for ctr in ([0, 0, 0, 0], [1, 0, 0, 0], [0, 1, 0, 0], [2**64 - 1, 0, 5, 0]):
+        key = [123, 456]
+        np.testing.assert_array_equal(oracle.philox(ctr, key), _numpy_block(ctr, key))
+
+
+def test_philox_known_answer_zero():
+    """Published known-answer vector of Philox4x64-10 for counter 0, key 0."""
+    want = [0x16554d9eca36314c, 0xdb20fe9d672d0fdc, 0xd7e772cee186176b, 0x7e68b68aec7ba23b]
+    assert [int(x) for x in oracle.philox([0] * 4, [0, 0])] == want
+
+
+def test_stream_layout_and_bounded_draws():
+    """A stream is blocks 0,1,2,... of counter (gen, chrom, tag<<32|stage, k);
+    a bounded draw below r is the high word of x*r when no rejection."""
+    seed, role, gen, chrom, tag, stage = 77, 2, 3, 9, 2, 4
+    raw = oracle.stream_draws(seed, role, gen, chrom, tag, stage, [0] * 12)
+    expect = np.concatenate([
+        _numpy_block([gen, chrom, (tag << 32) | stage, k], [seed, role]) for k in range(3)])
+    np.testing.assert_array_equal(raw, expect)
+    bounds = [2, 3, 10, 1000, 2**31 + 11, 2**40 + 3]
+    got = oracle.stream_draws(seed, role, gen, chrom, tag, stage, bounds)
+    for x, r, v in zip(raw, bounds, got):
+        prod = int(x) * r
+        assert (prod & ((1 << 64) - 1)) >= (2**64 - r) % r  # no rejection here
+        assert int(v) == prod >> 64
+
+
+def test_bounded_draws_uniform():
+    counts = np.zeros(7, np.int64)
+    for chrom in range(300):
+        v = oracle.stream_draws(1, 2, 0, chrom, 3, 0, [7] * 40)
+        counts += np.bincount(v.astype(np.int64), minlength=7)
+    exp = counts.sum() / 7
+    chi2 = ((counts - exp) ** 2 / exp).sum()
+    assert chi2 < 30  # 6 dof; p ~ 4e-5
+
+
+# ----------------------------------------------------------- GA operators
+def test_subset_sampler_uniform_and_exact_p():
+    m, p = 6, 3
+    seen = {}
+    for c in range(6000):
+        mask = oracle.sample_subset(11, 0, c, m, p)
+        s = tuple(gi.unpack_masks(mask[None, :], m)[0].nonzero()[0].tolist())
+        assert len(s) == p
+        seen[s] = seen.get(s, 0) + 1
+    assert len(seen) == math.comb(m, p)
+    counts = np.array(list(seen.values()))
+    exp = counts.sum() / len(counts)
+    assert ((counts - exp) ** 2 / exp).sum() < 60  # 19 dof
+
+
+def test_subset_sampler_large():
+    m, p = 900, 90
+    for c in range(20):
+        mask = oracle.sample_subset(3, 5, c, m, p)
+        assert gi.unpack_masks(mask[None, :], m).sum() == p
+
+
+def test_crossover_invariants():
+    rng = np.random.default_rng(0)
+    for trial in range(300):
+        m = int(rng.integers(2, 200))
+        p = int(rng.integers(1, m))
+        A = gi.random_population(1, m, p, 1000 + trial)[0]
+        B = gi.random_population(1, m, p, 5000 + trial)[0]
+        a = gi.unpack_masks(A[None], m)[0]
+        b = gi.unpack_masks(B[None], m)[0]
+        h = int((a & ~b).sum())
+        i = int(rng.integers(1, max(p // 2, 1) + 1))
+        r1 = int(rng.integers(0, m))
+        okA, FA = oracle.crossover(A, B, m, r1, i)
+        okB, FB = oracle.crossover(B, A, m, r1, i)
+        assert okA == okB == (h >= i)
+        if not okA:
+            continue
+        fa = gi.unpack_masks(FA[None], m)[0]
+        fb = gi.unpack_masks(FB[None], m)[0]
+        assert fa.sum() == p and fb.sum() == p
+        assert ((fa ^ a).sum()) == 2 * i
+        # the two offspring exchange the same genes
+        np.testing.assert_array_equal(fa ^ fb, a ^ b)
+        np.testing.assert_array_equal(fa.astype(int) + fb, a.astype(int) + b)
+        # changes happen only where the parents differ
+        assert not ((fa ^ a) & ~(a ^ b)).any()
+
+
+def test_crossover_takes_first_positions_from_r1():
+    # m = 10, p = 6 (the sizes of Figure 1), exchange i = 1 from r1 = 7
+    m = 10
+    A = gi.pack_masks([[0, 1, 2, 3, 4, 5]], m)[0]
+    B = gi.pack_masks([[0, 1, 6, 7, 8, 9]], m)[0]
+    ok, F = oracle.crossover(A, B, m, 7, 1)
+    # walking 7, 8, 9, 0, ...: position 7 is the first 0->1, then 2 (after
+    # wrapping past 9, 0, 1 which agree or are of the other kind) is 1->0
+    assert ok
+    assert gi.unpack_masks(F[None], m)[0].nonzero()[0].tolist() == [0, 1, 3, 4, 5, 7]
+
+
+def test_mutation_is_numpy_roll():
+    rng = np.random.default_rng(1)
+    kinds = set()
+    for trial in range(400):
+        m = int(rng.integers(2, 300))
+        p = int(rng.integers(1, m))
+        A = gi.random_population(1, m, p, trial)[0]
+        F, (typ, dirn, a, b, s) = oracle.mutate(9, 2, trial, trial % 5, A, m)
+        x = gi.unpack_masks(A[None], m)[0]
+        f = gi.unpack_masks(F[None], m)[0]
+        shift = s if dirn == 0 else -s
+        if typ == 0:
+            assert 1 <= s <= m - 1
+            np.testing.assert_array_equal(f, np.roll(x, shift))
+        else:
+            assert 0 <= a < b < m and 1 <= s <= b - a
+            y = x.copy()
+            y[a:b + 1] = np.roll(x[a:b + 1], shift)
+            np.testing.assert_array_equal(f, y)
+        kinds.add((typ, dirn))
+        assert f.sum() == p
+    assert kinds == {(0, 0), (0, 1), (1, 0), (1, 1)}
+
+
+# ----------------------------------------------------------------- the GA
+def test_ga_invariants_and_resume():
+    d = gi.graph_instance(100, 200, 3)
+    n, m, p = 100, 100, 5
+    a = oracle.GaState(n, m, p, 64, 16, 12, seed=5)
+    tr = oracle.ga_run(d, a, 12)
+    assert a.done and a.generation == 12
+    assert (np.diff(tr) <= 0).all()
+    bits = gi.unpack_masks(a.pop, m)
+    assert (bits.sum(axis=1) == p).all()
+    np.testing.assert_array_equal(oracle.objective(d, a.pop, p), a.fit)
+    assert oracle.objective(d, a.best_mask[None], p)[0] == a.best_cost == tr[-1]
+    np.testing.assert_array_equal(oracle.objective(d, a.gbest_mask, p), a.gbest_cost)
+    assert a.best_cost == a.gbest_cost.min()
+    # checkpoint/resume: 5 + 7 generations reproduce 12 straight
+    b = oracle.GaState(n, m, p, 64, 16, 12, seed=5)
+    oracle.ga_run(d, b, 5)
+    oracle.ga_run(d, b, 7)
+    np.testing.assert_array_equal(a.pop, b.pop)
+    np.testing.assert_array_equal(a.state, b.state)
+    # results do not depend on the thread count
+    c = oracle.GaState(n, m, p, 64, 16, 12, seed=5)
+    oracle.ga_run(d, c, 12, threads=1)
+    np.testing.assert_array_equal(a.pop, c.pop)
+
+
+def test_ga_saturation_stop_and_optimum_bound():
+    d = gi.graph_instance(20, 40, 0)
+    opt, _, _ = oracle.exhaustive(d, 4)
+    st = oracle.GaState(20, 20, 4, 32, 8, 1000, seed=1, saturation=5)
+    tr = oracle.ga_run(d, st, 1000)
+    assert st.done and st.generation < 1000
+    assert st.state[oracle.ST_SAT] == 5
+    assert st.best_cost >= opt
+    # with 32 chromosomes improved by crossover and mutation over several
+    # generations, a 4845-set space is searched to its optimum
+    assert st.best_cost == opt
+
+
+# ------------------------------------------------------------- generators
+def test_euclid_rounding_exact():
+    d = gi.euclid_instance(300, 4)
+    rng = np.random.default_rng([0x6575636C, 4, 300, 10_000])
+    pts = rng.integers(0, 10_000, size=(300, 2), dtype=np.int64)
+    for i, j in np.random.default_rng(0).integers(0, 300, size=(500, 2)):
+        s = int(((pts[i] - pts[j]) ** 2).sum())
+        r = math.isqrt(s)
+        want = r + 1 if (s - r * r) > r else r  # round half up; no exact .5 for ints
+        assert abs(math.sqrt(s) - want) <= 0.5
+        assert d[i, j] == want
+    assert (d == d.T).all() and (np.diag(d) == 0).all()
+
+
+def test_graph_generator_metric():
+    from scipy.sparse.csgraph import floyd_warshall
+    d = gi.graph_instance(60, 120, 9)
+    assert (d == d.T).all() and (np.diag(d) == 0).all() and (d[~np.eye(60, dtype=bool)] > 0).all()
+    # triangle inequality through every intermediate vertex k
+    for k in range(60):
+        assert (d <= d[:, [k]] + d[[k], :]).all()
+    # shortest paths through Floyd-Warshall agree with the generator's solver
+    rng = np.random.default_rng([0x6772617068, 9, 60, 120])
+    e, w = gi._graph_edges(60, 120, rng, 1, 100)
+    adj = np.full((60, 60), np.inf)
+    for (a, b), x in zip(e, w):
+        adj[a, b] = adj[b, a] = x
+    np.fill_diagonal(adj, 0)
+    fw = floyd_warshall(adj, directed=False)
+    np.testing.assert_array_equal(fw.astype(np.int64), d)
+
+
+def test_pack_roundtrip():
+    rng = np.random.default_rng(2)
+    for m in (1, 63, 64, 65, 200):
+        bits = rng.integers(0, 2, size=(5, m)).astype(bool)
+        np.testing.assert_array_equal(gi.unpack_masks(gi.pack_masks(bits, m), m), bits)
