@@ -1,0 +1,230 @@
+/*
+ * pmp.h - C ABI of the MI355X (gfx950) p-median hot path.
+ *
+ * Method: AlBdaiwi & AboElFotoh, "A GPU-Based Genetic Algorithm for the
+ * P-Median Problem" (arXiv 1610.10061).  An instance is an n x m matrix of
+ * non-negative distances d_ij between client i and facility j and an integer
+ * 0 < p < m (Section 1, Eq. (1)-(3)).  A chromosome is m bits, bit j set when
+ * facility j is open (Section 4.1).
+ *
+ * Conventions for every entry point
+ *  - Indices are 0-based (the paper's are 1-based).
+ *  - Every call returns a pmp_status; nothing throws across the ABI.  On
+ *    failure pmp_last_error() gives a thread-local message.
+ *  - Chromosome masks are P x W little-endian uint64 words, W = ceil(m/64),
+ *    row-major; bit j of word j/64 is facility j; bits at positions >= m
+ *    must be zero.
+ *  - Flags: PMP_ON_DEVICE says pointer arguments are device pointers and the
+ *    work is enqueued on `stream` (a hipStream_t, NULL = default stream);
+ *    without it pointers are host pointers and the call returns when the
+ *    results are in host memory.  PMP_ASYNC (with PMP_ON_DEVICE) skips the
+ *    final stream wait: errors found on the device are then kept in the
+ *    instance's error word until pmp_instance_check().
+ *  - Handles own all device memory they allocate until *_destroy.  Input
+ *    buffers are borrowed for the duration of the call (for asynchronous
+ *    calls: until the enqueued work has run); outputs go to caller buffers.
+ *  - Handles are not thread-safe: calls on one handle must not overlap.
+ */
+#ifndef PMP_H
+#define PMP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define PMP_API __attribute__((visibility("default")))
+#else
+#define PMP_API
+#endif
+
+typedef enum {
+    PMP_OK = 0,
+    PMP_EINVAL = 1,       /* bad argument: sizes, null pointers, d < 0, ... */
+    PMP_ENOMEM = 2,       /* device or host allocation failed */
+    PMP_EDEVICE = 3,      /* a HIP call failed; see pmp_last_error() */
+    PMP_EINFEASIBLE = 4,  /* a chromosome without exactly p open facilities */
+    PMP_EUNSUPPORTED = 5  /* a size this build does not handle (m > 8192) */
+} pmp_status;
+
+#define PMP_ON_DEVICE 1u
+#define PMP_ASYNC 2u
+
+/* Largest m handled: chromosome masks of a tile of 64 chromosomes are held in
+ * LDS (64 x 1 KiB at m = 8192). */
+#define PMP_MAX_FACILITIES 8192
+
+typedef struct pmp_instance pmp_instance;
+typedef struct pmp_ga pmp_ga;
+
+/* ---------------------------------------------------------------------------
+ * pmp_preprocess - Section 2.1 and Section 3.1 host step 3: for every client
+ * i, the ordering Pi^i of the facilities by d_i. ascending (equal distances
+ * ordered by lower facility index, the order Example 1 prints) and the gap
+ * terms Delta^i (delta_i1 = d_{i pi_i1}, delta_ir = d_{i pi_ir} -
+ * d_{i pi_i(r-1)}), both truncated to their first K = m - p + 1 columns, the
+ * truncation argued after Eq. (6).  The sorted distances D'_ik = d_{i pi_ik}
+ * (the running sums of Delta') are kept too; the evaluation reads them.
+ *
+ *  d       n x m int32, row stride ld >= m elements; host pointer, or device
+ *          pointer with PMP_ON_DEVICE.  Copied; not kept.
+ *  n, m, p 1 <= n, 2 <= m <= PMP_MAX_FACILITIES, 1 <= p <= m - 1.
+ *  out     receives a new instance handle (device tables, owned).
+ * Errors: PMP_EINVAL for sizes, null pointers or any d_ij < 0 (the paper
+ * assumes non-negative distances); PMP_EUNSUPPORTED for m above the limit.
+ * Always waits for its stream before returning (one-time step).
+ * ------------------------------------------------------------------------- */
+PMP_API pmp_status pmp_preprocess(const int32_t *d, int64_t ld, int32_t n, int32_t m,
+                          int32_t p, uint32_t flags, void *stream,
+                          pmp_instance **out);
+
+/* Sizes of an instance: n, m, p, K = m - p + 1 and W = ceil(m/64).  Any
+ * output pointer may be NULL. */
+PMP_API pmp_status pmp_instance_info(const pmp_instance *inst, int32_t *n, int32_t *m,
+                             int32_t *p, int32_t *K, int32_t *W);
+
+/* Copy the truncated tables out (Section 2.1): pi (uint16), delta and
+ * dsorted (int32), each n x K row-major.  NULL outputs are skipped.  Host
+ * pointers, or device pointers with PMP_ON_DEVICE. */
+PMP_API pmp_status pmp_instance_tables(const pmp_instance *inst, uint16_t *pi,
+                               int32_t *delta, int32_t *dsorted,
+                               uint32_t flags, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * pmp_eval_population - Eq. (6) for every chromosome of a population, the
+ * Fitness function of Section 4.2: for chromosome c and client i, walk
+ * Pi'_i to the first open facility, position s*_{c,i} (1-based); the
+ * client's cost is D'_{i,s*} (= the sum of the first s* gap terms), and
+ *     fitness[c] = sum_i D'_{i, s*_{c,i}}   (int64, exact).
+ *
+ *  masks       P x W uint64 chromosomes (see conventions).
+ *  P           >= 0 chromosomes.
+ *  fitness     P int64 outputs.
+ *  scan_total  optional (NULL = skip): P int64 outputs, sum_i s*_{c,i}, the
+ *              number of Pi' entries the walk reads for chromosome c.
+ * Errors: PMP_EINFEASIBLE if a chromosome's popcount is not p or it has bits
+ * at positions >= m (the truncated walk is defined only for exactly p open
+ * facilities); its fitness is then unspecified.  With PMP_ASYNC the error is
+ * only recorded in the instance (see pmp_instance_check).
+ * ------------------------------------------------------------------------- */
+PMP_API pmp_status pmp_eval_population(pmp_instance *inst, const uint64_t *masks,
+                               int32_t P, int64_t *fitness,
+                               int64_t *scan_total, uint32_t flags,
+                               void *stream);
+
+/* Wait for `stream`, then return and clear the errors recorded on the device
+ * by asynchronous calls on this instance (PMP_EINFEASIBLE or PMP_EINVAL). */
+PMP_API pmp_status pmp_instance_check(pmp_instance *inst, void *stream);
+
+PMP_API void pmp_instance_destroy(pmp_instance *inst);
+
+/* ---------------------------------------------------------------------------
+ * The genetic algorithm of Section 3 (host steps 7-16 around each Evolve call,
+ * Evolve steps 1-8), with the operators of Section 4.  One generation:
+ *  1. population: a uniform random p-subset in every slot (Section 4.1), but
+ *     from the second generation on slot b*NT holds group b's best of the
+ *     previous generation (migration to the same block, Section 4.5);
+ *  2. fitness of all (pmp_eval_population's kernel);
+ *  3. crossover stages k = 0..X-1, stride NT >> (1 + k mod lg NT); slot t
+ *     of a group pairs with t XOR stride; the pair's lower slot draws
+ *     r1 in [0, m) and i in [1, floor(p/2)]; each partner forms its offspring
+ *     from both parents as they were when the stage began (Section 4.3) and
+ *     takes it if strictly fitter;
+ *  4. up to Y mutation attempts (circular or block shift, Section 4.4),
+ *     stopping at a chromosome's first strict improvement;
+ *  5. group best (least fitness, lowest slot on ties; Evolve steps 7-8);
+ *  6. global best, saturation count (reset on strict improvement), stop at
+ *     S generations without improvement (S > 0) or at `generations`
+ *     (EvolveLimit) generations (host steps 13-15).
+ * All random choices come from Philox4x64-10 counter streams keyed by
+ * (seed, role) and addressed by (generation, chromosome, tag, stage), so a
+ * run is reproducible bit for bit and independent of launch shapes.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    uint64_t seed;
+    int32_t population;       /* P = NB x NT */
+    int32_t group_size;       /* NT: a power of two dividing P, <= 1024 */
+    int32_t generations;      /* EvolveLimit, >= 1 */
+    int32_t saturation;       /* S; 0 = off */
+    int32_t crossover_iters;  /* X; 0 = lg NT */
+    int32_t mutation_iters;   /* Y; 0 = lg NT */
+    int32_t reserved[2];      /* must be 0 */
+} pmp_ga_params;
+
+typedef struct {
+    int64_t generations;       /* generations run so far */
+    int64_t saturation_count;  /* generations since the last improvement */
+    int64_t done;              /* 1 once stopped */
+    int64_t best_cost;         /* INT64_MAX before the first generation */
+    int64_t chromosome_evals;  /* chromosomes evaluated */
+    int64_t crossover_fail;    /* crossover operations with no offspring */
+    int64_t crossover_taken;   /* offspring that replaced a parent */
+    int64_t mutation_taken;    /* mutants that replaced a parent */
+    int64_t scan_total;        /* Pi' entries read by all evaluations */
+    int64_t pair_evals;        /* chromosome_evals x n */
+} pmp_ga_stats;
+
+/* Create a GA run on an instance (the instance must outlive it).
+ * PMP_EINVAL: P < 1, NT not a power of two, NT > 1024, P % NT != 0,
+ * generations < 1, negative counts, reserved fields not 0. */
+PMP_API pmp_status pmp_ga_create(pmp_instance *inst, const pmp_ga_params *params,
+                         pmp_ga **out);
+
+/* Enqueue `generations` more generations on `stream` (asynchronous).  Once
+ * the run has stopped, further generations do nothing. */
+PMP_API pmp_status pmp_ga_step(pmp_ga *ga, int32_t generations, void *stream);
+
+/* Wait for `stream`; copy the best chromosome (W words, host), its cost and
+ * the counters.  NULL outputs are skipped. */
+PMP_API pmp_status pmp_ga_best(pmp_ga *ga, uint64_t *mask, int64_t *cost,
+                       pmp_ga_stats *stats, void *stream);
+
+/* Wait for `stream`; copy the state (host pointers; NULL = skip): the
+ * population (P x W) and its fitness (P) as the last generation left them,
+ * the group bests (NB x W masks, NB costs). */
+PMP_API pmp_status pmp_ga_state(pmp_ga *ga, uint64_t *population, int64_t *fitness,
+                        uint64_t *group_masks, int64_t *group_costs,
+                        void *stream);
+
+PMP_API void pmp_ga_destroy(pmp_ga *ga);
+
+/* ---------------------------------------------------------------------------
+ * pmp_solve - the whole method on host data: preprocess, run the GA to its
+ * stop, return the best open set.
+ *  d      n x m int32 host matrix (row stride m).
+ *  open   m bytes, 1 = open (host).  cost: its objective.  stats optional.
+ * ------------------------------------------------------------------------- */
+PMP_API pmp_status pmp_solve(const int32_t *d, int32_t n, int32_t m, int32_t p,
+                     const pmp_ga_params *params, uint8_t *open,
+                     int64_t *cost, pmp_ga_stats *stats);
+
+/* ---------------------------------------------------------------------------
+ * Profiling of the evaluation kernel inside pmp_ga_step: when enabled, every
+ * launch of the evaluation kernel is bracketed by HIP events on the GA's
+ * stream.  pmp_ga_profile_read waits for the stream and returns the summed
+ * kernel milliseconds, the number of launches, and the algorithmic bytes of
+ * those launches: sum over evaluated (chromosome, client) pairs of
+ * 2*s* + 4 (uint16 Pi' entries up to the serving facility plus one int32
+ * D' entry) plus 8*W + 8 per evaluated chromosome (mask read, fitness
+ * write).  Enabling or reading resets the totals.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    double eval_ms;
+    int64_t eval_launches;
+    int64_t eval_bytes;
+    int64_t eval_pairs;
+} pmp_profile;
+
+PMP_API pmp_status pmp_ga_profile(pmp_ga *ga, int32_t enable);
+PMP_API pmp_status pmp_ga_profile_read(pmp_ga *ga, pmp_profile *out, void *stream);
+
+PMP_API const char *pmp_status_str(pmp_status s);
+PMP_API const char *pmp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PMP_H */

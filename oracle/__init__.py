@@ -79,8 +79,15 @@ def lib():
         L.orc_mutate.argtypes = [_u64, _u64, _u64, _u64, _p, _i32, _p, _p]
         L.orc_ga_run.argtypes = [_p, _i64, _i32, _i32, _i32, C.POINTER(_GaParams),
                                  _i32, _p, _p, _p, _p, _p, _p, _p, _i32]
+        L.orc_default_threads.argtypes = []
+        L.orc_default_threads.restype = C.c_int
         _lib = L
     return _lib
+
+
+def default_threads() -> int:
+    """Threads the oracle uses when a call passes threads=0."""
+    return int(lib().orc_default_threads())
 
 
 def _ptr(a: np.ndarray):

@@ -45,6 +45,16 @@ static void pack(const uint8_t *bits, int32_t m, int32_t W, uint64_t *mask)
             mask[j / 64] |= (uint64_t)1 << (j % 64);
 }
 
+/* number of threads a call with threads = 0 uses */
+int orc_default_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 static int set_threads(int32_t threads)
 {
 #ifdef _OPENMP

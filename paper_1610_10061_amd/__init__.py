@@ -1,0 +1,335 @@
+"""Python binding of the gfx950 p-median library (include/pmp.h).
+
+Argument marshalling only: every step of the path runs in the HIP kernels of
+libpmp.so.  PyTorch provides device memory and streams.  The binding loads
+the library after torch so that both share one HIP runtime; if the library
+is missing the import fails (there is no CPU fallback).
+
+Functions carry the C names; pass torch CUDA tensors for device buffers
+(the call then runs on `stream`, default torch's current stream) or numpy
+arrays for host buffers.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch  # noqa: F401  (loads the HIP runtime libpmp.so binds to)
+
+__all__ = [
+    "PmpError", "lib", "pmp_preprocess", "pmp_instance_info",
+    "pmp_instance_tables", "pmp_eval_population", "pmp_instance_check",
+    "pmp_instance_destroy", "pmp_ga_create", "pmp_ga_step", "pmp_ga_best",
+    "pmp_ga_state", "pmp_ga_destroy", "pmp_solve", "pmp_ga_profile",
+    "pmp_ga_profile_read", "Instance", "GA", "EXPORTS",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpmp.so")
+
+PMP_OK, PMP_EINVAL, PMP_ENOMEM, PMP_EDEVICE, PMP_EINFEASIBLE, PMP_EUNSUPPORTED = range(6)
+PMP_ON_DEVICE = 1
+PMP_ASYNC = 2
+
+EXPORTS = [
+    "pmp_preprocess", "pmp_instance_info", "pmp_instance_tables",
+    "pmp_eval_population", "pmp_instance_check", "pmp_instance_destroy",
+    "pmp_ga_create", "pmp_ga_step", "pmp_ga_best", "pmp_ga_state",
+    "pmp_ga_destroy", "pmp_solve", "pmp_ga_profile", "pmp_ga_profile_read",
+    "pmp_status_str", "pmp_last_error",
+]
+
+
+class PmpError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: status {status} ({detail})")
+        self.status = status
+
+
+class GaParams(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("population", C.c_int32),
+                ("group_size", C.c_int32), ("generations", C.c_int32),
+                ("saturation", C.c_int32), ("crossover_iters", C.c_int32),
+                ("mutation_iters", C.c_int32), ("reserved", C.c_int32 * 2)]
+
+
+class GaStats(C.Structure):
+    _fields_ = [(name, C.c_int64) for name in (
+        "generations", "saturation_count", "done", "best_cost",
+        "chromosome_evals", "crossover_fail", "crossover_taken",
+        "mutation_taken", "scan_total", "pair_evals")]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+class Profile(C.Structure):
+    _fields_ = [("eval_ms", C.c_double), ("eval_launches", C.c_int64),
+                ("eval_bytes", C.c_int64), ("eval_pairs", C.c_int64)]
+
+
+_lib = None
+_vp = C.c_void_p
+_i32 = C.c_int32
+_i64 = C.c_int64
+_u32 = C.c_uint32
+
+
+def lib():
+    """Load libpmp.so (built in place by build.py); raise if it is absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with "
+            "`python paper_1610_10061_amd/build.py` (there is no fallback)")
+    L = C.CDLL(LIB_PATH)
+    L.pmp_preprocess.argtypes = [_vp, _i64, _i32, _i32, _i32, _u32, _vp, C.POINTER(_vp)]
+    L.pmp_instance_info.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
+    L.pmp_instance_tables.argtypes = [_vp, _vp, _vp, _vp, _u32, _vp]
+    L.pmp_eval_population.argtypes = [_vp, _vp, _i32, _vp, _vp, _u32, _vp]
+    L.pmp_instance_check.argtypes = [_vp, _vp]
+    L.pmp_instance_destroy.argtypes = [_vp]
+    L.pmp_instance_destroy.restype = None
+    L.pmp_ga_create.argtypes = [_vp, C.POINTER(GaParams), C.POINTER(_vp)]
+    L.pmp_ga_step.argtypes = [_vp, _i32, _vp]
+    L.pmp_ga_best.argtypes = [_vp, _vp, C.POINTER(_i64), C.POINTER(GaStats), _vp]
+    L.pmp_ga_state.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
+    L.pmp_ga_destroy.argtypes = [_vp]
+    L.pmp_ga_destroy.restype = None
+    L.pmp_solve.argtypes = [_vp, _i32, _i32, _i32, C.POINTER(GaParams), _vp,
+                            C.POINTER(_i64), C.POINTER(GaStats)]
+    L.pmp_ga_profile.argtypes = [_vp, _i32]
+    L.pmp_ga_profile_read.argtypes = [_vp, C.POINTER(Profile), _vp]
+    L.pmp_status_str.argtypes = [_i32]
+    L.pmp_status_str.restype = C.c_char_p
+    L.pmp_last_error.argtypes = []
+    L.pmp_last_error.restype = C.c_char_p
+    for name in EXPORTS:
+        if name not in ("pmp_instance_destroy", "pmp_ga_destroy",
+                        "pmp_status_str", "pmp_last_error"):
+            getattr(L, name).restype = _i32
+    _lib = L
+    return L
+
+
+def _check(status: int, where: str):
+    if status != PMP_OK:
+        detail = lib().pmp_last_error().decode(errors="replace")
+        raise PmpError(status, where, detail)
+
+
+def _stream(stream):
+    if stream is None:
+        return _vp(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return _vp(stream.cuda_stream)
+    return _vp(int(stream))
+
+
+def _buf(x, dtype_np, dtype_t):
+    """(pointer, on_device) for a numpy array or a CUDA tensor."""
+    if x is None:
+        return None, None
+    if isinstance(x, torch.Tensor):
+        if not x.is_cuda or not x.is_contiguous() or x.dtype != dtype_t:
+            raise ValueError(f"need a contiguous CUDA {dtype_t} tensor")
+        return _vp(x.data_ptr()), True
+    if not (isinstance(x, np.ndarray) and x.dtype == dtype_np and x.flags.c_contiguous):
+        raise ValueError(f"need a C-contiguous numpy {dtype_np} array")
+    return x.ctypes.data_as(_vp), False
+
+
+# --------------------------------------------------------------- C names
+def pmp_preprocess(d, p: int, stream=None):
+    """Section 2.1 tables of d (n x m int32, numpy or CUDA tensor)."""
+    ptr, dev = _buf(d, np.int32, torch.int32)
+    n, m = d.shape
+    out = _vp()
+    flags = PMP_ON_DEVICE if dev else 0
+    _check(lib().pmp_preprocess(ptr, m, n, m, p, flags,
+                                _stream(stream) if dev else None, C.byref(out)),
+           "pmp_preprocess")
+    return out
+
+
+def pmp_instance_info(inst):
+    v = [_i32() for _ in range(5)]
+    _check(lib().pmp_instance_info(inst, *[C.byref(x) for x in v]), "pmp_instance_info")
+    return tuple(x.value for x in v)  # n, m, p, K, W
+
+
+def pmp_instance_tables(inst):
+    n, m, p, K, W = pmp_instance_info(inst)
+    pi = np.zeros((n, K), np.uint16)
+    de = np.zeros((n, K), np.int32)
+    ds = np.zeros((n, K), np.int32)
+    _check(lib().pmp_instance_tables(inst, pi.ctypes.data_as(_vp), de.ctypes.data_as(_vp),
+                                     ds.ctypes.data_as(_vp), 0, None), "pmp_instance_tables")
+    return pi, de, ds
+
+
+def pmp_eval_population(inst, masks, fitness, scan_total=None, stream=None,
+                        asynchronous=False):
+    """Eq. (6) for every row of masks (P x W uint64) into fitness (P int64)."""
+    mp, dev = _buf(masks, np.uint64, torch.uint64)
+    fp, fdev = _buf(fitness, np.int64, torch.int64)
+    sp, sdev = _buf(scan_total, np.int64, torch.int64)
+    if fdev != dev or (sp is not None and sdev != dev):
+        raise ValueError("all buffers must be host arrays or all CUDA tensors")
+    P = masks.shape[0]
+    flags = (PMP_ON_DEVICE | (PMP_ASYNC if asynchronous else 0)) if dev else 0
+    _check(lib().pmp_eval_population(inst, mp, P, fp, sp, flags,
+                                     _stream(stream) if dev else None),
+           "pmp_eval_population")
+
+
+def pmp_instance_check(inst, stream=None):
+    _check(lib().pmp_instance_check(inst, _stream(stream)), "pmp_instance_check")
+
+
+def pmp_instance_destroy(inst):
+    lib().pmp_instance_destroy(inst)
+
+
+def pmp_ga_create(inst, population, group_size, generations, seed,
+                  saturation=0, crossover_iters=0, mutation_iters=0):
+    prm = GaParams(seed, population, group_size, generations, saturation,
+                   crossover_iters, mutation_iters)
+    out = _vp()
+    _check(lib().pmp_ga_create(inst, C.byref(prm), C.byref(out)), "pmp_ga_create")
+    return out
+
+
+def pmp_ga_step(ga, generations, stream=None):
+    _check(lib().pmp_ga_step(ga, generations, _stream(stream)), "pmp_ga_step")
+
+
+def pmp_ga_best(ga, W, stream=None):
+    mask = np.zeros(W, np.uint64)
+    cost = _i64()
+    st = GaStats()
+    _check(lib().pmp_ga_best(ga, mask.ctypes.data_as(_vp), C.byref(cost),
+                             C.byref(st), _stream(stream)), "pmp_ga_best")
+    return mask, cost.value, st.as_dict()
+
+
+def pmp_ga_state(ga, P, NB, W, stream=None):
+    pop = np.zeros((P, W), np.uint64)
+    fit = np.zeros(P, np.int64)
+    gm = np.zeros((NB, W), np.uint64)
+    gc = np.zeros(NB, np.int64)
+    _check(lib().pmp_ga_state(ga, pop.ctypes.data_as(_vp), fit.ctypes.data_as(_vp),
+                              gm.ctypes.data_as(_vp), gc.ctypes.data_as(_vp),
+                              _stream(stream)), "pmp_ga_state")
+    return pop, fit, gm, gc
+
+
+def pmp_ga_destroy(ga):
+    lib().pmp_ga_destroy(ga)
+
+
+def pmp_ga_profile(ga, enable: bool):
+    _check(lib().pmp_ga_profile(ga, 1 if enable else 0), "pmp_ga_profile")
+
+
+def pmp_ga_profile_read(ga, stream=None):
+    pr = Profile()
+    _check(lib().pmp_ga_profile_read(ga, C.byref(pr), _stream(stream)),
+           "pmp_ga_profile_read")
+    return {"eval_ms": pr.eval_ms, "eval_launches": pr.eval_launches,
+            "eval_bytes": pr.eval_bytes, "eval_pairs": pr.eval_pairs}
+
+
+def pmp_solve(d, p, population, group_size, generations, seed, saturation=0,
+              crossover_iters=0, mutation_iters=0):
+    d = np.ascontiguousarray(d, dtype=np.int32)
+    n, m = d.shape
+    prm = GaParams(seed, population, group_size, generations, saturation,
+                   crossover_iters, mutation_iters)
+    open_ = np.zeros(m, np.uint8)
+    cost = _i64()
+    st = GaStats()
+    _check(lib().pmp_solve(d.ctypes.data_as(_vp), n, m, p, C.byref(prm),
+                           open_.ctypes.data_as(_vp), C.byref(cost), C.byref(st)),
+           "pmp_solve")
+    return open_, cost.value, st.as_dict()
+
+
+# ------------------------------------------------------- small conveniences
+class Instance:
+    """Owning wrapper of a pmp_instance handle."""
+
+    def __init__(self, d, p: int, stream=None):
+        self.handle = pmp_preprocess(d, p, stream)
+        self.n, self.m, self.p, self.K, self.W = pmp_instance_info(self.handle)
+
+    def tables(self):
+        return pmp_instance_tables(self.handle)
+
+    def eval(self, masks, fitness=None, scan_total=None, stream=None,
+             asynchronous=False):
+        if fitness is None:
+            if isinstance(masks, torch.Tensor):
+                fitness = torch.empty(masks.shape[0], dtype=torch.int64,
+                                      device=masks.device)
+            else:
+                fitness = np.zeros(masks.shape[0], np.int64)
+        pmp_eval_population(self.handle, masks, fitness, scan_total, stream,
+                            asynchronous)
+        return fitness
+
+    def check(self, stream=None):
+        pmp_instance_check(self.handle, stream)
+
+    def close(self):
+        if self.handle:
+            pmp_instance_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class GA:
+    """Owning wrapper of a pmp_ga handle (the instance must outlive it)."""
+
+    def __init__(self, inst: Instance, population, group_size, generations,
+                 seed, saturation=0, crossover_iters=0, mutation_iters=0):
+        self.inst = inst
+        self.P, self.NT = population, group_size
+        self.NB = population // group_size
+        self.handle = pmp_ga_create(inst.handle, population, group_size,
+                                    generations, seed, saturation,
+                                    crossover_iters, mutation_iters)
+
+    def step(self, generations, stream=None):
+        pmp_ga_step(self.handle, generations, stream)
+
+    def best(self, stream=None):
+        return pmp_ga_best(self.handle, self.inst.W, stream)
+
+    def state(self, stream=None):
+        return pmp_ga_state(self.handle, self.P, self.NB, self.inst.W, stream)
+
+    def profile(self, enable=True):
+        pmp_ga_profile(self.handle, enable)
+
+    def profile_read(self, stream=None):
+        return pmp_ga_profile_read(self.handle, stream)
+
+    def close(self):
+        if self.handle:
+            pmp_ga_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

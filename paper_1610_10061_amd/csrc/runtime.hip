@@ -1,0 +1,676 @@
+// Host runtime of the p-median library: argument checking, device memory
+// owned by handles, launch sequencing and the extern "C" entry points
+// declared in pmp.h.
+#include "pmp.h"
+
+#include <climits>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+using namespace pmp;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+pmp_status fail(pmp_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                       \
+    do {                                                                    \
+        hipError_t e_ = (expr);                                             \
+        if (e_ != hipSuccess)                                               \
+            return fail(PMP_EDEVICE, "%s failed: %s", #expr,                \
+                        hipGetErrorString(e_));                             \
+    } while (0)
+
+template <class T>
+hipError_t dalloc(T **p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0)
+        count = 1;
+    return hipMalloc((void **)p, sizeof(T) * count);
+}
+
+template <class T>
+void dfree(T *&p)
+{
+    if (p)
+        (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+int env_int(const char *name, int dflt)
+{
+    const char *v = getenv(name);
+    if (!v || !*v)
+        return dflt;
+    return atoi(v);
+}
+
+// Clients per workgroup of the evaluation kernel: enough workgroups to fill
+// 256 CUs several times over, at least four clients (one per wave).
+int clients_per_block(int n, int P)
+{
+    const int forced = env_int("PMP_CLIENTS_PER_BLOCK", 0);
+    if (forced > 0)
+        return ((forced + 3) / 4) * 4;
+    const long tiles_c = (P + kEvalTile - 1) / kEvalTile;
+    long cpb = (long)n * tiles_c / 2048;
+    if (cpb < 4)
+        cpb = 4;
+    if (cpb > 64)
+        cpb = 64;
+    return (int)(((cpb + 3) / 4) * 4);
+}
+
+pmp_status status_from_err(uint32_t e)
+{
+    if (e & ERR_NEGATIVE_DISTANCE)
+        return fail(PMP_EINVAL, "negative distance in d");
+    if (e & (ERR_POPCOUNT | ERR_STRAY_BITS | ERR_SCAN_OVERRUN))
+        return fail(PMP_EINFEASIBLE,
+                    "chromosome without exactly p open facilities (error bits 0x%x)",
+                    e);
+    return PMP_OK;
+}
+
+}  // namespace
+
+struct pmp_instance {
+    int32_t n = 0, m = 0, p = 0, K = 0, W = 0, pitch = 0;
+    uint16_t *pi = nullptr;
+    int32_t *ds = nullptr;
+    int32_t *delta = nullptr;
+    uint32_t *err = nullptr;
+    // staging for host-pointer evaluation
+    uint64_t *h_masks = nullptr;
+    unsigned long long *h_fit = nullptr;
+    unsigned long long *h_scan = nullptr;
+    int32_t h_cap = 0;
+
+    Tables tables() const
+    {
+        Tables t;
+        t.pi = pi;
+        t.ds = ds;
+        t.n = n;
+        t.m = m;
+        t.p = p;
+        t.K = K;
+        t.W = W;
+        t.pitch = pitch;
+        return t;
+    }
+};
+
+struct pmp_ga {
+    pmp_instance *inst = nullptr;
+    pmp_ga_params prm{};
+    int NB = 0, lg = 0, X = 0, Y = 0;
+    uint64_t *cur = nullptr, *off = nullptr, *gmask = nullptr, *best = nullptr;
+    unsigned long long *fit = nullptr, *ofit = nullptr, *gcost = nullptr,
+                       *gs = nullptr;
+    uint8_t *ok = nullptr, *improved = nullptr;
+    // profiling of the evaluation kernel
+    bool prof = false;
+    std::vector<hipEvent_t> ev;
+    size_t ev_used = 0;
+    unsigned long long base_scan = 0, base_evals = 0;
+
+    GaArgs args() const
+    {
+        GaArgs g;
+        g.t = inst->tables();
+        g.seed = prm.seed;
+        g.P = prm.population;
+        g.NT = prm.group_size;
+        g.NB = NB;
+        g.lg = lg;
+        g.X = X;
+        g.Y = Y;
+        g.generations = prm.generations;
+        g.saturation = prm.saturation;
+        g.cur = cur;
+        g.off = off;
+        g.fit = fit;
+        g.ofit = ofit;
+        g.ok = ok;
+        g.improved = improved;
+        g.gmask = gmask;
+        g.gcost = gcost;
+        g.best_mask = best;
+        g.gs = gs;
+        g.err = inst->err;
+        return g;
+    }
+};
+
+extern "C" {
+
+const char *pmp_status_str(pmp_status s)
+{
+    switch (s) {
+    case PMP_OK: return "ok";
+    case PMP_EINVAL: return "invalid argument";
+    case PMP_ENOMEM: return "out of memory";
+    case PMP_EDEVICE: return "device error";
+    case PMP_EINFEASIBLE: return "infeasible chromosome";
+    case PMP_EUNSUPPORTED: return "unsupported size";
+    }
+    return "unknown status";
+}
+
+const char *pmp_last_error(void) { return g_last_error.c_str(); }
+
+void pmp_instance_destroy(pmp_instance *inst)
+{
+    if (!inst)
+        return;
+    dfree(inst->pi);
+    dfree(inst->ds);
+    dfree(inst->delta);
+    dfree(inst->err);
+    dfree(inst->h_masks);
+    dfree(inst->h_fit);
+    dfree(inst->h_scan);
+    delete inst;
+}
+
+pmp_status pmp_preprocess(const int32_t *d, int64_t ld, int32_t n, int32_t m,
+                          int32_t p, uint32_t flags, void *stream,
+                          pmp_instance **out)
+{
+    if (!out)
+        return fail(PMP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!d)
+        return fail(PMP_EINVAL, "d is NULL");
+    if (n < 1 || m < 2 || p < 1 || p > m - 1)
+        return fail(PMP_EINVAL, "need n >= 1, m >= 2, 1 <= p <= m-1 (n=%d m=%d p=%d)",
+                    n, m, p);
+    if (m > PMP_MAX_FACILITIES)
+        return fail(PMP_EUNSUPPORTED, "m=%d above %d", m, PMP_MAX_FACILITIES);
+    if (ld < m)
+        return fail(PMP_EINVAL, "row stride %lld < m", (long long)ld);
+    hipStream_t s = (hipStream_t)stream;
+    const bool on_dev = flags & PMP_ON_DEVICE;
+    if (!on_dev) {
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = 0; j < m; ++j)
+                if (d[i * ld + j] < 0)
+                    return fail(PMP_EINVAL, "d[%lld][%lld] < 0", (long long)i,
+                                (long long)j);
+    }
+    pmp_instance *inst = new pmp_instance;
+    inst->n = n;
+    inst->m = m;
+    inst->p = p;
+    inst->K = m - p + 1;
+    inst->W = (m + 63) / 64;
+    inst->pitch = ((inst->K + 63) / 64) * 64;
+    const size_t cells = (size_t)n * inst->pitch;
+    if (dalloc(&inst->pi, cells) != hipSuccess || dalloc(&inst->ds, cells) != hipSuccess ||
+        dalloc(&inst->delta, cells) != hipSuccess || dalloc(&inst->err, 1) != hipSuccess) {
+        pmp_instance_destroy(inst);
+        return fail(PMP_ENOMEM, "device allocation of tables (%zu cells)", cells);
+    }
+    int32_t *dd = nullptr;
+    const int32_t *src = d;
+    int64_t src_ld = ld;
+    pmp_status st = PMP_OK;
+    do {
+        hipError_t e = hipMemsetAsync(inst->err, 0, sizeof(uint32_t), s);
+        if (e != hipSuccess) {
+            st = fail(PMP_EDEVICE, "hipMemsetAsync: %s", hipGetErrorString(e));
+            break;
+        }
+        if (!on_dev) {
+            if (dalloc(&dd, (size_t)n * m) != hipSuccess) {
+                st = fail(PMP_ENOMEM, "device copy of d");
+                break;
+            }
+            e = hipMemcpy2DAsync(dd, sizeof(int32_t) * m, d, sizeof(int32_t) * ld,
+                                 sizeof(int32_t) * m, n, hipMemcpyHostToDevice, s);
+            if (e != hipSuccess) {
+                st = fail(PMP_EDEVICE, "copy of d: %s", hipGetErrorString(e));
+                break;
+            }
+            src = dd;
+            src_ld = m;
+        }
+        e = launch_sort_rows(src, src_ld, n, m, inst->K, inst->pitch, inst->pi,
+                             inst->delta, inst->ds, inst->err, s);
+        if (e != hipSuccess) {
+            st = fail(PMP_EDEVICE, "sort kernel launch: %s", hipGetErrorString(e));
+            break;
+        }
+        uint32_t herr = 0;
+        e = hipMemcpyAsync(&herr, inst->err, sizeof herr, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            st = fail(PMP_EDEVICE, "preprocess: %s", hipGetErrorString(e));
+            break;
+        }
+        st = status_from_err(herr);
+    } while (0);
+    dfree(dd);
+    if (st != PMP_OK) {
+        pmp_instance_destroy(inst);
+        return st;
+    }
+    *out = inst;
+    return PMP_OK;
+}
+
+pmp_status pmp_instance_info(const pmp_instance *inst, int32_t *n, int32_t *m,
+                             int32_t *p, int32_t *K, int32_t *W)
+{
+    if (!inst)
+        return fail(PMP_EINVAL, "instance is NULL");
+    if (n) *n = inst->n;
+    if (m) *m = inst->m;
+    if (p) *p = inst->p;
+    if (K) *K = inst->K;
+    if (W) *W = inst->W;
+    return PMP_OK;
+}
+
+pmp_status pmp_instance_tables(const pmp_instance *inst, uint16_t *pi,
+                               int32_t *delta, int32_t *dsorted,
+                               uint32_t flags, void *stream)
+{
+    if (!inst)
+        return fail(PMP_EINVAL, "instance is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const hipMemcpyKind kind = (flags & PMP_ON_DEVICE) ? hipMemcpyDeviceToDevice
+                                                        : hipMemcpyDeviceToHost;
+    const size_t K = inst->K, pitch = inst->pitch, n = inst->n;
+    if (pi)
+        HIP_TRY(hipMemcpy2DAsync(pi, K * 2, inst->pi, pitch * 2, K * 2, n, kind, s));
+    if (delta)
+        HIP_TRY(hipMemcpy2DAsync(delta, K * 4, inst->delta, pitch * 4, K * 4, n, kind, s));
+    if (dsorted)
+        HIP_TRY(hipMemcpy2DAsync(dsorted, K * 4, inst->ds, pitch * 4, K * 4, n, kind, s));
+    if (!(flags & PMP_ON_DEVICE) || !(flags & PMP_ASYNC))
+        HIP_TRY(hipStreamSynchronize(s));
+    return PMP_OK;
+}
+
+pmp_status pmp_instance_check(pmp_instance *inst, void *stream)
+{
+    if (!inst)
+        return fail(PMP_EINVAL, "instance is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t herr = 0;
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipMemcpy(&herr, inst->err, sizeof herr, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemset(inst->err, 0, sizeof herr));
+    return status_from_err(herr);
+}
+
+pmp_status pmp_eval_population(pmp_instance *inst, const uint64_t *masks,
+                               int32_t P, int64_t *fitness,
+                               int64_t *scan_total, uint32_t flags,
+                               void *stream)
+{
+    if (!inst)
+        return fail(PMP_EINVAL, "instance is NULL");
+    if (P < 0)
+        return fail(PMP_EINVAL, "P < 0");
+    if (P == 0)
+        return PMP_OK;
+    if (!masks || !fitness)
+        return fail(PMP_EINVAL, "masks or fitness is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const bool on_dev = flags & PMP_ON_DEVICE;
+    const bool async = on_dev && (flags & PMP_ASYNC);
+    const size_t W = inst->W;
+
+    const uint64_t *dmask = masks;
+    unsigned long long *dfit = (unsigned long long *)fitness;
+    unsigned long long *dscan = (unsigned long long *)scan_total;
+    if (!on_dev) {
+        if (inst->h_cap < P) {
+            dfree(inst->h_masks);
+            dfree(inst->h_fit);
+            dfree(inst->h_scan);
+            inst->h_cap = 0;
+            if (dalloc(&inst->h_masks, (size_t)P * W) != hipSuccess ||
+                dalloc(&inst->h_fit, (size_t)P) != hipSuccess ||
+                dalloc(&inst->h_scan, (size_t)P) != hipSuccess)
+                return fail(PMP_ENOMEM, "staging for P=%d", P);
+            inst->h_cap = P;
+        }
+        HIP_TRY(hipMemcpyAsync(inst->h_masks, masks, sizeof(uint64_t) * P * W,
+                               hipMemcpyHostToDevice, s));
+        dmask = inst->h_masks;
+        dfit = inst->h_fit;
+        dscan = scan_total ? inst->h_scan : nullptr;
+    }
+    if (!async)
+        HIP_TRY(launch_zero(inst->err, sizeof(uint32_t), s));
+    HIP_TRY(launch_zero(dfit, sizeof(unsigned long long) * P, s));
+    if (dscan)
+        HIP_TRY(launch_zero(dscan, sizeof(unsigned long long) * P, s));
+
+    EvalArgs a{};
+    a.t = inst->tables();
+    a.masks = dmask;
+    a.P = P;
+    a.active = nullptr;
+    a.fitness = dfit;
+    a.scan = dscan;
+    a.gstate = nullptr;
+    a.err = inst->err;
+    a.clients_per_block = clients_per_block(inst->n, P);
+    a.tiles_c = (P + kEvalTile - 1) / kEvalTile;
+    a.tiles_i = (inst->n + a.clients_per_block - 1) / a.clients_per_block;
+    HIP_TRY(launch_eval(a, s));
+
+    if (!on_dev) {
+        HIP_TRY(hipMemcpyAsync(fitness, dfit, sizeof(int64_t) * P,
+                               hipMemcpyDeviceToHost, s));
+        if (scan_total)
+            HIP_TRY(hipMemcpyAsync(scan_total, dscan, sizeof(int64_t) * P,
+                                   hipMemcpyDeviceToHost, s));
+    }
+    if (async)
+        return PMP_OK;
+    uint32_t herr = 0;
+    HIP_TRY(hipMemcpyAsync(&herr, inst->err, sizeof herr, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return status_from_err(herr);
+}
+
+void pmp_ga_destroy(pmp_ga *ga)
+{
+    if (!ga)
+        return;
+    dfree(ga->cur);
+    dfree(ga->off);
+    dfree(ga->gmask);
+    dfree(ga->best);
+    dfree(ga->fit);
+    dfree(ga->ofit);
+    dfree(ga->gcost);
+    dfree(ga->gs);
+    dfree(ga->ok);
+    dfree(ga->improved);
+    for (hipEvent_t e : ga->ev)
+        (void)hipEventDestroy(e);
+    delete ga;
+}
+
+pmp_status pmp_ga_create(pmp_instance *inst, const pmp_ga_params *prm,
+                         pmp_ga **out)
+{
+    if (!out)
+        return fail(PMP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!inst || !prm)
+        return fail(PMP_EINVAL, "instance or params is NULL");
+    const int P = prm->population, NT = prm->group_size;
+    if (P < 1 || NT < 1 || NT > 1024 || (NT & (NT - 1)) || P % NT)
+        return fail(PMP_EINVAL,
+                    "population %d must be a multiple of a power-of-two group size %d <= 1024",
+                    P, NT);
+    if (prm->generations < 1 || prm->saturation < 0 || prm->crossover_iters < 0 ||
+        prm->mutation_iters < 0 || prm->reserved[0] || prm->reserved[1])
+        return fail(PMP_EINVAL, "bad GA parameters");
+    pmp_ga *ga = new pmp_ga;
+    ga->inst = inst;
+    ga->prm = *prm;
+    ga->NB = P / NT;
+    int lg = 0;
+    while ((1 << (lg + 1)) <= NT)
+        ++lg;
+    ga->lg = lg;
+    ga->X = prm->crossover_iters > 0 ? prm->crossover_iters : lg;
+    ga->Y = prm->mutation_iters > 0 ? prm->mutation_iters : lg;
+    const size_t W = inst->W;
+    if (dalloc(&ga->cur, (size_t)P * W) || dalloc(&ga->off, (size_t)P * W) ||
+        dalloc(&ga->gmask, (size_t)ga->NB * W) || dalloc(&ga->best, W) ||
+        dalloc(&ga->fit, (size_t)P) || dalloc(&ga->ofit, (size_t)P) ||
+        dalloc(&ga->gcost, (size_t)ga->NB) || dalloc(&ga->gs, GS_COUNT) ||
+        dalloc(&ga->ok, (size_t)P) || dalloc(&ga->improved, (size_t)P)) {
+        pmp_ga_destroy(ga);
+        return fail(PMP_ENOMEM, "GA buffers for P=%d", P);
+    }
+    unsigned long long init[GS_COUNT] = {0};
+    init[GS_BEST] = (unsigned long long)INT64_MAX;
+    hipError_t e = hipMemcpy(ga->gs, init, sizeof init, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemset(ga->best, 0, sizeof(uint64_t) * W);
+    if (e == hipSuccess)
+        e = hipMemset(ga->gmask, 0, sizeof(uint64_t) * W * ga->NB);
+    if (e != hipSuccess) {
+        pmp_ga_destroy(ga);
+        return fail(PMP_EDEVICE, "GA state init: %s", hipGetErrorString(e));
+    }
+    *out = ga;
+    return PMP_OK;
+}
+
+namespace {
+
+hipEvent_t next_event(pmp_ga *ga)
+{
+    if (ga->ev_used == ga->ev.size()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess)
+            return nullptr;
+        ga->ev.push_back(e);
+    }
+    return ga->ev[ga->ev_used++];
+}
+
+hipError_t ga_eval(pmp_ga *ga, const GaArgs &g, const uint64_t *masks,
+                   unsigned long long *fit, hipStream_t s)
+{
+    EvalArgs a{};
+    a.t = g.t;
+    a.masks = masks;
+    a.P = g.P;
+    a.active = g.ok;
+    a.fitness = fit;
+    a.scan = nullptr;
+    a.gstate = g.gs;
+    a.err = g.err;
+    a.clients_per_block = clients_per_block(g.t.n, g.P);
+    a.tiles_c = (g.P + kEvalTile - 1) / kEvalTile;
+    a.tiles_i = (g.t.n + a.clients_per_block - 1) / a.clients_per_block;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (ga->prof) {
+        e0 = next_event(ga);
+        e1 = next_event(ga);
+        if (!e0 || !e1)
+            return hipErrorOutOfMemory;
+        hipError_t e = hipEventRecord(e0, s);
+        if (e != hipSuccess)
+            return e;
+    }
+    hipError_t e = launch_eval(a, s);
+    if (e == hipSuccess && ga->prof)
+        e = hipEventRecord(e1, s);
+    return e;
+}
+
+}  // namespace
+
+pmp_status pmp_ga_step(pmp_ga *ga, int32_t generations, void *stream)
+{
+    if (!ga)
+        return fail(PMP_EINVAL, "ga is NULL");
+    if (generations < 0)
+        return fail(PMP_EINVAL, "generations < 0");
+    hipStream_t s = (hipStream_t)stream;
+    const GaArgs g = ga->args();
+    const bool crossover = g.t.p >= 2 && g.lg > 0;
+    for (int gen = 0; gen < generations; ++gen) {
+        HIP_TRY(launch_ga_init(g, s));
+        HIP_TRY(ga_eval(ga, g, g.cur, g.fit, s));
+        for (int k = 0; crossover && k < g.X; ++k) {
+            HIP_TRY(launch_ga_crossover(g, k, s));
+            HIP_TRY(ga_eval(ga, g, g.off, g.ofit, s));
+            HIP_TRY(launch_ga_accept(g, 0, s));
+        }
+        for (int a = 0; a < g.Y; ++a) {
+            HIP_TRY(launch_ga_mutate(g, a, s));
+            HIP_TRY(ga_eval(ga, g, g.off, g.ofit, s));
+            HIP_TRY(launch_ga_accept(g, 1, s));
+        }
+        HIP_TRY(launch_ga_best(g, s));
+    }
+    return PMP_OK;
+}
+
+pmp_status pmp_ga_best(pmp_ga *ga, uint64_t *mask, int64_t *cost,
+                       pmp_ga_stats *stats, void *stream)
+{
+    if (!ga)
+        return fail(PMP_EINVAL, "ga is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipStreamSynchronize(s));
+    unsigned long long gs[GS_COUNT];
+    HIP_TRY(hipMemcpy(gs, ga->gs, sizeof gs, hipMemcpyDeviceToHost));
+    if (mask)
+        HIP_TRY(hipMemcpy(mask, ga->best, sizeof(uint64_t) * ga->inst->W,
+                          hipMemcpyDeviceToHost));
+    if (cost)
+        *cost = (int64_t)gs[GS_BEST];
+    if (stats) {
+        stats->generations = (int64_t)gs[GS_GEN];
+        stats->saturation_count = (int64_t)gs[GS_SAT];
+        stats->done = (int64_t)gs[GS_DONE];
+        stats->best_cost = (int64_t)gs[GS_BEST];
+        stats->chromosome_evals = (int64_t)gs[GS_CHROM_EVALS];
+        stats->crossover_fail = (int64_t)gs[GS_XO_FAIL];
+        stats->crossover_taken = (int64_t)gs[GS_XO_TAKEN];
+        stats->mutation_taken = (int64_t)gs[GS_MUT_TAKEN];
+        stats->scan_total = (int64_t)gs[GS_SCAN_TOTAL];
+        stats->pair_evals = (int64_t)gs[GS_CHROM_EVALS] * ga->inst->n;
+    }
+    uint32_t herr = 0;
+    HIP_TRY(hipMemcpy(&herr, ga->inst->err, sizeof herr, hipMemcpyDeviceToHost));
+    return status_from_err(herr);
+}
+
+pmp_status pmp_ga_state(pmp_ga *ga, uint64_t *population, int64_t *fitness,
+                        uint64_t *group_masks, int64_t *group_costs,
+                        void *stream)
+{
+    if (!ga)
+        return fail(PMP_EINVAL, "ga is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipStreamSynchronize(s));
+    const size_t W = ga->inst->W, P = ga->prm.population, NB = ga->NB;
+    if (population)
+        HIP_TRY(hipMemcpy(population, ga->cur, sizeof(uint64_t) * P * W,
+                          hipMemcpyDeviceToHost));
+    if (fitness)
+        HIP_TRY(hipMemcpy(fitness, ga->fit, sizeof(int64_t) * P, hipMemcpyDeviceToHost));
+    if (group_masks)
+        HIP_TRY(hipMemcpy(group_masks, ga->gmask, sizeof(uint64_t) * NB * W,
+                          hipMemcpyDeviceToHost));
+    if (group_costs)
+        HIP_TRY(hipMemcpy(group_costs, ga->gcost, sizeof(int64_t) * NB,
+                          hipMemcpyDeviceToHost));
+    return PMP_OK;
+}
+
+pmp_status pmp_ga_profile(pmp_ga *ga, int32_t enable)
+{
+    if (!ga)
+        return fail(PMP_EINVAL, "ga is NULL");
+    HIP_TRY(hipDeviceSynchronize());
+    unsigned long long gs[GS_COUNT];
+    HIP_TRY(hipMemcpy(gs, ga->gs, sizeof gs, hipMemcpyDeviceToHost));
+    ga->prof = enable != 0;
+    ga->ev_used = 0;
+    ga->base_scan = gs[GS_SCAN_TOTAL];
+    ga->base_evals = gs[GS_CHROM_EVALS];
+    return PMP_OK;
+}
+
+pmp_status pmp_ga_profile_read(pmp_ga *ga, pmp_profile *out, void *stream)
+{
+    if (!ga || !out)
+        return fail(PMP_EINVAL, "ga or out is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipStreamSynchronize(s));
+    double ms = 0;
+    for (size_t k = 0; k + 1 < ga->ev_used; k += 2) {
+        float t = 0;
+        HIP_TRY(hipEventElapsedTime(&t, ga->ev[k], ga->ev[k + 1]));
+        ms += t;
+    }
+    unsigned long long gs[GS_COUNT];
+    HIP_TRY(hipMemcpy(gs, ga->gs, sizeof gs, hipMemcpyDeviceToHost));
+    const int64_t evals = (int64_t)(gs[GS_CHROM_EVALS] - ga->base_evals);
+    const int64_t scan = (int64_t)(gs[GS_SCAN_TOTAL] - ga->base_scan);
+    const int64_t pairs = evals * ga->inst->n;
+    out->eval_ms = ms;
+    out->eval_launches = (int64_t)(ga->ev_used / 2);
+    out->eval_pairs = pairs;
+    out->eval_bytes = 2 * scan + 4 * pairs + evals * (8 * (int64_t)ga->inst->W + 8);
+    ga->ev_used = 0;
+    ga->base_scan = gs[GS_SCAN_TOTAL];
+    ga->base_evals = gs[GS_CHROM_EVALS];
+    return PMP_OK;
+}
+
+pmp_status pmp_solve(const int32_t *d, int32_t n, int32_t m, int32_t p,
+                     const pmp_ga_params *params, uint8_t *open, int64_t *cost,
+                     pmp_ga_stats *stats)
+{
+    if (!params || !open || !cost)
+        return fail(PMP_EINVAL, "params, open or cost is NULL");
+    pmp_instance *inst = nullptr;
+    pmp_status st = pmp_preprocess(d, m, n, m, p, 0, nullptr, &inst);
+    if (st != PMP_OK)
+        return st;
+    pmp_ga *ga = nullptr;
+    st = pmp_ga_create(inst, params, &ga);
+    // Enqueue generations in chunks and stop enqueueing once the run has
+    // stopped (saturation can end it long before EvolveLimit).
+    for (int done_gens = 0; st == PMP_OK && done_gens < params->generations;) {
+        const int chunk = params->generations - done_gens < 32
+                              ? params->generations - done_gens : 32;
+        st = pmp_ga_step(ga, chunk, nullptr);
+        done_gens += chunk;
+        unsigned long long flag = 0;
+        if (st == PMP_OK &&
+            hipMemcpy(&flag, ga->gs + GS_DONE, sizeof flag, hipMemcpyDeviceToHost) != hipSuccess)
+            st = fail(PMP_EDEVICE, "reading the stop flag");
+        if (flag)
+            break;
+    }
+    std::vector<uint64_t> mask((size_t)inst->W);
+    if (st == PMP_OK)
+        st = pmp_ga_best(ga, mask.data(), cost, stats, nullptr);
+    if (st == PMP_OK)
+        for (int j = 0; j < m; ++j)
+            open[j] = (uint8_t)((mask[j / 64] >> (j % 64)) & 1u);
+    pmp_ga_destroy(ga);
+    pmp_instance_destroy(inst);
+    return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,215 @@
+"""GPU parity of the preprocessing and population-evaluation kernels with the
+CPU oracle, through the C ABI.
+
+Bar: bit-exact.  The tables are integer data; fitness values are exact
+int64 sums of int32 distances; scan lengths are integer counts.  The oracle
+computes costs straight from d (never through the tables) and scan lengths
+by counting, so agreement checks the GPU tables and walk end to end.
+"""
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import pmp_inputs as gi
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pm():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1610_10061_amd as pm
+    pm.lib()
+    return pm
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _rand(n, m, hi, seed):
+    return np.random.default_rng(seed).integers(0, hi, size=(n, m)).astype(np.int32)
+
+
+INSTANCES = {
+    "example1": lambda: (gi.example1_matrix(), 2),
+    "g20": lambda: (gi.graph_instance(20, 40, 0), 4),
+    "g100": lambda: (gi.graph_instance(100, 200, 0), 5),
+    "g900": lambda: (gi.graph_instance(900, 16200, 0), 90),
+    "rect_37x150": lambda: (_rand(37, 150, 1000, 1), 20),
+    "ties_p1": lambda: (_rand(60, 65, 4, 2), 1),
+    "ties_pm1": lambda: (_rand(30, 64, 4, 3), 63),
+    "euclid_64": lambda: (gi.euclid_instance(64, 4), 7),
+    "euclid_129": lambda: (gi.euclid_instance(129, 5), 3),
+    "wide_2x700": lambda: (_rand(2, 700, 50, 6), 350),
+    "m2": lambda: (_rand(5, 2, 10, 7), 1),
+}
+
+
+@pytest.mark.parametrize("name", list(INSTANCES))
+def test_tables_bit_exact(pm, name):
+    d, p = INSTANCES[name]()
+    _say("case", name, d.shape, "p", p)
+    inst = pm.Instance(d, p)
+    pi, de, ds = inst.tables()
+    opi, ode, ods = oracle.tables(d, p)
+    np.testing.assert_array_equal(pi.astype(np.int32), opi)
+    np.testing.assert_array_equal(de, ode)
+    np.testing.assert_array_equal(ds, ods)
+
+
+@pytest.mark.parametrize("name,P", [("example1", 6), ("g20", 200), ("g100", 64), ("g100", 1),
+                                    ("g900", 1024), ("rect_37x150", 131), ("ties_p1", 70),
+                                    ("ties_pm1", 65), ("euclid_64", 127), ("euclid_129", 64),
+                                    ("wide_2x700", 300), ("m2", 3)])
+def test_eval_bit_exact_host_path(pm, name, P):
+    d, p = INSTANCES[name]()
+    n, m = d.shape
+    _say("case", name, d.shape, "p", p, "P", P)
+    masks = gi.random_population(P, m, p, seed=P + n)
+    inst = pm.Instance(d, p)
+    fit = np.zeros(P, np.int64)
+    scan = np.zeros(P, np.int64)
+    pm.pmp_eval_population(inst.handle, masks, fit, scan)
+    want, wscan = oracle.objective(d, masks, p, scan=True)
+    np.testing.assert_array_equal(fit, want)
+    np.testing.assert_array_equal(scan, wscan)
+
+
+def test_eval_device_path_and_async(pm):
+    import torch
+    d, p = INSTANCES["g900"]()
+    masks = gi.random_population(333, 900, p, seed=9)
+    inst = pm.Instance(torch.from_numpy(d).cuda(), p)
+    dm = torch.from_numpy(masks.view(np.int64)).cuda().view(torch.uint64)
+    fit = torch.empty(333, dtype=torch.int64, device="cuda")
+    scan = torch.empty(333, dtype=torch.int64, device="cuda")
+    pm.pmp_eval_population(inst.handle, dm, fit, scan)
+    want, wscan = oracle.objective(d, masks, p, scan=True)
+    np.testing.assert_array_equal(fit.cpu().numpy(), want)
+    np.testing.assert_array_equal(scan.cpu().numpy(), wscan)
+    fit2 = torch.full((333,), -5, dtype=torch.int64, device="cuda")
+    pm.pmp_eval_population(inst.handle, dm, fit2, None, asynchronous=True)
+    inst.check()
+    np.testing.assert_array_equal(fit2.cpu().numpy(), want)
+
+
+def test_g20_all_subsets_min_is_exhaustive_optimum(pm):
+    d, p = INSTANCES["g20"]()
+    allsets = gi.pack_masks([list(s) for s in itertools.combinations(range(20), p)], 20)
+    inst = pm.Instance(d, p)
+    fit = inst.eval(allsets)
+    assert len(fit) == 4845
+    np.testing.assert_array_equal(fit, oracle.objective(d, allsets, p))
+    best, _, _ = oracle.exhaustive(d, p)
+    assert fit.min() == best
+
+
+def test_example1_all_pairs_match_printed_costs(pm):
+    d, p = INSTANCES["example1"]()
+    sets = list(itertools.combinations(range(4), 2))
+    fit = pm.Instance(d, p).eval(gi.pack_masks([list(s) for s in sets], 4))
+    # costs of the six open pairs from the paper's reduced polynomial
+    assert fit.tolist() == [43, 37, 35, 46, 40, 44]
+
+
+@pytest.mark.parametrize("p", [10, 100, 500])
+def test_e5000_full_size_sampled(pm, p):
+    """Full E5000 shape (P = 4096) in the benchmark's launch configuration;
+    a sample of chromosomes and of table rows is recomputed by the oracle."""
+    import torch
+    d = _e5000()
+    _say("case e5000 p", p)
+    inst = pm.Instance(torch.from_numpy(d).cuda(), p)
+    masks = gi.random_population(4096, 5000, p, seed=p)
+    dm = torch.from_numpy(masks.view(np.int64)).cuda().view(torch.uint64)
+    fit = torch.empty(4096, dtype=torch.int64, device="cuda")
+    scan = torch.empty(4096, dtype=torch.int64, device="cuda")
+    pm.pmp_eval_population(inst.handle, dm, fit, scan)
+    fit, scan = fit.cpu().numpy(), scan.cpu().numpy()
+    rng = np.random.default_rng(p)
+    pick = np.concatenate([[0, 4095], rng.choice(4096, 30, replace=False)])
+    want, wscan = oracle.objective(d, masks[pick], p, scan=True)
+    np.testing.assert_array_equal(fit[pick], want)
+    np.testing.assert_array_equal(scan[pick], wscan)
+    # E[s*] = (m+1)/(p+1) for uniform random subsets
+    mean = scan.sum() / (4096 * 5000)
+    assert abs(mean - 5001 / (p + 1)) < 0.03 * 5001 / (p + 1)
+    rows = rng.choice(5000, 40, replace=False)
+    pi, de, ds = inst.tables()
+    opi, ode, ods = oracle.tables(d[rows], p)
+    np.testing.assert_array_equal(pi[rows].astype(np.int32), opi)
+    np.testing.assert_array_equal(de[rows], ode)
+    np.testing.assert_array_equal(ds[rows], ods)
+
+
+_E5000 = {}
+
+
+def _e5000():
+    if "d" not in _E5000:
+        _E5000["d"] = gi.euclid_instance(5000, 0)
+    return _E5000["d"]
+
+
+def test_tile_shape_does_not_change_results(pm):
+    d, p = INSTANCES["g900"]()
+    masks = gi.random_population(257, 900, p, seed=3)
+    inst = pm.Instance(d, p)
+    outs = []
+    old = os.environ.get("PMP_CLIENTS_PER_BLOCK")
+    try:
+        for cpb in ("4", "12", "64", "900"):
+            os.environ["PMP_CLIENTS_PER_BLOCK"] = cpb
+            outs.append(inst.eval(masks).copy())
+    finally:
+        if old is None:
+            os.environ.pop("PMP_CLIENTS_PER_BLOCK", None)
+        else:
+            os.environ["PMP_CLIENTS_PER_BLOCK"] = old
+    for o in outs[1:]:
+        np.testing.assert_array_equal(o, outs[0])
+    np.testing.assert_array_equal(outs[0], oracle.objective(d, masks, p))
+
+
+def test_empty_population_is_a_no_op(pm):
+    d, p = INSTANCES["g100"]()
+    inst = pm.Instance(d, p)
+    fit = np.zeros(0, np.int64)
+    pm.pmp_eval_population(inst.handle, np.zeros((0, 2), np.uint64), fit)
+
+
+@pytest.mark.parametrize("kind", ["fewer", "more", "stray"])
+def test_infeasible_chromosomes_rejected(pm, kind):
+    d, p = INSTANCES["euclid_129"]()
+    m = 129
+    masks = gi.random_population(10, m, p, seed=1)
+    bits = gi.unpack_masks(masks, m)
+    if kind == "fewer":
+        bits[4, np.nonzero(bits[4])[0][0]] = False
+        masks = gi.pack_masks(bits, m)
+    elif kind == "more":
+        bits[4, np.nonzero(~bits[4])[0][0]] = True
+        masks = gi.pack_masks(bits, m)
+    else:
+        masks[4, 2] |= np.uint64(1) << np.uint64(5)  # bit 133 >= m
+    inst = pm.Instance(d, p)
+    with pytest.raises(pm.PmpError) as e:
+        inst.eval(masks)
+    assert e.value.status == pm.PMP_EINFEASIBLE
+    # the instance stays usable; a feasible call succeeds afterwards
+    ok = gi.random_population(10, m, p, seed=2)
+    np.testing.assert_array_equal(inst.eval(ok), oracle.objective(d, ok, p))
+
+
+def test_negative_distance_rejected_on_device(pm):
+    import torch
+    d = _rand(10, 12, 9, 8)
+    d[3, 7] = -2
+    with pytest.raises(pm.PmpError) as e:
+        pm.Instance(torch.from_numpy(d).cuda(), 3)
+    assert e.value.status == pm.PMP_EINVAL

@@ -1,0 +1,109 @@
+"""GPU parity of the genetic algorithm (pmp_ga_step) with the oracle GA.
+
+Both sides draw every random choice from the same Philox counters and take
+every decision on exact integer fitness, so after k generations the whole
+state (population, fitness, group bests, global best and counters) must be
+identical bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import pmp_inputs as gi
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pm():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1610_10061_amd as pm
+    pm.lib()
+    return pm
+
+
+def _compare(pm, d, p, P, NT, G, seed, steps, sat=0, X=0, Y=0):
+    n, m = d.shape
+    print("case", d.shape, "p", p, "P", P, "NT", NT, "steps", steps, "seed", seed,
+          flush=True)
+    inst = pm.Instance(d, p)
+    ga = pm.GA(inst, P, NT, G, seed, sat, X, Y)
+    st = oracle.GaState(n, m, p, P, NT, G, seed, sat, X, Y)
+    for k in steps:
+        ga.step(k)
+        oracle.ga_run(d, st, k)
+    pop, fit, gm, gc = ga.state()
+    mask, cost, stats = ga.best()
+    np.testing.assert_array_equal(pop, st.pop)
+    np.testing.assert_array_equal(fit, st.fit)
+    np.testing.assert_array_equal(gm, st.gbest_mask)
+    np.testing.assert_array_equal(gc, st.gbest_cost)
+    np.testing.assert_array_equal(mask, st.best_mask)
+    assert cost == st.best_cost
+    assert stats["generations"] == st.state[oracle.ST_GEN]
+    assert stats["saturation_count"] == st.state[oracle.ST_SAT]
+    assert stats["done"] == st.state[oracle.ST_DONE]
+    assert stats["chromosome_evals"] == st.state[oracle.ST_CHROM_EVALS]
+    assert stats["crossover_fail"] == st.state[oracle.ST_XO_FAIL]
+    assert stats["crossover_taken"] == st.state[oracle.ST_XO_TAKEN]
+    assert stats["mutation_taken"] == st.state[oracle.ST_MUT_TAKEN]
+    assert stats["pair_evals"] == stats["chromosome_evals"] * n
+    # the reported best is what its mask costs
+    assert oracle.objective(d, mask[None], p)[0] == cost
+    return stats
+
+
+def test_ga_g100_config(pm):
+    """Graph n = m = 100, 200 edges, p = 5, population 64 (one group)."""
+    d = gi.graph_instance(100, 200, 0)
+    _compare(pm, d, 5, 64, 64, 100, seed=1, steps=[4])
+
+
+def test_ga_g20_groups_saturation(pm):
+    d = gi.graph_instance(20, 40, 0)
+    s = _compare(pm, d, 4, 32, 8, 500, seed=7, steps=[40, 40], sat=6)
+    assert s["done"] == 1
+
+
+def test_ga_example1_tiny(pm):
+    _compare(pm, gi.example1_matrix(), 2, 8, 4, 5, seed=3, steps=[2, 3])
+
+
+def test_ga_p1_has_no_crossover(pm):
+    d = gi.euclid_instance(70, 3)
+    s = _compare(pm, d, 1, 16, 16, 3, seed=2, steps=[3])
+    assert s["crossover_taken"] == 0 and s["crossover_fail"] == 0
+
+
+def test_ga_preset_iteration_counts(pm):
+    """More crossover stages than lg NT cycle the strides again."""
+    d = gi.euclid_instance(150, 8)
+    _compare(pm, d, 12, 64, 16, 4, seed=5, steps=[2], X=9, Y=2)
+
+
+def test_ga_ragged_m_and_resume(pm):
+    d = np.random.default_rng(4).integers(0, 50, size=(77, 131)).astype(np.int32)
+    _compare(pm, d, 17, 128, 32, 8, seed=11, steps=[1, 2, 4])
+
+
+def test_ga_g900_full_config(pm):
+    """Graph n = m = 900, 16200 edges, p = 90, population 1024 (NT = 256),
+    the benchmark's configuration, two generations."""
+    d = gi.graph_instance(900, 16200, 0)
+    _compare(pm, d, 90, 1024, 256, 500, seed=0, steps=[2])
+
+
+def test_ga_euclid_1000(pm):
+    d = gi.euclid_instance(1000, 1)
+    _compare(pm, d, 50, 512, 128, 3, seed=9, steps=[1])
+
+
+def test_solve_returns_consistent_best(pm):
+    d = gi.graph_instance(20, 40, 1)
+    open_, cost, stats = pm.pmp_solve(d, 4, 32, 8, 30, seed=2, saturation=5)
+    assert open_.sum() == 4
+    mask = gi.pack_masks(open_[None].astype(bool), 20)
+    assert oracle.objective(d, mask, 4)[0] == cost
+    best, _, _ = oracle.exhaustive(d, 4)
+    assert cost >= best
