@@ -668,6 +668,11 @@ int orc_ga_run(const int32_t *d, int64_t ld, int32_t n, int32_t m, int32_t p,
     if (!bits || !snap || !offs || !ok || !improved || !offfit || !tmp)
         return ORC_ENOMEM;
 
+    /* the population carried over from the previous call (left unchanged
+     * when this call runs no generation) */
+    for (int32_t c = 0; c < P; ++c)
+        unpack(pop + (int64_t)c * W, m, bits + (int64_t)c * m);
+
     for (int32_t step = 0; step < gens && !state[ORC_ST_DONE]; ++step) {
         const uint64_t g = (uint64_t)state[ORC_ST_GEN];
 

@@ -365,6 +365,12 @@ def test_ga_saturation_stop_and_optimum_bound():
     assert st.done and st.generation < 1000
     assert st.state[oracle.ST_SAT] == 5
     assert st.best_cost >= opt
+    # a call after the stop changes nothing
+    before = (st.pop.copy(), st.fit.copy(), st.state.copy())
+    oracle.ga_run(d, st, 10)
+    np.testing.assert_array_equal(st.pop, before[0])
+    np.testing.assert_array_equal(st.fit, before[1])
+    np.testing.assert_array_equal(st.state, before[2])
     # with 32 chromosomes improved by crossover and mutation over several
     # generations, a 4845-set space is searched to its optimum
     assert st.best_cost == opt
