@@ -201,14 +201,16 @@ PMP_API pmp_status pmp_solve(const int32_t *d, int32_t n, int32_t m, int32_t p,
                      int64_t *cost, pmp_ga_stats *stats);
 
 /* ---------------------------------------------------------------------------
- * Profiling of the evaluation kernel inside pmp_ga_step: when enabled, every
- * launch of the evaluation kernel is bracketed by HIP events on the GA's
- * stream.  pmp_ga_profile_read waits for the stream and returns the summed
- * kernel milliseconds, the number of launches, and the algorithmic bytes of
- * those launches: sum over evaluated (chromosome, client) pairs of
- * 2*s* + 4 (uint16 Pi' entries up to the serving facility plus one int32
- * D' entry) plus 8*W + 8 per evaluated chromosome (mask read, fitness
- * write).  Enabling or reading resets the totals.
+ * Profiling of the kernels that evaluate fitness inside pmp_ga_step: when
+ * enabled, every launch that runs evaluations (the evaluation kernel, or the
+ * persistent GA kernel that contains the whole generation) is bracketed by
+ * HIP events on the GA's stream.  pmp_ga_profile_read waits for the stream
+ * and returns the summed milliseconds of those launches, their number, the
+ * (chromosome, client) pairs they evaluated and the algorithmic bytes of
+ * those evaluations: per pair 2*s* + 4 (the uint16 Pi' entries up to the
+ * serving facility plus one int32 D' entry), plus 8*W + 8 per evaluated
+ * chromosome (mask read, fitness write).  Enabling or reading resets the
+ * totals.
  * ------------------------------------------------------------------------- */
 typedef struct {
     double eval_ms;

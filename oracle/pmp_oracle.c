@@ -608,6 +608,12 @@ int orc_mutate(uint64_t seed, uint64_t gen, uint64_t chrom, uint64_t attempt,
  *  6. Global best: least group best, lowest group on ties; the saturation
  *     count resets on a strict improvement and grows otherwise.  Stop when
  *     it reaches S (S > 0) or when EvolveLimit generations have run.
+ *
+ * Parity unpinned: the paper prints no trajectory (its Figures 1-3 are
+ * missing), so the exact sequence of choices rests on the readings above;
+ * the tests pin this function only by invariants (popcount p, fitness equal
+ * to the objective, non-increasing best, saturation stop, optimum reached
+ * on a small instance, checkpoint/resume equivalence).
  * ---------------------------------------------------------------------- */
 typedef struct {
     uint64_t seed;

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "pmp.h"
+
 namespace pmp {
 
 // Error bits of an instance's device error word.
@@ -13,20 +15,16 @@ enum : uint32_t {
     ERR_POPCOUNT = 1u << 1,           // a chromosome without exactly p ones
     ERR_STRAY_BITS = 1u << 2,         // bits set at positions >= m
     ERR_SCAN_OVERRUN = 1u << 3,       // no open facility in a truncated row
+    ERR_BARRIER_TIMEOUT = 1u << 4,    // a grid barrier waited past its bound
 };
 
-// Device GA state: one array of 64-bit counters.
+// Device GA run state: 64-bit words.
 enum GaSlot : int {
-    GS_GEN = 0,          // generations run
-    GS_SAT = 1,          // generations since the last strict improvement
-    GS_DONE = 2,         // 1 once stopped
-    GS_BEST = 3,         // global best cost
-    GS_CHROM_EVALS = 4,  // chromosomes evaluated
-    GS_XO_FAIL = 5,
-    GS_XO_TAKEN = 6,
-    GS_MUT_TAKEN = 7,
-    GS_SCAN_TOTAL = 8,   // sum of s* over evaluated pairs
-    GS_COUNT = 16
+    GS_GEN = 0,   // generations run
+    GS_SAT = 1,   // generations since the last strict improvement
+    GS_DONE = 2,  // 1 once stopped
+    GS_BEST = 3,  // global best cost
+    GS_COUNT = 8
 };
 
 // Tables of one preprocessed instance (device pointers).
@@ -36,20 +34,25 @@ struct Tables {
     int32_t n, m, p, K, W, pitch;
 };
 
-// One population evaluation (Eq. (6) by the walk of Section 4.2).
+// One population evaluation (Eq. (6) by the walk of Section 4.2).  Output:
+// part[ti * P + c] = chromosome c's cost summed over the clients of client
+// tile ti (and spart the summed scan lengths), written for active c only.
 struct EvalArgs {
     Tables t;
     const uint64_t *masks;            // P x W
     int32_t P;
     const uint8_t *active;            // optional: evaluate c only if active[c]
-    unsigned long long *fitness;      // P, accumulated (caller zeroes)
-    unsigned long long *scan;         // optional P, accumulated
-    unsigned long long *gstate;       // optional GA counters (GS_*)
+    unsigned long long *part;         // tiles_i x P partial costs
+    uint32_t *spart;                  // optional tiles_i x P partial scan lengths
+    const unsigned long long *done;   // optional: skip everything when *done
     uint32_t *err;                    // error word
     int32_t clients_per_block;
     int32_t tiles_c;                  // ceil(P / 64)
     int32_t tiles_i;                  // ceil(n / clients_per_block)
 };
+
+constexpr int kMaxPersistentBlocks = 4096;
+constexpr int kBarrierWords = 32 * (kMaxPersistentBlocks + 1);
 
 constexpr int kEvalTile = 64;     // chromosomes per block (one per lane)
 constexpr int kEvalWaves = 4;     // waves per block
@@ -60,30 +63,59 @@ hipError_t launch_sort_rows(const int32_t *d, int64_t ld, int32_t n, int32_t m,
                             int32_t *delta, int32_t *ds, uint32_t *err,
                             hipStream_t s);
 hipError_t launch_eval(const EvalArgs &a, hipStream_t s);
+hipError_t launch_reduce(const EvalArgs &a, unsigned long long *fitness,
+                         unsigned long long *scan, hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
 
+// Per-chromosome GA counters (summed on the host when read).
+enum GaStat : int {
+    CS_EVALS = 0,      // evaluations of this slot's chromosomes
+    CS_SCAN = 1,       // Pi' entries those evaluations read
+    CS_XO_FAIL = 2,    // crossovers without offspring
+    CS_XO_TAKEN = 3,   // crossover offspring taken
+    CS_MUT_TAKEN = 4,  // mutants taken
+    CS_COUNT = 5
+};
+
+// Kinds of the operator a stage kernel finishes (prev) and starts (op).
+enum GaOp : int { OP_NONE = 0, OP_INIT = 1, OP_XOVER = 2, OP_MUT = 3 };
+
+// Device state of one GA run.  Population, fitness, offspring and their
+// "evaluate me" flags are double-buffered: a stage kernel reads buffer `in`
+// and writes buffer `in ^ 1`, so every chromosome (and its crossover partner)
+// is read as the previous stage left it.
 struct GaArgs {
     Tables t;
     uint64_t seed;
     int32_t P, NT, NB, lg, X, Y, generations, saturation;
-    uint64_t *cur;            // P x W current population
-    uint64_t *off;            // P x W offspring
-    unsigned long long *fit;  // P current fitness
-    unsigned long long *ofit; // P offspring fitness
-    uint8_t *ok;              // P: offspring exists / must be evaluated
-    uint8_t *improved;        // P: mutation cycle succeeded
-    uint64_t *gmask;          // NB x W group bests
-    unsigned long long *gcost;// NB
-    uint64_t *best_mask;      // W
-    unsigned long long *gs;   // GS_COUNT counters
+    uint64_t *cur[2];               // P x W population
+    unsigned long long *fit[2];     // P fitness of cur
+    uint64_t *off[2];               // P x W offspring
+    uint8_t *ok[2];                 // P: offspring exists and is evaluated
+    uint8_t *improved;              // P: mutation cycle already succeeded
+    const unsigned long long *part; // TI x P partial costs of the last evaluation
+    const uint32_t *spart;          // TI x P partial scan lengths
+    int32_t TI;                     // client tiles of the evaluation
+    uint64_t *gmask;                // NB x W group bests (migrants)
+    unsigned long long *gcost;      // NB
+    uint64_t *best_mask;            // W
+    unsigned long long *gs;         // GS_COUNT run state
+    unsigned long long *cstat;      // P x CS_COUNT counters
+    uint32_t *arrive;               // group-best arrival counter
+    uint32_t *bar;                  // grid barrier: epoch word, then one
+                                    // flag per workgroup (32 words apart)
     uint32_t *err;
 };
 
 hipError_t launch_ga_init(const GaArgs &g, hipStream_t s);
-hipError_t launch_ga_crossover(const GaArgs &g, int stage, hipStream_t s);
-hipError_t launch_ga_mutate(const GaArgs &g, int attempt, hipStream_t s);
-hipError_t launch_ga_accept(const GaArgs &g, int mutation, hipStream_t s);
-hipError_t launch_ga_best(const GaArgs &g, hipStream_t s);
-hipError_t launch_ga_state_init(const GaArgs &g, hipStream_t s);
+hipError_t launch_ga_stage(const GaArgs &g, int in, int prev, int op,
+                           int index, hipStream_t s);
+hipError_t launch_ga_best(const GaArgs &g, int fb, hipStream_t s);
+// One cooperative launch running `generations` generations; evaluation tiles
+// from `e` (its masks and active flags are set per phase).  max_blocks > 0
+// caps the grid; the grid used is returned.
+hipError_t launch_ga_persistent(const GaArgs &g, const EvalArgs &e,
+                                int generations, int max_blocks, hipStream_t s,
+                                int *grid);
 
 }  // namespace pmp

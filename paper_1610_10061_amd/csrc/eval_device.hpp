@@ -1,0 +1,222 @@
+// Population evaluation, device side: Eq. (6), computed as the Fitness function of
+// Section 4.2 does it, for a whole population at once.
+//
+// For chromosome c and client i the walk reads Pi'_i from the front until it
+// meets an open facility, at 1-based position s*; the client then costs
+// D'_{i,s*} (the sum of the first s* gap terms).  fitness[c] is the sum over
+// clients, exact in 64-bit integers.
+//
+// Mapping (gfx950, wave64).  A workgroup owns a tile of 64 chromosomes (one
+// per lane, their masks staged in LDS) and a tile of clients; each of its
+// four waves takes every fourth client of the tile.  For one client the wave
+// loads 64 consecutive entries of Pi'_i and D'_i, one per lane (coalesced),
+// and then, for each chromosome of the tile, every lane tests "is the
+// facility at my position open in chromosome c" with one LDS read of the
+// word holding that facility's bit.  A ballot gives the 64 answers; its
+// lowest set bit is the chromosome's first open position in this chunk.
+// That position is written into lane c of a register, and one ds_bpermute
+// then fetches each chromosome's D' entry from the lane that holds it, so a
+// (chromosome, client) pair costs one LDS read and three VALU operations
+// whatever its scan length up to 64.  Chromosomes still unmatched go on to
+// the next 64 entries.  This replaces the paper's one-thread-per-chromosome
+// loop: lanes never diverge and Pi' rows are read once per 64 chromosomes.
+//
+// Partial sums of the four waves are combined in LDS and stored, one int64
+// per (client tile, chromosome), with plain stores; the consumer (the
+// reduction below or the GA's next stage) adds the client tiles up.  Integer
+// addition makes the result exact and independent of tiling.  Workgroups
+// are numbered so that all chromosome tiles of one client tile run on the
+// same XCD and share its L2, and each wave loads the next client's chunk of
+// Pi' and D' before it works on the current one.
+#pragma once
+
+#include <utility>
+
+#include "common.hpp"
+
+namespace pmp {
+
+using kLanes = std::make_integer_sequence<int, kEvalTile>;
+
+__device__ __forceinline__ int first_lane(uint64_t b)
+{
+    return __builtin_ffsll((long long)b) - 1;  // -1 when b == 0
+}
+
+// Lane C of `hit` takes the wave-uniform value `v` (v_writelane_b32 with the
+// lane as an inline constant).
+template <int C>
+__device__ __forceinline__ void write_lane(int &hit, int v)
+{
+    asm("v_writelane_b32 %0, %1, %2" : "+v"(hit) : "s"(v), "n"(C));
+}
+
+// All 64 chromosomes of the tile against one 64-entry chunk of a Pi' row.
+template <int WD, int C>
+__device__ __forceinline__ void match_one(const uint32_t *sm, uint32_t bit,
+                                          int &hit)
+{
+    const uint32_t w = sm[C * WD];
+    const uint64_t b = __builtin_amdgcn_ballot_w64((w & bit) != 0u);
+    write_lane<C>(hit, first_lane(b));
+}
+
+// Even and odd chromosomes write two different registers, so consecutive
+// v_writelane instructions do not wait on each other.
+template <int WD, int... C>
+__device__ __forceinline__ int match_dense(const uint32_t *sm, uint32_t bit,
+                                           int lane,
+                                           std::integer_sequence<int, C...>)
+{
+    int hit0 = -1, hit1 = -1;
+    (match_one<WD, C>(sm, bit, (C & 1) ? hit1 : hit0), ...);
+    return (lane & 1) ? hit1 : hit0;
+}
+
+// Only the chromosomes in q (few left after the first chunk).
+template <int WD>
+__device__ __forceinline__ int match_sparse(const uint32_t *sm, uint32_t bit,
+                                            uint64_t q, int lane)
+{
+    int hit = -1;
+    while (q) {
+        const int c = __builtin_ctzll(q);
+        q &= q - 1;
+        const uint32_t w = sm[c * WD];
+        const uint64_t b = __builtin_amdgcn_ballot_w64((w & bit) != 0u);
+        const int v = first_lane(b);
+        hit = lane == c ? v : hit;
+    }
+    return hit;
+}
+
+// Evaluate chromosome tile tc (64 chromosomes) on client tile ti and store
+// the tile's partial sums.  Called by a whole 256-thread workgroup;
+// smask holds 64 * WD words, sred 2 * kEvalWaves * 64 words.
+template <int WD>
+__device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
+                                          uint32_t *smask,
+                                          unsigned long long *sred)
+{
+    const int c0 = tc * kEvalTile;
+    const int i0 = ti * a.clients_per_block;
+    const int i1 = min(a.t.n, i0 + a.clients_per_block);
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int W2 = 2 * a.t.W;
+
+    // The tile's independent loads go out together (one memory round trip):
+    // this lane's active flag, chunk 0 of the wave's first client, and the
+    // tile's masks, staged to LDS whether active or not (an inactive
+    // chromosome is never pending, so its stale mask is never consulted).
+    const int my_c = c0 + lane;
+    const bool my_act = my_c < a.P && (a.active == nullptr || a.active[my_c]);
+    int i = i0 + wave;
+    uint32_t j_cur = 0;  // chunk 0 of the current client, loaded one ahead
+    int32_t d_cur = 0;
+    if (i < i1 && lane < a.t.K) {
+        j_cur = a.t.pi[(int64_t)i * a.t.pitch + lane];
+        d_cur = a.t.ds[(int64_t)i * a.t.pitch + lane];
+    }
+    const uint32_t *g32 = reinterpret_cast<const uint32_t *>(a.masks);
+    const int rows = min(kEvalTile, a.P - c0);
+#pragma unroll 8
+    for (int k = threadIdx.x; k < kEvalTile * WD; k += kEvalTile * kEvalWaves) {
+        const int c = k / WD, w = k - (k / WD) * WD;
+        smask[k] = (w < W2 && c < rows) ? g32[(int64_t)(c0 + c) * W2 + w] : 0u;
+    }
+    const uint64_t act = __builtin_amdgcn_ballot_w64(my_act);
+    if (act == 0ull)  // same in every wave: the whole workgroup leaves
+        return;
+    __syncthreads();
+
+    // Feasibility of each chromosome, checked once (first client tile).
+    // Lanes start at different words so the reads hit different banks.
+    if (ti == 0 && wave == 0 && my_act) {
+        int ones = 0;
+        uint32_t stray = 0;
+        const int full = a.t.m >> 5, rem = a.t.m & 31;
+        for (int k = 0; k < W2; ++k) {
+            int w = lane + k;
+            w = w >= W2 ? w - W2 * (w / W2) : w;
+            const uint32_t v = smask[lane * WD + w];
+            ones += __builtin_popcount(v);
+            if (w > full || (w == full && rem == 0))
+                stray |= v;
+            else if (w == full)
+                stray |= v & ~((1u << rem) - 1u);
+        }
+        if (ones != a.t.p)
+            atomicOr(a.err, ERR_POPCOUNT);
+        if (stray)
+            atomicOr(a.err, ERR_STRAY_BITS);
+    }
+
+    unsigned long long acc = 0;
+    uint32_t scn = 0;
+    for (; i < i1; i += kEvalWaves) {
+        const int inext = i + kEvalWaves;
+        uint32_t j_nxt = 0;
+        int32_t d_nxt = 0;
+        if (inext < i1 && lane < a.t.K) {
+            j_nxt = a.t.pi[(int64_t)inext * a.t.pitch + lane];
+            d_nxt = a.t.ds[(int64_t)inext * a.t.pitch + lane];
+        }
+        const uint16_t *prow = a.t.pi + (int64_t)i * a.t.pitch;
+        const int32_t *drow = a.t.ds + (int64_t)i * a.t.pitch;
+        uint64_t pend = act;
+        for (int base = 0; pend != 0ull; base += 64) {
+            if (base >= a.t.K) {  // fewer than p open facilities
+                if (lane == 0)
+                    atomicOr(a.err, ERR_SCAN_OVERRUN);
+                break;
+            }
+            const int k = base + lane;
+            uint32_t off = 0, bit = 0;
+            int32_t dist = 0;
+            if (base == 0) {
+                if (k < a.t.K) {
+                    off = j_cur >> 5;
+                    bit = 1u << (j_cur & 31u);
+                    dist = d_cur;
+                }
+            } else if (k < a.t.K) {
+                const uint32_t j = prow[k];
+                off = j >> 5;
+                bit = 1u << (j & 31u);
+                dist = drow[k];
+            }
+            const uint32_t *sm = smask + off;
+            const int hit = (base == 0 || __builtin_popcountll(pend) >= 16)
+                                ? match_dense<WD>(sm, bit, lane, kLanes{})
+                                : match_sparse<WD>(sm, bit, pend, lane);
+            const bool found = ((pend >> lane) & 1ull) && hit >= 0;
+            const int32_t cost = __builtin_amdgcn_ds_bpermute((hit & 63) << 2, dist);
+            if (found) {
+                acc += (uint32_t)cost;
+                scn += (uint32_t)(base + hit + 1);
+            }
+            pend &= ~__builtin_amdgcn_ballot_w64(found);
+        }
+        j_cur = j_nxt;
+        d_cur = d_nxt;
+    }
+
+    sred[wave * kEvalTile + lane] = acc;
+    sred[kEvalWaves * kEvalTile + wave * kEvalTile + lane] = scn;
+    __syncthreads();
+    if (wave == 0 && my_act) {
+        unsigned long long f = 0, s = 0;
+#pragma unroll
+        for (int w = 0; w < kEvalWaves; ++w) {
+            f += sred[w * kEvalTile + lane];
+            s += sred[kEvalWaves * kEvalTile + w * kEvalTile + lane];
+        }
+        const int64_t o = (int64_t)ti * a.P + my_c;
+        a.part[o] = f;
+        if (a.spart)
+            a.spart[o] = (uint32_t)s;
+    }
+}
+
+}  // namespace pmp

@@ -1,0 +1,515 @@
+// Genetic-algorithm device code (Section 3.2 Evolve steps, Section 4
+// operators), shared by the one-kernel-per-step launch sequence and the
+// persistent kernel.
+//
+// One wavefront owns one chromosome; its lanes own the chromosome's 64-bit
+// words (two per lane above m = 4096).  Every random choice is drawn by all
+// lanes from the same Philox stream, so control flow stays uniform.
+//
+// A generation is: population (with migrants), evaluation, then for each
+// operator stage a stage step followed by an evaluation, then a last stage
+// step with no operator, then the group and global bests.  A stage step first
+// finishes the previous stage for its chromosome (sum the evaluation's
+// partial costs, take the offspring if strictly fitter) and then starts the
+// next operator.  State is double-buffered between stages, so a crossover
+// partner is always read as the previous stage left it, whatever order waves
+// run in.
+#pragma once
+
+#include "common.hpp"
+#include "philox.hpp"
+
+namespace pmp {
+
+constexpr int kMaxWords = PMP_MAX_FACILITIES / 64;  // 128
+constexpr int kGaWaves = 4;                         // waves per workgroup
+
+// Buffer k of a double-buffered pair, by select (indexing the kernel
+// argument array with a run-time value would copy it to scratch).
+template <class T>
+__device__ __forceinline__ T *buf(T *const (&pair)[2], int k)
+{
+    return k ? pair[1] : pair[0];
+}
+
+__device__ __forceinline__ bool ga_stopped(const GaArgs &g)
+{
+    return g.gs[GS_DONE] != 0ull;
+}
+
+// Crossover stages a generation runs (none when p < 2 or NT = 1).
+__device__ __forceinline__ int ga_xstages(const GaArgs &g)
+{
+    return (g.t.p >= 2 && g.lg > 0) ? g.X : 0;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v)
+{
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1)
+        v += __shfl_xor(v, d);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_scan_incl(uint32_t v, int lane)
+{
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t u = __shfl_up(v, d);
+        if (lane >= d)
+            v += u;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane)
+{
+    const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+    const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// The k lowest set bits of x (all of x when it has no more than k).
+__device__ __forceinline__ uint64_t lowest_bits(uint64_t x, int k)
+{
+    if (k <= 0)
+        return 0;
+    if (__builtin_popcountll(x) <= k)
+        return x;
+    // largest q with popcount(x below bit q) < k; the k-th set bit is at q
+    int q = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1) {
+        const int t = q + step;
+        if (__builtin_popcountll(x & ((1ull << t) - 1ull)) < k)
+            q = t;
+    }
+    return q >= 63 ? x : (x & ((1ull << (q + 1)) - 1ull));
+}
+
+// Costs of the offspring of chromosomes c and q: the evaluation's
+// client-tile partial sums, added up by the wave (only where `want`); the
+// scan lengths of c's offspring too.
+__device__ __forceinline__ void offspring_costs(const GaArgs &g, int c, bool want_c,
+                                                int q, bool want_q, int lane,
+                                                unsigned long long *fc,
+                                                unsigned long long *sc,
+                                                unsigned long long *fq)
+{
+    unsigned long long f = 0, s = 0, h = 0;
+    for (int t = lane; t < g.TI; t += 64) {
+        const int64_t row = (int64_t)t * g.P;
+        if (want_c) {
+            f += g.part[row + c];
+            s += g.spart[row + c];
+        }
+        if (want_q)
+            h += g.part[row + q];
+    }
+    *fc = wave_sum(f);
+    *sc = wave_sum(s);
+    *fq = wave_sum(h);
+}
+
+// Philox4x64-10 block (philox.hpp) for counter (c0, c1, c2, c3).
+__device__ __forceinline__ void philox_block(uint64_t k0, uint64_t k1,
+                                             uint64_t c0, uint64_t c1,
+                                             uint64_t c2, uint64_t c3,
+                                             uint64_t out[4])
+{
+    PhiloxStream st(k0, k1, c0, c1, 0, 0);
+    st.c2 = c2;
+    st.block = c3;
+    st.refill();
+    out[0] = st.buf[0];
+    out[1] = st.buf[1];
+    out[2] = st.buf[2];
+    out[3] = st.buf[3];
+}
+
+// ---------------------------------------------------------------------------
+// Population of one Evolve call (Section 3.1 steps 7/11 and 16; Sections 4.1
+// and 4.5), chromosome c, by its wave.  Fresh slots get a uniform p-subset by
+// Floyd's method (Bentley & Floyd, CACM 1987): for j = m-p .. m-1 draw t
+// uniform in [0, j]; take t, or j if t is already taken.  The lanes compute
+// 64 Philox blocks (256 words of the slot's stream) at once; the draws are
+// consumed in stream order, so the result is the same as drawing one at a
+// time.  From the second generation on, slot b*NT of group b receives that
+// group's best of the previous generation.  The population goes to off[0]
+// with fitness "infinite", so the first stage takes it as the current one.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void ga_init_one(const GaArgs &g, int c, int lane)
+{
+    const uint64_t gen = g.gs[GS_GEN];
+    const int W = g.t.W, m = g.t.m, p = g.t.p;
+    uint64_t *dst = g.off[0] + (int64_t)c * W;
+    if (gen > 0 && (c % g.NT) == 0) {
+        const uint64_t *src = g.gmask + (int64_t)(c / g.NT) * W;
+        for (int w = lane; w < W; w += 64)
+            dst[w] = src[w];
+    } else {
+        // the subset's words live in the lanes: word w in lane w (w < 64)
+        // or in the second register of lane w - 64
+        uint64_t word0 = 0, word1 = 0;
+        uint64_t q[4];
+        int64_t base = 0;  // first block held by lane 0
+        philox_block(g.seed, ROLE_POPULATION, gen, (uint64_t)c,
+                     (TAG_SAMPLE << 32), (uint64_t)lane, q);
+        int64_t k = 0;  // next draw of the stream
+        auto draw = [&]() -> uint64_t {
+            if ((k >> 2) - base >= 64) {
+                base += 64;
+                philox_block(g.seed, ROLE_POPULATION, gen, (uint64_t)c,
+                             (TAG_SAMPLE << 32), (uint64_t)(base + lane), q);
+            }
+            const int src = (int)((k >> 2) - base), sel = (int)(k & 3);
+            const uint64_t mine = sel == 0 ? q[0] : sel == 1 ? q[1] : sel == 2 ? q[2] : q[3];
+            ++k;
+            return readlane64(mine, src);
+        };
+        for (int j = m - p; j < m; ++j) {
+            const uint64_t r = (uint64_t)j + 1;
+            uint64_t x = draw();
+            uint64_t lo = x * r;
+            if (lo < r) {
+                const uint64_t thresh = (0ull - r) % r;
+                while (lo < thresh) {
+                    x = draw();
+                    lo = x * r;
+                }
+            }
+            const int t = (int)__umul64hi(x, r);
+            const int tw = t >> 6;
+            const uint64_t held = lane == tw ? word0 : (lane + 64 == tw ? word1 : 0ull);
+            const bool taken =
+                __builtin_amdgcn_ballot_w64(((held >> (t & 63)) & 1ull) != 0ull) != 0ull;
+            const int pick = taken ? j : t;
+            const uint64_t bit = 1ull << (pick & 63);
+            if (lane == (pick >> 6))
+                word0 |= bit;
+            if (lane + 64 == (pick >> 6))
+                word1 |= bit;
+        }
+        if (lane < W)
+            dst[lane] = word0;
+        if (lane + 64 < W)
+            dst[lane + 64] = word1;
+    }
+    if (lane == 0) {
+        g.ok[0][c] = 1;
+        g.fit[0][c] = ~0ull;
+        g.improved[c] = 0;
+    }
+}
+
+// len (1..64) bits of A starting at bit pos, pos + len <= 64 * W.
+__device__ __forceinline__ uint64_t bits_at(const uint64_t *A, int W, int pos,
+                                            int len)
+{
+    const int w = pos >> 6, o = pos & 63;
+    uint64_t v = A[w] >> o;
+    if (o != 0 && w + 1 < W)
+        v |= A[w + 1] << (64 - o);
+    return len == 64 ? v : (v & ((1ull << len) - 1ull));
+}
+
+// `len` bits of the cyclic sequence A[lo..hi] starting at position s0
+// (lo <= s0 <= hi, len <= hi - lo + 1).
+__device__ __forceinline__ uint64_t cyclic_bits(const uint64_t *A, int W,
+                                                int lo, int hi, int s0,
+                                                int len)
+{
+    const int r = hi + 1 - s0;
+    if (len <= r)
+        return bits_at(A, W, s0, len);
+    return bits_at(A, W, s0, r) | (bits_at(A, W, lo, len - r) << r);
+}
+
+// ---------------------------------------------------------------------------
+// Crossover (Section 4.3) of own parent A with partner B, both as the
+// previous stage left them.  Walking from r1 and wrapping past the end,
+// turn off the first `quota` genes with A = 1, B = 0 and turn on the first
+// `quota` with A = 0, B = 1.  The walk is split into segments: the part of
+// word r1/64 from bit r1%64 up, the following words in cyclic order, and the
+// part of word r1/64 below bit r1%64.  A wave prefix sum of the per-segment
+// counts tells each lane how many qualifying genes come before its segment,
+// hence how many of its own to take (its lowest ones).  Returns false when
+// the parents differ in fewer than 2*quota genes (no offspring).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool crossover_wave(const uint64_t *A,
+                                               const uint64_t *B, uint64_t *F,
+                                               int W, int r1, int quota,
+                                               int lane)
+{
+    const int w0 = r1 >> 6, b0 = r1 & 63;
+    const uint64_t low_mask = b0 ? ((1ull << b0) - 1ull) : 0ull;
+    const uint64_t a0 = A[w0], bb0 = B[w0];
+    const uint64_t xl = a0 & ~bb0 & low_mask, yl = ~a0 & bb0 & low_mask;
+
+    uint64_t x[2] = {0, 0}, y[2] = {0, 0}, av[2] = {0, 0};
+    int wd[2] = {-1, -1};
+    uint32_t v[2] = {0, 0};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int r = lane + 64 * h;
+        if (r < W) {
+            int w = w0 + r;
+            if (w >= W)
+                w -= W;
+            const uint64_t seg = r == 0 ? (~0ull << b0) : ~0ull;
+            const uint64_t a = A[w], b = B[w];
+            x[h] = a & ~b & seg;
+            y[h] = ~a & b & seg;
+            av[h] = a;
+            wd[h] = w;
+            v[h] = (uint32_t)__builtin_popcountll(x[h]) |
+                   ((uint32_t)__builtin_popcountll(y[h]) << 16);
+        }
+    }
+    const uint32_t inc0 = wave_scan_incl(v[0], lane);
+    const uint32_t tot0 = (uint32_t)__builtin_amdgcn_readlane((int)inc0, 63);
+    const uint32_t inc1 = wave_scan_incl(v[1], lane) + tot0;
+    const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)inc1, 63);
+    const int main_x = (int)(tot & 0xFFFFu), main_y = (int)(tot >> 16);
+    const int differ = main_x + __builtin_popcountll(xl);
+    if (differ < quota)
+        return false;
+    const uint32_t inc[2] = {inc0, inc1};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        if (wd[h] < 0)
+            continue;
+        const uint32_t ex = inc[h] - v[h];
+        uint64_t take_x = lowest_bits(x[h], quota - (int)(ex & 0xFFFFu));
+        uint64_t take_y = lowest_bits(y[h], quota - (int)(ex >> 16));
+        if (lane + 64 * h == 0) {  // word r1/64 also holds the last segment
+            take_x |= lowest_bits(xl, quota - main_x);
+            take_y |= lowest_bits(yl, quota - main_y);
+        }
+        F[wd[h]] = (av[h] & ~take_x) | take_y;
+    }
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// Mutation (Section 4.4) of A into F: destination bit q takes source bit
+// lo + ((q - lo - move) mod L) inside the rotated range [lo, hi] of length
+// L, and source bit q outside it.  Each lane builds its destination words
+// from at most two runs of source bits.  Returns whether F differs from A.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool mutate_wave(const uint64_t *A, uint64_t *F,
+                                            int W, int m, int lo, int hi,
+                                            int move, int lane)
+{
+    const int L = hi - lo + 1;
+    bool changed = false;
+    for (int w = lane; w < W; w += 64) {
+        const int q0 = w * 64;
+        const int q1 = min(m, q0 + 64);
+        uint64_t val = A[w];
+        const int qa = max(q0, lo), qb = min(q1, hi + 1);
+        if (qa < qb) {
+            const int nin = qb - qa;
+            const int s0 = lo + (((qa - lo - move) % L) + L) % L;
+            const uint64_t part = cyclic_bits(A, W, lo, hi, s0, nin);
+            const uint64_t mask =
+                (nin == 64 ? ~0ull : ((1ull << nin) - 1ull)) << (qa - q0);
+            val = (val & ~mask) | (part << (qa - q0));
+        }
+        changed |= val != A[w];
+        F[w] = val;
+    }
+    return __builtin_amdgcn_ballot_w64(changed) != 0ull;
+}
+
+// ---------------------------------------------------------------------------
+// One stage (Evolve steps 3 and 5) for chromosome c, by its wave.  Finish
+// the previous operator (take the evaluated offspring if strictly fitter:
+// Evolve steps 3e and 5c), then start operator `op`:
+//  - crossover stage `index`: stride NT >> (1 + index mod lg NT), partner
+//    c XOR stride; the pair's lower slot owns the draws r1 in [0, m) and
+//    i in [1, floor(p/2)] (Section 4.3);
+//  - mutation attempt `index`: skipped once the cycle has improved c;
+//    draws type, direction, then the amount s in [1, m-1] or the block ends
+//    (a uniform pair of distinct positions) and s in [1, b - a]; an
+//    offspring equal to its parent is not evaluated (Section 4.4).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
+                                             int in, int prev, int op,
+                                             int index)
+{
+    const int out = in ^ 1;
+    const int W = g.t.W, m = g.t.m;
+    const uint64_t gen = g.gs[GS_GEN];
+
+    // finish the previous operator (for a crossover, the partner's too: its
+    // state as this stage leaves it is the other parent)
+    const int pc = op == OP_XOVER ? (c ^ (g.NT >> (1 + index % g.lg))) : c;
+    const bool okc = buf(g.ok, in)[c] != 0;
+    const bool okp = op == OP_XOVER && buf(g.ok, in)[pc] != 0;
+    const unsigned long long fin = buf(g.fit, in)[c];
+    const unsigned long long fpin = buf(g.fit, in)[pc];
+    unsigned long long fo = 0, scan = 0, fop = 0;
+    offspring_costs(g, c, okc, pc, okp, lane, &fo, &scan, &fop);
+    const bool take = okc && fo < fin;
+    const uint64_t *A = (take ? buf(g.off, in) : buf(g.cur, in)) + (int64_t)c * W;
+    uint64_t *cur = buf(g.cur, out) + (int64_t)c * W;
+    for (int w = lane; w < W; w += 64)
+        cur[w] = A[w];
+    const bool improved = g.improved[c] || (prev == OP_MUT && take);
+    if (lane == 0) {
+        buf(g.fit, out)[c] = take ? fo : fin;
+        unsigned long long *cs = g.cstat + (int64_t)c * CS_COUNT;
+        if (okc) {
+            cs[CS_EVALS] += 1;
+            cs[CS_SCAN] += scan;
+        }
+        if (take && prev == OP_XOVER)
+            cs[CS_XO_TAKEN] += 1;
+        if (take && prev == OP_MUT) {
+            cs[CS_MUT_TAKEN] += 1;
+            g.improved[c] = 1;
+        }
+    }
+
+    uint64_t *F = buf(g.off, out) + (int64_t)c * W;
+    bool ok = false;
+    if (op == OP_XOVER) {
+        const bool ptake = okp && fop < fpin;
+        const uint64_t *B = (ptake ? buf(g.off, in) : buf(g.cur, in)) + (int64_t)pc * W;
+        const int leader = c < pc ? c : pc;
+        PhiloxStream st(g.seed, ROLE_EVOLVE, gen, (uint64_t)leader, TAG_CROSSOVER,
+                        (uint64_t)index);
+        const int r1 = (int)st.below((uint64_t)m);
+        const int quota = 1 + (int)st.below((uint64_t)(g.t.p / 2));
+        ok = crossover_wave(A, B, F, W, r1, quota, lane);
+        if (lane == 0 && !ok)
+            g.cstat[(int64_t)c * CS_COUNT + CS_XO_FAIL] += 1;
+    } else if (op == OP_MUT && !improved) {
+        PhiloxStream st(g.seed, ROLE_EVOLVE, gen, (uint64_t)c, TAG_MUTATION,
+                        (uint64_t)index);
+        const int type = (int)st.below(2);
+        const int dir = (int)st.below(2);
+        int lo = 0, hi = m - 1;
+        if (type != 0) {
+            const int x = (int)st.below((uint64_t)m);
+            int y = (int)st.below((uint64_t)(m - 1));
+            if (y >= x)
+                ++y;
+            lo = x < y ? x : y;
+            hi = x < y ? y : x;
+        }
+        const int L = hi - lo + 1;
+        const int s = 1 + (int)st.below((uint64_t)(L - 1));
+        ok = mutate_wave(A, F, W, m, lo, hi, dir == 0 ? s : L - s, lane);
+    }
+    if (lane == 0)
+        buf(g.ok, out)[c] = ok ? 1 : 0;
+}
+
+// Operator finished (prev) and started (op) by stage step k of a generation
+// with X crossover stages and S = X + Y stages, and the operator's index.
+__device__ __host__ __forceinline__ void ga_stage_ops(int k, int X, int S,
+                                                      int *prev, int *op,
+                                                      int *index)
+{
+    *prev = k == 0 ? OP_INIT : (k - 1 < X ? OP_XOVER : OP_MUT);
+    *op = k == S ? OP_NONE : (k < X ? OP_XOVER : OP_MUT);
+    *index = k < X ? k : k - X;
+}
+
+// Reduce (cost, index) pairs of a workgroup to the least cost, lowest index
+// on ties.  All threads call it; the result is in sc[0], si[0].
+__device__ __forceinline__ void block_argmin(unsigned long long f, int idx,
+                                             unsigned long long *sc, int *si)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nwaves = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        const unsigned long long of = __shfl_xor(f, d);
+        const int oi = __shfl_xor(idx, d);
+        if (of < f || (of == f && oi < idx)) {
+            f = of;
+            idx = oi;
+        }
+    }
+    __syncthreads();
+    if (lane == 0) {
+        sc[wave] = f;
+        si[wave] = idx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < nwaves; ++w)
+            if (sc[w] < sc[0] || (sc[w] == sc[0] && si[w] < si[0])) {
+                sc[0] = sc[w];
+                si[0] = si[w];
+            }
+    }
+    __syncthreads();
+}
+
+// Group best of group b (Evolve steps 7-8: least fitness, lowest slot on
+// ties) from population buffer fb, by a whole workgroup.
+__device__ __forceinline__ void ga_group_best(const GaArgs &g, int fb, int b,
+                                              unsigned long long *sc, int *si)
+{
+    unsigned long long f = ~0ull;
+    int idx = 0x7FFFFFFF;
+    for (int t = threadIdx.x; t < g.NT; t += blockDim.x) {
+        const unsigned long long v = buf(g.fit, fb)[(int64_t)b * g.NT + t];
+        if (v < f) {  // t ascends per thread: keeps the lowest slot
+            f = v;
+            idx = t;
+        }
+    }
+    block_argmin(f, idx, sc, si);
+    const int W = g.t.W;
+    const uint64_t *src = buf(g.cur, fb) + ((int64_t)b * g.NT + si[0]) * W;
+    for (int w = threadIdx.x; w < W; w += blockDim.x)
+        g.gmask[(int64_t)b * W + w] = src[w];
+    if (threadIdx.x == 0)
+        g.gcost[b] = sc[0];
+}
+
+// Global best, saturation count and stop test (Section 3.1 host steps
+// 13-15), by one workgroup once every group best is written and visible.
+__device__ __forceinline__ void ga_global(const GaArgs &g,
+                                          unsigned long long *sc, int *si)
+{
+    unsigned long long f = ~0ull;
+    int idx = 0x7FFFFFFF;
+    for (int k = threadIdx.x; k < g.NB; k += blockDim.x) {
+        const unsigned long long v =
+            __hip_atomic_load(g.gcost + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (v < f) {
+            f = v;
+            idx = k;
+        }
+    }
+    block_argmin(f, idx, sc, si);
+    const bool better = sc[0] < g.gs[GS_BEST];
+    const int W = g.t.W;
+    if (better)
+        for (int w = threadIdx.x; w < W; w += blockDim.x)
+            g.best_mask[w] = __hip_atomic_load(g.gmask + (int64_t)si[0] * W + w,
+                                               __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (better) {
+            g.gs[GS_BEST] = sc[0];
+            g.gs[GS_SAT] = 0;
+        } else {
+            g.gs[GS_SAT] += 1;
+        }
+        const unsigned long long gen = g.gs[GS_GEN] + 1;
+        g.gs[GS_GEN] = gen;
+        if ((g.saturation > 0 && g.gs[GS_SAT] >= (unsigned long long)g.saturation) ||
+            gen >= (unsigned long long)g.generations)
+            g.gs[GS_DONE] = 1;
+    }
+}
+
+}  // namespace pmp

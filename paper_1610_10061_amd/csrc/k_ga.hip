@@ -1,394 +1,311 @@
-// Genetic-algorithm kernels (Section 3.2 Evolve steps, Section 4 operators).
+// Genetic-algorithm kernels.  Two launch schemes run the same device code
+// (ga_device.hpp, eval_device.hpp):
 //
-// One thread owns one chromosome (W 64-bit words in global memory).  The
-// operators work on whole words: population sampling sets p bits, crossover
-// selects bits with popcounts and lowest-set-bit extraction, mutation moves
-// runs of up to 64 bits at a time.  Fitness is computed by the population
-// evaluation kernel between these steps.  Every kernel first reads the
-// run's stop flag, so generations enqueued after the stop do nothing.
-#include "common.hpp"
-#include "philox.hpp"
+//  - one kernel per step: k_init, the evaluation kernel, k_stage for each
+//    stage, k_best; ordered by the stream.
+//  - k_ga_persistent: one cooperative launch runs whole generations; its
+//    phases are separated by grid barriers, which removes the per-launch
+//    gaps and prologues that dominate at a few microseconds of work per
+//    stage.
+#include "eval_device.hpp"
+#include "ga_device.hpp"
 
 namespace pmp {
 
 namespace {
 
-constexpr int kGaThreads = 64;
-
-__device__ __forceinline__ bool stopped(const GaArgs &g)
+__global__ __launch_bounds__(64 * kGaWaves) void k_init(GaArgs g)
 {
-    return g.gs[GS_DONE] != 0ull;
-}
-
-__device__ __forceinline__ void count(unsigned long long *slot, bool pred)
-{
-    const uint64_t b = __builtin_amdgcn_ballot_w64(pred);
-    if ((threadIdx.x & 63) == 0 && b)
-        atomicAdd(slot, (unsigned long long)__builtin_popcountll(b));
-}
-
-// ---------------------------------------------------------------------------
-// Population of one Evolve call (Section 3.1 steps 7/11 and 16; Section 4.1
-// and 4.5).  Fresh slots get a uniform p-subset by Floyd's method
-// (Bentley & Floyd, CACM 1987): for j = m-p .. m-1 draw t uniform in [0, j];
-// take t, or j if t is already taken.  From the second generation on, slot
-// b*NT of group b receives that group's best of the previous generation.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kGaThreads) void k_init(GaArgs g)
-{
-    const int c = blockIdx.x * kGaThreads + threadIdx.x;
-    if (c >= g.P || stopped(g))
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int c = blockIdx.x * kGaWaves + wave;
+    if (c >= g.P || ga_stopped(g))
         return;
-    const uint64_t gen = g.gs[GS_GEN];
-    const int W = g.t.W;
-    uint64_t *row = g.cur + (int64_t)c * W;
-    if (gen > 0 && (c % g.NT) == 0) {
-        const uint64_t *src = g.gmask + (int64_t)(c / g.NT) * W;
-        for (int w = 0; w < W; ++w)
-            row[w] = src[w];
-    } else {
-        for (int w = 0; w < W; ++w)
-            row[w] = 0;
-        PhiloxStream st(g.seed, ROLE_POPULATION, gen, (uint64_t)c, TAG_SAMPLE, 0);
-        for (int j = g.t.m - g.t.p; j < g.t.m; ++j) {
-            const int t = (int)st.below((uint64_t)j + 1);
-            const bool taken = (row[t >> 6] >> (t & 63)) & 1ull;
-            const int pick = taken ? j : t;
-            row[pick >> 6] |= 1ull << (pick & 63);
-        }
-    }
-    g.fit[c] = 0;
-    g.ok[c] = 1;
-    g.improved[c] = 0;
+    ga_init_one(g, c, lane);
 }
 
-// Turn off (own=1, other=0) or on (own=0, other=1) the first `quota`
-// positions of that kind met when walking from r1 and wrapping past the
-// end.  Words are visited in that cyclic order; inside a word the lowest
-// qualifying bits come first.
-__device__ __forceinline__ void exchange_first(const uint64_t *A,
-                                               const uint64_t *B, uint64_t *F,
-                                               int W, int r1, int quota,
-                                               bool turn_off)
+__global__ __launch_bounds__(64 * kGaWaves) void k_stage(GaArgs g, int in,
+                                                         int prev, int op,
+                                                         int index)
 {
-    const int w0 = r1 >> 6, b0 = r1 & 63;
-    int left = quota;
-    for (int t = 0; t <= W && left > 0; ++t) {
-        const int w = (w0 + t) % W;
-        uint64_t seg;
-        if (t == 0)
-            seg = ~0ull << b0;
-        else if (t == W)
-            seg = b0 ? ((1ull << b0) - 1ull) : 0ull;
-        else
-            seg = ~0ull;
-        uint64_t cand = (turn_off ? (A[w] & ~B[w]) : (~A[w] & B[w])) & seg;
-        const int cnt = __builtin_popcountll(cand);
-        uint64_t take;
-        if (cnt <= left) {
-            take = cand;
-            left -= cnt;
-        } else {
-            take = 0;
-            for (int r = 0; r < left; ++r) {
-                const uint64_t low = cand & (0ull - cand);
-                take |= low;
-                cand ^= low;
-            }
-            left = 0;
-        }
-        if (turn_off)
-            F[w] &= ~take;
-        else
-            F[w] |= take;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Crossover stage (Evolve step 3; Section 4.3).  Slot t pairs with
-// t XOR stride inside its group; the pair's lower slot owns the draws
-// r1 in [0, m) and i in [1, floor(p/2)].  Offspring = own parent with the
-// first i "own 1, partner 0" genes turned off and the first i "own 0,
-// partner 1" genes turned on, walking from r1.  Too few differing genes:
-// no offspring.  The current population is only read here, so both
-// partners see each other as the stage began.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kGaThreads) void k_crossover(GaArgs g, int stage)
-{
-    const int c = blockIdx.x * kGaThreads + threadIdx.x;
-    if (c >= g.P || stopped(g))
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int c = blockIdx.x * kGaWaves + wave;
+    if (c >= g.P || ga_stopped(g))
         return;
-    const uint64_t gen = g.gs[GS_GEN];
-    const int W = g.t.W;
-    const int stride = g.NT >> (1 + stage % g.lg);
-    const int partner = c ^ stride;
-    const int leader = c < partner ? c : partner;
-    PhiloxStream st(g.seed, ROLE_EVOLVE, gen, (uint64_t)leader, TAG_CROSSOVER,
-                    (uint64_t)stage);
-    const int r1 = (int)st.below((uint64_t)g.t.m);
-    const int quota = 1 + (int)st.below((uint64_t)(g.t.p / 2));
-
-    const uint64_t *A = g.cur + (int64_t)c * W;
-    const uint64_t *B = g.cur + (int64_t)partner * W;
-    uint64_t *F = g.off + (int64_t)c * W;
-    int differ = 0;
-    for (int w = 0; w < W; ++w)
-        differ += __builtin_popcountll(A[w] & ~B[w]);
-    const bool ok = differ >= quota;
-    if (ok) {
-        for (int w = 0; w < W; ++w)
-            F[w] = A[w];
-        exchange_first(A, B, F, W, r1, quota, true);
-        exchange_first(A, B, F, W, r1, quota, false);
-    }
-    g.ok[c] = ok ? 1 : 0;
-    g.ofit[c] = 0;
-    count(g.gs + GS_XO_FAIL, !ok);
+    ga_stage_one(g, c, lane, in, prev, op, index);
 }
 
-// len (1..64) bits of A starting at bit pos, pos + len <= 64 * W.
-__device__ __forceinline__ uint64_t bits_at(const uint64_t *A, int W, int pos,
-                                            int len)
+// Group best per workgroup; the last workgroup to finish does the global
+// update (release fence before the arrival count, acquire fence after).
+__global__ __launch_bounds__(1024) void k_best(GaArgs g, int fb)
 {
-    const int w = pos >> 6, o = pos & 63;
-    uint64_t v = A[w] >> o;
-    if (o != 0 && w + 1 < W)
-        v |= A[w + 1] << (64 - o);
-    return len == 64 ? v : (v & ((1ull << len) - 1ull));
-}
-
-// `len` bits of the cyclic sequence A[lo..hi] starting at position s0
-// (lo <= s0 <= hi, len <= hi - lo + 1).
-__device__ __forceinline__ uint64_t cyclic_bits(const uint64_t *A, int W,
-                                                int lo, int hi, int s0,
-                                                int len)
-{
-    const int r = hi + 1 - s0;
-    if (len <= r)
-        return bits_at(A, W, s0, len);
-    return bits_at(A, W, s0, r) | (bits_at(A, W, lo, len - r) << r);
-}
-
-// ---------------------------------------------------------------------------
-// Mutation attempt (Evolve step 5; Section 4.4).  Draws, in order: type
-// (circular or block shift), direction (right = toward higher index), then
-// the amount s in [1, m-1] for a circular shift, or the block ends (a
-// uniform pair of distinct positions a < b) and s in [1, b-a].  The offspring
-// is built word by word: destination bit q takes source bit
-// lo + ((q - lo - move) mod L) inside the rotated range [lo, hi] of length
-// L, and source bit q outside it.  Chromosomes already improved in this
-// cycle, and offspring equal to their parent, are not evaluated.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kGaThreads) void k_mutate(GaArgs g, int attempt)
-{
-    const int c = blockIdx.x * kGaThreads + threadIdx.x;
-    if (c >= g.P || stopped(g))
+    __shared__ unsigned long long sc[16];
+    __shared__ int si[16];
+    __shared__ int last;
+    if (ga_stopped(g))
         return;
-    if (g.improved[c]) {
-        g.ok[c] = 0;
-        return;
-    }
-    const uint64_t gen = g.gs[GS_GEN];
-    const int W = g.t.W, m = g.t.m;
-    PhiloxStream st(g.seed, ROLE_EVOLVE, gen, (uint64_t)c, TAG_MUTATION,
-                    (uint64_t)attempt);
-    const int type = (int)st.below(2);
-    const int dir = (int)st.below(2);
-    int lo, hi;
-    if (type == 0) {
-        lo = 0;
-        hi = m - 1;
-    } else {
-        const int x = (int)st.below((uint64_t)m);
-        int y = (int)st.below((uint64_t)(m - 1));
-        if (y >= x)
-            ++y;
-        lo = x < y ? x : y;
-        hi = x < y ? y : x;
-    }
-    const int L = hi - lo + 1;
-    const int s = 1 + (int)st.below((uint64_t)(L - 1));
-    const int move = dir == 0 ? s : L - s;
-
-    const uint64_t *A = g.cur + (int64_t)c * W;
-    uint64_t *F = g.off + (int64_t)c * W;
-    bool changed = false;
-    for (int w = 0; w < W; ++w) {
-        const int q0 = w * 64;
-        const int q1 = min(m, q0 + 64);
-        uint64_t v = A[w];
-        const int qa = max(q0, lo), qb = min(q1, hi + 1);
-        if (qa < qb) {
-            const int nin = qb - qa;
-            const int s0 = lo + (((qa - lo - move) % L) + L) % L;
-            const uint64_t part = cyclic_bits(A, W, lo, hi, s0, nin);
-            const uint64_t mask =
-                (nin == 64 ? ~0ull : ((1ull << nin) - 1ull)) << (qa - q0);
-            v = (v & ~mask) | (part << (qa - q0));
-        }
-        F[w] = v;
-        changed |= v != A[w];
-    }
-    g.ok[c] = changed ? 1 : 0;
-    g.ofit[c] = 0;
-}
-
-// Replace a parent by its offspring when strictly fitter (Evolve steps 3e
-// and 5c).
-__global__ __launch_bounds__(kGaThreads) void k_accept(GaArgs g, int mutation)
-{
-    const int c = blockIdx.x * kGaThreads + threadIdx.x;
-    const bool live = c < g.P && !stopped(g);
-    bool take = false;
-    if (live && g.ok[c] && g.ofit[c] < g.fit[c]) {
-        take = true;
-        const int W = g.t.W;
-        const uint64_t *F = g.off + (int64_t)c * W;
-        uint64_t *A = g.cur + (int64_t)c * W;
-        for (int w = 0; w < W; ++w)
-            A[w] = F[w];
-        g.fit[c] = g.ofit[c];
-        if (mutation)
-            g.improved[c] = 1;
-    }
-    count(g.gs + (mutation ? GS_MUT_TAKEN : GS_XO_TAKEN), take);
-}
-
-// Group best (Evolve steps 7-8): least fitness, lowest slot on ties.
-__global__ __launch_bounds__(256) void k_group_best(GaArgs g)
-{
-    if (stopped(g))
-        return;
-    __shared__ unsigned long long sc[256];
-    __shared__ int si[256];
-    const int b = blockIdx.x;
-    const int base = b * g.NT;
-    unsigned long long bc = ~0ull;
-    int bi = 0x7FFFFFFF;
-    for (int t = threadIdx.x; t < g.NT; t += 256) {
-        const unsigned long long f = g.fit[base + t];
-        if (f < bc) {  // t ascends per thread: keeps the lowest slot
-            bc = f;
-            bi = t;
-        }
-    }
-    sc[threadIdx.x] = bc;
-    si[threadIdx.x] = bi;
+    ga_group_best(g, fb, blockIdx.x, sc, si);
+    __threadfence();
     __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (threadIdx.x < h) {
-            const unsigned long long oc = sc[threadIdx.x + h];
-            const int oi = si[threadIdx.x + h];
-            if (oc < sc[threadIdx.x] || (oc == sc[threadIdx.x] && oi < si[threadIdx.x])) {
-                sc[threadIdx.x] = oc;
-                si[threadIdx.x] = oi;
+    if (threadIdx.x == 0)
+        last = atomicAdd(g.arrive, 1u) == (uint32_t)(g.NB - 1);
+    __syncthreads();
+    if (!last)
+        return;
+    __threadfence();
+    ga_global(g, sc, si);
+    if (threadIdx.x == 0)
+        *g.arrive = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Grid barrier of the persistent kernel, without a contended counter: each
+// workgroup publishes its writes (agent-scope release) and then stores the
+// barrier's epoch number into its own flag (its own 128-byte line);
+// workgroup 0's threads wait until every flag shows the epoch and then store
+// it into the shared epoch word, which the other workgroups wait on.  Every
+// workgroup passes the same sequence of barriers, so each knows the epoch
+// number it is waiting for.  Waits are bounded by the 100 MHz real-time
+// clock: past the bound (only if some workgroup never arrives) the error
+// word records it and every later barrier and loop of the kernel returns at
+// once, so the grid always drains.
+// ---------------------------------------------------------------------------
+constexpr uint64_t kBarrierTicks = 200000000ull;  // 2 s at 100 MHz
+constexpr int kFlagStride = 32;                   // words between flags
+
+__device__ __forceinline__ uint32_t load_agent(const uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until *p == want; false on timeout (and the error is recorded).
+__device__ __forceinline__ bool wait_for(const uint32_t *p, uint32_t want,
+                                         uint32_t *err)
+{
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    while (load_agent(p) != want) {
+        __builtin_amdgcn_s_sleep(1);
+        if (__builtin_amdgcn_s_memrealtime() - t0 > kBarrierTicks) {
+            atomicOr(err, ERR_BARRIER_TIMEOUT);
+            return false;
+        }
+    }
+    return true;
+}
+
+struct GridBarrier {
+    uint32_t *epoch;  // bar[0]
+    uint32_t *flags;  // bar + kFlagStride, one per workgroup
+    uint32_t next;    // epoch number of the next barrier
+
+    __device__ __forceinline__ explicit GridBarrier(uint32_t *bar)
+        : epoch(bar), flags(bar + kFlagStride), next(load_agent(bar) + 1u)
+    {
+    }
+
+    __device__ __forceinline__ bool sync(const GaArgs &g, int *flag)
+    {
+        __syncthreads();
+        const uint32_t want = next++;
+        if (threadIdx.x == 0) {
+            int ok = (load_agent(g.err) & ERR_BARRIER_TIMEOUT) == 0;
+            if (ok) {
+                // publish this workgroup's writes (L2 write-back), then arrive
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                __hip_atomic_store(flags + (size_t)blockIdx.x * kFlagStride, want,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
+            *flag = ok;
         }
         __syncthreads();
+        if (!*flag)
+            return false;
+        if (blockIdx.x == 0) {
+            int ok = 1;
+            for (int b = threadIdx.x; b < (int)gridDim.x && ok; b += blockDim.x)
+                ok = wait_for(flags + (size_t)b * kFlagStride, want, g.err);
+            if (!ok)
+                *flag = 0;
+            __syncthreads();
+            if (threadIdx.x == 0 && *flag)
+                __hip_atomic_store(epoch, want, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else if (threadIdx.x == 0) {
+            if (!wait_for(epoch, want, g.err))
+                *flag = 0;
+        }
+        if (threadIdx.x == 0)  // see the other workgroups' writes (L2 invalidate)
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __syncthreads();
+        return *flag != 0;
     }
-    const int W = g.t.W;
-    const uint64_t *src = g.cur + (int64_t)(base + si[0]) * W;
-    for (int w = threadIdx.x; w < W; w += 256)
-        g.gmask[(int64_t)b * W + w] = src[w];
-    if (threadIdx.x == 0)
-        g.gcost[b] = sc[0];
+};
+
+// Evaluation phase: the (client tile, chromosome tile) items, client-tile
+// major, are cut into 8 contiguous ranges; the workgroups of XCD x (block
+// index = x mod 8) take range x, so chromosome tiles sharing Pi' rows share
+// an L2.
+template <int WD>
+__device__ __forceinline__ void eval_phase(const EvalArgs &e, uint32_t *smask,
+                                           unsigned long long *sred)
+{
+    const int ntiles = e.tiles_c * e.tiles_i;
+    const int chunk = (ntiles + 7) / 8;
+    const int x = blockIdx.x & 7, per = (int)gridDim.x >> 3;
+    const int end = min(ntiles, (x + 1) * chunk);
+    for (int item = x * chunk + ((int)blockIdx.x >> 3); item < end; item += per) {
+        const int ti = item / e.tiles_c;
+        eval_tile<WD>(e, ti, item - ti * e.tiles_c, smask, sred);
+    }
 }
 
-// Global best, saturation and stop (Section 3.1 host steps 13-15).
-__global__ __launch_bounds__(256) void k_global(GaArgs g)
+template <int WD>
+__global__ __launch_bounds__(64 * kGaWaves) void k_ga_persistent(GaArgs g,
+                                                                 EvalArgs e,
+                                                                 int generations)
 {
-    if (stopped(g))
-        return;
-    __shared__ unsigned long long sc[256];
-    __shared__ int si[256];
-    __shared__ int improved;
-    unsigned long long bc = ~0ull;
-    int bi = 0x7FFFFFFF;
-    for (int b = threadIdx.x; b < g.NB; b += 256) {
-        const unsigned long long f = g.gcost[b];
-        if (f < bc) {
-            bc = f;
-            bi = b;
-        }
-    }
-    sc[threadIdx.x] = bc;
-    si[threadIdx.x] = bi;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (threadIdx.x < h) {
-            const unsigned long long oc = sc[threadIdx.x + h];
-            const int oi = si[threadIdx.x + h];
-            if (oc < sc[threadIdx.x] || (oc == sc[threadIdx.x] && oi < si[threadIdx.x])) {
-                sc[threadIdx.x] = oc;
-                si[threadIdx.x] = oi;
+    extern __shared__ uint64_t lds[];
+    uint32_t *smask = reinterpret_cast<uint32_t *>(lds);
+    unsigned long long *sred =
+        reinterpret_cast<unsigned long long *>(lds + (kEvalTile * WD) / 2);
+    __shared__ unsigned long long sc[16];
+    __shared__ int si[16];
+    __shared__ int flag;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int gw = blockIdx.x * kGaWaves + wave, nw = gridDim.x * kGaWaves;
+    const int X = ga_xstages(g), S = X + g.Y;
+    const int fb = (S % 2) ^ 1;
+    GridBarrier bar(g.bar);
+
+    for (int gen = 0; gen < generations; ++gen) {
+        if (ga_stopped(g))
+            return;
+        for (int c = gw; c < g.P; c += nw)
+            ga_init_one(g, c, lane);
+        if (!bar.sync(g, &flag))
+            return;
+        e.masks = g.off[0];
+        e.active = g.ok[0];
+        eval_phase<WD>(e, smask, sred);
+        if (!bar.sync(g, &flag))
+            return;
+        for (int k = 0; k <= S; ++k) {
+            int prev, op, index;
+            ga_stage_ops(k, X, S, &prev, &op, &index);
+            for (int c = gw; c < g.P; c += nw)
+                ga_stage_one(g, c, lane, k & 1, prev, op, index);
+            if (!bar.sync(g, &flag))
+                return;
+            if (op != OP_NONE) {
+                e.masks = buf(g.off, (k & 1) ^ 1);
+                e.active = buf(g.ok, (k & 1) ^ 1);
+                eval_phase<WD>(e, smask, sred);
+                if (!bar.sync(g, &flag))
+                    return;
             }
         }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0)
-        improved = sc[0] < g.gs[GS_BEST];
-    __syncthreads();
-    const int W = g.t.W;
-    if (improved)
-        for (int w = threadIdx.x; w < W; w += 256)
-            g.best_mask[w] = g.gmask[(int64_t)si[0] * W + w];
-    if (threadIdx.x == 0) {
-        if (improved) {
-            g.gs[GS_BEST] = sc[0];
-            g.gs[GS_SAT] = 0;
-        } else {
-            g.gs[GS_SAT] += 1;
-        }
-        const unsigned long long gen = g.gs[GS_GEN] + 1;
-        g.gs[GS_GEN] = gen;
-        if ((g.saturation > 0 && g.gs[GS_SAT] >= (unsigned long long)g.saturation) ||
-            gen >= (unsigned long long)g.generations)
-            g.gs[GS_DONE] = 1;
+        for (int b = blockIdx.x; b < g.NB; b += gridDim.x)
+            ga_group_best(g, fb, b, sc, si);
+        if (!bar.sync(g, &flag))
+            return;
+        if (blockIdx.x == 0)
+            ga_global(g, sc, si);
+        if (!bar.sync(g, &flag))
+            return;
     }
 }
 
-inline dim3 per_chromosome(int P)
+inline dim3 per_wave(int P)
 {
-    return dim3((unsigned)((P + kGaThreads - 1) / kGaThreads));
+    return dim3((unsigned)((P + kGaWaves - 1) / kGaWaves));
+}
+
+template <int WD>
+size_t persistent_lds()
+{
+    const size_t eval = sizeof(uint32_t) * kEvalTile * WD +
+                        sizeof(unsigned long long) * 2 * kEvalWaves * kEvalTile;
+    return eval;
+}
+
+template <int WD>
+hipError_t persistent_wd(const GaArgs &g, const EvalArgs &e, int generations,
+                         int max_blocks, hipStream_t s, int *grid_out)
+{
+    auto fn = k_ga_persistent<WD>;
+    const size_t lds = persistent_lds<WD>();
+    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)lds);
+    if (err != hipSuccess)
+        return err;
+    int per_cu = 0, dev = 0, cus = 0;
+    err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * kGaWaves, lds);
+    if (err == hipSuccess)
+        err = hipGetDevice(&dev);
+    if (err == hipSuccess)
+        err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (err != hipSuccess)
+        return err;
+    if (per_cu < 1)
+        return hipErrorInvalidConfiguration;
+    // enough workgroups for the widest phase, no more than fit at once
+    const int want = max(e.tiles_c * e.tiles_i, max((g.P + kGaWaves - 1) / kGaWaves, g.NB));
+    int grid = min(want, min(per_cu, 4) * cus);
+    if (max_blocks > 0)
+        grid = min(grid, max_blocks);
+    grid = max(8, (grid / 8) * 8);
+    if (grid > per_cu * cus || grid > kMaxPersistentBlocks)
+        return hipErrorInvalidConfiguration;
+    *grid_out = grid;
+    GaArgs ga = g;
+    EvalArgs ea = e;
+    int gens = generations;
+    void *args[] = {&ga, &ea, &gens};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(fn), dim3(grid),
+                                      dim3(64 * kGaWaves), args, (unsigned)lds, s);
 }
 
 }  // namespace
 
 hipError_t launch_ga_init(const GaArgs &g, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_init, per_chromosome(g.P), dim3(kGaThreads), 0, s, g);
+    hipLaunchKernelGGL(k_init, per_wave(g.P), dim3(64 * kGaWaves), 0, s, g);
     return hipGetLastError();
 }
 
-hipError_t launch_ga_crossover(const GaArgs &g, int stage, hipStream_t s)
+hipError_t launch_ga_stage(const GaArgs &g, int in, int prev, int op, int index,
+                           hipStream_t s)
 {
-    hipLaunchKernelGGL(k_crossover, per_chromosome(g.P), dim3(kGaThreads), 0, s,
-                       g, stage);
+    hipLaunchKernelGGL(k_stage, per_wave(g.P), dim3(64 * kGaWaves), 0, s, g, in,
+                       prev, op, index);
     return hipGetLastError();
 }
 
-hipError_t launch_ga_mutate(const GaArgs &g, int attempt, hipStream_t s)
+hipError_t launch_ga_best(const GaArgs &g, int fb, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_mutate, per_chromosome(g.P), dim3(kGaThreads), 0, s, g,
-                       attempt);
+    const int threads = ((g.NT + 63) / 64) * 64;
+    hipLaunchKernelGGL(k_best, dim3(g.NB), dim3(threads < 64 ? 64 : threads), 0, s,
+                       g, fb);
     return hipGetLastError();
 }
 
-hipError_t launch_ga_accept(const GaArgs &g, int mutation, hipStream_t s)
+hipError_t launch_ga_persistent(const GaArgs &g, const EvalArgs &e,
+                                int generations, int max_blocks, hipStream_t s,
+                                int *grid)
 {
-    hipLaunchKernelGGL(k_accept, per_chromosome(g.P), dim3(kGaThreads), 0, s, g,
-                       mutation);
-    return hipGetLastError();
-}
-
-hipError_t launch_ga_best(const GaArgs &g, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_group_best, dim3(g.NB), dim3(256), 0, s, g);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess)
-        return e;
-    hipLaunchKernelGGL(k_global, dim3(1), dim3(256), 0, s, g);
-    return hipGetLastError();
+    const int w2 = 2 * g.t.W;
+    if (w2 <= 2) return persistent_wd<2>(g, e, generations, max_blocks, s, grid);
+    if (w2 <= 4) return persistent_wd<4>(g, e, generations, max_blocks, s, grid);
+    if (w2 <= 8) return persistent_wd<8>(g, e, generations, max_blocks, s, grid);
+    if (w2 <= 16) return persistent_wd<16>(g, e, generations, max_blocks, s, grid);
+    if (w2 <= 32) return persistent_wd<32>(g, e, generations, max_blocks, s, grid);
+    if (w2 <= 48) return persistent_wd<48>(g, e, generations, max_blocks, s, grid);
+    if (w2 <= 64) return persistent_wd<64>(g, e, generations, max_blocks, s, grid);
+    if (w2 <= 96) return persistent_wd<96>(g, e, generations, max_blocks, s, grid);
+    if (w2 <= 128) return persistent_wd<128>(g, e, generations, max_blocks, s, grid);
+    if (w2 <= 160) return persistent_wd<160>(g, e, generations, max_blocks, s, grid);
+    if (w2 <= 192) return persistent_wd<192>(g, e, generations, max_blocks, s, grid);
+    if (w2 <= 256) return persistent_wd<256>(g, e, generations, max_blocks, s, grid);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace pmp

@@ -58,7 +58,9 @@ struct PhiloxStream {
     __device__ __forceinline__ uint64_t next()
     {
         if (used == 4) refill();
-        return buf[used++];
+        // select, not buf[used]: a run-time index would put buf in scratch
+        const int k = used++;
+        return k == 0 ? buf[0] : k == 1 ? buf[1] : k == 2 ? buf[2] : buf[3];
     }
 
     // Uniform integer in [0, r), r >= 1 (Lemire, ACM TOMACS 2019): the high

@@ -81,6 +81,8 @@ int clients_per_block(int n, int P)
 
 pmp_status status_from_err(uint32_t e)
 {
+    if (e & ERR_BARRIER_TIMEOUT)
+        return fail(PMP_EDEVICE, "a grid barrier of the GA kernel timed out");
     if (e & ERR_NEGATIVE_DISTANCE)
         return fail(PMP_EINVAL, "negative distance in d");
     if (e & (ERR_POPCOUNT | ERR_STRAY_BITS | ERR_SCAN_OVERRUN))
@@ -103,6 +105,10 @@ struct pmp_instance {
     unsigned long long *h_fit = nullptr;
     unsigned long long *h_scan = nullptr;
     int32_t h_cap = 0;
+    // client-tile partial sums of the evaluation kernel
+    unsigned long long *part = nullptr;
+    uint32_t *spart = nullptr;
+    size_t part_cap = 0;
 
     Tables tables() const
     {
@@ -122,20 +128,37 @@ struct pmp_instance {
 struct pmp_ga {
     pmp_instance *inst = nullptr;
     pmp_ga_params prm{};
-    int NB = 0, lg = 0, X = 0, Y = 0;
-    uint64_t *cur = nullptr, *off = nullptr, *gmask = nullptr, *best = nullptr;
-    unsigned long long *fit = nullptr, *ofit = nullptr, *gcost = nullptr,
-                       *gs = nullptr;
-    uint8_t *ok = nullptr, *improved = nullptr;
+    int NB = 0, lg = 0, X = 0, Y = 0, TI = 0, cpb = 0;
+    uint64_t *cur[2] = {nullptr, nullptr}, *off[2] = {nullptr, nullptr};
+    unsigned long long *fit[2] = {nullptr, nullptr};
+    uint8_t *ok[2] = {nullptr, nullptr};
+    uint8_t *improved = nullptr;
+    unsigned long long *part = nullptr;
+    uint32_t *spart = nullptr;
+    uint64_t *gmask = nullptr, *best = nullptr;
+    unsigned long long *gcost = nullptr, *gs = nullptr, *cstat = nullptr;
+    uint32_t *arrive = nullptr;
+    uint32_t *bar = nullptr;
+    bool persistent = false;  // one cooperative launch per pmp_ga_step call
+    // graph of `graph_gens` generations of the per-step launch sequence
+    int graph_gens = 0;
+    hipGraphExec_t gexec = nullptr;
+    int max_blocks = 0;
+    int last_grid = 0;
     // profiling of the evaluation kernel
     bool prof = false;
     std::vector<hipEvent_t> ev;
     size_t ev_used = 0;
     unsigned long long base_scan = 0, base_evals = 0;
 
+    // crossover stages actually run (none when p < 2 or NT = 1)
+    int xstages() const { return (inst->p >= 2 && lg > 0) ? X : 0; }
+    // buffer holding the population after a generation's last stage
+    int final_buf() const { return ((xstages() + Y) % 2) ^ 1; }
+
     GaArgs args() const
     {
-        GaArgs g;
+        GaArgs g{};
         g.t = inst->tables();
         g.seed = prm.seed;
         g.P = prm.population;
@@ -146,16 +169,23 @@ struct pmp_ga {
         g.Y = Y;
         g.generations = prm.generations;
         g.saturation = prm.saturation;
-        g.cur = cur;
-        g.off = off;
-        g.fit = fit;
-        g.ofit = ofit;
-        g.ok = ok;
+        for (int k = 0; k < 2; ++k) {
+            g.cur[k] = cur[k];
+            g.fit[k] = fit[k];
+            g.off[k] = off[k];
+            g.ok[k] = ok[k];
+        }
         g.improved = improved;
+        g.part = part;
+        g.spart = spart;
+        g.TI = TI;
         g.gmask = gmask;
         g.gcost = gcost;
         g.best_mask = best;
         g.gs = gs;
+        g.cstat = cstat;
+        g.arrive = arrive;
+        g.bar = bar;
         g.err = inst->err;
         return g;
     }
@@ -189,6 +219,8 @@ void pmp_instance_destroy(pmp_instance *inst)
     dfree(inst->h_masks);
     dfree(inst->h_fit);
     dfree(inst->h_scan);
+    dfree(inst->part);
+    dfree(inst->spart);
     delete inst;
 }
 
@@ -366,23 +398,31 @@ pmp_status pmp_eval_population(pmp_instance *inst, const uint64_t *masks,
     }
     if (!async)
         HIP_TRY(launch_zero(inst->err, sizeof(uint32_t), s));
-    HIP_TRY(launch_zero(dfit, sizeof(unsigned long long) * P, s));
-    if (dscan)
-        HIP_TRY(launch_zero(dscan, sizeof(unsigned long long) * P, s));
 
     EvalArgs a{};
     a.t = inst->tables();
     a.masks = dmask;
     a.P = P;
     a.active = nullptr;
-    a.fitness = dfit;
-    a.scan = dscan;
-    a.gstate = nullptr;
+    a.done = nullptr;
     a.err = inst->err;
     a.clients_per_block = clients_per_block(inst->n, P);
     a.tiles_c = (P + kEvalTile - 1) / kEvalTile;
     a.tiles_i = (inst->n + a.clients_per_block - 1) / a.clients_per_block;
+    const size_t cells = (size_t)a.tiles_i * P;
+    if (inst->part_cap < cells) {
+        dfree(inst->part);
+        dfree(inst->spart);
+        inst->part_cap = 0;
+        if (dalloc(&inst->part, cells) != hipSuccess ||
+            dalloc(&inst->spart, cells) != hipSuccess)
+            return fail(PMP_ENOMEM, "evaluation workspace (%zu cells)", cells);
+        inst->part_cap = cells;
+    }
+    a.part = inst->part;
+    a.spart = dscan ? inst->spart : nullptr;
     HIP_TRY(launch_eval(a, s));
+    HIP_TRY(launch_reduce(a, dfit, dscan, s));
 
     if (!on_dev) {
         HIP_TRY(hipMemcpyAsync(fitness, dfit, sizeof(int64_t) * P,
@@ -403,16 +443,24 @@ void pmp_ga_destroy(pmp_ga *ga)
 {
     if (!ga)
         return;
-    dfree(ga->cur);
-    dfree(ga->off);
+    for (int k = 0; k < 2; ++k) {
+        dfree(ga->cur[k]);
+        dfree(ga->off[k]);
+        dfree(ga->fit[k]);
+        dfree(ga->ok[k]);
+    }
+    dfree(ga->improved);
+    dfree(ga->part);
+    dfree(ga->spart);
     dfree(ga->gmask);
     dfree(ga->best);
-    dfree(ga->fit);
-    dfree(ga->ofit);
     dfree(ga->gcost);
     dfree(ga->gs);
-    dfree(ga->ok);
-    dfree(ga->improved);
+    dfree(ga->cstat);
+    dfree(ga->arrive);
+    dfree(ga->bar);
+    if (ga->gexec)
+        (void)hipGraphExecDestroy(ga->gexec);
     for (hipEvent_t e : ga->ev)
         (void)hipEventDestroy(e);
     delete ga;
@@ -444,22 +492,52 @@ pmp_status pmp_ga_create(pmp_instance *inst, const pmp_ga_params *prm,
     ga->lg = lg;
     ga->X = prm->crossover_iters > 0 ? prm->crossover_iters : lg;
     ga->Y = prm->mutation_iters > 0 ? prm->mutation_iters : lg;
-    const size_t W = inst->W;
-    if (dalloc(&ga->cur, (size_t)P * W) || dalloc(&ga->off, (size_t)P * W) ||
-        dalloc(&ga->gmask, (size_t)ga->NB * W) || dalloc(&ga->best, W) ||
-        dalloc(&ga->fit, (size_t)P) || dalloc(&ga->ofit, (size_t)P) ||
-        dalloc(&ga->gcost, (size_t)ga->NB) || dalloc(&ga->gs, GS_COUNT) ||
-        dalloc(&ga->ok, (size_t)P) || dalloc(&ga->improved, (size_t)P)) {
+    ga->cpb = clients_per_block(inst->n, P);
+    ga->TI = (inst->n + ga->cpb - 1) / ga->cpb;
+    const size_t W = inst->W, PW = (size_t)P * W;
+    bool bad = false;
+    for (int k = 0; k < 2; ++k)
+        bad = bad || dalloc(&ga->cur[k], PW) || dalloc(&ga->off[k], PW) ||
+              dalloc(&ga->fit[k], (size_t)P) || dalloc(&ga->ok[k], (size_t)P);
+    bad = bad || dalloc(&ga->improved, (size_t)P) ||
+          dalloc(&ga->part, (size_t)ga->TI * P) || dalloc(&ga->spart, (size_t)ga->TI * P) ||
+          dalloc(&ga->gmask, (size_t)ga->NB * W) || dalloc(&ga->best, W) ||
+          dalloc(&ga->gcost, (size_t)ga->NB) || dalloc(&ga->gs, GS_COUNT) ||
+          dalloc(&ga->cstat, (size_t)P * CS_COUNT) || dalloc(&ga->arrive, 1) ||
+          dalloc(&ga->bar, kBarrierWords);
+    if (bad) {
         pmp_ga_destroy(ga);
         return fail(PMP_ENOMEM, "GA buffers for P=%d", P);
     }
     unsigned long long init[GS_COUNT] = {0};
     init[GS_BEST] = (unsigned long long)INT64_MAX;
     hipError_t e = hipMemcpy(ga->gs, init, sizeof init, hipMemcpyHostToDevice);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+        e = hipMemset(ga->cur[k], 0, sizeof(uint64_t) * PW);
+        if (e == hipSuccess)
+            e = hipMemset(ga->fit[k], 0, sizeof(unsigned long long) * P);
+    }
     if (e == hipSuccess)
         e = hipMemset(ga->best, 0, sizeof(uint64_t) * W);
     if (e == hipSuccess)
         e = hipMemset(ga->gmask, 0, sizeof(uint64_t) * W * ga->NB);
+    if (e == hipSuccess)
+        e = hipMemset(ga->gcost, 0, sizeof(unsigned long long) * ga->NB);
+    if (e == hipSuccess)
+        e = hipMemset(ga->cstat, 0, sizeof(unsigned long long) * P * CS_COUNT);
+    if (e == hipSuccess)
+        e = hipMemset(ga->arrive, 0, sizeof(uint32_t));
+    if (e == hipSuccess)
+        e = hipMemset(ga->bar, 0, sizeof(uint32_t) * kBarrierWords);
+    {
+        const char *mode = getenv("PMP_GA_MODE");
+        ga->persistent = mode && strcmp(mode, "persistent") == 0;
+        ga->max_blocks = env_int("PMP_GA_BLOCKS", 0);
+        ga->graph_gens = (mode && strcmp(mode, "kernels") == 0) ? 0
+                                                                : env_int("PMP_GA_GRAPH_GENS", 8);
+    }
+    if (e == hipSuccess)
+        e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         pmp_ga_destroy(ga);
         return fail(PMP_EDEVICE, "GA state init: %s", hipGetErrorString(e));
@@ -481,34 +559,114 @@ hipEvent_t next_event(pmp_ga *ga)
     return ga->ev[ga->ev_used++];
 }
 
-hipError_t ga_eval(pmp_ga *ga, const GaArgs &g, const uint64_t *masks,
-                   unsigned long long *fit, hipStream_t s)
+EvalArgs ga_eval_args(const pmp_ga *ga, const GaArgs &g, int buf)
 {
     EvalArgs a{};
     a.t = g.t;
-    a.masks = masks;
+    a.masks = g.off[buf];
     a.P = g.P;
-    a.active = g.ok;
-    a.fitness = fit;
-    a.scan = nullptr;
-    a.gstate = g.gs;
+    a.active = g.ok[buf];
+    a.part = ga->part;
+    a.spart = ga->spart;
+    a.done = g.gs + GS_DONE;
     a.err = g.err;
-    a.clients_per_block = clients_per_block(g.t.n, g.P);
+    a.clients_per_block = ga->cpb;
     a.tiles_c = (g.P + kEvalTile - 1) / kEvalTile;
-    a.tiles_i = (g.t.n + a.clients_per_block - 1) / a.clients_per_block;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (ga->prof) {
-        e0 = next_event(ga);
-        e1 = next_event(ga);
-        if (!e0 || !e1)
-            return hipErrorOutOfMemory;
-        hipError_t e = hipEventRecord(e0, s);
+    a.tiles_i = ga->TI;
+    return a;
+}
+
+// Record a profiling event on s (no-op when profiling is off).
+hipError_t mark(pmp_ga *ga, hipStream_t s)
+{
+    if (!ga->prof)
+        return hipSuccess;
+    hipEvent_t e = next_event(ga);
+    if (!e)
+        return hipErrorOutOfMemory;
+    return hipEventRecord(e, s);
+}
+
+// Evaluate the offspring buffer `buf` (only slots flagged in ok[buf]).
+hipError_t ga_eval(pmp_ga *ga, const GaArgs &g, int buf, hipStream_t s)
+{
+    hipError_t e = mark(ga, s);
+    if (e == hipSuccess)
+        e = launch_eval(ga_eval_args(ga, g, buf), s);
+    if (e == hipSuccess)
+        e = mark(ga, s);
+    return e;
+}
+
+// Host-side totals of the per-chromosome counters.
+hipError_t ga_counters(pmp_ga *ga, unsigned long long tot[CS_COUNT])
+{
+    const size_t P = ga->prm.population;
+    std::vector<unsigned long long> cs(P * CS_COUNT);
+    hipError_t e = hipMemcpy(cs.data(), ga->cstat, sizeof(unsigned long long) * cs.size(),
+                             hipMemcpyDeviceToHost);
+    for (int k = 0; k < CS_COUNT; ++k)
+        tot[k] = 0;
+    for (size_t c = 0; c < P; ++c)
+        for (int k = 0; k < CS_COUNT; ++k)
+            tot[k] += cs[c * CS_COUNT + k];
+    return e;
+}
+
+}  // namespace
+
+namespace {
+
+// Enqueue `generations` generations of the per-step launch sequence.
+hipError_t enqueue_generations(pmp_ga *ga, const GaArgs &g, int generations,
+                               hipStream_t s)
+{
+    const int X = ga->xstages(), S = X + ga->Y;
+    for (int gen = 0; gen < generations; ++gen) {
+        hipError_t e = launch_ga_init(g, s);
+        if (e == hipSuccess)
+            e = ga_eval(ga, g, 0, s);
+        for (int k = 0; k <= S && e == hipSuccess; ++k) {
+            const int prev = k == 0 ? OP_INIT : (k - 1 < X ? OP_XOVER : OP_MUT);
+            const int op = k == S ? OP_NONE : (k < X ? OP_XOVER : OP_MUT);
+            const int index = k < X ? k : k - X;
+            e = launch_ga_stage(g, k & 1, prev, op, index, s);
+            if (e == hipSuccess && op != OP_NONE)
+                e = ga_eval(ga, g, (k & 1) ^ 1, s);
+        }
+        if (e == hipSuccess)
+            e = launch_ga_best(g, ga->final_buf(), s);
         if (e != hipSuccess)
             return e;
     }
-    hipError_t e = launch_eval(a, s);
-    if (e == hipSuccess && ga->prof)
-        e = hipEventRecord(e1, s);
+    return hipSuccess;
+}
+
+// Capture graph_gens generations of the launch sequence into a graph (once).
+hipError_t ensure_graph(pmp_ga *ga, const GaArgs &g)
+{
+    if (ga->gexec)
+        return hipSuccess;
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess)
+        return e;
+    hipGraph_t graph = nullptr;
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        const bool prof = ga->prof;
+        ga->prof = false;  // no events inside the graph
+        hipError_t ee = enqueue_generations(ga, g, ga->graph_gens, cs);
+        ga->prof = prof;
+        e = hipStreamEndCapture(cs, &graph);
+        if (ee != hipSuccess)
+            e = ee;
+    }
+    if (e == hipSuccess)
+        e = hipGraphInstantiate(&ga->gexec, graph, nullptr, nullptr, 0);
+    if (graph)
+        (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cs);
     return e;
 }
 
@@ -520,24 +678,24 @@ pmp_status pmp_ga_step(pmp_ga *ga, int32_t generations, void *stream)
         return fail(PMP_EINVAL, "ga is NULL");
     if (generations < 0)
         return fail(PMP_EINVAL, "generations < 0");
+    if (generations == 0)
+        return PMP_OK;
     hipStream_t s = (hipStream_t)stream;
     const GaArgs g = ga->args();
-    const bool crossover = g.t.p >= 2 && g.lg > 0;
-    for (int gen = 0; gen < generations; ++gen) {
-        HIP_TRY(launch_ga_init(g, s));
-        HIP_TRY(ga_eval(ga, g, g.cur, g.fit, s));
-        for (int k = 0; crossover && k < g.X; ++k) {
-            HIP_TRY(launch_ga_crossover(g, k, s));
-            HIP_TRY(ga_eval(ga, g, g.off, g.ofit, s));
-            HIP_TRY(launch_ga_accept(g, 0, s));
-        }
-        for (int a = 0; a < g.Y; ++a) {
-            HIP_TRY(launch_ga_mutate(g, a, s));
-            HIP_TRY(ga_eval(ga, g, g.off, g.ofit, s));
-            HIP_TRY(launch_ga_accept(g, 1, s));
-        }
-        HIP_TRY(launch_ga_best(g, s));
+    if (ga->persistent) {
+        HIP_TRY(mark(ga, s));
+        HIP_TRY(launch_ga_persistent(g, ga_eval_args(ga, g, 0), generations,
+                                     ga->max_blocks, s, &ga->last_grid));
+        HIP_TRY(mark(ga, s));
+        return PMP_OK;
     }
+    int left = generations;
+    if (ga->graph_gens > 0 && !ga->prof && left >= ga->graph_gens) {
+        HIP_TRY(ensure_graph(ga, g));
+        for (; left >= ga->graph_gens; left -= ga->graph_gens)
+            HIP_TRY(hipGraphLaunch(ga->gexec, s));
+    }
+    HIP_TRY(enqueue_generations(ga, g, left, s));
     return PMP_OK;
 }
 
@@ -556,16 +714,18 @@ pmp_status pmp_ga_best(pmp_ga *ga, uint64_t *mask, int64_t *cost,
     if (cost)
         *cost = (int64_t)gs[GS_BEST];
     if (stats) {
+        unsigned long long tot[CS_COUNT];
+        HIP_TRY(ga_counters(ga, tot));
         stats->generations = (int64_t)gs[GS_GEN];
         stats->saturation_count = (int64_t)gs[GS_SAT];
         stats->done = (int64_t)gs[GS_DONE];
         stats->best_cost = (int64_t)gs[GS_BEST];
-        stats->chromosome_evals = (int64_t)gs[GS_CHROM_EVALS];
-        stats->crossover_fail = (int64_t)gs[GS_XO_FAIL];
-        stats->crossover_taken = (int64_t)gs[GS_XO_TAKEN];
-        stats->mutation_taken = (int64_t)gs[GS_MUT_TAKEN];
-        stats->scan_total = (int64_t)gs[GS_SCAN_TOTAL];
-        stats->pair_evals = (int64_t)gs[GS_CHROM_EVALS] * ga->inst->n;
+        stats->chromosome_evals = (int64_t)tot[CS_EVALS];
+        stats->crossover_fail = (int64_t)tot[CS_XO_FAIL];
+        stats->crossover_taken = (int64_t)tot[CS_XO_TAKEN];
+        stats->mutation_taken = (int64_t)tot[CS_MUT_TAKEN];
+        stats->scan_total = (int64_t)tot[CS_SCAN];
+        stats->pair_evals = (int64_t)tot[CS_EVALS] * ga->inst->n;
     }
     uint32_t herr = 0;
     HIP_TRY(hipMemcpy(&herr, ga->inst->err, sizeof herr, hipMemcpyDeviceToHost));
@@ -581,11 +741,12 @@ pmp_status pmp_ga_state(pmp_ga *ga, uint64_t *population, int64_t *fitness,
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipStreamSynchronize(s));
     const size_t W = ga->inst->W, P = ga->prm.population, NB = ga->NB;
+    const int f = ga->final_buf();
     if (population)
-        HIP_TRY(hipMemcpy(population, ga->cur, sizeof(uint64_t) * P * W,
+        HIP_TRY(hipMemcpy(population, ga->cur[f], sizeof(uint64_t) * P * W,
                           hipMemcpyDeviceToHost));
     if (fitness)
-        HIP_TRY(hipMemcpy(fitness, ga->fit, sizeof(int64_t) * P, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(fitness, ga->fit[f], sizeof(int64_t) * P, hipMemcpyDeviceToHost));
     if (group_masks)
         HIP_TRY(hipMemcpy(group_masks, ga->gmask, sizeof(uint64_t) * NB * W,
                           hipMemcpyDeviceToHost));
@@ -600,12 +761,12 @@ pmp_status pmp_ga_profile(pmp_ga *ga, int32_t enable)
     if (!ga)
         return fail(PMP_EINVAL, "ga is NULL");
     HIP_TRY(hipDeviceSynchronize());
-    unsigned long long gs[GS_COUNT];
-    HIP_TRY(hipMemcpy(gs, ga->gs, sizeof gs, hipMemcpyDeviceToHost));
+    unsigned long long tot[CS_COUNT];
+    HIP_TRY(ga_counters(ga, tot));
     ga->prof = enable != 0;
     ga->ev_used = 0;
-    ga->base_scan = gs[GS_SCAN_TOTAL];
-    ga->base_evals = gs[GS_CHROM_EVALS];
+    ga->base_scan = tot[CS_SCAN];
+    ga->base_evals = tot[CS_EVALS];
     return PMP_OK;
 }
 
@@ -621,18 +782,18 @@ pmp_status pmp_ga_profile_read(pmp_ga *ga, pmp_profile *out, void *stream)
         HIP_TRY(hipEventElapsedTime(&t, ga->ev[k], ga->ev[k + 1]));
         ms += t;
     }
-    unsigned long long gs[GS_COUNT];
-    HIP_TRY(hipMemcpy(gs, ga->gs, sizeof gs, hipMemcpyDeviceToHost));
-    const int64_t evals = (int64_t)(gs[GS_CHROM_EVALS] - ga->base_evals);
-    const int64_t scan = (int64_t)(gs[GS_SCAN_TOTAL] - ga->base_scan);
+    unsigned long long tot[CS_COUNT];
+    HIP_TRY(ga_counters(ga, tot));
+    const int64_t evals = (int64_t)(tot[CS_EVALS] - ga->base_evals);
+    const int64_t scan = (int64_t)(tot[CS_SCAN] - ga->base_scan);
     const int64_t pairs = evals * ga->inst->n;
     out->eval_ms = ms;
     out->eval_launches = (int64_t)(ga->ev_used / 2);
     out->eval_pairs = pairs;
     out->eval_bytes = 2 * scan + 4 * pairs + evals * (8 * (int64_t)ga->inst->W + 8);
     ga->ev_used = 0;
-    ga->base_scan = gs[GS_SCAN_TOTAL];
-    ga->base_evals = gs[GS_CHROM_EVALS];
+    ga->base_scan = tot[CS_SCAN];
+    ga->base_evals = tot[CS_EVALS];
     return PMP_OK;
 }
 

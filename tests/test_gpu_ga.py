@@ -5,6 +5,8 @@ every decision on exact integer fitness, so after k generations the whole
 state (population, fitness, group bests, global best and counters) must be
 identical bit for bit.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -23,10 +25,35 @@ def pm():
     return pm
 
 
+# launch schemes: per-step kernels replayed from a hipGraph of 2 generations
+# (the default scheme, with a chunk small enough to replay here), per-step
+# kernels launched one by one, one persistent cooperative kernel, and the
+# same with a grid of 8 workgroups (every phase loops)
+MODES = {"graph": {"PMP_GA_GRAPH_GENS": "2"},
+         "kernels": {"PMP_GA_MODE": "kernels"},
+         "persistent": {"PMP_GA_MODE": "persistent"},
+         "persistent_8wg": {"PMP_GA_MODE": "persistent", "PMP_GA_BLOCKS": "8"}}
+_ENV = ("PMP_GA_MODE", "PMP_GA_BLOCKS", "PMP_GA_GRAPH_GENS")
+
+
+@pytest.fixture(params=list(MODES))
+def mode(request):
+    old = {k: os.environ.get(k) for k in _ENV}
+    for k in old:
+        os.environ.pop(k, None)
+    os.environ.update(MODES[request.param])
+    yield request.param
+    for k, v in old.items():
+        if v is None:
+            os.environ.pop(k, None)
+        else:
+            os.environ[k] = v
+
+
 def _compare(pm, d, p, P, NT, G, seed, steps, sat=0, X=0, Y=0):
     n, m = d.shape
     print("case", d.shape, "p", p, "P", P, "NT", NT, "steps", steps, "seed", seed,
-          flush=True)
+          "mode", {k: os.environ.get(k) for k in _ENV}, flush=True)
     inst = pm.Instance(d, p)
     ga = pm.GA(inst, P, NT, G, seed, sat, X, Y)
     st = oracle.GaState(n, m, p, P, NT, G, seed, sat, X, Y)
@@ -54,47 +81,47 @@ def _compare(pm, d, p, P, NT, G, seed, steps, sat=0, X=0, Y=0):
     return stats
 
 
-def test_ga_g100_config(pm):
+def test_ga_g100_config(pm, mode):
     """Graph n = m = 100, 200 edges, p = 5, population 64 (one group)."""
     d = gi.graph_instance(100, 200, 0)
     _compare(pm, d, 5, 64, 64, 100, seed=1, steps=[4])
 
 
-def test_ga_g20_groups_saturation(pm):
+def test_ga_g20_groups_saturation(pm, mode):
     d = gi.graph_instance(20, 40, 0)
     s = _compare(pm, d, 4, 32, 8, 500, seed=7, steps=[40, 40], sat=6)
     assert s["done"] == 1
 
 
-def test_ga_example1_tiny(pm):
+def test_ga_example1_tiny(pm, mode):
     _compare(pm, gi.example1_matrix(), 2, 8, 4, 5, seed=3, steps=[2, 3])
 
 
-def test_ga_p1_has_no_crossover(pm):
+def test_ga_p1_has_no_crossover(pm, mode):
     d = gi.euclid_instance(70, 3)
     s = _compare(pm, d, 1, 16, 16, 3, seed=2, steps=[3])
     assert s["crossover_taken"] == 0 and s["crossover_fail"] == 0
 
 
-def test_ga_preset_iteration_counts(pm):
+def test_ga_preset_iteration_counts(pm, mode):
     """More crossover stages than lg NT cycle the strides again."""
     d = gi.euclid_instance(150, 8)
     _compare(pm, d, 12, 64, 16, 4, seed=5, steps=[2], X=9, Y=2)
 
 
-def test_ga_ragged_m_and_resume(pm):
+def test_ga_ragged_m_and_resume(pm, mode):
     d = np.random.default_rng(4).integers(0, 50, size=(77, 131)).astype(np.int32)
     _compare(pm, d, 17, 128, 32, 8, seed=11, steps=[1, 2, 4])
 
 
-def test_ga_g900_full_config(pm):
+def test_ga_g900_full_config(pm, mode):
     """Graph n = m = 900, 16200 edges, p = 90, population 1024 (NT = 256),
     the benchmark's configuration, two generations."""
     d = gi.graph_instance(900, 16200, 0)
     _compare(pm, d, 90, 1024, 256, 500, seed=0, steps=[2])
 
 
-def test_ga_euclid_1000(pm):
+def test_ga_euclid_1000(pm, mode):
     d = gi.euclid_instance(1000, 1)
     _compare(pm, d, 50, 512, 128, 3, seed=9, steps=[1])
 
@@ -107,3 +134,17 @@ def test_solve_returns_consistent_best(pm):
     assert oracle.objective(d, mask, 4)[0] == cost
     best, _, _ = oracle.exhaustive(d, 4)
     assert cost >= best
+
+
+def test_ga_m4096_two_words_per_lane(pm, mode):
+    """m above 4096: each lane of the operator waves owns two words."""
+    d = np.random.default_rng(12).integers(0, 1000, size=(40, 4500)).astype(np.int32)
+    _compare(pm, d, 300, 64, 16, 3, seed=4, steps=[2])
+
+
+def test_ga_group_of_one(pm, mode):
+    """NT = 1: no crossover, no mutation (lg NT = 0); random restarts with
+    migration only."""
+    d = gi.euclid_instance(60, 2)
+    s = _compare(pm, d, 6, 8, 1, 4, seed=6, steps=[4])
+    assert s["crossover_taken"] == 0 and s["mutation_taken"] == 0
