@@ -77,6 +77,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="no per-launch events (the GA then replays hipGraphs)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device copy of known size (scales the "
+                         "FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the path "
@@ -86,6 +89,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.calibrate_copy:
+        # 256 MiB read + 256 MiB written per copy, 4 copies
+        x = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(4):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": x.numel() * 4, "copies": 4}))
+        return
 
     import paper_1610_10061_amd as pm
     import pmp_inputs as gi

@@ -38,9 +38,13 @@ namespace pmp {
 
 using kLanes = std::make_integer_sequence<int, kEvalTile>;
 
+// Lowest set lane of a ballot, -1 when none (s_ff1_i32_b64 returns -1 for
+// zero, so no compare and select are needed around it).
 __device__ __forceinline__ int first_lane(uint64_t b)
 {
-    return __builtin_ffsll((long long)b) - 1;  // -1 when b == 0
+    int r;
+    asm("s_ff1_i32_b64 %0, %1" : "=s"(r) : "s"(b));
+    return r;
 }
 
 // Lane C of `hit` takes the wave-uniform value `v` (v_writelane_b32 with the

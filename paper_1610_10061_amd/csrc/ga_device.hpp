@@ -87,30 +87,6 @@ __device__ __forceinline__ uint64_t lowest_bits(uint64_t x, int k)
     return q >= 63 ? x : (x & ((1ull << (q + 1)) - 1ull));
 }
 
-// Costs of the offspring of chromosomes c and q: the evaluation's
-// client-tile partial sums, added up by the wave (only where `want`); the
-// scan lengths of c's offspring too.
-__device__ __forceinline__ void offspring_costs(const GaArgs &g, int c, bool want_c,
-                                                int q, bool want_q, int lane,
-                                                unsigned long long *fc,
-                                                unsigned long long *sc,
-                                                unsigned long long *fq)
-{
-    unsigned long long f = 0, s = 0, h = 0;
-    for (int t = lane; t < g.TI; t += 64) {
-        const int64_t row = (int64_t)t * g.P;
-        if (want_c) {
-            f += g.part[row + c];
-            s += g.spart[row + c];
-        }
-        if (want_q)
-            h += g.part[row + q];
-    }
-    *fc = wave_sum(f);
-    *sc = wave_sum(s);
-    *fq = wave_sum(h);
-}
-
 // Philox4x64-10 block (philox.hpp) for counter (c0, c1, c2, c3).
 __device__ __forceinline__ void philox_block(uint64_t k0, uint64_t k1,
                                              uint64_t c0, uint64_t c1,
@@ -202,27 +178,48 @@ __device__ __forceinline__ void ga_init_one(const GaArgs &g, int c, int lane)
     }
 }
 
-// len (1..64) bits of A starting at bit pos, pos + len <= 64 * W.
-__device__ __forceinline__ uint64_t bits_at(const uint64_t *A, int W, int pos,
+// A chromosome held by a wave: word w in register w >> 6 of lane w & 63.
+struct WaveWords {
+    uint64_t v[2];
+
+    // word w, for a lane-varying w (two ds_bpermute per register)
+    __device__ __forceinline__ uint64_t at(int w) const
+    {
+        const uint64_t lo = __shfl(v[0], w & 63), hi = __shfl(v[1], w & 63);
+        return (w >> 6) ? hi : lo;
+    }
+    // word w, for a wave-uniform w
+    __device__ __forceinline__ uint64_t at_uniform(int w) const
+    {
+        return readlane64((w >> 6) ? v[1] : v[0], w & 63);
+    }
+};
+
+// len (1..64) bits of A starting at bit pos, pos + len <= 64 * W (lanes may
+// ask for different positions).
+__device__ __forceinline__ uint64_t bits_at(const WaveWords &A, int W, int pos,
                                             int len)
 {
     const int w = pos >> 6, o = pos & 63;
-    uint64_t v = A[w] >> o;
+    uint64_t v = A.at(w) >> o;
+    const uint64_t next = A.at(w + 1 < W ? w + 1 : w);
     if (o != 0 && w + 1 < W)
-        v |= A[w + 1] << (64 - o);
+        v |= next << (64 - o);
     return len == 64 ? v : (v & ((1ull << len) - 1ull));
 }
 
 // `len` bits of the cyclic sequence A[lo..hi] starting at position s0
-// (lo <= s0 <= hi, len <= hi - lo + 1).
-__device__ __forceinline__ uint64_t cyclic_bits(const uint64_t *A, int W,
+// (lo <= s0 <= hi, len <= hi - lo + 1).  Branch-free, so every lane takes
+// part in the shuffles of both runs.
+__device__ __forceinline__ uint64_t cyclic_bits(const WaveWords &A, int W,
                                                 int lo, int hi, int s0,
                                                 int len)
 {
-    const int r = hi + 1 - s0;
-    if (len <= r)
-        return bits_at(A, W, s0, len);
-    return bits_at(A, W, s0, r) | (bits_at(A, W, lo, len - r) << r);
+    const int first = min(len, hi + 1 - s0);  // bits before the wrap
+    const int second = len - first;           // bits after it (0: none)
+    const uint64_t v1 = bits_at(A, W, s0, first);
+    const uint64_t v2 = bits_at(A, W, lo, second > 0 ? second : 1);
+    return second > 0 ? (v1 | (v2 << first)) : v1;
 }
 
 // ---------------------------------------------------------------------------
@@ -236,14 +233,14 @@ __device__ __forceinline__ uint64_t cyclic_bits(const uint64_t *A, int W,
 // hence how many of its own to take (its lowest ones).  Returns false when
 // the parents differ in fewer than 2*quota genes (no offspring).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool crossover_wave(const uint64_t *A,
-                                               const uint64_t *B, uint64_t *F,
+__device__ __forceinline__ bool crossover_wave(const WaveWords &A,
+                                               const WaveWords &B, uint64_t *F,
                                                int W, int r1, int quota,
                                                int lane)
 {
     const int w0 = r1 >> 6, b0 = r1 & 63;
     const uint64_t low_mask = b0 ? ((1ull << b0) - 1ull) : 0ull;
-    const uint64_t a0 = A[w0], bb0 = B[w0];
+    const uint64_t a0 = A.at_uniform(w0), bb0 = B.at_uniform(w0);
     const uint64_t xl = a0 & ~bb0 & low_mask, yl = ~a0 & bb0 & low_mask;
 
     uint64_t x[2] = {0, 0}, y[2] = {0, 0}, av[2] = {0, 0};
@@ -252,12 +249,12 @@ __device__ __forceinline__ bool crossover_wave(const uint64_t *A,
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int r = lane + 64 * h;
+        int w = w0 + r;
+        if (w >= W)
+            w -= W;
+        const uint64_t a = A.at(w < W ? w : 0), b = B.at(w < W ? w : 0);
         if (r < W) {
-            int w = w0 + r;
-            if (w >= W)
-                w -= W;
             const uint64_t seg = r == 0 ? (~0ull << b0) : ~0ull;
-            const uint64_t a = A[w], b = B[w];
             x[h] = a & ~b & seg;
             y[h] = ~a & b & seg;
             av[h] = a;
@@ -297,27 +294,33 @@ __device__ __forceinline__ bool crossover_wave(const uint64_t *A,
 // L, and source bit q outside it.  Each lane builds its destination words
 // from at most two runs of source bits.  Returns whether F differs from A.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool mutate_wave(const uint64_t *A, uint64_t *F,
+__device__ __forceinline__ bool mutate_wave(const WaveWords &A, uint64_t *F,
                                             int W, int m, int lo, int hi,
                                             int move, int lane)
 {
     const int L = hi - lo + 1;
     bool changed = false;
-    for (int w = lane; w < W; w += 64) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int w = lane + 64 * h;
         const int q0 = w * 64;
         const int q1 = min(m, q0 + 64);
-        uint64_t val = A[w];
         const int qa = max(q0, lo), qb = min(q1, hi + 1);
-        if (qa < qb) {
-            const int nin = qb - qa;
-            const int s0 = lo + (((qa - lo - move) % L) + L) % L;
-            const uint64_t part = cyclic_bits(A, W, lo, hi, s0, nin);
-            const uint64_t mask =
-                (nin == 64 ? ~0ull : ((1ull << nin) - 1ull)) << (qa - q0);
-            val = (val & ~mask) | (part << (qa - q0));
+        // every lane takes part in the shuffles; only words < W are kept
+        const bool inside = w < W && qa < qb;
+        const int nin = inside ? qb - qa : 1;
+        const int s0 = inside ? lo + (((qa - lo - move) % L) + L) % L : lo;
+        const uint64_t part = cyclic_bits(A, W, lo, hi, s0, nin);
+        if (w < W) {
+            uint64_t val = A.v[h];
+            if (inside) {
+                const uint64_t mask =
+                    (nin == 64 ? ~0ull : ((1ull << nin) - 1ull)) << (qa - q0);
+                val = (val & ~mask) | (part << (qa - q0));
+            }
+            changed |= val != A.v[h];
+            F[w] = val;
         }
-        changed |= val != A[w];
-        F[w] = val;
     }
     return __builtin_amdgcn_ballot_w64(changed) != 0ull;
 }
@@ -333,6 +336,9 @@ __device__ __forceinline__ bool mutate_wave(const uint64_t *A, uint64_t *F,
 //    draws type, direction, then the amount s in [1, m-1] or the block ends
 //    (a uniform pair of distinct positions) and s in [1, b - a]; an
 //    offspring equal to its parent is not evaluated (Section 4.4).
+// All of the step's loads are issued together and the random draws are
+// computed while they are in flight; the operators then work on the words
+// held by the lanes.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
                                              int in, int prev, int op,
@@ -340,23 +346,74 @@ __device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
 {
     const int out = in ^ 1;
     const int W = g.t.W, m = g.t.m;
-    const uint64_t gen = g.gs[GS_GEN];
+    const bool xo = op == OP_XOVER;
+    const int pc = xo ? (c ^ (g.NT >> (1 + index % g.lg))) : c;
 
-    // finish the previous operator (for a crossover, the partner's too: its
-    // state as this stage leaves it is the other parent)
-    const int pc = op == OP_XOVER ? (c ^ (g.NT >> (1 + index % g.lg))) : c;
+    // one round of independent loads
+    const uint64_t gen = g.gs[GS_GEN];
     const bool okc = buf(g.ok, in)[c] != 0;
-    const bool okp = op == OP_XOVER && buf(g.ok, in)[pc] != 0;
+    const bool okp = xo && buf(g.ok, in)[pc] != 0;
     const unsigned long long fin = buf(g.fit, in)[c];
     const unsigned long long fpin = buf(g.fit, in)[pc];
-    unsigned long long fo = 0, scan = 0, fop = 0;
-    offspring_costs(g, c, okc, pc, okp, lane, &fo, &scan, &fop);
+    const bool was_improved = g.improved[c] != 0;
+    unsigned long long f = 0, s = 0, h = 0;
+    for (int t = lane; t < g.TI; t += 64) {
+        const int64_t row = (int64_t)t * g.P;
+        f += g.part[row + c];
+        s += g.spart[row + c];
+        h += g.part[row + pc];
+    }
+    WaveWords cc{}, oc{}, cp{}, opw{};
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int w = lane + 64 * k;
+        if (w < W) {
+            cc.v[k] = buf(g.cur, in)[(int64_t)c * W + w];
+            oc.v[k] = buf(g.off, in)[(int64_t)c * W + w];
+            if (xo) {
+                cp.v[k] = buf(g.cur, in)[(int64_t)pc * W + w];
+                opw.v[k] = buf(g.off, in)[(int64_t)pc * W + w];
+            }
+        }
+    }
+
+    // the operator's draws, while the loads are in flight
+    int r1 = 0, quota = 0, lo = 0, hi = m - 1, move = 0;
+    if (xo) {
+        const int leader = c < pc ? c : pc;
+        PhiloxStream st(g.seed, ROLE_EVOLVE, gen, (uint64_t)leader, TAG_CROSSOVER,
+                        (uint64_t)index);
+        r1 = (int)st.below((uint64_t)m);
+        quota = 1 + (int)st.below((uint64_t)(g.t.p / 2));
+    } else if (op == OP_MUT) {
+        PhiloxStream st(g.seed, ROLE_EVOLVE, gen, (uint64_t)c, TAG_MUTATION,
+                        (uint64_t)index);
+        const int type = (int)st.below(2);
+        const int dir = (int)st.below(2);
+        if (type != 0) {
+            const int x = (int)st.below((uint64_t)m);
+            int y = (int)st.below((uint64_t)(m - 1));
+            if (y >= x)
+                ++y;
+            lo = x < y ? x : y;
+            hi = x < y ? y : x;
+        }
+        const int L = hi - lo + 1;
+        const int sh = 1 + (int)st.below((uint64_t)(L - 1));
+        move = dir == 0 ? sh : L - sh;
+    }
+
+    // finish the previous operator: c, and for a crossover the partner
+    const unsigned long long fo = wave_sum(f), scan = wave_sum(s), fop = wave_sum(h);
     const bool take = okc && fo < fin;
-    const uint64_t *A = (take ? buf(g.off, in) : buf(g.cur, in)) + (int64_t)c * W;
+    const bool ptake = okp && fop < fpin;
+    const WaveWords A = take ? oc : cc;
     uint64_t *cur = buf(g.cur, out) + (int64_t)c * W;
-    for (int w = lane; w < W; w += 64)
-        cur[w] = A[w];
-    const bool improved = g.improved[c] || (prev == OP_MUT && take);
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+        if (lane + 64 * k < W)
+            cur[lane + 64 * k] = A.v[k];
+    const bool improved = was_improved || (prev == OP_MUT && take);
     if (lane == 0) {
         buf(g.fit, out)[c] = take ? fo : fin;
         unsigned long long *cs = g.cstat + (int64_t)c * CS_COUNT;
@@ -372,36 +429,16 @@ __device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
         }
     }
 
+    // start the next operator
     uint64_t *F = buf(g.off, out) + (int64_t)c * W;
     bool ok = false;
-    if (op == OP_XOVER) {
-        const bool ptake = okp && fop < fpin;
-        const uint64_t *B = (ptake ? buf(g.off, in) : buf(g.cur, in)) + (int64_t)pc * W;
-        const int leader = c < pc ? c : pc;
-        PhiloxStream st(g.seed, ROLE_EVOLVE, gen, (uint64_t)leader, TAG_CROSSOVER,
-                        (uint64_t)index);
-        const int r1 = (int)st.below((uint64_t)m);
-        const int quota = 1 + (int)st.below((uint64_t)(g.t.p / 2));
+    if (xo) {
+        const WaveWords B = ptake ? opw : cp;
         ok = crossover_wave(A, B, F, W, r1, quota, lane);
         if (lane == 0 && !ok)
             g.cstat[(int64_t)c * CS_COUNT + CS_XO_FAIL] += 1;
     } else if (op == OP_MUT && !improved) {
-        PhiloxStream st(g.seed, ROLE_EVOLVE, gen, (uint64_t)c, TAG_MUTATION,
-                        (uint64_t)index);
-        const int type = (int)st.below(2);
-        const int dir = (int)st.below(2);
-        int lo = 0, hi = m - 1;
-        if (type != 0) {
-            const int x = (int)st.below((uint64_t)m);
-            int y = (int)st.below((uint64_t)(m - 1));
-            if (y >= x)
-                ++y;
-            lo = x < y ? x : y;
-            hi = x < y ? y : x;
-        }
-        const int L = hi - lo + 1;
-        const int s = 1 + (int)st.below((uint64_t)(L - 1));
-        ok = mutate_wave(A, F, W, m, lo, hi, dir == 0 ? s : L - s, lane);
+        ok = mutate_wave(A, F, W, m, lo, hi, move, lane);
     }
     if (lane == 0)
         buf(g.ok, out)[c] = ok ? 1 : 0;

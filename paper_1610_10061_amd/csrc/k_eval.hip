@@ -1,5 +1,7 @@
 // Population evaluation kernels: one launch evaluates a population
 // (eval_device.hpp), a second adds the client-tile partial sums up.
+#include <hip/hip_ext.h>
+
 #include "eval_device.hpp"
 
 namespace pmp {
@@ -46,12 +48,19 @@ __global__ __launch_bounds__(256) void k_reduce(
 }
 
 template <int WD>
-hipError_t launch_wd(const EvalArgs &a, hipStream_t s)
+hipError_t launch_wd(const EvalArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     const int tiles = a.tiles_c * a.tiles_i;
     const int grid = ((tiles + 7) / 8) * 8;
-    hipLaunchKernelGGL(k_eval<WD>, dim3(grid), dim3(kEvalTile * kEvalWaves), 0,
-                       s, a);
+    if (e0 && e1) {
+        // events stamped by the dispatch itself: their interval is the
+        // kernel's execution, without the gaps around it
+        hipExtLaunchKernelGGL(k_eval<WD>, dim3(grid), dim3(kEvalTile * kEvalWaves), 0,
+                              s, e0, e1, 0, a);
+    } else {
+        hipLaunchKernelGGL(k_eval<WD>, dim3(grid), dim3(kEvalTile * kEvalWaves), 0,
+                           s, a);
+    }
     return hipGetLastError();
 }
 
@@ -65,23 +74,23 @@ hipError_t launch_reduce(const EvalArgs &a, unsigned long long *fitness,
     return hipGetLastError();
 }
 
-hipError_t launch_eval(const EvalArgs &a, hipStream_t s)
+hipError_t launch_eval(const EvalArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     if (a.P <= 0 || a.tiles_c <= 0 || a.tiles_i <= 0)
         return hipSuccess;
     const int w2 = 2 * a.t.W;
-    if (w2 <= 2) return launch_wd<2>(a, s);
-    if (w2 <= 4) return launch_wd<4>(a, s);
-    if (w2 <= 8) return launch_wd<8>(a, s);
-    if (w2 <= 16) return launch_wd<16>(a, s);
-    if (w2 <= 32) return launch_wd<32>(a, s);
-    if (w2 <= 48) return launch_wd<48>(a, s);
-    if (w2 <= 64) return launch_wd<64>(a, s);
-    if (w2 <= 96) return launch_wd<96>(a, s);
-    if (w2 <= 128) return launch_wd<128>(a, s);
-    if (w2 <= 160) return launch_wd<160>(a, s);
-    if (w2 <= 192) return launch_wd<192>(a, s);
-    if (w2 <= 256) return launch_wd<256>(a, s);
+    if (w2 <= 2) return launch_wd<2>(a, s, e0, e1);
+    if (w2 <= 4) return launch_wd<4>(a, s, e0, e1);
+    if (w2 <= 8) return launch_wd<8>(a, s, e0, e1);
+    if (w2 <= 16) return launch_wd<16>(a, s, e0, e1);
+    if (w2 <= 32) return launch_wd<32>(a, s, e0, e1);
+    if (w2 <= 48) return launch_wd<48>(a, s, e0, e1);
+    if (w2 <= 64) return launch_wd<64>(a, s, e0, e1);
+    if (w2 <= 96) return launch_wd<96>(a, s, e0, e1);
+    if (w2 <= 128) return launch_wd<128>(a, s, e0, e1);
+    if (w2 <= 160) return launch_wd<160>(a, s, e0, e1);
+    if (w2 <= 192) return launch_wd<192>(a, s, e0, e1);
+    if (w2 <= 256) return launch_wd<256>(a, s, e0, e1);
     return hipErrorInvalidValue;
 }
 

@@ -71,7 +71,7 @@ int clients_per_block(int n, int P)
     if (forced > 0)
         return ((forced + 3) / 4) * 4;
     const long tiles_c = (P + kEvalTile - 1) / kEvalTile;
-    long cpb = (long)n * tiles_c / 2048;
+    long cpb = (long)n * tiles_c / 1024;
     if (cpb < 4)
         cpb = 4;
     if (cpb > 64)
@@ -587,15 +587,18 @@ hipError_t mark(pmp_ga *ga, hipStream_t s)
     return hipEventRecord(e, s);
 }
 
-// Evaluate the offspring buffer `buf` (only slots flagged in ok[buf]).
+// Evaluate the offspring buffer `buf` (only slots flagged in ok[buf]); when
+// profiling, with a pair of events stamped by the launch itself.
 hipError_t ga_eval(pmp_ga *ga, const GaArgs &g, int buf, hipStream_t s)
 {
-    hipError_t e = mark(ga, s);
-    if (e == hipSuccess)
-        e = launch_eval(ga_eval_args(ga, g, buf), s);
-    if (e == hipSuccess)
-        e = mark(ga, s);
-    return e;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (ga->prof) {
+        e0 = next_event(ga);
+        e1 = next_event(ga);
+        if (!e0 || !e1)
+            return hipErrorOutOfMemory;
+    }
+    return launch_eval(ga_eval_args(ga, g, buf), s, e0, e1);
 }
 
 // Host-side totals of the per-chromosome counters.
