@@ -191,6 +191,53 @@ PMP_API pmp_status pmp_ga_state(pmp_ga *ga, uint64_t *population, int64_t *fitne
 PMP_API void pmp_ga_destroy(pmp_ga *ga);
 
 /* ---------------------------------------------------------------------------
+ * pmp_ga_autotune (not in the paper) - choose the evaluation tile of a run:
+ * how many clients one workgroup of the evaluation kernel takes (its 64
+ * chromosomes are fixed, one per lane).  Candidates 4..128 are timed on a
+ * generation-0 population of this run with HIP events; the fastest is kept
+ * and remembered for runs of similar shape (n, m/p, W, P) in this process.
+ * Results do not depend on the choice (integer sums).  Call it before the
+ * first pmp_ga_step and before adding the run to a batch.  `chosen`
+ * (optional) receives the clients per workgroup.  PMP_EINVAL after the first
+ * generation.
+ * ------------------------------------------------------------------------- */
+PMP_API pmp_status pmp_ga_autotune(pmp_ga *ga, int32_t *chosen, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Batching (not in the paper): advance many GA runs, typically on different
+ * instances of uneven n, m, p, in one persistent kernel launch.  Each phase
+ * of a generation (population, evaluation, each crossover/mutation stage,
+ * group and global bests) spreads the work items of all runs over the whole
+ * GPU, with grid barriers between phases; runs that have stopped, or have
+ * fewer stages, sit the later phases out.  Every run evolves exactly as
+ * pmp_ga_step would evolve it alone (same Philox streams, same decisions).
+ *
+ * pmp_batch_create  gas: `count` distinct GA handles (borrowed; they must
+ *                   outlive the batch and must not be stepped otherwise
+ *                   while a batch step is in flight).  Tune a GA
+ *                   (pmp_ga_autotune) before adding it to a batch.
+ * pmp_batch_step    enqueue `generations` generations of every run on
+ *                   `stream`: one launch, captured once per generation count
+ *                   into a hipGraph and replayed (PMP_BATCH_GRAPH=0: plain
+ *                   cooperative launch).  Asynchronous.
+ * pmp_batch_check   wait for `stream`; PMP_EDEVICE if a grid barrier timed
+ *                   out (the kernel then drains without finishing); `grid`
+ *                   (optional) receives the workgroups of the last launch.
+ * pmp_ga_step_batch create, step once, check, destroy.
+ * Results are read per run with pmp_ga_best / pmp_ga_state.
+ * ------------------------------------------------------------------------- */
+typedef struct pmp_batch pmp_batch;
+
+PMP_API pmp_status pmp_batch_create(pmp_ga *const *gas, int32_t count,
+                                    pmp_batch **out);
+PMP_API pmp_status pmp_batch_step(pmp_batch *batch, int32_t generations,
+                                  void *stream);
+PMP_API pmp_status pmp_batch_check(pmp_batch *batch, int32_t *grid, void *stream);
+PMP_API void pmp_batch_destroy(pmp_batch *batch);
+PMP_API pmp_status pmp_ga_step_batch(pmp_ga *const *gas, int32_t count,
+                                     int32_t generations, void *stream);
+
+/* ---------------------------------------------------------------------------
  * pmp_solve - the whole method on host data: preprocess, run the GA to its
  * stop, return the best open set.
  *  d      n x m int32 host matrix (row stride m).

@@ -22,7 +22,9 @@ __all__ = [
     "pmp_instance_tables", "pmp_eval_population", "pmp_instance_check",
     "pmp_instance_destroy", "pmp_ga_create", "pmp_ga_step", "pmp_ga_best",
     "pmp_ga_state", "pmp_ga_destroy", "pmp_solve", "pmp_ga_profile",
-    "pmp_ga_profile_read", "Instance", "GA", "EXPORTS",
+    "pmp_ga_profile_read", "pmp_ga_autotune", "pmp_batch_create",
+    "pmp_batch_step", "pmp_batch_check", "pmp_batch_destroy",
+    "pmp_ga_step_batch", "Instance", "GA", "Batch", "EXPORTS",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -37,7 +39,8 @@ EXPORTS = [
     "pmp_eval_population", "pmp_instance_check", "pmp_instance_destroy",
     "pmp_ga_create", "pmp_ga_step", "pmp_ga_best", "pmp_ga_state",
     "pmp_ga_destroy", "pmp_solve", "pmp_ga_profile", "pmp_ga_profile_read",
-    "pmp_status_str", "pmp_last_error",
+    "pmp_status_str", "pmp_last_error", "pmp_ga_autotune", "pmp_batch_create",
+    "pmp_batch_step", "pmp_batch_check", "pmp_batch_destroy", "pmp_ga_step_batch",
 ]
 
 
@@ -103,13 +106,20 @@ def lib():
                             C.POINTER(_i64), C.POINTER(GaStats)]
     L.pmp_ga_profile.argtypes = [_vp, _i32]
     L.pmp_ga_profile_read.argtypes = [_vp, C.POINTER(Profile), _vp]
+    L.pmp_ga_autotune.argtypes = [_vp, C.POINTER(_i32), _vp]
+    L.pmp_batch_create.argtypes = [C.POINTER(_vp), _i32, C.POINTER(_vp)]
+    L.pmp_batch_step.argtypes = [_vp, _i32, _vp]
+    L.pmp_batch_check.argtypes = [_vp, C.POINTER(_i32), _vp]
+    L.pmp_batch_destroy.argtypes = [_vp]
+    L.pmp_batch_destroy.restype = None
+    L.pmp_ga_step_batch.argtypes = [C.POINTER(_vp), _i32, _i32, _vp]
     L.pmp_status_str.argtypes = [_i32]
     L.pmp_status_str.restype = C.c_char_p
     L.pmp_last_error.argtypes = []
     L.pmp_last_error.restype = C.c_char_p
     for name in EXPORTS:
         if name not in ("pmp_instance_destroy", "pmp_ga_destroy",
-                        "pmp_status_str", "pmp_last_error"):
+                        "pmp_batch_destroy", "pmp_status_str", "pmp_last_error"):
             getattr(L, name).restype = _i32
     _lib = L
     return L
@@ -258,6 +268,43 @@ def pmp_solve(d, p, population, group_size, generations, seed, saturation=0,
     return open_, cost.value, st.as_dict()
 
 
+def pmp_ga_autotune(ga, stream=None):
+    out = _i32()
+    _check(lib().pmp_ga_autotune(ga, C.byref(out), _stream(stream)), "pmp_ga_autotune")
+    return out.value
+
+
+def _handles(gas):
+    arr = (_vp * len(gas))(*[g.value if isinstance(g, _vp) else g for g in gas])
+    return arr
+
+
+def pmp_batch_create(gas):
+    out = _vp()
+    _check(lib().pmp_batch_create(_handles(gas), len(gas), C.byref(out)),
+           "pmp_batch_create")
+    return out
+
+
+def pmp_batch_step(batch, generations, stream=None):
+    _check(lib().pmp_batch_step(batch, generations, _stream(stream)), "pmp_batch_step")
+
+
+def pmp_batch_check(batch, stream=None):
+    grid = _i32()
+    _check(lib().pmp_batch_check(batch, C.byref(grid), _stream(stream)), "pmp_batch_check")
+    return grid.value
+
+
+def pmp_batch_destroy(batch):
+    lib().pmp_batch_destroy(batch)
+
+
+def pmp_ga_step_batch(gas, generations, stream=None):
+    _check(lib().pmp_ga_step_batch(_handles(gas), len(gas), generations, _stream(stream)),
+           "pmp_ga_step_batch")
+
+
 # ------------------------------------------------------- small conveniences
 class Instance:
     """Owning wrapper of a pmp_instance handle."""
@@ -320,12 +367,41 @@ class GA:
     def profile(self, enable=True):
         pmp_ga_profile(self.handle, enable)
 
+    def autotune(self, stream=None):
+        return pmp_ga_autotune(self.handle, stream)
+
     def profile_read(self, stream=None):
         return pmp_ga_profile_read(self.handle, stream)
 
     def close(self):
         if self.handle:
             pmp_ga_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Owning wrapper of a pmp_batch handle over GA objects (which must
+    outlive it)."""
+
+    def __init__(self, gas):
+        self.gas = list(gas)
+        self.handle = pmp_batch_create([g.handle for g in self.gas])
+
+    def step(self, generations, stream=None):
+        pmp_batch_step(self.handle, generations, stream)
+
+    def check(self, stream=None):
+        return pmp_batch_check(self.handle, stream)
+
+    def close(self):
+        if self.handle:
+            pmp_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

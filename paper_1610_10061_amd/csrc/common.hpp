@@ -113,11 +113,31 @@ hipError_t launch_ga_init(const GaArgs &g, hipStream_t s);
 hipError_t launch_ga_stage(const GaArgs &g, int in, int prev, int op,
                            int index, hipStream_t s);
 hipError_t launch_ga_best(const GaArgs &g, int fb, hipStream_t s);
-// One cooperative launch running `generations` generations; evaluation tiles
-// from `e` (its masks and active flags are set per phase).  max_blocks > 0
-// caps the grid; the grid used is returned.
-hipError_t launch_ga_persistent(const GaArgs &g, const EvalArgs &e,
-                                int generations, int max_blocks, hipStream_t s,
-                                int *grid);
+// One instance of a batched (persistent) GA launch: its GA state and its
+// evaluation tiling, with its offsets in the batch's global item ranges.
+struct BatchItem {
+    GaArgs g;
+    EvalArgs e;       // masks / active are set per phase by the kernel
+    int32_t X, S;     // crossover stages run, all stages (X + Y)
+    int32_t fb;       // buffer holding the population after the last stage
+};
+
+struct BatchArgs {
+    const BatchItem *items;
+    const int32_t *chrom0;  // count + 1 prefix offsets of chromosomes
+    const int32_t *tile0;   // ... of evaluation tiles
+    const int32_t *group0;  // ... of groups
+    int32_t count, max_S;
+    uint32_t *bar;          // grid barrier: epoch word, then one flag per
+                            // workgroup (32 words apart)
+    uint32_t *err;          // batch error word (barrier time-outs)
+};
+
+// One cooperative launch running `generations` generations of every
+// instance of the batch.  max_blocks > 0 caps the grid; the grid used is
+// returned.  max_w2 = largest 2*W of the batch (LDS sizing).
+hipError_t launch_ga_batch(const BatchArgs &b, int generations, int max_w2,
+                           int max_blocks, int want_blocks, hipStream_t s,
+                           int *grid, bool cooperative);
 
 }  // namespace pmp

@@ -3,10 +3,11 @@
 //
 //  - one kernel per step: k_init, the evaluation kernel, k_stage for each
 //    stage, k_best; ordered by the stream.
-//  - k_ga_persistent: one cooperative launch runs whole generations; its
-//    phases are separated by grid barriers, which removes the per-launch
-//    gaps and prologues that dominate at a few microseconds of work per
-//    stage.
+//  - k_ga_batch: one persistent launch runs whole generations of one or
+//    many instances; its phases are separated by grid barriers.  It pays
+//    off when a phase holds much work (a batch of instances); for a single
+//    small instance the per-step kernels are faster, because every barrier
+//    costs each workgroup an L2 write-back and invalidate.
 #include "eval_device.hpp"
 #include "ga_device.hpp"
 
@@ -95,19 +96,20 @@ __device__ __forceinline__ bool wait_for(const uint32_t *p, uint32_t want,
 struct GridBarrier {
     uint32_t *epoch;  // bar[0]
     uint32_t *flags;  // bar + kFlagStride, one per workgroup
+    uint32_t *err;
     uint32_t next;    // epoch number of the next barrier
 
-    __device__ __forceinline__ explicit GridBarrier(uint32_t *bar)
-        : epoch(bar), flags(bar + kFlagStride), next(load_agent(bar) + 1u)
+    __device__ __forceinline__ GridBarrier(uint32_t *bar, uint32_t *e)
+        : epoch(bar), flags(bar + kFlagStride), err(e), next(load_agent(bar) + 1u)
     {
     }
 
-    __device__ __forceinline__ bool sync(const GaArgs &g, int *flag)
+    __device__ __forceinline__ bool sync(int *flag)
     {
         __syncthreads();
         const uint32_t want = next++;
         if (threadIdx.x == 0) {
-            int ok = (load_agent(g.err) & ERR_BARRIER_TIMEOUT) == 0;
+            int ok = (load_agent(err) & ERR_BARRIER_TIMEOUT) == 0;
             if (ok) {
                 // publish this workgroup's writes (L2 write-back), then arrive
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -122,14 +124,14 @@ struct GridBarrier {
         if (blockIdx.x == 0) {
             int ok = 1;
             for (int b = threadIdx.x; b < (int)gridDim.x && ok; b += blockDim.x)
-                ok = wait_for(flags + (size_t)b * kFlagStride, want, g.err);
+                ok = wait_for(flags + (size_t)b * kFlagStride, want, err);
             if (!ok)
                 *flag = 0;
             __syncthreads();
             if (threadIdx.x == 0 && *flag)
                 __hip_atomic_store(epoch, want, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else if (threadIdx.x == 0) {
-            if (!wait_for(epoch, want, g.err))
+            if (!wait_for(epoch, want, err))
                 *flag = 0;
         }
         if (threadIdx.x == 0)  // see the other workgroups' writes (L2 invalidate)
@@ -139,28 +141,70 @@ struct GridBarrier {
     }
 };
 
-// Evaluation phase: the (client tile, chromosome tile) items, client-tile
-// major, are cut into 8 contiguous ranges; the workgroups of XCD x (block
-// index = x mod 8) take range x, so chromosome tiles sharing Pi' rows share
-// an L2.
+// Instance owning global item `x` of a range with prefix offsets `start`
+// (count + 1 entries): the last b with start[b] <= x.
+__device__ __forceinline__ int owner(const int32_t *start, int count, int x)
+{
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= x)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// Evaluation phase: evaluation tiles of every instance whose generation has
+// a stage k (k < 0: the population's first evaluation), evaluating offspring
+// buffer `buf`.  The global tile range (instance-major, client-tile major
+// inside an instance) is cut into 8 contiguous parts; the workgroups of XCD
+// x (block index = x mod 8) take part x, so chromosome tiles sharing Pi'
+// rows share an L2.
 template <int WD>
-__device__ __forceinline__ void eval_phase(const EvalArgs &e, uint32_t *smask,
+__device__ __forceinline__ void eval_phase(const BatchArgs &B, int k, int buf,
+                                           uint32_t *smask,
                                            unsigned long long *sred)
 {
-    const int ntiles = e.tiles_c * e.tiles_i;
+    const int ntiles = B.tile0[B.count];
     const int chunk = (ntiles + 7) / 8;
     const int x = blockIdx.x & 7, per = (int)gridDim.x >> 3;
     const int end = min(ntiles, (x + 1) * chunk);
     for (int item = x * chunk + ((int)blockIdx.x >> 3); item < end; item += per) {
-        const int ti = item / e.tiles_c;
-        eval_tile<WD>(e, ti, item - ti * e.tiles_c, smask, sred);
+        const int b = owner(B.tile0, B.count, item);
+        const BatchItem &it = B.items[b];
+        if (ga_stopped(it.g) || k >= it.S)
+            continue;
+        EvalArgs e = it.e;
+        e.masks = buf ? it.g.off[1] : it.g.off[0];
+        e.active = buf ? it.g.ok[1] : it.g.ok[0];
+        const int local = item - B.tile0[b];
+        const int ti = local / e.tiles_c;
+        eval_tile<WD>(e, ti, local - ti * e.tiles_c, smask, sred);
     }
 }
 
+// All instances stopped?  (Every workgroup reads the same flags after the
+// same barrier, so the answer is the same everywhere.)
+__device__ __forceinline__ bool all_stopped(const BatchArgs &B)
+{
+    for (int b = 0; b < B.count; ++b)
+        if (!ga_stopped(B.items[b].g))
+            return false;
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// Persistent kernel: `generations` generations of every instance of the
+// batch in one launch.  Each phase spreads the work items of all instances
+// (chromosomes, evaluation tiles, groups) over the whole grid; grid barriers
+// separate the phases.  Instances with fewer stages skip the later ones,
+// stopped instances skip everything.  A single instance is a batch of one.
+// ---------------------------------------------------------------------------
 template <int WD>
-__global__ __launch_bounds__(64 * kGaWaves) void k_ga_persistent(GaArgs g,
-                                                                 EvalArgs e,
-                                                                 int generations)
+__global__ __launch_bounds__(64 * kGaWaves) void k_ga_batch(BatchArgs B,
+                                                            int generations)
 {
     extern __shared__ uint64_t lds[];
     uint32_t *smask = reinterpret_cast<uint32_t *>(lds);
@@ -171,44 +215,53 @@ __global__ __launch_bounds__(64 * kGaWaves) void k_ga_persistent(GaArgs g,
     __shared__ int flag;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int gw = blockIdx.x * kGaWaves + wave, nw = gridDim.x * kGaWaves;
-    const int X = ga_xstages(g), S = X + g.Y;
-    const int fb = (S % 2) ^ 1;
-    GridBarrier bar(g.bar);
+    const int nchrom = B.chrom0[B.count], ngroups = B.group0[B.count];
+    GridBarrier bar(B.bar, B.err);
 
     for (int gen = 0; gen < generations; ++gen) {
-        if (ga_stopped(g))
+        if (all_stopped(B))
             return;
-        for (int c = gw; c < g.P; c += nw)
-            ga_init_one(g, c, lane);
-        if (!bar.sync(g, &flag))
+        for (int cg = gw; cg < nchrom; cg += nw) {
+            const int b = owner(B.chrom0, B.count, cg);
+            const BatchItem &it = B.items[b];
+            if (!ga_stopped(it.g))
+                ga_init_one(it.g, cg - B.chrom0[b], lane);
+        }
+        if (!bar.sync(&flag))
             return;
-        e.masks = g.off[0];
-        e.active = g.ok[0];
-        eval_phase<WD>(e, smask, sred);
-        if (!bar.sync(g, &flag))
+        eval_phase<WD>(B, -1, 0, smask, sred);
+        if (!bar.sync(&flag))
             return;
-        for (int k = 0; k <= S; ++k) {
-            int prev, op, index;
-            ga_stage_ops(k, X, S, &prev, &op, &index);
-            for (int c = gw; c < g.P; c += nw)
-                ga_stage_one(g, c, lane, k & 1, prev, op, index);
-            if (!bar.sync(g, &flag))
+        for (int k = 0; k <= B.max_S; ++k) {
+            for (int cg = gw; cg < nchrom; cg += nw) {
+                const int b = owner(B.chrom0, B.count, cg);
+                const BatchItem &it = B.items[b];
+                if (ga_stopped(it.g) || k > it.S)
+                    continue;
+                int prev, op, index;
+                ga_stage_ops(k, it.X, it.S, &prev, &op, &index);
+                ga_stage_one(it.g, cg - B.chrom0[b], lane, k & 1, prev, op, index);
+            }
+            if (!bar.sync(&flag))
                 return;
-            if (op != OP_NONE) {
-                e.masks = buf(g.off, (k & 1) ^ 1);
-                e.active = buf(g.ok, (k & 1) ^ 1);
-                eval_phase<WD>(e, smask, sred);
-                if (!bar.sync(g, &flag))
+            if (k < B.max_S) {
+                eval_phase<WD>(B, k, (k & 1) ^ 1, smask, sred);
+                if (!bar.sync(&flag))
                     return;
             }
         }
-        for (int b = blockIdx.x; b < g.NB; b += gridDim.x)
-            ga_group_best(g, fb, b, sc, si);
-        if (!bar.sync(g, &flag))
+        for (int xg = blockIdx.x; xg < ngroups; xg += gridDim.x) {
+            const int b = owner(B.group0, B.count, xg);
+            const BatchItem &it = B.items[b];
+            if (!ga_stopped(it.g))
+                ga_group_best(it.g, it.fb, xg - B.group0[b], sc, si);
+        }
+        if (!bar.sync(&flag))
             return;
-        if (blockIdx.x == 0)
-            ga_global(g, sc, si);
-        if (!bar.sync(g, &flag))
+        for (int b = blockIdx.x; b < B.count; b += gridDim.x)
+            if (!ga_stopped(B.items[b].g))
+                ga_global(B.items[b].g, sc, si);
+        if (!bar.sync(&flag))
             return;
     }
 }
@@ -219,19 +272,18 @@ inline dim3 per_wave(int P)
 }
 
 template <int WD>
-size_t persistent_lds()
+size_t batch_lds()
 {
-    const size_t eval = sizeof(uint32_t) * kEvalTile * WD +
-                        sizeof(unsigned long long) * 2 * kEvalWaves * kEvalTile;
-    return eval;
+    return sizeof(uint32_t) * kEvalTile * WD +
+           sizeof(unsigned long long) * 2 * kEvalWaves * kEvalTile;
 }
 
 template <int WD>
-hipError_t persistent_wd(const GaArgs &g, const EvalArgs &e, int generations,
-                         int max_blocks, hipStream_t s, int *grid_out)
+hipError_t batch_wd(const BatchArgs &b, int generations, int max_blocks,
+                    int want, hipStream_t s, int *grid_out, bool cooperative)
 {
-    auto fn = k_ga_persistent<WD>;
-    const size_t lds = persistent_lds<WD>();
+    auto fn = k_ga_batch<WD>;
+    const size_t lds = batch_lds<WD>();
     hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
                                          hipFuncAttributeMaxDynamicSharedMemorySize,
                                          (int)lds);
@@ -248,7 +300,6 @@ hipError_t persistent_wd(const GaArgs &g, const EvalArgs &e, int generations,
     if (per_cu < 1)
         return hipErrorInvalidConfiguration;
     // enough workgroups for the widest phase, no more than fit at once
-    const int want = max(e.tiles_c * e.tiles_i, max((g.P + kGaWaves - 1) / kGaWaves, g.NB));
     int grid = min(want, min(per_cu, 4) * cus);
     if (max_blocks > 0)
         grid = min(grid, max_blocks);
@@ -256,10 +307,15 @@ hipError_t persistent_wd(const GaArgs &g, const EvalArgs &e, int generations,
     if (grid > per_cu * cus || grid > kMaxPersistentBlocks)
         return hipErrorInvalidConfiguration;
     *grid_out = grid;
-    GaArgs ga = g;
-    EvalArgs ea = e;
+    if (!cooperative) {
+        // every workgroup fits at once (checked above); the barrier waits
+        // are bounded in any case
+        hipLaunchKernelGGL(fn, dim3(grid), dim3(64 * kGaWaves), lds, s, b, generations);
+        return hipGetLastError();
+    }
+    BatchArgs ba = b;
     int gens = generations;
-    void *args[] = {&ga, &ea, &gens};
+    void *args[] = {&ba, &gens};
     return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(fn), dim3(grid),
                                       dim3(64 * kGaWaves), args, (unsigned)lds, s);
 }
@@ -288,23 +344,28 @@ hipError_t launch_ga_best(const GaArgs &g, int fb, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_ga_persistent(const GaArgs &g, const EvalArgs &e,
-                                int generations, int max_blocks, hipStream_t s,
-                                int *grid)
+hipError_t launch_ga_batch(const BatchArgs &b, int generations, int max_w2,
+                           int max_blocks, int want_blocks, hipStream_t s,
+                           int *grid, bool cooperative)
 {
-    const int w2 = 2 * g.t.W;
-    if (w2 <= 2) return persistent_wd<2>(g, e, generations, max_blocks, s, grid);
-    if (w2 <= 4) return persistent_wd<4>(g, e, generations, max_blocks, s, grid);
-    if (w2 <= 8) return persistent_wd<8>(g, e, generations, max_blocks, s, grid);
-    if (w2 <= 16) return persistent_wd<16>(g, e, generations, max_blocks, s, grid);
-    if (w2 <= 32) return persistent_wd<32>(g, e, generations, max_blocks, s, grid);
-    if (w2 <= 48) return persistent_wd<48>(g, e, generations, max_blocks, s, grid);
-    if (w2 <= 64) return persistent_wd<64>(g, e, generations, max_blocks, s, grid);
-    if (w2 <= 96) return persistent_wd<96>(g, e, generations, max_blocks, s, grid);
-    if (w2 <= 128) return persistent_wd<128>(g, e, generations, max_blocks, s, grid);
-    if (w2 <= 160) return persistent_wd<160>(g, e, generations, max_blocks, s, grid);
-    if (w2 <= 192) return persistent_wd<192>(g, e, generations, max_blocks, s, grid);
-    if (w2 <= 256) return persistent_wd<256>(g, e, generations, max_blocks, s, grid);
+    const int w2 = max_w2;
+#define PMP_BATCH_WD(N)                                                        \
+    if (w2 <= N)                                                               \
+        return batch_wd<N>(b, generations, max_blocks, want_blocks, s, grid,   \
+                           cooperative);
+    PMP_BATCH_WD(2)
+    PMP_BATCH_WD(4)
+    PMP_BATCH_WD(8)
+    PMP_BATCH_WD(16)
+    PMP_BATCH_WD(32)
+    PMP_BATCH_WD(48)
+    PMP_BATCH_WD(64)
+    PMP_BATCH_WD(96)
+    PMP_BATCH_WD(128)
+    PMP_BATCH_WD(160)
+    PMP_BATCH_WD(192)
+    PMP_BATCH_WD(256)
+#undef PMP_BATCH_WD
     return hipErrorInvalidValue;
 }
 

@@ -7,8 +7,12 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "common.hpp"
@@ -125,6 +129,34 @@ struct pmp_instance {
     }
 };
 
+namespace {
+
+// Device-side description of a set of GA runs advanced together by the
+// persistent kernel (k_ga_batch).
+struct BatchHost {
+    std::vector<pmp_ga *> gas;
+    BatchItem *d_items = nullptr;
+    int32_t *d_prefix = nullptr;  // chrom0 | tile0 | group0, count + 1 each
+    uint32_t *d_bar = nullptr;
+    uint32_t *d_err = nullptr;
+    BatchArgs args{};
+    int max_w2 = 2, want = 8, last_grid = 0;
+    std::map<int, hipGraphExec_t> graphs;  // by generations per launch
+
+    void release()
+    {
+        for (auto &kv : graphs)
+            (void)hipGraphExecDestroy(kv.second);
+        graphs.clear();
+        dfree(d_items);
+        dfree(d_prefix);
+        dfree(d_bar);
+        dfree(d_err);
+    }
+};
+
+}  // namespace
+
 struct pmp_ga {
     pmp_instance *inst = nullptr;
     pmp_ga_params prm{};
@@ -139,7 +171,8 @@ struct pmp_ga {
     unsigned long long *gcost = nullptr, *gs = nullptr, *cstat = nullptr;
     uint32_t *arrive = nullptr;
     uint32_t *bar = nullptr;
-    bool persistent = false;  // one cooperative launch per pmp_ga_step call
+    bool persistent = false;  // one persistent launch per pmp_ga_step call
+    BatchHost *self = nullptr;  // this run as a batch of one
     // graph of `graph_gens` generations of the per-step launch sequence
     int graph_gens = 0;
     hipGraphExec_t gexec = nullptr;
@@ -189,6 +222,76 @@ struct pmp_ga {
         g.err = inst->err;
         return g;
     }
+};
+
+
+namespace {
+
+EvalArgs ga_eval_args(const pmp_ga *ga, const GaArgs &g, int buf);
+
+hipError_t batch_build(BatchHost &bh, pmp_ga *const *gas, int count)
+{
+    bh.gas.assign(gas, gas + count);
+    std::vector<BatchItem> items((size_t)count);
+    std::vector<int32_t> prefix(3 * ((size_t)count + 1), 0);
+    int32_t *c0 = prefix.data(), *t0 = c0 + count + 1, *g0 = t0 + count + 1;
+    int max_S = 0, max_w2 = 2;
+    for (int b = 0; b < count; ++b) {
+        pmp_ga *ga = gas[b];
+        BatchItem &it = items[b];
+        it.g = ga->args();
+        it.e = ga_eval_args(ga, it.g, 0);
+        it.e.done = nullptr;
+        it.X = ga->xstages();
+        it.S = it.X + ga->Y;
+        it.fb = ga->final_buf();
+        c0[b + 1] = c0[b] + ga->prm.population;
+        t0[b + 1] = t0[b] + it.e.tiles_c * it.e.tiles_i;
+        g0[b + 1] = g0[b] + ga->NB;
+        max_S = max_S > it.S ? max_S : it.S;
+        max_w2 = max_w2 > 2 * ga->inst->W ? max_w2 : 2 * ga->inst->W;
+    }
+    hipError_t e = hipSuccess;
+    if (dalloc(&bh.d_items, (size_t)count) || dalloc(&bh.d_prefix, prefix.size()) ||
+        dalloc(&bh.d_bar, kBarrierWords) || dalloc(&bh.d_err, 1))
+        return hipErrorOutOfMemory;
+    e = hipMemcpy(bh.d_items, items.data(), sizeof(BatchItem) * count, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(bh.d_prefix, prefix.data(), sizeof(int32_t) * prefix.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemset(bh.d_bar, 0, sizeof(uint32_t) * kBarrierWords);
+    if (e == hipSuccess)
+        e = hipMemset(bh.d_err, 0, sizeof(uint32_t));
+    bh.args.items = bh.d_items;
+    bh.args.chrom0 = bh.d_prefix;
+    bh.args.tile0 = bh.d_prefix + count + 1;
+    bh.args.group0 = bh.d_prefix + 2 * (count + 1);
+    bh.args.count = count;
+    bh.args.max_S = max_S;
+    bh.args.bar = bh.d_bar;
+    bh.args.err = bh.d_err;
+    bh.max_w2 = max_w2;
+    const int waves = (c0[count] + 3) / 4;  // one wave per chromosome, 4 per workgroup
+    bh.want = t0[count] > waves ? t0[count] : waves;
+    if (g0[count] > bh.want)
+        bh.want = g0[count];
+    return e;
+}
+
+hipError_t batch_launch(BatchHost &bh, int generations, int max_blocks,
+                        hipStream_t s, bool cooperative)
+{
+    return launch_ga_batch(bh.args, generations, bh.max_w2, max_blocks, bh.want, s,
+                           &bh.last_grid, cooperative);
+}
+
+}  // namespace
+
+struct pmp_batch {
+    BatchHost bh;
+    bool graphs = true;
+    int max_blocks = 0;
 };
 
 extern "C" {
@@ -459,6 +562,10 @@ void pmp_ga_destroy(pmp_ga *ga)
     dfree(ga->cstat);
     dfree(ga->arrive);
     dfree(ga->bar);
+    if (ga->self) {
+        ga->self->release();
+        delete ga->self;
+    }
     if (ga->gexec)
         (void)hipGraphExecDestroy(ga->gexec);
     for (hipEvent_t e : ga->ev)
@@ -686,9 +793,14 @@ pmp_status pmp_ga_step(pmp_ga *ga, int32_t generations, void *stream)
     hipStream_t s = (hipStream_t)stream;
     const GaArgs g = ga->args();
     if (ga->persistent) {
+        if (!ga->self) {
+            ga->self = new BatchHost;
+            pmp_ga *one = ga;
+            if (batch_build(*ga->self, &one, 1) != hipSuccess)
+                return fail(PMP_ENOMEM, "persistent launch set-up");
+        }
         HIP_TRY(mark(ga, s));
-        HIP_TRY(launch_ga_persistent(g, ga_eval_args(ga, g, 0), generations,
-                                     ga->max_blocks, s, &ga->last_grid));
+        HIP_TRY(batch_launch(*ga->self, generations, ga->max_blocks, s, true));
         HIP_TRY(mark(ga, s));
         return PMP_OK;
     }
@@ -732,6 +844,11 @@ pmp_status pmp_ga_best(pmp_ga *ga, uint64_t *mask, int64_t *cost,
     }
     uint32_t herr = 0;
     HIP_TRY(hipMemcpy(&herr, ga->inst->err, sizeof herr, hipMemcpyDeviceToHost));
+    if (ga->self) {
+        uint32_t berr = 0;
+        HIP_TRY(hipMemcpy(&berr, ga->self->d_err, sizeof berr, hipMemcpyDeviceToHost));
+        herr |= berr;
+    }
     return status_from_err(herr);
 }
 
@@ -798,6 +915,226 @@ pmp_status pmp_ga_profile_read(pmp_ga *ga, pmp_profile *out, void *stream)
     ga->base_scan = tot[CS_SCAN];
     ga->base_evals = tot[CS_EVALS];
     return PMP_OK;
+}
+
+pmp_status pmp_ga_autotune(pmp_ga *ga, int32_t *chosen, void *stream)
+{
+    if (!ga)
+        return fail(PMP_EINVAL, "ga is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipStreamSynchronize(s));
+    unsigned long long gs[GS_COUNT];
+    HIP_TRY(hipMemcpy(gs, ga->gs, sizeof gs, hipMemcpyDeviceToHost));
+    if (gs[GS_GEN] != 0)
+        return fail(PMP_EINVAL, "autotune a GA before its first generation");
+    const pmp_instance *inst = ga->inst;
+    const int P = ga->prm.population, n = inst->n;
+    int best = clients_per_block(n, P);
+    const bool forced = env_int("PMP_CLIENTS_PER_BLOCK", 0) > 0;
+    // measured choices are shared by runs of similar shape
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int, int>, int> cache;
+    const auto key = std::make_tuple((int)std::lround(std::log((double)n) / std::log(1.15)),
+                                     2 * inst->W,
+                                     (int)std::lround(std::log((inst->m + 1.0) / (inst->p + 1.0)) /
+                                                      std::log(1.3)),
+                                     P);
+    bool cached = false;
+    if (!forced) {
+        std::lock_guard<std::mutex> lock(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            best = it->second;
+            cached = true;
+        }
+    }
+    if (!forced && !cached) {
+        // a generation-0 population to time the evaluation on
+        GaArgs g = ga->args();
+        HIP_TRY(launch_ga_init(g, s));
+        const int cands[] = {4, 8, 16, 32, 64, 128};
+        const int max_ti = (n + 3) / 4;
+        unsigned long long *part = nullptr;
+        uint32_t *spart = nullptr;
+        if (dalloc(&part, (size_t)max_ti * P) || dalloc(&spart, (size_t)max_ti * P)) {
+            dfree(part);
+            return fail(PMP_ENOMEM, "autotune workspace");
+        }
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        hipError_t e = hipEventCreate(&e0);
+        if (e == hipSuccess)
+            e = hipEventCreate(&e1);
+        float best_ms = 1e30f;
+        int last_ti = -1;
+        for (int cpb : cands) {
+            if (e != hipSuccess)
+                break;
+            if (cpb > ((n + 3) / 4) * 4 && last_ti == 1)
+                break;
+            EvalArgs a = ga_eval_args(ga, g, 0);
+            a.done = nullptr;
+            a.part = part;
+            a.spart = spart;
+            a.clients_per_block = cpb;
+            a.tiles_i = (n + cpb - 1) / cpb;
+            if (a.tiles_i == last_ti)
+                continue;
+            last_ti = a.tiles_i;
+            e = launch_eval(a, s);  // warm-up
+            if (e == hipSuccess)
+                e = hipEventRecord(e0, s);
+            for (int rep = 0; rep < 5 && e == hipSuccess; ++rep)
+                e = launch_eval(a, s);
+            if (e == hipSuccess)
+                e = hipEventRecord(e1, s);
+            if (e == hipSuccess)
+                e = hipEventSynchronize(e1);
+            float ms = 0;
+            if (e == hipSuccess)
+                e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess && ms < best_ms) {
+                best_ms = ms;
+                best = cpb;
+            }
+        }
+        if (e0)
+            (void)hipEventDestroy(e0);
+        if (e1)
+            (void)hipEventDestroy(e1);
+        dfree(part);
+        dfree(spart);
+        if (e != hipSuccess)
+            return fail(PMP_EDEVICE, "autotune: %s", hipGetErrorString(e));
+        std::lock_guard<std::mutex> lock(mu);
+        cache[key] = best;
+    }
+    if (best != ga->cpb) {
+        const int ti = (n + best - 1) / best;
+        dfree(ga->part);
+        dfree(ga->spart);
+        if (dalloc(&ga->part, (size_t)ti * P) || dalloc(&ga->spart, (size_t)ti * P))
+            return fail(PMP_ENOMEM, "GA partial sums for %d client tiles", ti);
+        ga->cpb = best;
+        ga->TI = ti;
+        if (ga->gexec) {
+            (void)hipGraphExecDestroy(ga->gexec);
+            ga->gexec = nullptr;
+        }
+        if (ga->self) {
+            ga->self->release();
+            delete ga->self;
+            ga->self = nullptr;
+        }
+    }
+    if (chosen)
+        *chosen = best;
+    return PMP_OK;
+}
+
+pmp_status pmp_batch_create(pmp_ga *const *gas, int32_t count, pmp_batch **out)
+{
+    if (!out)
+        return fail(PMP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!gas || count < 1)
+        return fail(PMP_EINVAL, "need at least one GA");
+    for (int b = 0; b < count; ++b) {
+        if (!gas[b])
+            return fail(PMP_EINVAL, "GA %d is NULL", b);
+        for (int c = 0; c < b; ++c)
+            if (gas[c] == gas[b])
+                return fail(PMP_EINVAL, "GA %d appears twice", b);
+    }
+    pmp_batch *bt = new pmp_batch;
+    hipError_t e = batch_build(bt->bh, gas, count);
+    if (e != hipSuccess) {
+        bt->bh.release();
+        delete bt;
+        return fail(PMP_ENOMEM, "batch set-up: %s", hipGetErrorString(e));
+    }
+    const char *g = getenv("PMP_BATCH_GRAPH");
+    bt->graphs = !(g && strcmp(g, "0") == 0);
+    bt->max_blocks = env_int("PMP_GA_BLOCKS", 0);
+    *out = bt;
+    return PMP_OK;
+}
+
+pmp_status pmp_batch_step(pmp_batch *bt, int32_t generations, void *stream)
+{
+    if (!bt)
+        return fail(PMP_EINVAL, "batch is NULL");
+    if (generations < 0)
+        return fail(PMP_EINVAL, "generations < 0");
+    if (generations == 0)
+        return PMP_OK;
+    hipStream_t s = (hipStream_t)stream;
+    BatchHost &bh = bt->bh;
+    if (!bt->graphs) {
+        HIP_TRY(batch_launch(bh, generations, bt->max_blocks, s, true));
+        return PMP_OK;
+    }
+    auto it = bh.graphs.find(generations);
+    if (it == bh.graphs.end()) {
+        // capture the single persistent launch once per generation count
+        hipStream_t cs = nullptr;
+        HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t le = batch_launch(bh, generations, bt->max_blocks, cs, false);
+            e = hipStreamEndCapture(cs, &graph);
+            if (le != hipSuccess)
+                e = le;
+        }
+        if (e == hipSuccess)
+            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (graph)
+            (void)hipGraphDestroy(graph);
+        (void)hipStreamDestroy(cs);
+        if (e != hipSuccess)
+            return fail(PMP_EDEVICE, "capturing the batch launch: %s", hipGetErrorString(e));
+        it = bh.graphs.emplace(generations, exec).first;
+    }
+    HIP_TRY(hipGraphLaunch(it->second, s));
+    return PMP_OK;
+}
+
+pmp_status pmp_batch_check(pmp_batch *bt, int32_t *grid, void *stream)
+{
+    if (!bt)
+        return fail(PMP_EINVAL, "batch is NULL");
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    uint32_t herr = 0;
+    HIP_TRY(hipMemcpy(&herr, bt->bh.d_err, sizeof herr, hipMemcpyDeviceToHost));
+    if (grid)
+        *grid = bt->bh.last_grid;
+    return status_from_err(herr);
+}
+
+void pmp_batch_destroy(pmp_batch *bt)
+{
+    if (!bt)
+        return;
+    bt->bh.release();
+    delete bt;
+}
+
+pmp_status pmp_ga_step_batch(pmp_ga *const *gas, int32_t count, int32_t generations,
+                             void *stream)
+{
+    pmp_batch *bt = nullptr;
+    pmp_status st = pmp_batch_create(gas, count, &bt);
+    if (st != PMP_OK)
+        return st;
+    const bool graphs = bt->graphs;
+    bt->graphs = false;  // a one-off launch needs no graph
+    st = pmp_batch_step(bt, generations, stream);
+    bt->graphs = graphs;
+    if (st == PMP_OK)
+        st = pmp_batch_check(bt, nullptr, stream);
+    pmp_batch_destroy(bt);
+    return st;
 }
 
 pmp_status pmp_solve(const int32_t *d, int32_t n, int32_t m, int32_t p,

@@ -26,7 +26,7 @@ from scipy.sparse.csgraph import dijkstra
 
 __all__ = [
     "graph_instance", "euclid_instance", "random_population", "pack_masks",
-    "unpack_masks", "words_for", "batch_specs", "batch_instance",
+    "unpack_masks", "words_for", "batch_specs", "batch_instance", "batch_instances",
     "example1_matrix",
 ]
 
@@ -39,37 +39,42 @@ def words_for(m: int) -> int:
 def _graph_edges(n: int, n_edges: int, rng: np.random.Generator,
                  wmin: int, wmax: int):
     """Random connected simple graph: a random spanning tree over a random
-    vertex order, then distinct extra edges drawn uniformly until n_edges."""
+    vertex order (vertex order[k] joins a uniformly chosen earlier vertex),
+    then distinct extra edges drawn uniformly, kept in draw order, until
+    n_edges."""
     if n_edges < n - 1:
         raise ValueError("a connected graph on n vertices needs n-1 edges")
     if n_edges > n * (n - 1) // 2:
         raise ValueError("too many edges for a simple graph")
-    order = rng.permutation(n)
-    edges = []
-    seen = set()
-    for k in range(1, n):
-        a = int(order[k])
-        b = int(order[int(rng.integers(0, k))])
-        key = (min(a, b), max(a, b))
-        seen.add(key)
-        edges.append(key)
-    while len(edges) < n_edges:
-        need = n_edges - len(edges)
+    order = rng.permutation(n).astype(np.int64)
+    if n > 1:
+        earlier = rng.integers(0, np.arange(1, n))
+        a, b = order[1:], order[earlier]
+    else:
+        a = b = np.zeros(0, np.int64)
+    lo, hi = np.minimum(a, b), np.maximum(a, b)
+    keys = lo * n + hi
+    seen = set(keys.tolist())
+    chosen = [keys]
+    have = len(keys)
+    while have < n_edges:
+        need = n_edges - have
         cand = rng.integers(0, n, size=(2 * need + 16, 2))
-        for a, b in cand:
-            a = int(a)
-            b = int(b)
-            if a == b:
-                continue
-            key = (min(a, b), max(a, b))
-            if key in seen:
-                continue
-            seen.add(key)
-            edges.append(key)
-            if len(edges) == n_edges:
-                break
+        x, y = cand[:, 0], cand[:, 1]
+        ok = x != y
+        k2 = np.minimum(x, y)[ok] * n + np.maximum(x, y)[ok]
+        # first occurrence of each new key, in draw order
+        _, first = np.unique(k2, return_index=True)
+        k2 = k2[np.sort(first)]
+        fresh = np.fromiter((k not in seen for k in k2.tolist()), bool, len(k2))
+        k2 = k2[fresh][:need]
+        seen.update(k2.tolist())
+        chosen.append(k2)
+        have += len(k2)
+    keys = np.concatenate(chosen)
+    edges = np.stack([keys // n, keys % n], axis=1)
     w = rng.integers(wmin, wmax + 1, size=len(edges))
-    return np.asarray(edges, dtype=np.int64), w.astype(np.int64)
+    return edges.astype(np.int64), w.astype(np.int64)
 
 
 def graph_instance(n: int, n_edges: int, seed: int, wmin: int = 1,
@@ -177,3 +182,11 @@ def batch_instance(spec) -> np.ndarray:
     if spec["kind"] == "graph":
         return graph_instance(spec["n"], 4 * spec["n"], spec["seed"])
     return euclid_instance(spec["n"], spec["seed"])
+
+
+def batch_instances(specs, workers: int = 8):
+    """All instances of a batch, built on a thread pool (the shortest-path
+    and distance computations release the interpreter lock)."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(batch_instance, specs))

@@ -1,0 +1,197 @@
+"""Batched GA (one persistent launch for many instances) and the evaluation
+tile autotuner, on the GPU.
+
+A batch step must leave every run exactly as stepping it alone would: same
+Philox streams, same integer decisions.  Each batched run is compared with
+the same run stepped on its own (per-step kernels) and, where the oracle
+finishes in seconds, with the oracle GA.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import pmp_inputs as gi
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pm():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1610_10061_amd as pm
+    pm.lib()
+    return pm
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _state(ga):
+    pop, fit, gm, gc = ga.state()
+    mask, cost, stats = ga.best()
+    return pop, fit, gm, gc, mask, cost, stats
+
+
+def _assert_same(a, b):
+    for x, y in zip(a[:6], b[:6]):
+        np.testing.assert_array_equal(x, y)
+    for k in ("generations", "saturation_count", "done", "chromosome_evals",
+              "crossover_fail", "crossover_taken", "mutation_taken", "scan_total"):
+        assert a[6][k] == b[6][k], k
+
+
+def _mini_batch():
+    """Ragged shapes: graph and Euclidean, n != m, small and large p, p = 1
+    (no crossover), several group sizes and stage counts, m past 64."""
+    rng = np.random.default_rng(3)
+    cases = []
+    for k, (kind, n, m, p, P, NT, X, Y, sat) in enumerate([
+            ("graph", 60, 60, 4, 64, 16, 0, 0, 0),
+            ("euclid", 90, 90, 9, 128, 64, 0, 0, 3),
+            ("rand", 37, 150, 20, 64, 32, 5, 2, 0),
+            ("euclid", 200, 200, 1, 32, 8, 0, 0, 0),
+            ("graph", 130, 130, 30, 256, 256, 0, 0, 0),
+            ("rand", 20, 300, 150, 64, 64, 2, 9, 0),
+            ("euclid", 70, 70, 5, 8, 1, 0, 0, 2)]):
+        if kind == "graph":
+            d = gi.graph_instance(n, 2 * n, 100 + k)
+        elif kind == "euclid":
+            d = gi.euclid_instance(n, 100 + k)
+        else:
+            d = rng.integers(0, 500, size=(n, m)).astype(np.int32)
+        cases.append((d, p, P, NT, X, Y, sat, 7 + k))
+    return cases
+
+
+def _make(pm, cases, G):
+    insts, gas = [], []
+    for d, p, P, NT, X, Y, sat, seed in cases:
+        inst = pm.Instance(d, p)
+        insts.append(inst)
+        gas.append(pm.GA(inst, P, NT, G, seed, sat, X, Y))
+    return insts, gas
+
+
+@pytest.mark.parametrize("graph", ["1", "0"])
+def test_batch_equals_single_runs_and_oracle(pm, graph):
+    old = {k: os.environ.get(k) for k in ("PMP_BATCH_GRAPH", "PMP_GA_MODE")}
+    os.environ["PMP_BATCH_GRAPH"] = graph
+    os.environ["PMP_GA_MODE"] = "kernels"
+    try:
+        cases = _mini_batch()
+        G = 6
+        _say("mini batch of", len(cases), "graph", graph)
+        insts, gas = _make(pm, cases, G)
+        batch = pm.Batch(gas)
+        batch.step(3)
+        batch.step(3)  # the same generation count replays the captured graph
+        batch.check()
+        rinsts, refs = _make(pm, cases, G)
+        for r in refs:
+            r.step(G)
+        for (d, p, P, NT, X, Y, sat, seed), ga, ref in zip(cases, gas, refs):
+            a, b = _state(ga), _state(ref)
+            _assert_same(a, b)
+            st = oracle.GaState(d.shape[0], d.shape[1], p, P, NT, G, seed, sat, X, Y)
+            oracle.ga_run(d, st, G)
+            np.testing.assert_array_equal(a[0], st.pop)
+            assert a[5] == st.best_cost
+        batch.close()
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+def test_batch_small_grid_loops_every_phase(pm):
+    old = os.environ.get("PMP_GA_BLOCKS")
+    os.environ["PMP_GA_BLOCKS"] = "8"
+    try:
+        cases = _mini_batch()
+        insts, gas = _make(pm, cases, 4)
+        batch = pm.Batch(gas)
+        batch.step(4)
+        assert batch.check() == 8
+        rinsts, refs = _make(pm, cases, 4)
+        for r in refs:
+            r.step(4)
+        for ga, ref in zip(gas, refs):
+            _assert_same(_state(ga), _state(ref))
+        batch.close()
+    finally:
+        if old is None:
+            os.environ.pop("PMP_GA_BLOCKS", None)
+        else:
+            os.environ["PMP_GA_BLOCKS"] = old
+
+
+def test_step_batch_convenience_and_stopped_runs(pm):
+    cases = _mini_batch()[:3]
+    insts, gas = _make(pm, cases, 2)  # EvolveLimit 2: stepping 5 stops at 2
+    pm.pmp_ga_step_batch([g.handle for g in gas], 5)
+    for ga in gas:
+        _, _, stats = ga.best()
+        assert stats["generations"] == 2 and stats["done"] == 1
+
+
+def test_autotune_keeps_results(pm):
+    d = gi.euclid_instance(700, 5)
+    inst = pm.Instance(d, 40)
+    a = pm.GA(inst, 512, 128, 3, seed=1)
+    chosen = a.autotune()
+    assert chosen in (4, 8, 16, 32, 64, 128)
+    b = pm.GA(inst, 512, 128, 3, seed=1)
+    os.environ["PMP_CLIENTS_PER_BLOCK"] = "4"
+    try:
+        b.autotune()  # forced tile
+    finally:
+        os.environ.pop("PMP_CLIENTS_PER_BLOCK")
+    a.step(3)
+    b.step(3)
+    _assert_same(_state(a), _state(b))
+    with pytest.raises(pm.PmpError):
+        a.autotune()  # after the first generation
+
+
+def test_full_batch_config_sampled(pm):
+    """The ragged 256-instance configuration (n = m log-uniform in
+    [100, 2000], p uniform in [5, n/4], half graphs with 4n edges, half
+    Euclidean, population 256) stepped in one launch per call, as the
+    benchmark runs it; sampled runs are compared with the same runs stepped
+    alone and two with the oracle."""
+    specs = gi.batch_specs(256)
+    _say("generating 256 instances")
+    ds = [gi.batch_instance(s) for s in specs]
+    G = 2
+    insts, gas = [], []
+    for s, d in zip(specs, ds):
+        inst = pm.Instance(d, s["p"])
+        insts.append(inst)
+        ga = pm.GA(inst, 256, 256, 100, seed=s["index"])
+        ga.autotune()
+        gas.append(ga)
+    _say("batch step")
+    batch = pm.Batch(gas)
+    batch.step(G)
+    batch.check()
+    pick = [0, 1, 2, 3, 100, 101, 254, 255]
+    small = sorted(range(256), key=lambda b: specs[b]["n"])[:2]
+    for b in pick + small:
+        s = specs[b]
+        ref_inst = pm.Instance(ds[b], s["p"])
+        ref = pm.GA(ref_inst, 256, 256, 100, seed=b)
+        ref.step(G)
+        a = _state(gas[b])
+        _assert_same(a, _state(ref))
+        if b in small:
+            st = oracle.GaState(s["n"], s["n"], s["p"], 256, 256, 100, b)
+            oracle.ga_run(ds[b], st, G)
+            np.testing.assert_array_equal(a[0], st.pop)
+            assert a[5] == st.best_cost
+    batch.close()
