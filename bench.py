@@ -67,6 +67,71 @@ def cpu_baseline(d, p, P, NT, budget_s):
                       f"in {dt:.1f} s"}
 
 
+def bench_batch(args, specs, ds):
+    """256 ragged instances (population 256 each): all preprocessed, then
+    `--batch-generations` generations of every GA run, (a) in one persistent
+    launch per step replayed from a hipGraph, (b) instance by instance with
+    pmp_ga_step.  Reports instances per second of (a) and (b)."""
+    import torch
+    import paper_1610_10061_amd as pm
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    G = args.batch_generations
+    dd = [torch.from_numpy(d).cuda() for d in ds]
+
+    def run(batched, seed0):
+        t0 = time.perf_counter()
+        insts = [pm.Instance(d, s["p"], stream) for s, d in zip(specs, dd)]
+        gas = [pm.GA(i, 256, 256, G, seed0 + s["index"]) for i, s in zip(insts, specs)]
+        for g in gas:
+            g.autotune(stream)
+        t1 = time.perf_counter()
+        if batched:
+            bt = pm.Batch(gas)
+            bt.step(G, stream)
+            bt.check(stream)
+        else:
+            for g in gas:
+                g.step(G, stream)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        pairs = 0
+        costs = []
+        for g in gas:
+            _, c, st = g.best(stream)
+            pairs += st["pair_evals"]
+            costs.append(c)
+        if batched:
+            bt.close()
+        return t1 - t0, t2 - t1, pairs, costs
+
+    log("warm-up ...")
+    run(True, 10_000)
+    log("batched ...")
+    prep_b, evo_b, pairs_b, costs_b = run(True, 0)
+    log("one launch per instance ...")
+    prep_s, evo_s, pairs_s, costs_s = run(False, 0)
+    assert costs_b == costs_s, "batched and per-instance runs must agree"
+    out = {
+        "metric": "instances/s, 256 ragged instances x %d generations" % G,
+        "value": 256 / (prep_b + evo_b),
+        "unit": "instances/s",
+        "n_gpus": 1, "higher_is_better": True, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "batch of 256: n=m log-uniform [100,2000], p U[5,n/4], "
+                               "half graphs (4n edges, weights 1..100), half Euclidean; "
+                               "population 256 (NT=256), %d generations" % G},
+        "batched": {"preprocess_s": prep_b, "evolve_s": evo_b,
+                    "instances_per_s_evolve": 256 / evo_b,
+                    "pair_evals_per_s": pairs_b / evo_b},
+        "per_instance_launches": {"preprocess_s": prep_s, "evolve_s": evo_s,
+                                  "instances_per_s_evolve": 256 / evo_s,
+                                  "pair_evals_per_s": pairs_s / evo_s},
+        "speedup_evolve": evo_s / evo_b,
+        "identical_results": costs_b == costs_s,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +142,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="no per-launch events (the GA then replays hipGraphs)")
+    ap.add_argument("--workload", choices=["g900", "batch"], default="g900",
+                    help="g900: the headline configuration; batch: 256 ragged "
+                         "instances in one launch vs one launch per instance")
+    ap.add_argument("--batch-generations", type=int, default=100)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (scales the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
@@ -86,6 +155,17 @@ def main():
               "would shard by population across GPUs, which this build does not run.",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batch":
+        # instances are built before anything touches the GPU (worker
+        # processes must not inherit a GPU context)
+        import pmp_inputs as gi
+        from concurrent.futures import ProcessPoolExecutor
+        specs = gi.batch_specs(256)
+        log("generating 256 instances ...")
+        with ProcessPoolExecutor(max_workers=8) as ex:
+            ds = list(ex.map(gi.batch_instance, specs))
+        return bench_batch(args, specs, ds)
 
     import numpy as np
     import torch

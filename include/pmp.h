@@ -205,11 +205,13 @@ PMP_API pmp_status pmp_ga_autotune(pmp_ga *ga, int32_t *chosen, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Batching (not in the paper): advance many GA runs, typically on different
- * instances of uneven n, m, p, in one persistent kernel launch.  Each phase
- * of a generation (population, evaluation, each crossover/mutation stage,
- * group and global bests) spreads the work items of all runs over the whole
- * GPU, with grid barriers between phases; runs that have stopped, or have
- * fewer stages, sit the later phases out.  Every run evolves exactly as
+ * instances of uneven n, m, p, together.  Each phase of a generation
+ * (population, evaluation, each crossover/mutation stage, group and global
+ * bests) spreads the work items of all runs over the whole GPU; runs that
+ * have stopped, or have fewer stages, sit the later phases out.  Default:
+ * one batch-wide kernel per phase; PMP_BATCH_MODE=persistent: one persistent
+ * kernel with grid barriers between phases.  Either way a step is captured
+ * once into a hipGraph and replayed.  Every run evolves exactly as
  * pmp_ga_step would evolve it alone (same Philox streams, same decisions).
  *
  * pmp_batch_create  gas: `count` distinct GA handles (borrowed; they must
@@ -217,9 +219,10 @@ PMP_API pmp_status pmp_ga_autotune(pmp_ga *ga, int32_t *chosen, void *stream);
  *                   while a batch step is in flight).  Tune a GA
  *                   (pmp_ga_autotune) before adding it to a batch.
  * pmp_batch_step    enqueue `generations` generations of every run on
- *                   `stream`: one launch, captured once per generation count
- *                   into a hipGraph and replayed (PMP_BATCH_GRAPH=0: plain
- *                   cooperative launch).  Asynchronous.
+ *                   `stream`, captured once per generation count into a
+ *                   hipGraph and replayed (PMP_BATCH_GRAPH=0: launched
+ *                   directly, the persistent kernel cooperatively).
+ *                   Asynchronous.
  * pmp_batch_check   wait for `stream`; PMP_EDEVICE if a grid barrier timed
  *                   out (the kernel then drains without finishing); `grid`
  *                   (optional) receives the workgroups of the last launch.

@@ -51,6 +51,14 @@ struct EvalArgs {
     int32_t tiles_i;                  // ceil(n / clients_per_block)
 };
 
+// Index of the calling wave in its workgroup, as a wave-uniform (scalar)
+// value: derived from threadIdx.x the compiler cannot prove it uniform and
+// would keep everything computed from it in vector registers.
+__device__ __forceinline__ int wave_id()
+{
+    return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+}
+
 constexpr int kMaxPersistentBlocks = 4096;
 constexpr int kBarrierWords = 32 * (kMaxPersistentBlocks + 1);
 
@@ -139,5 +147,9 @@ struct BatchArgs {
 hipError_t launch_ga_batch(const BatchArgs &b, int generations, int max_w2,
                            int max_blocks, int want_blocks, hipStream_t s,
                            int *grid, bool cooperative);
+// The same generations as a sequence of batch-wide kernels (one per phase).
+hipError_t launch_ga_batch_kernels(const BatchArgs &b, int nchrom, int ntiles,
+                                   int ngroups, int generations, int max_w2,
+                                   hipStream_t s);
 
 }  // namespace pmp

@@ -106,7 +106,7 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
     const int i0 = ti * a.clients_per_block;
     const int i1 = min(a.t.n, i0 + a.clients_per_block);
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = wave_id();
     const int W2 = 2 * a.t.W;
 
     // The tile's independent loads go out together (one memory round trip):

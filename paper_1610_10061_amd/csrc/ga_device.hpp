@@ -460,7 +460,7 @@ __device__ __host__ __forceinline__ void ga_stage_ops(int k, int X, int S,
 __device__ __forceinline__ void block_argmin(unsigned long long f, int idx,
                                              unsigned long long *sc, int *si)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = wave_id();
     const int nwaves = (blockDim.x + 63) >> 6;
 #pragma unroll
     for (int d = 32; d > 0; d >>= 1) {

@@ -17,7 +17,7 @@ namespace {
 
 __global__ __launch_bounds__(64 * kGaWaves) void k_init(GaArgs g)
 {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = wave_id(), lane = threadIdx.x & 63;
     const int c = blockIdx.x * kGaWaves + wave;
     if (c >= g.P || ga_stopped(g))
         return;
@@ -28,7 +28,7 @@ __global__ __launch_bounds__(64 * kGaWaves) void k_stage(GaArgs g, int in,
                                                          int prev, int op,
                                                          int index)
 {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = wave_id(), lane = threadIdx.x & 63;
     const int c = blockIdx.x * kGaWaves + wave;
     if (c >= g.P || ga_stopped(g))
         return;
@@ -213,7 +213,7 @@ __global__ __launch_bounds__(64 * kGaWaves) void k_ga_batch(BatchArgs B,
     __shared__ unsigned long long sc[16];
     __shared__ int si[16];
     __shared__ int flag;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = wave_id(), lane = threadIdx.x & 63;
     const int gw = blockIdx.x * kGaWaves + wave, nw = gridDim.x * kGaWaves;
     const int nchrom = B.chrom0[B.count], ngroups = B.group0[B.count];
     GridBarrier bar(B.bar, B.err);
@@ -264,6 +264,112 @@ __global__ __launch_bounds__(64 * kGaWaves) void k_ga_batch(BatchArgs B,
         if (!bar.sync(&flag))
             return;
     }
+}
+
+// ---------------------------------------------------------------------------
+// The same phases as separate kernels, each spanning every instance of the
+// batch (the stream orders them; a hipGraph replays whole generations).
+// With a batch, each phase holds milliseconds of work, so launch gaps are
+// negligible and each kernel runs at its own register budget.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64 * kGaWaves) void k_batch_init(BatchArgs B)
+{
+    const int cg = blockIdx.x * kGaWaves + wave_id();
+    if (cg >= B.chrom0[B.count])
+        return;
+    const int b = owner(B.chrom0, B.count, cg);
+    const BatchItem &it = B.items[b];
+    if (!ga_stopped(it.g))
+        ga_init_one(it.g, cg - B.chrom0[b], threadIdx.x & 63);
+}
+
+template <int WD>
+__global__ __launch_bounds__(kEvalTile *kEvalWaves) void k_batch_eval(BatchArgs B, int k,
+                                                                      int buf)
+{
+    __shared__ uint32_t smask[kEvalTile * WD];
+    __shared__ unsigned long long sred[2 * kEvalWaves * kEvalTile];
+    const int ntiles = B.tile0[B.count];
+    // blocks are dealt to the 8 XCDs round-robin: give XCD x a contiguous
+    // eighth of the tile range
+    const int per_xcd = (int)gridDim.x >> 3;
+    const int item = ((int)blockIdx.x & 7) * per_xcd + ((int)blockIdx.x >> 3);
+    if (item >= ntiles)
+        return;
+    const int b = owner(B.tile0, B.count, item);
+    const BatchItem &it = B.items[b];
+    if (ga_stopped(it.g) || k >= it.S)
+        return;
+    EvalArgs e = it.e;
+    e.masks = buf ? it.g.off[1] : it.g.off[0];
+    e.active = buf ? it.g.ok[1] : it.g.ok[0];
+    const int local = item - B.tile0[b];
+    const int ti = local / e.tiles_c;
+    eval_tile<WD>(e, ti, local - ti * e.tiles_c, smask, sred);
+}
+
+__global__ __launch_bounds__(64 * kGaWaves) void k_batch_stage(BatchArgs B, int k)
+{
+    const int cg = blockIdx.x * kGaWaves + wave_id();
+    if (cg >= B.chrom0[B.count])
+        return;
+    const int b = owner(B.chrom0, B.count, cg);
+    const BatchItem &it = B.items[b];
+    if (ga_stopped(it.g) || k > it.S)
+        return;
+    int prev, op, index;
+    ga_stage_ops(k, it.X, it.S, &prev, &op, &index);
+    ga_stage_one(it.g, cg - B.chrom0[b], threadIdx.x & 63, k & 1, prev, op, index);
+}
+
+// Group bests; the last group of an instance to finish does that
+// instance's global update.
+__global__ __launch_bounds__(256) void k_batch_best(BatchArgs B)
+{
+    __shared__ unsigned long long sc[16];
+    __shared__ int si[16];
+    __shared__ int last;
+    const int xg = blockIdx.x;
+    const int b = owner(B.group0, B.count, xg);
+    const BatchItem &it = B.items[b];
+    if (ga_stopped(it.g))
+        return;
+    ga_group_best(it.g, it.fb, xg - B.group0[b], sc, si);
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0)
+        last = atomicAdd(it.g.arrive, 1u) == (uint32_t)(it.g.NB - 1);
+    __syncthreads();
+    if (!last)
+        return;
+    __threadfence();
+    ga_global(it.g, sc, si);
+    if (threadIdx.x == 0)
+        *it.g.arrive = 0;
+}
+
+template <int WD>
+hipError_t batch_kernels_wd(const BatchArgs &b, int nchrom, int ntiles, int ngroups,
+                            int generations, hipStream_t s)
+{
+    const dim3 waves((unsigned)((nchrom + kGaWaves - 1) / kGaWaves));
+    const dim3 tiles((unsigned)(((ntiles + 7) / 8) * 8));
+    for (int gen = 0; gen < generations; ++gen) {
+        hipLaunchKernelGGL(k_batch_init, waves, dim3(64 * kGaWaves), 0, s, b);
+        hipLaunchKernelGGL(k_batch_eval<WD>, tiles, dim3(kEvalTile * kEvalWaves), 0, s,
+                           b, -1, 0);
+        for (int k = 0; k <= b.max_S; ++k) {
+            hipLaunchKernelGGL(k_batch_stage, waves, dim3(64 * kGaWaves), 0, s, b, k);
+            if (k < b.max_S)
+                hipLaunchKernelGGL(k_batch_eval<WD>, tiles, dim3(kEvalTile * kEvalWaves),
+                                   0, s, b, k, (k & 1) ^ 1);
+        }
+        hipLaunchKernelGGL(k_batch_best, dim3((unsigned)ngroups), dim3(256), 0, s, b);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
 }
 
 inline dim3 per_wave(int P)
@@ -342,6 +448,30 @@ hipError_t launch_ga_best(const GaArgs &g, int fb, hipStream_t s)
     hipLaunchKernelGGL(k_best, dim3(g.NB), dim3(threads < 64 ? 64 : threads), 0, s,
                        g, fb);
     return hipGetLastError();
+}
+
+hipError_t launch_ga_batch_kernels(const BatchArgs &b, int nchrom, int ntiles,
+                                   int ngroups, int generations, int max_w2,
+                                   hipStream_t s)
+{
+    const int w2 = max_w2;
+#define PMP_BATCH_KWD(N)                                                       \
+    if (w2 <= N)                                                               \
+        return batch_kernels_wd<N>(b, nchrom, ntiles, ngroups, generations, s);
+    PMP_BATCH_KWD(2)
+    PMP_BATCH_KWD(4)
+    PMP_BATCH_KWD(8)
+    PMP_BATCH_KWD(16)
+    PMP_BATCH_KWD(32)
+    PMP_BATCH_KWD(48)
+    PMP_BATCH_KWD(64)
+    PMP_BATCH_KWD(96)
+    PMP_BATCH_KWD(128)
+    PMP_BATCH_KWD(160)
+    PMP_BATCH_KWD(192)
+    PMP_BATCH_KWD(256)
+#undef PMP_BATCH_KWD
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_ga_batch(const BatchArgs &b, int generations, int max_w2,

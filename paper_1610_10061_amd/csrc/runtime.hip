@@ -141,6 +141,7 @@ struct BatchHost {
     uint32_t *d_err = nullptr;
     BatchArgs args{};
     int max_w2 = 2, want = 8, last_grid = 0;
+    int nchrom = 0, ntiles = 0, ngroups = 0;
     std::map<int, hipGraphExec_t> graphs;  // by generations per launch
 
     void release()
@@ -272,6 +273,9 @@ hipError_t batch_build(BatchHost &bh, pmp_ga *const *gas, int count)
     bh.args.bar = bh.d_bar;
     bh.args.err = bh.d_err;
     bh.max_w2 = max_w2;
+    bh.nchrom = c0[count];
+    bh.ntiles = t0[count];
+    bh.ngroups = g0[count];
     const int waves = (c0[count] + 3) / 4;  // one wave per chromosome, 4 per workgroup
     bh.want = t0[count] > waves ? t0[count] : waves;
     if (g0[count] > bh.want)
@@ -291,8 +295,24 @@ hipError_t batch_launch(BatchHost &bh, int generations, int max_blocks,
 struct pmp_batch {
     BatchHost bh;
     bool graphs = true;
+    bool persistent = false;  // one persistent kernel instead of per-phase kernels
     int max_blocks = 0;
 };
+
+namespace {
+
+// Enqueue `generations` generations of a batch: one persistent kernel, or
+// one batch-wide kernel per phase.
+hipError_t batch_enqueue(pmp_batch *bt, int generations, hipStream_t s, bool cooperative)
+{
+    BatchHost &bh = bt->bh;
+    if (bt->persistent)
+        return batch_launch(bh, generations, bt->max_blocks, s, cooperative);
+    return launch_ga_batch_kernels(bh.args, bh.nchrom, bh.ntiles, bh.ngroups, generations,
+                                   bh.max_w2, s);
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -1054,6 +1074,8 @@ pmp_status pmp_batch_create(pmp_ga *const *gas, int32_t count, pmp_batch **out)
     }
     const char *g = getenv("PMP_BATCH_GRAPH");
     bt->graphs = !(g && strcmp(g, "0") == 0);
+    const char *mode = getenv("PMP_BATCH_MODE");
+    bt->persistent = mode && strcmp(mode, "persistent") == 0;
     bt->max_blocks = env_int("PMP_GA_BLOCKS", 0);
     *out = bt;
     return PMP_OK;
@@ -1070,7 +1092,7 @@ pmp_status pmp_batch_step(pmp_batch *bt, int32_t generations, void *stream)
     hipStream_t s = (hipStream_t)stream;
     BatchHost &bh = bt->bh;
     if (!bt->graphs) {
-        HIP_TRY(batch_launch(bh, generations, bt->max_blocks, s, true));
+        HIP_TRY(batch_enqueue(bt, generations, s, true));
         return PMP_OK;
     }
     auto it = bh.graphs.find(generations);
@@ -1082,7 +1104,7 @@ pmp_status pmp_batch_step(pmp_batch *bt, int32_t generations, void *stream)
         hipGraphExec_t exec = nullptr;
         hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            hipError_t le = batch_launch(bh, generations, bt->max_blocks, cs, false);
+            hipError_t le = batch_enqueue(bt, generations, cs, false);
             e = hipStreamEndCapture(cs, &graph);
             if (le != hipSuccess)
                 e = le;

@@ -77,14 +77,16 @@ def _make(pm, cases, G):
 
 
 @pytest.mark.parametrize("graph", ["1", "0"])
-def test_batch_equals_single_runs_and_oracle(pm, graph):
-    old = {k: os.environ.get(k) for k in ("PMP_BATCH_GRAPH", "PMP_GA_MODE")}
+@pytest.mark.parametrize("bmode", ["kernels", "persistent"])
+def test_batch_equals_single_runs_and_oracle(pm, graph, bmode):
+    old = {k: os.environ.get(k) for k in ("PMP_BATCH_GRAPH", "PMP_GA_MODE", "PMP_BATCH_MODE")}
     os.environ["PMP_BATCH_GRAPH"] = graph
     os.environ["PMP_GA_MODE"] = "kernels"
+    os.environ["PMP_BATCH_MODE"] = bmode
     try:
         cases = _mini_batch()
         G = 6
-        _say("mini batch of", len(cases), "graph", graph)
+        _say("mini batch of", len(cases), "graph", graph, "mode", bmode)
         insts, gas = _make(pm, cases, G)
         batch = pm.Batch(gas)
         batch.step(3)
@@ -112,6 +114,7 @@ def test_batch_equals_single_runs_and_oracle(pm, graph):
 def test_batch_small_grid_loops_every_phase(pm):
     old = os.environ.get("PMP_GA_BLOCKS")
     os.environ["PMP_GA_BLOCKS"] = "8"
+    os.environ["PMP_BATCH_MODE"] = "persistent"
     try:
         cases = _mini_batch()
         insts, gas = _make(pm, cases, 4)
@@ -125,6 +128,7 @@ def test_batch_small_grid_loops_every_phase(pm):
             _assert_same(_state(ga), _state(ref))
         batch.close()
     finally:
+        os.environ.pop("PMP_BATCH_MODE", None)
         if old is None:
             os.environ.pop("PMP_GA_BLOCKS", None)
         else:
