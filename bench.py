@@ -14,6 +14,9 @@ every timed step), and the CPU oracle's rate on the same workload, timed on
 this host's cores.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W]
+python bench.py --workload batch     256 ragged instances, one launch vs many
+python bench.py --workload learned   plain vs learned-proposal GA at equal
+                                     wall time (Euclidean n=m=2000, p=200)
 """
 from __future__ import annotations
 
@@ -132,6 +135,143 @@ def bench_batch(args, specs, ds):
     print(json.dumps(out), flush=True)
 
 
+LEARNED = {
+    "workload": "learned proposal: Euclidean n=m=2000 on the 10^4 x 10^4 integer grid, "
+                "p=200, population 1024 (NB=4 x NT=256); network trained online on "
+                "training seeds, then plain vs learned GA at equal wall time on fresh seeds",
+    "n": 2000, "p": 200, "population": 1024, "group_size": 256,
+    "candidates": 64, "learned_iters": 4, "explore_permille": 50, "history": 4,
+    "lr": 1e-3,
+}
+
+
+def _run_timed(pm, inst, seed, params, seconds, chunk, stream, learn_kw):
+    """Step a GA (learned, starting from network parameters `params`, when
+    given) for `seconds` of wall time in chunks of `chunk` generations;
+    returns [(t, best, generations)] after every chunk."""
+    import torch
+
+    def make():
+        ga = pm.GA(inst, LEARNED["population"], LEARNED["group_size"], 1 << 30, seed)
+        model = None
+        if params is not None:
+            model = pm.Model(0)
+            model.set_params(params)
+            ga.set_model(model, **learn_kw)
+        return ga, model
+
+    ga, model = make()  # first launches (code loading) outside the clock
+    ga.step(chunk, stream)
+    ga.best(stream)
+    ga.close()
+    ga, model = make()
+    torch.cuda.synchronize()
+    trace = []
+    t0 = time.perf_counter()
+    while True:
+        ga.step(chunk, stream)
+        _, best, stats = ga.best(stream)
+        t = time.perf_counter() - t0
+        trace.append((t, best, stats["generations"]))
+        if t >= seconds:
+            break
+    ga.close()
+    return trace
+
+
+def bench_learned(args):
+    """Train the network online on `--train-seeds` instances, then on each
+    fresh seed run the plain and the learned GA for the same wall time;
+    report the time the learned GA needs to reach the plain GA's best."""
+    import numpy as np
+    import torch
+    import paper_1610_10061_amd as pm
+    import pmp_inputs as gi
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    n, p = LEARNED["n"], LEARNED["p"]
+    kw = {k: LEARNED[k] for k in ("candidates", "learned_iters", "explore_permille",
+                                  "history", "lr")}
+    model = pm.Model(1)
+    t0 = time.perf_counter()
+    for s in range(args.train_seeds):
+        d = torch.from_numpy(gi.euclid_instance(n, s)).cuda()
+        inst = pm.Instance(d, p, stream)
+        ga = pm.GA(inst, LEARNED["population"], LEARNED["group_size"], 1 << 30, s)
+        ga.set_model(model, train_every=1, **kw)
+        ga.step(args.train_generations, stream)
+        _, best, st = ga.best(stream)
+        log(f"training seed {s}: best {best}, swaps taken {st['swap_taken']}"
+            f"/{st['swap_tried']}")
+        ga.close()
+        inst.close()
+    train_s = time.perf_counter() - t0
+    rows = []
+    for s in range(100, 100 + args.eval_seeds):
+        d = torch.from_numpy(gi.euclid_instance(n, s)).cuda()
+        inst = pm.Instance(d, p, stream)
+        plain = _run_timed(pm, inst, s, None, args.seconds, 8, stream, kw)
+        learned = _run_timed(pm, inst, s, model.params(), args.seconds, 8, stream,
+                             dict(kw, train_every=1))
+        target = plain[-1][1]
+        reach = next((t for t, b, _ in learned if b <= target), None)
+        rows.append({"seed": s, "plain_best": plain[-1][1], "learned_best": learned[-1][1],
+                     "plain_time_s": plain[-1][0], "learned_time_s": learned[-1][0],
+                     "plain_generations": plain[-1][2], "learned_generations": learned[-1][2],
+                     "learned_reaches_plain_best_s": reach})
+        log(json.dumps(rows[-1]))
+        inst.close()
+    speed = [r["plain_time_s"] / r["learned_reaches_plain_best_s"]
+             for r in rows if r["learned_reaches_plain_best_s"]]
+    gap = [(r["plain_best"] - r["learned_best"]) / r["plain_best"] for r in rows]
+    q = lambda v: [float(np.percentile(v, x)) for x in (25, 50, 75)] if v else None  # noqa
+    # network throughput: forward over a device batch of P x C rows
+    X = torch.randn(1024 * 64, 32, device="cuda")
+    model.forward(X)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        model.forward(X)
+    e1.record()
+    torch.cuda.synchronize()
+    fwd_s = e0.elapsed_time(e1) / 1e3 / 20
+    flops_row = 2 * (32 * 128 + 128 * 128 + 128)
+    out = {
+        "metric": "time-to-best, plain vs learned-proposal GA: plain GA's wall time / "
+                  "learned GA's time to reach the plain GA's best (median over fresh seeds)",
+        "value": q(speed)[1] if speed else None,
+        "unit": "x",
+        "n_gpus": 1, "higher_is_better": True, "dtype": "int32 eval / bf16-fp32 network",
+        "data": "synthetic",
+        "config": dict(LEARNED, train_seeds=args.train_seeds,
+                       train_generations=args.train_generations,
+                       eval_seeds=args.eval_seeds, seconds_per_run=args.seconds),
+        "speedup_iqr": q(speed),
+        "reached": f"{len(speed)}/{len(rows)}",
+        "relative_gap_at_equal_time_iqr": q(gap),
+        "training_s": train_s,
+        "per_seed": rows,
+        "mlp_forward": {"rows": X.shape[0], "seconds": fwd_s,
+                        "tflops": X.shape[0] * flops_row / fwd_s / 1e12,
+                        "peak_tflops_bf16": 2500.0},
+    }
+    if not args.no_cpu_baseline:
+        import oracle.learned as OL
+        Xc = X[:8192].cpu().numpy()
+        t1 = time.perf_counter()
+        OL.forward(model.params(), Xc)
+        dt = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": Xc.shape[0] / dt, "unit": "network rows/s",
+                               "cores": oracle_threads(), "kind": "oracle",
+                               "sample": "oracle forward (numpy float64) of 8192 rows"}
+    print(json.dumps(out), flush=True)
+
+
+def oracle_threads():
+    import oracle
+    return oracle.default_threads()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,9 +282,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="no per-launch events (the GA then replays hipGraphs)")
-    ap.add_argument("--workload", choices=["g900", "batch"], default="g900",
+    ap.add_argument("--workload", choices=["g900", "batch", "learned"], default="g900",
                     help="g900: the headline configuration; batch: 256 ragged "
-                         "instances in one launch vs one launch per instance")
+                         "instances in one launch vs one launch per instance; "
+                         "learned: plain vs learned-proposal GA at equal wall time")
+    ap.add_argument("--train-seeds", type=int, default=20)
+    ap.add_argument("--train-generations", type=int, default=100)
+    ap.add_argument("--eval-seeds", type=int, default=10)
+    ap.add_argument("--seconds", type=float, default=2.0,
+                    help="wall time of each plain / learned run (learned workload)")
     ap.add_argument("--batch-generations", type=int, default=100)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (scales the "
@@ -166,6 +312,9 @@ def main():
         with ProcessPoolExecutor(max_workers=8) as ex:
             ds = list(ex.map(gi.batch_instance, specs))
         return bench_batch(args, specs, ds)
+
+    if args.workload == "learned":
+        return bench_learned(args)
 
     import numpy as np
     import torch

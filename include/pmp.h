@@ -164,6 +164,8 @@ typedef struct {
     int64_t mutation_taken;    /* mutants that replaced a parent */
     int64_t scan_total;        /* Pi' entries read by all evaluations */
     int64_t pair_evals;        /* chromosome_evals x n */
+    int64_t swap_tried;        /* scored swaps evaluated (learned proposal) */
+    int64_t swap_taken;        /* scored swaps that replaced a parent */
 } pmp_ga_stats;
 
 /* Create a GA run on an instance (the instance must outlive it).
@@ -271,6 +273,128 @@ typedef struct {
 
 PMP_API pmp_status pmp_ga_profile(pmp_ga *ga, int32_t enable);
 PMP_API pmp_status pmp_ga_profile_read(pmp_ga *ga, pmp_profile *out, void *stream);
+
+/* ===========================================================================
+ * Learned swap proposal (not in the paper).  A small network scores swap
+ * moves of a chromosome (close open facility j, open closed facility k) from
+ * 16 features of j and 16 of k; the GA's mutation cycle (step 4 above) tries
+ * the best-scored swaps before its plain mutation attempts, and every tried
+ * swap is judged by the exact evaluation kernel and taken only if strictly
+ * fitter, like any mutant.  Each judged swap yields a training tuple (the 32
+ * inputs; the exact change of the objective), on which the network is
+ * trained on the GPU.
+ * ======================================================================== */
+#define PMP_FEATURES 16
+#define PMP_MLP_INPUTS 32
+#define PMP_MLP_HIDDEN 128
+#define PMP_MLP_PARAMS 20865
+#define PMP_MAX_LEARNED_FACILITIES 4096
+#define PMP_MAX_CANDIDATES 64
+
+/* ---------------------------------------------------------------------------
+ * pmp_features - the 16 features of every facility j of every chromosome x.
+ * For client i, with positions in the truncated row Pi'_i (Section 2.1):
+ * a_i, c1_i = first open facility and its cost (Eq. (6)'s term), b_i, c2_i =
+ * the second open facility and its cost, or c2_i = D'_{i,K} and no b_i when
+ * the truncated row holds no second open facility.  f = cost of x,
+ * F = max(f, 1), T = max(sum of all d_ij, 1), L = ceil(m / p).
+ *   0 1 if j is open          1 #{i : a_i = j} p / n
+ *   2 sum_{a_i = j} c1_i p/F  3 sum_{a_i = j} (c2_i - c1_i) p / F
+ *   4 #{i : b_i = j} p / n    5 sum_{b_i = j} (c2_i - c1_i) p / F
+ *   6 #{i : j closed, before a_i in Pi'_i} p / n
+ *   7 sum over those i of (c1_i - d_ij) p / F
+ *   8 #{i : j closed, after a_i and before b_i (up to K without b_i)} p / n
+ *   9 sum over those i of (c2_i - d_ij) p / F
+ *  10 (sum_i d_ij) m / T      11 #{i : j among the first L of Pi'_i} m/(n L)
+ *  12 p / m                   13 f m / T
+ *  14 gen_frac                15 1
+ * Each value is (float)(a * b / c) evaluated in double from the integers.
+ *  masks    P x W chromosomes, exactly p open facilities each.
+ *  out      P x m x 16 float32 (chromosome-major, then facility).
+ * Errors: PMP_EUNSUPPORTED if m > PMP_MAX_LEARNED_FACILITIES; PMP_EINFEASIBLE
+ * as pmp_eval_population.  Host pointers, or device with PMP_ON_DEVICE.
+ * ------------------------------------------------------------------------- */
+PMP_API pmp_status pmp_features(pmp_instance *inst, const uint64_t *masks, int32_t P,
+                                float gen_frac, float *out, uint32_t flags, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * The scoring network: 32 inputs -> 128 -> 128 -> 1, ReLU after each hidden
+ * layer.  Parameters (PMP_MLP_PARAMS float32, in this order): W1 [128][32],
+ * b1 [128], W2 [128][128], b2 [128], w3 [128], b3 [1];
+ * y = w3 . relu(W2 h1 + b2) + b3 with h1 = relu(W1 x + b1).  Weights and
+ * inputs are rounded to BF16 (nearest even) and h1 too; products accumulate
+ * in FP32 on the matrix cores.  The training loss of rows (x_r, t_r, w_r) is
+ * sum_r w_r (y_r - t_r)^2 / (2 sum_r w_r); gradients treat the BF16
+ * roundings as identity; Adam (beta1 0.9, beta2 0.999, eps 1e-8) updates
+ * FP32 master parameters.
+ *
+ * pmp_model_create   Glorot-uniform weights from Philox (seed), zero biases.
+ * pmp_model_get/set  the FP32 master parameters (set clears Adam's state).
+ * pmp_model_forward  y[rows] for x[rows x 32] (float32, rounded to BF16).
+ * pmp_model_grad     gradient (PMP_MLP_PARAMS) and loss of the rows; w may
+ *                    be NULL (all 1).  Rows whose weights sum to 0: no output.
+ * pmp_model_train    `steps` Adam steps of size lr on the rows.
+ * Host pointers, or device pointers with PMP_ON_DEVICE.  A model may be
+ * shared by several GA runs; calls on one model must not overlap.
+ * ------------------------------------------------------------------------- */
+typedef struct pmp_model pmp_model;
+
+PMP_API pmp_status pmp_model_create(uint64_t seed, pmp_model **out);
+PMP_API pmp_status pmp_model_get(pmp_model *model, float *params, uint32_t flags,
+                                 void *stream);
+PMP_API pmp_status pmp_model_set(pmp_model *model, const float *params, uint32_t flags,
+                                 void *stream);
+PMP_API pmp_status pmp_model_forward(pmp_model *model, const float *x, int32_t rows,
+                                     float *y, uint32_t flags, void *stream);
+PMP_API pmp_status pmp_model_grad(pmp_model *model, const float *x, const float *t,
+                                  const float *w, int32_t rows, float *grad, float *loss,
+                                  uint32_t flags, void *stream);
+PMP_API pmp_status pmp_model_train(pmp_model *model, const float *x, const float *t,
+                                   const float *w, int32_t rows, float lr, int32_t steps,
+                                   float *loss, uint32_t flags, void *stream);
+PMP_API void pmp_model_destroy(pmp_model *model);
+
+/* ---------------------------------------------------------------------------
+ * pmp_ga_set_model - let a GA run use (and train) a model.  Each generation,
+ * after the crossover stages, every chromosome x draws C candidates: for
+ * candidate t, r_j uniform in [0, p) and r_k uniform in [0, m - p) from its
+ * Philox stream (role 2, tag 5, stage t), j = the r_j-th open and k = the
+ * r_k-th closed facility in index order; input row t = [features of j |
+ * features of k] (pmp_features, gen_frac = generation / EvolveLimit), scored
+ * by the network (the predicted normalised change of the cost).  Mutation
+ * attempt a < L takes the swap of rank a (ascending score, ties to lower t),
+ * or, when a draw in [0, 1000) of stream (role 2, tag 6, stage a) falls below
+ * explore_permille, the candidate of a second draw uniform in [0, C).  The
+ * remaining Y - L attempts are the plain mutations.  Each evaluated swap
+ * stores (inputs, target) in a ring of H generations: target =
+ * clamp((f(x') - f(x)) p / max(f(x), 1), -4, 4).  After every train_every-th
+ * generation one Adam step (lr) is taken on the whole ring.
+ *  model  borrowed, must outlive the run; NULL detaches (plain GA again).
+ * PMP_EINVAL: bad parameters; PMP_EUNSUPPORTED: m above
+ * PMP_MAX_LEARNED_FACILITIES, or a run in persistent-kernel mode.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int32_t candidates;        /* C, 1..PMP_MAX_CANDIDATES; 0 = 64 */
+    int32_t learned_iters;     /* L, 1..min(C, Y); 0 = ceil(Y / 2) */
+    int32_t explore_permille;  /* 0..1000 */
+    int32_t history;           /* H generations kept for training; 0 = 4 */
+    int32_t train_every;       /* 0 = never (frozen model) */
+    float lr;                  /* Adam step size; 0 = 1e-3 */
+    int32_t reserved[2];       /* must be 0 */
+} pmp_learn_params;
+
+PMP_API pmp_status pmp_ga_set_model(pmp_ga *ga, pmp_model *model,
+                                    const pmp_learn_params *params);
+
+/* pmp_ga_replay - wait for `stream`; copy the training ring of a learned run
+ * (host pointers, NULL = skip).  Row ((g mod H) L + a) P + c holds attempt a
+ * of chromosome c in generation g: x (32 BF16 inputs as uint16), target,
+ * weight (1 = evaluated, 0 = not run), swap (j, k), delta (f(x') - f(x),
+ * f(x)).  *rows receives H L P.  scores (P x C): the network's scores of the
+ * candidates of the last generation. */
+PMP_API pmp_status pmp_ga_replay(pmp_ga *ga, int32_t *rows, uint16_t *x, float *target,
+                                 float *weight, int32_t *swap, int64_t *delta,
+                                 float *scores, void *stream);
 
 PMP_API const char *pmp_status_str(pmp_status s);
 PMP_API const char *pmp_last_error(void);

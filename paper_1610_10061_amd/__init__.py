@@ -24,7 +24,10 @@ __all__ = [
     "pmp_ga_state", "pmp_ga_destroy", "pmp_solve", "pmp_ga_profile",
     "pmp_ga_profile_read", "pmp_ga_autotune", "pmp_batch_create",
     "pmp_batch_step", "pmp_batch_check", "pmp_batch_destroy",
-    "pmp_ga_step_batch", "Instance", "GA", "Batch", "EXPORTS",
+    "pmp_ga_step_batch", "pmp_features", "pmp_model_create", "pmp_model_get",
+    "pmp_model_set", "pmp_model_forward", "pmp_model_grad", "pmp_model_train",
+    "pmp_model_destroy", "pmp_ga_set_model", "pmp_ga_replay", "Instance", "GA",
+    "Batch", "Model", "LearnParams", "EXPORTS", "MLP_PARAMS",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -41,7 +44,14 @@ EXPORTS = [
     "pmp_ga_destroy", "pmp_solve", "pmp_ga_profile", "pmp_ga_profile_read",
     "pmp_status_str", "pmp_last_error", "pmp_ga_autotune", "pmp_batch_create",
     "pmp_batch_step", "pmp_batch_check", "pmp_batch_destroy", "pmp_ga_step_batch",
+    "pmp_features", "pmp_model_create", "pmp_model_get", "pmp_model_set",
+    "pmp_model_forward", "pmp_model_grad", "pmp_model_train", "pmp_model_destroy",
+    "pmp_ga_set_model", "pmp_ga_replay",
 ]
+
+FEATURES = 16
+MLP_INPUTS = 32
+MLP_PARAMS = 20865
 
 
 class PmpError(RuntimeError):
@@ -61,10 +71,18 @@ class GaStats(C.Structure):
     _fields_ = [(name, C.c_int64) for name in (
         "generations", "saturation_count", "done", "best_cost",
         "chromosome_evals", "crossover_fail", "crossover_taken",
-        "mutation_taken", "scan_total", "pair_evals")]
+        "mutation_taken", "scan_total", "pair_evals", "swap_tried",
+        "swap_taken")]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+class LearnParams(C.Structure):
+    _fields_ = [("candidates", C.c_int32), ("learned_iters", C.c_int32),
+                ("explore_permille", C.c_int32), ("history", C.c_int32),
+                ("train_every", C.c_int32), ("lr", C.c_float),
+                ("reserved", C.c_int32 * 2)]
 
 
 class Profile(C.Structure):
@@ -113,12 +131,24 @@ def lib():
     L.pmp_batch_destroy.argtypes = [_vp]
     L.pmp_batch_destroy.restype = None
     L.pmp_ga_step_batch.argtypes = [C.POINTER(_vp), _i32, _i32, _vp]
+    L.pmp_features.argtypes = [_vp, _vp, _i32, C.c_float, _vp, _u32, _vp]
+    L.pmp_model_create.argtypes = [C.c_uint64, C.POINTER(_vp)]
+    L.pmp_model_get.argtypes = [_vp, _vp, _u32, _vp]
+    L.pmp_model_set.argtypes = [_vp, _vp, _u32, _vp]
+    L.pmp_model_forward.argtypes = [_vp, _vp, _i32, _vp, _u32, _vp]
+    L.pmp_model_grad.argtypes = [_vp, _vp, _vp, _vp, _i32, _vp, _vp, _u32, _vp]
+    L.pmp_model_train.argtypes = [_vp, _vp, _vp, _vp, _i32, C.c_float, _i32, _vp, _u32,
+                                  _vp]
+    L.pmp_model_destroy.argtypes = [_vp]
+    L.pmp_model_destroy.restype = None
+    L.pmp_ga_set_model.argtypes = [_vp, _vp, C.POINTER(LearnParams)]
+    L.pmp_ga_replay.argtypes = [_vp, C.POINTER(_i32), _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     L.pmp_status_str.argtypes = [_i32]
     L.pmp_status_str.restype = C.c_char_p
     L.pmp_last_error.argtypes = []
     L.pmp_last_error.restype = C.c_char_p
     for name in EXPORTS:
-        if name not in ("pmp_instance_destroy", "pmp_ga_destroy",
+        if name not in ("pmp_instance_destroy", "pmp_ga_destroy", "pmp_model_destroy",
                         "pmp_batch_destroy", "pmp_status_str", "pmp_last_error"):
             getattr(L, name).restype = _i32
     _lib = L
@@ -305,6 +335,121 @@ def pmp_ga_step_batch(gas, generations, stream=None):
            "pmp_ga_step_batch")
 
 
+def _same_side(*bufs):
+    """All given (pointer, on_device) pairs on one side; returns on_device."""
+    sides = {dev for ptr, dev in bufs if ptr is not None}
+    if len(sides) > 1:
+        raise ValueError("all buffers must be host arrays or all CUDA tensors")
+    return sides.pop() if sides else False
+
+
+def pmp_features(inst, masks, gen_frac=0.0, out=None, stream=None):
+    """The 16 features of every facility of every chromosome: P x m x 16."""
+    n, m, p, K, W = pmp_instance_info(inst)
+    P = masks.shape[0]
+    if out is None:
+        out = (torch.empty((P, m, FEATURES), dtype=torch.float32, device=masks.device)
+               if isinstance(masks, torch.Tensor) else np.zeros((P, m, FEATURES), np.float32))
+    mb = _buf(masks, np.uint64, torch.uint64)
+    ob = _buf(out, np.float32, torch.float32)
+    dev = _same_side(mb, ob)
+    _check(lib().pmp_features(inst, mb[0], P, float(gen_frac), ob[0],
+                              PMP_ON_DEVICE if dev else 0, _stream(stream) if dev else None),
+           "pmp_features")
+    return out
+
+
+def pmp_model_create(seed=0):
+    out = _vp()
+    _check(lib().pmp_model_create(seed, C.byref(out)), "pmp_model_create")
+    return out
+
+
+def pmp_model_get(model, params=None, stream=None):
+    if params is None:
+        params = np.zeros(MLP_PARAMS, np.float32)
+    pb = _buf(params, np.float32, torch.float32)
+    _check(lib().pmp_model_get(model, pb[0], PMP_ON_DEVICE if pb[1] else 0,
+                               _stream(stream) if pb[1] else None), "pmp_model_get")
+    return params
+
+
+def pmp_model_set(model, params, stream=None):
+    pb = _buf(params, np.float32, torch.float32)
+    _check(lib().pmp_model_set(model, pb[0], PMP_ON_DEVICE if pb[1] else 0,
+                               _stream(stream) if pb[1] else None), "pmp_model_set")
+
+
+def pmp_model_forward(model, x, y=None, stream=None):
+    """Scores of rows x (rows x 32 float32)."""
+    rows = x.shape[0]
+    if y is None:
+        y = (torch.empty(rows, dtype=torch.float32, device=x.device)
+             if isinstance(x, torch.Tensor) else np.zeros(rows, np.float32))
+    xb, yb = _buf(x, np.float32, torch.float32), _buf(y, np.float32, torch.float32)
+    dev = _same_side(xb, yb)
+    _check(lib().pmp_model_forward(model, xb[0], rows, yb[0], PMP_ON_DEVICE if dev else 0,
+                                   _stream(stream) if dev else None), "pmp_model_forward")
+    return y
+
+
+def pmp_model_grad(model, x, t, w=None, stream=None):
+    """(gradient, loss) of rows (x, t, w) on the host."""
+    rows = x.shape[0]
+    grad = np.zeros(MLP_PARAMS, np.float32)
+    loss = np.zeros(1, np.float32)
+    xb, tb = _buf(x, np.float32, torch.float32), _buf(t, np.float32, torch.float32)
+    wb = _buf(w, np.float32, torch.float32)
+    if _same_side(xb, tb, wb):
+        raise ValueError("pmp_model_grad binding takes host arrays")
+    _check(lib().pmp_model_grad(model, xb[0], tb[0], wb[0], rows, grad.ctypes.data_as(_vp),
+                                loss.ctypes.data_as(_vp), 0, None), "pmp_model_grad")
+    return grad, float(loss[0])
+
+
+def pmp_model_train(model, x, t, w=None, lr=1e-3, steps=1, stream=None):
+    """`steps` Adam steps on host rows; returns the loss before the last."""
+    rows = x.shape[0]
+    loss = np.zeros(1, np.float32)
+    xb, tb = _buf(x, np.float32, torch.float32), _buf(t, np.float32, torch.float32)
+    wb = _buf(w, np.float32, torch.float32)
+    if _same_side(xb, tb, wb):
+        raise ValueError("pmp_model_train binding takes host arrays")
+    _check(lib().pmp_model_train(model, xb[0], tb[0], wb[0], rows, float(lr), steps,
+                                 loss.ctypes.data_as(_vp), 0, None), "pmp_model_train")
+    return float(loss[0])
+
+
+def pmp_model_destroy(model):
+    lib().pmp_model_destroy(model)
+
+
+def pmp_ga_set_model(ga, model, candidates=0, learned_iters=0, explore_permille=0,
+                     history=0, train_every=0, lr=0.0):
+    prm = LearnParams(candidates, learned_iters, explore_permille, history, train_every,
+                      lr)
+    _check(lib().pmp_ga_set_model(ga, model, C.byref(prm)), "pmp_ga_set_model")
+
+
+def pmp_ga_replay(ga, population, candidates, stream=None):
+    """The training ring: dict of x (rows x 32 uint16 BF16 bits), target,
+    weight, swap (rows x 2), delta (rows x 2: change, parent cost), and the
+    last generation's candidate scores (population x candidates)."""
+    rows = _i32()
+    _check(lib().pmp_ga_replay(ga, C.byref(rows), None, None, None, None, None, None,
+                               _stream(stream)), "pmp_ga_replay")
+    R = rows.value
+    out = {"x": np.zeros((R, MLP_INPUTS), np.uint16), "target": np.zeros(R, np.float32),
+           "weight": np.zeros(R, np.float32), "swap": np.zeros((R, 2), np.int32),
+           "delta": np.zeros((R, 2), np.int64),
+           "scores": np.zeros((population, candidates), np.float32)}
+    _check(lib().pmp_ga_replay(ga, C.byref(rows), *[out[k].ctypes.data_as(_vp) for k in
+                                                     ("x", "target", "weight", "swap",
+                                                      "delta", "scores")], _stream(stream)),
+           "pmp_ga_replay")
+    return out
+
+
 # ------------------------------------------------------- small conveniences
 class Instance:
     """Owning wrapper of a pmp_instance handle."""
@@ -370,6 +515,15 @@ class GA:
     def autotune(self, stream=None):
         return pmp_ga_autotune(self.handle, stream)
 
+    def set_model(self, model, **kw):
+        """Attach a Model (keyword arguments: LearnParams fields)."""
+        pmp_ga_set_model(self.handle, model.handle if model is not None else None, **kw)
+        self.model = model
+        self.candidates = (kw.get("candidates") or 64) if model is not None else 0
+
+    def replay(self, stream=None):
+        return pmp_ga_replay(self.handle, self.P, self.candidates, stream)
+
     def profile_read(self, stream=None):
         return pmp_ga_profile_read(self.handle, stream)
 
@@ -402,6 +556,39 @@ class Batch:
     def close(self):
         if self.handle:
             pmp_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Model:
+    """Owning wrapper of a pmp_model handle."""
+
+    def __init__(self, seed=0):
+        self.handle = pmp_model_create(seed)
+
+    def params(self):
+        return pmp_model_get(self.handle)
+
+    def set_params(self, params):
+        pmp_model_set(self.handle, np.ascontiguousarray(params, dtype=np.float32))
+
+    def forward(self, x, y=None, stream=None):
+        return pmp_model_forward(self.handle, x, y, stream)
+
+    def grad(self, x, t, w=None):
+        return pmp_model_grad(self.handle, x, t, w)
+
+    def train(self, x, t, w=None, lr=1e-3, steps=1):
+        return pmp_model_train(self.handle, x, t, w, lr, steps)
+
+    def close(self):
+        if self.handle:
+            pmp_model_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -84,11 +84,30 @@ enum GaStat : int {
     CS_XO_FAIL = 2,    // crossovers without offspring
     CS_XO_TAKEN = 3,   // crossover offspring taken
     CS_MUT_TAKEN = 4,  // mutants taken
-    CS_COUNT = 5
+    CS_SWAP_TRIED = 5, // scored swaps evaluated
+    CS_SWAP_TAKEN = 6, // scored swaps taken
+    CS_COUNT = 7
 };
 
 // Kinds of the operator a stage kernel finishes (prev) and starts (op).
-enum GaOp : int { OP_NONE = 0, OP_INIT = 1, OP_XOVER = 2, OP_MUT = 3 };
+enum GaOp : int { OP_NONE = 0, OP_INIT = 1, OP_XOVER = 2, OP_MUT = 3, OP_SWAP = 4 };
+
+// Operator finished (prev) and started (op) by stage step k of a generation
+// with X crossover stages and S = X + Y stages, of which the first L
+// mutation attempts take scored swaps; and the operator's index.
+__device__ __host__ __forceinline__ int ga_stage_kind(int k, int X, int L)
+{
+    return k < X ? OP_XOVER : (k - X < L ? OP_SWAP : OP_MUT);
+}
+
+__device__ __host__ __forceinline__ void ga_stage_ops(int k, int X, int S,
+                                                      int *prev, int *op,
+                                                      int *index, int L = 0)
+{
+    *prev = k == 0 ? OP_INIT : ga_stage_kind(k - 1, X, L);
+    *op = k == S ? OP_NONE : ga_stage_kind(k, X, L);
+    *index = k < X ? k : k - X;
+}
 
 // Device state of one GA run.  Population, fitness, offspring and their
 // "evaluate me" flags are double-buffered: a stage kernel reads buffer `in`
@@ -115,6 +134,14 @@ struct GaArgs {
     uint32_t *bar;                  // grid barrier: epoch word, then one
                                     // flag per workgroup (32 words apart)
     uint32_t *err;
+    // learned proposal (L = 0: none): the first L mutation attempts take
+    // the swaps listed in `swaps` (P x L pairs j, k); each evaluated swap's
+    // exact change of cost goes to the replay ring slot
+    // ((generation mod H) L + attempt) P + chromosome.
+    const int32_t *swaps;
+    float *rep_t, *rep_w;           // normalised target, row weight (0/1)
+    long long *rep_d;               // change of cost, parent cost
+    int32_t L, H;
 };
 
 hipError_t launch_ga_init(const GaArgs &g, hipStream_t s);

@@ -351,6 +351,12 @@ __device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
 
     // one round of independent loads
     const uint64_t gen = g.gs[GS_GEN];
+    int sj = 0, sk = 0;
+    if (op == OP_SWAP) {
+        const int32_t *sw = g.swaps + ((int64_t)c * g.L + index) * 2;
+        sj = sw[0];
+        sk = sw[1];
+    }
     const bool okc = buf(g.ok, in)[c] != 0;
     const bool okp = xo && buf(g.ok, in)[pc] != 0;
     const unsigned long long fin = buf(g.fit, in)[c];
@@ -413,7 +419,8 @@ __device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
     for (int k = 0; k < 2; ++k)
         if (lane + 64 * k < W)
             cur[lane + 64 * k] = A.v[k];
-    const bool improved = was_improved || (prev == OP_MUT && take);
+    const bool mut_prev = prev == OP_MUT || prev == OP_SWAP;
+    const bool improved = was_improved || (mut_prev && take);
     if (lane == 0) {
         buf(g.fit, out)[c] = take ? fo : fin;
         unsigned long long *cs = g.cstat + (int64_t)c * CS_COUNT;
@@ -423,9 +430,22 @@ __device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
         }
         if (take && prev == OP_XOVER)
             cs[CS_XO_TAKEN] += 1;
-        if (take && prev == OP_MUT) {
-            cs[CS_MUT_TAKEN] += 1;
+        if (take && mut_prev) {
+            cs[prev == OP_MUT ? CS_MUT_TAKEN : CS_SWAP_TAKEN] += 1;
             g.improved[c] = 1;
+        }
+        if (prev == OP_SWAP && okc) {
+            // training tuple of attempt index - 1: exact change of cost,
+            // normalised by the parent's cost per open facility, clamped
+            cs[CS_SWAP_TRIED] += 1;
+            const int64_t slot =
+                ((int64_t)(gen % (uint64_t)g.H) * g.L + (index - 1)) * g.P + c;
+            const long long delta = (long long)fo - (long long)fin;
+            double tv = (double)delta * (double)g.t.p / (fin > 0 ? (double)fin : 1.0);
+            tv = tv < -4.0 ? -4.0 : (tv > 4.0 ? 4.0 : tv);
+            g.rep_d[2 * slot] = delta;
+            g.rep_t[slot] = (float)tv;
+            g.rep_w[slot] = 1.f;
         }
     }
 
@@ -439,20 +459,23 @@ __device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
             g.cstat[(int64_t)c * CS_COUNT + CS_XO_FAIL] += 1;
     } else if (op == OP_MUT && !improved) {
         ok = mutate_wave(A, F, W, m, lo, hi, move, lane);
+    } else if (op == OP_SWAP && !improved) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int w = lane + 64 * k;
+            if (w < W) {
+                uint64_t v = A.v[k];
+                if ((sj >> 6) == w)
+                    v ^= 1ull << (sj & 63);
+                if ((sk >> 6) == w)
+                    v ^= 1ull << (sk & 63);
+                F[w] = v;
+            }
+        }
+        ok = true;
     }
     if (lane == 0)
         buf(g.ok, out)[c] = ok ? 1 : 0;
-}
-
-// Operator finished (prev) and started (op) by stage step k of a generation
-// with X crossover stages and S = X + Y stages, and the operator's index.
-__device__ __host__ __forceinline__ void ga_stage_ops(int k, int X, int S,
-                                                      int *prev, int *op,
-                                                      int *index)
-{
-    *prev = k == 0 ? OP_INIT : (k - 1 < X ? OP_XOVER : OP_MUT);
-    *op = k == S ? OP_NONE : (k < X ? OP_XOVER : OP_MUT);
-    *index = k < X ? k : k - X;
 }
 
 // Reduce (cost, index) pairs of a workgroup to the least cost, lowest index

@@ -1,0 +1,207 @@
+// Swap-scoring network shared by the proposal kernel and the training
+// kernels: 32 inputs -> 128 -> 128 -> 1 with ReLU, BF16 weights and inputs,
+// FP32 accumulation on the MFMA units (v_mfma_f32_16x16x16bf16_1k).
+//
+// MFMA 16x16x16 BF16 operand layout (wave64, lane l, g = l / 16, i = 0..3):
+//   A fragment: A[row l%16][k 4g + i]
+//   B fragment: B[k 4g + i][col l%16]
+//   C/D:        D[row 4g + i][col l%16]
+//
+// Parameter vector (FP32 master copy, kParams values):
+//   W1 [128][32] | b1 [128] | W2 [128][128] | b2 [128] | w3 [128] | b3 [1]
+// BF16 copies are kept of W1, W2, W2^T and w3.  The first hidden layer's
+// activations are rounded to BF16 (they are the second product's operand);
+// the second layer's activations and the output stay FP32.
+#pragma once
+
+#include "common.hpp"
+
+namespace pmp {
+
+constexpr int kIn = 32;
+constexpr int kHidden = 128;
+constexpr int kOffW1 = 0;
+constexpr int kOffB1 = kOffW1 + kHidden * kIn;       // 4096
+constexpr int kOffW2 = kOffB1 + kHidden;             // 4224
+constexpr int kOffB2 = kOffW2 + kHidden * kHidden;   // 20608
+constexpr int kOffW3 = kOffB2 + kHidden;             // 20736
+constexpr int kOffB3 = kOffW3 + kHidden;             // 20864
+constexpr int kParams = kOffB3 + 1;                  // 20865
+static_assert(kParams == PMP_MLP_PARAMS, "parameter count");
+
+// Header words of one training block's partial sums (after kParams values).
+constexpr int kPartHead = 4;            // count, loss, step, unused
+constexpr int kPartStride = kParams + kPartHead + 3;  // 20872, 16-byte multiple
+
+// Round-to-nearest-even FP32 -> BF16 (finite inputs).
+__device__ __host__ __forceinline__ uint16_t f32_to_bf16(float x)
+{
+    uint32_t u;
+    __builtin_memcpy(&u, &x, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h)
+{
+    return __uint_as_float((uint32_t)h << 16);
+}
+
+// Read-only view of a model for the forward pass.
+struct MlpDev {
+    const uint16_t *W1;   // [128][32]  BF16
+    const uint16_t *W2;   // [128][128] BF16
+    const uint16_t *W2T;  // [128][128] BF16, W2 transposed
+    const uint16_t *w3;   // [128]      BF16
+    const float *b1, *b2, *b3;
+};
+
+// Everything a model owns on the device.
+struct MlpModelDev {
+    float *master;  // kParams
+    float *m1, *m2; // Adam moments
+    uint16_t *W1, *W2, *W2T, *w3;
+    uint32_t *step; // Adam steps taken
+    MlpDev view() const
+    {
+        MlpDev v;
+        v.W1 = W1;
+        v.W2 = W2;
+        v.W2T = W2T;
+        v.w3 = w3;
+        v.b1 = master + kOffB1;
+        v.b2 = master + kOffB2;
+        v.b3 = master + kOffB3;
+        return v;
+    }
+};
+
+// When a training step runs inside a GA's generation sequence: after
+// generation counts divisible by `every`, once per generation count.
+struct TrainGate {
+    const unsigned long long *gen;  // null: always train
+    unsigned long long *last;       // generation count of the last step
+    int32_t every;
+};
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f32x4 mfma_bf16(bf16x4 a, bf16x4 b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// Four consecutive BF16 values at an 8-byte aligned address.
+__device__ __forceinline__ bf16x4 load_bf16x4(const uint16_t *p)
+{
+    const uint2 v = *reinterpret_cast<const uint2 *>(p);
+    bf16x4 r;
+    r[0] = (short)(v.x & 0xFFFFu);
+    r[1] = (short)(v.x >> 16);
+    r[2] = (short)(v.y & 0xFFFFu);
+    r[3] = (short)(v.y >> 16);
+    return r;
+}
+
+// Order this wave's earlier LDS accesses before its later ones.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+constexpr int kXStride = kIn + 4;       // padded LDS row of inputs (BF16)
+constexpr int kHStride = kHidden + 4;   // padded LDS row of activations
+
+// Forward pass of 16 rows by one wave.  x: the rows' inputs in LDS (row r at
+// x + r * kXStride); h1: 16 x kHStride BF16 of LDS scratch.  Leaves the
+// pre-activations z1 = W1 x + b1 and z2 = W2 h1 + b2 in D layout (tile t =
+// hidden units 16t..16t+15) and y for rows 4g..4g+3 in y[0..3] (all lanes of
+// the group of 16 hold them).
+__device__ __forceinline__ void mlp_forward16(const MlpDev &P, const uint16_t *x,
+                                              uint16_t *h1, int lane, f32x4 z1[8],
+                                              f32x4 z2[8], float y[4])
+{
+    const int r = lane & 15, g = lane >> 4;
+    bf16x4 ax[kIn / 16];
+#pragma unroll
+    for (int kb = 0; kb < kIn / 16; ++kb)
+        ax[kb] = load_bf16x4(x + r * kXStride + kb * 16 + 4 * g);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < kIn / 16; ++kb)
+            acc = mfma_bf16(ax[kb], load_bf16x4(P.W1 + (t * 16 + r) * kIn + kb * 16 + 4 * g),
+                            acc);
+        const float bias = P.b1[t * 16 + r];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            acc[i] += bias;
+        z1[t] = acc;
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            h1[(4 * g + i) * kHStride + t * 16 + r] = f32_to_bf16(fmaxf(z1[t][i], 0.f));
+    wave_lds_sync();
+    bf16x4 ah[kHidden / 16];
+#pragma unroll
+    for (int kb = 0; kb < kHidden / 16; ++kb)
+        ah[kb] = load_bf16x4(h1 + r * kHStride + kb * 16 + 4 * g);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < kHidden / 16; ++kb)
+            acc = mfma_bf16(ah[kb],
+                            load_bf16x4(P.W2 + (t * 16 + r) * kHidden + kb * 16 + 4 * g),
+                            acc);
+        const float bias = P.b2[t * 16 + r];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            acc[i] += bias;
+        z2[t] = acc;
+    }
+    float part[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const float w = bf16_to_f32(P.w3[t * 16 + r]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            part[i] += fmaxf(z2[t][i], 0.f) * w;
+    }
+    const float b3 = P.b3[0];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        float v = part[i];
+        v += __shfl_xor(v, 1);
+        v += __shfl_xor(v, 2);
+        v += __shfl_xor(v, 4);
+        v += __shfl_xor(v, 8);
+        y[i] = v + b3;
+    }
+    wave_lds_sync();  // h1 may be reused by the caller
+}
+
+// Launchers (k_mlp.hip).
+hipError_t launch_mlp_forward(const MlpDev &P, const uint16_t *X, int rows, float *y,
+                              hipStream_t s);
+// Partial gradient sums of L = sum_r w_r (y_r - t_r)^2 / (2 sum_r w_r) into
+// `partials` (blocks x kPartStride); returns the block count used.
+hipError_t launch_mlp_grad(const MlpDev &P, const uint16_t *X, const float *T,
+                           const float *Wt, int rows, float *partials, int max_blocks,
+                           const MlpModelDev &M, TrainGate gate, int *blocks,
+                           hipStream_t s);
+// Sum the partials: gradient (and loss) out, and/or an Adam step when lr > 0.
+hipError_t launch_mlp_update(const MlpModelDev &M, const float *partials, int blocks,
+                             float lr, float *grad_out, float *loss_out, TrainGate gate,
+                             hipStream_t s);
+hipError_t launch_mlp_publish(const MlpModelDev &M, hipStream_t s);
+hipError_t launch_mlp_init(const MlpModelDev &M, uint64_t seed, hipStream_t s);
+hipError_t launch_to_bf16(const float *x, uint16_t *y, int64_t count, hipStream_t s);
+hipError_t launch_from_bf16(const uint16_t *x, float *y, int64_t count, hipStream_t s);
+
+}  // namespace pmp

@@ -14,8 +14,15 @@
 
 namespace pmp {
 
-enum : uint64_t { ROLE_POPULATION = 1, ROLE_EVOLVE = 2 };
-enum : uint64_t { TAG_SAMPLE = 1, TAG_CROSSOVER = 2, TAG_MUTATION = 3 };
+enum : uint64_t { ROLE_POPULATION = 1, ROLE_EVOLVE = 2, ROLE_MODEL = 3 };
+enum : uint64_t {
+    TAG_SAMPLE = 1,
+    TAG_CROSSOVER = 2,
+    TAG_MUTATION = 3,
+    TAG_WEIGHTS = 4,  // initial network weights
+    TAG_PROPOSE = 5,  // swap candidates of the learned proposal
+    TAG_EXPLORE = 6,  // exploration draws of the learned proposal
+};
 
 struct PhiloxStream {
     uint64_t k0, k1;       // key

@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "learn_device.hpp"
 
 using namespace pmp;
 
@@ -113,6 +114,11 @@ struct pmp_instance {
     unsigned long long *part = nullptr;
     uint32_t *spart = nullptr;
     size_t part_cap = 0;
+    // static sums of the learned proposal's features
+    unsigned long long *colsum = nullptr;  // m column sums of d
+    uint32_t *nearc = nullptr;             // m near counts
+    int64_t total = 0;                     // sum of d
+    int32_t near_len = 1;                  // ceil(m / p)
 
     Tables tables() const
     {
@@ -158,6 +164,22 @@ struct BatchHost {
 
 }  // namespace
 
+// A scoring network: device parameters, Adam state and staging buffers.
+struct pmp_model {
+    MlpModelDev d{};
+    float *partials = nullptr;   // training partial sums, kTrainBlocks rows
+    float *grad = nullptr;       // staging of a host gradient output
+    float *loss = nullptr;       // one float
+    float *xf = nullptr;         // staging of host inputs (rows x 32)
+    uint16_t *xb = nullptr;      // BF16 inputs (rows x 32)
+    float *tf = nullptr, *wf = nullptr, *yf = nullptr;  // rows each
+    int64_t cap = 0;             // rows the staging holds
+};
+
+namespace {
+constexpr int kTrainBlocks = 128;  // workgroups of a training gradient launch
+}
+
 struct pmp_ga {
     pmp_instance *inst = nullptr;
     pmp_ga_params prm{};
@@ -184,6 +206,19 @@ struct pmp_ga {
     std::vector<hipEvent_t> ev;
     size_t ev_used = 0;
     unsigned long long base_scan = 0, base_evals = 0;
+    // learned proposal (model == nullptr: plain GA)
+    pmp_model *model = nullptr;
+    int LC = 0, LL = 0, Lexp = 0, LH = 0, Levery = 0;
+    float Llr = 0.f;
+    int32_t *swaps = nullptr;
+    uint16_t *rep_x = nullptr;
+    float *rep_t = nullptr, *rep_w = nullptr;
+    int32_t *rep_jk = nullptr;
+    long long *rep_d = nullptr;
+    float *scores = nullptr;
+    unsigned long long *last_trained = nullptr;
+
+    int64_t ring_rows() const { return (int64_t)LH * LL * prm.population; }
 
     // crossover stages actually run (none when p < 2 or NT = 1)
     int xstages() const { return (inst->p >= 2 && lg > 0) ? X : 0; }
@@ -221,7 +256,48 @@ struct pmp_ga {
         g.arrive = arrive;
         g.bar = bar;
         g.err = inst->err;
+        g.swaps = swaps;
+        g.rep_t = rep_t;
+        g.rep_w = rep_w;
+        g.rep_d = rep_d;
+        g.L = model ? LL : 0;
+        g.H = model ? LH : 1;
         return g;
+    }
+
+    LearnArgs learn_args(const GaArgs &g) const
+    {
+        LearnArgs a{};
+        a.g = g;
+        a.net = model->d.view();
+        a.colsum = inst->colsum;
+        a.nearc = inst->nearc;
+        a.total = inst->total;
+        a.near_len = inst->near_len;
+        a.C = LC;
+        a.L = LL;
+        a.explore = Lexp;
+        a.H = LH;
+        a.swaps = swaps;
+        a.rep_x = rep_x;
+        a.rep_jk = rep_jk;
+        a.rep_d = rep_d;
+        a.rep_t = rep_t;
+        a.rep_w = rep_w;
+        a.scores = scores;
+        return a;
+    }
+
+    void free_learned()
+    {
+        dfree(swaps);
+        dfree(rep_x);
+        dfree(rep_t);
+        dfree(rep_w);
+        dfree(rep_jk);
+        dfree(rep_d);
+        dfree(scores);
+        dfree(last_trained);
     }
 };
 
@@ -344,6 +420,8 @@ void pmp_instance_destroy(pmp_instance *inst)
     dfree(inst->h_scan);
     dfree(inst->part);
     dfree(inst->spart);
+    dfree(inst->colsum);
+    dfree(inst->nearc);
     delete inst;
 }
 
@@ -380,8 +458,11 @@ pmp_status pmp_preprocess(const int32_t *d, int64_t ld, int32_t n, int32_t m,
     inst->W = (m + 63) / 64;
     inst->pitch = ((inst->K + 63) / 64) * 64;
     const size_t cells = (size_t)n * inst->pitch;
+    inst->near_len = (m + p - 1) / p;
     if (dalloc(&inst->pi, cells) != hipSuccess || dalloc(&inst->ds, cells) != hipSuccess ||
-        dalloc(&inst->delta, cells) != hipSuccess || dalloc(&inst->err, 1) != hipSuccess) {
+        dalloc(&inst->delta, cells) != hipSuccess || dalloc(&inst->err, 1) != hipSuccess ||
+        dalloc(&inst->colsum, (size_t)m) != hipSuccess ||
+        dalloc(&inst->nearc, (size_t)m) != hipSuccess) {
         pmp_instance_destroy(inst);
         return fail(PMP_ENOMEM, "device allocation of tables (%zu cells)", cells);
     }
@@ -415,14 +496,28 @@ pmp_status pmp_preprocess(const int32_t *d, int64_t ld, int32_t n, int32_t m,
             st = fail(PMP_EDEVICE, "sort kernel launch: %s", hipGetErrorString(e));
             break;
         }
+        // static sums of the learned proposal's features
+        std::vector<unsigned long long> cs((size_t)m);
+        e = hipMemsetAsync(inst->colsum, 0, sizeof(unsigned long long) * m, s);
+        if (e == hipSuccess)
+            e = hipMemsetAsync(inst->nearc, 0, sizeof(uint32_t) * m, s);
+        if (e == hipSuccess)
+            e = launch_static_sums(src, src_ld, n, m, inst->pi, inst->pitch, inst->near_len,
+                                   inst->colsum, inst->nearc, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(cs.data(), inst->colsum, sizeof(unsigned long long) * m,
+                               hipMemcpyDeviceToHost, s);
         uint32_t herr = 0;
-        e = hipMemcpyAsync(&herr, inst->err, sizeof herr, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&herr, inst->err, sizeof herr, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess)
             e = hipStreamSynchronize(s);
         if (e != hipSuccess) {
             st = fail(PMP_EDEVICE, "preprocess: %s", hipGetErrorString(e));
             break;
         }
+        for (unsigned long long v : cs)
+            inst->total += (int64_t)v;
         st = status_from_err(herr);
     } while (0);
     dfree(dd);
@@ -582,6 +677,7 @@ void pmp_ga_destroy(pmp_ga *ga)
     dfree(ga->cstat);
     dfree(ga->arrive);
     dfree(ga->bar);
+    ga->free_learned();
     if (ga->self) {
         ga->self->release();
         delete ga->self;
@@ -751,21 +847,41 @@ namespace {
 hipError_t enqueue_generations(pmp_ga *ga, const GaArgs &g, int generations,
                                hipStream_t s)
 {
-    const int X = ga->xstages(), S = X + ga->Y;
+    const int X = ga->xstages(), S = X + ga->Y, L = g.L;
+    const bool train = L > 0 && ga->Levery > 0;
     for (int gen = 0; gen < generations; ++gen) {
         hipError_t e = launch_ga_init(g, s);
         if (e == hipSuccess)
             e = ga_eval(ga, g, 0, s);
         for (int k = 0; k <= S && e == hipSuccess; ++k) {
-            const int prev = k == 0 ? OP_INIT : (k - 1 < X ? OP_XOVER : OP_MUT);
-            const int op = k == S ? OP_NONE : (k < X ? OP_XOVER : OP_MUT);
-            const int index = k < X ? k : k - X;
-            e = launch_ga_stage(g, k & 1, prev, op, index, s);
+            int prev, op, index;
+            ga_stage_ops(k, X, S, &prev, &op, &index, L);
+            if (L > 0 && k == X) {
+                // first mutation stage: finish the crossovers, then the
+                // proposal kernel starts attempt 0 (a scored swap)
+                e = launch_ga_stage(g, k & 1, prev, OP_NONE, 0, s);
+                if (e == hipSuccess)
+                    e = launch_propose(ga->learn_args(g), k & 1, s);
+            } else {
+                e = launch_ga_stage(g, k & 1, prev, op, index, s);
+            }
             if (e == hipSuccess && op != OP_NONE)
                 e = ga_eval(ga, g, (k & 1) ^ 1, s);
         }
         if (e == hipSuccess)
             e = launch_ga_best(g, ga->final_buf(), s);
+        if (e == hipSuccess && train) {
+            // one Adam step on the ring after every Levery-th generation
+            TrainGate gate{g.gs + GS_GEN, ga->last_trained, ga->Levery};
+            int nb = 0;
+            pmp_model *md = ga->model;
+            e = launch_mlp_grad(md->d.view(), ga->rep_x, ga->rep_t, ga->rep_w,
+                                (int)ga->ring_rows(), md->partials, kTrainBlocks, md->d, gate,
+                                &nb, s);
+            if (e == hipSuccess)
+                e = launch_mlp_update(md->d, md->partials, nb, ga->Llr, nullptr, nullptr, gate,
+                                      s);
+        }
         if (e != hipSuccess)
             return e;
     }
@@ -813,6 +929,8 @@ pmp_status pmp_ga_step(pmp_ga *ga, int32_t generations, void *stream)
     hipStream_t s = (hipStream_t)stream;
     const GaArgs g = ga->args();
     if (ga->persistent) {
+        if (ga->model)
+            return fail(PMP_EUNSUPPORTED, "learned proposal in persistent-kernel mode");
         if (!ga->self) {
             ga->self = new BatchHost;
             pmp_ga *one = ga;
@@ -861,6 +979,8 @@ pmp_status pmp_ga_best(pmp_ga *ga, uint64_t *mask, int64_t *cost,
         stats->mutation_taken = (int64_t)tot[CS_MUT_TAKEN];
         stats->scan_total = (int64_t)tot[CS_SCAN];
         stats->pair_evals = (int64_t)tot[CS_EVALS] * ga->inst->n;
+        stats->swap_tried = (int64_t)tot[CS_SWAP_TRIED];
+        stats->swap_taken = (int64_t)tot[CS_SWAP_TAKEN];
     }
     uint32_t herr = 0;
     HIP_TRY(hipMemcpy(&herr, ga->inst->err, sizeof herr, hipMemcpyDeviceToHost));
@@ -1061,6 +1181,8 @@ pmp_status pmp_batch_create(pmp_ga *const *gas, int32_t count, pmp_batch **out)
     for (int b = 0; b < count; ++b) {
         if (!gas[b])
             return fail(PMP_EINVAL, "GA %d is NULL", b);
+        if (gas[b]->model)
+            return fail(PMP_EUNSUPPORTED, "GA %d uses a learned proposal (not batched)", b);
         for (int c = 0; c < b; ++c)
             if (gas[c] == gas[b])
                 return fail(PMP_EINVAL, "GA %d appears twice", b);
@@ -1194,6 +1316,385 @@ pmp_status pmp_solve(const int32_t *d, int32_t n, int32_t m, int32_t p,
     pmp_ga_destroy(ga);
     pmp_instance_destroy(inst);
     return st;
+}
+
+
+pmp_status pmp_features(pmp_instance *inst, const uint64_t *masks, int32_t P,
+                        float gen_frac, float *out, uint32_t flags, void *stream)
+{
+    if (!inst)
+        return fail(PMP_EINVAL, "instance is NULL");
+    if (P < 0)
+        return fail(PMP_EINVAL, "P < 0");
+    if (inst->m > PMP_MAX_LEARNED_FACILITIES)
+        return fail(PMP_EUNSUPPORTED, "m=%d above %d", inst->m, PMP_MAX_LEARNED_FACILITIES);
+    if (P == 0)
+        return PMP_OK;
+    if (!masks || !out)
+        return fail(PMP_EINVAL, "masks or out is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const bool on_dev = flags & PMP_ON_DEVICE;
+    const size_t W = inst->W, cells = (size_t)P * inst->m * kFeatures;
+    const uint64_t *dm = masks;
+    float *dout = out;
+    uint64_t *tm = nullptr;
+    float *to = nullptr;
+    pmp_status st = PMP_OK;
+    do {
+        if (!on_dev) {
+            if (dalloc(&tm, (size_t)P * W) || dalloc(&to, cells)) {
+                st = fail(PMP_ENOMEM, "feature staging for P=%d", P);
+                break;
+            }
+            if (hipMemcpyAsync(tm, masks, sizeof(uint64_t) * P * W, hipMemcpyHostToDevice,
+                               s) != hipSuccess) {
+                st = fail(PMP_EDEVICE, "copy of masks");
+                break;
+            }
+            dm = tm;
+            dout = to;
+        }
+        FeatCtx ctx{};
+        ctx.n = inst->n;
+        ctx.m = inst->m;
+        ctx.p = inst->p;
+        ctx.near_len = inst->near_len;
+        ctx.total = inst->total;
+        ctx.gen_frac = gen_frac;
+        ctx.colsum = inst->colsum;
+        ctx.nearc = inst->nearc;
+        hipError_t e = launch_zero(inst->err, sizeof(uint32_t), s);
+        if (e == hipSuccess)
+            e = launch_features(inst->tables(), dm, P, ctx, dout, inst->err, s);
+        if (e == hipSuccess && !on_dev)
+            e = hipMemcpyAsync(out, dout, sizeof(float) * cells, hipMemcpyDeviceToHost, s);
+        uint32_t herr = 0;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&herr, inst->err, sizeof herr, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            st = fail(PMP_EDEVICE, "features: %s", hipGetErrorString(e));
+            break;
+        }
+        st = status_from_err(herr);
+    } while (0);
+    dfree(tm);
+    dfree(to);
+    return st;
+}
+
+void pmp_model_destroy(pmp_model *md)
+{
+    if (!md)
+        return;
+    dfree(md->d.master);
+    dfree(md->d.m1);
+    dfree(md->d.m2);
+    dfree(md->d.W1);
+    dfree(md->d.W2);
+    dfree(md->d.W2T);
+    dfree(md->d.w3);
+    dfree(md->d.step);
+    dfree(md->partials);
+    dfree(md->grad);
+    dfree(md->loss);
+    dfree(md->xf);
+    dfree(md->xb);
+    dfree(md->tf);
+    dfree(md->wf);
+    dfree(md->yf);
+    delete md;
+}
+
+pmp_status pmp_model_create(uint64_t seed, pmp_model **out)
+{
+    if (!out)
+        return fail(PMP_EINVAL, "out is NULL");
+    *out = nullptr;
+    pmp_model *md = new pmp_model;
+    MlpModelDev &d = md->d;
+    if (dalloc(&d.master, kParams) || dalloc(&d.m1, kParams) || dalloc(&d.m2, kParams) ||
+        dalloc(&d.W1, (size_t)kHidden * kIn) || dalloc(&d.W2, (size_t)kHidden * kHidden) ||
+        dalloc(&d.W2T, (size_t)kHidden * kHidden) || dalloc(&d.w3, kHidden) ||
+        dalloc(&d.step, 1) || dalloc(&md->partials, (size_t)kTrainBlocks * kPartStride) ||
+        dalloc(&md->grad, kParams) || dalloc(&md->loss, 1)) {
+        pmp_model_destroy(md);
+        return fail(PMP_ENOMEM, "model buffers");
+    }
+    hipError_t e = launch_mlp_init(d, seed, nullptr);
+    if (e == hipSuccess)
+        e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        pmp_model_destroy(md);
+        return fail(PMP_EDEVICE, "model init: %s", hipGetErrorString(e));
+    }
+    *out = md;
+    return PMP_OK;
+}
+
+pmp_status pmp_model_get(pmp_model *md, float *params, uint32_t flags, void *stream)
+{
+    if (!md || !params)
+        return fail(PMP_EINVAL, "model or params is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const bool on_dev = flags & PMP_ON_DEVICE;
+    HIP_TRY(hipMemcpyAsync(params, md->d.master, sizeof(float) * kParams,
+                           on_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+    if (!on_dev)
+        HIP_TRY(hipStreamSynchronize(s));
+    return PMP_OK;
+}
+
+pmp_status pmp_model_set(pmp_model *md, const float *params, uint32_t flags, void *stream)
+{
+    if (!md || !params)
+        return fail(PMP_EINVAL, "model or params is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const bool on_dev = flags & PMP_ON_DEVICE;
+    HIP_TRY(hipMemcpyAsync(md->d.master, params, sizeof(float) * kParams,
+                           on_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_zero(md->d.m1, sizeof(float) * kParams, s));
+    HIP_TRY(launch_zero(md->d.m2, sizeof(float) * kParams, s));
+    HIP_TRY(launch_zero(md->d.step, sizeof(uint32_t), s));
+    HIP_TRY(launch_mlp_publish(md->d, s));
+    if (!on_dev)
+        HIP_TRY(hipStreamSynchronize(s));
+    return PMP_OK;
+}
+
+namespace {
+
+// Device copies of a call's rows: BF16 inputs, and targets / weights.
+pmp_status model_stage(pmp_model *md, const float *x, const float *t, const float *w,
+                       int32_t rows, bool on_dev, hipStream_t s, const float **dt,
+                       const float **dw)
+{
+    if (md->cap < rows) {
+        dfree(md->xf);
+        dfree(md->xb);
+        dfree(md->tf);
+        dfree(md->wf);
+        dfree(md->yf);
+        md->cap = 0;
+        if (dalloc(&md->xf, (size_t)rows * kIn) || dalloc(&md->xb, (size_t)rows * kIn) ||
+            dalloc(&md->tf, (size_t)rows) || dalloc(&md->wf, (size_t)rows) ||
+            dalloc(&md->yf, (size_t)rows))
+            return fail(PMP_ENOMEM, "model staging for %d rows", rows);
+        md->cap = rows;
+    }
+    const float *dx = x;
+    if (!on_dev) {
+        HIP_TRY(hipMemcpyAsync(md->xf, x, sizeof(float) * rows * kIn, hipMemcpyHostToDevice, s));
+        dx = md->xf;
+    }
+    HIP_TRY(launch_to_bf16(dx, md->xb, (int64_t)rows * kIn, s));
+    if (dt) {
+        *dt = t;
+        if (t && !on_dev) {
+            HIP_TRY(hipMemcpyAsync(md->tf, t, sizeof(float) * rows, hipMemcpyHostToDevice, s));
+            *dt = md->tf;
+        }
+    }
+    if (dw) {
+        *dw = w;
+        if (w && !on_dev) {
+            HIP_TRY(hipMemcpyAsync(md->wf, w, sizeof(float) * rows, hipMemcpyHostToDevice, s));
+            *dw = md->wf;
+        }
+    }
+    return PMP_OK;
+}
+
+}  // namespace
+
+pmp_status pmp_model_forward(pmp_model *md, const float *x, int32_t rows, float *y,
+                             uint32_t flags, void *stream)
+{
+    if (!md)
+        return fail(PMP_EINVAL, "model is NULL");
+    if (rows < 0)
+        return fail(PMP_EINVAL, "rows < 0");
+    if (rows == 0)
+        return PMP_OK;
+    if (!x || !y)
+        return fail(PMP_EINVAL, "x or y is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const bool on_dev = flags & PMP_ON_DEVICE;
+    pmp_status st = model_stage(md, x, nullptr, nullptr, rows, on_dev, s, nullptr, nullptr);
+    if (st != PMP_OK)
+        return st;
+    float *dy = on_dev ? y : md->yf;
+    HIP_TRY(launch_mlp_forward(md->d.view(), md->xb, rows, dy, s));
+    if (!on_dev) {
+        HIP_TRY(hipMemcpyAsync(y, dy, sizeof(float) * rows, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    return PMP_OK;
+}
+
+namespace {
+
+pmp_status model_steps(pmp_model *md, const float *x, const float *t, const float *w,
+                       int32_t rows, float lr, int32_t steps, float *grad, float *loss,
+                       uint32_t flags, hipStream_t s)
+{
+    if (!md)
+        return fail(PMP_EINVAL, "model is NULL");
+    if (rows < 1 || !x || !t)
+        return fail(PMP_EINVAL, "need rows >= 1, x and t");
+    const bool on_dev = flags & PMP_ON_DEVICE;
+    const float *dt = nullptr, *dw = nullptr;
+    pmp_status st = model_stage(md, x, t, w, rows, on_dev, s, &dt, &dw);
+    if (st != PMP_OK)
+        return st;
+    float *dgrad = grad ? (on_dev ? grad : md->grad) : nullptr;
+    if (dgrad)
+        HIP_TRY(launch_zero(dgrad, sizeof(float) * kParams, s));
+    if (loss)
+        HIP_TRY(launch_zero(md->loss, sizeof(float), s));
+    for (int k = 0; k < steps; ++k) {
+        int nb = 0;
+        HIP_TRY(launch_mlp_grad(md->d.view(), md->xb, dt, dw, rows, md->partials, kTrainBlocks,
+                                md->d, TrainGate{nullptr, nullptr, 1}, &nb, s));
+        const bool last = k == steps - 1;
+        HIP_TRY(launch_mlp_update(md->d, md->partials, nb, lr, last ? dgrad : nullptr,
+                                  last && loss ? md->loss : nullptr,
+                                  TrainGate{nullptr, nullptr, 1}, s));
+    }
+    if (grad && !on_dev)
+        HIP_TRY(hipMemcpyAsync(grad, dgrad, sizeof(float) * kParams, hipMemcpyDeviceToHost, s));
+    if (loss)
+        HIP_TRY(hipMemcpyAsync(loss, md->loss, sizeof(float),
+                               on_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+    if (!on_dev)
+        HIP_TRY(hipStreamSynchronize(s));
+    return PMP_OK;
+}
+
+}  // namespace
+
+pmp_status pmp_model_grad(pmp_model *md, const float *x, const float *t, const float *w,
+                          int32_t rows, float *grad, float *loss, uint32_t flags, void *stream)
+{
+    return model_steps(md, x, t, w, rows, 0.f, 1, grad, loss, flags, (hipStream_t)stream);
+}
+
+pmp_status pmp_model_train(pmp_model *md, const float *x, const float *t, const float *w,
+                           int32_t rows, float lr, int32_t steps, float *loss, uint32_t flags,
+                           void *stream)
+{
+    if (!(lr > 0.f) || steps < 1)
+        return fail(PMP_EINVAL, "need lr > 0 and steps >= 1");
+    return model_steps(md, x, t, w, rows, lr, steps, nullptr, loss, flags,
+                       (hipStream_t)stream);
+}
+
+pmp_status pmp_ga_set_model(pmp_ga *ga, pmp_model *model, const pmp_learn_params *lp)
+{
+    if (!ga)
+        return fail(PMP_EINVAL, "ga is NULL");
+    HIP_TRY(hipDeviceSynchronize());
+    if (ga->gexec) {
+        (void)hipGraphExecDestroy(ga->gexec);
+        ga->gexec = nullptr;
+    }
+    if (!model) {
+        ga->model = nullptr;
+        ga->free_learned();
+        return PMP_OK;
+    }
+    if (ga->persistent)
+        return fail(PMP_EUNSUPPORTED, "learned proposal in persistent-kernel mode");
+    if (ga->inst->m > PMP_MAX_LEARNED_FACILITIES)
+        return fail(PMP_EUNSUPPORTED, "m=%d above %d", ga->inst->m, PMP_MAX_LEARNED_FACILITIES);
+    pmp_learn_params q{};
+    if (lp)
+        q = *lp;
+    if (q.reserved[0] || q.reserved[1])
+        return fail(PMP_EINVAL, "reserved fields must be 0");
+    const int C = q.candidates ? q.candidates : PMP_MAX_CANDIDATES;
+    if (C < 1 || C > PMP_MAX_CANDIDATES)
+        return fail(PMP_EINVAL, "candidates %d outside 1..%d", C, PMP_MAX_CANDIDATES);
+    if (ga->Y < 1)
+        return fail(PMP_EINVAL, "the run has no mutation attempts");
+    const int L = q.learned_iters ? q.learned_iters : (ga->Y + 1) / 2;
+    if (L < 1 || L > C || L > ga->Y)
+        return fail(PMP_EINVAL, "learned_iters %d outside 1..min(C=%d, Y=%d)", L, C, ga->Y);
+    if (q.explore_permille < 0 || q.explore_permille > 1000)
+        return fail(PMP_EINVAL, "explore_permille outside 0..1000");
+    const int H = q.history ? q.history : 4;
+    if (H < 1 || (int64_t)H * L * ga->prm.population > (1 << 24))
+        return fail(PMP_EINVAL, "history %d: ring too large", H);
+    if (q.train_every < 0)
+        return fail(PMP_EINVAL, "train_every < 0");
+    const float lr = q.lr == 0.f ? 1e-3f : q.lr;
+    if (!(lr > 0.f) || lr > 1.f)
+        return fail(PMP_EINVAL, "lr outside (0, 1]");
+    ga->free_learned();
+    ga->model = nullptr;
+    const size_t P = ga->prm.population, R = (size_t)H * L * P;
+    if (dalloc(&ga->swaps, P * L * 2) || dalloc(&ga->rep_x, R * kIn) || dalloc(&ga->rep_t, R) ||
+        dalloc(&ga->rep_w, R) || dalloc(&ga->rep_jk, R * 2) || dalloc(&ga->rep_d, R * 2) ||
+        dalloc(&ga->scores, P * C) || dalloc(&ga->last_trained, 1)) {
+        ga->free_learned();
+        return fail(PMP_ENOMEM, "learned proposal buffers (%zu ring rows)", R);
+    }
+    hipError_t e = hipMemset(ga->rep_w, 0, sizeof(float) * R);
+    if (e == hipSuccess)
+        e = hipMemset(ga->rep_t, 0, sizeof(float) * R);
+    if (e == hipSuccess)
+        e = hipMemset(ga->rep_x, 0, sizeof(uint16_t) * R * kIn);
+    if (e == hipSuccess)
+        e = hipMemset(ga->rep_jk, 0, sizeof(int32_t) * R * 2);
+    if (e == hipSuccess)
+        e = hipMemset(ga->rep_d, 0, sizeof(long long) * R * 2);
+    if (e == hipSuccess)
+        e = hipMemset(ga->scores, 0, sizeof(float) * P * C);
+    if (e == hipSuccess)
+        e = hipMemset(ga->last_trained, 0, sizeof(unsigned long long));
+    if (e == hipSuccess)
+        e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        ga->free_learned();
+        return fail(PMP_EDEVICE, "learned proposal init: %s", hipGetErrorString(e));
+    }
+    ga->model = model;
+    ga->LC = C;
+    ga->LL = L;
+    ga->Lexp = q.explore_permille;
+    ga->LH = H;
+    ga->Levery = q.train_every;
+    ga->Llr = lr;
+    return PMP_OK;
+}
+
+pmp_status pmp_ga_replay(pmp_ga *ga, int32_t *rows, uint16_t *x, float *target,
+                         float *weight, int32_t *swap, int64_t *delta, float *scores,
+                         void *stream)
+{
+    if (!ga)
+        return fail(PMP_EINVAL, "ga is NULL");
+    if (!ga->model)
+        return fail(PMP_EINVAL, "the run has no model");
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    const size_t R = (size_t)ga->ring_rows();
+    if (rows)
+        *rows = (int32_t)R;
+    if (x)
+        HIP_TRY(hipMemcpy(x, ga->rep_x, sizeof(uint16_t) * R * kIn, hipMemcpyDeviceToHost));
+    if (target)
+        HIP_TRY(hipMemcpy(target, ga->rep_t, sizeof(float) * R, hipMemcpyDeviceToHost));
+    if (weight)
+        HIP_TRY(hipMemcpy(weight, ga->rep_w, sizeof(float) * R, hipMemcpyDeviceToHost));
+    if (swap)
+        HIP_TRY(hipMemcpy(swap, ga->rep_jk, sizeof(int32_t) * R * 2, hipMemcpyDeviceToHost));
+    if (delta)
+        HIP_TRY(hipMemcpy(delta, ga->rep_d, sizeof(int64_t) * R * 2, hipMemcpyDeviceToHost));
+    if (scores)
+        HIP_TRY(hipMemcpy(scores, ga->scores, sizeof(float) * ga->prm.population * ga->LC,
+                          hipMemcpyDeviceToHost));
+    return PMP_OK;
 }
 
 }  // extern "C"
