@@ -267,6 +267,96 @@ def bench_learned(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_e5000(args):
+    """The evaluation kernel alone on the Euclidean n = m = 5000 instance,
+    p in {10, 100, 500}, population 4096: a uniform random population and
+    one evolved for --evolve-generations generations; median of 20 timed
+    launches (HIP events on the launch stream) after 3 warm-ups.  Also the
+    preprocessing time of each instance."""
+    import numpy as np
+    import torch
+    import paper_1610_10061_amd as pm
+    import pmp_inputs as gi
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    n, P = 5000, 4096
+    d = gi.euclid_instance(n, 0)
+    dd = torch.from_numpy(d).cuda()
+    W = gi.words_for(n)
+    res = []
+    for p in (10, 100, 500):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        pm.Instance(dd, p, stream).close()  # first use outside the clock
+        torch.cuda.synchronize()
+        e0.record()
+        inst = pm.Instance(dd, p, stream)
+        e1.record()
+        torch.cuda.synchronize()
+        prep_ms = e0.elapsed_time(e1)
+        pops = {"random": torch.from_numpy(gi.random_population(P, n, p, 1)).cuda()}
+        ga = pm.GA(inst, P, 256, args.evolve_generations, 0)
+        ga.step(args.evolve_generations, stream)
+        pops["evolved"] = torch.from_numpy(ga.state()[0]).cuda()
+        ga.close()
+        for kind, masks in pops.items():
+            fit = torch.empty(P, dtype=torch.int64, device="cuda")
+            scan = torch.empty(P, dtype=torch.int64, device="cuda")
+            for _ in range(3):
+                inst.eval(masks, fit, scan, stream, asynchronous=True)
+            times = []
+            for _ in range(20):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                inst.eval(masks, fit, scan, stream, asynchronous=True)
+                b.record()
+                times.append((a, b))
+            inst.check(stream)
+            ms = float(np.median([a.elapsed_time(b) for a, b in times]))
+            s_tot = int(scan.sum().item())
+            pairs = P * n
+            byts = 2 * s_tot + 4 * pairs + P * (8 * W + 8)
+            row = {"p": p, "population": kind, "eval_ms": ms,
+                   "pair_evals_per_s": pairs / (ms / 1e3),
+                   "mean_scan": s_tot / pairs, "expected_scan_random": (n + 1) / (p + 1),
+                   "algorithmic_GBps": byts / (ms / 1e3) / 1e9,
+                   "frac_of_hbm_peak": byts / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                   "preprocess_ms": prep_ms, "preprocess_rows_per_s": n / (prep_ms / 1e3)}
+            if kind == "random":
+                import oracle
+                sub = masks[:8].cpu().numpy()
+                oc, os_ = oracle.objective(d, sub, p, scan=True)
+                assert np.array_equal(oc, fit[:8].cpu().numpy())
+                assert np.array_equal(os_, scan[:8].cpu().numpy())
+            log(json.dumps(row))
+            res.append(row)
+        inst.close()
+    best = max(res, key=lambda r: r["frac_of_hbm_peak"])
+    out = {
+        "metric": "client×chromosome fitness evals/s (evaluation kernel alone)",
+        "value": float(np.median([r["pair_evals_per_s"] for r in res])),
+        "unit": "client×chromosome evals/s",
+        "n_gpus": 1, "higher_is_better": True, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "E5000: Euclidean n=m=5000 on the 10^4 x 10^4 integer grid, "
+                               "p in {10,100,500}, population 4096, random and evolved "
+                               "(%d generations) populations" % args.evolve_generations},
+        "roofline": {"bound": "hbm", "kernel": "k_eval", "achieved": best["algorithmic_GBps"],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": best["frac_of_hbm_peak"], "traffic": None,
+                     "case": f"p={best['p']} {best['population']}"},
+        "cases": res,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        sub = pops["random"][:256].cpu().numpy()
+        t0 = time.perf_counter()
+        oracle.objective(d, sub, 500)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": 256 * n / dt, "unit": "client×chromosome evals/s",
+                               "cores": oracle.default_threads(), "kind": "oracle",
+                               "sample": "oracle objective of 256 chromosomes (p=500)"}
+    print(json.dumps(out), flush=True)
+
+
 def oracle_threads():
     import oracle
     return oracle.default_threads()
@@ -282,13 +372,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="no per-launch events (the GA then replays hipGraphs)")
-    ap.add_argument("--workload", choices=["g900", "batch", "learned"], default="g900",
+    ap.add_argument("--workload", choices=["g900", "batch", "learned", "e5000"],
+                    default="g900",
                     help="g900: the headline configuration; batch: 256 ragged "
                          "instances in one launch vs one launch per instance; "
                          "learned: plain vs learned-proposal GA at equal wall time")
     ap.add_argument("--train-seeds", type=int, default=20)
     ap.add_argument("--train-generations", type=int, default=100)
     ap.add_argument("--eval-seeds", type=int, default=10)
+    ap.add_argument("--evolve-generations", type=int, default=20)
     ap.add_argument("--seconds", type=float, default=2.0,
                     help="wall time of each plain / learned run (learned workload)")
     ap.add_argument("--batch-generations", type=int, default=100)
@@ -315,6 +407,8 @@ def main():
 
     if args.workload == "learned":
         return bench_learned(args)
+    if args.workload == "e5000":
+        return bench_e5000(args)
 
     import numpy as np
     import torch

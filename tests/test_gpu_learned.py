@@ -321,8 +321,9 @@ def test_trained_network_gains(pm):
     rate_u, tgt_u = _success(pm, fresh, p, pm.Model(12), 7, 0)
     rate_r, tgt_r = _success(pm, fresh, p, pm.Model(12), 7, 1000)
     _say("success trained/untrained/random", rate_t, rate_u, rate_r, tgt_t, tgt_u, tgt_r)
-    assert rate_t > 1.5 * max(rate_u, rate_r)
-    assert tgt_t < min(tgt_u, tgt_r)
+    # success rates are capped at 1: compare by margins
+    assert rate_t >= max(rate_u, rate_r) + 0.1
+    assert tgt_t <= min(tgt_u, tgt_r) - 0.3
     # same generations, fresh seed: learned GA (continuing to train) vs plain
     G = 40
     inst, lga = _learned_ga(pm, fresh, p, 256, 64, G, 3, trained, candidates=32,
