@@ -47,6 +47,34 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "k_eval_g900_counters.json")
+EVAL_SOURCES = ("eval_device.hpp", "k_eval.hip")
+
+
+def eval_sources_digest():
+    """Digest of the evaluation kernel's source files."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in EVAL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1610_10061_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per evaluation dispatch from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's readings),
+    or None when it is absent or the kernel's sources changed since."""
+    try:
+        with open(COUNTERS) as fh:
+            c = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if c.get("eval_sources_digest") != eval_sources_digest():
+        return None
+    return c.get("hbm_bytes_per_dispatch")
+
+
 def cpu_baseline(d, p, P, NT, budget_s):
     """The oracle GA on the same instance and parameters, a bounded number of
     generations, on all host cores it is allowed."""
@@ -495,7 +523,9 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(),
+            "traffic_source": "profiles/k_eval_g900_counters.json (null if the "
+                              "evaluation kernel changed since)",
             "launches": ev_n,
             "avg_launch_us": ev_ms * 1e3 / max(ev_n, 1),
             "bytes_per_launch": ev_bytes / max(ev_n, 1),

@@ -25,8 +25,10 @@ namespace pmp {
 
 namespace {
 
-constexpr int kLearnWaves = 4;
+constexpr int kLearnWaves = 8;   // walk the clients
+constexpr int kMlpWaves = 4;     // score the 64 candidate rows (16 rows each)
 constexpr int kLearnThreads = 64 * kLearnWaves;
+constexpr int kPrefetch = 8;     // clients in flight per wave
 
 // Position of the set bit of x that has exactly r set bits below it.
 __device__ __forceinline__ int select_bit(uint64_t x, int r)
@@ -41,40 +43,55 @@ __device__ __forceinline__ int select_bit(uint64_t x, int r)
     return b;
 }
 
-// Walk every client of the instance; each wave takes clients wave,
-// wave + 4, ...; the next client's first chunk is loaded while the current
-// one is walked.  Returns the wave's summed c1 (wave-uniform); -1 in *bad if
-// some row has no open facility.
+// Walk every client of the instance.  Wave w takes the clients w + kLearnWaves
+// * (kPrefetch * r + d), d < kPrefetch, in batches of kPrefetch: the first
+// chunk of every client of the next batch is loaded while the current batch
+// is walked (the walk is bound by the latency of these loads).  The loads are
+// unconditional, at a clamped row and column that are always in bounds, so
+// none of them has to complete before its value is used.  Returns the wave's
+// summed c1 (wave-uniform); *bad if some row has no open facility.
 template <class SlotFn>
 __device__ __forceinline__ long long scan_all(const Tables &t, const uint32_t *smask,
                                               const SlotFn &slot, SlotBins &B, int wave,
                                               int lane, bool *bad)
 {
+    constexpr int step = kLearnWaves * kPrefetch;
     long long f = 0;
-    const bool v = lane < t.K;
-    int i = wave;
-    int fac = 0;
-    int32_t dist = 0;
-    if (i < t.n && v) {
-        fac = t.pi[(int64_t)i * t.pitch + lane];
-        dist = t.ds[(int64_t)i * t.pitch + lane];
+    const int col = lane < t.K ? lane : t.K - 1;
+    const int last = t.n - 1;
+    int fac[kPrefetch];
+    int32_t dist[kPrefetch];
+#pragma unroll
+    for (int d = 0; d < kPrefetch; ++d) {
+        const int i = min(wave + kLearnWaves * d, last);
+        fac[d] = t.pi[(int64_t)i * t.pitch + col];
+        dist[d] = t.ds[(int64_t)i * t.pitch + col];
     }
-    while (i < t.n) {
-        const int in = i + kLearnWaves;
-        int nfac = 0;
-        int32_t ndist = 0;
-        if (in < t.n && v) {
-            nfac = t.pi[(int64_t)in * t.pitch + lane];
-            ndist = t.ds[(int64_t)in * t.pitch + lane];
+    for (int i0 = wave; i0 < t.n; i0 += step) {
+        int nfac[kPrefetch];
+        int32_t ndist[kPrefetch];
+#pragma unroll
+        for (int d = 0; d < kPrefetch; ++d) {
+            const int i = min(i0 + step + kLearnWaves * d, last);
+            nfac[d] = t.pi[(int64_t)i * t.pitch + col];
+            ndist[d] = t.ds[(int64_t)i * t.pitch + col];
         }
-        const int32_t c1 = scan_client(t, i, fac, dist, smask, slot, B, lane);
-        if (c1 < 0)
-            *bad = true;
-        else
-            f += c1;
-        fac = nfac;
-        dist = ndist;
-        i = in;
+#pragma unroll
+        for (int d = 0; d < kPrefetch; ++d) {
+            const int i = i0 + kLearnWaves * d;
+            if (i < t.n) {
+                const int32_t c1 = scan_client(t, i, fac[d], dist[d], smask, slot, B, lane);
+                if (c1 < 0)
+                    *bad = true;
+                else
+                    f += c1;
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < kPrefetch; ++d) {
+            fac[d] = nfac[d];
+            dist[d] = ndist[d];
+        }
     }
     return f;
 }
@@ -162,7 +179,7 @@ struct ProposeLds {
     int32_t order[PMP_MAX_CANDIDATES];
     float score[PMP_MAX_CANDIDATES];
     __align__(16) uint16_t x[PMP_MAX_CANDIDATES * kXStride];
-    __align__(16) uint16_t h[kLearnWaves][16 * kHStride];
+    __align__(16) uint16_t h[kMlpWaves][16 * kHStride];
     long long sf[kLearnWaves];
     int scount, sbad;
 };
@@ -256,7 +273,7 @@ __global__ __launch_bounds__(kLearnThreads) void k_propose(LearnArgs A, int in)
         return;
     }
     // 3. input rows: thread (row, quarter) writes 8 inputs
-    {
+    if (threadIdx.x < 4 * PMP_MAX_CANDIDATES) {
         const int row = threadIdx.x >> 2, qtr = threadIdx.x & 3;
         uint16_t v8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         if (row < C) {
@@ -273,8 +290,8 @@ __global__ __launch_bounds__(kLearnThreads) void k_propose(LearnArgs A, int in)
         d[1] = uint2{v8[4] | ((uint32_t)v8[5] << 16), v8[6] | ((uint32_t)v8[7] << 16)};
     }
     __syncthreads();
-    // scores
-    {
+    // scores (16 rows per wave)
+    if (wave < kMlpWaves) {
         f32x4 z1[8], z2[8];
         float y[4];
         mlp_forward16(A.net, L.x + wave * 16 * kXStride, L.h[wave], lane, z1, z2, y);

@@ -304,25 +304,61 @@ __device__ __forceinline__ void publish(const MlpModelDev &M, int k, float v)
     }
 }
 
-// Sum the partials in workgroup order; gradient = sum / (row weight sum).
-// With lr > 0, an Adam step on the master parameters and their BF16
-// copies.  Nothing happens when the row weights sum to zero.
-__global__ void k_mlp_update(MlpModelDev M, const float *partials, int blocks, float lr,
-                             float *grad_out, float *loss_out, TrainGate gate)
+// Sum the partials of `blocks` training workgroups: gradient = sum / (row
+// weight sum).  With lr > 0, an Adam step on the master parameters and their
+// BF16 copies.  Nothing happens when the row weights sum to zero.
+// Workgroup layout: 64 parameters x 8 partial groups; thread (k, q) adds the
+// partials of workgroups q, q + 8, ... in order, then the 8 group sums are
+// added in order, so the result does not depend on scheduling.
+constexpr int kUpdGroups = 8;
+constexpr int kUpdMaxBlocks = 256;
+
+__global__ __launch_bounds__(64 * kUpdGroups) void k_mlp_update(MlpModelDev M,
+                                                                 const float *partials,
+                                                                 int blocks, float lr,
+                                                                 float *grad_out,
+                                                                 float *loss_out,
+                                                                 TrainGate gate)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    float n = 0.f;
-    for (int b = 0; b < blocks; ++b)
-        n += partials[(int64_t)b * kPartStride + kParams];
-    if (!(n > 0.f))
-        return;
-    if (k == 0) {
-        if (loss_out) {
-            float l = 0.f;
-            for (int b = 0; b < blocks; ++b)
-                l += partials[(int64_t)b * kPartStride + kParams + 1];
-            *loss_out = l / (2.f * n);
+    __shared__ float hn[kUpdMaxBlocks], hl[kUpdMaxBlocks];
+    __shared__ float red[kUpdGroups][64];
+    __shared__ float tot[2];
+    const int tx = threadIdx.x & 63, q = threadIdx.x >> 6;
+    if (threadIdx.x < blocks) {
+        hn[threadIdx.x] = partials[(int64_t)threadIdx.x * kPartStride + kParams];
+        hl[threadIdx.x] = partials[(int64_t)threadIdx.x * kPartStride + kParams + 1];
+    }
+    const int k = blockIdx.x * 64 + tx;
+    float s = 0.f;
+    if (k < kParams) {
+        float v[kUpdMaxBlocks / kUpdGroups];
+#pragma unroll
+        for (int r = 0; r < kUpdMaxBlocks / kUpdGroups; ++r) {
+            const int b = q + kUpdGroups * r;
+            v[r] = b < blocks ? partials[(int64_t)b * kPartStride + k] : 0.f;
         }
+#pragma unroll
+        for (int r = 0; r < kUpdMaxBlocks / kUpdGroups; ++r)
+            s += v[r];
+    }
+    red[q][tx] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float n = 0.f, l = 0.f;
+        for (int b = 0; b < blocks; ++b) {
+            n += hn[b];
+            l += hl[b];
+        }
+        tot[0] = n;
+        tot[1] = l;
+    }
+    __syncthreads();
+    const float n = tot[0];
+    if (!(n > 0.f) || q != 0)
+        return;
+    if (blockIdx.x == 0 && tx == 0) {
+        if (loss_out)
+            *loss_out = tot[1] / (2.f * n);
         if (lr > 0.f) {
             *M.step = __float_as_uint(partials[kParams + 2]);
             if (gate.last)
@@ -331,10 +367,11 @@ __global__ void k_mlp_update(MlpModelDev M, const float *partials, int blocks, f
     }
     if (k >= kParams)
         return;
-    float s = 0.f;
-    for (int b = 0; b < blocks; ++b)
-        s += partials[(int64_t)b * kPartStride + k];
-    const float gk = s / n;
+    float sum = 0.f;
+#pragma unroll
+    for (int g = 0; g < kUpdGroups; ++g)
+        sum += red[g][tx];
+    const float gk = sum / n;
     if (grad_out)
         grad_out[k] = gk;
     if (!(lr > 0.f))
@@ -432,8 +469,10 @@ hipError_t launch_mlp_update(const MlpModelDev &M, const float *partials, int bl
                              float lr, float *grad_out, float *loss_out, TrainGate gate,
                              hipStream_t s)
 {
-    hipLaunchKernelGGL(k_mlp_update, dim3(grid_for(kParams, 256)), dim3(256), 0, s, M,
-                       partials, blocks, lr, grad_out, loss_out, gate);
+    if (blocks > kUpdMaxBlocks)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_mlp_update, dim3(grid_for(kParams, 64)), dim3(64 * kUpdGroups), 0, s,
+                       M, partials, blocks, lr, grad_out, loss_out, gate);
     return hipGetLastError();
 }
 

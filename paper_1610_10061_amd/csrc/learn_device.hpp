@@ -63,16 +63,59 @@ __device__ __forceinline__ bool mask_bit(const uint32_t *smask, int f)
     return (smask[f >> 5] >> (f & 31)) & 1u;
 }
 
-// Walk client i's row (chunk 0 already loaded: fac0/dist0 = entry `lane`,
-// valid below K) and add its terms to the slots `slot(facility)` names
-// (-1: not gathered).  Returns c1_i (wave-uniform), or -1 if the row holds
-// no open facility (infeasible chromosome).
+// Add one Pi' entry's terms to its slot: position pos of client i's row
+// (facility's slot sl >= 0, distance dist), first / second open positions
+// s1 / s2 (s2 = -1: none inside the row), costs c1 / c2.
+__device__ __forceinline__ void add_terms(SlotBins &B, int sl, int pos, int s1, int s2,
+                                          int32_t c1, int32_t c2, int32_t dist)
+{
+    // counts: ahead and first open -> a; between and second open -> dd
+    atomicAdd(pos <= s1 ? &B.a[sl] : &B.dd[sl], 1u);
+    // sums: ahead -> gain, first -> served, second -> c2share, between -> bgain
+    unsigned long long *sum;
+    int32_t v;
+    if (pos < s1) {
+        sum = &B.b[sl];
+        v = c1 - dist;
+    } else if (pos == s1) {
+        sum = &B.b[sl];
+        v = c1;
+    } else if (pos == s2) {
+        sum = &B.e[sl];
+        v = c2 - c1;
+    } else {
+        sum = &B.cc[sl];
+        v = c2 - dist;
+    }
+    atomicAdd(sum, (unsigned long long)v);
+    if (pos == s1)
+        atomicAdd(&B.cc[sl], (unsigned long long)(c2 - c1));  // loss
+}
+
+// Walk client i's row (its first chunk already loaded: fac0/dist0 = entry
+// `lane`, meaningful below K) and add its terms to the slots `slot(facility)`
+// names (-1: not gathered).  Returns c1_i (wave-uniform), or -1 if the row
+// holds no open facility (infeasible chromosome).
 template <class SlotFn>
 __device__ __forceinline__ int32_t scan_client(const Tables &t, int i, int fac0,
                                                int32_t dist0, const uint32_t *smask,
                                                const SlotFn &slot, SlotBins &B, int lane)
 {
     const int K = t.K;
+    const bool valid0 = lane < K;
+    const uint64_t bits0 = __builtin_amdgcn_ballot_w64(valid0 && mask_bit(smask, fac0));
+    if (__builtin_popcountll(bits0) >= 2) {
+        // common case: both open positions inside the first chunk
+        const int s1 = (int)__builtin_ctzll(bits0);
+        const int s2 = (int)__builtin_ctzll(bits0 & (bits0 - 1));
+        const int32_t c1 = __builtin_amdgcn_readlane(dist0, s1);
+        const int32_t c2 = __builtin_amdgcn_readlane(dist0, s2);
+        const int sl = lane <= s2 ? slot(fac0) : -1;
+        if (sl >= 0)
+            add_terms(B, sl, lane, s1, s2, c1, c2, dist0);
+        return c1;
+    }
+    // general case: positions beyond the first chunk
     const uint16_t *prow = t.pi + (int64_t)i * t.pitch;
     const int32_t *drow = t.ds + (int64_t)i * t.pitch;
     int s1 = -1, s2 = -1;
@@ -111,25 +154,9 @@ __device__ __forceinline__ int32_t scan_client(const Tables &t, int i, int fac0,
             fac = prow[pos];
             dist = drow[pos];
         }
-        if (pos < end) {
-            const int sl = slot(fac);
-            if (sl >= 0) {
-                if (pos < s1) {
-                    atomicAdd(&B.a[sl], 1u);
-                    atomicAdd(&B.b[sl], (unsigned long long)(c1 - dist));
-                } else if (pos == s1) {
-                    atomicAdd(&B.a[sl], 1u);
-                    atomicAdd(&B.b[sl], (unsigned long long)c1);
-                    atomicAdd(&B.cc[sl], (unsigned long long)(c2 - c1));
-                } else if (pos == s2) {
-                    atomicAdd(&B.dd[sl], 1u);
-                    atomicAdd(&B.e[sl], (unsigned long long)(c2 - c1));
-                } else {
-                    atomicAdd(&B.dd[sl], 1u);
-                    atomicAdd(&B.cc[sl], (unsigned long long)(c2 - dist));
-                }
-            }
-        }
+        const int sl = pos < end ? slot(fac) : -1;
+        if (sl >= 0)
+            add_terms(B, sl, pos, s1, s2, c1, c2, dist);
     }
     return c1;
 }

@@ -177,7 +177,7 @@ struct pmp_model {
 };
 
 namespace {
-constexpr int kTrainBlocks = 128;  // workgroups of a training gradient launch
+constexpr int kTrainBlocks = 256;  // workgroups of a training gradient launch
 }
 
 struct pmp_ga {
