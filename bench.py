@@ -85,7 +85,7 @@ def cpu_baseline(d, p, P, NT, budget_s):
     t0 = time.perf_counter()
     oracle.ga_run(d, st, 1)
     one = time.perf_counter() - t0
-    more = max(0, min(40, int(budget_s / max(one, 1e-3)) - 1))
+    more = max(0, min(400, int(budget_s / max(one, 1e-3)) - 1))
     if more:
         oracle.ga_run(d, st, more)
     dt = time.perf_counter() - t0

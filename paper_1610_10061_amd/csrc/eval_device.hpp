@@ -114,23 +114,51 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
     // tile's masks, staged to LDS whether active or not (an inactive
     // chromosome is never pending, so its stale mask is never consulted).
     const int my_c = c0 + lane;
-    const bool my_act = my_c < a.P && (a.active == nullptr || a.active[my_c]);
     int i = i0 + wave;
-    uint32_t j_cur = 0;  // chunk 0 of the current client, loaded one ahead
-    int32_t d_cur = 0;
-    if (i < i1 && lane < a.t.K) {
-        j_cur = a.t.pi[(int64_t)i * a.t.pitch + lane];
-        d_cur = a.t.ds[(int64_t)i * a.t.pitch + lane];
-    }
+    // Chunk 0 of the current client is loaded one client ahead.  The loads
+    // are unconditional, at a row clamped into the tile and a column clamped
+    // below K (always in bounds; lanes at or past K are masked when used), so
+    // the compiler never has to wait for a prefetch before using the
+    // previous one.
+    const int col = lane < a.t.K ? lane : a.t.K - 1;
+    const bool in_row = lane < a.t.K;
+    const int last = i1 - 1;
+    const uint32_t j_first = a.t.pi[(int64_t)min(i, last) * a.t.pitch + col];
+    int32_t d_cur = a.t.ds[(int64_t)min(i, last) * a.t.pitch + col];
+    // Masks: every load unconditional at a clamped (always valid) address,
+    // in batches, so that a batch costs one round trip; out-of-range words
+    // are replaced by 0 when stored.
     const uint32_t *g32 = reinterpret_cast<const uint32_t *>(a.masks);
     const int rows = min(kEvalTile, a.P - c0);
-#pragma unroll 8
-    for (int k = threadIdx.x; k < kEvalTile * WD; k += kEvalTile * kEvalWaves) {
-        const int c = k / WD, w = k - (k / WD) * WD;
-        smask[k] = (w < W2 && c < rows) ? g32[(int64_t)(c0 + c) * W2 + w] : 0u;
+    constexpr int kTot = kEvalTile * WD, kThreads = kEvalTile * kEvalWaves;
+    constexpr int kIt = (kTot + kThreads - 1) / kThreads;
+    constexpr int kBatch = kIt < 16 ? kIt : 16;
+    // active flag: also an unconditional load (of any valid byte when every
+    // chromosome is active)
+    const uint8_t *ap = a.active ? a.active + min(my_c, a.P - 1) : (const uint8_t *)a.masks;
+    const uint8_t actv = *ap;
+#pragma unroll
+    for (int r0 = 0; r0 < kIt; r0 += kBatch) {
+        uint32_t v[kBatch];
+#pragma unroll
+        for (int r = 0; r < kBatch; ++r) {
+            const int k = min((int)threadIdx.x + (r0 + r) * kThreads, kTot - 1);
+            const int c = k / WD, w = k - (k / WD) * WD;
+            v[r] = g32[(int64_t)(c0 + min(c, rows - 1)) * W2 + min(w, W2 - 1)];
+        }
+#pragma unroll
+        for (int r = 0; r < kBatch; ++r) {
+            const int k = (int)threadIdx.x + (r0 + r) * kThreads;
+            const int c = k / WD, w = k - (k / WD) * WD;
+            if (k < kTot)
+                smask[k] = (w < W2 && c < rows) ? v[r] : 0u;
+        }
     }
+    const bool my_act = my_c < a.P && (a.active == nullptr || actv != 0);
     const uint64_t act = __builtin_amdgcn_ballot_w64(my_act);
-    if (act == 0ull)  // same in every wave: the whole workgroup leaves
+    // nothing to do (same in every wave: the whole workgroup leaves), or a
+    // stopped GA run, whose later generations are no-ops
+    if (act == 0ull || (a.done && *a.done))
         return;
     __syncthreads();
 
@@ -158,14 +186,13 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
 
     unsigned long long acc = 0;
     uint32_t scn = 0;
+    // chunk-0 operands of the current client: mask word, bit (0 past K)
+    uint32_t off_cur = j_first >> 5;
+    uint32_t bit_cur = in_row ? 1u << (j_first & 31u) : 0u;
     for (; i < i1; i += kEvalWaves) {
-        const int inext = i + kEvalWaves;
-        uint32_t j_nxt = 0;
-        int32_t d_nxt = 0;
-        if (inext < i1 && lane < a.t.K) {
-            j_nxt = a.t.pi[(int64_t)inext * a.t.pitch + lane];
-            d_nxt = a.t.ds[(int64_t)inext * a.t.pitch + lane];
-        }
+        const int inext = min(i + kEvalWaves, last);
+        const uint32_t j_nxt = a.t.pi[(int64_t)inext * a.t.pitch + col];
+        const int32_t d_nxt = a.t.ds[(int64_t)inext * a.t.pitch + col];
         const uint16_t *prow = a.t.pi + (int64_t)i * a.t.pitch;
         const int32_t *drow = a.t.ds + (int64_t)i * a.t.pitch;
         uint64_t pend = act;
@@ -179,11 +206,9 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
             uint32_t off = 0, bit = 0;
             int32_t dist = 0;
             if (base == 0) {
-                if (k < a.t.K) {
-                    off = j_cur >> 5;
-                    bit = 1u << (j_cur & 31u);
-                    dist = d_cur;
-                }
+                off = off_cur;
+                bit = bit_cur;
+                dist = d_cur;
             } else if (k < a.t.K) {
                 const uint32_t j = prow[k];
                 off = j >> 5;
@@ -202,7 +227,10 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
             }
             pend &= ~__builtin_amdgcn_ballot_w64(found);
         }
-        j_cur = j_nxt;
+        // the next client's operands, computed here so that the wait for
+        // its loads falls after this client's work
+        off_cur = j_nxt >> 5;
+        bit_cur = in_row ? 1u << (j_nxt & 31u) : 0u;
         d_cur = d_nxt;
     }
 

@@ -349,7 +349,10 @@ __device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
     const bool xo = op == OP_XOVER;
     const int pc = xo ? (c ^ (g.NT >> (1 + index % g.lg))) : c;
 
-    // one round of independent loads
+    // One round of independent loads, all issued before anything waits:
+    // every load is unconditional at an address that is always valid
+    // (clamped index; the partner is c itself when no crossover runs) and
+    // values outside the range are masked afterwards.
     const uint64_t gen = g.gs[GS_GEN];
     int sj = 0, sk = 0;
     if (op == OP_SWAP) {
@@ -357,31 +360,52 @@ __device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
         sj = sw[0];
         sk = sw[1];
     }
-    const bool okc = buf(g.ok, in)[c] != 0;
-    const bool okp = xo && buf(g.ok, in)[pc] != 0;
+    const uint8_t okc_b = buf(g.ok, in)[c];
+    const uint8_t okp_b = buf(g.ok, in)[pc];
     const unsigned long long fin = buf(g.fit, in)[c];
     const unsigned long long fpin = buf(g.fit, in)[pc];
-    const bool was_improved = g.improved[c] != 0;
-    unsigned long long f = 0, s = 0, h = 0;
-    for (int t = lane; t < g.TI; t += 64) {
-        const int64_t row = (int64_t)t * g.P;
-        f += g.part[row + c];
-        s += g.spart[row + c];
-        h += g.part[row + pc];
-    }
+    const uint8_t imp_b = g.improved[c];
+    // lane k < CS_COUNT holds counter k of chromosome c
+    unsigned long long *cs = g.cstat + (int64_t)c * CS_COUNT;
+    const unsigned long long cs_old = cs[lane < CS_COUNT ? lane : 0];
+    // partial sums of the first 64 client tiles (straight-line; more tiles
+    // are added below)
+    const bool use0 = lane < g.TI;
+    const int64_t row0 = (int64_t)min(lane, g.TI - 1) * g.P;
+    const unsigned long long pf0 = g.part[row0 + c], ph0 = g.part[row0 + pc];
+    const uint32_t ps0 = g.spart[row0 + c];
     WaveWords cc{}, oc{}, cp{}, opw{};
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
+        if (k == 1 && W <= 64)
+            break;
         const int w = lane + 64 * k;
-        if (w < W) {
-            cc.v[k] = buf(g.cur, in)[(int64_t)c * W + w];
-            oc.v[k] = buf(g.off, in)[(int64_t)c * W + w];
-            if (xo) {
-                cp.v[k] = buf(g.cur, in)[(int64_t)pc * W + w];
-                opw.v[k] = buf(g.off, in)[(int64_t)pc * W + w];
-            }
-        }
+        const int wl = min(w, W - 1);
+        const uint64_t a0 = buf(g.cur, in)[(int64_t)c * W + wl];
+        const uint64_t a1 = buf(g.off, in)[(int64_t)c * W + wl];
+        const uint64_t a2 = buf(g.cur, in)[(int64_t)pc * W + wl];
+        const uint64_t a3 = buf(g.off, in)[(int64_t)pc * W + wl];
+        cc.v[k] = w < W ? a0 : 0ull;
+        oc.v[k] = w < W ? a1 : 0ull;
+        cp.v[k] = w < W ? a2 : 0ull;
+        opw.v[k] = w < W ? a3 : 0ull;
     }
+    if (ga_stopped(g))  // checked once the loads are on their way
+        return;
+    unsigned long long f = use0 ? pf0 : 0ull, h = use0 ? ph0 : 0ull;
+    unsigned long long s = use0 ? ps0 : 0u;
+    for (int t0 = 64; t0 < g.TI; t0 += 64) {
+        const bool use = t0 + lane < g.TI;
+        const int64_t row = (int64_t)min(t0 + lane, g.TI - 1) * g.P;
+        const unsigned long long pf = g.part[row + c], ph = g.part[row + pc];
+        const uint32_t ps = g.spart[row + c];
+        f += use ? pf : 0ull;
+        s += use ? ps : 0u;
+        h += use ? ph : 0ull;
+    }
+    const bool okc = okc_b != 0;
+    const bool okp = xo && okp_b != 0;
+    const bool was_improved = imp_b != 0;
 
     // the operator's draws, while the loads are in flight
     int r1 = 0, quota = 0, lo = 0, hi = m - 1, move = 0;
@@ -421,23 +445,25 @@ __device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
             cur[lane + 64 * k] = A.v[k];
     const bool mut_prev = prev == OP_MUT || prev == OP_SWAP;
     const bool improved = was_improved || (mut_prev && take);
+    // this stage's counter increments, lane k for counter k
+    unsigned long long cs_inc = 0;
+    if (okc) {
+        cs_inc += lane == CS_EVALS ? 1ull : 0ull;
+        cs_inc += lane == CS_SCAN ? scan : 0ull;
+    }
+    if (take && prev == OP_XOVER)
+        cs_inc += lane == CS_XO_TAKEN ? 1ull : 0ull;
+    if (take && mut_prev)
+        cs_inc += lane == (prev == OP_MUT ? CS_MUT_TAKEN : CS_SWAP_TAKEN) ? 1ull : 0ull;
+    if (prev == OP_SWAP && okc)
+        cs_inc += lane == CS_SWAP_TRIED ? 1ull : 0ull;
     if (lane == 0) {
         buf(g.fit, out)[c] = take ? fo : fin;
-        unsigned long long *cs = g.cstat + (int64_t)c * CS_COUNT;
-        if (okc) {
-            cs[CS_EVALS] += 1;
-            cs[CS_SCAN] += scan;
-        }
-        if (take && prev == OP_XOVER)
-            cs[CS_XO_TAKEN] += 1;
-        if (take && mut_prev) {
-            cs[prev == OP_MUT ? CS_MUT_TAKEN : CS_SWAP_TAKEN] += 1;
+        if (take && mut_prev)
             g.improved[c] = 1;
-        }
         if (prev == OP_SWAP && okc) {
             // training tuple of attempt index - 1: exact change of cost,
             // normalised by the parent's cost per open facility, clamped
-            cs[CS_SWAP_TRIED] += 1;
             const int64_t slot =
                 ((int64_t)(gen % (uint64_t)g.H) * g.L + (index - 1)) * g.P + c;
             const long long delta = (long long)fo - (long long)fin;
@@ -455,8 +481,8 @@ __device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
     if (xo) {
         const WaveWords B = ptake ? opw : cp;
         ok = crossover_wave(A, B, F, W, r1, quota, lane);
-        if (lane == 0 && !ok)
-            g.cstat[(int64_t)c * CS_COUNT + CS_XO_FAIL] += 1;
+        if (!ok)
+            cs_inc += lane == CS_XO_FAIL ? 1ull : 0ull;
     } else if (op == OP_MUT && !improved) {
         ok = mutate_wave(A, F, W, m, lo, hi, move, lane);
     } else if (op == OP_SWAP && !improved) {
@@ -476,6 +502,8 @@ __device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
     }
     if (lane == 0)
         buf(g.ok, out)[c] = ok ? 1 : 0;
+    if (lane < CS_COUNT && cs_inc != 0ull)
+        cs[lane] = cs_old + cs_inc;
 }
 
 // Reduce (cost, index) pairs of a workgroup to the least cost, lowest index

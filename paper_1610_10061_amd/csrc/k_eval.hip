@@ -13,9 +13,8 @@ __global__ __launch_bounds__(kEvalTile *kEvalWaves) void k_eval(EvalArgs a)
 {
     __shared__ uint32_t smask[kEvalTile * WD];
     __shared__ unsigned long long sred[2 * kEvalWaves * kEvalTile];
-    // A stopped GA run enqueues no-op generations: evaluate nothing.
-    if (a.done && *a.done)
-        return;
+    // (A stopped GA run enqueues no-op generations: eval_tile checks the
+    // stop flag once its loads are on their way.)
     // All chromosome tiles of one client tile on one XCD (workgroups are
     // dealt to the 8 XCDs round-robin).
     const int ntiles = a.tiles_c * a.tiles_i;

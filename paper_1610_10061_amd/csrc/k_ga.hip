@@ -30,9 +30,9 @@ __global__ __launch_bounds__(64 * kGaWaves) void k_stage(GaArgs g, int in,
 {
     const int wave = wave_id(), lane = threadIdx.x & 63;
     const int c = blockIdx.x * kGaWaves + wave;
-    if (c >= g.P || ga_stopped(g))
+    if (c >= g.P)
         return;
-    ga_stage_one(g, c, lane, in, prev, op, index);
+    ga_stage_one(g, c, lane, in, prev, op, index);  // checks the stop flag itself
 }
 
 // Group best per workgroup; the last workgroup to finish does the global
