@@ -467,6 +467,7 @@ def main():
     def step(seed, record):
         inst = pm.Instance(d_dev, p, stream)
         ga = pm.GA(inst, P, NT, G, seed)
+        tile = ga.autotune(stream)  # timed once per process, then cached
         # events bracket the evaluation launches of the first PROFILE_GENS
         # generations only: an event between every pair of kernels would
         # slow the whole run down
@@ -482,7 +483,7 @@ def main():
         ga.close()
         inst.close()
         if record is not None:
-            record.append((stats, prof, cost))
+            record.append((stats, prof, cost, tile))
 
     for w in range(args.warmup):
         log(f"warmup step {w}")
@@ -492,12 +493,12 @@ def main():
     t0 = time.perf_counter()
     for k in range(args.steps):
         step(k, rec)
-        log(f"step {k} done: best {rec[-1][2]}")
+        log(f"step {k} done: best {rec[-1][2]} (tile {rec[-1][3]} clients)")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
 
-    pairs = sum(s["pair_evals"] for s, _, _ in rec)
-    profs = [pr for _, pr, _ in rec if pr]
+    pairs = sum(r[0]["pair_evals"] for r in rec)
+    profs = [r[1] for r in rec if r[1]]
     ev_ms = sum(pr["eval_ms"] for pr in profs)
     ev_n = sum(pr["eval_launches"] for pr in profs)
     ev_bytes = sum(pr["eval_bytes"] for pr in profs)
@@ -531,7 +532,8 @@ def main():
             "bytes_per_launch": ev_bytes / max(ev_n, 1),
             "sampled": f"evaluation launches of the first {PROFILE_GENS} generations of each timed step",
         },
-        "best_costs": [int(c) for _, _, c in rec],
+        "best_costs": [int(r[2]) for r in rec],
+        "eval_tile_clients": rec[0][3] if rec else None,
     }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle ...")

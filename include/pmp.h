@@ -195,7 +195,7 @@ PMP_API void pmp_ga_destroy(pmp_ga *ga);
 /* ---------------------------------------------------------------------------
  * pmp_ga_autotune (not in the paper) - choose the evaluation tile of a run:
  * how many clients one workgroup of the evaluation kernel takes (its 64
- * chromosomes are fixed, one per lane).  Candidates 4..128 are timed on a
+ * chromosomes are fixed, one per lane).  Candidates 4, 8, 12, ..., 128 are timed on a
  * generation-0 population of this run with HIP events; the fastest is kept
  * and remembered for runs of similar shape (n, m/p, W, P) in this process.
  * Results do not depend on the choice (integer sums).  Call it before the

@@ -59,22 +59,30 @@ __device__ __forceinline__ long long scan_all(const Tables &t, const uint32_t *s
     long long f = 0;
     const int col = lane < t.K ? lane : t.K - 1;
     const int last = t.n - 1;
+    // Row offsets are computed in vector registers (the row index is copied
+    // into one): per client a multiply-add there instead of several 64-bit
+    // scalar instructions, which the walk is short of.
+    auto entry = [&](int i) -> int64_t {
+        int iv;
+        asm volatile("v_mov_b32 %0, %1" : "=v"(iv) : "s"(i));
+        return (int64_t)min(iv, last) * t.pitch + col;
+    };
     int fac[kPrefetch];
     int32_t dist[kPrefetch];
 #pragma unroll
     for (int d = 0; d < kPrefetch; ++d) {
-        const int i = min(wave + kLearnWaves * d, last);
-        fac[d] = t.pi[(int64_t)i * t.pitch + col];
-        dist[d] = t.ds[(int64_t)i * t.pitch + col];
+        const int64_t e = entry(wave + kLearnWaves * d);
+        fac[d] = t.pi[e];
+        dist[d] = t.ds[e];
     }
     for (int i0 = wave; i0 < t.n; i0 += step) {
         int nfac[kPrefetch];
         int32_t ndist[kPrefetch];
 #pragma unroll
         for (int d = 0; d < kPrefetch; ++d) {
-            const int i = min(i0 + step + kLearnWaves * d, last);
-            nfac[d] = t.pi[(int64_t)i * t.pitch + col];
-            ndist[d] = t.ds[(int64_t)i * t.pitch + col];
+            const int64_t e = entry(i0 + step + kLearnWaves * d);
+            nfac[d] = t.pi[e];
+            ndist[d] = t.ds[e];
         }
 #pragma unroll
         for (int d = 0; d < kPrefetch; ++d) {

@@ -65,31 +65,20 @@ __device__ __forceinline__ bool mask_bit(const uint32_t *smask, int f)
 
 // Add one Pi' entry's terms to its slot: position pos of client i's row
 // (facility's slot sl >= 0, distance dist), first / second open positions
-// s1 / s2 (s2 = -1: none inside the row), costs c1 / c2.
+// s1 / s2 (s2 = -1: none inside the row), costs c1 / c2.  Branch-free: the
+// counter and sum are chosen by selects, and the first open facility's loss
+// term is a third add (of zero for the other positions).
 __device__ __forceinline__ void add_terms(SlotBins &B, int sl, int pos, int s1, int s2,
                                           int32_t c1, int32_t c2, int32_t dist)
 {
+    const bool upto1 = pos <= s1, first = pos == s1, second = pos == s2;
     // counts: ahead and first open -> a; between and second open -> dd
-    atomicAdd(pos <= s1 ? &B.a[sl] : &B.dd[sl], 1u);
+    atomicAdd(upto1 ? &B.a[sl] : &B.dd[sl], 1u);
     // sums: ahead -> gain, first -> served, second -> c2share, between -> bgain
-    unsigned long long *sum;
-    int32_t v;
-    if (pos < s1) {
-        sum = &B.b[sl];
-        v = c1 - dist;
-    } else if (pos == s1) {
-        sum = &B.b[sl];
-        v = c1;
-    } else if (pos == s2) {
-        sum = &B.e[sl];
-        v = c2 - c1;
-    } else {
-        sum = &B.cc[sl];
-        v = c2 - dist;
-    }
+    unsigned long long *sum = upto1 ? &B.b[sl] : (second ? &B.e[sl] : &B.cc[sl]);
+    const int32_t v = pos < s1 ? c1 - dist : (first ? c1 : (second ? c2 - c1 : c2 - dist));
     atomicAdd(sum, (unsigned long long)v);
-    if (pos == s1)
-        atomicAdd(&B.cc[sl], (unsigned long long)(c2 - c1));  // loss
+    atomicAdd(&B.cc[sl], first ? (unsigned long long)(c2 - c1) : 0ull);  // loss
 }
 
 // Walk client i's row (its first chunk already loaded: fac0/dist0 = entry

@@ -1092,7 +1092,7 @@ pmp_status pmp_ga_autotune(pmp_ga *ga, int32_t *chosen, void *stream)
         // a generation-0 population to time the evaluation on
         GaArgs g = ga->args();
         HIP_TRY(launch_ga_init(g, s));
-        const int cands[] = {4, 8, 16, 32, 64, 128};
+        const int cands[] = {4, 8, 12, 16, 24, 32, 48, 64, 96, 128};
         const int max_ti = (n + 3) / 4;
         unsigned long long *part = nullptr;
         uint32_t *spart = nullptr;
