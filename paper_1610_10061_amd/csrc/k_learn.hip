@@ -1,22 +1,22 @@
-// Learned swap proposal (not in the paper): feature gathering, candidate
-// scoring on the MFMA units, ranking, and the first scored swap of every
-// chromosome; plus the per-instance static feature sums.
-//
-// k_propose runs once per generation, after the crossover stages, with one
-// workgroup per chromosome:
-//  1. C swap candidates (j open, k closed): candidate t draws r_j uniform in
-//     [0, p) and r_k uniform in [0, m - p) from its own Philox stream
-//     (tag TAG_PROPOSE, stage t) and takes the r_j-th open and the r_k-th
-//     closed facility in index order;
-//  2. one walk over all clients gathers the slot sums of the (at most 2C)
-//     candidate facilities (learn_device.hpp);
-//  3. input row t = [16 features of j_t | 16 features of k_t] in BF16, and
-//     the network's score (the predicted normalised change of the cost);
-//  4. candidates are ranked by score (ties: lower t); mutation attempt a < L
-//     takes rank a, or with probability explore/1000 (draws of stream
-//     TAG_EXPLORE, stage a) a candidate drawn uniformly;
-//  5. the attempts' swaps and input rows go to the GA (swap list, replay
-//     ring), and attempt 0's offspring is written for evaluation.
+// Learned swap proposal (not in the paper), once per generation after the
+// crossover stages, in three launches:
+//  1. k_prop_cand: C swap candidates per chromosome (j open, k closed):
+//     candidate t draws r_j uniform in [0, p) and r_k uniform in [0, m - p)
+//     from its own Philox stream (tag TAG_PROPOSE, stage t) and takes the
+//     r_j-th open and the r_k-th closed facility in index order;
+//  2. k_prop_walk: one walk over all clients gathers the slot sums of the
+//     (at most 2C) candidate facilities of every chromosome
+//     (learn_device.hpp);
+//  3. k_prop_score: input row t = [16 features of j_t | 16 features of k_t]
+//     in BF16 and the network's score (the predicted normalised change of
+//     the cost); candidates ranked by score (ties: lower t); mutation
+//     attempt a < L takes rank a or, with probability explore/1000 (draws of
+//     stream TAG_EXPLORE, stage a), a candidate drawn uniformly; the swaps
+//     and input rows go to the GA (swap list, training ring), and attempt
+//     0's offspring is written for evaluation.
+// Also here: the full feature table of pmp_features and the per-instance
+// static sums.
+#include "eval_device.hpp"
 #include "learn_device.hpp"
 #include "ga_device.hpp"
 #include "mlp.hpp"
@@ -178,117 +178,318 @@ __global__ __launch_bounds__(kLearnThreads) void k_features(Tables t, const uint
     }
 }
 
-struct ProposeLds {
-    uint64_t smask[kMaxWords / 2];  // m <= PMP_MAX_LEARNED_FACILITIES
-    uint8_t slotmap[PMP_MAX_LEARNED_FACILITIES];
-    SlotBins B;
-    int32_t pre[kMaxWords / 2];     // inclusive prefix of open counts per word
+// ---------------------------------------------------------------------------
+// Proposal, step 1 (one wave per chromosome): the C candidates and the bitmap
+// of candidate facilities with the number of candidate facilities before
+// each of its words (a facility's slot is that count plus the candidate bits
+// below it in its word).
+// ---------------------------------------------------------------------------
+constexpr int kCandWaves = 4;
+
+__global__ __launch_bounds__(64 * kCandWaves) void k_prop_cand(LearnArgs A, int out)
+{
+    __shared__ unsigned long long sb[kCandWaves][64];
+    const GaArgs &g = A.g;
+    const int wave = wave_id(), lane = threadIdx.x & 63;
+    const int c = blockIdx.x * kCandWaves + wave;
+    if (c >= g.P)
+        return;
+    const Tables &t = g.t;
+    const int W = t.W, m = t.m, p = t.p, C = A.C;
+    const uint64_t gen = g.gs[GS_GEN];
+    const uint64_t w0 = buf(g.cur, out)[(int64_t)c * W + min(lane, W - 1)];
+    if (ga_stopped(g))
+        return;
+    const uint64_t word = lane < W ? w0 : 0ull;
+    const uint32_t inc = wave_scan_incl((uint32_t)__builtin_popcountll(word), lane);
+    // closed facilities up to and including word w
+    const int nbits = lane < W ? min(64, m - 64 * lane) : 0;
+    const uint32_t cinc = (uint32_t)min(64 * (lane + 1), m) - inc;
+    const uint64_t valid = nbits >= 64 ? ~0ull : ((1ull << nbits) - 1ull);
+    const uint64_t cword = ~word & valid;
+
+    PhiloxStream st(g.seed, ROLE_EVOLVE, gen, (uint64_t)c, TAG_PROPOSE, (uint64_t)lane);
+    const uint32_t rj = (uint32_t)st.below((uint64_t)p);
+    const uint32_t rk = (uint32_t)st.below((uint64_t)(m - p));
+    // first word whose inclusive count exceeds the rank (every lane takes part
+    // in every shuffle)
+    int wj = 0, wk = 0;
+#pragma unroll
+    for (int b = 32; b > 0; b >>= 1) {
+        const int qj = min(wj + b - 1, 63), qk = min(wk + b - 1, 63);
+        const uint32_t vj = (uint32_t)__shfl((int)inc, qj);
+        const uint32_t vk = (uint32_t)__shfl((int)cinc, qk);
+        if (wj + b - 1 < W && vj <= rj)
+            wj += b;
+        if (wk + b - 1 < W && vk <= rk)
+            wk += b;
+    }
+    wj = min(wj, W - 1);
+    wk = min(wk, W - 1);
+    // unconditional shuffles (a lane outside the active set reads as 0)
+    const uint32_t pj = (uint32_t)__shfl((int)inc, max(wj - 1, 0));
+    const uint32_t pk = (uint32_t)__shfl((int)cinc, max(wk - 1, 0));
+    const uint32_t bj = wj > 0 ? pj : 0u;
+    const uint32_t bk = wk > 0 ? pk : 0u;
+    const uint64_t xj = (uint64_t)(uint32_t)__shfl((int)(uint32_t)word, wj) |
+                        ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(word >> 32), wj) << 32);
+    const uint64_t xk = (uint64_t)(uint32_t)__shfl((int)(uint32_t)cword, wk) |
+                        ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(cword >> 32), wk) << 32);
+    const int j = wj * 64 + select_bit(xj, (int)(rj - bj));
+    const int k = wk * 64 + select_bit(xk, (int)(rk - bk));
+
+    // candidate-facility bitmap
+    sb[wave][lane] = 0ull;
+    wave_lds_sync();
+    if (lane < C) {
+        atomicOr(&sb[wave][j >> 6], 1ull << (j & 63));
+        atomicOr(&sb[wave][k >> 6], 1ull << (k & 63));
+        int32_t *cd = A.cand + ((int64_t)c * C + lane) * 2;
+        cd[0] = j;
+        cd[1] = k;
+    }
+    wave_lds_sync();
+    const uint64_t cb = sb[wave][lane];
+    const uint32_t cpc = (uint32_t)__builtin_popcountll(cb);
+    const uint32_t cex = wave_scan_incl(cpc, lane) - cpc;
+    if (lane < W) {
+        A.cbits[(int64_t)c * W + lane] = cb;
+        A.cpre[(int64_t)c * W + lane] = (uint8_t)cex;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Proposal, step 2: the walk.  A workgroup takes CH chromosomes
+// (masks, candidate bitmaps, slot bases and slot sums in LDS) and every
+// client; each of its NW waves takes clients wave, wave + NW, ...,
+// the first 64-entry chunk of kWalkAhead clients in flight.  Lane l holds
+// entry l of the chunk; for each chromosome one LDS read per lane and a
+// ballot give the open positions in the chunk; with two or more, s1 and s2
+// are the two lowest, and the lanes up to s2 whose facility is a candidate
+// of that chromosome add their terms to its slot sums (LDS integer atomics:
+// deterministic).  Rows with fewer than two open facilities in the first
+// chunk take the general path.  The sums are stored once at the end.
+// ---------------------------------------------------------------------------
+constexpr int kWalkAhead = 4;
+
+template <int CH>
+struct WalkLds {
+    uint64_t mask[CH][kMaxWords / 2];
+    uint64_t cb[CH][kMaxWords / 2];
+    uint8_t cp[CH][kMaxWords / 2];
+    SlotBins bins[CH];
+};
+
+template <int CH>
+__device__ __forceinline__ int walk_slot(const WalkLds<CH> &L, int g, int fac)
+{
+    const uint64_t w = L.cb[g][fac >> 6];
+    const int fb = fac & 63;
+    return ((w >> fb) & 1ull) ? L.cp[g][fac >> 6] + __builtin_popcountll(w & ((1ull << fb) - 1ull))
+                              : -1;
+}
+
+template <int CH>
+struct SlotFnLds {  // slot of a facility for chromosome g of the walk's LDS
+    const WalkLds<CH> *L;
+    int g;
+    __device__ __forceinline__ int operator()(int f) const { return walk_slot(*L, g, f); }
+};
+
+// CH chromosomes per workgroup, NW waves.
+template <int CH, int NW>
+__global__ __launch_bounds__(64 * NW) void k_prop_walk(LearnArgs A, int out)
+{
+    __shared__ WalkLds<CH> L;
+    const GaArgs &g = A.g;
+    const Tables &t = g.t;
+    const int c0 = blockIdx.x * CH, rows = min(CH, g.P - c0);
+    const int lane = threadIdx.x & 63, wave = wave_id();
+    const int W = t.W, K = t.K;
+    // loads first: masks, bitmaps, slot bases (clamped, unconditional) and
+    // the first clients' chunks
+    const uint64_t *cur = buf(g.cur, out);
+    for (int e = threadIdx.x; e < CH * (kMaxWords / 2); e += (64 * NW)) {
+        const int cc = e / (kMaxWords / 2), w = e - cc * (kMaxWords / 2);
+        const int64_t src = (int64_t)(c0 + min(cc, rows - 1)) * W + min(w, W - 1);
+        const uint64_t mv = cur[src], cv = A.cbits[src];
+        const uint8_t pv = A.cpre[src];
+        const bool in = cc < rows && w < W;
+        L.mask[cc][w] = in ? mv : 0ull;
+        L.cb[cc][w] = in ? cv : 0ull;
+        L.cp[cc][w] = in ? pv : (uint8_t)0;
+    }
+    for (int e = threadIdx.x; e < CH * kSlots; e += (64 * NW)) {
+        SlotBins &B = L.bins[e / kSlots];
+        const int sl = e % kSlots;
+        B.a[sl] = 0;
+        B.dd[sl] = 0;
+        B.b[sl] = 0;
+        B.cc[sl] = 0;
+        B.e[sl] = 0;
+    }
+    const int col = lane < K ? lane : K - 1;
+    const int last = t.n - 1;
+    constexpr int step = NW * kWalkAhead;
+    int fac[kWalkAhead];
+    int32_t dist[kWalkAhead];
+#pragma unroll
+    for (int d = 0; d < kWalkAhead; ++d) {
+        const int64_t e = (int64_t)min(wave + NW * d, last) * t.pitch + col;
+        fac[d] = t.pi[e];
+        dist[d] = t.ds[e];
+    }
+    if (ga_stopped(g))
+        return;
+    __syncthreads();
+    const bool valid = lane < K;
+    for (int i0 = wave; i0 < t.n; i0 += step) {
+        // this batch's operands (loaded one batch ago), taken before the next
+        // batch's loads are issued so that no wait falls inside the work
+        int fw[kWalkAhead], fb[kWalkAhead];
+        int32_t dv[kWalkAhead];
+#pragma unroll
+        for (int d = 0; d < kWalkAhead; ++d) {
+            fw[d] = fac[d] >> 6;
+            fb[d] = fac[d] & 63;
+            dv[d] = dist[d];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int d = 0; d < kWalkAhead; ++d) {
+            const int64_t e = (int64_t)min(i0 + step + NW * d, last) * t.pitch + col;
+            fac[d] = t.pi[e];
+            dist[d] = t.ds[e];
+        }
+        uint32_t slow = 0;  // (client d, chromosome cc) pairs for the general path
+#pragma unroll
+        for (int d = 0; d < kWalkAhead; ++d) {
+            if (i0 + NW * d >= t.n)
+                break;
+            const uint64_t below = (1ull << fb[d]) - 1ull;
+            for (int cc = 0; cc < rows; ++cc) {
+                const uint64_t mw = L.mask[cc][fw[d]];
+                const uint64_t cw = L.cb[cc][fw[d]];
+                const int cpv = L.cp[cc][fw[d]];
+                const bool open = (((mw >> fb[d]) & 1ull) != 0ull) & valid;
+                const uint64_t bits = __builtin_amdgcn_ballot_w64(open);
+                const uint64_t rest = bits & (bits - 1ull);
+                if (rest == 0ull) {
+                    slow |= 1u << (d * CH + cc);
+                    continue;
+                }
+                const int s1 = (int)__builtin_ctzll(bits);
+                const int s2 = (int)__builtin_ctzll(rest);
+                const int32_t c1 = __builtin_amdgcn_readlane(dv[d], s1);
+                const int32_t c2 = __builtin_amdgcn_readlane(dv[d], s2);
+                const bool hit = (((cw >> fb[d]) & 1ull) != 0ull) & (lane <= s2);
+                if (hit) {
+                    const int sl = cpv + __builtin_popcountll(cw & below);
+                    SlotBins &B = L.bins[cc];
+                    const bool upto1 = lane <= s1, first = lane == s1, second = lane == s2;
+                    int32_t v = c2 - dv[d];           // between
+                    v = second ? c2 - c1 : v;
+                    v = first ? c1 : v;
+                    v = lane < s1 ? c1 - dv[d] : v;   // ahead
+                    atomicAdd(upto1 ? &B.a[sl] : &B.dd[sl], 1u);
+                    atomicAdd(upto1 ? &B.b[sl] : (second ? &B.e[sl] : &B.cc[sl]),
+                              (unsigned long long)v);
+                    atomicAdd(&B.cc[sl], first ? (unsigned long long)(c2 - c1) : 0ull);
+                }
+            }
+        }
+        // rows whose second open facility lies past the first chunk (rare)
+        while (slow) {
+            const int bit = (int)__builtin_ctz(slow);
+            slow &= slow - 1u;
+            const int d = bit / CH, cc = bit - d * CH;
+            int32_t dcur = dv[0];
+            int fcur = fw[0] * 64 + fb[0];
+#pragma unroll
+            for (int q = 1; q < kWalkAhead; ++q)
+                if (q == d) {
+                    dcur = dv[q];
+                    fcur = fw[q] * 64 + fb[q];
+                }
+            const SlotFnLds<CH> fn{&L, cc};
+            if (scan_client(t, i0 + NW * d, fcur, dcur,
+                            reinterpret_cast<const uint32_t *>(L.mask[cc]), fn, L.bins[cc],
+                            lane) < 0 &&
+                lane == 0)
+                atomicOr(g.err, ERR_SCAN_OVERRUN);
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < rows * kSlots; e += (64 * NW)) {
+        const SlotBins &B = L.bins[e / kSlots];
+        const int sl = e % kSlots;
+        const int64_t o = (int64_t)(c0 + e / kSlots) * kSlots + sl;
+        A.sums.a[o] = B.a[sl];
+        A.sums.dd[o] = B.dd[sl];
+        A.sums.b[o] = B.b[sl];
+        A.sums.cc[o] = B.cc[sl];
+        A.sums.e[o] = B.e[sl];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Proposal, step 3 (one workgroup per chromosome): input rows from the slot
+// sums, scores, ranking, the attempts' picks, ring rows and attempt 0's
+// offspring.
+// ---------------------------------------------------------------------------
+struct ScoreLds {
+    uint64_t cb[kMaxWords / 2];
+    uint8_t cp[kMaxWords / 2];
     int32_t cj[PMP_MAX_CANDIDATES], ck[PMP_MAX_CANDIDATES];
     int32_t order[PMP_MAX_CANDIDATES];
     float score[PMP_MAX_CANDIDATES];
     __align__(16) uint16_t x[PMP_MAX_CANDIDATES * kXStride];
     __align__(16) uint16_t h[kMlpWaves][16 * kHStride];
-    long long sf[kLearnWaves];
-    int scount, sbad;
 };
 
-__global__ __launch_bounds__(kLearnThreads) void k_propose(LearnArgs A, int in)
+__global__ __launch_bounds__(64 * kMlpWaves) void k_prop_score(LearnArgs A, int out)
 {
-    __shared__ ProposeLds L;
+    __shared__ ScoreLds L;
     const GaArgs &g = A.g;
     const int c = blockIdx.x;
-    if (c >= g.P || ga_stopped(g))
-        return;
-    const int out = in ^ 1;
-    const int wave = wave_id(), lane = threadIdx.x & 63;
     const Tables &t = g.t;
-    const int W = t.W, m = t.m, p = t.p, C = A.C;
+    const int W = t.W, C = A.C;
+    const int wave = wave_id(), lane = threadIdx.x & 63;
     const uint64_t gen = g.gs[GS_GEN];
-
-    bins_clear(L.B);
-    for (int f = threadIdx.x; f < m; f += blockDim.x)
-        L.slotmap[f] = 0xFF;
-    if (threadIdx.x == 0)
-        L.sbad = 0;
-    const uint64_t *mask = buf(g.cur, out) + (int64_t)c * W;
-    if (!load_mask(mask, W, m, p, L.smask, &L.scount)) {
-        if (threadIdx.x == 0)
-            atomicOr(g.err, ERR_POPCOUNT);
+    const unsigned long long f = buf(g.fit, out)[c];
+    if (threadIdx.x < W) {
+        L.cb[threadIdx.x] = A.cbits[(int64_t)c * W + threadIdx.x];
+        L.cp[threadIdx.x] = A.cpre[(int64_t)c * W + threadIdx.x];
+    }
+    if (threadIdx.x < C) {
+        L.cj[threadIdx.x] = A.cand[((int64_t)c * C + threadIdx.x) * 2];
+        L.ck[threadIdx.x] = A.cand[((int64_t)c * C + threadIdx.x) * 2 + 1];
+    }
+    if (ga_stopped(g))
         return;
-    }
-    // 1. candidates (wave 0; lane t draws candidate t)
-    if (wave == 0) {
-        const uint32_t pc = lane < W ? (uint32_t)__builtin_popcountll(L.smask[lane]) : 0u;
-        const uint32_t inc = wave_scan_incl(pc, lane);
-        if (lane < W)
-            L.pre[lane] = (int32_t)inc;
-        wave_lds_sync();
-        if (lane < C) {
-            PhiloxStream st(g.seed, ROLE_EVOLVE, gen, (uint64_t)c, TAG_PROPOSE,
-                            (uint64_t)lane);
-            const int rj = (int)st.below((uint64_t)p);
-            const int rk = (int)st.below((uint64_t)(m - p));
-            // r_j-th open facility: first word whose inclusive count exceeds r_j
-            int lo = 0, hi = W - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (L.pre[mid] > rj)
-                    hi = mid;
-                else
-                    lo = mid + 1;
-            }
-            const int j = lo * 64 + select_bit(L.smask[lo], rj - (lo ? L.pre[lo - 1] : 0));
-            // r_k-th closed facility
-            lo = 0;
-            hi = W - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (min(64 * (mid + 1), m) - L.pre[mid] > rk)
-                    hi = mid;
-                else
-                    lo = mid + 1;
-            }
-            const int before = lo ? 64 * lo - L.pre[lo - 1] : 0;
-            const int nbits = min(64, m - 64 * lo);
-            const uint64_t valid = nbits == 64 ? ~0ull : ((1ull << nbits) - 1ull);
-            const int k = lo * 64 + select_bit(~L.smask[lo] & valid, rk - before);
-            L.cj[lane] = j;
-            L.ck[lane] = k;
-            L.slotmap[j] = (uint8_t)(2 * lane);
-            L.slotmap[k] = (uint8_t)(2 * lane + 1);
-        }
-    }
     __syncthreads();
-    // 2. gather
-    bool bad = false;
-    const long long f = scan_all(t, reinterpret_cast<const uint32_t *>(L.smask),
-                                 MapSlot{L.slotmap}, L.B, wave, lane, &bad);
-    if (bad)
-        L.sbad = 1;
     FeatCtx ctx;
     ctx.n = t.n;
-    ctx.m = m;
-    ctx.p = p;
+    ctx.m = t.m;
+    ctx.p = t.p;
     ctx.near_len = A.near_len;
     ctx.total = A.total;
     ctx.colsum = A.colsum;
     ctx.nearc = A.nearc;
     ctx.gen_frac = (float)((double)gen / (double)g.generations);
-    ctx.f = block_cost(f, L.sf, wave, lane);
-    if (L.sbad) {
-        if (threadIdx.x == 0)
-            atomicOr(g.err, ERR_SCAN_OVERRUN);
-        return;
-    }
-    // 3. input rows: thread (row, quarter) writes 8 inputs
-    if (threadIdx.x < 4 * PMP_MAX_CANDIDATES) {
+    ctx.f = (int64_t)f;
+    // input rows: thread (row, quarter) writes 8 inputs; j is open, k closed
+    {
         const int row = threadIdx.x >> 2, qtr = threadIdx.x & 3;
         uint16_t v8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         if (row < C) {
             const int fac = qtr < 2 ? L.cj[row] : L.ck[row];
-            const int sl = L.slotmap[fac];
+            const uint64_t w = L.cb[fac >> 6];
+            const int sl = L.cp[fac >> 6] + __builtin_popcountll(w & ((1ull << (fac & 63)) - 1ull));
+            const int64_t o = (int64_t)c * kSlots + sl;
             float v[kFeatures];
-            features16(ctx, L.B, sl == 0xFF ? -1 : sl, fac, qtr < 2, v);
+            features16_sums(ctx, (double)A.sums.a[o], (double)A.sums.dd[o], (double)A.sums.b[o],
+                            (double)A.sums.cc[o], (double)A.sums.e[o], fac, qtr < 2, v);
 #pragma unroll
             for (int e = 0; e < 8; ++e)
                 v8[e] = f32_to_bf16(v[(qtr & 1) * 8 + e]);
@@ -298,8 +499,7 @@ __global__ __launch_bounds__(kLearnThreads) void k_propose(LearnArgs A, int in)
         d[1] = uint2{v8[4] | ((uint32_t)v8[5] << 16), v8[6] | ((uint32_t)v8[7] << 16)};
     }
     __syncthreads();
-    // scores (16 rows per wave)
-    if (wave < kMlpWaves) {
+    {
         f32x4 z1[8], z2[8];
         float y[4];
         mlp_forward16(A.net, L.x + wave * 16 * kXStride, L.h[wave], lane, z1, z2, y);
@@ -309,7 +509,7 @@ __global__ __launch_bounds__(kLearnThreads) void k_propose(LearnArgs A, int in)
                 L.score[wave * 16 + 4 * (lane >> 4) + i] = y[i];
     }
     __syncthreads();
-    // 4. rank (wave 0): rank of t = #{u : (y_u, u) < (y_t, t)}, NaN as +inf
+    // rank (wave 0): rank of t = #{u : (y_u, u) < (y_t, t)}, NaN as +inf
     if (wave == 0) {
         float y = lane < C ? L.score[lane] : __builtin_inff();
         if (lane < C)
@@ -324,10 +524,9 @@ __global__ __launch_bounds__(kLearnThreads) void k_propose(LearnArgs A, int in)
         if (lane < C)
             L.order[rank] = lane;
         wave_lds_sync();
-        // 5. the attempts' picks, swaps and replay rows
+        // the attempts' picks, swaps and ring rows
         if (lane < A.L) {
-            PhiloxStream st(g.seed, ROLE_EVOLVE, gen, (uint64_t)c, TAG_EXPLORE,
-                            (uint64_t)lane);
+            PhiloxStream st(g.seed, ROLE_EVOLVE, gen, (uint64_t)c, TAG_EXPLORE, (uint64_t)lane);
             const int e = (int)st.below(1000);
             const int u = (int)st.below((uint64_t)C);
             const int pick = e < A.explore ? u : L.order[lane];
@@ -335,8 +534,7 @@ __global__ __launch_bounds__(kLearnThreads) void k_propose(LearnArgs A, int in)
             int32_t *sw = A.swaps + ((int64_t)c * A.L + lane) * 2;
             sw[0] = j;
             sw[1] = k;
-            const int64_t slot =
-                ((int64_t)(gen % (uint64_t)A.H) * A.L + lane) * g.P + c;
+            const int64_t slot = ((int64_t)(gen % (uint64_t)A.H) * A.L + lane) * g.P + c;
             const uint2 *src = reinterpret_cast<const uint2 *>(L.x + pick * kXStride);
             uint2 *dst = reinterpret_cast<uint2 *>(A.rep_x + slot * kIn);
 #pragma unroll
@@ -345,7 +543,7 @@ __global__ __launch_bounds__(kLearnThreads) void k_propose(LearnArgs A, int in)
             A.rep_jk[slot * 2] = j;
             A.rep_jk[slot * 2 + 1] = k;
             A.rep_d[slot * 2] = 0;
-            A.rep_d[slot * 2 + 1] = ctx.f;
+            A.rep_d[slot * 2 + 1] = (long long)f;
             A.rep_t[slot] = 0.f;
             A.rep_w[slot] = 0.f;
         }
@@ -354,9 +552,10 @@ __global__ __launch_bounds__(kLearnThreads) void k_propose(LearnArgs A, int in)
     // attempt 0's offspring
     const int32_t *sw0 = A.swaps + (int64_t)c * A.L * 2;
     const int j0 = sw0[0], k0 = sw0[1];
+    const uint64_t *mask = buf(g.cur, out) + (int64_t)c * W;
     uint64_t *F = buf(g.off, out) + (int64_t)c * W;
     for (int w = threadIdx.x; w < W; w += blockDim.x) {
-        uint64_t v = L.smask[w];
+        uint64_t v = mask[w];
         if ((j0 >> 6) == w)
             v ^= 1ull << (j0 & 63);
         if ((k0 >> 6) == w)
@@ -366,6 +565,7 @@ __global__ __launch_bounds__(kLearnThreads) void k_propose(LearnArgs A, int in)
     if (threadIdx.x == 0)
         buf(g.ok, out)[c] = 1;
 }
+
 
 // Column sums of d (int64), rows split over gridDim.y slices.
 __global__ void k_colsum(const int32_t *d, int64_t ld, int n, int m,
@@ -405,9 +605,37 @@ hipError_t launch_features(const Tables &t, const uint64_t *masks, int P, const 
     return hipGetLastError();
 }
 
+template <int CH, int NW>
+hipError_t launch_walk_t(const LearnArgs &a, int out, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_prop_walk<CH, NW>), dim3((a.g.P + CH - 1) / CH), dim3(64 * NW), 0, s,
+                       a, out);
+    return hipGetLastError();
+}
+
+// Walk shape: chromosomes per workgroup x waves (the default keeps eight
+// waves per SIMD resident at P = 1024).
+hipError_t launch_walk(const LearnArgs &a, int out, hipStream_t s)
+{
+    switch (a.walk) {
+    case 1: return launch_walk_t<1, 8>(a, out, s);
+    case 4: return launch_walk_t<4, 16>(a, out, s);
+    default: return launch_walk_t<2, 16>(a, out, s);
+    }
+}
+
 hipError_t launch_propose(const LearnArgs &a, int in, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_propose, dim3(a.g.P), dim3(kLearnThreads), 0, s, a, in);
+    const int out = in ^ 1;
+    hipLaunchKernelGGL(k_prop_cand, dim3((a.g.P + kCandWaves - 1) / kCandWaves),
+                       dim3(64 * kCandWaves), 0, s, a, out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    e = launch_walk(a, out, s);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_prop_score, dim3(a.g.P), dim3(64 * kMlpWaves), 0, s, a, out);
     return hipGetLastError();
 }
 

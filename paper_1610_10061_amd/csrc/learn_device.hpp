@@ -164,18 +164,15 @@ __device__ __forceinline__ float fdiv3(double a, double b, double c)
     return (float)(a * b / c);
 }
 
-// The 16 features of facility j (slot s, or -1 for none gathered).
-__device__ __forceinline__ void features16(const FeatCtx &x, const SlotBins &B, int s,
-                                           int j, bool open, float out[kFeatures])
+// The 16 features of facility j from its five sums (A = count | ahead,
+// D = cnt2 | bcount, Bv = served | gain, Cv = loss | bgain, E = c2share).
+__device__ __forceinline__ void features16_sums(const FeatCtx &x, double A, double D,
+                                                double Bv, double Cv, double E, int j,
+                                                bool open, float out[kFeatures])
 {
     const double n = x.n, m = x.m, p = x.p;
     const double F = x.f > 0 ? (double)x.f : 1.0;
     const double T = x.total > 0 ? (double)x.total : 1.0;
-    const double A = s >= 0 ? (double)B.a[s] : 0.0;
-    const double D = s >= 0 ? (double)B.dd[s] : 0.0;
-    const double Bv = s >= 0 ? (double)B.b[s] : 0.0;
-    const double Cv = s >= 0 ? (double)B.cc[s] : 0.0;
-    const double E = s >= 0 ? (double)B.e[s] : 0.0;
     out[0] = open ? 1.f : 0.f;
     out[1] = open ? fdiv3(A, p, n) : 0.f;
     out[2] = open ? fdiv3(Bv, p, F) : 0.f;
@@ -194,6 +191,21 @@ __device__ __forceinline__ void features16(const FeatCtx &x, const SlotBins &B, 
     out[15] = 1.f;
 }
 
+// The 16 features of facility j (slot s of B, or -1 for none gathered).
+__device__ __forceinline__ void features16(const FeatCtx &x, const SlotBins &B, int s,
+                                           int j, bool open, float out[kFeatures])
+{
+    features16_sums(x, s >= 0 ? (double)B.a[s] : 0.0, s >= 0 ? (double)B.dd[s] : 0.0,
+                    s >= 0 ? (double)B.b[s] : 0.0, s >= 0 ? (double)B.cc[s] : 0.0,
+                    s >= 0 ? (double)B.e[s] : 0.0, j, open, out);
+}
+
+// Slot sums of every chromosome in device memory: kSlots slots each.
+struct SlotSums {
+    uint32_t *a, *dd;             // P x kSlots
+    unsigned long long *b, *cc, *e;
+};
+
 // Arguments of the proposal kernel.
 struct LearnArgs {
     GaArgs g;
@@ -209,10 +221,18 @@ struct LearnArgs {
     long long *rep_d;                  // ring rows x 2
     float *rep_t, *rep_w;              // ring rows
     float *scores;                     // P x C scores of the last proposal
+    int32_t *cand;                     // P x C x 2 candidate swaps (j, k)
+    uint64_t *cbits;                   // P x W candidate-facility bitmaps
+    uint8_t *cpre;                     // P x W slots before each bitmap word
+    SlotSums sums;                     // per chromosome and slot
+    int32_t clients_per_block, tiles_i;  // client tiling of the walk
+    int32_t walk;                      // walk shape (chromosomes per workgroup)
 };
 
 hipError_t launch_features(const Tables &t, const uint64_t *masks, int P, const FeatCtx &ctx,
                            float *out, uint32_t *err, hipStream_t s);
+// The proposal of one generation (candidates, walk, scoring and picks);
+// `in` is the buffer the finished crossover stages read.
 hipError_t launch_propose(const LearnArgs &a, int in, hipStream_t s);
 // Column sums of d and near counts (first L entries of the Pi' rows).
 hipError_t launch_static_sums(const int32_t *d, int64_t ld, int n, int m, const uint16_t *pi,

@@ -216,7 +216,12 @@ struct pmp_ga {
     int32_t *rep_jk = nullptr;
     long long *rep_d = nullptr;
     float *scores = nullptr;
+    int32_t *cand = nullptr;
+    uint64_t *cbits = nullptr;
+    uint8_t *cpre = nullptr;
+    void *sums = nullptr;  // P x kSlots: a, dd (uint32), b, cc, e (uint64)
     unsigned long long *last_trained = nullptr;
+    int walk_shape = 2;  // chromosomes per workgroup of the proposal walk
 
     int64_t ring_rows() const { return (int64_t)LH * LL * prm.population; }
 
@@ -285,6 +290,18 @@ struct pmp_ga {
         a.rep_t = rep_t;
         a.rep_w = rep_w;
         a.scores = scores;
+        a.cand = cand;
+        a.cbits = cbits;
+        a.cpre = cpre;
+        const size_t PS = (size_t)prm.population * kSlots;
+        a.sums.a = (uint32_t *)sums;
+        a.sums.dd = a.sums.a + PS;
+        a.sums.b = (unsigned long long *)(a.sums.dd + PS);
+        a.sums.cc = a.sums.b + PS;
+        a.sums.e = a.sums.cc + PS;
+        a.clients_per_block = cpb;
+        a.tiles_i = TI;
+        a.walk = walk_shape;
         return a;
     }
 
@@ -297,6 +314,12 @@ struct pmp_ga {
         dfree(rep_jk);
         dfree(rep_d);
         dfree(scores);
+        dfree(cand);
+        dfree(cbits);
+        dfree(cpre);
+        if (sums)
+            (void)hipFree(sums);
+        sums = nullptr;
         dfree(last_trained);
     }
 };
@@ -1636,7 +1659,10 @@ pmp_status pmp_ga_set_model(pmp_ga *ga, pmp_model *model, const pmp_learn_params
     const size_t P = ga->prm.population, R = (size_t)H * L * P;
     if (dalloc(&ga->swaps, P * L * 2) || dalloc(&ga->rep_x, R * kIn) || dalloc(&ga->rep_t, R) ||
         dalloc(&ga->rep_w, R) || dalloc(&ga->rep_jk, R * 2) || dalloc(&ga->rep_d, R * 2) ||
-        dalloc(&ga->scores, P * C) || dalloc(&ga->last_trained, 1)) {
+        dalloc(&ga->scores, P * C) || dalloc(&ga->cand, P * C * 2) ||
+        dalloc(&ga->cbits, P * ga->inst->W) || dalloc(&ga->cpre, P * ga->inst->W) ||
+        hipMalloc(&ga->sums, P * kSlots * (2 * sizeof(uint32_t) + 3 * sizeof(uint64_t))) ||
+        dalloc(&ga->last_trained, 1)) {
         ga->free_learned();
         return fail(PMP_ENOMEM, "learned proposal buffers (%zu ring rows)", R);
     }
@@ -1660,6 +1686,7 @@ pmp_status pmp_ga_set_model(pmp_ga *ga, pmp_model *model, const pmp_learn_params
         return fail(PMP_EDEVICE, "learned proposal init: %s", hipGetErrorString(e));
     }
     ga->model = model;
+    ga->walk_shape = env_int("PMP_WALK", 2);
     ga->LC = C;
     ga->LL = L;
     ga->Lexp = q.explore_permille;
