@@ -385,6 +385,84 @@ def bench_e5000(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_g100(args):
+    """G100 (n = m = 100, 200 edges, p = 5; the shape of pmed1): the exact
+    optimum of instance seeds 0-9 by GPU enumeration of all C(100, 5)
+    subsets (the first three cross-checked with the CPU oracle), then the
+    plain GA (population 64, NT 64, 100 generations, GA seed = instance seed)
+    and the learned-proposal GA stepped one generation at a time until their
+    best equals the optimum: generations and wall time to the optimum."""
+    import numpy as np
+    import torch
+    import paper_1610_10061_amd as pm
+    import pmp_inputs as gi
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    rows = []
+    enum_s, pairs = 0.0, 0
+    for s in range(args.g100_instances):
+        d = gi.graph_instance(100, 200, s)
+        inst = pm.Instance(torch.from_numpy(d).cuda(), 5, stream)
+        if s == 0:
+            pm.pmp_exhaustive(inst.handle, stream)  # first use outside the clock
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        opt, mask, count = pm.pmp_exhaustive(inst.handle, stream)
+        enum_s += time.perf_counter() - t0
+        pairs += count * 100
+        row = {"seed": s, "optimum": opt, "subsets": count}
+        if s < 3 and not args.no_cpu_baseline:
+            import oracle
+            t1 = time.perf_counter()
+            ocost, omask, _ = oracle.exhaustive(d, 5)
+            row["oracle_exhaustive_s"] = time.perf_counter() - t1
+            assert ocost == opt and np.array_equal(omask, mask), "enumeration disagrees"
+        for kind in ("plain", "learned"):
+            ga = pm.GA(inst, 64, 64, 100, s)
+            if kind == "learned":
+                model = pm.Model(s)
+                ga.set_model(model, candidates=64, learned_iters=3, explore_permille=50,
+                             train_every=1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            reached = None
+            for gen in range(1, 101):
+                ga.step(1, stream)
+                _, best, _ = ga.best(stream)
+                if best == opt:
+                    reached = (gen, time.perf_counter() - t0)
+                    break
+            row[kind + "_generations"] = reached[0] if reached else None
+            row[kind + "_ms"] = reached[1] * 1e3 if reached else None
+            row[kind + "_best"] = best
+            ga.close()
+        log(json.dumps(row))
+        rows.append(row)
+        inst.close()
+    med = lambda v: float(np.median(v)) if v else None  # noqa: E731
+    pl = [r["plain_ms"] for r in rows if r["plain_ms"] is not None]
+    le = [r["learned_ms"] for r in rows if r["learned_ms"] is not None]
+    out = {
+        "metric": "time to the exact optimum, plain vs learned-proposal GA (G100)",
+        "value": med(pl), "unit": "ms (median over instances that reached it)",
+        "n_gpus": 1, "higher_is_better": False, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "G100: random connected graph n=m=100, 200 edges, weights "
+                               "U{1..100}, APSP int32, p=5, population 64 (NT=64), 100 "
+                               "generations; instance and GA seeds 0-%d" % (args.g100_instances - 1)},
+        "plain_reached": f"{len(pl)}/{len(rows)}", "learned_reached": f"{len(le)}/{len(rows)}",
+        "learned_median_ms": med(le),
+        "plain_median_generations": med([r["plain_generations"] for r in rows
+                                         if r["plain_generations"] is not None]),
+        "learned_median_generations": med([r["learned_generations"] for r in rows
+                                           if r["learned_generations"] is not None]),
+        "enumeration": {"subsets_per_instance": rows[0]["subsets"] if rows else None,
+                        "seconds_per_instance": enum_s / max(len(rows), 1),
+                        "pair_evals_per_s": pairs / enum_s if enum_s else None},
+        "per_instance": rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def oracle_threads():
     import oracle
     return oracle.default_threads()
@@ -400,7 +478,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="no per-launch events (the GA then replays hipGraphs)")
-    ap.add_argument("--workload", choices=["g900", "batch", "learned", "e5000"],
+    ap.add_argument("--g100-instances", type=int, default=10)
+    ap.add_argument("--workload", choices=["g900", "batch", "learned", "e5000", "g100"],
                     default="g900",
                     help="g900: the headline configuration; batch: 256 ragged "
                          "instances in one launch vs one launch per instance; "
@@ -437,6 +516,8 @@ def main():
         return bench_learned(args)
     if args.workload == "e5000":
         return bench_e5000(args)
+    if args.workload == "g100":
+        return bench_g100(args)
 
     import numpy as np
     import torch

@@ -253,6 +253,20 @@ PMP_API pmp_status pmp_solve(const int32_t *d, int32_t n, int32_t m, int32_t p,
                      int64_t *cost, pmp_ga_stats *stats);
 
 /* ---------------------------------------------------------------------------
+ * pmp_exhaustive (not in the paper's method; its ground truth) - the exact
+ * optimum of Eq. (1)-(3) over all C(m, p) open sets, on the GPU: every
+ * p-subset, in lexicographic order of its sorted facility indices, is built
+ * by combinadic unranking and evaluated by the kernel of
+ * pmp_eval_population, in batches.
+ *  best_mask  W words (host; NULL = skip): the lexicographically first open
+ *             set of least cost.
+ *  best_cost  its cost (host; NULL = skip).   count  C(m, p) (NULL = skip).
+ * Synchronous on `stream`.  PMP_EUNSUPPORTED when C(m, p) >= 2^62.
+ * ------------------------------------------------------------------------- */
+PMP_API pmp_status pmp_exhaustive(pmp_instance *inst, uint64_t *best_mask, int64_t *best_cost,
+                                  int64_t *count, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Profiling of the kernels that evaluate fitness inside pmp_ga_step: when
  * enabled, every launch that runs evaluations (the evaluation kernel, or the
  * persistent GA kernel that contains the whole generation) is bracketed by

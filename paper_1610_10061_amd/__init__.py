@@ -26,7 +26,8 @@ __all__ = [
     "pmp_batch_step", "pmp_batch_check", "pmp_batch_destroy",
     "pmp_ga_step_batch", "pmp_features", "pmp_model_create", "pmp_model_get",
     "pmp_model_set", "pmp_model_forward", "pmp_model_grad", "pmp_model_train",
-    "pmp_model_destroy", "pmp_ga_set_model", "pmp_ga_replay", "Instance", "GA",
+    "pmp_model_destroy", "pmp_ga_set_model", "pmp_ga_replay", "pmp_exhaustive",
+    "Instance", "GA",
     "Batch", "Model", "LearnParams", "EXPORTS", "MLP_PARAMS",
 ]
 
@@ -46,7 +47,7 @@ EXPORTS = [
     "pmp_batch_step", "pmp_batch_check", "pmp_batch_destroy", "pmp_ga_step_batch",
     "pmp_features", "pmp_model_create", "pmp_model_get", "pmp_model_set",
     "pmp_model_forward", "pmp_model_grad", "pmp_model_train", "pmp_model_destroy",
-    "pmp_ga_set_model", "pmp_ga_replay",
+    "pmp_ga_set_model", "pmp_ga_replay", "pmp_exhaustive",
 ]
 
 FEATURES = 16
@@ -143,6 +144,7 @@ def lib():
     L.pmp_model_destroy.restype = None
     L.pmp_ga_set_model.argtypes = [_vp, _vp, C.POINTER(LearnParams)]
     L.pmp_ga_replay.argtypes = [_vp, C.POINTER(_i32), _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    L.pmp_exhaustive.argtypes = [_vp, _vp, C.POINTER(_i64), C.POINTER(_i64), _vp]
     L.pmp_status_str.argtypes = [_i32]
     L.pmp_status_str.restype = C.c_char_p
     L.pmp_last_error.argtypes = []
@@ -448,6 +450,16 @@ def pmp_ga_replay(ga, population, candidates, stream=None):
                                                       "delta", "scores")], _stream(stream)),
            "pmp_ga_replay")
     return out
+
+
+def pmp_exhaustive(inst, stream=None):
+    """(best cost, best mask (W words), C(m, p)) by GPU enumeration."""
+    n, m, p, K, W = pmp_instance_info(inst)
+    mask = np.zeros(W, np.uint64)
+    cost, cnt = _i64(), _i64()
+    _check(lib().pmp_exhaustive(inst, mask.ctypes.data_as(_vp), C.byref(cost), C.byref(cnt),
+                                _stream(stream)), "pmp_exhaustive")
+    return cost.value, mask, cnt.value
 
 
 # ------------------------------------------------------- small conveniences

@@ -144,6 +144,14 @@ struct GaArgs {
     int32_t L, H;
 };
 
+// Exhaustive enumeration (k_enum.hip).
+hipError_t launch_unrank(const unsigned long long *binom, int m, int p, int W,
+                         unsigned long long r0, int count, uint64_t *masks, hipStream_t s);
+hipError_t launch_argmin(const unsigned long long *fit, int count, unsigned long long *best_cost,
+                         int *best_idx, hipStream_t s);
+hipError_t launch_fold(const unsigned long long *bc, const int *bi, int nblk,
+                       unsigned long long r0, unsigned long long *run, hipStream_t s);
+
 hipError_t launch_ga_init(const GaArgs &g, hipStream_t s);
 hipError_t launch_ga_stage(const GaArgs &g, int in, int prev, int op,
                            int index, hipStream_t s);

@@ -3,6 +3,7 @@
 // declared in pmp.h.
 #include "pmp.h"
 
+#include <algorithm>
 #include <climits>
 #include <cstdarg>
 #include <cstdio>
@@ -1722,6 +1723,127 @@ pmp_status pmp_ga_replay(pmp_ga *ga, int32_t *rows, uint16_t *x, float *target,
         HIP_TRY(hipMemcpy(scores, ga->scores, sizeof(float) * ga->prm.population * ga->LC,
                           hipMemcpyDeviceToHost));
     return PMP_OK;
+}
+
+
+pmp_status pmp_exhaustive(pmp_instance *inst, uint64_t *best_mask, int64_t *best_cost,
+                          int64_t *count, void *stream)
+{
+    if (!inst)
+        return fail(PMP_EINVAL, "instance is NULL");
+    const int m = inst->m, p = inst->p, n = inst->n, W = inst->W;
+    // binomials C(a, b), a < m, b <= p, saturating at 2^63
+    const unsigned long long kSat = 1ull << 63;
+    std::vector<unsigned long long> binom((size_t)m * (p + 1), 0ull);
+    for (int a = 0; a < m; ++a) {
+        binom[(size_t)a * (p + 1)] = 1;
+        for (int b = 1; b <= p && b <= a; ++b) {
+            const unsigned long long x = binom[(size_t)(a - 1) * (p + 1) + b - 1];
+            const unsigned long long y = b <= a - 1 ? binom[(size_t)(a - 1) * (p + 1) + b] : 0ull;
+            binom[(size_t)a * (p + 1) + b] = (x >= kSat - y) ? kSat : x + y;
+        }
+    }
+    // C(m, p) = C(m-1, p-1) + C(m-1, p)
+    const unsigned long long x = binom[(size_t)(m - 1) * (p + 1) + p - 1];
+    const unsigned long long y = binom[(size_t)(m - 1) * (p + 1) + p];
+    if (x >= kSat - y || x + y >= (1ull << 62))
+        return fail(PMP_EUNSUPPORTED, "C(%d, %d) is too large to enumerate", m, p);
+    const unsigned long long total = x + y;
+    if (count)
+        *count = (int64_t)total;
+    hipStream_t s = (hipStream_t)stream;
+    const int B = (int)std::min<unsigned long long>(total, 1ull << 18);
+    const int nblk = (B + 255) / 256;
+    EvalArgs a{};
+    a.t = inst->tables();
+    a.P = B;
+    a.active = nullptr;
+    a.done = nullptr;
+    a.err = inst->err;
+    a.clients_per_block = clients_per_block(n, B);
+    a.tiles_c = (B + kEvalTile - 1) / kEvalTile;
+    a.tiles_i = (n + a.clients_per_block - 1) / a.clients_per_block;
+    unsigned long long *d_binom = nullptr, *fit = nullptr, *bc = nullptr, *run = nullptr;
+    uint64_t *masks = nullptr;
+    unsigned long long *part = nullptr;
+    int *bi = nullptr;
+    pmp_status st = PMP_OK;
+    do {
+        if (dalloc(&d_binom, binom.size()) || dalloc(&fit, (size_t)B) || dalloc(&bc, (size_t)nblk) ||
+            dalloc(&bi, (size_t)nblk) || dalloc(&run, 2) || dalloc(&masks, (size_t)B * W) ||
+            dalloc(&part, (size_t)a.tiles_i * B)) {
+            st = fail(PMP_ENOMEM, "enumeration buffers (batch %d)", B);
+            break;
+        }
+        const unsigned long long init[2] = {~0ull, 0ull};
+        hipError_t e = hipMemcpyAsync(d_binom, binom.data(), sizeof(unsigned long long) * binom.size(),
+                                      hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(run, init, sizeof init, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = launch_zero(inst->err, sizeof(uint32_t), s);
+        a.masks = masks;
+        a.part = part;
+        a.spart = nullptr;
+        for (unsigned long long r0 = 0; r0 < total && e == hipSuccess; r0 += (unsigned long long)B) {
+            const int cnt = (int)std::min<unsigned long long>((unsigned long long)B, total - r0);
+            EvalArgs b = a;
+            b.P = cnt;
+            b.tiles_c = (cnt + kEvalTile - 1) / kEvalTile;
+            e = launch_unrank(d_binom, m, p, W, r0, cnt, masks, s);
+            if (e == hipSuccess)
+                e = launch_eval(b, s);
+            if (e == hipSuccess)
+                e = launch_reduce(b, fit, nullptr, s);
+            if (e == hipSuccess)
+                e = launch_argmin(fit, cnt, bc, bi, s);
+            if (e == hipSuccess)
+                e = launch_fold(bc, bi, (cnt + 255) / 256, r0, run, s);
+        }
+        unsigned long long res[2] = {0, 0};
+        uint32_t herr = 0;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(res, run, sizeof res, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&herr, inst->err, sizeof herr, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            st = fail(PMP_EDEVICE, "enumeration: %s", hipGetErrorString(e));
+            break;
+        }
+        st = status_from_err(herr);
+        if (st != PMP_OK)
+            break;
+        if (best_cost)
+            *best_cost = (int64_t)res[0];
+        if (best_mask) {
+            // the winning rank, unranked on the host
+            for (int w = 0; w < W; ++w)
+                best_mask[w] = 0;
+            unsigned long long r = res[1];
+            int xx = 0;
+            for (int i = 0; i < p; ++i) {
+                for (;;) {
+                    const unsigned long long c = binom[(size_t)(m - xx - 1) * (p + 1) + (p - i - 1)];
+                    if (r < c)
+                        break;
+                    r -= c;
+                    ++xx;
+                }
+                best_mask[xx >> 6] |= 1ull << (xx & 63);
+                ++xx;
+            }
+        }
+    } while (0);
+    dfree(d_binom);
+    dfree(fit);
+    dfree(bc);
+    dfree(bi);
+    dfree(run);
+    dfree(masks);
+    dfree(part);
+    return st;
 }
 
 }  // extern "C"
