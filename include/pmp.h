@@ -124,8 +124,10 @@ PMP_API void pmp_instance_destroy(pmp_instance *inst);
  * The genetic algorithm of Section 3 (host steps 7-16 around each Evolve call,
  * Evolve steps 1-8), with the operators of Section 4.  One generation:
  *  1. population: a uniform random p-subset in every slot (Section 4.1), but
- *     from the second generation on slot b*NT holds group b's best of the
- *     previous generation (migration to the same block, Section 4.5);
+ *     from the second generation on the group bests of the previous
+ *     generation migrate (Section 4.5): group b's best to slot b*NT (the same
+ *     block; default) or, with PMP_MIG_ONE_BLOCK, to slot b (the team of
+ *     bests in one block, or the first ones when NB > NT);
  *  2. fitness of all (pmp_eval_population's kernel);
  *  3. crossover stages k = 0..X-1, stride NT >> (1 + k mod lg NT); slot t
  *     of a group pairs with t XOR stride; the pair's lower slot draws
@@ -142,6 +144,10 @@ PMP_API void pmp_instance_destroy(pmp_instance *inst);
  * (seed, role) and addressed by (generation, chromosome, tag, stage), so a
  * run is reproducible bit for bit and independent of launch shapes.
  * ------------------------------------------------------------------------- */
+/* Migration variants (Section 4.5). */
+#define PMP_MIG_SAME_BLOCK 0  /* group b's best -> slot b*NT (its own block) */
+#define PMP_MIG_ONE_BLOCK 1   /* all group bests -> slots 0..NB-1 (one block) */
+
 typedef struct {
     uint64_t seed;
     int32_t population;       /* P = NB x NT */
@@ -150,7 +156,8 @@ typedef struct {
     int32_t saturation;       /* S; 0 = off */
     int32_t crossover_iters;  /* X; 0 = lg NT */
     int32_t mutation_iters;   /* Y; 0 = lg NT */
-    int32_t reserved[2];      /* must be 0 */
+    int32_t migration;        /* PMP_MIG_SAME_BLOCK (0) or PMP_MIG_ONE_BLOCK */
+    int32_t reserved;         /* must be 0 */
 } pmp_ga_params;
 
 typedef struct {
@@ -170,7 +177,7 @@ typedef struct {
 
 /* Create a GA run on an instance (the instance must outlive it).
  * PMP_EINVAL: P < 1, NT not a power of two, NT > 1024, P % NT != 0,
- * generations < 1, negative counts, reserved fields not 0. */
+ * generations < 1, negative counts, unknown migration, reserved not 0. */
 PMP_API pmp_status pmp_ga_create(pmp_instance *inst, const pmp_ga_params *params,
                          pmp_ga **out);
 

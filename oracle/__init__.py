@@ -57,7 +57,7 @@ class _GaParams(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("population", C.c_int32),
                 ("group_size", C.c_int32), ("generations", C.c_int32),
                 ("saturation", C.c_int32), ("crossover_iters", C.c_int32),
-                ("mutation_iters", C.c_int32)]
+                ("mutation_iters", C.c_int32), ("migration", C.c_int32)]
 
 
 def lib():
@@ -226,10 +226,11 @@ class GaState:
     """Resumable GA state: everything the next generation depends on."""
 
     def __init__(self, n, m, p, population, group_size, generations, seed,
-                 saturation=0, crossover_iters=0, mutation_iters=0):
+                 saturation=0, crossover_iters=0, mutation_iters=0, migration=0):
         self.n, self.m, self.p = n, m, p
         self.params = _GaParams(seed, population, group_size, generations,
-                                saturation, crossover_iters, mutation_iters)
+                                saturation, crossover_iters, mutation_iters,
+                                migration)
         W = (m + 63) // 64
         NB = population // group_size
         self.pop = np.zeros((population, W), np.uint64)

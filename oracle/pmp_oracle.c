@@ -590,8 +590,9 @@ int orc_mutate(uint64_t seed, uint64_t gen, uint64_t chrom, uint64_t attempt,
  * b*NT .. b*NT+NT-1 (a thread block of the paper).
  *
  *  1. Population: a fresh uniform p-subset for every slot, except that from
- *     the second generation on, slot b*NT receives group b's best of the
- *     previous generation (migration to the same block, Section 4.5).
+ *     the second generation on the group bests of the previous generation
+ *     migrate (Section 4.5): group b's best to slot b*NT (to the same block,
+ *     migration 0) or to slot b (the team of bests in one block, migration 1).
  *  2. Fitness of every chromosome.
  *  3. Crossover cycle: stages k = 0 .. X-1 with stride NT/2, NT/4, ..., 1
  *     (repeating if X > lg NT).  Chromosome t of a group pairs with t XOR
@@ -623,6 +624,7 @@ typedef struct {
     int32_t saturation;       /* S, 0 = off */
     int32_t crossover_iters;  /* 0 = lg NT */
     int32_t mutation_iters;   /* 0 = lg NT */
+    int32_t migration;        /* 0: to the same block, 1: all to one block */
 } orc_ga_params;
 
 /* state layout (int64): */
@@ -685,8 +687,9 @@ int orc_ga_run(const int32_t *d, int64_t ld, int32_t n, int32_t m, int32_t p,
         /* 1. population of this Evolve call, with migrants */
 #pragma omp parallel for num_threads(nt) schedule(static)
         for (int32_t c = 0; c < P; ++c) {
-            if (g > 0 && c % NT == 0) {
-                unpack(gbest_mask + (int64_t)(c / NT) * W, m,
+            const int one = prm->migration == 1;
+            if (g > 0 && (one ? c < NB : c % NT == 0)) {
+                unpack(gbest_mask + (int64_t)(one ? c : c / NT) * W, m,
                        bits + (int64_t)c * m);
             } else {
                 orc_stream s;

@@ -117,6 +117,7 @@ struct GaArgs {
     Tables t;
     uint64_t seed;
     int32_t P, NT, NB, lg, X, Y, generations, saturation;
+    int32_t migration;              // PMP_MIG_SAME_BLOCK or PMP_MIG_ONE_BLOCK
     uint64_t *cur[2];               // P x W population
     unsigned long long *fit[2];     // P fitness of cur
     uint64_t *off[2];               // P x W offspring

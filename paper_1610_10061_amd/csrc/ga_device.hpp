@@ -119,8 +119,11 @@ __device__ __forceinline__ void ga_init_one(const GaArgs &g, int c, int lane)
     const uint64_t gen = g.gs[GS_GEN];
     const int W = g.t.W, m = g.t.m, p = g.t.p;
     uint64_t *dst = g.off[0] + (int64_t)c * W;
-    if (gen > 0 && (c % g.NT) == 0) {
-        const uint64_t *src = g.gmask + (int64_t)(c / g.NT) * W;
+    // migrant slots: b*NT for group b (same block) or b (one block)
+    const bool one = g.migration == PMP_MIG_ONE_BLOCK;
+    const bool migrant = gen > 0 && (one ? c < g.NB : (c % g.NT) == 0);
+    if (migrant) {
+        const uint64_t *src = g.gmask + (int64_t)(one ? c : c / g.NT) * W;
         for (int w = lane; w < W; w += 64)
             dst[w] = src[w];
     } else {

@@ -244,6 +244,7 @@ struct pmp_ga {
         g.Y = Y;
         g.generations = prm.generations;
         g.saturation = prm.saturation;
+        g.migration = prm.migration;
         for (int k = 0; k < 2; ++k) {
             g.cur[k] = cur[k];
             g.fit[k] = fit[k];
@@ -727,7 +728,8 @@ pmp_status pmp_ga_create(pmp_instance *inst, const pmp_ga_params *prm,
                     "population %d must be a multiple of a power-of-two group size %d <= 1024",
                     P, NT);
     if (prm->generations < 1 || prm->saturation < 0 || prm->crossover_iters < 0 ||
-        prm->mutation_iters < 0 || prm->reserved[0] || prm->reserved[1])
+        prm->mutation_iters < 0 || prm->reserved ||
+        (prm->migration != PMP_MIG_SAME_BLOCK && prm->migration != PMP_MIG_ONE_BLOCK))
         return fail(PMP_EINVAL, "bad GA parameters");
     pmp_ga *ga = new pmp_ga;
     ga->inst = inst;

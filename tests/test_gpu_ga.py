@@ -50,13 +50,13 @@ def mode(request):
             os.environ[k] = v
 
 
-def _compare(pm, d, p, P, NT, G, seed, steps, sat=0, X=0, Y=0):
+def _compare(pm, d, p, P, NT, G, seed, steps, sat=0, X=0, Y=0, mig=0):
     n, m = d.shape
     print("case", d.shape, "p", p, "P", P, "NT", NT, "steps", steps, "seed", seed,
-          "mode", {k: os.environ.get(k) for k in _ENV}, flush=True)
+          "migration", mig, "mode", {k: os.environ.get(k) for k in _ENV}, flush=True)
     inst = pm.Instance(d, p)
-    ga = pm.GA(inst, P, NT, G, seed, sat, X, Y)
-    st = oracle.GaState(n, m, p, P, NT, G, seed, sat, X, Y)
+    ga = pm.GA(inst, P, NT, G, seed, sat, X, Y, mig)
+    st = oracle.GaState(n, m, p, P, NT, G, seed, sat, X, Y, mig)
     for k in steps:
         ga.step(k)
         oracle.ga_run(d, st, k)
@@ -148,3 +148,18 @@ def test_ga_group_of_one(pm, mode):
     d = gi.euclid_instance(60, 2)
     s = _compare(pm, d, 6, 8, 1, 4, seed=6, steps=[4])
     assert s["crossover_taken"] == 0 and s["mutation_taken"] == 0
+
+
+@pytest.mark.parametrize("P,NT", [(128, 32), (64, 8), (256, 8)],
+                         ids=["NB<NT", "NB=NT", "NB>NT"])
+def test_ga_migration_to_one_block(pm, mode, P, NT):
+    """The other migration variant: every group best goes to slots 0..NB-1
+    (one block when NB <= NT, the first NB / NT blocks otherwise)."""
+    d = gi.graph_instance(100, 200, 2)
+    _compare(pm, d, 5, P, NT, 20, seed=13, steps=[1, 3, 2], mig=1)
+
+
+def test_ga_rejects_unknown_migration(pm):
+    inst = pm.Instance(gi.graph_instance(20, 40, 0), 4)
+    with pytest.raises(pm.PmpError):
+        pm.GA(inst, 32, 8, 5, 1, migration=2)

@@ -376,6 +376,37 @@ def test_ga_saturation_stop_and_optimum_bound():
     assert st.best_cost == opt
 
 
+def test_ga_migration_to_one_block():
+    """With every group best migrating to slots 0..NB-1 (NB <= NT: all into
+    group 0), slot c < NB starts each generation at the previous best of
+    group c and only takes strictly fitter offspring, so it ends no worse;
+    group 0's best is then never worse than the global best before the
+    generation.  The default variant does not have that property on this
+    instance."""
+    d = gi.graph_instance(100, 200, 2)
+    n, m, p, P, NT = 100, 100, 5, 64, 16
+    NB = P // NT
+    st = oracle.GaState(n, m, p, P, NT, 30, seed=13, migration=1)
+    other = oracle.GaState(n, m, p, P, NT, 30, seed=13, migration=0)
+    misses = 0
+    for g in range(30):
+        prev, prev_best, prev_other = st.gbest_cost.copy(), st.best_cost, other.best_cost
+        oracle.ga_run(d, st, 1)
+        oracle.ga_run(d, other, 1)
+        np.testing.assert_array_equal(oracle.objective(d, st.pop, p), st.fit)
+        if g > 0:
+            assert (st.fit[:NB] <= prev).all()
+            assert st.gbest_cost[0] <= prev_best
+            misses += int(other.gbest_cost[0] > prev_other)
+    assert misses > 0
+    # the variants differ only from the second generation on
+    a = oracle.GaState(n, m, p, P, NT, 30, seed=13, migration=1)
+    b = oracle.GaState(n, m, p, P, NT, 30, seed=13, migration=0)
+    oracle.ga_run(d, a, 1)
+    oracle.ga_run(d, b, 1)
+    np.testing.assert_array_equal(a.pop, b.pop)
+
+
 # ------------------------------------------------------------- generators
 def test_euclid_rounding_exact():
     d = gi.euclid_instance(300, 4)
