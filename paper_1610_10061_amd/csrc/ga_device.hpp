@@ -69,6 +69,21 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane)
     return ((uint64_t)hi << 32) | lo;
 }
 
+// v of lane src (src may differ between lanes; every lane must take part)
+__device__ __forceinline__ uint64_t readpair(uint64_t v, int src)
+{
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Orders a wave's LDS accesses before and after it (one wave owns the data).
+__device__ __forceinline__ void wave_lds_fence()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // The k lowest set bits of x (all of x when it has no more than k).
 __device__ __forceinline__ uint64_t lowest_bits(uint64_t x, int k)
 {
@@ -104,17 +119,122 @@ __device__ __forceinline__ void philox_block(uint64_t k0, uint64_t k1,
 }
 
 // ---------------------------------------------------------------------------
+// Floyd's method (Bentley & Floyd, CACM 1987) draws a uniform p-subset of
+// [0, m): for j = m-p .. m-1 draw t uniform in [0, j]; take t, or j if t is
+// already taken.  The loop is sequential, but its result has a closed form
+// that lanes can evaluate together.  Write e = j - (m-p) and t_e for the
+// draw of step e.  Since every earlier pick is below j, t_e is already taken
+// exactly when it equals an earlier draw, or equals an earlier j whose own
+// draw was already taken.  So with
+//   col(e) = [t_e = t_e' for some e' < e]
+//            or [m-p <= t_e < j_e and col(t_e - (m-p))]
+// the subset is {t_e : all e} together with {j_e : col(e)}.  The lanes
+// evaluate the draws 64 at a time in step order: a draw repeated from an
+// earlier batch shows in the bitmap T of all earlier draws; one repeated
+// within the batch shows in a match of the draws' bits by ballots; col of an
+// earlier batch is read from the bitmap Cb; col of a lower lane of the same
+// batch is taken once that lane has settled (the lowest unsettled lane
+// always can, so the loop ends).  Returns false, before writing anything,
+// when a draw would need Lemire's rejection step: the caller then runs the
+// loop one step at a time, which consumes the stream in the same order.
+// sw: 2 * W words of LDS owned by the wave.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool floyd_wave(const GaArgs &g, uint64_t gen, int c,
+                                           int lane, uint64_t *sw,
+                                           uint64_t &word0, uint64_t &word1)
+{
+    const int W = g.t.W, m = g.t.m, p = g.t.p;
+    const int off = m - p, nC = (p + 63) >> 6;
+    uint64_t *T = sw, *Cb = sw + W;
+    for (int w = lane; w < 2 * W; w += 64)
+        sw[w] = 0ull;
+    wave_lds_fence();
+    const int nbits = m > 1 ? 32 - __builtin_clz((unsigned)(m - 1)) : 1;
+    const uint64_t below = (1ull << lane) - 1ull;
+    uint64_t q[4];
+    for (int ch = 0; ch < nC; ++ch) {
+        // draw e = 64 ch + lane is word (lane & 3) of block 16 ch + lane / 4;
+        // lane l computes block 64 r + l for r = ch / 4
+        if ((ch & 3) == 0)
+            philox_block(g.seed, ROLE_POPULATION, gen, (uint64_t)c,
+                         (TAG_SAMPLE << 32), (uint64_t)(64 * (ch >> 2) + lane), q);
+        const int src = 16 * (ch & 3) + (lane >> 2), sel = lane & 3;
+        const uint64_t x0 = readpair(q[0], src), x1 = readpair(q[1], src);
+        const uint64_t x2 = readpair(q[2], src), x3 = readpair(q[3], src);
+        const uint64_t x = sel == 0 ? x0 : sel == 1 ? x1 : sel == 2 ? x2 : x3;
+        const int e = 64 * ch + lane;
+        const bool valid = e < p;
+        const uint64_t r = (uint64_t)(off + e) + 1ull;
+        if (__builtin_amdgcn_ballot_w64(valid && x * r < r) != 0ull)
+            return false;
+        const int t = valid ? (int)__umul64hi(x, r) : 0;
+        // repeated from an earlier batch
+        bool col = valid && ((T[t >> 6] >> (t & 63)) & 1ull) != 0ull;
+        // repeated from a lower lane of this batch
+        uint64_t same = __builtin_amdgcn_ballot_w64(valid);
+        for (int b = 0; b < nbits; ++b) {
+            const bool set = ((t >> b) & 1) != 0;
+            const uint64_t v = __builtin_amdgcn_ballot_w64(set);
+            same &= set ? v : ~v;
+        }
+        col = col || (valid && (same & below) != 0ull);
+        // equal to an earlier j: that step's col decides
+        const bool ref = valid && !col && t >= off && t < off + e;
+        const int tgt = ref ? t - off : 0;
+        const bool ref_prev = ref && tgt < 64 * ch;
+        const uint64_t cw = Cb[tgt >> 6];
+        if (ref_prev)
+            col = ((cw >> (tgt & 63)) & 1ull) != 0ull;
+        bool pending = ref && !ref_prev;
+        const int tl = pending ? tgt - 64 * ch : lane;
+        while (__builtin_amdgcn_ballot_w64(pending) != 0ull) {
+            const int tp = __shfl((int)pending, tl);
+            const int tc = __shfl((int)col, tl);
+            if (pending && tp == 0) {
+                col = tc != 0;
+                pending = false;
+            }
+        }
+        const uint64_t cmask = __builtin_amdgcn_ballot_w64(col);
+        wave_lds_fence();  // every lane has read T and Cb for this batch
+        if (lane == 0)
+            Cb[ch] = cmask;
+        if (valid)
+            atomicOr((unsigned long long *)&T[t >> 6], 1ull << (t & 63));
+        wave_lds_fence();
+    }
+    // the subset: every draw, and j = m-p+e for each e with col(e)
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int w = lane + 64 * k;
+        const int wl = min(w, W - 1);
+        const int base = 64 * wl - off;  // bit of Cb for facility 64 w
+        const int i = base >> 6, o = base & 63;
+        const uint64_t lo = (i >= 0 && i < nC) ? Cb[i] : 0ull;
+        const uint64_t hi = (i + 1 >= 0 && i + 1 < nC) ? Cb[i + 1] : 0ull;
+        const uint64_t jb = o == 0 ? lo : ((lo >> o) | (hi << (64 - o)));
+        const uint64_t v = w < W ? (T[wl] | jb) : 0ull;
+        if (k == 0)
+            word0 = v;
+        else
+            word1 = v;
+    }
+    return true;
+}
+
+// ---------------------------------------------------------------------------
 // Population of one Evolve call (Section 3.1 steps 7/11 and 16; Sections 4.1
 // and 4.5), chromosome c, by its wave.  Fresh slots get a uniform p-subset by
-// Floyd's method (Bentley & Floyd, CACM 1987): for j = m-p .. m-1 draw t
-// uniform in [0, j]; take t, or j if t is already taken.  The lanes compute
-// 64 Philox blocks (256 words of the slot's stream) at once; the draws are
-// consumed in stream order, so the result is the same as drawing one at a
-// time.  From the second generation on, slot b*NT of group b receives that
-// group's best of the previous generation.  The population goes to off[0]
+// Floyd's method: floyd_wave above, or, when a draw needs Lemire's rejection
+// step, one step at a time; either way the draws are consumed in stream
+// order, so the result is the same as drawing one at a time.  From the
+// second generation on the group bests migrate: group b's best to slot b*NT
+// (the same block) or to slot b (one block).  The population goes to off[0]
 // with fitness "infinite", so the first stage takes it as the current one.
+// sw: 2 * W words of LDS owned by the wave.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void ga_init_one(const GaArgs &g, int c, int lane)
+__device__ __forceinline__ void ga_init_one(const GaArgs &g, int c, int lane,
+                                            uint64_t *sw)
 {
     const uint64_t gen = g.gs[GS_GEN];
     const int W = g.t.W, m = g.t.m, p = g.t.p;
@@ -130,44 +250,47 @@ __device__ __forceinline__ void ga_init_one(const GaArgs &g, int c, int lane)
         // the subset's words live in the lanes: word w in lane w (w < 64)
         // or in the second register of lane w - 64
         uint64_t word0 = 0, word1 = 0;
-        uint64_t q[4];
-        int64_t base = 0;  // first block held by lane 0
-        philox_block(g.seed, ROLE_POPULATION, gen, (uint64_t)c,
-                     (TAG_SAMPLE << 32), (uint64_t)lane, q);
-        int64_t k = 0;  // next draw of the stream
-        auto draw = [&]() -> uint64_t {
-            if ((k >> 2) - base >= 64) {
-                base += 64;
-                philox_block(g.seed, ROLE_POPULATION, gen, (uint64_t)c,
-                             (TAG_SAMPLE << 32), (uint64_t)(base + lane), q);
-            }
-            const int src = (int)((k >> 2) - base), sel = (int)(k & 3);
-            const uint64_t mine = sel == 0 ? q[0] : sel == 1 ? q[1] : sel == 2 ? q[2] : q[3];
-            ++k;
-            return readlane64(mine, src);
-        };
-        for (int j = m - p; j < m; ++j) {
-            const uint64_t r = (uint64_t)j + 1;
-            uint64_t x = draw();
-            uint64_t lo = x * r;
-            if (lo < r) {
-                const uint64_t thresh = (0ull - r) % r;
-                while (lo < thresh) {
-                    x = draw();
-                    lo = x * r;
+        if (!floyd_wave(g, gen, c, lane, sw, word0, word1)) {
+            word0 = word1 = 0ull;
+            uint64_t q[4];
+            int64_t base = 0;  // first block held by lane 0
+            philox_block(g.seed, ROLE_POPULATION, gen, (uint64_t)c,
+                         (TAG_SAMPLE << 32), (uint64_t)lane, q);
+            int64_t k = 0;  // next draw of the stream
+            auto draw = [&]() -> uint64_t {
+                if ((k >> 2) - base >= 64) {
+                    base += 64;
+                    philox_block(g.seed, ROLE_POPULATION, gen, (uint64_t)c,
+                                 (TAG_SAMPLE << 32), (uint64_t)(base + lane), q);
                 }
+                const int src = (int)((k >> 2) - base), sel = (int)(k & 3);
+                const uint64_t mine = sel == 0 ? q[0] : sel == 1 ? q[1] : sel == 2 ? q[2] : q[3];
+                ++k;
+                return readlane64(mine, src);
+            };
+            for (int j = m - p; j < m; ++j) {
+                const uint64_t r = (uint64_t)j + 1;
+                uint64_t x = draw();
+                uint64_t lo = x * r;
+                if (lo < r) {
+                    const uint64_t thresh = (0ull - r) % r;
+                    while (lo < thresh) {
+                        x = draw();
+                        lo = x * r;
+                    }
+                }
+                const int t = (int)__umul64hi(x, r);
+                const int tw = t >> 6;
+                const uint64_t held = lane == tw ? word0 : (lane + 64 == tw ? word1 : 0ull);
+                const bool taken =
+                    __builtin_amdgcn_ballot_w64(((held >> (t & 63)) & 1ull) != 0ull) != 0ull;
+                const int pick = taken ? j : t;
+                const uint64_t bit = 1ull << (pick & 63);
+                if (lane == (pick >> 6))
+                    word0 |= bit;
+                if (lane + 64 == (pick >> 6))
+                    word1 |= bit;
             }
-            const int t = (int)__umul64hi(x, r);
-            const int tw = t >> 6;
-            const uint64_t held = lane == tw ? word0 : (lane + 64 == tw ? word1 : 0ull);
-            const bool taken =
-                __builtin_amdgcn_ballot_w64(((held >> (t & 63)) & 1ull) != 0ull) != 0ull;
-            const int pick = taken ? j : t;
-            const uint64_t bit = 1ull << (pick & 63);
-            if (lane == (pick >> 6))
-                word0 |= bit;
-            if (lane + 64 == (pick >> 6))
-                word1 |= bit;
         }
         if (lane < W)
             dst[lane] = word0;
@@ -371,12 +494,22 @@ __device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
     // lane k < CS_COUNT holds counter k of chromosome c
     unsigned long long *cs = g.cstat + (int64_t)c * CS_COUNT;
     const unsigned long long cs_old = cs[lane < CS_COUNT ? lane : 0];
-    // partial sums of the first 64 client tiles (straight-line; more tiles
+    // partial sums of the first 128 client tiles (straight-line; more tiles
     // are added below)
     const bool use0 = lane < g.TI;
     const int64_t row0 = (int64_t)min(lane, g.TI - 1) * g.P;
     const unsigned long long pf0 = g.part[row0 + c], ph0 = g.part[row0 + pc];
     const uint32_t ps0 = g.spart[row0 + c];
+    // tiles 64..127 in the same round (the branch is uniform)
+    const bool use1 = lane + 64 < g.TI;
+    unsigned long long pf1 = 0, ph1 = 0;
+    uint32_t ps1 = 0;
+    if (g.TI > 64) {
+        const int64_t row1 = (int64_t)min(lane + 64, g.TI - 1) * g.P;
+        pf1 = g.part[row1 + c];
+        ph1 = g.part[row1 + pc];
+        ps1 = g.spart[row1 + c];
+    }
     WaveWords cc{}, oc{}, cp{}, opw{};
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
@@ -395,9 +528,10 @@ __device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
     }
     if (ga_stopped(g))  // checked once the loads are on their way
         return;
-    unsigned long long f = use0 ? pf0 : 0ull, h = use0 ? ph0 : 0ull;
-    unsigned long long s = use0 ? ps0 : 0u;
-    for (int t0 = 64; t0 < g.TI; t0 += 64) {
+    unsigned long long f = (use0 ? pf0 : 0ull) + (use1 ? pf1 : 0ull);
+    unsigned long long h = (use0 ? ph0 : 0ull) + (use1 ? ph1 : 0ull);
+    unsigned long long s = (unsigned long long)(use0 ? ps0 : 0u) + (use1 ? ps1 : 0u);
+    for (int t0 = 128; t0 < g.TI; t0 += 64) {
         const bool use = t0 + lane < g.TI;
         const int64_t row = (int64_t)min(t0 + lane, g.TI - 1) * g.P;
         const unsigned long long pf = g.part[row + c], ph = g.part[row + pc];

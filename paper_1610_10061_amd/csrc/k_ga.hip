@@ -17,11 +17,12 @@ namespace {
 
 __global__ __launch_bounds__(64 * kGaWaves) void k_init(GaArgs g)
 {
+    __shared__ uint64_t sw[kGaWaves][2 * kMaxWords];
     const int wave = wave_id(), lane = threadIdx.x & 63;
     const int c = blockIdx.x * kGaWaves + wave;
     if (c >= g.P || ga_stopped(g))
         return;
-    ga_init_one(g, c, lane);
+    ga_init_one(g, c, lane, sw[wave]);
 }
 
 __global__ __launch_bounds__(64 * kGaWaves) void k_stage(GaArgs g, int in,
@@ -224,8 +225,10 @@ __global__ __launch_bounds__(64 * kGaWaves) void k_ga_batch(BatchArgs B,
         for (int cg = gw; cg < nchrom; cg += nw) {
             const int b = owner(B.chrom0, B.count, cg);
             const BatchItem &it = B.items[b];
+            // the sampler's 2 W words per wave fit in WD (>= 2 W) words of
+            // the evaluation's LDS, which is idle in this phase
             if (!ga_stopped(it.g))
-                ga_init_one(it.g, cg - B.chrom0[b], lane);
+                ga_init_one(it.g, cg - B.chrom0[b], lane, lds + wave * WD);
         }
         if (!bar.sync(&flag))
             return;
@@ -274,13 +277,14 @@ __global__ __launch_bounds__(64 * kGaWaves) void k_ga_batch(BatchArgs B,
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(64 * kGaWaves) void k_batch_init(BatchArgs B)
 {
+    __shared__ uint64_t sw[kGaWaves][2 * kMaxWords];
     const int cg = blockIdx.x * kGaWaves + wave_id();
     if (cg >= B.chrom0[B.count])
         return;
     const int b = owner(B.chrom0, B.count, cg);
     const BatchItem &it = B.items[b];
     if (!ga_stopped(it.g))
-        ga_init_one(it.g, cg - B.chrom0[b], threadIdx.x & 63);
+        ga_init_one(it.g, cg - B.chrom0[b], threadIdx.x & 63, sw[wave_id()]);
 }
 
 template <int WD>

@@ -163,3 +163,12 @@ def test_ga_rejects_unknown_migration(pm):
     inst = pm.Instance(gi.graph_instance(20, 40, 0), 4)
     with pytest.raises(pm.PmpError):
         pm.GA(inst, 32, 8, 5, 1, migration=2)
+
+
+@pytest.mark.parametrize("m,p", [(150, 147), (130, 129), (200, 129)],
+                         ids=["p=m-3", "p=m-1", "p=129"])
+def test_ga_dense_subsets(pm, m, p):
+    """Populations where most of Floyd's draws collide: chains of repeated
+    draws inside and across the sampler's 64-draw batches."""
+    d = np.random.default_rng(m + p).integers(0, 200, size=(40, m)).astype(np.int32)
+    _compare(pm, d, p, 64, 16, 3, seed=21, steps=[2])
