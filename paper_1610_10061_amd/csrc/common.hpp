@@ -109,6 +109,12 @@ __device__ __host__ __forceinline__ void ga_stage_ops(int k, int X, int S,
     *index = k < X ? k : k - X;
 }
 
+// The random draws of one operator application: crossover (a, b) = (r1,
+// quota); mutation (a, b, c) = (lo, hi, move) of the rotated range.
+struct __align__(16) OpDraw {
+    int32_t a, b, c, d;
+};
+
 // Device state of one GA run.  Population, fitness, offspring and their
 // "evaluate me" flags are double-buffered: a stage kernel reads buffer `in`
 // and writes buffer `in ^ 1`, so every chromosome (and its crossover partner)
@@ -118,6 +124,9 @@ struct GaArgs {
     uint64_t seed;
     int32_t P, NT, NB, lg, X, Y, generations, saturation;
     int32_t migration;              // PMP_MIG_SAME_BLOCK or PMP_MIG_ONE_BLOCK
+    OpDraw *draws;                  // P x (X + Y) draws of this generation:
+                                    // crossover stage k at k, mutation
+                                    // attempt a at X + a
     uint64_t *cur[2];               // P x W population
     unsigned long long *fit[2];     // P fitness of cur
     uint64_t *off[2];               // P x W offspring

@@ -222,6 +222,142 @@ __device__ __forceinline__ bool floyd_wave(const GaArgs &g, uint64_t gen, int c,
     return true;
 }
 
+// Blocks 0 and 1 of the Philox4x64-10 stream with key (k0, k1) and counter
+// words (c0, c1, c2): two independent round chains side by side, so their
+// latencies overlap (the same rounds as PhiloxStream::refill).
+__device__ __forceinline__ void philox_two_blocks(uint64_t k0, uint64_t k1, uint64_t c0,
+                                                  uint64_t c1, uint64_t c2,
+                                                  uint64_t out[8])
+{
+    const uint64_t kM0 = 0xD2E7470EE14C6C93ull, kM1 = 0xCA5A826395121157ull;
+    const uint64_t kW0 = 0x9E3779B97F4A7C15ull, kW1 = 0xBB67AE8584CAA73Bull;
+    uint64_t x0 = c0, x1 = c1, x2 = c2, x3 = 0;
+    uint64_t y0 = c0, y1 = c1, y2 = c2, y3 = 1;
+    uint64_t a = k0, b = k1;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t hx0 = __umul64hi(kM0, x0), lx0 = kM0 * x0;
+        const uint64_t hy0 = __umul64hi(kM0, y0), ly0 = kM0 * y0;
+        const uint64_t hx1 = __umul64hi(kM1, x2), lx1 = kM1 * x2;
+        const uint64_t hy1 = __umul64hi(kM1, y2), ly1 = kM1 * y2;
+        x0 = hx1 ^ x1 ^ a;
+        y0 = hy1 ^ y1 ^ a;
+        x1 = lx1;
+        y1 = ly1;
+        x2 = hx0 ^ x3 ^ b;
+        y2 = hy0 ^ y3 ^ b;
+        x3 = lx0;
+        y3 = ly0;
+        a += kW0;
+        b += kW1;
+    }
+    out[0] = x0;
+    out[1] = x1;
+    out[2] = x2;
+    out[3] = x3;
+    out[4] = y0;
+    out[5] = y1;
+    out[6] = y2;
+    out[7] = y3;
+}
+
+// The high word of x * r, uniform in [0, r) when the draw needs no
+// rejection step; flags `rej` when it might (then the caller redraws the
+// whole stream one word at a time with PhiloxStream::below).
+__device__ __forceinline__ uint64_t lemire_fast(uint64_t x, uint64_t r, bool &rej)
+{
+    rej = rej || x * r < r;
+    return __umul64hi(x, r);
+}
+
+// Mutation operands from the draws type, direction, block ends x and y
+// (y skips x) and the amount: the rotated range [lo, hi] and the move.
+__device__ __forceinline__ void mutation_draws(uint64_t type, uint64_t dir, uint64_t x,
+                                               uint64_t y, uint64_t sh, int m, OpDraw &d)
+{
+    int lo = 0, hi = m - 1;
+    if (type != 0) {
+        int yy = (int)y;
+        if (yy >= (int)x)
+            ++yy;
+        lo = (int)x < yy ? (int)x : yy;
+        hi = (int)x < yy ? yy : (int)x;
+    }
+    const int L = hi - lo + 1;
+    d.a = lo;
+    d.b = hi;
+    d.c = dir == 0 ? 1 + (int)sh : L - 1 - (int)sh;
+}
+
+// ---------------------------------------------------------------------------
+// The operator draws of chromosome c for one generation, one stream per lane
+// (the streams are independent): crossover stage k draws r1 in [0, m) and
+// the quota i in [1, floor(p/2)] from c's stream for stage k (used when c is
+// the lower slot of its pair, Section 4.3); mutation attempt a draws the
+// type, the direction, the block ends if any and the amount from c's stream
+// for attempt a (Section 4.4).  The stage kernels load them with their other
+// inputs instead of running the generator on their critical path.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void ga_draws_one(const GaArgs &g, uint64_t gen, int c,
+                                             int lane)
+{
+    const int m = g.t.m, p = g.t.p, S = g.X + g.Y;
+    const uint64_t rq = (uint64_t)max(p / 2, 1);
+    for (int s0 = 0; s0 < S; s0 += 64) {
+        const int s = s0 + lane;
+        const bool isx = s < g.X;
+        const uint64_t tag = isx ? TAG_CROSSOVER : TAG_MUTATION;
+        const uint64_t idx = (uint64_t)(isx ? s : s - g.X);
+        uint64_t w[8];
+        philox_two_blocks(g.seed, ROLE_EVOLVE, gen, (uint64_t)c,
+                          (tag << 32) | (idx & 0xFFFFFFFFull), w);
+        // without rejections the draws are words 0, 1, ... of the stream
+        bool rej = false;
+        OpDraw d{0, 0, 0, 0};
+        if (isx) {
+            d.a = (int)lemire_fast(w[0], (uint64_t)m, rej);
+            d.b = 1 + (int)lemire_fast(w[1], rq, rej);
+        } else {
+            const uint64_t type = lemire_fast(w[0], 2, rej);
+            const uint64_t dir = lemire_fast(w[1], 2, rej);
+            uint64_t x = 0, y = 0, sh;
+            if (type != 0) {
+                x = lemire_fast(w[2], (uint64_t)m, rej);
+                y = lemire_fast(w[3], (uint64_t)(m - 1), rej);
+                const int yy = (int)y >= (int)x ? (int)y + 1 : (int)y;
+                const int L = ((int)x < yy ? yy - (int)x : (int)x - yy) + 1;
+                sh = lemire_fast(w[4], (uint64_t)(L - 1), rej);
+            } else {
+                sh = lemire_fast(w[2], (uint64_t)(m - 1), rej);
+            }
+            mutation_draws(type, dir, x, y, sh, m, d);
+        }
+        if (rej) {
+            PhiloxStream st(g.seed, ROLE_EVOLVE, gen, (uint64_t)c, tag, idx);
+            if (isx) {
+                d.a = (int)st.below((uint64_t)m);
+                d.b = 1 + (int)st.below(rq);
+            } else {
+                const uint64_t type = st.below(2), dir = st.below(2);
+                uint64_t x = 0, y = 0;
+                int L = m;
+                if (type != 0) {
+                    x = st.below((uint64_t)m);
+                    y = st.below((uint64_t)(m - 1));
+                    const int yy = (int)y >= (int)x ? (int)y + 1 : (int)y;
+                    L = ((int)x < yy ? yy - (int)x : (int)x - yy) + 1;
+                }
+                const uint64_t sh = st.below((uint64_t)(L - 1));
+                mutation_draws(type, dir, x, y, sh, m, d);
+            }
+        }
+        if (isx && p < 2)
+            d = OpDraw{0, 0, 0, 0};
+        if (s < S)
+            g.draws[(int64_t)c * S + s] = d;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Population of one Evolve call (Section 3.1 steps 7/11 and 16; Sections 4.1
 // and 4.5), chromosome c, by its wave.  Fresh slots get a uniform p-subset by
@@ -231,6 +367,7 @@ __device__ __forceinline__ bool floyd_wave(const GaArgs &g, uint64_t gen, int c,
 // second generation on the group bests migrate: group b's best to slot b*NT
 // (the same block) or to slot b (one block).  The population goes to off[0]
 // with fitness "infinite", so the first stage takes it as the current one.
+// The generation's operator draws are made here too (ga_draws_one).
 // sw: 2 * W words of LDS owned by the wave.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void ga_init_one(const GaArgs &g, int c, int lane,
@@ -297,6 +434,7 @@ __device__ __forceinline__ void ga_init_one(const GaArgs &g, int c, int lane,
         if (lane + 64 < W)
             dst[lane + 64] = word1;
     }
+    ga_draws_one(g, gen, c, lane);
     if (lane == 0) {
         g.ok[0][c] = 1;
         g.fit[0][c] = ~0ull;
@@ -462,9 +600,9 @@ __device__ __forceinline__ bool mutate_wave(const WaveWords &A, uint64_t *F,
 //    draws type, direction, then the amount s in [1, m-1] or the block ends
 //    (a uniform pair of distinct positions) and s in [1, b - a]; an
 //    offspring equal to its parent is not evaluated (Section 4.4).
-// All of the step's loads are issued together and the random draws are
-// computed while they are in flight; the operators then work on the words
-// held by the lanes.
+// The draws were made with the population (ga_draws_one).  All of the step's
+// loads are issued together; the operators then work on the words held by
+// the lanes.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
                                              int in, int prev, int op,
@@ -526,6 +664,12 @@ __device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
         cp.v[k] = w < W ? a2 : 0ull;
         opw.v[k] = w < W ? a3 : 0ull;
     }
+    // the operator's draws (the branch is uniform)
+    OpDraw dr{0, 0, 0, 0};
+    if (xo || op == OP_MUT) {
+        const int leader = c < pc ? c : pc;
+        dr = g.draws[(int64_t)(xo ? leader : c) * (g.X + g.Y) + (xo ? index : g.X + index)];
+    }
     if (ga_stopped(g))  // checked once the loads are on their way
         return;
     unsigned long long f = (use0 ? pf0 : 0ull) + (use1 ? pf1 : 0ull);
@@ -544,31 +688,9 @@ __device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
     const bool okp = xo && okp_b != 0;
     const bool was_improved = imp_b != 0;
 
-    // the operator's draws, while the loads are in flight
-    int r1 = 0, quota = 0, lo = 0, hi = m - 1, move = 0;
-    if (xo) {
-        const int leader = c < pc ? c : pc;
-        PhiloxStream st(g.seed, ROLE_EVOLVE, gen, (uint64_t)leader, TAG_CROSSOVER,
-                        (uint64_t)index);
-        r1 = (int)st.below((uint64_t)m);
-        quota = 1 + (int)st.below((uint64_t)(g.t.p / 2));
-    } else if (op == OP_MUT) {
-        PhiloxStream st(g.seed, ROLE_EVOLVE, gen, (uint64_t)c, TAG_MUTATION,
-                        (uint64_t)index);
-        const int type = (int)st.below(2);
-        const int dir = (int)st.below(2);
-        if (type != 0) {
-            const int x = (int)st.below((uint64_t)m);
-            int y = (int)st.below((uint64_t)(m - 1));
-            if (y >= x)
-                ++y;
-            lo = x < y ? x : y;
-            hi = x < y ? y : x;
-        }
-        const int L = hi - lo + 1;
-        const int sh = 1 + (int)st.below((uint64_t)(L - 1));
-        move = dir == 0 ? sh : L - sh;
-    }
+    const int r1 = dr.a, quota = dr.b;
+    const int lo = op == OP_MUT ? dr.a : 0, hi = op == OP_MUT ? dr.b : m - 1;
+    const int move = dr.c;
 
     // finish the previous operator: c, and for a crossover the partner
     const unsigned long long fo = wave_sum(f), scan = wave_sum(s), fop = wave_sum(h);

@@ -189,6 +189,7 @@ struct pmp_ga {
     unsigned long long *fit[2] = {nullptr, nullptr};
     uint8_t *ok[2] = {nullptr, nullptr};
     uint8_t *improved = nullptr;
+    OpDraw *draws = nullptr;
     unsigned long long *part = nullptr;
     uint32_t *spart = nullptr;
     uint64_t *gmask = nullptr, *best = nullptr;
@@ -252,6 +253,7 @@ struct pmp_ga {
             g.ok[k] = ok[k];
         }
         g.improved = improved;
+        g.draws = draws;
         g.part = part;
         g.spart = spart;
         g.TI = TI;
@@ -693,6 +695,7 @@ void pmp_ga_destroy(pmp_ga *ga)
         dfree(ga->ok[k]);
     }
     dfree(ga->improved);
+    dfree(ga->draws);
     dfree(ga->part);
     dfree(ga->spart);
     dfree(ga->gmask);
@@ -749,6 +752,7 @@ pmp_status pmp_ga_create(pmp_instance *inst, const pmp_ga_params *prm,
         bad = bad || dalloc(&ga->cur[k], PW) || dalloc(&ga->off[k], PW) ||
               dalloc(&ga->fit[k], (size_t)P) || dalloc(&ga->ok[k], (size_t)P);
     bad = bad || dalloc(&ga->improved, (size_t)P) ||
+          dalloc(&ga->draws, (size_t)P * std::max(1, ga->X + ga->Y)) ||
           dalloc(&ga->part, (size_t)ga->TI * P) || dalloc(&ga->spart, (size_t)ga->TI * P) ||
           dalloc(&ga->gmask, (size_t)ga->NB * W) || dalloc(&ga->best, W) ||
           dalloc(&ga->gcost, (size_t)ga->NB) || dalloc(&ga->gs, GS_COUNT) ||
