@@ -51,6 +51,13 @@ typedef enum {
 
 #define PMP_ON_DEVICE 1u
 #define PMP_ASYNC 2u
+/* Thread mappings of pmp_eval_population other than the default tiled one
+ * (at most one of them): one thread per chromosome walking every client, or
+ * one thread per (client, chromosome) pair - the paper's "n threads"
+ * scenario (Section 5, the observation on the Fitness bottleneck).  Same
+ * results; kept to measure the load-balance argument. */
+#define PMP_EVAL_PER_CHROMOSOME 4u
+#define PMP_EVAL_PER_CLIENT 8u
 
 /* Largest m handled: chromosome masks of a tile of 64 chromosomes are held in
  * LDS (64 x 1 KiB at m = 8192). */
@@ -104,15 +111,42 @@ PMP_API pmp_status pmp_instance_tables(const pmp_instance *inst, uint16_t *pi,
  *  fitness     P int64 outputs.
  *  scan_total  optional (NULL = skip): P int64 outputs, sum_i s*_{c,i}, the
  *              number of Pi' entries the walk reads for chromosome c.
+ *  flags       PMP_ON_DEVICE, PMP_ASYNC, and at most one of
+ *              PMP_EVAL_PER_CHROMOSOME / PMP_EVAL_PER_CLIENT.
  * Errors: PMP_EINFEASIBLE if a chromosome's popcount is not p or it has bits
  * at positions >= m (the truncated walk is defined only for exactly p open
  * facilities); its fitness is then unspecified.  With PMP_ASYNC the error is
- * only recorded in the instance (see pmp_instance_check).
+ * only recorded in the instance (see pmp_instance_check).  PMP_EINVAL for
+ * both scheme flags at once.
  * ------------------------------------------------------------------------- */
 PMP_API pmp_status pmp_eval_population(pmp_instance *inst, const uint64_t *masks,
                                int32_t P, int64_t *fitness,
                                int64_t *scan_total, uint32_t flags,
                                void *stream);
+
+/* ---------------------------------------------------------------------------
+ * pmp_apsp - all-pairs shortest path lengths of a weighted directed graph
+ * (blocked Floyd-Warshall on the device): the distance matrix of a graph
+ * instance (the p-median benchmarks the paper uses give graphs, whose cost
+ * d_ij is the length of a shortest path from i to j), ready for
+ * pmp_preprocess.
+ *
+ *  w       n x n int32 weights, row stride ldw >= n: w_ij >= 0 is an arc
+ *          i -> j (an undirected edge is two arcs), w_ij < 0 no arc; the
+ *          diagonal is taken as 0.  Host pointer, or device pointer with
+ *          PMP_ON_DEVICE.  Not modified.
+ *  d       n x n int32 output, row stride ldd >= n (same memory kind as w):
+ *          d_ij = length of a shortest path from i to j, or -1 if there is
+ *          none.  d may not overlap w.
+ *  n       1 <= n <= 32768.
+ * The library keeps one padded n x n work matrix per device between calls
+ * (grown on demand, held until the process ends); calls are serialised.
+ * Errors: PMP_EINVAL for null pointers, n or strides out of range;
+ * PMP_EUNSUPPORTED when (n - 1) * (largest weight) >= 2^31 - 1 (a path
+ * length might not fit int32); PMP_ENOMEM.  Always waits for its stream.
+ * ------------------------------------------------------------------------- */
+PMP_API pmp_status pmp_apsp(const int32_t *w, int64_t ldw, int32_t n, int32_t *d,
+                            int64_t ldd, uint32_t flags, void *stream);
 
 /* Wait for `stream`, then return and clear the errors recorded on the device
  * by asynchronous calls on this instance (PMP_EINFEASIBLE or PMP_EINVAL). */

@@ -22,6 +22,7 @@ Functions and the passages they follow:
 * ``crossover``      Section 4.3.
 * ``mutate``         Section 4.4.
 * ``ga_run``         Section 3 (host steps 7-16, Evolve steps 1-8).
+* ``apsp``           shortest-path cost matrix of a graph (Floyd 1962).
 """
 from __future__ import annotations
 
@@ -72,6 +73,7 @@ def lib():
         L.orc_bc_eval.argtypes = [_p, _p, _i32, _i32, _i32, _p, _i32, _p, _p]
         L.orc_exhaustive.argtypes = [_p, _i64, _i32, _i32, _i32, _p, _p, _p, _i32]
         L.orc_philox4x64.argtypes = [_p, _p, _p]
+        L.orc_apsp.argtypes = [_p, _i32, _p]
         L.orc_philox4x64.restype = None
         L.orc_stream_draws.argtypes = [_u64, _u64, _u64, _u64, _u64, _u64, _p, _i32, _p]
         L.orc_sample_subset.argtypes = [_u64, _u64, _u64, _i32, _i32, _p]
@@ -177,6 +179,18 @@ def exhaustive(d, p: int, threads: int = 0):
     _check(lib().orc_exhaustive(_ptr(d), m, n, m, p, _ptr(best), _ptr(mask),
                                 _ptr(cnt), threads), "exhaustive")
     return int(best[0]), mask, int(cnt[0])
+
+
+def apsp(w):
+    """Shortest path lengths of the graph with arc weights w (n x n int32,
+    negative = no arc), by Floyd-Warshall; -1 where there is no path."""
+    w = _d(w)
+    n = w.shape[0]
+    if w.shape != (n, n):
+        raise ValueError("w must be square")
+    d = np.zeros((n, n), np.int32)
+    _check(lib().orc_apsp(_ptr(w), n, _ptr(d)), "apsp")
+    return d
 
 
 def philox(ctr, key):

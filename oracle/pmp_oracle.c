@@ -821,3 +821,48 @@ int orc_ga_run(const int32_t *d, int64_t ld, int32_t n, int32_t m, int32_t p,
     free(tmp);
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------
+ * All-pairs shortest path lengths (Floyd, CACM 1962), the step that turns a
+ * graph instance into its cost matrix (the benchmark graphs the paper
+ * evaluates on give costs as shortest-path lengths).  w: n x n, w_ij >= 0 an
+ * arc i -> j, w_ij < 0 no arc, diagonal taken as 0.  d: n x n, -1 where
+ * there is no path.  Plain triple loop over the intermediate vertex k in
+ * 64-bit arithmetic.  Returns ORC_EINVAL when a path length exceeds int32.
+ * ---------------------------------------------------------------------- */
+int orc_apsp(const int32_t *w, int32_t n, int32_t *d)
+{
+    if (!w || !d || n < 1)
+        return ORC_EINVAL;
+    const int64_t INF = INT64_MAX / 4;
+    int64_t *D = (int64_t *)malloc(sizeof(int64_t) * (size_t)n * (size_t)n);
+    if (!D)
+        return ORC_ENOMEM;
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t j = 0; j < n; ++j) {
+            const int32_t x = w[(int64_t)i * n + j];
+            D[(int64_t)i * n + j] = i == j ? 0 : (x >= 0 ? (int64_t)x : INF);
+        }
+    for (int32_t k = 0; k < n; ++k)
+        for (int32_t i = 0; i < n; ++i) {
+            const int64_t dik = D[(int64_t)i * n + k];
+            if (dik >= INF)
+                continue;
+            for (int32_t j = 0; j < n; ++j) {
+                const int64_t via = dik + D[(int64_t)k * n + j];
+                if (via < D[(int64_t)i * n + j])
+                    D[(int64_t)i * n + j] = via;
+            }
+        }
+    int rc = ORC_OK;
+    for (int64_t e = 0; e < (int64_t)n * n; ++e) {
+        if (D[e] >= INF)
+            d[e] = -1;
+        else if (D[e] > INT32_MAX)
+            rc = ORC_EINVAL;
+        else
+            d[e] = (int32_t)D[e];
+    }
+    free(D);
+    return rc;
+}

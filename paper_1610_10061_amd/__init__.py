@@ -27,7 +27,7 @@ __all__ = [
     "pmp_ga_step_batch", "pmp_features", "pmp_model_create", "pmp_model_get",
     "pmp_model_set", "pmp_model_forward", "pmp_model_grad", "pmp_model_train",
     "pmp_model_destroy", "pmp_ga_set_model", "pmp_ga_replay", "pmp_exhaustive",
-    "Instance", "GA",
+    "pmp_apsp", "Instance", "GA",
     "Batch", "Model", "LearnParams", "EXPORTS", "MLP_PARAMS",
 ]
 
@@ -37,6 +37,10 @@ LIB_PATH = os.path.join(_HERE, "libpmp.so")
 PMP_OK, PMP_EINVAL, PMP_ENOMEM, PMP_EDEVICE, PMP_EINFEASIBLE, PMP_EUNSUPPORTED = range(6)
 PMP_ON_DEVICE = 1
 PMP_ASYNC = 2
+PMP_EVAL_PER_CHROMOSOME = 4
+PMP_EVAL_PER_CLIENT = 8
+EVAL_SCHEMES = {"tiled": 0, "per_chromosome": PMP_EVAL_PER_CHROMOSOME,
+                "per_client": PMP_EVAL_PER_CLIENT}
 
 EXPORTS = [
     "pmp_preprocess", "pmp_instance_info", "pmp_instance_tables",
@@ -47,7 +51,7 @@ EXPORTS = [
     "pmp_batch_step", "pmp_batch_check", "pmp_batch_destroy", "pmp_ga_step_batch",
     "pmp_features", "pmp_model_create", "pmp_model_get", "pmp_model_set",
     "pmp_model_forward", "pmp_model_grad", "pmp_model_train", "pmp_model_destroy",
-    "pmp_ga_set_model", "pmp_ga_replay", "pmp_exhaustive",
+    "pmp_ga_set_model", "pmp_ga_replay", "pmp_exhaustive", "pmp_apsp",
 ]
 
 FEATURES = 16
@@ -146,6 +150,7 @@ def lib():
     L.pmp_ga_set_model.argtypes = [_vp, _vp, C.POINTER(LearnParams)]
     L.pmp_ga_replay.argtypes = [_vp, C.POINTER(_i32), _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     L.pmp_exhaustive.argtypes = [_vp, _vp, C.POINTER(_i64), C.POINTER(_i64), _vp]
+    L.pmp_apsp.argtypes = [_vp, _i64, _i32, _vp, _i64, _u32, _vp]
     L.pmp_status_str.argtypes = [_i32]
     L.pmp_status_str.restype = C.c_char_p
     L.pmp_last_error.argtypes = []
@@ -215,8 +220,10 @@ def pmp_instance_tables(inst):
 
 
 def pmp_eval_population(inst, masks, fitness, scan_total=None, stream=None,
-                        asynchronous=False):
-    """Eq. (6) for every row of masks (P x W uint64) into fitness (P int64)."""
+                        asynchronous=False, scheme="tiled"):
+    """Eq. (6) for every row of masks (P x W uint64) into fitness (P int64).
+    scheme: "tiled" (default), "per_chromosome" or "per_client" (the thread
+    mappings the paper compares; same results)."""
     mp, dev = _buf(masks, np.uint64, torch.uint64)
     fp, fdev = _buf(fitness, np.int64, torch.int64)
     sp, sdev = _buf(scan_total, np.int64, torch.int64)
@@ -224,9 +231,29 @@ def pmp_eval_population(inst, masks, fitness, scan_total=None, stream=None,
         raise ValueError("all buffers must be host arrays or all CUDA tensors")
     P = masks.shape[0]
     flags = (PMP_ON_DEVICE | (PMP_ASYNC if asynchronous else 0)) if dev else 0
+    flags |= EVAL_SCHEMES[scheme]
     _check(lib().pmp_eval_population(inst, mp, P, fp, sp, flags,
                                      _stream(stream) if dev else None),
            "pmp_eval_population")
+
+
+def pmp_apsp(w, d=None, stream=None):
+    """Shortest path lengths of the graph with arc weights w (n x n int32,
+    negative = no arc; numpy or CUDA tensor) into d (same kind; allocated
+    when None); -1 where there is no path.  Returns d."""
+    n = w.shape[0]
+    if w.shape != (n, n):
+        raise ValueError("w must be square")
+    if d is None:
+        d = (torch.empty((n, n), dtype=torch.int32, device=w.device)
+             if isinstance(w, torch.Tensor) else np.empty((n, n), np.int32))
+    wp, wdev = _buf(w, np.int32, torch.int32)
+    dp, ddev = _buf(d, np.int32, torch.int32)
+    if wdev != ddev:
+        raise ValueError("w and d must both be host arrays or both CUDA tensors")
+    _check(lib().pmp_apsp(wp, n, n, dp, n, PMP_ON_DEVICE if wdev else 0,
+                          _stream(stream) if wdev else None), "pmp_apsp")
+    return d
 
 
 def pmp_instance_check(inst, stream=None):

@@ -76,6 +76,16 @@ hipError_t launch_eval(const EvalArgs &a, hipStream_t s, hipEvent_t e0 = nullptr
 hipError_t launch_reduce(const EvalArgs &a, unsigned long long *fitness,
                          unsigned long long *scan, hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
+// The other thread mappings of the evaluation (k_eval_schemes.hip).
+hipError_t launch_eval_per_chromosome(const EvalArgs &a, unsigned long long *fitness,
+                                      unsigned long long *scan, hipStream_t s);
+hipError_t launch_eval_per_client(const EvalArgs &a, hipStream_t s);
+// All-pairs shortest paths (k_apsp.hip) on a padded uint32 work matrix.
+int apsp_padded(int n);
+hipError_t launch_apsp_in(const int32_t *w, int64_t ldw, int n, uint32_t *D, uint32_t *wmax,
+                          hipStream_t s);
+hipError_t launch_apsp_rounds(uint32_t *D, int n, hipStream_t s);
+hipError_t launch_apsp_out(const uint32_t *D, int n, int32_t *d, int64_t ldd, hipStream_t s);
 
 // Per-chromosome GA counters (summed on the host when read).
 enum GaStat : int {

@@ -590,6 +590,87 @@ pmp_status pmp_instance_tables(const pmp_instance *inst, uint16_t *pi,
     return PMP_OK;
 }
 
+// Work buffers of pmp_apsp, kept per device and grown on demand (a call
+// would otherwise pay for allocating and freeing an n x n matrix); calls are
+// serialised by the mutex.  Held until the process ends.
+struct ApspCache {
+    std::mutex mu;
+    struct Dev {
+        uint32_t *work = nullptr, *wmax = nullptr;
+        int32_t *w = nullptr, *d = nullptr;  // staging for host arguments
+        size_t work_cap = 0, stage_cap = 0;
+    };
+    std::map<int, Dev> dev;
+};
+
+ApspCache &apsp_cache()
+{
+    static ApspCache *c = new ApspCache;  // never destroyed: outlives the runtime
+    return *c;
+}
+
+pmp_status pmp_apsp(const int32_t *w, int64_t ldw, int32_t n, int32_t *d, int64_t ldd,
+                    uint32_t flags, void *stream)
+{
+    if (!w || !d)
+        return fail(PMP_EINVAL, "w or d is NULL");
+    if (n < 1 || n > 32768 || ldw < n || ldd < n)
+        return fail(PMP_EINVAL, "need 1 <= n <= 32768 and strides >= n (n=%d ldw=%lld ldd=%lld)",
+                    n, (long long)ldw, (long long)ldd);
+    hipStream_t s = (hipStream_t)stream;
+    const bool on_dev = flags & PMP_ON_DEVICE;
+    const int ld = apsp_padded(n);
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device));
+    ApspCache &cache = apsp_cache();
+    std::lock_guard<std::mutex> lock(cache.mu);
+    ApspCache::Dev &b = cache.dev[device];
+    const size_t cells = (size_t)ld * ld;
+    if (b.work_cap < cells) {
+        dfree(b.work);
+        b.work_cap = 0;
+        if (dalloc(&b.work, cells) != hipSuccess)
+            return fail(PMP_ENOMEM, "APSP work matrix (%d x %d)", ld, ld);
+        b.work_cap = cells;
+    }
+    if (!b.wmax && dalloc(&b.wmax, 1) != hipSuccess)
+        return fail(PMP_ENOMEM, "APSP word");
+    const int32_t *dw = w;
+    int32_t *dd = d;
+    int64_t ldw_dev = ldw, ldd_dev = ldd;
+    if (!on_dev) {
+        const size_t nn = (size_t)n * n;
+        if (b.stage_cap < nn) {
+            dfree(b.w);
+            dfree(b.d);
+            b.stage_cap = 0;
+            if (dalloc(&b.w, nn) != hipSuccess || dalloc(&b.d, nn) != hipSuccess)
+                return fail(PMP_ENOMEM, "APSP staging (n=%d)", n);
+            b.stage_cap = nn;
+        }
+        HIP_TRY(hipMemcpy2DAsync(b.w, (size_t)n * 4, w, (size_t)ldw * 4, (size_t)n * 4, n,
+                                 hipMemcpyHostToDevice, s));
+        dw = b.w;
+        dd = b.d;
+        ldw_dev = ldd_dev = n;
+    }
+    HIP_TRY(launch_zero(b.wmax, sizeof(uint32_t), s));
+    HIP_TRY(launch_apsp_in(dw, ldw_dev, n, b.work, b.wmax, s));
+    uint32_t wmax = 0;
+    HIP_TRY(hipMemcpyAsync(&wmax, b.wmax, sizeof wmax, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if ((int64_t)(n - 1) * (int64_t)wmax >= 0x7FFFFFFFll)
+        return fail(PMP_EUNSUPPORTED, "path lengths may exceed int32: (n-1) * max weight = %lld",
+                    (long long)(n - 1) * (long long)wmax);
+    HIP_TRY(launch_apsp_rounds(b.work, n, s));
+    HIP_TRY(launch_apsp_out(b.work, n, dd, ldd_dev, s));
+    if (!on_dev)
+        HIP_TRY(hipMemcpy2DAsync(d, (size_t)ldd * 4, b.d, (size_t)n * 4, (size_t)n * 4, n,
+                                 hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return PMP_OK;
+}
+
 pmp_status pmp_instance_check(pmp_instance *inst, void *stream)
 {
     if (!inst)
@@ -615,6 +696,9 @@ pmp_status pmp_eval_population(pmp_instance *inst, const uint64_t *masks,
         return PMP_OK;
     if (!masks || !fitness)
         return fail(PMP_EINVAL, "masks or fitness is NULL");
+    const uint32_t scheme = flags & (PMP_EVAL_PER_CHROMOSOME | PMP_EVAL_PER_CLIENT);
+    if (scheme == (PMP_EVAL_PER_CHROMOSOME | PMP_EVAL_PER_CLIENT))
+        return fail(PMP_EINVAL, "at most one evaluation scheme flag");
     hipStream_t s = (hipStream_t)stream;
     const bool on_dev = flags & PMP_ON_DEVICE;
     const bool async = on_dev && (flags & PMP_ASYNC);
@@ -654,6 +738,8 @@ pmp_status pmp_eval_population(pmp_instance *inst, const uint64_t *masks,
     a.clients_per_block = clients_per_block(inst->n, P);
     a.tiles_c = (P + kEvalTile - 1) / kEvalTile;
     a.tiles_i = (inst->n + a.clients_per_block - 1) / a.clients_per_block;
+    if (scheme == PMP_EVAL_PER_CLIENT)
+        a.tiles_i = 4 * ((inst->n + 255) / 256);  // one partial per wave of 64 clients
     const size_t cells = (size_t)a.tiles_i * P;
     if (inst->part_cap < cells) {
         dfree(inst->part);
@@ -666,8 +752,12 @@ pmp_status pmp_eval_population(pmp_instance *inst, const uint64_t *masks,
     }
     a.part = inst->part;
     a.spart = dscan ? inst->spart : nullptr;
-    HIP_TRY(launch_eval(a, s));
-    HIP_TRY(launch_reduce(a, dfit, dscan, s));
+    if (scheme == PMP_EVAL_PER_CHROMOSOME) {
+        HIP_TRY(launch_eval_per_chromosome(a, dfit, dscan, s));
+    } else {
+        HIP_TRY(scheme == PMP_EVAL_PER_CLIENT ? launch_eval_per_client(a, s) : launch_eval(a, s));
+        HIP_TRY(launch_reduce(a, dfit, dscan, s));
+    }
 
     if (!on_dev) {
         HIP_TRY(hipMemcpyAsync(fitness, dfit, sizeof(int64_t) * P,

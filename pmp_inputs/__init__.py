@@ -77,6 +77,20 @@ def _graph_edges(n: int, n_edges: int, rng: np.random.Generator,
     return edges.astype(np.int64), w.astype(np.int64)
 
 
+def graph_weights(n: int, n_edges: int, seed: int, wmin: int = 1,
+                  wmax: int = 100) -> np.ndarray:
+    """n x n int32 arc weights of the random connected graph that
+    graph_instance(n, n_edges, seed) measures: both arcs of every edge carry
+    its weight, -1 where there is no edge, 0 on the diagonal."""
+    rng = np.random.default_rng([0x6772617068, seed, n, n_edges])
+    e, w = _graph_edges(n, n_edges, rng, wmin, wmax)
+    out = np.full((n, n), -1, np.int32)
+    out[e[:, 0], e[:, 1]] = w
+    out[e[:, 1], e[:, 0]] = w
+    np.fill_diagonal(out, 0)
+    return out
+
+
 def graph_instance(n: int, n_edges: int, seed: int, wmin: int = 1,
                    wmax: int = 100) -> np.ndarray:
     """n x n int32 shortest-path distance matrix of a random connected graph.

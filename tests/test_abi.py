@@ -100,3 +100,17 @@ def test_oracle_and_product_share_nothing():
                     incs = [ln for ln in open(path) if ln.lstrip().startswith("#include")]
                     banned = ("oracle",) if pkg != "oracle" else ("pmp.h", "common.hpp", "philox.hpp")
                     assert not [ln for ln in incs if any(b in ln for b in banned)], path
+
+
+def test_apsp_rejects_bad_arguments_before_any_device_work():
+    import ctypes as C
+    import paper_1610_10061_amd as pm
+    w = np.zeros((4, 4), np.int32)
+    d = np.zeros((4, 4), np.int32)
+    L = pm.lib()
+    vp = pm._vp
+    assert L.pmp_apsp(None, 4, 4, d.ctypes.data_as(vp), 4, 0, None) == pm.PMP_EINVAL
+    assert L.pmp_apsp(w.ctypes.data_as(vp), 4, 0, d.ctypes.data_as(vp), 4, 0, None) == pm.PMP_EINVAL
+    assert L.pmp_apsp(w.ctypes.data_as(vp), 3, 4, d.ctypes.data_as(vp), 4, 0, None) == pm.PMP_EINVAL
+    assert L.pmp_apsp(w.ctypes.data_as(vp), 4, 40000, d.ctypes.data_as(vp), 40000, 0,
+                      None) == pm.PMP_EINVAL

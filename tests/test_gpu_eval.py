@@ -213,3 +213,60 @@ def test_negative_distance_rejected_on_device(pm):
     with pytest.raises(pm.PmpError) as e:
         pm.Instance(torch.from_numpy(d).cuda(), 3)
     assert e.value.status == pm.PMP_EINVAL
+
+
+SCHEME_CASES = [("example1", 6), ("g20", 200), ("g100", 64), ("g900", 257),
+                ("rect_37x150", 131), ("ties_p1", 70), ("ties_pm1", 65),
+                ("euclid_129", 64), ("wide_2x700", 30), ("m2", 3)]
+
+
+@pytest.mark.parametrize("scheme", ["per_chromosome", "per_client"])
+@pytest.mark.parametrize("name,P", SCHEME_CASES)
+def test_eval_schemes_bit_exact(pm, scheme, name, P):
+    """The other thread mappings (one thread per chromosome, one per client)
+    give the same exact costs and scan lengths."""
+    d, p = INSTANCES[name]()
+    n, m = d.shape
+    _say("case", name, d.shape, "p", p, "P", P, "scheme", scheme)
+    masks = gi.random_population(P, m, p, seed=P + n + 1)
+    inst = pm.Instance(d, p)
+    fit = np.zeros(P, np.int64)
+    scan = np.zeros(P, np.int64)
+    pm.pmp_eval_population(inst.handle, masks, fit, scan, scheme=scheme)
+    want, wscan = oracle.objective(d, masks, p, scan=True)
+    np.testing.assert_array_equal(fit, want)
+    np.testing.assert_array_equal(scan, wscan)
+    fit2 = np.zeros(P, np.int64)
+    pm.pmp_eval_population(inst.handle, masks, fit2, None, scheme=scheme)
+    np.testing.assert_array_equal(fit2, want)
+
+
+@pytest.mark.parametrize("scheme", ["per_chromosome", "per_client"])
+@pytest.mark.parametrize("kind", ["fewer", "stray"])
+def test_eval_schemes_reject_infeasible(pm, scheme, kind):
+    d, p = INSTANCES["euclid_129"]()
+    m = 129
+    masks = gi.random_population(10, m, p, seed=3)
+    if kind == "fewer":
+        bits = gi.unpack_masks(masks, m)
+        bits[7, np.nonzero(bits[7])[0][0]] = False
+        masks = gi.pack_masks(bits, m)
+    else:
+        masks[7, 2] |= np.uint64(1) << np.uint64(9)  # bit 137 >= m
+    _say("infeasible", kind, "scheme", scheme)
+    inst = pm.Instance(d, p)
+    fit = np.zeros(10, np.int64)
+    with pytest.raises(pm.PmpError) as e:
+        pm.pmp_eval_population(inst.handle, masks, fit, scheme=scheme)
+    assert e.value.status == pm.PMP_EINFEASIBLE
+
+
+def test_eval_both_scheme_flags_rejected(pm):
+    d, p = INSTANCES["g20"]()
+    inst = pm.Instance(d, p)
+    masks = gi.random_population(4, 20, p, seed=1)
+    fit = np.zeros(4, np.int64)
+    rc = pm.lib().pmp_eval_population(inst.handle, masks.ctypes.data_as(pm._vp), 4,
+                                      fit.ctypes.data_as(pm._vp), None,
+                                      pm.PMP_EVAL_PER_CHROMOSOME | pm.PMP_EVAL_PER_CLIENT, None)
+    assert rc == pm.PMP_EINVAL
