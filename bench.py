@@ -535,6 +535,86 @@ def bench_apsp(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_hbp(args):
+    """The reduced Hammer-Beresnev polynomial against the plain walk: for
+    G900 (p = 90), E5000 (p = 100) and a clustered-demand instance (5000
+    clients at 500 distinct sites, 500 candidate facilities, p = 50: every
+    site's 10 clients give identical rows), the reduction's term counts and
+    kept rows, its construction time, and the evaluation of a random
+    population by both walks (median of 20 launches after 3 warm-ups, HIP
+    events on the launch stream).  Algorithmic bytes: plain 2 s* + 4 per
+    (client, chromosome) pair; reduced 2 s + 8 per (kept row, chromosome)
+    pair (s = positions read, int64 running sums)."""
+    import numpy as np
+    import torch
+    import paper_1610_10061_amd as pm
+    import pmp_inputs as gi
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    sites = gi.euclid_instance(500, 9)
+    clustered = np.repeat(sites, 10, axis=0)
+    cases = [("G900", gi.graph_instance(900, 16200, 0), 90, 1024),
+             ("E5000", gi.euclid_instance(5000, 0), 100, 4096),
+             ("clustered 5000x500", clustered, 50, 4096)]
+    rows = []
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        ts = []
+        for _ in range(20):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            ts.append((a, b))
+        torch.cuda.synchronize()
+        return float(np.median([a.elapsed_time(b) for a, b in ts]))
+
+    for name, d, p, P in cases:
+        n, m = d.shape
+        W = gi.words_for(m)
+        inst = pm.Instance(torch.from_numpy(np.ascontiguousarray(d)).cuda(), p, stream)
+        pm.Hbp(inst, stream).close()  # first use outside the clock
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = pm.Hbp(inst, stream)
+        reduce_ms = (time.perf_counter() - t0) * 1e3
+        const, T, kept, maxlen = h.info()
+        _, _, _, rl = h.terms()
+        masks = torch.from_numpy(gi.random_population(P, m, p, 1).view(np.int64)).cuda().view(torch.uint64)
+        f1 = torch.empty(P, dtype=torch.int64, device="cuda")
+        s1 = torch.empty(P, dtype=torch.int64, device="cuda")
+        f2 = torch.empty_like(f1)
+        s2 = torch.empty_like(s1)
+        ms_plain = timed(lambda: inst.eval(masks, f1, s1, stream, asynchronous=True))
+        ms_red = timed(lambda: h.eval(masks, f2, s2, stream, asynchronous=True))
+        inst.check(stream)
+        assert torch.equal(f1, f2), "reduced evaluation disagrees with the plain walk"
+        b_plain = 2 * int(s1.sum().item()) + 4 * P * n + P * (8 * W + 8)
+        b_red = 2 * int(s2.sum().item()) + 8 * P * kept + P * (8 * W + 8)
+        row = {"instance": name, "n": n, "m": m, "p": p, "population": P,
+               "terms_full": n * (m - p + 1), "terms_reduced": T + 1,
+               "rows_kept": kept, "mean_row_len_kept": float(rl[rl > 0].mean()) if kept else 0.0,
+               "reduce_ms": reduce_ms,
+               "plain_ms": ms_plain, "reduced_ms": ms_red, "speedup": ms_plain / ms_red,
+               "plain_bytes": b_plain, "reduced_bytes": b_red,
+               "plain_GBps": b_plain / ms_plain / 1e6, "reduced_GBps": b_red / ms_red / 1e6}
+        log(json.dumps(row))
+        rows.append(row)
+        h.close()
+        inst.close()
+    out = {"metric": "evaluation time, plain walk / reduced-polynomial walk",
+           "value": rows[-1]["speedup"], "unit": "x", "n_gpus": 1, "higher_is_better": True,
+           "dtype": "int32 / int64", "data": "synthetic",
+           "config": {"workload": "reduced Hammer-Beresnev polynomial: G900 p=90 (population "
+                                  "1024), E5000 p=100 and clustered demand 5000 clients at 500 "
+                                  "sites x 500 facilities p=50 (population 4096); value = the "
+                                  "clustered case"},
+           "cases": rows}
+    print(json.dumps(out), flush=True)
+
+
 def bench_g100(args):
     """G100 (n = m = 100, 200 edges, p = 5; the shape of pmed1): the exact
     optimum of instance seeds 0-9 by GPU enumeration of all C(100, 5)
@@ -630,7 +710,7 @@ def main():
                     help="no per-launch events (the GA then replays hipGraphs)")
     ap.add_argument("--g100-instances", type=int, default=10)
     ap.add_argument("--workload", choices=["g900", "batch", "learned", "e5000", "g100",
-                                           "ablation", "apsp"],
+                                           "ablation", "apsp", "hbp"],
                     default="g900",
                     help="g900: the headline configuration; batch: 256 ragged "
                          "instances in one launch vs one launch per instance; "
@@ -673,6 +753,8 @@ def main():
         return bench_ablation(args)
     if args.workload == "apsp":
         return bench_apsp(args)
+    if args.workload == "hbp":
+        return bench_hbp(args)
 
     import numpy as np
     import torch

@@ -125,6 +125,56 @@ PMP_API pmp_status pmp_eval_population(pmp_instance *inst, const uint64_t *masks
                                void *stream);
 
 /* ---------------------------------------------------------------------------
+ * The reduced Hammer-Beresnev polynomial (Section 2.1, after Eq. (6); Example
+ * 1 reduces 15 terms to 7).  Term t >= 1 of client i has coefficient
+ * Delta'_{i,t} and the monomial "the first t facilities of row i are all
+ * closed" (0-based t); monomials are sets, so equal sets from different
+ * clients merge into one term with the summed coefficient, and sets whose
+ * coefficients are all 0 drop out.  The constant is sum_i Delta'_{i,0}.
+ *
+ * pmp_hbp_reduce builds it on the device from an instance's tables.  Each
+ * merged term is charged to the lowest client row holding it with a
+ * positive coefficient; row i keeps its first K_i positions, K_i - 1 being
+ * the highest degree it is charged (rows charged nothing are dropped), so
+ * that the polynomial is evaluated as walks: a kept row costs the running
+ * sum of its charged coefficients up to min(first open position, K_i - 1),
+ * and the cost is the constant plus the kept rows' costs - equal to Eq. (1)
+ * for every feasible chromosome.  Sets are merged by 64-bit keys and every
+ * merge is then checked exactly; a key collision (never expected) makes the
+ * call fail with PMP_EUNSUPPORTED rather than merge different sets.
+ *
+ *  inst    a preprocessed instance (borrowed: it must outlive the handle);
+ *          m <= 8128.
+ *  out     receives the handle (device tables, owned).
+ * Errors: PMP_EINVAL (null), PMP_EUNSUPPORTED (m too large, key collision),
+ * PMP_ENOMEM.  Waits for its stream.
+ * ------------------------------------------------------------------------- */
+typedef struct pmp_hbp pmp_hbp;
+PMP_API pmp_status pmp_hbp_reduce(pmp_instance *inst, void *stream, pmp_hbp **out);
+
+/* constant, number of non-constant monomials, kept rows and the longest
+ * kept row (any pointer may be NULL). */
+PMP_API pmp_status pmp_hbp_info(const pmp_hbp *h, int64_t *constant, int64_t *monomials,
+                                int32_t *rows, int32_t *max_len);
+
+/* The monomials as (row, degree, coefficient), row by row and by degree
+ * within a row (the monomial is the set of the row's first `degree`
+ * facilities), and K_i of every client row (n entries; 0 = dropped).  Each
+ * output may be NULL; host pointers, or device pointers with PMP_ON_DEVICE.
+ * Waits for its stream. */
+PMP_API pmp_status pmp_hbp_terms(const pmp_hbp *h, int32_t *row, int32_t *degree,
+                                 int64_t *coef, int32_t *row_len, uint32_t flags,
+                                 void *stream);
+
+/* The reduced polynomial at every chromosome of a population: arguments,
+ * flags and errors as pmp_eval_population (no scheme flags); scan_total
+ * counts the positions the truncated walks read. */
+PMP_API pmp_status pmp_hbp_eval(pmp_hbp *h, const uint64_t *masks, int32_t P,
+                                int64_t *fitness, int64_t *scan_total, uint32_t flags,
+                                void *stream);
+PMP_API void pmp_hbp_destroy(pmp_hbp *h);
+
+/* ---------------------------------------------------------------------------
  * pmp_apsp - all-pairs shortest path lengths of a weighted directed graph
  * (blocked Floyd-Warshall on the device): the distance matrix of a graph
  * instance (the p-median benchmarks the paper uses give graphs, whose cost

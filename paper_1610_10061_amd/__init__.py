@@ -27,7 +27,8 @@ __all__ = [
     "pmp_ga_step_batch", "pmp_features", "pmp_model_create", "pmp_model_get",
     "pmp_model_set", "pmp_model_forward", "pmp_model_grad", "pmp_model_train",
     "pmp_model_destroy", "pmp_ga_set_model", "pmp_ga_replay", "pmp_exhaustive",
-    "pmp_apsp", "Instance", "GA",
+    "pmp_apsp", "pmp_hbp_reduce", "pmp_hbp_info", "pmp_hbp_terms", "pmp_hbp_eval",
+    "pmp_hbp_destroy", "Instance", "GA", "Hbp",
     "Batch", "Model", "LearnParams", "EXPORTS", "MLP_PARAMS",
 ]
 
@@ -52,6 +53,7 @@ EXPORTS = [
     "pmp_features", "pmp_model_create", "pmp_model_get", "pmp_model_set",
     "pmp_model_forward", "pmp_model_grad", "pmp_model_train", "pmp_model_destroy",
     "pmp_ga_set_model", "pmp_ga_replay", "pmp_exhaustive", "pmp_apsp",
+    "pmp_hbp_reduce", "pmp_hbp_info", "pmp_hbp_terms", "pmp_hbp_eval", "pmp_hbp_destroy",
 ]
 
 FEATURES = 16
@@ -151,6 +153,13 @@ def lib():
     L.pmp_ga_replay.argtypes = [_vp, C.POINTER(_i32), _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     L.pmp_exhaustive.argtypes = [_vp, _vp, C.POINTER(_i64), C.POINTER(_i64), _vp]
     L.pmp_apsp.argtypes = [_vp, _i64, _i32, _vp, _i64, _u32, _vp]
+    L.pmp_hbp_reduce.argtypes = [_vp, _vp, C.POINTER(_vp)]
+    L.pmp_hbp_info.argtypes = [_vp, C.POINTER(_i64), C.POINTER(_i64), C.POINTER(_i32),
+                               C.POINTER(_i32)]
+    L.pmp_hbp_terms.argtypes = [_vp, _vp, _vp, _vp, _vp, _u32, _vp]
+    L.pmp_hbp_eval.argtypes = [_vp, _vp, _i32, _vp, _vp, _u32, _vp]
+    L.pmp_hbp_destroy.argtypes = [_vp]
+    L.pmp_hbp_destroy.restype = None
     L.pmp_status_str.argtypes = [_i32]
     L.pmp_status_str.restype = C.c_char_p
     L.pmp_last_error.argtypes = []
@@ -254,6 +263,51 @@ def pmp_apsp(w, d=None, stream=None):
     _check(lib().pmp_apsp(wp, n, n, dp, n, PMP_ON_DEVICE if wdev else 0,
                           _stream(stream) if wdev else None), "pmp_apsp")
     return d
+
+
+def pmp_hbp_reduce(inst, stream=None):
+    """The reduced polynomial of an instance (a handle)."""
+    out = _vp()
+    _check(lib().pmp_hbp_reduce(inst, _stream(stream), C.byref(out)), "pmp_hbp_reduce")
+    return out
+
+
+def pmp_hbp_info(h):
+    c, t = _i64(), _i64()
+    r, k = _i32(), _i32()
+    _check(lib().pmp_hbp_info(h, C.byref(c), C.byref(t), C.byref(r), C.byref(k)),
+           "pmp_hbp_info")
+    return c.value, t.value, r.value, k.value  # constant, monomials, rows, max_len
+
+
+def pmp_hbp_terms(h, n):
+    """(row, degree, coefficient) arrays of the monomials and K_i of the n
+    client rows."""
+    _, T, _, _ = pmp_hbp_info(h)
+    row = np.zeros(T, np.int32)
+    deg = np.zeros(T, np.int32)
+    coef = np.zeros(T, np.int64)
+    rl = np.zeros(n, np.int32)
+    _check(lib().pmp_hbp_terms(h, row.ctypes.data_as(_vp), deg.ctypes.data_as(_vp),
+                               coef.ctypes.data_as(_vp), rl.ctypes.data_as(_vp), 0, None),
+           "pmp_hbp_terms")
+    return row, deg, coef, rl
+
+
+def pmp_hbp_eval(h, masks, fitness, scan_total=None, stream=None, asynchronous=False):
+    """The reduced polynomial at every row of masks into fitness."""
+    mp, dev = _buf(masks, np.uint64, torch.uint64)
+    fp, fdev = _buf(fitness, np.int64, torch.int64)
+    sp, sdev = _buf(scan_total, np.int64, torch.int64)
+    if fdev != dev or (sp is not None and sdev != dev):
+        raise ValueError("all buffers must be host arrays or all CUDA tensors")
+    flags = (PMP_ON_DEVICE | (PMP_ASYNC if asynchronous else 0)) if dev else 0
+    _check(lib().pmp_hbp_eval(h, mp, masks.shape[0], fp, sp, flags,
+                              _stream(stream) if dev else None), "pmp_hbp_eval")
+
+
+def pmp_hbp_destroy(h):
+    lib().pmp_hbp_destroy(h)
 
 
 def pmp_instance_check(inst, stream=None):
@@ -519,6 +573,42 @@ class Instance:
     def close(self):
         if self.handle:
             pmp_instance_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Hbp:
+    """Owning wrapper of a reduced-polynomial handle (its instance must stay
+    open while it is used)."""
+
+    def __init__(self, inst: "Instance", stream=None):
+        self.inst = inst
+        self.handle = pmp_hbp_reduce(inst.handle, stream)
+
+    def info(self):
+        """(constant, monomials, kept rows, longest kept row)."""
+        return pmp_hbp_info(self.handle)
+
+    def terms(self):
+        return pmp_hbp_terms(self.handle, pmp_instance_info(self.inst.handle)[0])
+
+    def eval(self, masks, fitness=None, scan_total=None, stream=None, asynchronous=False):
+        if fitness is None:
+            if isinstance(masks, torch.Tensor):
+                fitness = torch.empty(masks.shape[0], dtype=torch.int64, device=masks.device)
+            else:
+                fitness = np.zeros(masks.shape[0], np.int64)
+        pmp_hbp_eval(self.handle, masks, fitness, scan_total, stream, asynchronous)
+        return fitness
+
+    def close(self):
+        if self.handle:
+            pmp_hbp_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libpmp.so")
 ARCH = "gfx950"
 
 SOURCES = ["k_preprocess.hip", "k_eval.hip", "k_ga.hip", "k_mlp.hip", "k_learn.hip",
-           "k_enum.hip", "k_apsp.hip", "k_eval_schemes.hip", "runtime.hip"]
+           "k_enum.hip", "k_apsp.hip", "k_eval_schemes.hip", "k_hbp.hip", "runtime.hip"]
 
 CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

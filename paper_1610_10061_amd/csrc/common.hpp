@@ -16,6 +16,8 @@ enum : uint32_t {
     ERR_STRAY_BITS = 1u << 2,         // bits set at positions >= m
     ERR_SCAN_OVERRUN = 1u << 3,       // no open facility in a truncated row
     ERR_BARRIER_TIMEOUT = 1u << 4,    // a grid barrier waited past its bound
+    ERR_HASH_TABLE = 1u << 5,         // reduced polynomial: no free slot
+    ERR_HASH_COLLISION = 1u << 6,     // reduced polynomial: two sets, one key
 };
 
 // Device GA run state: 64-bit words.
@@ -49,7 +51,42 @@ struct EvalArgs {
     int32_t clients_per_block;
     int32_t tiles_c;                  // ceil(P / 64)
     int32_t tiles_i;                  // ceil(n / clients_per_block)
+    // reduced-polynomial walk (k_hbp.hip), else null: row lengths K_i and
+    // the int64 running sums replacing t.ds; c0 is added to every fitness
+    const int32_t *rlen;
+    const long long *e64;
+    long long c0;
 };
+
+// Reduced polynomial construction (k_hbp.hip).  t: the instance's tables.
+struct HbpArgs {
+    Tables t;
+    uint64_t *key;                 // n x pitch term keys (0: zero term)
+    int32_t *slot_of;              // n x pitch table slot of each term
+    uint16_t *posinv;              // n x m position in the row (0xFFFF past K)
+    uint64_t *slot_key;            // table: key (0 = free)
+    int32_t *slot_row, *slot_tmin, *slot_tmax;
+    unsigned long long *slot_sum;
+    uint64_t mask;                 // table size - 1 (a power of two)
+    long long *charged;            // n x pitch owned coefficient (0: none)
+    long long *esum;               // n x pitch running sums of charged
+    int32_t *rlen_full, *owned;    // per row: K_i, owned terms
+    int32_t *maxlen;               // max K_i
+    int32_t *kept_at, *term_at;    // per row: compacted row, first term
+    int32_t *tot;                  // kept rows, terms
+    uint16_t *rpi;                 // kept rows x rpitch walk order
+    long long *re;                 // kept rows x rpitch running sums
+    int32_t *rlen;                 // kept rows: K_i
+    int32_t rpitch;
+    int32_t *term_row, *term_deg;  // owned terms, row by row
+    long long *term_coef;
+    unsigned long long *npos;      // positive terms
+    unsigned long long *c0;        // constant: sum of the rows' first terms
+    uint32_t *err;
+};
+hipError_t launch_hbp_keys(const HbpArgs &h, hipStream_t s);
+hipError_t launch_hbp_table(const HbpArgs &h, hipStream_t s);
+hipError_t launch_hbp_emit(const HbpArgs &h, hipStream_t s);
 
 // Index of the calling wave in its workgroup, as a wave-uniform (scalar)
 // value: derived from threadIdx.x the compiler cannot prove it uniform and

@@ -97,7 +97,14 @@ __device__ __forceinline__ int match_sparse(const uint32_t *sm, uint32_t bit,
 // Evaluate chromosome tile tc (64 chromosomes) on client tile ti and store
 // the tile's partial sums.  Called by a whole 256-thread workgroup;
 // smask holds 64 * WD words, sred 2 * kEvalWaves * 64 words.
-template <int WD>
+//
+// R: the walk tables of the reduced polynomial (k_hbp.hip) instead of the
+// instance's: row i stops at position K_i - 1 at the latest (a.rlen) and
+// the value read there is the int64 running sum a.e64.  The stop is made
+// with no extra work in the walk: the last position's lane tests a mask
+// word that is all ones for every chromosome (word 2W of each staged row,
+// so WD > 2W).
+template <int WD, bool R = false>
 __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
                                           uint32_t *smask,
                                           unsigned long long *sred)
@@ -124,7 +131,15 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
     const bool in_row = lane < a.t.K;
     const int last = i1 - 1;
     const uint32_t j_first = a.t.pi[(int64_t)min(i, last) * a.t.pitch + col];
-    int32_t d_cur = a.t.ds[(int64_t)min(i, last) * a.t.pitch + col];
+    int32_t d_cur = 0;
+    long long e_cur = 0;
+    int k_cur = 0;  // R: the row's length K_i
+    if (R) {
+        e_cur = a.e64[(int64_t)min(i, last) * a.t.pitch + col];
+        k_cur = a.rlen[min(i, last)];
+    } else {
+        d_cur = a.t.ds[(int64_t)min(i, last) * a.t.pitch + col];
+    }
     // Masks: every load unconditional at a clamped (always valid) address,
     // in batches, so that a batch costs one round trip; out-of-range words
     // are replaced by 0 when stored.
@@ -151,7 +166,7 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
             const int k = (int)threadIdx.x + (r0 + r) * kThreads;
             const int c = k / WD, w = k - (k / WD) * WD;
             if (k < kTot)
-                smask[k] = (w < W2 && c < rows) ? v[r] : 0u;
+                smask[k] = (w < W2 && c < rows) ? v[r] : ((R && w == W2) ? ~0u : 0u);
         }
     }
     const bool my_act = my_c < a.P && (a.active == nullptr || actv != 0);
@@ -192,9 +207,18 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
     for (; i < i1; i += kEvalWaves) {
         const int inext = min(i + kEvalWaves, last);
         const uint32_t j_nxt = a.t.pi[(int64_t)inext * a.t.pitch + col];
-        const int32_t d_nxt = a.t.ds[(int64_t)inext * a.t.pitch + col];
+        int32_t d_nxt = 0;
+        long long e_nxt = 0;
+        int k_nxt = 0;
+        if (R) {
+            e_nxt = a.e64[(int64_t)inext * a.t.pitch + col];
+            k_nxt = a.rlen[inext];
+        } else {
+            d_nxt = a.t.ds[(int64_t)inext * a.t.pitch + col];
+        }
         const uint16_t *prow = a.t.pi + (int64_t)i * a.t.pitch;
         const int32_t *drow = a.t.ds + (int64_t)i * a.t.pitch;
+        const long long *erow = R ? a.e64 + (int64_t)i * a.t.pitch : nullptr;
         uint64_t pend = act;
         for (int base = 0; pend != 0ull; base += 64) {
             if (base >= a.t.K) {  // fewer than p open facilities
@@ -205,25 +229,47 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
             const int k = base + lane;
             uint32_t off = 0, bit = 0;
             int32_t dist = 0;
+            long long ev = 0;
             if (base == 0) {
                 off = off_cur;
                 bit = bit_cur;
-                dist = d_cur;
+                if (R)
+                    ev = e_cur;
+                else
+                    dist = d_cur;
             } else if (k < a.t.K) {
                 const uint32_t j = prow[k];
                 off = j >> 5;
                 bit = 1u << (j & 31u);
-                dist = drow[k];
+                if (R)
+                    ev = erow[k];
+                else
+                    dist = drow[k];
+            }
+            if (R && k == k_cur - 1) {  // the row's last kept position
+                off = (uint32_t)W2;
+                bit = 1u;
             }
             const uint32_t *sm = smask + off;
             const int hit = (base == 0 || __builtin_popcountll(pend) >= 16)
                                 ? match_dense<WD>(sm, bit, lane, kLanes{})
                                 : match_sparse<WD>(sm, bit, pend, lane);
             const bool found = ((pend >> lane) & 1ull) && hit >= 0;
-            const int32_t cost = __builtin_amdgcn_ds_bpermute((hit & 63) << 2, dist);
-            if (found) {
-                acc += (uint32_t)cost;
-                scn += (uint32_t)(base + hit + 1);
+            if (R) {
+                const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(
+                    (hit & 63) << 2, (int)(uint32_t)(unsigned long long)ev);
+                const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(
+                    (hit & 63) << 2, (int)(uint32_t)((unsigned long long)ev >> 32));
+                if (found) {
+                    acc += ((unsigned long long)hi << 32) | lo;
+                    scn += (uint32_t)(base + hit + 1);
+                }
+            } else {
+                const int32_t cost = __builtin_amdgcn_ds_bpermute((hit & 63) << 2, dist);
+                if (found) {
+                    acc += (uint32_t)cost;
+                    scn += (uint32_t)(base + hit + 1);
+                }
             }
             pend &= ~__builtin_amdgcn_ballot_w64(found);
         }
@@ -232,6 +278,8 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
         off_cur = j_nxt >> 5;
         bit_cur = in_row ? 1u << (j_nxt & 31u) : 0u;
         d_cur = d_nxt;
+        e_cur = e_nxt;
+        k_cur = k_nxt;
     }
 
     sred[wave * kEvalTile + lane] = acc;

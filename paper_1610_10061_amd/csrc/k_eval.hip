@@ -8,7 +8,7 @@ namespace pmp {
 
 namespace {
 
-template <int WD>
+template <int WD, bool R>
 __global__ __launch_bounds__(kEvalTile *kEvalWaves) void k_eval(EvalArgs a)
 {
     __shared__ uint32_t smask[kEvalTile * WD];
@@ -23,14 +23,14 @@ __global__ __launch_bounds__(kEvalTile *kEvalWaves) void k_eval(EvalArgs a)
     if (logical >= ntiles)
         return;
     const int ti = logical / a.tiles_c;
-    eval_tile<WD>(a, ti, logical - ti * a.tiles_c, smask, sred);
+    eval_tile<WD, R>(a, ti, logical - ti * a.tiles_c, smask, sred);
 }
 
 // fitness[c] (and scan[c]) = sum over client tiles of the partial sums.
 __global__ __launch_bounds__(256) void k_reduce(
     const unsigned long long *__restrict__ part, const uint32_t *__restrict__ spart,
     int tiles_i, int P, unsigned long long *__restrict__ fitness,
-    unsigned long long *__restrict__ scan)
+    unsigned long long *__restrict__ scan, long long c0)
 {
     const int c = blockIdx.x * 256 + threadIdx.x;
     if (c >= P)
@@ -41,23 +41,24 @@ __global__ __launch_bounds__(256) void k_reduce(
         if (spart)
             s += spart[(int64_t)t * P + c];
     }
-    fitness[c] = f;
+    fitness[c] = f + (unsigned long long)c0;
     if (scan)
         scan[c] = s;
 }
 
-template <int WD>
+template <int WD, bool R>
 hipError_t launch_wd(const EvalArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     const int tiles = a.tiles_c * a.tiles_i;
     const int grid = ((tiles + 7) / 8) * 8;
+    auto kernel = k_eval<WD, R>;
     if (e0 && e1) {
         // events stamped by the dispatch itself: their interval is the
         // kernel's execution, without the gaps around it
-        hipExtLaunchKernelGGL(k_eval<WD>, dim3(grid), dim3(kEvalTile * kEvalWaves), 0,
+        hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(kEvalTile * kEvalWaves), 0,
                               s, e0, e1, 0, a);
     } else {
-        hipLaunchKernelGGL(k_eval<WD>, dim3(grid), dim3(kEvalTile * kEvalWaves), 0,
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(kEvalTile * kEvalWaves), 0,
                            s, a);
     }
     return hipGetLastError();
@@ -69,7 +70,7 @@ hipError_t launch_reduce(const EvalArgs &a, unsigned long long *fitness,
                          unsigned long long *scan, hipStream_t s)
 {
     hipLaunchKernelGGL(k_reduce, dim3((a.P + 255) / 256), dim3(256), 0, s, a.part,
-                       a.spart, a.tiles_i, a.P, fitness, scan);
+                       a.spart, a.tiles_i, a.P, fitness, scan, a.c0);
     return hipGetLastError();
 }
 
@@ -77,19 +78,25 @@ hipError_t launch_eval(const EvalArgs &a, hipStream_t s, hipEvent_t e0, hipEvent
 {
     if (a.P <= 0 || a.tiles_c <= 0 || a.tiles_i <= 0)
         return hipSuccess;
-    const int w2 = 2 * a.t.W;
-    if (w2 <= 2) return launch_wd<2>(a, s, e0, e1);
-    if (w2 <= 4) return launch_wd<4>(a, s, e0, e1);
-    if (w2 <= 8) return launch_wd<8>(a, s, e0, e1);
-    if (w2 <= 16) return launch_wd<16>(a, s, e0, e1);
-    if (w2 <= 32) return launch_wd<32>(a, s, e0, e1);
-    if (w2 <= 48) return launch_wd<48>(a, s, e0, e1);
-    if (w2 <= 64) return launch_wd<64>(a, s, e0, e1);
-    if (w2 <= 96) return launch_wd<96>(a, s, e0, e1);
-    if (w2 <= 128) return launch_wd<128>(a, s, e0, e1);
-    if (w2 <= 160) return launch_wd<160>(a, s, e0, e1);
-    if (w2 <= 192) return launch_wd<192>(a, s, e0, e1);
-    if (w2 <= 256) return launch_wd<256>(a, s, e0, e1);
+    // the reduced walk needs one spare staged word per chromosome
+    const bool red = a.rlen != nullptr;
+    const int w2 = 2 * a.t.W + (red ? 1 : 0);
+#define PMP_EVAL_WD(N)                                                         \
+    if (w2 <= N)                                                               \
+        return red ? launch_wd<N, true>(a, s, e0, e1) : launch_wd<N, false>(a, s, e0, e1);
+    PMP_EVAL_WD(2)
+    PMP_EVAL_WD(4)
+    PMP_EVAL_WD(8)
+    PMP_EVAL_WD(16)
+    PMP_EVAL_WD(32)
+    PMP_EVAL_WD(48)
+    PMP_EVAL_WD(64)
+    PMP_EVAL_WD(96)
+    PMP_EVAL_WD(128)
+    PMP_EVAL_WD(160)
+    PMP_EVAL_WD(192)
+    PMP_EVAL_WD(256)
+#undef PMP_EVAL_WD
     return hipErrorInvalidValue;
 }
 

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <tuple>
@@ -588,6 +589,284 @@ pmp_status pmp_instance_tables(const pmp_instance *inst, uint16_t *pi,
     if (!(flags & PMP_ON_DEVICE) || !(flags & PMP_ASYNC))
         HIP_TRY(hipStreamSynchronize(s));
     return PMP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The reduced polynomial (k_hbp.hip): construction and evaluation.
+// ---------------------------------------------------------------------------
+struct pmp_hbp {
+    pmp_instance *inst = nullptr;
+    long long c0 = 0;
+    int32_t terms = 0, rows = 0, maxlen = 0, rpitch = 0, kept = 0;
+    uint16_t *rpi = nullptr;
+    long long *re = nullptr;
+    int32_t *rlen = nullptr, *rlen_full = nullptr;
+    int32_t *term_row = nullptr, *term_deg = nullptr;
+    long long *term_coef = nullptr;
+    unsigned long long *part = nullptr, *h_fit = nullptr, *h_scan = nullptr;
+    uint32_t *spart = nullptr;
+    uint64_t *h_masks = nullptr;
+    size_t part_cap = 0;
+    int32_t h_cap = 0;
+    ~pmp_hbp()
+    {
+        dfree(rpi);
+        dfree(re);
+        dfree(rlen);
+        dfree(rlen_full);
+        dfree(term_row);
+        dfree(term_deg);
+        dfree(term_coef);
+        dfree(part);
+        dfree(spart);
+        dfree(h_fit);
+        dfree(h_scan);
+        dfree(h_masks);
+    }
+};
+
+// Temporaries of one construction, freed on every return.
+struct HbpScratch {
+    HbpArgs h{};
+    ~HbpScratch()
+    {
+        dfree(h.key);
+        dfree(h.slot_of);
+        dfree(h.posinv);
+        dfree(h.slot_key);
+        dfree(h.slot_row);
+        dfree(h.slot_tmin);
+        dfree(h.slot_tmax);
+        dfree(h.slot_sum);
+        dfree(h.charged);
+        dfree(h.esum);
+        dfree(h.owned);
+        dfree(h.maxlen);
+        dfree(h.kept_at);
+        dfree(h.term_at);
+        dfree(h.tot);
+        dfree(h.npos);
+        dfree(h.c0);
+        dfree(h.err);
+    }
+};
+
+pmp_status pmp_hbp_reduce(pmp_instance *inst, void *stream, pmp_hbp **out)
+{
+    if (!inst || !out)
+        return fail(PMP_EINVAL, "instance or out is NULL");
+    *out = nullptr;
+    if (2 * inst->W + 1 > 256)
+        return fail(PMP_EUNSUPPORTED, "reduced polynomial: m = %d above 8128", inst->m);
+    hipStream_t s = (hipStream_t)stream;
+    const int n = inst->n, m = inst->m;
+    const size_t cells = (size_t)n * inst->pitch;
+    HbpScratch sc;
+    HbpArgs &h = sc.h;
+    h.t = inst->tables();
+    bool bad = dalloc(&h.key, cells) || dalloc(&h.npos, 1) || dalloc(&h.c0, 1) ||
+               dalloc(&h.err, 1);
+    if (bad)
+        return fail(PMP_ENOMEM, "reduced polynomial keys (n=%d)", n);
+    HIP_TRY(hipMemsetAsync(h.npos, 0, sizeof(unsigned long long), s));
+    HIP_TRY(hipMemsetAsync(h.c0, 0, sizeof(unsigned long long), s));
+    HIP_TRY(hipMemsetAsync(h.err, 0, sizeof(uint32_t), s));
+    HIP_TRY(launch_hbp_keys(h, s));
+    unsigned long long npos = 0;
+    HIP_TRY(hipMemcpyAsync(&npos, h.npos, sizeof npos, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    // table of at least twice the positive terms (load factor <= 1/2)
+    uint64_t cap = 64;
+    while (cap < 2 * npos)
+        cap <<= 1;
+    h.mask = cap - 1;
+    bad = dalloc(&h.slot_of, cells) || dalloc(&h.posinv, (size_t)n * m) ||
+          dalloc(&h.slot_key, cap) || dalloc(&h.slot_row, cap) || dalloc(&h.slot_tmin, cap) ||
+          dalloc(&h.slot_tmax, cap) || dalloc(&h.slot_sum, cap) || dalloc(&h.charged, cells) ||
+          dalloc(&h.esum, cells) || dalloc(&h.owned, (size_t)n) || dalloc(&h.maxlen, 1) ||
+          dalloc(&h.kept_at, (size_t)n) || dalloc(&h.term_at, (size_t)n) || dalloc(&h.tot, 2);
+    if (bad)
+        return fail(PMP_ENOMEM, "reduced polynomial table (%llu slots)", (unsigned long long)cap);
+    pmp_hbp *r = new pmp_hbp;
+    std::unique_ptr<pmp_hbp> guard(r);
+    r->inst = inst;
+    if (dalloc(&r->rlen_full, (size_t)n))
+        return fail(PMP_ENOMEM, "reduced polynomial rows");
+    h.rlen_full = r->rlen_full;
+    HIP_TRY(hipMemsetAsync(h.posinv, 0xFF, sizeof(uint16_t) * (size_t)n * m, s));
+    HIP_TRY(hipMemsetAsync(h.slot_of, 0, sizeof(int32_t) * cells, s));
+    HIP_TRY(hipMemsetAsync(h.slot_key, 0, sizeof(uint64_t) * cap, s));
+    HIP_TRY(hipMemsetAsync(h.slot_row, 0x7F, sizeof(int32_t) * cap, s));
+    HIP_TRY(hipMemsetAsync(h.slot_tmin, 0x7F, sizeof(int32_t) * cap, s));
+    HIP_TRY(hipMemsetAsync(h.slot_tmax, 0, sizeof(int32_t) * cap, s));
+    HIP_TRY(hipMemsetAsync(h.slot_sum, 0, sizeof(unsigned long long) * cap, s));
+    HIP_TRY(hipMemsetAsync(h.maxlen, 0, sizeof(int32_t), s));
+    HIP_TRY(launch_hbp_table(h, s));
+    int32_t tot[2] = {0, 0}, maxlen = 0;
+    uint32_t err = 0;
+    unsigned long long c0 = 0;
+    HIP_TRY(hipMemcpyAsync(tot, h.tot, sizeof tot, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&maxlen, h.maxlen, sizeof maxlen, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&err, h.err, sizeof err, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&c0, h.c0, sizeof c0, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (err & (ERR_HASH_TABLE | ERR_HASH_COLLISION))
+        return fail(PMP_EUNSUPPORTED, "reduced polynomial: set keys collided (error bits 0x%x)",
+                    err);
+    r->c0 = (long long)c0;
+    r->kept = tot[0];
+    r->terms = tot[1];
+    // an instance whose rows all reduce to constants keeps one dummy row
+    // (length 1, value 0) so that the evaluation still checks feasibility
+    r->rows = std::max(1, tot[0]);
+    r->maxlen = std::max(1, maxlen);
+    r->rpitch = ((r->maxlen + 63) / 64) * 64;
+    const size_t rcells = (size_t)r->rows * r->rpitch;
+    bad = dalloc(&r->rpi, rcells) || dalloc(&r->re, rcells) || dalloc(&r->rlen, (size_t)r->rows) ||
+          dalloc(&r->term_row, (size_t)r->terms) || dalloc(&r->term_deg, (size_t)r->terms) ||
+          dalloc(&r->term_coef, (size_t)r->terms);
+    if (bad)
+        return fail(PMP_ENOMEM, "reduced polynomial walk tables (%d rows)", r->rows);
+    if (tot[0] == 0) {
+        const int32_t one = 1;
+        HIP_TRY(hipMemsetAsync(r->rpi, 0, sizeof(uint16_t) * rcells, s));
+        HIP_TRY(hipMemsetAsync(r->re, 0, sizeof(long long) * rcells, s));
+        HIP_TRY(hipMemcpyAsync(r->rlen, &one, sizeof one, hipMemcpyHostToDevice, s));
+    }
+    h.rpi = r->rpi;
+    h.re = r->re;
+    h.rlen = r->rlen;
+    h.rpitch = r->rpitch;
+    h.term_row = r->term_row;
+    h.term_deg = r->term_deg;
+    h.term_coef = r->term_coef;
+    HIP_TRY(launch_hbp_emit(h, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *out = guard.release();
+    return PMP_OK;
+}
+
+pmp_status pmp_hbp_info(const pmp_hbp *hp, int64_t *constant, int64_t *monomials,
+                        int32_t *rows, int32_t *max_len)
+{
+    if (!hp)
+        return fail(PMP_EINVAL, "handle is NULL");
+    if (constant)
+        *constant = hp->c0;
+    if (monomials)
+        *monomials = hp->terms;
+    if (rows)
+        *rows = hp->kept;
+    if (max_len)
+        *max_len = hp->kept ? hp->maxlen : 0;
+    return PMP_OK;
+}
+
+pmp_status pmp_hbp_terms(const pmp_hbp *hp, int32_t *row, int32_t *degree, int64_t *coef,
+                         int32_t *row_len, uint32_t flags, void *stream)
+{
+    if (!hp)
+        return fail(PMP_EINVAL, "handle is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const hipMemcpyKind kind =
+        (flags & PMP_ON_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    const size_t T = (size_t)hp->terms;
+    if (row && T)
+        HIP_TRY(hipMemcpyAsync(row, hp->term_row, sizeof(int32_t) * T, kind, s));
+    if (degree && T)
+        HIP_TRY(hipMemcpyAsync(degree, hp->term_deg, sizeof(int32_t) * T, kind, s));
+    if (coef && T)
+        HIP_TRY(hipMemcpyAsync(coef, hp->term_coef, sizeof(int64_t) * T, kind, s));
+    if (row_len)
+        HIP_TRY(hipMemcpyAsync(row_len, hp->rlen_full, sizeof(int32_t) * hp->inst->n, kind, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return PMP_OK;
+}
+
+pmp_status pmp_hbp_eval(pmp_hbp *hp, const uint64_t *masks, int32_t P, int64_t *fitness,
+                        int64_t *scan_total, uint32_t flags, void *stream)
+{
+    if (!hp)
+        return fail(PMP_EINVAL, "handle is NULL");
+    if (P < 0)
+        return fail(PMP_EINVAL, "P < 0");
+    if (P == 0)
+        return PMP_OK;
+    if (!masks || !fitness)
+        return fail(PMP_EINVAL, "masks or fitness is NULL");
+    pmp_instance *inst = hp->inst;
+    hipStream_t s = (hipStream_t)stream;
+    const bool on_dev = flags & PMP_ON_DEVICE;
+    const bool async = on_dev && (flags & PMP_ASYNC);
+    const size_t W = inst->W;
+    const uint64_t *dmask = masks;
+    unsigned long long *dfit = (unsigned long long *)fitness;
+    unsigned long long *dscan = (unsigned long long *)scan_total;
+    if (!on_dev) {
+        if (hp->h_cap < P) {
+            dfree(hp->h_masks);
+            dfree(hp->h_fit);
+            dfree(hp->h_scan);
+            hp->h_cap = 0;
+            if (dalloc(&hp->h_masks, (size_t)P * W) || dalloc(&hp->h_fit, (size_t)P) ||
+                dalloc(&hp->h_scan, (size_t)P))
+                return fail(PMP_ENOMEM, "staging for P=%d", P);
+            hp->h_cap = P;
+        }
+        HIP_TRY(hipMemcpyAsync(hp->h_masks, masks, sizeof(uint64_t) * P * W,
+                               hipMemcpyHostToDevice, s));
+        dmask = hp->h_masks;
+        dfit = hp->h_fit;
+        dscan = scan_total ? hp->h_scan : nullptr;
+    }
+    if (!async)
+        HIP_TRY(launch_zero(inst->err, sizeof(uint32_t), s));
+    EvalArgs a{};
+    a.t = inst->tables();
+    a.t.pi = hp->rpi;
+    a.t.ds = nullptr;
+    a.t.n = hp->rows;
+    a.t.K = hp->maxlen;
+    a.t.pitch = hp->rpitch;
+    a.rlen = hp->rlen;
+    a.e64 = hp->re;
+    a.c0 = hp->c0;
+    a.masks = dmask;
+    a.P = P;
+    a.err = inst->err;
+    a.clients_per_block = clients_per_block(hp->rows, P);
+    a.tiles_c = (P + kEvalTile - 1) / kEvalTile;
+    a.tiles_i = (hp->rows + a.clients_per_block - 1) / a.clients_per_block;
+    const size_t cells = (size_t)a.tiles_i * P;
+    if (hp->part_cap < cells) {
+        dfree(hp->part);
+        dfree(hp->spart);
+        hp->part_cap = 0;
+        if (dalloc(&hp->part, cells) || dalloc(&hp->spart, cells))
+            return fail(PMP_ENOMEM, "evaluation workspace (%zu cells)", cells);
+        hp->part_cap = cells;
+    }
+    a.part = hp->part;
+    a.spart = dscan ? hp->spart : nullptr;
+    HIP_TRY(launch_eval(a, s));
+    HIP_TRY(launch_reduce(a, dfit, dscan, s));
+    if (!on_dev) {
+        HIP_TRY(hipMemcpyAsync(fitness, dfit, sizeof(int64_t) * P, hipMemcpyDeviceToHost, s));
+        if (scan_total)
+            HIP_TRY(hipMemcpyAsync(scan_total, dscan, sizeof(int64_t) * P,
+                                   hipMemcpyDeviceToHost, s));
+    }
+    if (async)
+        return PMP_OK;
+    uint32_t herr = 0;
+    HIP_TRY(hipMemcpyAsync(&herr, inst->err, sizeof herr, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return status_from_err(herr);
+}
+
+void pmp_hbp_destroy(pmp_hbp *hp)
+{
+    delete hp;
 }
 
 // Work buffers of pmp_apsp, kept per device and grown on demand (a call
