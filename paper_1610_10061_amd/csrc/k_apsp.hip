@@ -15,6 +15,8 @@
 //  - k_fw_rest: every other tile (i, j) takes min over k of
 //    D(i, kb)[., k] + D(kb, j)[k, .] - a min-plus product of the two panel
 //    tiles, staged in LDS, 4 x 4 elements per thread.
+#include <algorithm>
+
 #include "common.hpp"
 
 namespace pmp {
@@ -30,75 +32,146 @@ __device__ __forceinline__ uint32_t tile_at(const uint32_t *D, int ld, int ti, i
     return D[(int64_t)(ti * kTile + r) * ld + tj * kTile + c];
 }
 
-// Close an LDS tile T over its own intermediate vertices: for each k in
-// order, T[i][j] = min(T[i][j], A[i][k] + B[k][j]) with A = T (column k of
-// the tile itself) or A = the diagonal, likewise B.  Row k and column k do
-// not change during step k (the diagonal entry is 0), so updating in place
-// is exact.
-template <bool AfromT, bool BfromT>
-__device__ __forceinline__ void close_tile(uint32_t (*T)[kTile + 1],
-                                           const uint32_t (*Dg)[kTile + 1])
+// A thread's 4 x 4 block of a 64 x 64 tile: rows 4 ty .. 4 ty + 3, columns
+// 4 tx .. 4 tx + 3 (ty = thread / 16, tx = thread % 16).
+struct Block {
+    uint32_t v[4][4];
+};
+
+__device__ __forceinline__ void load_block(Block &b, const uint32_t *D, int ld, int ti, int tj)
+{
+    const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const uint4 q = *reinterpret_cast<const uint4 *>(
+            &D[(int64_t)(ti * kTile + 4 * ty + r) * ld + tj * kTile + 4 * tx]);
+        b.v[r][0] = q.x;
+        b.v[r][1] = q.y;
+        b.v[r][2] = q.z;
+        b.v[r][3] = q.w;
+    }
+}
+
+__device__ __forceinline__ void store_block(const Block &b, uint32_t *D, int ld, int ti, int tj)
+{
+    const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        *reinterpret_cast<uint4 *>(&D[(int64_t)(ti * kTile + 4 * ty + r) * ld + tj * kTile + 4 * tx]) =
+            make_uint4(b.v[r][0], b.v[r][1], b.v[r][2], b.v[r][3]);
+}
+
+// Row k and column k of a tile held in registers, published for step k:
+// the threads holding column k write it to col[k & 1], those holding row k
+// to row[k & 1].  Double buffering needs one barrier per step: a buffer is
+// rewritten two steps later, after every thread has passed the next barrier.
+struct Lines {
+    uint32_t row[2][kTile];
+    uint32_t col[2][kTile];
+};
+
+__device__ __forceinline__ void publish(const Block &b, Lines &L, int k, bool pub_row,
+                                        bool pub_col)
+{
+    const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+    const int q = k & 3;  // selected, not indexed: a run-time index would spill the block
+    if (pub_col && tx == (k >> 2)) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            L.col[k & 1][4 * ty + r] =
+                q == 0 ? b.v[r][0] : q == 1 ? b.v[r][1] : q == 2 ? b.v[r][2] : b.v[r][3];
+    }
+    if (pub_row && ty == (k >> 2)) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            L.row[k & 1][4 * tx + c] =
+                q == 0 ? b.v[0][c] : q == 1 ? b.v[1][c] : q == 2 ? b.v[2][c] : b.v[3][c];
+    }
+}
+
+__device__ __forceinline__ void relax(Block &b, const uint32_t a[4], const uint32_t c[4])
+{
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            b.v[r][q] = min(b.v[r][q], a[r] + c[q]);
+}
+
+__device__ __forceinline__ void read4(const uint32_t *p, uint32_t out[4])
+{
+    const uint4 q = *reinterpret_cast<const uint4 *>(p);
+    out[0] = q.x;
+    out[1] = q.y;
+    out[2] = q.z;
+    out[3] = q.w;
+}
+
+// Close the diagonal tile over its own 64 vertices, in registers: step k
+// relaxes every entry through vertex k (row k and column k do not change
+// during step k, the diagonal entry being 0).
+__device__ __forceinline__ void close_diagonal(Block &g, Lines &L)
 {
     const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
     for (int k = 0; k < kTile; ++k) {
-        uint32_t a[4], b[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-            a[r] = AfromT ? T[4 * ty + r][k] : Dg[4 * ty + r][k];
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-            b[c] = BfromT ? T[k][4 * tx + c] : Dg[k][4 * tx + c];
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                uint32_t &v = T[4 * ty + r][4 * tx + c];
-                v = min(v, a[r] + b[c]);
-            }
+        publish(g, L, k, true, true);
         __syncthreads();
+        uint32_t a[4], c[4];
+        read4(&L.col[k & 1][4 * ty], a);
+        read4(&L.row[k & 1][4 * tx], c);
+        relax(g, a, c);
     }
-}
-
-__device__ __forceinline__ void load_tile(uint32_t (*T)[kTile + 1], const uint32_t *D, int ld,
-                                          int ti, int tj)
-{
-    for (int e = threadIdx.x; e < kTile * kTile; e += 256)
-        T[e >> 6][e & 63] = tile_at(D, ld, ti, tj, e >> 6, e & 63);
-}
-
-__device__ __forceinline__ void store_tile(const uint32_t (*T)[kTile + 1], uint32_t *D, int ld,
-                                           int ti, int tj)
-{
-    for (int e = threadIdx.x; e < kTile * kTile; e += 256)
-        D[(int64_t)(ti * kTile + (e >> 6)) * ld + tj * kTile + (e & 63)] = T[e >> 6][e & 63];
 }
 
 // Phases 1 and 2 of round kb.  Workgroup b < nb: row tile (kb, b);
-// nb <= b < 2 nb: column tile (b - nb, kb).  The diagonal's own workgroups
-// (b = kb and b = nb + kb) close only the diagonal; b = kb stores it.
+// nb <= b < 2 nb: column tile (b - nb, kb).  Every workgroup closes the
+// diagonal tile itself (no extra launch); the diagonal's own workgroups
+// (b = kb and b = nb + kb) stop there, and b = kb stores it.  A row tile
+// then relaxes through the closed diagonal's column k and its own row k, a
+// column tile through its own column k and the diagonal's row k.
 __global__ __launch_bounds__(256) void k_fw_panels(uint32_t *D, int ld, int nb, int kb)
 {
-    __shared__ uint32_t Dg[kTile][kTile + 1];
-    __shared__ uint32_t T[kTile][kTile + 1];
+    __shared__ __attribute__((aligned(16))) Lines L;
+    // the closed diagonal: Gt[k][i] = G[i][k] (columns), G[k][j] (rows)
+    __shared__ __attribute__((aligned(16))) uint32_t Gt[kTile][kTile + 4];
+    __shared__ __attribute__((aligned(16))) uint32_t G[kTile][kTile + 4];
     const int b = blockIdx.x;
     const bool row = b < nb;
     const int other = row ? b : b - nb;
-    load_tile(Dg, D, ld, kb, kb);
-    __syncthreads();
-    close_tile<true, true>(Dg, Dg);
-    if (other == kb) {
+    const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+    const bool diag = other == kb;
+    Block g, t;
+    load_block(g, D, ld, kb, kb);
+    if (!diag)
+        load_block(t, D, ld, row ? kb : other, row ? other : kb);
+    close_diagonal(g, L);
+    if (diag) {
         if (row)
-            store_tile(Dg, D, ld, kb, kb);
+            store_block(g, D, ld, kb, kb);
         return;
     }
-    const int ti = row ? kb : other, tj = row ? other : kb;
-    load_tile(T, D, ld, ti, tj);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            Gt[4 * tx + c][4 * ty + r] = g.v[r][c];
+            G[4 * ty + r][4 * tx + c] = g.v[r][c];
+        }
     __syncthreads();
-    if (row)
-        close_tile<false, true>(T, Dg);  // T[i][j] = min(., Dg[i][k] + T[k][j])
-    else
-        close_tile<true, false>(T, Dg);  // T[i][j] = min(., T[i][k] + Dg[k][j])
-    store_tile(T, D, ld, ti, tj);
+    for (int k = 0; k < kTile; ++k) {
+        publish(t, L, k, row, !row);
+        __syncthreads();
+        uint32_t a[4], c[4];
+        if (row) {
+            read4(&Gt[k][4 * ty], a);
+            read4(&L.row[k & 1][4 * tx], c);
+        } else {
+            read4(&L.col[k & 1][4 * ty], a);
+            read4(&G[k][4 * tx], c);
+        }
+        relax(t, a, c);
+    }
+    store_block(t, D, ld, row ? kb : other, row ? other : kb);
 }
 
 // Phase 3 of round kb: tile (i, j) off row and column kb.  The column-panel
@@ -150,25 +223,28 @@ __global__ __launch_bounds__(256) void k_fw_rest(uint32_t *D, int ld, int nb, in
 }
 
 // Work matrix from the weights: INF where there is no edge (w < 0) and in the
-// padding, 0 on the diagonal, and the largest weight into *wmax.
+// padding, 0 on the diagonal, and the largest weight into *wmax (a grid-stride
+// loop, so that only a few thousand waves meet at the one atomic).
 __global__ __launch_bounds__(256) void k_fw_in(const int32_t *w, int64_t ldw, int n, uint32_t *D,
                                                int ld, uint32_t *wmax)
 {
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const bool in = e < (int64_t)ld * ld;
-    const int i = in ? (int)(e / ld) : 0, j = in ? (int)(e - (int64_t)i * ld) : 0;
-    uint32_t v = kInf, mx = 0;
-    if (in && i < n && j < n) {
-        const int32_t x = w[(int64_t)i * ldw + j];
-        if (x >= 0) {
-            v = (uint32_t)x;
-            mx = v;
+    const int64_t cells = (int64_t)ld * ld;
+    uint32_t mx = 0;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < cells;
+         e += (int64_t)gridDim.x * 256) {
+        const int i = (int)(e / ld), j = (int)(e - (int64_t)i * ld);
+        uint32_t v = kInf;
+        if (i < n && j < n) {
+            const int32_t x = w[(int64_t)i * ldw + j];
+            if (x >= 0) {
+                v = (uint32_t)x;
+                mx = max(mx, v);
+            }
         }
-    }
-    if (i == j)
-        v = 0;
-    if (in)
+        if (i == j)
+            v = 0;
         D[e] = v;
+    }
     // one atomic per wave (every lane takes part in the shuffles)
 #pragma unroll
     for (int dd = 32; dd > 0; dd >>= 1)
@@ -201,8 +277,8 @@ hipError_t launch_apsp_in(const int32_t *w, int64_t ldw, int n, uint32_t *D, uin
 {
     const int ld = apsp_padded(n);
     const int64_t cells = (int64_t)ld * ld;
-    hipLaunchKernelGGL(k_fw_in, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, s, w, ldw, n,
-                       D, ld, wmax);
+    const int64_t blocks = std::min<int64_t>((cells + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_fw_in, dim3((unsigned)blocks), dim3(256), 0, s, w, ldw, n, D, ld, wmax);
     return hipGetLastError();
 }
 
