@@ -48,7 +48,9 @@ def log(*a):
 
 
 COUNTERS = os.path.join(ROOT, "profiles", "k_eval_g900_counters.json")
-EVAL_SOURCES = ("eval_device.hpp", "k_eval.hip")
+# sources that decide what the evaluation dispatches of a GA step read and
+# write: the kernel, and the runtime that builds the schedule of dispatches
+EVAL_SOURCES = ("eval_device.hpp", "k_eval.hip", "runtime.hip")
 
 
 def eval_sources_digest():

@@ -257,6 +257,10 @@ typedef struct {
     int64_t pair_evals;        /* chromosome_evals x n */
     int64_t swap_tried;        /* scored swaps evaluated (learned proposal) */
     int64_t swap_taken;        /* scored swaps that replaced a parent */
+    int64_t speculative_evals; /* mutants evaluated beyond the ones above: the
+                                  per-step schedule evaluates a whole mutation
+                                  cycle at once, also the attempts after its
+                                  first improvement (results unchanged) */
 } pmp_ga_stats;
 
 /* Create a GA run on an instance (the instance must outlive it).

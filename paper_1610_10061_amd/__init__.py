@@ -80,7 +80,7 @@ class GaStats(C.Structure):
         "generations", "saturation_count", "done", "best_cost",
         "chromosome_evals", "crossover_fail", "crossover_taken",
         "mutation_taken", "scan_total", "pair_evals", "swap_tried",
-        "swap_taken")]
+        "swap_taken", "speculative_evals")]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

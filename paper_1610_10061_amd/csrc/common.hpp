@@ -133,11 +133,18 @@ enum GaStat : int {
     CS_MUT_TAKEN = 4,  // mutants taken
     CS_SWAP_TRIED = 5, // scored swaps evaluated
     CS_SWAP_TAKEN = 6, // scored swaps taken
-    CS_COUNT = 7
+    CS_SPEC_EVALS = 7, // mutants evaluated past the cycle's first improvement
+    CS_SPEC_SCAN = 8,  // Pi' entries those evaluations read
+    CS_COUNT = 9
 };
 
 // Kinds of the operator a stage kernel finishes (prev) and starts (op).
-enum GaOp : int { OP_NONE = 0, OP_INIT = 1, OP_XOVER = 2, OP_MUT = 3, OP_SWAP = 4 };
+// OP_MUT_ALL: every attempt of the mutation cycle at once (the mutants of
+// one parent; see ga_resolve_one).
+enum GaOp : int { OP_NONE = 0, OP_INIT = 1, OP_XOVER = 2, OP_MUT = 3, OP_SWAP = 4, OP_MUT_ALL = 5 };
+
+// Largest mutation cycle evaluated at once.
+constexpr int kMaxSpec = 16;
 
 // Operator finished (prev) and started (op) by stage step k of a generation
 // with X crossover stages and S = X + Y stages, of which the first L
@@ -174,6 +181,13 @@ struct GaArgs {
     OpDraw *draws;                  // P x (X + Y) draws of this generation:
                                     // crossover stage k at k, mutation
                                     // attempt a at X + a
+    // the mutation cycle evaluated at once: mutant a of chromosome c at
+    // row c Y + a (P Y x W), its "differs from the parent" flag, and the
+    // evaluation's partial sums (TI x P Y)
+    uint64_t *mut;
+    uint8_t *mut_ok;
+    const unsigned long long *mpart;
+    const uint32_t *mspart;
     uint64_t *cur[2];               // P x W population
     unsigned long long *fit[2];     // P fitness of cur
     uint64_t *off[2];               // P x W offspring
@@ -213,6 +227,7 @@ hipError_t launch_ga_init(const GaArgs &g, hipStream_t s);
 hipError_t launch_ga_stage(const GaArgs &g, int in, int prev, int op,
                            int index, hipStream_t s);
 hipError_t launch_ga_best(const GaArgs &g, int fb, hipStream_t s);
+hipError_t launch_ga_resolve(const GaArgs &g, int in, int out, hipStream_t s);
 // One instance of a batched (persistent) GA launch: its GA state and its
 // evaluation tiling, with its offsets in the batch's global item ranges.
 struct BatchItem {

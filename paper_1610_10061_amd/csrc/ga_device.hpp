@@ -664,11 +664,14 @@ __device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
         cp.v[k] = w < W ? a2 : 0ull;
         opw.v[k] = w < W ? a3 : 0ull;
     }
-    // the operator's draws (the branch is uniform)
+    // the operator's draws (the branch is uniform); for the whole mutation
+    // cycle, lane a loads attempt a's
     OpDraw dr{0, 0, 0, 0};
     if (xo || op == OP_MUT) {
         const int leader = c < pc ? c : pc;
         dr = g.draws[(int64_t)(xo ? leader : c) * (g.X + g.Y) + (xo ? index : g.X + index)];
+    } else if (op == OP_MUT_ALL) {
+        dr = g.draws[(int64_t)c * (g.X + g.Y) + g.X + min(lane, g.Y - 1)];
     }
     if (ga_stopped(g))  // checked once the loads are on their way
         return;
@@ -744,6 +747,18 @@ __device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
             cs_inc += lane == CS_XO_FAIL ? 1ull : 0ull;
     } else if (op == OP_MUT && !improved) {
         ok = mutate_wave(A, F, W, m, lo, hi, move, lane);
+    } else if (op == OP_MUT_ALL) {
+        // every attempt mutates the same parent A (the cycle has not improved
+        // it yet); ga_resolve_one takes the first strictly fitter mutant
+        for (int a = 0; a < g.Y; ++a) {
+            const int lo_a = __builtin_amdgcn_readlane(dr.a, a);
+            const int hi_a = __builtin_amdgcn_readlane(dr.b, a);
+            const int mv_a = __builtin_amdgcn_readlane(dr.c, a);
+            const int64_t row = (int64_t)c * g.Y + a;
+            const bool ch = mutate_wave(A, g.mut + row * W, W, m, lo_a, hi_a, mv_a, lane);
+            if (lane == 0)
+                g.mut_ok[row] = ch ? 1 : 0;
+        }
     } else if (op == OP_SWAP && !improved) {
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
@@ -763,6 +778,106 @@ __device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
         buf(g.ok, out)[c] = ok ? 1 : 0;
     if (lane < CS_COUNT && cs_inc != 0ull)
         cs[lane] = cs_old + cs_inc;
+}
+
+// ---------------------------------------------------------------------------
+// The mutation cycle of chromosome c resolved at once (Evolve step 5).  All
+// Y attempts mutate the same parent - the chromosome as the crossover cycle
+// left it - until one is strictly fitter, after which the cycle stops; so
+// having evaluated every mutant together, taking the first strictly fitter
+// one in attempt order gives exactly the sequential cycle's result.  The
+// counters count what the sequential cycle evaluates (mutants that differ
+// from the parent, up to and including the first improvement); the others
+// go to the speculative counters.  Reads buffer `in`, writes buffer `out`
+// (possibly the same: only chromosome c's own entries are touched, after
+// they have been read).  Needs Y <= kMaxSpec and at most 128 client tiles.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void ga_resolve_one(const GaArgs &g, int c, int lane, int in,
+                                               int out)
+{
+    const int W = g.t.W, Y = g.Y;
+    const int64_t PY = (int64_t)g.P * Y;
+    const unsigned long long fin = buf(g.fit, in)[c];
+    const uint8_t okm = g.mut_ok[(int64_t)c * Y + min(lane, Y - 1)];
+    unsigned long long *cs = g.cstat + (int64_t)c * CS_COUNT;
+    const unsigned long long cs_old = cs[lane < CS_COUNT ? lane : 0];
+    WaveWords cc{};
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        if (k == 1 && W <= 64)
+            break;
+        const int w = lane + 64 * k;
+        const uint64_t v = buf(g.cur, in)[(int64_t)c * W + min(w, W - 1)];
+        cc.v[k] = w < W ? v : 0ull;
+    }
+    // every attempt's partial sums: client tiles lane and lane + 64
+    const bool use0 = lane < g.TI, use1 = lane + 64 < g.TI;
+    const int64_t row0 = (int64_t)min(lane, g.TI - 1) * PY;
+    const int64_t row1 = (int64_t)min(lane + 64, g.TI - 1) * PY;
+    unsigned long long pf[kMaxSpec];
+    uint32_t ps[kMaxSpec];
+#pragma unroll
+    for (int a = 0; a < kMaxSpec; ++a) {
+        pf[a] = 0;
+        ps[a] = 0;
+        if (a < Y) {
+            const int64_t col = (int64_t)c * Y + a;
+            const unsigned long long f0 = g.mpart[row0 + col], f1 = g.mpart[row1 + col];
+            const uint32_t s0 = g.mspart[row0 + col], s1 = g.mspart[row1 + col];
+            pf[a] = (use0 ? f0 : 0ull) + (use1 ? f1 : 0ull);
+            ps[a] = (use0 ? s0 : 0u) + (use1 ? s1 : 0u);
+        }
+    }
+    if (ga_stopped(g))  // checked once the loads are on their way
+        return;
+    int taken = -1;
+    unsigned long long fbest = fin, evals = 0, scan = 0, sevals = 0, sscan = 0;
+#pragma unroll
+    for (int a = 0; a < kMaxSpec; ++a) {
+        if (a < Y) {
+            const bool oka = __builtin_amdgcn_readlane((int)okm, a) != 0;
+            const unsigned long long fa = wave_sum(pf[a]);
+            const unsigned long long sa = wave_sum((unsigned long long)ps[a]);
+            if (oka) {
+                if (taken < 0) {
+                    evals += 1;
+                    scan += sa;
+                    if (fa < fin) {
+                        taken = a;
+                        fbest = fa;
+                    }
+                } else {
+                    sevals += 1;
+                    sscan += sa;
+                }
+            }
+        }
+    }
+    uint64_t *cur = buf(g.cur, out) + (int64_t)c * W;
+    if (taken >= 0) {
+        const uint64_t *src = g.mut + ((int64_t)c * Y + taken) * W;
+        for (int w = lane; w < W; w += 64)
+            cur[w] = src[w];
+    } else {
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+            if (lane + 64 * k < W)
+                cur[lane + 64 * k] = cc.v[k];
+    }
+    if (lane == 0) {
+        buf(g.fit, out)[c] = fbest;
+        buf(g.ok, out)[c] = 0;
+        if (taken >= 0)
+            g.improved[c] = 1;
+    }
+    unsigned long long inc = 0;
+    inc += lane == CS_EVALS ? evals : 0ull;
+    inc += lane == CS_SCAN ? scan : 0ull;
+    inc += (lane == CS_MUT_TAKEN && taken >= 0) ? 1ull : 0ull;
+    inc += lane == CS_SPEC_EVALS ? sevals : 0ull;
+    inc += lane == CS_SPEC_SCAN ? sscan : 0ull;
+    if (lane < CS_COUNT && inc != 0ull)
+        cs[lane] = cs_old + inc;
 }
 
 // Reduce (cost, index) pairs of a workgroup to the least cost, lowest index

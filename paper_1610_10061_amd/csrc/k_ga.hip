@@ -36,6 +36,16 @@ __global__ __launch_bounds__(64 * kGaWaves) void k_stage(GaArgs g, int in,
     ga_stage_one(g, c, lane, in, prev, op, index);  // checks the stop flag itself
 }
 
+// The mutation cycle resolved at once (ga_resolve_one), a wave per chromosome.
+__global__ __launch_bounds__(64 * kGaWaves) void k_resolve(GaArgs g, int in, int out)
+{
+    const int wave = wave_id(), lane = threadIdx.x & 63;
+    const int c = blockIdx.x * kGaWaves + wave;
+    if (c >= g.P)
+        return;
+    ga_resolve_one(g, c, lane, in, out);
+}
+
 // Group best per workgroup; the last workgroup to finish does the global
 // update (release fence before the arrival count, acquire fence after).
 __global__ __launch_bounds__(1024) void k_best(GaArgs g, int fb)
@@ -443,6 +453,12 @@ hipError_t launch_ga_stage(const GaArgs &g, int in, int prev, int op, int index,
 {
     hipLaunchKernelGGL(k_stage, per_wave(g.P), dim3(64 * kGaWaves), 0, s, g, in,
                        prev, op, index);
+    return hipGetLastError();
+}
+
+hipError_t launch_ga_resolve(const GaArgs &g, int in, int out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_resolve, per_wave(g.P), dim3(64 * kGaWaves), 0, s, g, in, out);
     return hipGetLastError();
 }
 

@@ -191,6 +191,13 @@ struct pmp_ga {
     uint8_t *ok[2] = {nullptr, nullptr};
     uint8_t *improved = nullptr;
     OpDraw *draws = nullptr;
+    // the mutation cycle evaluated at once (allocated on first use)
+    uint64_t *mut = nullptr;
+    uint8_t *mut_ok = nullptr;
+    unsigned long long *mpart = nullptr;
+    uint32_t *mspart = nullptr;
+    int spec_ti = 0;  // client tiles mpart was sized for
+    bool spec_on = true;
     unsigned long long *part = nullptr;
     uint32_t *spart = nullptr;
     uint64_t *gmask = nullptr, *best = nullptr;
@@ -232,6 +239,37 @@ struct pmp_ga {
     int xstages() const { return (inst->p >= 2 && lg > 0) ? X : 0; }
     // buffer holding the population after a generation's last stage
     int final_buf() const { return ((xstages() + Y) % 2) ^ 1; }
+    // the per-step schedule evaluates the whole mutation cycle at once (one
+    // evaluation of P x Y mutants instead of Y dependent ones); the batched
+    // and persistent schedules, and the learned proposal, run it attempt by
+    // attempt.  Both give the same results.
+    bool spec() const
+    {
+        return spec_on && !model && Y >= 2 && Y <= kMaxSpec && TI <= 128;
+    }
+    hipError_t ensure_spec()
+    {
+        const size_t PY = (size_t)prm.population * Y;
+        if (!mut) {
+            hipError_t e = dalloc(&mut, PY * inst->W);
+            if (e == hipSuccess)
+                e = dalloc(&mut_ok, PY);
+            if (e != hipSuccess)
+                return e;
+        }
+        if (spec_ti != TI) {
+            dfree(mpart);
+            dfree(mspart);
+            spec_ti = 0;
+            hipError_t e = dalloc(&mpart, PY * TI);
+            if (e == hipSuccess)
+                e = dalloc(&mspart, PY * TI);
+            if (e != hipSuccess)
+                return e;
+            spec_ti = TI;
+        }
+        return hipSuccess;
+    }
 
     GaArgs args() const
     {
@@ -255,6 +293,10 @@ struct pmp_ga {
         }
         g.improved = improved;
         g.draws = draws;
+        g.mut = mut;
+        g.mut_ok = mut_ok;
+        g.mpart = mpart;
+        g.mspart = mspart;
         g.part = part;
         g.spart = spart;
         g.TI = TI;
@@ -1065,6 +1107,10 @@ void pmp_ga_destroy(pmp_ga *ga)
     }
     dfree(ga->improved);
     dfree(ga->draws);
+    dfree(ga->mut);
+    dfree(ga->mut_ok);
+    dfree(ga->mpart);
+    dfree(ga->mspart);
     dfree(ga->part);
     dfree(ga->spart);
     dfree(ga->gmask);
@@ -1157,6 +1203,7 @@ pmp_status pmp_ga_create(pmp_instance *inst, const pmp_ga_params *prm,
         ga->max_blocks = env_int("PMP_GA_BLOCKS", 0);
         ga->graph_gens = (mode && strcmp(mode, "kernels") == 0) ? 0
                                                                 : env_int("PMP_GA_GRAPH_GENS", 8);
+        ga->spec_on = env_int("PMP_GA_SPEC", 1) != 0;
     }
     if (e == hipSuccess)
         e = hipDeviceSynchronize();
@@ -1211,7 +1258,7 @@ hipError_t mark(pmp_ga *ga, hipStream_t s)
 
 // Evaluate the offspring buffer `buf` (only slots flagged in ok[buf]); when
 // profiling, with a pair of events stamped by the launch itself.
-hipError_t ga_eval(pmp_ga *ga, const GaArgs &g, int buf, hipStream_t s)
+hipError_t ga_eval(pmp_ga *ga, const GaArgs &g, int buf, hipStream_t s, bool mutants = false)
 {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (ga->prof) {
@@ -1220,7 +1267,17 @@ hipError_t ga_eval(pmp_ga *ga, const GaArgs &g, int buf, hipStream_t s)
         if (!e0 || !e1)
             return hipErrorOutOfMemory;
     }
-    return launch_eval(ga_eval_args(ga, g, buf), s, e0, e1);
+    EvalArgs a = ga_eval_args(ga, g, buf);
+    if (mutants) {
+        // the P x Y mutants of the mutation cycle, evaluated at once
+        a.masks = g.mut;
+        a.P = g.P * g.Y;
+        a.active = g.mut_ok;
+        a.part = ga->mpart;
+        a.spart = ga->mspart;
+        a.tiles_c = (a.P + kEvalTile - 1) / kEvalTile;
+    }
+    return launch_eval(a, s, e0, e1);
 }
 
 // Host-side totals of the per-chromosome counters.
@@ -1248,6 +1305,33 @@ hipError_t enqueue_generations(pmp_ga *ga, const GaArgs &g, int generations,
 {
     const int X = ga->xstages(), S = X + ga->Y, L = g.L;
     const bool train = L > 0 && ga->Levery > 0;
+    if (ga->spec()) {
+        // crossover stages as usual; stage X finishes the last crossover and
+        // makes all Y mutants; one evaluation; the cycle is resolved
+        for (int gen = 0; gen < generations; ++gen) {
+            hipError_t e = launch_ga_init(g, s);
+            if (e == hipSuccess)
+                e = ga_eval(ga, g, 0, s);
+            for (int k = 0; k < X && e == hipSuccess; ++k) {
+                int prev, op, index;
+                ga_stage_ops(k, X, S, &prev, &op, &index, 0);
+                e = launch_ga_stage(g, k & 1, prev, op, index, s);
+                if (e == hipSuccess)
+                    e = ga_eval(ga, g, (k & 1) ^ 1, s);
+            }
+            if (e == hipSuccess)
+                e = launch_ga_stage(g, X & 1, X == 0 ? OP_INIT : OP_XOVER, OP_MUT_ALL, 0, s);
+            if (e == hipSuccess)
+                e = ga_eval(ga, g, 0, s, true);
+            if (e == hipSuccess)
+                e = launch_ga_resolve(g, (X & 1) ^ 1, ga->final_buf(), s);
+            if (e == hipSuccess)
+                e = launch_ga_best(g, ga->final_buf(), s);
+            if (e != hipSuccess)
+                return e;
+        }
+        return hipSuccess;
+    }
     for (int gen = 0; gen < generations; ++gen) {
         hipError_t e = launch_ga_init(g, s);
         if (e == hipSuccess)
@@ -1326,6 +1410,9 @@ pmp_status pmp_ga_step(pmp_ga *ga, int32_t generations, void *stream)
     if (generations == 0)
         return PMP_OK;
     hipStream_t s = (hipStream_t)stream;
+    if (!ga->persistent && ga->spec() && ga->ensure_spec() != hipSuccess)
+        return fail(PMP_ENOMEM, "mutation-cycle buffers for P=%d, Y=%d", ga->prm.population,
+                    ga->Y);
     const GaArgs g = ga->args();
     if (ga->persistent) {
         if (ga->model)
@@ -1380,6 +1467,7 @@ pmp_status pmp_ga_best(pmp_ga *ga, uint64_t *mask, int64_t *cost,
         stats->pair_evals = (int64_t)tot[CS_EVALS] * ga->inst->n;
         stats->swap_tried = (int64_t)tot[CS_SWAP_TRIED];
         stats->swap_taken = (int64_t)tot[CS_SWAP_TAKEN];
+        stats->speculative_evals = (int64_t)tot[CS_SPEC_EVALS];
     }
     uint32_t herr = 0;
     HIP_TRY(hipMemcpy(&herr, ga->inst->err, sizeof herr, hipMemcpyDeviceToHost));
@@ -1424,8 +1512,8 @@ pmp_status pmp_ga_profile(pmp_ga *ga, int32_t enable)
     HIP_TRY(ga_counters(ga, tot));
     ga->prof = enable != 0;
     ga->ev_used = 0;
-    ga->base_scan = tot[CS_SCAN];
-    ga->base_evals = tot[CS_EVALS];
+    ga->base_scan = tot[CS_SCAN] + tot[CS_SPEC_SCAN];
+    ga->base_evals = tot[CS_EVALS] + tot[CS_SPEC_EVALS];
     return PMP_OK;
 }
 
@@ -1443,16 +1531,18 @@ pmp_status pmp_ga_profile_read(pmp_ga *ga, pmp_profile *out, void *stream)
     }
     unsigned long long tot[CS_COUNT];
     HIP_TRY(ga_counters(ga, tot));
-    const int64_t evals = (int64_t)(tot[CS_EVALS] - ga->base_evals);
-    const int64_t scan = (int64_t)(tot[CS_SCAN] - ga->base_scan);
+    // every evaluation the kernel ran, the mutation cycle's speculative ones
+    // included
+    const int64_t evals = (int64_t)(tot[CS_EVALS] + tot[CS_SPEC_EVALS] - ga->base_evals);
+    const int64_t scan = (int64_t)(tot[CS_SCAN] + tot[CS_SPEC_SCAN] - ga->base_scan);
     const int64_t pairs = evals * ga->inst->n;
     out->eval_ms = ms;
     out->eval_launches = (int64_t)(ga->ev_used / 2);
     out->eval_pairs = pairs;
     out->eval_bytes = 2 * scan + 4 * pairs + evals * (8 * (int64_t)ga->inst->W + 8);
     ga->ev_used = 0;
-    ga->base_scan = tot[CS_SCAN];
-    ga->base_evals = tot[CS_EVALS];
+    ga->base_scan = tot[CS_SCAN] + tot[CS_SPEC_SCAN];
+    ga->base_evals = tot[CS_EVALS] + tot[CS_SPEC_EVALS];
     return PMP_OK;
 }
 

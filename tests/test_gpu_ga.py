@@ -27,13 +27,15 @@ def pm():
 
 # launch schemes: per-step kernels replayed from a hipGraph of 2 generations
 # (the default scheme, with a chunk small enough to replay here), per-step
-# kernels launched one by one, one persistent cooperative kernel, and the
-# same with a grid of 8 workgroups (every phase loops)
+# kernels launched one by one, the per-step kernels with the mutation cycle
+# run attempt by attempt instead of at once, one persistent cooperative
+# kernel, and the same with a grid of 8 workgroups (every phase loops)
 MODES = {"graph": {"PMP_GA_GRAPH_GENS": "2"},
          "kernels": {"PMP_GA_MODE": "kernels"},
+         "sequential": {"PMP_GA_GRAPH_GENS": "2", "PMP_GA_SPEC": "0"},
          "persistent": {"PMP_GA_MODE": "persistent"},
          "persistent_8wg": {"PMP_GA_MODE": "persistent", "PMP_GA_BLOCKS": "8"}}
-_ENV = ("PMP_GA_MODE", "PMP_GA_BLOCKS", "PMP_GA_GRAPH_GENS")
+_ENV = ("PMP_GA_MODE", "PMP_GA_BLOCKS", "PMP_GA_GRAPH_GENS", "PMP_GA_SPEC")
 
 
 @pytest.fixture(params=list(MODES))
@@ -172,3 +174,15 @@ def test_ga_dense_subsets(pm, m, p):
     draws inside and across the sampler's 64-draw batches."""
     d = np.random.default_rng(m + p).integers(0, 200, size=(40, m)).astype(np.int32)
     _compare(pm, d, p, 64, 16, 3, seed=21, steps=[2])
+
+
+def test_mutation_cycle_at_once_counts(pm, mode):
+    """Evaluating the mutation cycle at once evaluates mutants beyond the
+    first improvement (counted apart); attempt by attempt it does not.  The
+    algorithm's own counters match the oracle either way (_compare)."""
+    d = gi.graph_instance(100, 200, 3)
+    s = _compare(pm, d, 5, 128, 32, 10, seed=2, steps=[3])
+    if mode in ("graph", "kernels"):
+        assert s["speculative_evals"] > 0
+    else:
+        assert s["speculative_evals"] == 0
