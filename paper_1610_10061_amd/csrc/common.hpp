@@ -143,8 +143,8 @@ enum GaStat : int {
 // one parent; see ga_resolve_one).
 enum GaOp : int { OP_NONE = 0, OP_INIT = 1, OP_XOVER = 2, OP_MUT = 3, OP_SWAP = 4, OP_MUT_ALL = 5 };
 
-// Largest mutation cycle evaluated at once.
-constexpr int kMaxSpec = 16;
+// Largest mutation cycle evaluated at once (lanes of a wave).
+constexpr int kMaxSpec = 64;
 
 // Operator finished (prev) and started (op) by stage step k of a generation
 // with X crossover stages and S = X + Y stages, of which the first L
@@ -188,6 +188,7 @@ struct GaArgs {
     uint8_t *mut_ok;
     const unsigned long long *mpart;
     const uint32_t *mspart;
+    int32_t TIm;                    // client tiles of the mutants' evaluation
     uint64_t *cur[2];               // P x W population
     unsigned long long *fit[2];     // P fitness of cur
     uint64_t *off[2];               // P x W offspring

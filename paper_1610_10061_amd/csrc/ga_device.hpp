@@ -604,10 +604,15 @@ __device__ __forceinline__ bool mutate_wave(const WaveWords &A, uint64_t *F,
 // loads are issued together; the operators then work on the words held by
 // the lanes.
 // ---------------------------------------------------------------------------
+//
+// With op = OP_MUT_ALL the stage runs on Y waves per chromosome: wave `sub`
+// makes mutant `sub` of the parent, and only wave 0 writes the chromosome's
+// own state (every wave computes the same parent from the same loads).
 __device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
                                              int in, int prev, int op,
-                                             int index)
+                                             int index, int sub = 0)
 {
+    const bool primary = sub == 0;
     const int out = in ^ 1;
     const int W = g.t.W, m = g.t.m;
     const bool xo = op == OP_XOVER;
@@ -703,7 +708,7 @@ __device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
     uint64_t *cur = buf(g.cur, out) + (int64_t)c * W;
 #pragma unroll
     for (int k = 0; k < 2; ++k)
-        if (lane + 64 * k < W)
+        if (primary && lane + 64 * k < W)
             cur[lane + 64 * k] = A.v[k];
     const bool mut_prev = prev == OP_MUT || prev == OP_SWAP;
     const bool improved = was_improved || (mut_prev && take);
@@ -719,7 +724,7 @@ __device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
         cs_inc += lane == (prev == OP_MUT ? CS_MUT_TAKEN : CS_SWAP_TAKEN) ? 1ull : 0ull;
     if (prev == OP_SWAP && okc)
         cs_inc += lane == CS_SWAP_TRIED ? 1ull : 0ull;
-    if (lane == 0) {
+    if (primary && lane == 0) {
         buf(g.fit, out)[c] = take ? fo : fin;
         if (take && mut_prev)
             g.improved[c] = 1;
@@ -750,15 +755,13 @@ __device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
     } else if (op == OP_MUT_ALL) {
         // every attempt mutates the same parent A (the cycle has not improved
         // it yet); ga_resolve_one takes the first strictly fitter mutant
-        for (int a = 0; a < g.Y; ++a) {
-            const int lo_a = __builtin_amdgcn_readlane(dr.a, a);
-            const int hi_a = __builtin_amdgcn_readlane(dr.b, a);
-            const int mv_a = __builtin_amdgcn_readlane(dr.c, a);
-            const int64_t row = (int64_t)c * g.Y + a;
-            const bool ch = mutate_wave(A, g.mut + row * W, W, m, lo_a, hi_a, mv_a, lane);
-            if (lane == 0)
-                g.mut_ok[row] = ch ? 1 : 0;
-        }
+        const int lo_a = __builtin_amdgcn_readlane(dr.a, sub);
+        const int hi_a = __builtin_amdgcn_readlane(dr.b, sub);
+        const int mv_a = __builtin_amdgcn_readlane(dr.c, sub);
+        const int64_t row = (int64_t)c * g.Y + sub;
+        const bool ch = mutate_wave(A, g.mut + row * W, W, m, lo_a, hi_a, mv_a, lane);
+        if (lane == 0)
+            g.mut_ok[row] = ch ? 1 : 0;
     } else if (op == OP_SWAP && !improved) {
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
@@ -774,110 +777,93 @@ __device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
         }
         ok = true;
     }
-    if (lane == 0)
+    if (primary && lane == 0)
         buf(g.ok, out)[c] = ok ? 1 : 0;
-    if (lane < CS_COUNT && cs_inc != 0ull)
+    if (primary && lane < CS_COUNT && cs_inc != 0ull)
         cs[lane] = cs_old + cs_inc;
 }
 
 // ---------------------------------------------------------------------------
-// The mutation cycle of chromosome c resolved at once (Evolve step 5).  All
-// Y attempts mutate the same parent - the chromosome as the crossover cycle
-// left it - until one is strictly fitter, after which the cycle stops; so
-// having evaluated every mutant together, taking the first strictly fitter
-// one in attempt order gives exactly the sequential cycle's result.  The
-// counters count what the sequential cycle evaluates (mutants that differ
-// from the parent, up to and including the first improvement); the others
-// go to the speculative counters.  Reads buffer `in`, writes buffer `out`
-// (possibly the same: only chromosome c's own entries are touched, after
-// they have been read).  Needs Y <= kMaxSpec and at most 128 client tiles.
+// The mutation cycle resolved at once (Evolve step 5).  All Y attempts mutate
+// the same parent - the chromosome as the crossover cycle left it - until one
+// is strictly fitter, after which the cycle stops; so having evaluated every
+// mutant together, taking the first strictly fitter one in attempt order
+// gives exactly the sequential cycle's result.  The counters count what the
+// sequential cycle evaluates (mutants that differ from the parent, up to and
+// including the first improvement); the others go to the speculative
+// counters.
+//
+// A wave takes 64 / YP chromosomes (YP = Y rounded up to a power of two),
+// lane (c, a) for mutant a of chromosome c: it adds up its mutant's client
+// tile partial sums (consecutive lanes read consecutive entries), and a
+// ballot over the chromosome's lanes finds the first improvement.  Reads
+// buffer `in`, writes buffer `out` (possibly the same: a lane reads the words
+// it then writes).  Y <= 64.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void ga_resolve_one(const GaArgs &g, int c, int lane, int in,
-                                               int out)
+__device__ __forceinline__ void ga_resolve_wave(const GaArgs &g, int gw, int lane, int YP,
+                                                int in, int out)
 {
     const int W = g.t.W, Y = g.Y;
     const int64_t PY = (int64_t)g.P * Y;
-    const unsigned long long fin = buf(g.fit, in)[c];
-    const uint8_t okm = g.mut_ok[(int64_t)c * Y + min(lane, Y - 1)];
-    unsigned long long *cs = g.cstat + (int64_t)c * CS_COUNT;
-    const unsigned long long cs_old = cs[lane < CS_COUNT ? lane : 0];
-    WaveWords cc{};
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        if (k == 1 && W <= 64)
-            break;
-        const int w = lane + 64 * k;
-        const uint64_t v = buf(g.cur, in)[(int64_t)c * W + min(w, W - 1)];
-        cc.v[k] = w < W ? v : 0ull;
+    const int per = 64 / YP, grp = lane / YP, a = lane - grp * YP;
+    const int c = gw * per + grp;
+    const bool valid_c = c < g.P, valid = valid_c && a < Y;
+    const int cc = min(c, g.P - 1);
+    const int64_t row = (int64_t)cc * Y + min(a, Y - 1);
+    const uint8_t okm = g.mut_ok[row];
+    const unsigned long long fin = buf(g.fit, in)[cc];
+    unsigned long long *cs = g.cstat + (int64_t)cc * CS_COUNT;
+    // the group leader's counters (the other lanes load them too, unused)
+    const unsigned long long c_ev = cs[CS_EVALS], c_sc = cs[CS_SCAN], c_mt = cs[CS_MUT_TAKEN];
+    const unsigned long long c_se = cs[CS_SPEC_EVALS], c_ss = cs[CS_SPEC_SCAN];
+    unsigned long long f = 0, sc = 0;
+#pragma unroll 8
+    for (int t = 0; t < g.TIm; ++t) {
+        f += g.mpart[(int64_t)t * PY + row];
+        sc += g.mspart[(int64_t)t * PY + row];
     }
-    // every attempt's partial sums: client tiles lane and lane + 64
-    const bool use0 = lane < g.TI, use1 = lane + 64 < g.TI;
-    const int64_t row0 = (int64_t)min(lane, g.TI - 1) * PY;
-    const int64_t row1 = (int64_t)min(lane + 64, g.TI - 1) * PY;
-    unsigned long long pf[kMaxSpec];
-    uint32_t ps[kMaxSpec];
-#pragma unroll
-    for (int a = 0; a < kMaxSpec; ++a) {
-        pf[a] = 0;
-        ps[a] = 0;
-        if (a < Y) {
-            const int64_t col = (int64_t)c * Y + a;
-            const unsigned long long f0 = g.mpart[row0 + col], f1 = g.mpart[row1 + col];
-            const uint32_t s0 = g.mspart[row0 + col], s1 = g.mspart[row1 + col];
-            pf[a] = (use0 ? f0 : 0ull) + (use1 ? f1 : 0ull);
-            ps[a] = (use0 ? s0 : 0u) + (use1 ? s1 : 0u);
-        }
-    }
-    if (ga_stopped(g))  // checked once the loads are on their way
+    if (ga_stopped(g))  // checked once the loads are on their way (uniform)
         return;
-    int taken = -1;
-    unsigned long long fbest = fin, evals = 0, scan = 0, sevals = 0, sscan = 0;
-#pragma unroll
-    for (int a = 0; a < kMaxSpec; ++a) {
-        if (a < Y) {
-            const bool oka = __builtin_amdgcn_readlane((int)okm, a) != 0;
-            const unsigned long long fa = wave_sum(pf[a]);
-            const unsigned long long sa = wave_sum((unsigned long long)ps[a]);
-            if (oka) {
-                if (taken < 0) {
-                    evals += 1;
-                    scan += sa;
-                    if (fa < fin) {
-                        taken = a;
-                        fbest = fa;
-                    }
-                } else {
-                    sevals += 1;
-                    sscan += sa;
-                }
-            }
+    const bool ok_l = valid && okm != 0;
+    const uint64_t gmask = (YP == 64 ? ~0ull : ((1ull << YP) - 1ull)) << (grp * YP);
+    const uint64_t imp = __builtin_amdgcn_ballot_w64(ok_l && f < fin) & gmask;
+    const int first = imp ? __builtin_ctzll(imp) : -1;  // lane of the taken mutant
+    const uint64_t upto = first < 0 ? ~0ull : (first == 63 ? ~0ull : ((2ull << first) - 1ull));
+    const bool counted = ok_l && ((upto >> lane) & 1ull);
+    const bool spec = ok_l && !counted;
+    unsigned long long s_cnt = counted ? sc : 0ull, s_spec = spec ? sc : 0ull;
+    for (int d = 1; d < YP; d <<= 1) {  // sums within the chromosome's lanes
+        s_cnt += __shfl_xor(s_cnt, d);
+        s_spec += __shfl_xor(s_spec, d);
+    }
+    const int n_cnt = __builtin_popcountll(__builtin_amdgcn_ballot_w64(counted) & gmask);
+    const int n_spec = __builtin_popcountll(__builtin_amdgcn_ballot_w64(spec) & gmask);
+    const unsigned long long f_taken = __shfl(f, first < 0 ? lane : first);
+    const int taken = first < 0 ? -1 : first - grp * YP;
+    // the chromosome: the taken mutant or the parent, word w by lane w mod YP
+    if (valid_c) {
+        uint64_t *dst = buf(g.cur, out) + (int64_t)cc * W;
+        const uint64_t *src = taken >= 0 ? g.mut + ((int64_t)cc * Y + taken) * W
+                                         : buf(g.cur, in) + (int64_t)cc * W;
+        for (int w = a; w < W; w += YP)
+            dst[w] = src[w];
+    }
+    if (valid_c && a == 0) {
+        buf(g.fit, out)[cc] = taken >= 0 ? f_taken : fin;
+        buf(g.ok, out)[cc] = 0;
+        if (taken >= 0)
+            g.improved[cc] = 1;
+        if (n_cnt) {
+            cs[CS_EVALS] = c_ev + (unsigned long long)n_cnt;
+            cs[CS_SCAN] = c_sc + s_cnt;
+        }
+        if (taken >= 0)
+            cs[CS_MUT_TAKEN] = c_mt + 1ull;
+        if (n_spec) {
+            cs[CS_SPEC_EVALS] = c_se + (unsigned long long)n_spec;
+            cs[CS_SPEC_SCAN] = c_ss + s_spec;
         }
     }
-    uint64_t *cur = buf(g.cur, out) + (int64_t)c * W;
-    if (taken >= 0) {
-        const uint64_t *src = g.mut + ((int64_t)c * Y + taken) * W;
-        for (int w = lane; w < W; w += 64)
-            cur[w] = src[w];
-    } else {
-#pragma unroll
-        for (int k = 0; k < 2; ++k)
-            if (lane + 64 * k < W)
-                cur[lane + 64 * k] = cc.v[k];
-    }
-    if (lane == 0) {
-        buf(g.fit, out)[c] = fbest;
-        buf(g.ok, out)[c] = 0;
-        if (taken >= 0)
-            g.improved[c] = 1;
-    }
-    unsigned long long inc = 0;
-    inc += lane == CS_EVALS ? evals : 0ull;
-    inc += lane == CS_SCAN ? scan : 0ull;
-    inc += (lane == CS_MUT_TAKEN && taken >= 0) ? 1ull : 0ull;
-    inc += lane == CS_SPEC_EVALS ? sevals : 0ull;
-    inc += lane == CS_SPEC_SCAN ? sscan : 0ull;
-    if (lane < CS_COUNT && inc != 0ull)
-        cs[lane] = cs_old + inc;
 }
 
 // Reduce (cost, index) pairs of a workgroup to the least cost, lowest index

@@ -30,20 +30,23 @@ __global__ __launch_bounds__(64 * kGaWaves) void k_stage(GaArgs g, int in,
                                                          int index)
 {
     const int wave = wave_id(), lane = threadIdx.x & 63;
-    const int c = blockIdx.x * kGaWaves + wave;
+    const int gw = blockIdx.x * kGaWaves + wave;
+    // the whole mutation cycle at once: Y waves per chromosome
+    const int per = op == OP_MUT_ALL ? g.Y : 1;
+    const int c = gw / per, sub = gw - c * per;
     if (c >= g.P)
         return;
-    ga_stage_one(g, c, lane, in, prev, op, index);  // checks the stop flag itself
+    ga_stage_one(g, c, lane, in, prev, op, index, sub);  // checks the stop flag itself
 }
 
-// The mutation cycle resolved at once (ga_resolve_one), a wave per chromosome.
-__global__ __launch_bounds__(64 * kGaWaves) void k_resolve(GaArgs g, int in, int out)
+// The mutation cycle resolved at once (ga_resolve_wave): 64 / YP
+// chromosomes per wave.
+__global__ __launch_bounds__(64 * kGaWaves) void k_resolve(GaArgs g, int YP, int in, int out)
 {
-    const int wave = wave_id(), lane = threadIdx.x & 63;
-    const int c = blockIdx.x * kGaWaves + wave;
-    if (c >= g.P)
+    const int gw = blockIdx.x * kGaWaves + wave_id();
+    if (gw * (64 / YP) >= g.P)
         return;
-    ga_resolve_one(g, c, lane, in, out);
+    ga_resolve_wave(g, gw, threadIdx.x & 63, YP, in, out);
 }
 
 // Group best per workgroup; the last workgroup to finish does the global
@@ -451,14 +454,20 @@ hipError_t launch_ga_init(const GaArgs &g, hipStream_t s)
 hipError_t launch_ga_stage(const GaArgs &g, int in, int prev, int op, int index,
                            hipStream_t s)
 {
-    hipLaunchKernelGGL(k_stage, per_wave(g.P), dim3(64 * kGaWaves), 0, s, g, in,
+    const int waves = op == OP_MUT_ALL ? g.P * g.Y : g.P;
+    hipLaunchKernelGGL(k_stage, per_wave(waves), dim3(64 * kGaWaves), 0, s, g, in,
                        prev, op, index);
     return hipGetLastError();
 }
 
 hipError_t launch_ga_resolve(const GaArgs &g, int in, int out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_resolve, per_wave(g.P), dim3(64 * kGaWaves), 0, s, g, in, out);
+    int YP = 1;
+    while (YP < g.Y)
+        YP <<= 1;
+    const int per = 64 / YP;
+    hipLaunchKernelGGL(k_resolve, per_wave((g.P + per - 1) / per), dim3(64 * kGaWaves), 0, s, g,
+                       YP, in, out);
     return hipGetLastError();
 }
 

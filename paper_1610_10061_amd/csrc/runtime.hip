@@ -196,7 +196,8 @@ struct pmp_ga {
     uint8_t *mut_ok = nullptr;
     unsigned long long *mpart = nullptr;
     uint32_t *mspart = nullptr;
-    int spec_ti = 0;  // client tiles mpart was sized for
+    int spec_ti = 0;  // client tiles mpart was sized for (the mutants' evaluation)
+    int spec_cpb = 0;  // its clients per workgroup
     bool spec_on = true;
     unsigned long long *part = nullptr;
     uint32_t *spart = nullptr;
@@ -245,8 +246,11 @@ struct pmp_ga {
     // attempt.  Both give the same results.
     bool spec() const
     {
-        return spec_on && !model && Y >= 2 && Y <= kMaxSpec && TI <= 128;
+        return spec_on && !model && Y >= 2 && Y <= kMaxSpec;
     }
+    // The mutants' evaluation covers Y times the population, so it takes
+    // larger client tiles than the population's (about 2048 workgroups):
+    // fewer partial sums for the resolve step to add up.
     hipError_t ensure_spec()
     {
         const size_t PY = (size_t)prm.population * Y;
@@ -257,16 +261,29 @@ struct pmp_ga {
             if (e != hipSuccess)
                 return e;
         }
-        if (spec_ti != TI) {
+        const long tiles_c = (long)((PY + kEvalTile - 1) / kEvalTile);
+        const int n = inst->n;
+        int ti = (int)std::max(1L, std::min((long)n, 2048L / std::max(1L, tiles_c)));
+        ti = std::max(ti, (n + 127) / 128);  // at most 128 clients per workgroup
+        int cpb = (n + ti - 1) / ti;
+        cpb = std::max(cpb, this->cpb);
+        cpb = ((cpb + 3) / 4) * 4;
+        ti = (n + cpb - 1) / cpb;
+        if (spec_ti != ti || spec_cpb != cpb) {
             dfree(mpart);
             dfree(mspart);
             spec_ti = 0;
-            hipError_t e = dalloc(&mpart, PY * TI);
+            hipError_t e = dalloc(&mpart, PY * ti);
             if (e == hipSuccess)
-                e = dalloc(&mspart, PY * TI);
+                e = dalloc(&mspart, PY * ti);
             if (e != hipSuccess)
                 return e;
-            spec_ti = TI;
+            spec_ti = ti;
+            spec_cpb = cpb;
+            if (gexec) {  // a captured graph holds the old buffers
+                (void)hipGraphExecDestroy(gexec);
+                gexec = nullptr;
+            }
         }
         return hipSuccess;
     }
@@ -297,6 +314,7 @@ struct pmp_ga {
         g.mut_ok = mut_ok;
         g.mpart = mpart;
         g.mspart = mspart;
+        g.TIm = spec_ti;
         g.part = part;
         g.spart = spart;
         g.TI = TI;
@@ -1276,6 +1294,8 @@ hipError_t ga_eval(pmp_ga *ga, const GaArgs &g, int buf, hipStream_t s, bool mut
         a.part = ga->mpart;
         a.spart = ga->mspart;
         a.tiles_c = (a.P + kEvalTile - 1) / kEvalTile;
+        a.clients_per_block = ga->spec_cpb;
+        a.tiles_i = ga->spec_ti;
     }
     return launch_eval(a, s, e0, e1);
 }
