@@ -37,6 +37,7 @@
 namespace pmp {
 
 using kLanes = std::make_integer_sequence<int, kEvalTile>;
+using kQuads = std::make_integer_sequence<int, kEvalTile / 4>;
 
 // Lowest set lane of a ballot, -1 when none (s_ff1_i32_b64 returns -1 for
 // zero, so no compare and select are needed around it).
@@ -65,16 +66,45 @@ __device__ __forceinline__ void match_one(const uint32_t *sm, uint32_t bit,
     write_lane<C>(hit, first_lane(b));
 }
 
-// Even and odd chromosomes write two different registers, so consecutive
-// v_writelane instructions do not wait on each other.
-template <int WD, int... C>
+// Chromosomes 4Q .. 4Q+3 together: four ballots live in four SGPR pairs and
+// one asm block takes their four lowest lanes, so the compare, find-first
+// and write-lane steps of neighbouring chromosomes overlap instead of
+// waiting on one shared scalar register.  Chromosome C goes to register
+// C mod 4.
+template <int WD, int Q>
+__device__ __forceinline__ void match_quad(const uint32_t *sm, uint32_t bit, int &h0,
+                                           int &h1, int &h2, int &h3)
+{
+    constexpr int C = 4 * Q;
+    const uint32_t w0 = sm[C * WD], w1 = sm[(C + 1) * WD];
+    const uint32_t w2 = sm[(C + 2) * WD], w3 = sm[(C + 3) * WD];
+    const uint64_t b0 = __builtin_amdgcn_ballot_w64((w0 & bit) != 0u);
+    const uint64_t b1 = __builtin_amdgcn_ballot_w64((w1 & bit) != 0u);
+    const uint64_t b2 = __builtin_amdgcn_ballot_w64((w2 & bit) != 0u);
+    const uint64_t b3 = __builtin_amdgcn_ballot_w64((w3 & bit) != 0u);
+    int f0, f1, f2, f3;
+    asm("s_ff1_i32_b64 %0, %4\n\t"
+        "s_ff1_i32_b64 %1, %5\n\t"
+        "s_ff1_i32_b64 %2, %6\n\t"
+        "s_ff1_i32_b64 %3, %7"
+        : "=&s"(f0), "=&s"(f1), "=&s"(f2), "=&s"(f3)
+        : "s"(b0), "s"(b1), "s"(b2), "s"(b3));
+    write_lane<C>(h0, f0);
+    write_lane<C + 1>(h1, f1);
+    write_lane<C + 2>(h2, f2);
+    write_lane<C + 3>(h3, f3);
+}
+
+// Every chromosome of the tile (kEvalTile = 64) against one chunk.
+template <int WD, int... Q>
 __device__ __forceinline__ int match_dense(const uint32_t *sm, uint32_t bit,
                                            int lane,
-                                           std::integer_sequence<int, C...>)
+                                           std::integer_sequence<int, Q...>)
 {
-    int hit0 = -1, hit1 = -1;
-    (match_one<WD, C>(sm, bit, (C & 1) ? hit1 : hit0), ...);
-    return (lane & 1) ? hit1 : hit0;
+    int h0 = -1, h1 = -1, h2 = -1, h3 = -1;
+    (match_quad<WD, Q>(sm, bit, h0, h1, h2, h3), ...);
+    const int q = lane & 3;
+    return q == 0 ? h0 : q == 1 ? h1 : q == 2 ? h2 : h3;
 }
 
 // Only the chromosomes in q (few left after the first chunk).
@@ -252,7 +282,7 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
             }
             const uint32_t *sm = smask + off;
             const int hit = (base == 0 || __builtin_popcountll(pend) >= 16)
-                                ? match_dense<WD>(sm, bit, lane, kLanes{})
+                                ? match_dense<WD>(sm, bit, lane, kQuads{})
                                 : match_sparse<WD>(sm, bit, pend, lane);
             const bool found = ((pend >> lane) & 1ull) && hit >= 0;
             if (R) {

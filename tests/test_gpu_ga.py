@@ -186,3 +186,11 @@ def test_mutation_cycle_at_once_counts(pm, mode):
         assert s["speculative_evals"] > 0
     else:
         assert s["speculative_evals"] == 0
+
+
+def test_ga_paper_preset_counts(pm, mode):
+    """The preset iteration counts of the paper's runs (60 crossover stages,
+    20 mutation attempts): crossover strides cycle, and the mutation cycle
+    evaluated at once takes 32 lanes per chromosome."""
+    d = gi.graph_instance(60, 150, 5)
+    _compare(pm, d, 6, 64, 16, 3, seed=8, steps=[2], X=60, Y=20)
