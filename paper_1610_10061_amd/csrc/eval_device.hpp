@@ -107,6 +107,57 @@ __device__ __forceinline__ int match_dense(const uint32_t *sm, uint32_t bit,
     return q == 0 ? h0 : q == 1 ? h1 : q == 2 ? h2 : h3;
 }
 
+// Two clients per chunk (short scans): lanes 0-31 hold the first 32 entries
+// of client A's row, lanes 32-63 those of client B.  One compare per
+// chromosome serves both rows; the ballot's low and high halves give each
+// client's first open position.
+template <int WD, int Q>
+__device__ __forceinline__ void match_quad2(const uint32_t *sm, uint32_t bit, int (&ha)[4],
+                                            int (&hb)[4])
+{
+    constexpr int C = 4 * Q;
+    const uint32_t w0 = sm[C * WD], w1 = sm[(C + 1) * WD];
+    const uint32_t w2 = sm[(C + 2) * WD], w3 = sm[(C + 3) * WD];
+    const uint64_t b0 = __builtin_amdgcn_ballot_w64((w0 & bit) != 0u);
+    const uint64_t b1 = __builtin_amdgcn_ballot_w64((w1 & bit) != 0u);
+    const uint64_t b2 = __builtin_amdgcn_ballot_w64((w2 & bit) != 0u);
+    const uint64_t b3 = __builtin_amdgcn_ballot_w64((w3 & bit) != 0u);
+    int a0, a1, a2, a3, e0, e1, e2, e3;
+    asm("s_ff1_i32_b32 %0, %8\n\t"
+        "s_ff1_i32_b32 %1, %9\n\t"
+        "s_ff1_i32_b32 %2, %10\n\t"
+        "s_ff1_i32_b32 %3, %11\n\t"
+        "s_ff1_i32_b32 %4, %12\n\t"
+        "s_ff1_i32_b32 %5, %13\n\t"
+        "s_ff1_i32_b32 %6, %14\n\t"
+        "s_ff1_i32_b32 %7, %15"
+        : "=&s"(a0), "=&s"(a1), "=&s"(a2), "=&s"(a3), "=&s"(e0), "=&s"(e1), "=&s"(e2),
+          "=&s"(e3)
+        : "s"((uint32_t)b0), "s"((uint32_t)b1), "s"((uint32_t)b2), "s"((uint32_t)b3),
+          "s"((uint32_t)(b0 >> 32)), "s"((uint32_t)(b1 >> 32)), "s"((uint32_t)(b2 >> 32)),
+          "s"((uint32_t)(b3 >> 32)));
+    write_lane<C>(ha[0], a0);
+    write_lane<C + 1>(ha[1], a1);
+    write_lane<C + 2>(ha[2], a2);
+    write_lane<C + 3>(ha[3], a3);
+    write_lane<C>(hb[0], e0);
+    write_lane<C + 1>(hb[1], e1);
+    write_lane<C + 2>(hb[2], e2);
+    write_lane<C + 3>(hb[3], e3);
+}
+
+template <int WD, int... Q>
+__device__ __forceinline__ void match_dense2(const uint32_t *sm, uint32_t bit, int lane,
+                                             int &hit_a, int &hit_b,
+                                             std::integer_sequence<int, Q...>)
+{
+    int ha[4] = {-1, -1, -1, -1}, hb[4] = {-1, -1, -1, -1};
+    (match_quad2<WD, Q>(sm, bit, ha, hb), ...);
+    const int q = lane & 3;
+    hit_a = q == 0 ? ha[0] : q == 1 ? ha[1] : q == 2 ? ha[2] : ha[3];
+    hit_b = q == 0 ? hb[0] : q == 1 ? hb[1] : q == 2 ? hb[2] : hb[3];
+}
+
 // Only the chromosomes in q (few left after the first chunk).
 template <int WD>
 __device__ __forceinline__ int match_sparse(const uint32_t *sm, uint32_t bit,
@@ -124,6 +175,43 @@ __device__ __forceinline__ int match_sparse(const uint32_t *sm, uint32_t bit,
     return hit;
 }
 
+// The rest of one client's walk from position `base` for the chromosomes in
+// `pend` (64-entry chunks, loaded here).
+template <int WD>
+__device__ __forceinline__ void walk_tail(const EvalArgs &a, const uint16_t *prow,
+                                          const int32_t *drow, int base, uint64_t pend,
+                                          int lane, const uint32_t *smask,
+                                          unsigned long long &acc, uint32_t &scn)
+{
+    for (; pend != 0ull; base += 64) {
+        if (base >= a.t.K) {  // fewer than p open facilities
+            if (lane == 0)
+                atomicOr(a.err, ERR_SCAN_OVERRUN);
+            break;
+        }
+        const int k = base + lane;
+        uint32_t off = 0, bit = 0;
+        int32_t dist = 0;
+        if (k < a.t.K) {
+            const uint32_t j = prow[k];
+            off = j >> 5;
+            bit = 1u << (j & 31u);
+            dist = drow[k];
+        }
+        const uint32_t *sm = smask + off;
+        const int hit = __builtin_popcountll(pend) >= 16
+                            ? match_dense<WD>(sm, bit, lane, kQuads{})
+                            : match_sparse<WD>(sm, bit, pend, lane);
+        const bool found = ((pend >> lane) & 1ull) && hit >= 0;
+        const int32_t cost = __builtin_amdgcn_ds_bpermute((hit & 63) << 2, dist);
+        if (found) {
+            acc += (uint32_t)cost;
+            scn += (uint32_t)(base + hit + 1);
+        }
+        pend &= ~__builtin_amdgcn_ballot_w64(found);
+    }
+}
+
 // Evaluate chromosome tile tc (64 chromosomes) on client tile ti and store
 // the tile's partial sums.  Called by a whole 256-thread workgroup;
 // smask holds 64 * WD words, sred 2 * kEvalWaves * 64 words.
@@ -134,7 +222,11 @@ __device__ __forceinline__ int match_sparse(const uint32_t *sm, uint32_t bit,
 // with no extra work in the walk: the last position's lane tests a mask
 // word that is all ones for every chromosome (word 2W of each staged row,
 // so WD > 2W).
-template <int WD, bool R = false>
+//
+// H (short scans, not with R): a wave walks its clients two at a time, the
+// first 32 entries of each row in one chunk (match_dense2); the few rows
+// whose first open facility lies past entry 31 finish in walk_tail.
+template <int WD, bool R = false, bool H = false>
 __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
                                           uint32_t *smask,
                                           unsigned long long *sred)
@@ -157,10 +249,13 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
     // below K (always in bounds; lanes at or past K are masked when used), so
     // the compiler never has to wait for a prefetch before using the
     // previous one.
-    const int col = lane < a.t.K ? lane : a.t.K - 1;
-    const bool in_row = lane < a.t.K;
+    // (H: lanes 32-63 hold the wave's second client of the pair)
+    const int pos = H ? (lane & 31) : lane;
+    const int col = pos < a.t.K ? pos : a.t.K - 1;
+    const bool in_row = pos < a.t.K;
     const int last = i1 - 1;
-    const uint32_t j_first = a.t.pi[(int64_t)min(i, last) * a.t.pitch + col];
+    const int row_first = (H && lane >= 32) ? min(i + kEvalWaves, last) : min(i, last);
+    const uint32_t j_first = a.t.pi[(int64_t)row_first * a.t.pitch + col];
     int32_t d_cur = 0;
     long long e_cur = 0;
     int k_cur = 0;  // R: the row's length K_i
@@ -168,7 +263,7 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
         e_cur = a.e64[(int64_t)min(i, last) * a.t.pitch + col];
         k_cur = a.rlen[min(i, last)];
     } else {
-        d_cur = a.t.ds[(int64_t)min(i, last) * a.t.pitch + col];
+        d_cur = a.t.ds[(int64_t)row_first * a.t.pitch + col];
     }
     // Masks: every load unconditional at a clamped (always valid) address,
     // in batches, so that a batch costs one round trip; out-of-range words
@@ -234,7 +329,44 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
     // chunk-0 operands of the current client: mask word, bit (0 past K)
     uint32_t off_cur = j_first >> 5;
     uint32_t bit_cur = in_row ? 1u << (j_first & 31u) : 0u;
-    for (; i < i1; i += kEvalWaves) {
+    if constexpr (H) {
+        for (; i < i1; i += 2 * kEvalWaves) {
+            const int ib = i + kEvalWaves;
+            const bool has_b = ib < i1;
+            const int na = min(i + 2 * kEvalWaves, last), nb = min(i + 3 * kEvalWaves, last);
+            const int rown = lane >= 32 ? nb : na;
+            const uint32_t j_nxt = a.t.pi[(int64_t)rown * a.t.pitch + col];
+            const int32_t d_nxt = a.t.ds[(int64_t)rown * a.t.pitch + col];
+            const uint32_t bit = (lane >= 32 && !has_b) ? 0u : bit_cur;
+            int ha, hb;
+            match_dense2<WD>(smask + off_cur, bit, lane, ha, hb, kQuads{});
+            const uint64_t pa = act, pb = has_b ? act : 0ull;
+            const bool fa = ((pa >> lane) & 1ull) && ha >= 0;
+            const bool fb = ((pb >> lane) & 1ull) && hb >= 0;
+            const int32_t ca = __builtin_amdgcn_ds_bpermute((ha & 31) << 2, d_cur);
+            const int32_t cb = __builtin_amdgcn_ds_bpermute((32 + (hb & 31)) << 2, d_cur);
+            if (fa) {
+                acc += (uint32_t)ca;
+                scn += (uint32_t)(ha + 1);
+            }
+            if (fb) {
+                acc += (uint32_t)cb;
+                scn += (uint32_t)(hb + 1);
+            }
+            const uint64_t ra = pa & ~__builtin_amdgcn_ballot_w64(fa);
+            const uint64_t rb = pb & ~__builtin_amdgcn_ballot_w64(fb);
+            if (ra)
+                walk_tail<WD>(a, a.t.pi + (int64_t)i * a.t.pitch, a.t.ds + (int64_t)i * a.t.pitch,
+                              32, ra, lane, smask, acc, scn);
+            if (rb)
+                walk_tail<WD>(a, a.t.pi + (int64_t)ib * a.t.pitch,
+                              a.t.ds + (int64_t)ib * a.t.pitch, 32, rb, lane, smask, acc, scn);
+            off_cur = j_nxt >> 5;
+            bit_cur = in_row ? 1u << (j_nxt & 31u) : 0u;
+            d_cur = d_nxt;
+        }
+    }
+    for (; !H && i < i1; i += kEvalWaves) {
         const int inext = min(i + kEvalWaves, last);
         const uint32_t j_nxt = a.t.pi[(int64_t)inext * a.t.pitch + col];
         int32_t d_nxt = 0;

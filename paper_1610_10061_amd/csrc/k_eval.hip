@@ -8,7 +8,7 @@ namespace pmp {
 
 namespace {
 
-template <int WD, bool R>
+template <int WD, bool R, bool H>
 __global__ __launch_bounds__(kEvalTile *kEvalWaves) void k_eval(EvalArgs a)
 {
     __shared__ uint32_t smask[kEvalTile * WD];
@@ -23,7 +23,7 @@ __global__ __launch_bounds__(kEvalTile *kEvalWaves) void k_eval(EvalArgs a)
     if (logical >= ntiles)
         return;
     const int ti = logical / a.tiles_c;
-    eval_tile<WD, R>(a, ti, logical - ti * a.tiles_c, smask, sred);
+    eval_tile<WD, R, H>(a, ti, logical - ti * a.tiles_c, smask, sred);
 }
 
 // fitness[c] (and scan[c]) = sum over client tiles of the partial sums.
@@ -46,12 +46,12 @@ __global__ __launch_bounds__(256) void k_reduce(
         scan[c] = s;
 }
 
-template <int WD, bool R>
+template <int WD, bool R, bool H>
 hipError_t launch_wd(const EvalArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     const int tiles = a.tiles_c * a.tiles_i;
     const int grid = ((tiles + 7) / 8) * 8;
-    auto kernel = k_eval<WD, R>;
+    auto kernel = k_eval<WD, R, H>;
     if (e0 && e1) {
         // events stamped by the dispatch itself: their interval is the
         // kernel's execution, without the gaps around it
@@ -83,7 +83,9 @@ hipError_t launch_eval(const EvalArgs &a, hipStream_t s, hipEvent_t e0, hipEvent
     const int w2 = 2 * a.t.W + (red ? 1 : 0);
 #define PMP_EVAL_WD(N)                                                         \
     if (w2 <= N)                                                               \
-        return red ? launch_wd<N, true>(a, s, e0, e1) : launch_wd<N, false>(a, s, e0, e1);
+        return red ? launch_wd<N, true, false>(a, s, e0, e1)                     \
+                   : (a.paired ? launch_wd<N, false, true>(a, s, e0, e1)         \
+                               : launch_wd<N, false, false>(a, s, e0, e1));
     PMP_EVAL_WD(2)
     PMP_EVAL_WD(4)
     PMP_EVAL_WD(8)

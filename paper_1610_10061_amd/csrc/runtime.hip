@@ -70,6 +70,17 @@ int env_int(const char *name, int dflt)
     return atoi(v);
 }
 
+// Whether the evaluation walks two clients per chunk: when the expected scan
+// (m + 1) / (p + 1) of a random chromosome is short, almost every row finds
+// its first open facility within 32 entries.  PMP_EVAL_PAIRED=0/1 forces it.
+int paired_scans(int m, int p)
+{
+    const int forced = env_int("PMP_EVAL_PAIRED", -1);
+    if (forced >= 0)
+        return forced ? 1 : 0;
+    return (int64_t)m + 1 <= 12LL * ((int64_t)p + 1) ? 1 : 0;
+}
+
 // Clients per workgroup of the evaluation kernel: enough workgroups to fill
 // 256 CUs several times over, at least four clients (one per wave).
 int clients_per_block(int n, int P)
@@ -1069,6 +1080,7 @@ pmp_status pmp_eval_population(pmp_instance *inst, const uint64_t *masks,
 
     EvalArgs a{};
     a.t = inst->tables();
+    a.paired = paired_scans(inst->m, inst->p);
     a.masks = dmask;
     a.P = P;
     a.active = nullptr;
@@ -1250,6 +1262,7 @@ EvalArgs ga_eval_args(const pmp_ga *ga, const GaArgs &g, int buf)
 {
     EvalArgs a{};
     a.t = g.t;
+    a.paired = paired_scans(g.t.m, g.t.p);
     a.masks = g.off[buf];
     a.P = g.P;
     a.active = g.ok[buf];
@@ -2241,6 +2254,7 @@ pmp_status pmp_exhaustive(pmp_instance *inst, uint64_t *best_mask, int64_t *best
     const int nblk = (B + 255) / 256;
     EvalArgs a{};
     a.t = inst->tables();
+    a.paired = paired_scans(inst->m, inst->p);
     a.P = B;
     a.active = nullptr;
     a.done = nullptr;

@@ -270,3 +270,32 @@ def test_eval_both_scheme_flags_rejected(pm):
                                       fit.ctypes.data_as(pm._vp), None,
                                       pm.PMP_EVAL_PER_CHROMOSOME | pm.PMP_EVAL_PER_CLIENT, None)
     assert rc == pm.PMP_EINVAL
+
+
+@pytest.mark.parametrize("paired", ["1", "0"])
+@pytest.mark.parametrize("name,P", [("g100", 130), ("euclid_129", 64), ("ties_p1", 70),
+                                    ("g900", 257), ("ties_pm1", 65), ("m2", 3),
+                                    ("rect_37x150", 131), ("wide_2x700", 300)])
+def test_eval_paired_and_single_chunks(pm, paired, name, P):
+    """Both walks of the tiled kernel - two clients per 32-entry chunk, or
+    one client per 64-entry chunk - on short scans, long scans (rows finish
+    in the tail walk) and rows shorter than 32 entries."""
+    d, p = INSTANCES[name]()
+    n, m = d.shape
+    _say("case", name, d.shape, "p", p, "P", P, "paired", paired)
+    old = os.environ.get("PMP_EVAL_PAIRED")
+    os.environ["PMP_EVAL_PAIRED"] = paired
+    try:
+        masks = gi.random_population(P, m, p, seed=P + 3)
+        inst = pm.Instance(d, p)
+        fit = np.zeros(P, np.int64)
+        scan = np.zeros(P, np.int64)
+        pm.pmp_eval_population(inst.handle, masks, fit, scan)
+        want, wscan = oracle.objective(d, masks, p, scan=True)
+        np.testing.assert_array_equal(fit, want)
+        np.testing.assert_array_equal(scan, wscan)
+    finally:
+        if old is None:
+            os.environ.pop("PMP_EVAL_PAIRED", None)
+        else:
+            os.environ["PMP_EVAL_PAIRED"] = old

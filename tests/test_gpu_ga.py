@@ -194,3 +194,18 @@ def test_ga_paper_preset_counts(pm, mode):
     evaluated at once takes 32 lanes per chromosome."""
     d = gi.graph_instance(60, 150, 5)
     _compare(pm, d, 6, 64, 16, 3, seed=8, steps=[2], X=60, Y=20)
+
+
+def test_ga_paired_walk_with_long_scans(pm):
+    """The GA with the two-clients-per-chunk walk forced on an instance whose
+    rows often reach past 32 entries (G100, p = 5)."""
+    old = os.environ.get("PMP_EVAL_PAIRED")
+    os.environ["PMP_EVAL_PAIRED"] = "1"
+    try:
+        d = gi.graph_instance(100, 200, 6)
+        _compare(pm, d, 5, 128, 32, 6, seed=4, steps=[3])
+    finally:
+        if old is None:
+            os.environ.pop("PMP_EVAL_PAIRED", None)
+        else:
+            os.environ["PMP_EVAL_PAIRED"] = old
