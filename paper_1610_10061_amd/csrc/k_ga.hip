@@ -322,7 +322,11 @@ __global__ __launch_bounds__(kEvalTile *kEvalWaves) void k_batch_eval(BatchArgs 
     e.active = buf ? it.g.ok[1] : it.g.ok[0];
     const int local = item - B.tile0[b];
     const int ti = local / e.tiles_c;
-    eval_tile<WD>(e, ti, local - ti * e.tiles_c, smask, sred);
+    // the walk each instance's scan lengths call for (uniform per workgroup)
+    if (e.paired)
+        eval_tile<WD, false, true>(e, ti, local - ti * e.tiles_c, smask, sred);
+    else
+        eval_tile<WD>(e, ti, local - ti * e.tiles_c, smask, sred);
 }
 
 __global__ __launch_bounds__(64 * kGaWaves) void k_batch_stage(BatchArgs B, int k)
