@@ -628,6 +628,10 @@ __device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
         const int32_t *sw = g.swaps + ((int64_t)c * g.L + index) * 2;
         sj = sw[0];
         sk = sw[1];
+    } else if (op == OP_MUT_ALL && sub < g.L) {  // a scored swap among the mutants
+        const int32_t *sw = g.swaps + ((int64_t)c * g.L + sub) * 2;
+        sj = sw[0];
+        sk = sw[1];
     }
     const uint8_t okc_b = buf(g.ok, in)[c];
     const uint8_t okp_b = buf(g.ok, in)[pc];
@@ -692,7 +696,9 @@ __device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
         s += use ? ps : 0u;
         h += use ? ph : 0ull;
     }
-    const bool okc = okc_b != 0;
+    // prev == OP_NONE: the previous operator was already finished (the
+    // learned proposal ran in between), so there is nothing to take
+    const bool okc = okc_b != 0 && prev != OP_NONE;
     const bool okp = xo && okp_b != 0;
     const bool was_improved = imp_b != 0;
 
@@ -755,11 +761,28 @@ __device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
     } else if (op == OP_MUT_ALL) {
         // every attempt mutates the same parent A (the cycle has not improved
         // it yet); ga_resolve_one takes the first strictly fitter mutant
-        const int lo_a = __builtin_amdgcn_readlane(dr.a, sub);
-        const int hi_a = __builtin_amdgcn_readlane(dr.b, sub);
-        const int mv_a = __builtin_amdgcn_readlane(dr.c, sub);
         const int64_t row = (int64_t)c * g.Y + sub;
-        const bool ch = mutate_wave(A, g.mut + row * W, W, m, lo_a, hi_a, mv_a, lane);
+        bool ch = true;
+        if (sub < g.L) {  // scored swap: close sj, open sk
+            uint64_t *Fm = g.mut + row * W;
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int w = lane + 64 * k;
+                if (w < W) {
+                    uint64_t v = A.v[k];
+                    if ((sj >> 6) == w)
+                        v ^= 1ull << (sj & 63);
+                    if ((sk >> 6) == w)
+                        v ^= 1ull << (sk & 63);
+                    Fm[w] = v;
+                }
+            }
+        } else {
+            const int lo_a = __builtin_amdgcn_readlane(dr.a, sub);
+            const int hi_a = __builtin_amdgcn_readlane(dr.b, sub);
+            const int mv_a = __builtin_amdgcn_readlane(dr.c, sub);
+            ch = mutate_wave(A, g.mut + row * W, W, m, lo_a, hi_a, mv_a, lane);
+        }
         if (lane == 0)
             g.mut_ok[row] = ch ? 1 : 0;
     } else if (op == OP_SWAP && !improved) {
@@ -816,6 +839,7 @@ __device__ __forceinline__ void ga_resolve_wave(const GaArgs &g, int gw, int lan
     // the group leader's counters (the other lanes load them too, unused)
     const unsigned long long c_ev = cs[CS_EVALS], c_sc = cs[CS_SCAN], c_mt = cs[CS_MUT_TAKEN];
     const unsigned long long c_se = cs[CS_SPEC_EVALS], c_ss = cs[CS_SPEC_SCAN];
+    const unsigned long long c_st = cs[CS_SWAP_TRIED], c_sk = cs[CS_SWAP_TAKEN];
     unsigned long long f = 0, sc = 0;
 #pragma unroll 8
     for (int t = 0; t < g.TIm; ++t) {
@@ -840,6 +864,20 @@ __device__ __forceinline__ void ga_resolve_wave(const GaArgs &g, int gw, int lan
     const int n_spec = __builtin_popcountll(__builtin_amdgcn_ballot_w64(spec) & gmask);
     const unsigned long long f_taken = __shfl(f, first < 0 ? lane : first);
     const int taken = first < 0 ? -1 : first - grp * YP;
+    // learned proposal: the first L attempts are scored swaps; each one the
+    // attempt-by-attempt cycle evaluates leaves its training tuple
+    const bool swap_l = counted && a < g.L;
+    const int n_swap = __builtin_popcountll(__builtin_amdgcn_ballot_w64(swap_l) & gmask);
+    if (swap_l) {
+        const uint64_t gen = g.gs[GS_GEN];
+        const int64_t slot = ((int64_t)(gen % (uint64_t)g.H) * g.L + a) * g.P + cc;
+        const long long delta = (long long)f - (long long)fin;
+        double tv = (double)delta * (double)g.t.p / (fin > 0 ? (double)fin : 1.0);
+        tv = tv < -4.0 ? -4.0 : (tv > 4.0 ? 4.0 : tv);
+        g.rep_d[2 * slot] = delta;
+        g.rep_t[slot] = (float)tv;
+        g.rep_w[slot] = 1.f;
+    }
     // the chromosome: the taken mutant or the parent, word w by lane w mod YP
     if (valid_c) {
         uint64_t *dst = buf(g.cur, out) + (int64_t)cc * W;
@@ -857,8 +895,12 @@ __device__ __forceinline__ void ga_resolve_wave(const GaArgs &g, int gw, int lan
             cs[CS_EVALS] = c_ev + (unsigned long long)n_cnt;
             cs[CS_SCAN] = c_sc + s_cnt;
         }
-        if (taken >= 0)
+        if (taken >= 0 && taken < g.L)
+            cs[CS_SWAP_TAKEN] = c_sk + 1ull;
+        else if (taken >= 0)
             cs[CS_MUT_TAKEN] = c_mt + 1ull;
+        if (n_swap)
+            cs[CS_SWAP_TRIED] = c_st + (unsigned long long)n_swap;
         if (n_spec) {
             cs[CS_SPEC_EVALS] = c_se + (unsigned long long)n_spec;
             cs[CS_SPEC_SCAN] = c_ss + s_spec;

@@ -257,7 +257,7 @@ struct pmp_ga {
     // attempt.  Both give the same results.
     bool spec() const
     {
-        return spec_on && !model && Y >= 2 && Y <= kMaxSpec;
+        return spec_on && Y >= 2 && Y <= kMaxSpec;
     }
     // The mutants' evaluation covers Y times the population, so it takes
     // larger client tiles than the population's (about 2048 workgroups):
@@ -1332,6 +1332,21 @@ hipError_t ga_counters(pmp_ga *ga, unsigned long long tot[CS_COUNT])
 
 namespace {
 
+// One Adam step on the learned proposal's ring after every Levery-th
+// generation (gated on the device, so a captured graph replays correctly).
+hipError_t launch_train(pmp_ga *ga, const GaArgs &g, hipStream_t s)
+{
+    TrainGate gate{g.gs + GS_GEN, ga->last_trained, ga->Levery};
+    int nb = 0;
+    pmp_model *md = ga->model;
+    hipError_t e = launch_mlp_grad(md->d.view(), ga->rep_x, ga->rep_t, ga->rep_w,
+                                   (int)ga->ring_rows(), md->partials, kTrainBlocks, md->d, gate,
+                                   &nb, s);
+    if (e == hipSuccess)
+        e = launch_mlp_update(md->d, md->partials, nb, ga->Llr, nullptr, nullptr, gate, s);
+    return e;
+}
+
 // Enqueue `generations` generations of the per-step launch sequence.
 hipError_t enqueue_generations(pmp_ga *ga, const GaArgs &g, int generations,
                                hipStream_t s)
@@ -1352,14 +1367,29 @@ hipError_t enqueue_generations(pmp_ga *ga, const GaArgs &g, int generations,
                 if (e == hipSuccess)
                     e = ga_eval(ga, g, (k & 1) ^ 1, s);
             }
-            if (e == hipSuccess)
-                e = launch_ga_stage(g, X & 1, X == 0 ? OP_INIT : OP_XOVER, OP_MUT_ALL, 0, s);
+            int in = X & 1;  // the buffer holding the last crossover's results
+            const int prev = X == 0 ? OP_INIT : OP_XOVER;
+            if (L > 0) {
+                // finish the crossovers, score the swaps of the chromosomes as
+                // they stand, then make every mutant (the swaps among them)
+                if (e == hipSuccess)
+                    e = launch_ga_stage(g, in, prev, OP_NONE, 0, s);
+                if (e == hipSuccess)
+                    e = launch_propose(ga->learn_args(g), in, s);
+                in ^= 1;
+                if (e == hipSuccess)
+                    e = launch_ga_stage(g, in, OP_NONE, OP_MUT_ALL, 0, s);
+            } else if (e == hipSuccess) {
+                e = launch_ga_stage(g, in, prev, OP_MUT_ALL, 0, s);
+            }
             if (e == hipSuccess)
                 e = ga_eval(ga, g, 0, s, true);
             if (e == hipSuccess)
-                e = launch_ga_resolve(g, (X & 1) ^ 1, ga->final_buf(), s);
+                e = launch_ga_resolve(g, in ^ 1, ga->final_buf(), s);
             if (e == hipSuccess)
                 e = launch_ga_best(g, ga->final_buf(), s);
+            if (e == hipSuccess && train)
+                e = launch_train(ga, g, s);
             if (e != hipSuccess)
                 return e;
         }
@@ -1386,18 +1416,8 @@ hipError_t enqueue_generations(pmp_ga *ga, const GaArgs &g, int generations,
         }
         if (e == hipSuccess)
             e = launch_ga_best(g, ga->final_buf(), s);
-        if (e == hipSuccess && train) {
-            // one Adam step on the ring after every Levery-th generation
-            TrainGate gate{g.gs + GS_GEN, ga->last_trained, ga->Levery};
-            int nb = 0;
-            pmp_model *md = ga->model;
-            e = launch_mlp_grad(md->d.view(), ga->rep_x, ga->rep_t, ga->rep_w,
-                                (int)ga->ring_rows(), md->partials, kTrainBlocks, md->d, gate,
-                                &nb, s);
-            if (e == hipSuccess)
-                e = launch_mlp_update(md->d, md->partials, nb, ga->Llr, nullptr, nullptr, gate,
-                                      s);
-        }
+        if (e == hipSuccess && train)
+            e = launch_train(ga, g, s);
         if (e != hipSuccess)
             return e;
     }
