@@ -236,9 +236,14 @@ def test_learned_ga_invariants_graph_replay_and_determinism(pm):
     d = gi.euclid_instance(300, 7)
     p, P, NT, G = 30, 128, 32, 40
     runs = []
-    for mode in ("graph", "kernels", "graph"):
+    # the graph-replayed and kernel-by-kernel schedules, and the mutation
+    # cycle attempt by attempt instead of at once: all must agree
+    for mode, spec in (("graph", "1"), ("kernels", "1"), ("graph", "1"), ("graph", "0"),
+                       ("kernels", "0")):
         old = os.environ.get("PMP_GA_MODE")
+        old_spec = os.environ.get("PMP_GA_SPEC")
         os.environ["PMP_GA_MODE"] = mode
+        os.environ["PMP_GA_SPEC"] = spec
         try:
             model = pm.Model(9)
             inst, ga = _learned_ga(pm, d, p, P, NT, G, 5, model, candidates=32,
@@ -255,6 +260,10 @@ def test_learned_ga_invariants_graph_replay_and_determinism(pm):
                 os.environ.pop("PMP_GA_MODE", None)
             else:
                 os.environ["PMP_GA_MODE"] = old
+            if old_spec is None:
+                os.environ.pop("PMP_GA_SPEC", None)
+            else:
+                os.environ["PMP_GA_SPEC"] = old_spec
         np.testing.assert_array_equal(fit, oracle.objective(d, pop, p))
         assert all(a >= b for a, b in zip(trace, trace[1:]))
         assert np.all(gi.unpack_masks(pop, 300).sum(axis=1) == p)
@@ -262,6 +271,9 @@ def test_learned_ga_invariants_graph_replay_and_determinism(pm):
         assert runs[0][0] == other[0]
         for x, y in zip(runs[0][1:6], other[1:6]):
             np.testing.assert_array_equal(x, y)
+        for k in ("chromosome_evals", "swap_tried", "swap_taken", "mutation_taken",
+                  "crossover_taken", "scan_total"):
+            assert runs[0][6][k] == other[6][k], k
     st = runs[0][6]
     assert st["generations"] == G and st["done"] == 1
     assert st["swap_tried"] > 0 and st["swap_taken"] > 0
