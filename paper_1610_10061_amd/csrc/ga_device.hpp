@@ -43,23 +43,50 @@ __device__ __forceinline__ int ga_xstages(const GaArgs &g)
     return (g.t.p >= 2 && g.lg > 0) ? g.X : 0;
 }
 
-__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v)
+// Wave-wide inclusive prefix sums with DPP lane moves instead of LDS
+// permutes: shifts by 1, 2, 4 and 8 within each 16-lane row (lanes without
+// a source add 0), then the last lane of row 0 and of row 2 is broadcast into
+// rows 1 and 3, and the last lane of row 1 into rows 2 and 3.
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ uint32_t dpp_from(uint32_t v)
 {
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1)
-        v += __shfl_xor(v, d);
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, Ctrl, RowMask, 0xF, false);
+}
+
+__device__ __forceinline__ uint32_t wave_scan_incl(uint32_t v, int /*lane*/)
+{
+    v += dpp_from<0x111, 0xF>(v);  // row_shr:1
+    v += dpp_from<0x112, 0xF>(v);  // row_shr:2
+    v += dpp_from<0x114, 0xF>(v);  // row_shr:4
+    v += dpp_from<0x118, 0xF>(v);  // row_shr:8
+    v += dpp_from<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_from<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
     return v;
 }
 
-__device__ __forceinline__ uint32_t wave_scan_incl(uint32_t v, int lane)
+// The same on 64-bit values (low and high words, carry by compare).
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ void dpp_add64(uint32_t &lo, uint32_t &hi)
 {
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t u = __shfl_up(v, d);
-        if (lane >= d)
-            v += u;
-    }
-    return v;
+    const uint32_t l2 = dpp_from<Ctrl, RowMask>(lo), h2 = dpp_from<Ctrl, RowMask>(hi);
+    const uint32_t nl = lo + l2;
+    hi = hi + h2 + (nl < lo ? 1u : 0u);
+    lo = nl;
+}
+
+// Sum over the wave, the same value in every lane.
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v)
+{
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+    dpp_add64<0x111, 0xF>(lo, hi);
+    dpp_add64<0x112, 0xF>(lo, hi);
+    dpp_add64<0x114, 0xF>(lo, hi);
+    dpp_add64<0x118, 0xF>(lo, hi);
+    dpp_add64<0x142, 0xA>(lo, hi);
+    dpp_add64<0x143, 0xC>(lo, hi);
+    const uint32_t tl = (uint32_t)__builtin_amdgcn_readlane((int)lo, 63);
+    const uint32_t th = (uint32_t)__builtin_amdgcn_readlane((int)hi, 63);
+    return ((unsigned long long)th << 32) | tl;
 }
 
 __device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane)
