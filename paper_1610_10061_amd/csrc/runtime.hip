@@ -274,7 +274,8 @@ struct pmp_ga {
         }
         const long tiles_c = (long)((PY + kEvalTile - 1) / kEvalTile);
         const int n = inst->n;
-        int ti = (int)std::max(1L, std::min((long)n, 2048L / std::max(1L, tiles_c)));
+        const long target = std::max(1, env_int("PMP_MUTANT_WORKGROUPS", 2048));
+        int ti = (int)std::max(1L, std::min((long)n, target / std::max(1L, tiles_c)));
         ti = std::max(ti, (n + 127) / 128);  // at most 128 clients per workgroup
         int cpb = (n + ti - 1) / ti;
         cpb = std::max(cpb, this->cpb);
