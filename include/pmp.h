@@ -231,6 +231,10 @@ PMP_API void pmp_instance_destroy(pmp_instance *inst);
 /* Migration variants (Section 4.5). */
 #define PMP_MIG_SAME_BLOCK 0  /* group b's best -> slot b*NT (its own block) */
 #define PMP_MIG_ONE_BLOCK 1   /* all group bests -> slots 0..NB-1 (one block) */
+/* Generation of fresh chromosomes (Section 4.1). */
+#define PMP_INIT_SUBSET 0     /* a uniform p-subset by Floyd's method */
+#define PMP_INIT_RANK 1       /* a uniform rank below C(m, p), unranked in
+                                 lexicographic order; needs C(m, p) < 2^63 */
 
 typedef struct {
     uint64_t seed;
@@ -241,7 +245,7 @@ typedef struct {
     int32_t crossover_iters;  /* X; 0 = lg NT */
     int32_t mutation_iters;   /* Y; 0 = lg NT */
     int32_t migration;        /* PMP_MIG_SAME_BLOCK (0) or PMP_MIG_ONE_BLOCK */
-    int32_t reserved;         /* must be 0 */
+    int32_t init;             /* PMP_INIT_SUBSET (0) or PMP_INIT_RANK */
 } pmp_ga_params;
 
 typedef struct {
@@ -265,7 +269,8 @@ typedef struct {
 
 /* Create a GA run on an instance (the instance must outlive it).
  * PMP_EINVAL: P < 1, NT not a power of two, NT > 1024, P % NT != 0,
- * generations < 1, negative counts, unknown migration, reserved not 0. */
+ * generations < 1, negative counts, unknown migration or init.
+ * PMP_EUNSUPPORTED: PMP_INIT_RANK with C(m, p) >= 2^63. */
 PMP_API pmp_status pmp_ga_create(pmp_instance *inst, const pmp_ga_params *params,
                          pmp_ga **out);
 

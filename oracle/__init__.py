@@ -58,7 +58,8 @@ class _GaParams(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("population", C.c_int32),
                 ("group_size", C.c_int32), ("generations", C.c_int32),
                 ("saturation", C.c_int32), ("crossover_iters", C.c_int32),
-                ("mutation_iters", C.c_int32), ("migration", C.c_int32)]
+                ("mutation_iters", C.c_int32), ("migration", C.c_int32),
+                ("init", C.c_int32)]
 
 
 def lib():
@@ -74,6 +75,7 @@ def lib():
         L.orc_exhaustive.argtypes = [_p, _i64, _i32, _i32, _i32, _p, _p, _p, _i32]
         L.orc_philox4x64.argtypes = [_p, _p, _p]
         L.orc_apsp.argtypes = [_p, _i32, _p]
+        L.orc_unrank.argtypes = [_u64, _i32, _i32, _p]
         L.orc_philox4x64.restype = None
         L.orc_stream_draws.argtypes = [_u64, _u64, _u64, _u64, _u64, _u64, _p, _i32, _p]
         L.orc_sample_subset.argtypes = [_u64, _u64, _u64, _i32, _i32, _p]
@@ -181,6 +183,13 @@ def exhaustive(d, p: int, threads: int = 0):
     return int(best[0]), mask, int(cnt[0])
 
 
+def unrank(r: int, m: int, p: int):
+    """The p-subset of lexicographic rank r (packed mask), Section 4.1."""
+    mask = np.zeros((m + 63) // 64, np.uint64)
+    _check(lib().orc_unrank(r, m, p, _ptr(mask)), "unrank")
+    return mask
+
+
 def apsp(w):
     """Shortest path lengths of the graph with arc weights w (n x n int32,
     negative = no arc), by Floyd-Warshall; -1 where there is no path."""
@@ -240,11 +249,11 @@ class GaState:
     """Resumable GA state: everything the next generation depends on."""
 
     def __init__(self, n, m, p, population, group_size, generations, seed,
-                 saturation=0, crossover_iters=0, mutation_iters=0, migration=0):
+                 saturation=0, crossover_iters=0, mutation_iters=0, migration=0, init=0):
         self.n, self.m, self.p = n, m, p
         self.params = _GaParams(seed, population, group_size, generations,
                                 saturation, crossover_iters, mutation_iters,
-                                migration)
+                                migration, init)
         W = (m + 63) // 64
         NB = population // group_size
         self.pop = np.zeros((population, W), np.uint64)

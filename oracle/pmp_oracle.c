@@ -471,6 +471,58 @@ static void sample_subset(orc_stream *s, int32_t m, int32_t p, uint8_t *bits)
     }
 }
 
+/* ------------------------------------------------------------------------
+ * Chromosome generation as Section 4.1 describes it: a uniform random rank
+ * r in [0, C(m, p)) names the r-th p-subset in lexicographic order of its
+ * sorted elements.  The GA takes it only when C(m, p) < 2^63, so that one
+ * bounded 64-bit draw covers every subset.  Unranking walks the candidates x = 0, 1, ... for each
+ * element in turn and skips x while the C(m - x - 1, p - i - 1) subsets
+ * whose i-th element is x all come before r.
+ * ---------------------------------------------------------------------- */
+static uint64_t binom_u64(int32_t a, int32_t b)  /* exact; UINT64_MAX past 2^64 */
+{
+    if (b < 0 || b > a)
+        return 0;
+    if (b > a - b)
+        b = a - b;
+    unsigned __int128 c = 1;
+    for (int32_t j = 1; j <= b; ++j) {
+        c = c * (unsigned __int128)(a - b + j) / (unsigned __int128)j;
+        if (c > (unsigned __int128)UINT64_MAX)
+            return UINT64_MAX;
+    }
+    return (uint64_t)c;
+}
+
+static void unrank_subset(uint64_t r, int32_t m, int32_t p, uint8_t *bits)
+{
+    memset(bits, 0, (size_t)m);
+    int32_t x = 0;
+    for (int32_t i = 0; i < p; ++i) {
+        for (;;) {
+            const uint64_t c = binom_u64(m - x - 1, p - i - 1);
+            if (r < c)
+                break;
+            r -= c;
+            ++x;
+        }
+        bits[x] = 1;
+        ++x;
+    }
+}
+
+int orc_unrank(uint64_t r, int32_t m, int32_t p, uint64_t *mask)
+{
+    if (m < 1 || p < 1 || p > m || !mask || binom_u64(m, p) == UINT64_MAX ||
+        r >= binom_u64(m, p))
+        return ORC_EINVAL;
+    uint8_t *bits = (uint8_t *)malloc((size_t)m);
+    unrank_subset(r, m, p, bits);
+    pack(bits, m, (m + 63) / 64, mask);
+    free(bits);
+    return ORC_OK;
+}
+
 int orc_sample_subset(uint64_t seed, uint64_t gen, uint64_t chrom, int32_t m,
                       int32_t p, uint64_t *mask)
 {
@@ -589,7 +641,8 @@ int orc_mutate(uint64_t seed, uint64_t gen, uint64_t chrom, uint64_t attempt,
  * after it.  Population of P = NB x NT chromosomes; group b is chromosomes
  * b*NT .. b*NT+NT-1 (a thread block of the paper).
  *
- *  1. Population: a fresh uniform p-subset for every slot, except that from
+ *  1. Population: a fresh uniform p-subset for every slot (Floyd's method, or
+ *     with init 1 the subset of a uniform lexicographic rank), except that from
  *     the second generation on the group bests of the previous generation
  *     migrate (Section 4.5): group b's best to slot b*NT (to the same block,
  *     migration 0) or to slot b (the team of bests in one block, migration 1).
@@ -625,6 +678,7 @@ typedef struct {
     int32_t crossover_iters;  /* 0 = lg NT */
     int32_t mutation_iters;   /* 0 = lg NT */
     int32_t migration;        /* 0: to the same block, 1: all to one block */
+    int32_t init;             /* 0: uniform subset (Floyd), 1: uniform rank, unranked */
 } orc_ga_params;
 
 /* state layout (int64): */
@@ -661,6 +715,9 @@ int orc_ga_run(const int32_t *d, int64_t ld, int32_t n, int32_t m, int32_t p,
     if (n < 1 || m < 2 || p < 1 || p >= m || P < 1 || NT < 1 ||
         (NT & (NT - 1)) || P % NT || prm->generations < 1)
         return ORC_EINVAL;
+    const uint64_t nsets = binom_u64(m, p);
+    if ((prm->init != 0 && prm->init != 1) || (prm->init == 1 && nsets >= (1ull << 63)))
+        return ORC_EINVAL;
     const int32_t W = (m + 63) / 64, NB = P / NT, lg = ilog2(NT);
     const int32_t X = prm->crossover_iters > 0 ? prm->crossover_iters : lg;
     const int32_t Y = prm->mutation_iters > 0 ? prm->mutation_iters : lg;
@@ -695,7 +752,10 @@ int orc_ga_run(const int32_t *d, int64_t ld, int32_t n, int32_t m, int32_t p,
                 orc_stream s;
                 stream_open(&s, prm->seed, ORC_ROLE_INIT, g, (uint64_t)c,
                             ORC_TAG_INIT, 0);
-                sample_subset(&s, m, p, bits + (int64_t)c * m);
+                if (prm->init == 1)
+                    unrank_subset(stream_below(&s, nsets), m, p, bits + (int64_t)c * m);
+                else
+                    sample_subset(&s, m, p, bits + (int64_t)c * m);
             }
         }
         /* 2. fitness */

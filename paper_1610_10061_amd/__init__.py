@@ -72,7 +72,7 @@ class GaParams(C.Structure):
                 ("group_size", C.c_int32), ("generations", C.c_int32),
                 ("saturation", C.c_int32), ("crossover_iters", C.c_int32),
                 ("mutation_iters", C.c_int32), ("migration", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("init", C.c_int32)]
 
 
 class GaStats(C.Structure):
@@ -319,9 +319,9 @@ def pmp_instance_destroy(inst):
 
 
 def pmp_ga_create(inst, population, group_size, generations, seed,
-                  saturation=0, crossover_iters=0, mutation_iters=0, migration=0):
+                  saturation=0, crossover_iters=0, mutation_iters=0, migration=0, init=0):
     prm = GaParams(seed, population, group_size, generations, saturation,
-                   crossover_iters, mutation_iters, migration)
+                   crossover_iters, mutation_iters, migration, init)
     out = _vp()
     _check(lib().pmp_ga_create(inst, C.byref(prm), C.byref(out)), "pmp_ga_create")
     return out
@@ -368,11 +368,11 @@ def pmp_ga_profile_read(ga, stream=None):
 
 
 def pmp_solve(d, p, population, group_size, generations, seed, saturation=0,
-              crossover_iters=0, mutation_iters=0, migration=0):
+              crossover_iters=0, mutation_iters=0, migration=0, init=0):
     d = np.ascontiguousarray(d, dtype=np.int32)
     n, m = d.shape
     prm = GaParams(seed, population, group_size, generations, saturation,
-                   crossover_iters, mutation_iters, migration)
+                   crossover_iters, mutation_iters, migration, init)
     open_ = np.zeros(m, np.uint8)
     cost = _i64()
     st = GaStats()
@@ -622,13 +622,14 @@ class GA:
     """Owning wrapper of a pmp_ga handle (the instance must outlive it)."""
 
     def __init__(self, inst: Instance, population, group_size, generations,
-                 seed, saturation=0, crossover_iters=0, mutation_iters=0, migration=0):
+                 seed, saturation=0, crossover_iters=0, mutation_iters=0, migration=0,
+                 init=0):
         self.inst = inst
         self.P, self.NT = population, group_size
         self.NB = population // group_size
         self.handle = pmp_ga_create(inst.handle, population, group_size,
                                     generations, seed, saturation,
-                                    crossover_iters, mutation_iters, migration)
+                                    crossover_iters, mutation_iters, migration, init)
 
     def step(self, generations, stream=None):
         pmp_ga_step(self.handle, generations, stream)

@@ -180,6 +180,9 @@ struct GaArgs {
     uint64_t seed;
     int32_t P, NT, NB, lg, X, Y, generations, saturation;
     int32_t migration;              // PMP_MIG_SAME_BLOCK or PMP_MIG_ONE_BLOCK
+    int32_t init_rank;              // fresh chromosomes by lexicographic rank
+    const unsigned long long *binom;// with init_rank: C(a, b) at a (p + 1) + b, a < m, b <= p
+    uint64_t nsets;                 // with init_rank: C(m, p), below 2^63
     OpDraw *draws;                  // P x (X + Y) draws of this generation:
                                     // crossover stage k at k, mutation
                                     // attempt a at X + a

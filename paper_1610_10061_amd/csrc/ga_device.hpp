@@ -385,12 +385,99 @@ __device__ __forceinline__ void ga_draws_one(const GaArgs &g, uint64_t gen, int 
     }
 }
 
+// The sample stream of chromosome c read one draw at a time by the whole
+// wave: lane l holds block base + l, and the k-th draw is word k & 3 of block
+// k >> 2, read from its lane.
+struct SerialDraws {
+    uint64_t q[4];
+    int64_t base = 0, k = 0;
+
+    __device__ __forceinline__ SerialDraws(const GaArgs &g, uint64_t gen, int c, int lane)
+    {
+        philox_block(g.seed, ROLE_POPULATION, gen, (uint64_t)c, (TAG_SAMPLE << 32),
+                     (uint64_t)lane, q);
+    }
+
+    __device__ __forceinline__ uint64_t next(const GaArgs &g, uint64_t gen, int c, int lane)
+    {
+        if ((k >> 2) - base >= 64) {
+            base += 64;
+            philox_block(g.seed, ROLE_POPULATION, gen, (uint64_t)c, (TAG_SAMPLE << 32),
+                         (uint64_t)(base + lane), q);
+        }
+        const int src = (int)((k >> 2) - base), sel = (int)(k & 3);
+        const uint64_t mine = sel == 0 ? q[0] : sel == 1 ? q[1] : sel == 2 ? q[2] : q[3];
+        ++k;
+        return readlane64(mine, src);
+    }
+
+    // uniform in [0, r), r >= 1, by Lemire's multiply-and-reject method
+    __device__ __forceinline__ uint64_t below(const GaArgs &g, uint64_t gen, int c, int lane,
+                                              uint64_t r)
+    {
+        uint64_t x = next(g, gen, c, lane);
+        uint64_t lo = x * r;
+        if (lo < r) {
+            const uint64_t thresh = (0ull - r) % r;
+            while (lo < thresh) {
+                x = next(g, gen, c, lane);
+                lo = x * r;
+            }
+        }
+        return __umul64hi(x, r);
+    }
+};
+
+// Chromosome generation by rank (Section 4.1): the p-subset of lexicographic
+// rank r, r uniform below C(m, p).  Element i is the least candidate x >= x0
+// (x0 one past element i - 1) such that the subsets whose element i lies in
+// [x0, x] reach past r.  By the hockey-stick identity there are
+// C(m - x0, p - i) - C(m - x - 1, p - i) of them, so x is the least candidate
+// with C(m - x - 1, p - i) < C(m - x0, p - i) - r; the lanes test 64
+// candidates at a time and a ballot picks the least.  The subsets skipped,
+// C(m - x0, p - i) - C(m - x, p - i), come off r.  Every binomial read has
+// top index below m except C(m, p) itself.
+__device__ __forceinline__ void unrank_wave(const GaArgs &g, uint64_t r, int lane,
+                                            uint64_t &word0, uint64_t &word1)
+{
+    const int m = g.t.m, p = g.t.p;
+    const unsigned long long *bn = g.binom;  // C(a, b) at a (p + 1) + b, a < m
+    auto C = [&](int a, int b) -> uint64_t {
+        if (a < b || a < 0)
+            return 0ull;
+        return a == m ? g.nsets : (uint64_t)bn[(int64_t)a * (p + 1) + b];
+    };
+    int x0 = 0;
+    for (int i = 0; i < p; ++i) {
+        const int b = p - i;
+        const uint64_t top = C(m - x0, b);
+        const uint64_t need = top - r;  // >= 1
+        int x = -1;
+        for (int base = x0; x < 0; base += 64) {
+            const int xc = base + lane;
+            const bool hit = C(m - xc - 1, b) < need;
+            const uint64_t bal = __builtin_amdgcn_ballot_w64(hit);
+            if (bal)
+                x = base + (int)__builtin_ctzll(bal);
+        }
+        r -= top - C(m - x, b);
+        const uint64_t bit = 1ull << (x & 63);
+        if (lane == (x >> 6))
+            word0 |= bit;
+        if (lane + 64 == (x >> 6))
+            word1 |= bit;
+        x0 = x + 1;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Population of one Evolve call (Section 3.1 steps 7/11 and 16; Sections 4.1
 // and 4.5), chromosome c, by its wave.  Fresh slots get a uniform p-subset by
 // Floyd's method: floyd_wave above, or, when a draw needs Lemire's rejection
 // step, one step at a time; either way the draws are consumed in stream
-// order, so the result is the same as drawing one at a time.  From the
+// order, so the result is the same as drawing one at a time.  With init by rank
+// a fresh slot takes the subset of a uniform lexicographic rank instead, the
+// rank being the first bounded draw of the same stream.  From the
 // second generation on the group bests migrate: group b's best to slot b*NT
 // (the same block) or to slot b (one block).  The population goes to off[0]
 // with fitness "infinite", so the first stage takes it as the current one.
@@ -414,36 +501,14 @@ __device__ __forceinline__ void ga_init_one(const GaArgs &g, int c, int lane,
         // the subset's words live in the lanes: word w in lane w (w < 64)
         // or in the second register of lane w - 64
         uint64_t word0 = 0, word1 = 0;
-        if (!floyd_wave(g, gen, c, lane, sw, word0, word1)) {
+        if (g.init_rank) {
+            SerialDraws sd(g, gen, c, lane);
+            unrank_wave(g, sd.below(g, gen, c, lane, g.nsets), lane, word0, word1);
+        } else if (!floyd_wave(g, gen, c, lane, sw, word0, word1)) {
             word0 = word1 = 0ull;
-            uint64_t q[4];
-            int64_t base = 0;  // first block held by lane 0
-            philox_block(g.seed, ROLE_POPULATION, gen, (uint64_t)c,
-                         (TAG_SAMPLE << 32), (uint64_t)lane, q);
-            int64_t k = 0;  // next draw of the stream
-            auto draw = [&]() -> uint64_t {
-                if ((k >> 2) - base >= 64) {
-                    base += 64;
-                    philox_block(g.seed, ROLE_POPULATION, gen, (uint64_t)c,
-                                 (TAG_SAMPLE << 32), (uint64_t)(base + lane), q);
-                }
-                const int src = (int)((k >> 2) - base), sel = (int)(k & 3);
-                const uint64_t mine = sel == 0 ? q[0] : sel == 1 ? q[1] : sel == 2 ? q[2] : q[3];
-                ++k;
-                return readlane64(mine, src);
-            };
+            SerialDraws sd(g, gen, c, lane);
             for (int j = m - p; j < m; ++j) {
-                const uint64_t r = (uint64_t)j + 1;
-                uint64_t x = draw();
-                uint64_t lo = x * r;
-                if (lo < r) {
-                    const uint64_t thresh = (0ull - r) % r;
-                    while (lo < thresh) {
-                        x = draw();
-                        lo = x * r;
-                    }
-                }
-                const int t = (int)__umul64hi(x, r);
+                const int t = (int)sd.below(g, gen, c, lane, (uint64_t)j + 1);
                 const int tw = t >> 6;
                 const uint64_t held = lane == tw ? word0 : (lane + 64 == tw ? word1 : 0ull);
                 const bool taken =

@@ -97,6 +97,28 @@ int clients_per_block(int n, int P)
     return (int)(((cpb + 3) / 4) * 4);
 }
 
+// binom[a (p + 1) + b] = C(a, b) for a < m, b <= p, by Pascal's rule,
+// saturating at 2^63; returns C(m, p) (kBinomSat when it saturates).
+constexpr unsigned long long kBinomSat = 1ull << 63;
+
+unsigned long long binomial_table(int m, int p, std::vector<unsigned long long> &binom)
+{
+    binom.assign((size_t)m * (p + 1), 0ull);
+    auto add = [](unsigned long long x, unsigned long long y) {
+        return x >= kBinomSat - y ? kBinomSat : x + y;
+    };
+    for (int a = 0; a < m; ++a) {
+        binom[(size_t)a * (p + 1)] = 1;
+        for (int b = 1; b <= p && b <= a; ++b) {
+            const unsigned long long x = binom[(size_t)(a - 1) * (p + 1) + b - 1];
+            const unsigned long long y = b <= a - 1 ? binom[(size_t)(a - 1) * (p + 1) + b] : 0ull;
+            binom[(size_t)a * (p + 1) + b] = add(x, y);
+        }
+    }
+    // C(m, p) = C(m - 1, p - 1) + C(m - 1, p)
+    return add(binom[(size_t)(m - 1) * (p + 1) + p - 1], binom[(size_t)(m - 1) * (p + 1) + p]);
+}
+
 pmp_status status_from_err(uint32_t e)
 {
     if (e & ERR_BARRIER_TIMEOUT)
@@ -213,6 +235,8 @@ struct pmp_ga {
     unsigned long long *part = nullptr;
     uint32_t *spart = nullptr;
     uint64_t *gmask = nullptr, *best = nullptr;
+    unsigned long long *binom = nullptr;  // PMP_INIT_RANK: binomial table
+    uint64_t nsets = 0;                   // PMP_INIT_RANK: C(m, p)
     unsigned long long *gcost = nullptr, *gs = nullptr, *cstat = nullptr;
     uint32_t *arrive = nullptr;
     uint32_t *bar = nullptr;
@@ -314,6 +338,9 @@ struct pmp_ga {
         g.generations = prm.generations;
         g.saturation = prm.saturation;
         g.migration = prm.migration;
+        g.init_rank = prm.init == PMP_INIT_RANK;
+        g.binom = binom;
+        g.nsets = nsets;
         for (int k = 0; k < 2; ++k) {
             g.cur[k] = cur[k];
             g.fit[k] = fit[k];
@@ -1137,6 +1164,7 @@ void pmp_ga_destroy(pmp_ga *ga)
         dfree(ga->ok[k]);
     }
     dfree(ga->improved);
+    dfree(ga->binom);
     dfree(ga->draws);
     dfree(ga->mut);
     dfree(ga->mut_ok);
@@ -1177,9 +1205,16 @@ pmp_status pmp_ga_create(pmp_instance *inst, const pmp_ga_params *prm,
                     "population %d must be a multiple of a power-of-two group size %d <= 1024",
                     P, NT);
     if (prm->generations < 1 || prm->saturation < 0 || prm->crossover_iters < 0 ||
-        prm->mutation_iters < 0 || prm->reserved ||
-        (prm->migration != PMP_MIG_SAME_BLOCK && prm->migration != PMP_MIG_ONE_BLOCK))
+        prm->mutation_iters < 0 ||
+        (prm->migration != PMP_MIG_SAME_BLOCK && prm->migration != PMP_MIG_ONE_BLOCK) ||
+        (prm->init != PMP_INIT_SUBSET && prm->init != PMP_INIT_RANK))
         return fail(PMP_EINVAL, "bad GA parameters");
+    std::vector<unsigned long long> binom;
+    const unsigned long long nsets =
+        prm->init == PMP_INIT_RANK ? binomial_table(inst->m, inst->p, binom) : 0ull;
+    if (prm->init == PMP_INIT_RANK && nsets >= kBinomSat)
+        return fail(PMP_EUNSUPPORTED, "C(%d, %d) is too large to draw ranks from", inst->m,
+                    inst->p);
     pmp_ga *ga = new pmp_ga;
     ga->inst = inst;
     ga->prm = *prm;
@@ -1203,7 +1238,8 @@ pmp_status pmp_ga_create(pmp_instance *inst, const pmp_ga_params *prm,
           dalloc(&ga->gmask, (size_t)ga->NB * W) || dalloc(&ga->best, W) ||
           dalloc(&ga->gcost, (size_t)ga->NB) || dalloc(&ga->gs, GS_COUNT) ||
           dalloc(&ga->cstat, (size_t)P * CS_COUNT) || dalloc(&ga->arrive, 1) ||
-          dalloc(&ga->bar, kBarrierWords);
+          dalloc(&ga->bar, kBarrierWords) ||
+          (!binom.empty() && dalloc(&ga->binom, binom.size()));
     if (bad) {
         pmp_ga_destroy(ga);
         return fail(PMP_ENOMEM, "GA buffers for P=%d", P);
@@ -1228,6 +1264,10 @@ pmp_status pmp_ga_create(pmp_instance *inst, const pmp_ga_params *prm,
         e = hipMemset(ga->arrive, 0, sizeof(uint32_t));
     if (e == hipSuccess)
         e = hipMemset(ga->bar, 0, sizeof(uint32_t) * kBarrierWords);
+    if (e == hipSuccess && ga->binom)
+        e = hipMemcpy(ga->binom, binom.data(), sizeof(unsigned long long) * binom.size(),
+                      hipMemcpyHostToDevice);
+    ga->nsets = nsets;
     {
         const char *mode = getenv("PMP_GA_MODE");
         ga->persistent = mode && strcmp(mode, "persistent") == 0;
@@ -2251,23 +2291,10 @@ pmp_status pmp_exhaustive(pmp_instance *inst, uint64_t *best_mask, int64_t *best
     if (!inst)
         return fail(PMP_EINVAL, "instance is NULL");
     const int m = inst->m, p = inst->p, n = inst->n, W = inst->W;
-    // binomials C(a, b), a < m, b <= p, saturating at 2^63
-    const unsigned long long kSat = 1ull << 63;
-    std::vector<unsigned long long> binom((size_t)m * (p + 1), 0ull);
-    for (int a = 0; a < m; ++a) {
-        binom[(size_t)a * (p + 1)] = 1;
-        for (int b = 1; b <= p && b <= a; ++b) {
-            const unsigned long long x = binom[(size_t)(a - 1) * (p + 1) + b - 1];
-            const unsigned long long y = b <= a - 1 ? binom[(size_t)(a - 1) * (p + 1) + b] : 0ull;
-            binom[(size_t)a * (p + 1) + b] = (x >= kSat - y) ? kSat : x + y;
-        }
-    }
-    // C(m, p) = C(m-1, p-1) + C(m-1, p)
-    const unsigned long long x = binom[(size_t)(m - 1) * (p + 1) + p - 1];
-    const unsigned long long y = binom[(size_t)(m - 1) * (p + 1) + p];
-    if (x >= kSat - y || x + y >= (1ull << 62))
+    std::vector<unsigned long long> binom;
+    const unsigned long long total = binomial_table(m, p, binom);
+    if (total >= (1ull << 62))
         return fail(PMP_EUNSUPPORTED, "C(%d, %d) is too large to enumerate", m, p);
-    const unsigned long long total = x + y;
     if (count)
         *count = (int64_t)total;
     hipStream_t s = (hipStream_t)stream;

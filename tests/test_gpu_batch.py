@@ -47,34 +47,34 @@ def _assert_same(a, b):
 def _mini_batch():
     """Ragged shapes: graph and Euclidean, n != m, small and large p, p = 1
     (no crossover), several group sizes and stage counts, m past 64, both
-    migration variants."""
+    migration variants, both ways of generating chromosomes."""
     rng = np.random.default_rng(3)
     cases = []
-    for k, (kind, n, m, p, P, NT, X, Y, sat, mig) in enumerate([
-            ("graph", 60, 60, 4, 64, 16, 0, 0, 0, 1),
-            ("euclid", 90, 90, 9, 128, 64, 0, 0, 3, 0),
-            ("rand", 37, 150, 20, 64, 32, 5, 2, 0, 0),
-            ("euclid", 200, 200, 1, 32, 8, 0, 0, 0, 1),
-            ("graph", 130, 130, 30, 256, 256, 0, 0, 0, 0),
-            ("rand", 20, 300, 150, 64, 64, 2, 9, 0, 0),
-            ("euclid", 70, 70, 5, 8, 1, 0, 0, 2, 0),
-            ("graph", 80, 80, 6, 256, 8, 0, 0, 0, 1)]):
+    for k, (kind, n, m, p, P, NT, X, Y, sat, mig, init) in enumerate([
+            ("graph", 60, 60, 4, 64, 16, 0, 0, 0, 1, 1),
+            ("euclid", 90, 90, 9, 128, 64, 0, 0, 3, 0, 0),
+            ("rand", 37, 150, 20, 64, 32, 5, 2, 0, 0, 0),
+            ("euclid", 200, 200, 1, 32, 8, 0, 0, 0, 1, 0),
+            ("graph", 130, 130, 30, 256, 256, 0, 0, 0, 0, 0),
+            ("rand", 20, 300, 150, 64, 64, 2, 9, 0, 0, 0),
+            ("euclid", 70, 70, 5, 8, 1, 0, 0, 2, 0, 1),
+            ("graph", 80, 80, 6, 256, 8, 0, 0, 0, 1, 1)]):
         if kind == "graph":
             d = gi.graph_instance(n, 2 * n, 100 + k)
         elif kind == "euclid":
             d = gi.euclid_instance(n, 100 + k)
         else:
             d = rng.integers(0, 500, size=(n, m)).astype(np.int32)
-        cases.append((d, p, P, NT, X, Y, sat, 7 + k, mig))
+        cases.append((d, p, P, NT, X, Y, sat, 7 + k, mig, init))
     return cases
 
 
 def _make(pm, cases, G):
     insts, gas = [], []
-    for d, p, P, NT, X, Y, sat, seed, mig in cases:
+    for d, p, P, NT, X, Y, sat, seed, mig, init in cases:
         inst = pm.Instance(d, p)
         insts.append(inst)
-        gas.append(pm.GA(inst, P, NT, G, seed, sat, X, Y, mig))
+        gas.append(pm.GA(inst, P, NT, G, seed, sat, X, Y, mig, init))
     return insts, gas
 
 
@@ -97,10 +97,10 @@ def test_batch_equals_single_runs_and_oracle(pm, graph, bmode):
         rinsts, refs = _make(pm, cases, G)
         for r in refs:
             r.step(G)
-        for (d, p, P, NT, X, Y, sat, seed, mig), ga, ref in zip(cases, gas, refs):
+        for (d, p, P, NT, X, Y, sat, seed, mig, init), ga, ref in zip(cases, gas, refs):
             a, b = _state(ga), _state(ref)
             _assert_same(a, b)
-            st = oracle.GaState(d.shape[0], d.shape[1], p, P, NT, G, seed, sat, X, Y, mig)
+            st = oracle.GaState(d.shape[0], d.shape[1], p, P, NT, G, seed, sat, X, Y, mig, init)
             oracle.ga_run(d, st, G)
             np.testing.assert_array_equal(a[0], st.pop)
             assert a[5] == st.best_cost

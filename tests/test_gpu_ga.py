@@ -52,13 +52,14 @@ def mode(request):
             os.environ[k] = v
 
 
-def _compare(pm, d, p, P, NT, G, seed, steps, sat=0, X=0, Y=0, mig=0):
+def _compare(pm, d, p, P, NT, G, seed, steps, sat=0, X=0, Y=0, mig=0, init=0):
     n, m = d.shape
     print("case", d.shape, "p", p, "P", P, "NT", NT, "steps", steps, "seed", seed,
-          "migration", mig, "mode", {k: os.environ.get(k) for k in _ENV}, flush=True)
+          "migration", mig, "init", init, "mode", {k: os.environ.get(k) for k in _ENV},
+          flush=True)
     inst = pm.Instance(d, p)
-    ga = pm.GA(inst, P, NT, G, seed, sat, X, Y, mig)
-    st = oracle.GaState(n, m, p, P, NT, G, seed, sat, X, Y, mig)
+    ga = pm.GA(inst, P, NT, G, seed, sat, X, Y, mig, init)
+    st = oracle.GaState(n, m, p, P, NT, G, seed, sat, X, Y, mig, init)
     for k in steps:
         ga.step(k)
         oracle.ga_run(d, st, k)
@@ -165,6 +166,32 @@ def test_ga_rejects_unknown_migration(pm):
     inst = pm.Instance(gi.graph_instance(20, 40, 0), 4)
     with pytest.raises(pm.PmpError):
         pm.GA(inst, 32, 8, 5, 1, migration=2)
+
+
+def test_ga_init_by_rank(pm, mode):
+    """Chromosomes generated from uniform lexicographic ranks (Section 4.1)
+    in every launch scheme: fresh slots each generation, with migrants."""
+    d = gi.graph_instance(100, 200, 4)
+    _compare(pm, d, 5, 128, 16, 10, seed=17, steps=[1, 4], init=1)
+
+
+@pytest.mark.parametrize("n,m,p", [(40, 62, 31), (40, 300, 4), (40, 130, 127),
+                                   (32, 5000, 3), (30, 67, 1)],
+                         ids=["C(62,31)", "m=300", "p=m-3", "m=5000", "p=1"])
+def test_ga_init_by_rank_shapes(pm, n, m, p):
+    """Ranks up to 4.7e17, candidates that run past one 64-lane batch, subsets
+    that fill almost every slot, and words past 64 (the second word register
+    of each lane)."""
+    d = np.random.default_rng(m * 7 + p).integers(0, 300, size=(n, m)).astype(np.int32)
+    _compare(pm, d, p, 64, 8, 3, seed=31, steps=[2], init=1)
+
+
+def test_ga_init_by_rank_rejects(pm):
+    inst = pm.Instance(gi.graph_instance(100, 200, 0), 50)
+    with pytest.raises(pm.PmpError):  # C(100, 50) is past 2^63
+        pm.GA(inst, 32, 8, 5, 1, init=1)
+    with pytest.raises(pm.PmpError):
+        pm.GA(inst, 32, 8, 5, 1, init=2)
 
 
 @pytest.mark.parametrize("m,p", [(150, 147), (130, 129), (200, 129)],

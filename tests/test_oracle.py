@@ -9,6 +9,7 @@ import itertools
 import json
 import math
 import os
+import random
 
 import numpy as np
 import pytest
@@ -265,6 +266,76 @@ def test_subset_sampler_large():
     for c in range(20):
         mask = oracle.sample_subset(3, 5, c, m, p)
         assert gi.unpack_masks(mask[None, :], m).sum() == p
+
+
+@pytest.mark.parametrize("m,p", [(1, 1), (6, 3), (9, 4), (12, 1), (10, 9), (65, 2), (70, 68)])
+def test_unrank_follows_itertools_order(m, p):
+    """Section 4.1 numbers the p-subsets in lexicographic order; itertools
+    lists combinations in that order."""
+    for r, s in enumerate(itertools.combinations(range(m), p)):
+        got = gi.unpack_masks(oracle.unrank(r, m, p)[None, :], m)[0].nonzero()[0]
+        assert got.tolist() == list(s)
+        if r >= 3000:
+            break
+    total = math.comb(m, p)
+    last = gi.unpack_masks(oracle.unrank(total - 1, m, p)[None, :], m)[0].nonzero()[0]
+    assert last.tolist() == list(range(m - p, m))
+    with pytest.raises(oracle.OracleError):
+        oracle.unrank(total, m, p)
+
+
+def test_unrank_large_ranks():
+    """Ranks across a space of 4.7e17 subsets: the subset's own rank, summed
+    from its elements by the combinatorial number system, is r."""
+    m, p = 62, 31
+    total = math.comb(m, p)
+    rng = random.Random(3)
+    for r in [0, 1, total // 3, total - 2] + [rng.randrange(total) for _ in range(50)]:
+        s = gi.unpack_masks(oracle.unrank(r, m, p)[None, :], m)[0].nonzero()[0].tolist()
+        assert len(s) == p
+        # rank = sum over i of the subsets that share elements 0..i-1 and have
+        # a smaller element i
+        rank, prev = 0, -1
+        for i, x in enumerate(s):
+            rank += sum(math.comb(m - y - 1, p - i - 1) for y in range(prev + 1, x))
+            prev = x
+        assert rank == r
+
+
+def test_ga_init_by_rank_draws_uniform_ranks():
+    """With NT = 1 there are no operator stages, so after one generation the
+    population is the fresh one: with init 1 chromosome c is the subset of
+    rank below(C(m, p)), the first draw of its sample stream, and the subsets
+    are uniform."""
+    m, p, P = 6, 3, 4000
+    d = gi.graph_instance(m, 2 * m, 1)
+    st = oracle.GaState(m, m, p, P, 1, 5, seed=21, init=1)
+    oracle.ga_run(d, st, 1)
+    total = math.comb(m, p)
+    seen = {}
+    for c in range(P):
+        r = int(oracle.stream_draws(21, oracle.ROLE_INIT, 0, c, oracle.TAG_INIT, 0, [total])[0])
+        np.testing.assert_array_equal(st.pop[c], oracle.unrank(r, m, p))
+        s = tuple(gi.unpack_masks(st.pop[c][None, :], m)[0].nonzero()[0].tolist())
+        seen[s] = seen.get(s, 0) + 1
+    assert len(seen) == total
+    counts = np.array(list(seen.values()))
+    exp = counts.sum() / total
+    assert ((counts - exp) ** 2 / exp).sum() < 60  # 19 dof
+    # the default init draws other subsets from the same stream
+    dflt = oracle.GaState(m, m, p, P, 1, 5, seed=21)
+    oracle.ga_run(d, dflt, 1)
+    assert (dflt.pop != st.pop).any()
+
+
+def test_ga_init_by_rank_needs_a_64_bit_rank():
+    d = gi.graph_instance(100, 200, 0)
+    with pytest.raises(oracle.OracleError):
+        oracle.ga_run(d, oracle.GaState(100, 100, 50, 64, 16, 2, seed=1, init=1), 1)
+    st = oracle.GaState(100, 100, 5, 64, 16, 3, seed=1, init=1)
+    oracle.ga_run(d, st, 3)
+    assert (gi.unpack_masks(st.pop, 100).sum(axis=1) == 5).all()
+    np.testing.assert_array_equal(oracle.objective(d, st.pop, 5), st.fit)
 
 
 def test_crossover_invariants():
