@@ -110,6 +110,9 @@ hipError_t launch_sort_rows(const int32_t *d, int64_t ld, int32_t n, int32_t m,
                             int32_t *delta, int32_t *ds, uint32_t *err,
                             hipStream_t s);
 // e0/e1 (optional) are recorded at the kernel's start and end.
+// Workgroups of the evaluation kernel for W words per chromosome (reduced
+// or paired walk) that one CU holds at once.
+int eval_workgroups_per_cu(int W, bool reduced, bool paired);
 hipError_t launch_eval(const EvalArgs &a, hipStream_t s, hipEvent_t e0 = nullptr,
                        hipEvent_t e1 = nullptr);
 hipError_t launch_reduce(const EvalArgs &a, unsigned long long *fitness,

@@ -6,20 +6,22 @@
 // D'_{i,s*} (the sum of the first s* gap terms).  fitness[c] is the sum over
 // clients, exact in 64-bit integers.
 //
-// Mapping (gfx950, wave64).  A workgroup owns a tile of 64 chromosomes (one
-// per lane, their masks staged in LDS) and a tile of clients; each of its
-// four waves takes every fourth client of the tile.  For one client the wave
-// loads 64 consecutive entries of Pi'_i and D'_i, one per lane (coalesced),
-// and then, for each chromosome of the tile, every lane tests "is the
-// facility at my position open in chromosome c" with one LDS read of the
-// word holding that facility's bit.  A ballot gives the 64 answers; its
-// lowest set bit is the chromosome's first open position in this chunk.
-// That position is written into lane c of a register, and one ds_bpermute
-// then fetches each chromosome's D' entry from the lane that holds it, so a
-// (chromosome, client) pair costs one LDS read and three VALU operations
-// whatever its scan length up to 64.  Chromosomes still unmatched go on to
-// the next 64 entries.  This replaces the paper's one-thread-per-chromosome
-// loop: lanes never diverge and Pi' rows are read once per 64 chromosomes.
+// Mapping (gfx950, wave64).  A workgroup owns a tile of 64 chromosomes and
+// a tile of clients; each of its four waves takes every fourth client of the
+// tile.  The tile's masks are staged in LDS and turned facility-major once:
+// T[j] is a 64-bit word whose bit c says whether facility j is open in
+// chromosome c (a 64 x 64 bit transpose per 64 facilities).  For one client
+// the wave loads 64 consecutive entries of Pi'_i and D'_i, one per lane
+// (coalesced), and every lane reads T of the facility at its position: lane
+// k then holds row k of the 64 x 64 bit matrix "position k is open in
+// chromosome c".  One more transpose in registers (lane exchanges and bit
+// selects, about 35 instructions) gives lane c its column, and the column's
+// lowest set bit is chromosome c's first open position in this chunk.  One
+// ds_bpermute then fetches each chromosome's D' entry from the lane that
+// holds it, so a chunk costs the same for all 64 chromosomes whatever their
+// scan lengths up to 64.  Chromosomes still unmatched go on to the next 64
+// entries.  This replaces the paper's one-thread-per-chromosome loop: lanes
+// never diverge and Pi' rows are read once per 64 chromosomes.
 //
 // Partial sums of the four waves are combined in LDS and stored, one int64
 // per (client tile, chromosome), with plain stores; the consumer (the
@@ -30,158 +32,116 @@
 // Pi' and D' before it works on the current one.
 #pragma once
 
-#include <utility>
-
 #include "common.hpp"
 
 namespace pmp {
 
-using kLanes = std::make_integer_sequence<int, kEvalTile>;
-using kQuads = std::make_integer_sequence<int, kEvalTile / 4>;
 
-// Lowest set lane of a ballot, -1 when none (s_ff1_i32_b64 returns -1 for
-// zero, so no compare and select are needed around it).
-__device__ __forceinline__ int first_lane(uint64_t b)
+// Lowest set bit of x, -1 when x is 0 (v_ffbl_b32 returns -1 for zero).
+__device__ __forceinline__ int lowest_bit(uint32_t x)
 {
     int r;
-    asm("s_ff1_i32_b64 %0, %1" : "=s"(r) : "s"(b));
+    asm("v_ffbl_b32 %0, %1" : "=v"(r) : "v"(x));
     return r;
 }
 
-// Lane C of `hit` takes the wave-uniform value `v` (v_writelane_b32 with the
-// lane as an inline constant).
-template <int C>
-__device__ __forceinline__ void write_lane(int &hit, int v)
+// The value of v in lane (this lane) ^ J: ds_swizzle's xor mode (within 32
+// lanes) for J = 16, 8, 4, DPP quad permutations for J = 2, 1.
+template <int J>
+__device__ __forceinline__ uint32_t from_lane_xor(uint32_t v)
 {
-    asm("v_writelane_b32 %0, %1, %2" : "+v"(hit) : "s"(v), "n"(C));
+    if constexpr (J >= 4)
+        return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1F | (J << 10));
+    else
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, J == 2 ? 0x4E : 0xB1, 0xF, 0xF,
+                                                     false);
 }
 
-// All 64 chromosomes of the tile against one 64-entry chunk of a Pi' row.
-template <int WD, int C>
-__device__ __forceinline__ void match_one(const uint32_t *sm, uint32_t bit,
-                                          int &hit)
-{
-    const uint32_t w = sm[C * WD];
-    const uint64_t b = __builtin_amdgcn_ballot_w64((w & bit) != 0u);
-    write_lane<C>(hit, first_lane(b));
-}
+// Per-lane operands of the transpose steps J = 16, 8, 4, 2, 1 (index 0-4):
+// the bits a lane keeps, and the rotation that brings its partner's bits
+// into the others.
+struct TransposeLanes {
+    uint32_t keep[5], rot[5];
 
-// Chromosomes 4Q .. 4Q+3 together: four ballots live in four SGPR pairs and
-// one asm block takes their four lowest lanes, so the compare, find-first
-// and write-lane steps of neighbouring chromosomes overlap instead of
-// waiting on one shared scalar register.  Chromosome C goes to register
-// C mod 4.
-template <int WD, int Q>
-__device__ __forceinline__ void match_quad(const uint32_t *sm, uint32_t bit, int &h0,
-                                           int &h1, int &h2, int &h3)
-{
-    constexpr int C = 4 * Q;
-    const uint32_t w0 = sm[C * WD], w1 = sm[(C + 1) * WD];
-    const uint32_t w2 = sm[(C + 2) * WD], w3 = sm[(C + 3) * WD];
-    const uint64_t b0 = __builtin_amdgcn_ballot_w64((w0 & bit) != 0u);
-    const uint64_t b1 = __builtin_amdgcn_ballot_w64((w1 & bit) != 0u);
-    const uint64_t b2 = __builtin_amdgcn_ballot_w64((w2 & bit) != 0u);
-    const uint64_t b3 = __builtin_amdgcn_ballot_w64((w3 & bit) != 0u);
-    int f0, f1, f2, f3;
-    asm("s_ff1_i32_b64 %0, %4\n\t"
-        "s_ff1_i32_b64 %1, %5\n\t"
-        "s_ff1_i32_b64 %2, %6\n\t"
-        "s_ff1_i32_b64 %3, %7"
-        : "=&s"(f0), "=&s"(f1), "=&s"(f2), "=&s"(f3)
-        : "s"(b0), "s"(b1), "s"(b2), "s"(b3));
-    write_lane<C>(h0, f0);
-    write_lane<C + 1>(h1, f1);
-    write_lane<C + 2>(h2, f2);
-    write_lane<C + 3>(h3, f3);
-}
-
-// Every chromosome of the tile (kEvalTile = 64) against one chunk.
-template <int WD, int... Q>
-__device__ __forceinline__ int match_dense(const uint32_t *sm, uint32_t bit,
-                                           int lane,
-                                           std::integer_sequence<int, Q...>)
-{
-    int h0 = -1, h1 = -1, h2 = -1, h3 = -1;
-    (match_quad<WD, Q>(sm, bit, h0, h1, h2, h3), ...);
-    const int q = lane & 3;
-    return q == 0 ? h0 : q == 1 ? h1 : q == 2 ? h2 : h3;
-}
-
-// Two clients per chunk (short scans): lanes 0-31 hold the first 32 entries
-// of client A's row, lanes 32-63 those of client B.  One compare per
-// chromosome serves both rows; the ballot's low and high halves give each
-// client's first open position.
-template <int WD, int Q>
-__device__ __forceinline__ void match_quad2(const uint32_t *sm, uint32_t bit, int (&ha)[4],
-                                            int (&hb)[4])
-{
-    constexpr int C = 4 * Q;
-    const uint32_t w0 = sm[C * WD], w1 = sm[(C + 1) * WD];
-    const uint32_t w2 = sm[(C + 2) * WD], w3 = sm[(C + 3) * WD];
-    const uint64_t b0 = __builtin_amdgcn_ballot_w64((w0 & bit) != 0u);
-    const uint64_t b1 = __builtin_amdgcn_ballot_w64((w1 & bit) != 0u);
-    const uint64_t b2 = __builtin_amdgcn_ballot_w64((w2 & bit) != 0u);
-    const uint64_t b3 = __builtin_amdgcn_ballot_w64((w3 & bit) != 0u);
-    int a0, a1, a2, a3, e0, e1, e2, e3;
-    asm("s_ff1_i32_b32 %0, %8\n\t"
-        "s_ff1_i32_b32 %1, %9\n\t"
-        "s_ff1_i32_b32 %2, %10\n\t"
-        "s_ff1_i32_b32 %3, %11\n\t"
-        "s_ff1_i32_b32 %4, %12\n\t"
-        "s_ff1_i32_b32 %5, %13\n\t"
-        "s_ff1_i32_b32 %6, %14\n\t"
-        "s_ff1_i32_b32 %7, %15"
-        : "=&s"(a0), "=&s"(a1), "=&s"(a2), "=&s"(a3), "=&s"(e0), "=&s"(e1), "=&s"(e2),
-          "=&s"(e3)
-        : "s"((uint32_t)b0), "s"((uint32_t)b1), "s"((uint32_t)b2), "s"((uint32_t)b3),
-          "s"((uint32_t)(b0 >> 32)), "s"((uint32_t)(b1 >> 32)), "s"((uint32_t)(b2 >> 32)),
-          "s"((uint32_t)(b3 >> 32)));
-    write_lane<C>(ha[0], a0);
-    write_lane<C + 1>(ha[1], a1);
-    write_lane<C + 2>(ha[2], a2);
-    write_lane<C + 3>(ha[3], a3);
-    write_lane<C>(hb[0], e0);
-    write_lane<C + 1>(hb[1], e1);
-    write_lane<C + 2>(hb[2], e2);
-    write_lane<C + 3>(hb[3], e3);
-}
-
-template <int WD, int... Q>
-__device__ __forceinline__ void match_dense2(const uint32_t *sm, uint32_t bit, int lane,
-                                             int &hit_a, int &hit_b,
-                                             std::integer_sequence<int, Q...>)
-{
-    int ha[4] = {-1, -1, -1, -1}, hb[4] = {-1, -1, -1, -1};
-    (match_quad2<WD, Q>(sm, bit, ha, hb), ...);
-    const int q = lane & 3;
-    hit_a = q == 0 ? ha[0] : q == 1 ? ha[1] : q == 2 ? ha[2] : ha[3];
-    hit_b = q == 0 ? hb[0] : q == 1 ? hb[1] : q == 2 ? hb[2] : hb[3];
-}
-
-// Only the chromosomes in q (few left after the first chunk).
-template <int WD>
-__device__ __forceinline__ int match_sparse(const uint32_t *sm, uint32_t bit,
-                                            uint64_t q, int lane)
-{
-    int hit = -1;
-    while (q) {
-        const int c = __builtin_ctzll(q);
-        q &= q - 1;
-        const uint32_t w = sm[c * WD];
-        const uint64_t b = __builtin_amdgcn_ballot_w64((w & bit) != 0u);
-        const int v = first_lane(b);
-        hit = lane == c ? v : hit;
+    __device__ __forceinline__ explicit TransposeLanes(int lane)
+    {
+        constexpr uint32_t M[5] = {0x0000FFFFu, 0x00FF00FFu, 0x0F0F0F0Fu, 0x33333333u,
+                                   0x55555555u};
+#pragma unroll
+        for (int s = 0; s < 5; ++s) {
+            const int J = 16 >> s;
+            const bool up = (lane & J) != 0;
+            keep[s] = up ? ~M[s] : M[s];
+            rot[s] = up ? (uint32_t)J : (uint32_t)(32 - J);
+        }
     }
-    return hit;
+};
+
+// Step J of a 32 x 32 bit transpose (rows in the lanes of each half-wave,
+// one 32-bit word per row): exchange bit J of the row and the column index.
+// A lane whose row has that bit clear keeps its bits at positions with bit J
+// clear and takes its partner's bits moved up by J; the partner keeps the
+// others and takes this lane's moved down by J.  Rotations stand in for the
+// shifts: the bits they wrap around land in positions that are not taken.
+template <int S>
+__device__ __forceinline__ void transpose_step(uint32_t &lo, uint32_t &hi,
+                                               const TransposeLanes &tl)
+{
+    constexpr int J = 16 >> S;
+    const uint32_t ylo = from_lane_xor<J>(lo), yhi = from_lane_xor<J>(hi);
+    const uint32_t k = tl.keep[S], r = tl.rot[S];
+    lo = (lo & k) | (__builtin_amdgcn_alignbit(ylo, ylo, r) & ~k);
+    hi = (hi & k) | (__builtin_amdgcn_alignbit(yhi, yhi, r) & ~k);
+}
+
+// Transpose of the 64 x 64 bit matrix whose row l is lane l's (hi:lo): on
+// return lane c holds column c, bit l = bit c of row l.  Bit 5 of the row and
+// column index is exchanged first (lanes 32-63 give their low words for the
+// high words of lanes 0-31), then bits 4 to 0 within each half-wave.
+__device__ __forceinline__ void transpose64(uint32_t &lo, uint32_t &hi, int lane,
+                                            const TransposeLanes &tl)
+{
+    const bool up = lane >= 32;
+    const uint32_t got =
+        (uint32_t)__builtin_amdgcn_ds_bpermute((lane ^ 32) << 2, (int)(up ? lo : hi));
+    lo = up ? got : lo;
+    hi = up ? hi : got;
+    transpose_step<0>(lo, hi, tl);
+    transpose_step<1>(lo, hi, tl);
+    transpose_step<2>(lo, hi, tl);
+    transpose_step<3>(lo, hi, tl);
+    transpose_step<4>(lo, hi, tl);
+}
+
+// All 64 chromosomes of the tile against one 64-entry chunk: lane k's row is
+// T of the facility at its position (0 for positions that do not count).
+// Returns, in lane c, chromosome c's first open position in the chunk (-1 if
+// none).  first_open2: lanes 0-31 and 32-63 hold the first 32 positions of
+// two clients A and B, and lane c gets both clients' first open positions.
+__device__ __forceinline__ int first_open(uint64_t row, int lane, const TransposeLanes &tl)
+{
+    uint32_t lo = (uint32_t)row, hi = (uint32_t)(row >> 32);
+    transpose64(lo, hi, lane, tl);
+    const int a = lowest_bit(lo), b = lowest_bit(hi);
+    return a >= 0 ? a : (b >= 0 ? 32 + b : -1);
+}
+
+__device__ __forceinline__ void first_open2(uint64_t row, int lane, const TransposeLanes &tl,
+                                            int &hit_a, int &hit_b)
+{
+    uint32_t lo = (uint32_t)row, hi = (uint32_t)(row >> 32);
+    transpose64(lo, hi, lane, tl);
+    hit_a = lowest_bit(lo);
+    hit_b = lowest_bit(hi);
 }
 
 // The rest of one client's walk from position `base` for the chromosomes in
-// `pend` (64-entry chunks, loaded here).
-template <int WD>
+// `pend` (64-entry chunks, loaded here).  sT: the tile's facility-major masks.
 __device__ __forceinline__ void walk_tail(const EvalArgs &a, const uint16_t *prow,
                                           const int32_t *drow, int base, uint64_t pend,
-                                          int lane, const uint32_t *smask,
-                                          unsigned long long &acc, uint32_t &scn)
+                                          int lane, const uint64_t *sT,
+                                          const TransposeLanes &tl, unsigned long long &acc,
+                                          uint32_t &scn)
 {
     for (; pend != 0ull; base += 64) {
         if (base >= a.t.K) {  // fewer than p open facilities
@@ -190,18 +150,12 @@ __device__ __forceinline__ void walk_tail(const EvalArgs &a, const uint16_t *pro
             break;
         }
         const int k = base + lane;
-        uint32_t off = 0, bit = 0;
-        int32_t dist = 0;
-        if (k < a.t.K) {
-            const uint32_t j = prow[k];
-            off = j >> 5;
-            bit = 1u << (j & 31u);
-            dist = drow[k];
-        }
-        const uint32_t *sm = smask + off;
-        const int hit = __builtin_popcountll(pend) >= 16
-                            ? match_dense<WD>(sm, bit, lane, kQuads{})
-                            : match_sparse<WD>(sm, bit, pend, lane);
+        const bool in = k < a.t.K;
+        const int kc = in ? k : a.t.K - 1;
+        const uint32_t j = prow[kc];
+        const int32_t dist = drow[kc];
+        const uint64_t t = sT[j];
+        const int hit = first_open(in ? t : 0ull, lane, tl);
         const bool found = ((pend >> lane) & 1ull) && hit >= 0;
         const int32_t cost = __builtin_amdgcn_ds_bpermute((hit & 63) << 2, dist);
         if (found) {
@@ -212,31 +166,43 @@ __device__ __forceinline__ void walk_tail(const EvalArgs &a, const uint16_t *pro
     }
 }
 
+// LDS words (32-bit) eval_tile needs for its staged masks: rows of WD words
+// at an odd stride WD + 1, so that reading one word of every row (a lane per
+// row) hits 64 different banks.  The facility-major copy, 64 W 64-bit words,
+// reuses the same space.
+template <int WD>
+constexpr int eval_stage_words()
+{
+    static_assert(WD % 2 == 0, "WD is even");
+    return kEvalTile * (WD + 1);
+}
+
 // Evaluate chromosome tile tc (64 chromosomes) on client tile ti and store
 // the tile's partial sums.  Called by a whole 256-thread workgroup;
-// smask holds 64 * WD words, sred 2 * kEvalWaves * 64 words.
+// smask holds eval_stage_words<WD>() words (8-byte aligned), sred
+// 2 * kEvalWaves * 64 words.
 //
 // R: the walk tables of the reduced polynomial (k_hbp.hip) instead of the
 // instance's: row i stops at position K_i - 1 at the latest (a.rlen) and
 // the value read there is the int64 running sum a.e64.  The stop is made
-// with no extra work in the walk: the last position's lane tests a mask
-// word that is all ones for every chromosome (word 2W of each staged row,
-// so WD > 2W).
+// with no extra work in the walk: the last position's lane takes a row of
+// all ones, as if its facility were open in every chromosome.
 //
 // H (short scans, not with R): a wave walks its clients two at a time, the
-// first 32 entries of each row in one chunk (match_dense2); the few rows
+// first 32 entries of each row in one chunk (first_open2); the few rows
 // whose first open facility lies past entry 31 finish in walk_tail.
 template <int WD, bool R = false, bool H = false>
 __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
                                           uint32_t *smask,
                                           unsigned long long *sred)
 {
+    constexpr int SD = WD + 1;  // staged row stride
     const int c0 = tc * kEvalTile;
     const int i0 = ti * a.clients_per_block;
     const int i1 = min(a.t.n, i0 + a.clients_per_block);
     const int lane = threadIdx.x & 63;
     const int wave = wave_id();
-    const int W2 = 2 * a.t.W;
+    const int W = a.t.W, W2 = 2 * W;
 
     // The tile's independent loads go out together (one memory round trip):
     // this lane's active flag, chunk 0 of the wave's first client, and the
@@ -255,7 +221,7 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
     const bool in_row = pos < a.t.K;
     const int last = i1 - 1;
     const int row_first = (H && lane >= 32) ? min(i + kEvalWaves, last) : min(i, last);
-    const uint32_t j_first = a.t.pi[(int64_t)row_first * a.t.pitch + col];
+    uint32_t j_cur = a.t.pi[(int64_t)row_first * a.t.pitch + col];
     int32_t d_cur = 0;
     long long e_cur = 0;
     int k_cur = 0;  // R: the row's length K_i
@@ -291,7 +257,7 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
             const int k = (int)threadIdx.x + (r0 + r) * kThreads;
             const int c = k / WD, w = k - (k / WD) * WD;
             if (k < kTot)
-                smask[k] = (w < W2 && c < rows) ? v[r] : ((R && w == W2) ? ~0u : 0u);
+                smask[c * SD + w] = (w < W2 && c < rows) ? v[r] : 0u;
         }
     }
     const bool my_act = my_c < a.P && (a.active == nullptr || actv != 0);
@@ -311,7 +277,7 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
         for (int k = 0; k < W2; ++k) {
             int w = lane + k;
             w = w >= W2 ? w - W2 * (w / W2) : w;
-            const uint32_t v = smask[lane * WD + w];
+            const uint32_t v = smask[lane * SD + w];
             ones += __builtin_popcount(v);
             if (w > full || (w == full && rem == 0))
                 stray |= v;
@@ -324,11 +290,32 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
             atomicOr(a.err, ERR_STRAY_BITS);
     }
 
+    // Facility-major copy: wave v turns the tile's 64-bit words v, v + 4, ...
+    // (one row per lane) into T[64 w + f], f = 0..63, by one transpose each,
+    // in place once every wave has read its rows.
+    constexpr int NW = (WD / 2 + kEvalWaves - 1) / kEvalWaves;
+    uint32_t rlo[NW], rhi[NW];
+#pragma unroll
+    for (int r = 0; r < NW; ++r) {
+        const int w = min(wave + r * kEvalWaves, W - 1);
+        rlo[r] = smask[lane * SD + 2 * w];
+        rhi[r] = smask[lane * SD + 2 * w + 1];
+    }
+    __syncthreads();
+    uint64_t *sT = reinterpret_cast<uint64_t *>(smask);
+    const TransposeLanes tl(lane);
+#pragma unroll
+    for (int r = 0; r < NW; ++r) {
+        const int w = wave + r * kEvalWaves;
+        if (w < W) {
+            transpose64(rlo[r], rhi[r], lane, tl);
+            sT[w * 64 + lane] = ((uint64_t)rhi[r] << 32) | rlo[r];
+        }
+    }
+    __syncthreads();
+
     unsigned long long acc = 0;
     uint32_t scn = 0;
-    // chunk-0 operands of the current client: mask word, bit (0 past K)
-    uint32_t off_cur = j_first >> 5;
-    uint32_t bit_cur = in_row ? 1u << (j_first & 31u) : 0u;
     if constexpr (H) {
         for (; i < i1; i += 2 * kEvalWaves) {
             const int ib = i + kEvalWaves;
@@ -337,9 +324,10 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
             const int rown = lane >= 32 ? nb : na;
             const uint32_t j_nxt = a.t.pi[(int64_t)rown * a.t.pitch + col];
             const int32_t d_nxt = a.t.ds[(int64_t)rown * a.t.pitch + col];
-            const uint32_t bit = (lane >= 32 && !has_b) ? 0u : bit_cur;
+            const bool use = in_row && !(lane >= 32 && !has_b);
+            const uint64_t t = sT[j_cur];
             int ha, hb;
-            match_dense2<WD>(smask + off_cur, bit, lane, ha, hb, kQuads{});
+            first_open2(use ? t : 0ull, lane, tl, ha, hb);
             const uint64_t pa = act, pb = has_b ? act : 0ull;
             const bool fa = ((pa >> lane) & 1ull) && ha >= 0;
             const bool fb = ((pb >> lane) & 1ull) && hb >= 0;
@@ -356,13 +344,12 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
             const uint64_t ra = pa & ~__builtin_amdgcn_ballot_w64(fa);
             const uint64_t rb = pb & ~__builtin_amdgcn_ballot_w64(fb);
             if (ra)
-                walk_tail<WD>(a, a.t.pi + (int64_t)i * a.t.pitch, a.t.ds + (int64_t)i * a.t.pitch,
-                              32, ra, lane, smask, acc, scn);
+                walk_tail(a, a.t.pi + (int64_t)i * a.t.pitch, a.t.ds + (int64_t)i * a.t.pitch,
+                          32, ra, lane, sT, tl, acc, scn);
             if (rb)
-                walk_tail<WD>(a, a.t.pi + (int64_t)ib * a.t.pitch,
-                              a.t.ds + (int64_t)ib * a.t.pitch, 32, rb, lane, smask, acc, scn);
-            off_cur = j_nxt >> 5;
-            bit_cur = in_row ? 1u << (j_nxt & 31u) : 0u;
+                walk_tail(a, a.t.pi + (int64_t)ib * a.t.pitch, a.t.ds + (int64_t)ib * a.t.pitch,
+                          32, rb, lane, sT, tl, acc, scn);
+            j_cur = j_nxt;
             d_cur = d_nxt;
         }
     }
@@ -389,33 +376,30 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
                 break;
             }
             const int k = base + lane;
-            uint32_t off = 0, bit = 0;
+            uint32_t j = 0;
+            bool use = false;
             int32_t dist = 0;
             long long ev = 0;
             if (base == 0) {
-                off = off_cur;
-                bit = bit_cur;
+                j = j_cur;
+                use = in_row;
                 if (R)
                     ev = e_cur;
                 else
                     dist = d_cur;
             } else if (k < a.t.K) {
-                const uint32_t j = prow[k];
-                off = j >> 5;
-                bit = 1u << (j & 31u);
+                j = prow[k];
+                use = true;
                 if (R)
                     ev = erow[k];
                 else
                     dist = drow[k];
             }
-            if (R && k == k_cur - 1) {  // the row's last kept position
-                off = (uint32_t)W2;
-                bit = 1u;
-            }
-            const uint32_t *sm = smask + off;
-            const int hit = (base == 0 || __builtin_popcountll(pend) >= 16)
-                                ? match_dense<WD>(sm, bit, lane, kQuads{})
-                                : match_sparse<WD>(sm, bit, pend, lane);
+            const uint64_t t0 = sT[j];
+            uint64_t t = use ? t0 : 0ull;
+            if (R && k == k_cur - 1)  // the row's last kept position
+                t = ~0ull;
+            const int hit = first_open(t, lane, tl);
             const bool found = ((pend >> lane) & 1ull) && hit >= 0;
             if (R) {
                 const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(
@@ -437,8 +421,7 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
         }
         // the next client's operands, computed here so that the wait for
         // its loads falls after this client's work
-        off_cur = j_nxt >> 5;
-        bit_cur = in_row ? 1u << (j_nxt & 31u) : 0u;
+        j_cur = j_nxt;
         d_cur = d_nxt;
         e_cur = e_nxt;
         k_cur = k_nxt;

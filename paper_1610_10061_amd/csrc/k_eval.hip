@@ -11,7 +11,7 @@ namespace {
 template <int WD, bool R, bool H>
 __global__ __launch_bounds__(kEvalTile *kEvalWaves) void k_eval(EvalArgs a)
 {
-    __shared__ uint32_t smask[kEvalTile * WD];
+    __shared__ __align__(16) uint32_t smask[eval_stage_words<WD>()];
     __shared__ unsigned long long sred[2 * kEvalWaves * kEvalTile];
     // (A stopped GA run enqueues no-op generations: eval_tile checks the
     // stop flag once its loads are on their way.)
@@ -72,6 +72,50 @@ hipError_t launch_reduce(const EvalArgs &a, unsigned long long *fitness,
     hipLaunchKernelGGL(k_reduce, dim3((a.P + 255) / 256), dim3(256), 0, s, a.part,
                        a.spart, a.tiles_i, a.P, fitness, scan, a.c0);
     return hipGetLastError();
+}
+
+namespace {
+
+template <int WD, bool R, bool H>
+int resident_wd()
+{
+    static int cached = 0;  // the same for every call: computed once
+    if (cached == 0) {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per_cu, reinterpret_cast<const void *>(k_eval<WD, R, H>),
+                kEvalTile * kEvalWaves, 0) != hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        cached = per_cu;
+    }
+    return cached;
+}
+
+}  // namespace
+
+int eval_workgroups_per_cu(int W, bool reduced, bool paired)
+{
+    const int w2 = 2 * W + (reduced ? 1 : 0);
+#define PMP_EVAL_WD(N)                                                           \
+    if (w2 <= N)                                                                 \
+        return reduced ? resident_wd<N, true, false>()                            \
+                       : (paired ? resident_wd<N, false, true>()                  \
+                                 : resident_wd<N, false, false>());
+    PMP_EVAL_WD(2)
+    PMP_EVAL_WD(4)
+    PMP_EVAL_WD(8)
+    PMP_EVAL_WD(16)
+    PMP_EVAL_WD(32)
+    PMP_EVAL_WD(48)
+    PMP_EVAL_WD(64)
+    PMP_EVAL_WD(96)
+    PMP_EVAL_WD(128)
+    PMP_EVAL_WD(160)
+    PMP_EVAL_WD(192)
+    PMP_EVAL_WD(256)
+#undef PMP_EVAL_WD
+    return 1;
 }
 
 hipError_t launch_eval(const EvalArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1)

@@ -223,7 +223,7 @@ __global__ __launch_bounds__(64 * kGaWaves) void k_ga_batch(BatchArgs B,
     extern __shared__ uint64_t lds[];
     uint32_t *smask = reinterpret_cast<uint32_t *>(lds);
     unsigned long long *sred =
-        reinterpret_cast<unsigned long long *>(lds + (kEvalTile * WD) / 2);
+        reinterpret_cast<unsigned long long *>(lds + eval_stage_words<WD>() / 2);
     __shared__ unsigned long long sc[16];
     __shared__ int si[16];
     __shared__ int flag;
@@ -304,7 +304,7 @@ template <int WD>
 __global__ __launch_bounds__(kEvalTile *kEvalWaves) void k_batch_eval(BatchArgs B, int k,
                                                                       int buf)
 {
-    __shared__ uint32_t smask[kEvalTile * WD];
+    __shared__ __align__(16) uint32_t smask[eval_stage_words<WD>()];
     __shared__ unsigned long long sred[2 * kEvalWaves * kEvalTile];
     const int ntiles = B.tile0[B.count];
     // blocks are dealt to the 8 XCDs round-robin: give XCD x a contiguous
@@ -401,7 +401,7 @@ inline dim3 per_wave(int P)
 template <int WD>
 size_t batch_lds()
 {
-    return sizeof(uint32_t) * kEvalTile * WD +
+    return sizeof(uint32_t) * eval_stage_words<WD>() +
            sizeof(unsigned long long) * 2 * kEvalWaves * kEvalTile;
 }
 

@@ -81,20 +81,32 @@ int paired_scans(int m, int p)
     return (int64_t)m + 1 <= 12LL * ((int64_t)p + 1) ? 1 : 0;
 }
 
-// Clients per workgroup of the evaluation kernel: enough workgroups to fill
-// 256 CUs several times over, at least four clients (one per wave).
-int clients_per_block(int n, int P)
+// Clients per workgroup of the evaluation kernel.  A workgroup first stages
+// its chromosome tile (W words per chromosome loaded and turned
+// facility-major), then walks its clients.  With long scans (mean
+// (m+1)/(p+1) of 128 entries or more) the walks dominate: enough workgroups
+// to fill 256 CUs four times over, at most 64 clients each, so that uneven
+// scan lengths even out.  With short scans the staging counts: the fewest
+// client tiles that still give every CU about 3.5 workgroups, or that fill
+// every CU's resident slots once when it holds fewer, so that no workgroup
+// waits for a slot.
+int clients_per_block(int n, int P, int m, int p, int W, bool reduced = false)
 {
     const int forced = env_int("PMP_CLIENTS_PER_BLOCK", 0);
     if (forced > 0)
-        return ((forced + 3) / 4) * 4;
+        return forced;
     const long tiles_c = (P + kEvalTile - 1) / kEvalTile;
-    long cpb = (long)n * tiles_c / 1024;
-    if (cpb < 4)
-        cpb = 4;
-    if (cpb > 64)
-        cpb = 64;
-    return (int)(((cpb + 3) / 4) * 4);
+    const bool long_scans = (long)m + 1 >= 128L * ((long)p + 1);
+    if (long_scans) {
+        long cpb = (long)n * tiles_c / 1024;
+        cpb = std::min(64L, std::max(4L, cpb));
+        return (int)(((cpb + 3) / 4) * 4);
+    }
+    const long slots = 256L * eval_workgroups_per_cu(W, reduced, paired_scans(m, p) != 0);
+    const long want = std::min(slots, 896L);
+    long ti = want >= slots ? std::max(1L, slots / tiles_c) : (want + tiles_c - 1) / tiles_c;
+    ti = std::min(ti, std::max(1L, ((long)n + 3) / 4));
+    return (int)std::max(1L, ((long)n + ti - 1) / ti);
 }
 
 // binom[a (p + 1) + b] = C(a, b) for a < m, b <= p, by Pascal's rule,
@@ -933,7 +945,7 @@ pmp_status pmp_hbp_eval(pmp_hbp *hp, const uint64_t *masks, int32_t P, int64_t *
     a.masks = dmask;
     a.P = P;
     a.err = inst->err;
-    a.clients_per_block = clients_per_block(hp->rows, P);
+    a.clients_per_block = clients_per_block(hp->rows, P, inst->m, inst->p, inst->W, true);
     a.tiles_c = (P + kEvalTile - 1) / kEvalTile;
     a.tiles_i = (hp->rows + a.clients_per_block - 1) / a.clients_per_block;
     const size_t cells = (size_t)a.tiles_i * P;
@@ -1114,7 +1126,7 @@ pmp_status pmp_eval_population(pmp_instance *inst, const uint64_t *masks,
     a.active = nullptr;
     a.done = nullptr;
     a.err = inst->err;
-    a.clients_per_block = clients_per_block(inst->n, P);
+    a.clients_per_block = clients_per_block(inst->n, P, inst->m, inst->p, inst->W);
     a.tiles_c = (P + kEvalTile - 1) / kEvalTile;
     a.tiles_i = (inst->n + a.clients_per_block - 1) / a.clients_per_block;
     if (scheme == PMP_EVAL_PER_CLIENT)
@@ -1225,7 +1237,7 @@ pmp_status pmp_ga_create(pmp_instance *inst, const pmp_ga_params *prm,
     ga->lg = lg;
     ga->X = prm->crossover_iters > 0 ? prm->crossover_iters : lg;
     ga->Y = prm->mutation_iters > 0 ? prm->mutation_iters : lg;
-    ga->cpb = clients_per_block(inst->n, P);
+    ga->cpb = clients_per_block(inst->n, P, inst->m, inst->p, inst->W);
     ga->TI = (inst->n + ga->cpb - 1) / ga->cpb;
     const size_t W = inst->W, PW = (size_t)P * W;
     bool bad = false;
@@ -1652,7 +1664,7 @@ pmp_status pmp_ga_autotune(pmp_ga *ga, int32_t *chosen, void *stream)
         return fail(PMP_EINVAL, "autotune a GA before its first generation");
     const pmp_instance *inst = ga->inst;
     const int P = ga->prm.population, n = inst->n;
-    int best = clients_per_block(n, P);
+    int best = clients_per_block(n, P, inst->m, inst->p, inst->W);
     const bool forced = env_int("PMP_CLIENTS_PER_BLOCK", 0) > 0;
     // measured choices are shared by runs of similar shape
     static std::mutex mu;
@@ -1675,7 +1687,7 @@ pmp_status pmp_ga_autotune(pmp_ga *ga, int32_t *chosen, void *stream)
         // a generation-0 population to time the evaluation on
         GaArgs g = ga->args();
         HIP_TRY(launch_ga_init(g, s));
-        const int cands[] = {4, 8, 12, 16, 24, 32, 48, 64, 96, 128};
+        const int cands[] = {4, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512};
         const int max_ti = (n + 3) / 4;
         unsigned long long *part = nullptr;
         uint32_t *spart = nullptr;
@@ -2307,7 +2319,7 @@ pmp_status pmp_exhaustive(pmp_instance *inst, uint64_t *best_mask, int64_t *best
     a.active = nullptr;
     a.done = nullptr;
     a.err = inst->err;
-    a.clients_per_block = clients_per_block(n, B);
+    a.clients_per_block = clients_per_block(n, B, m, p, W);
     a.tiles_c = (B + kEvalTile - 1) / kEvalTile;
     a.tiles_i = (n + a.clients_per_block - 1) / a.clients_per_block;
     unsigned long long *d_binom = nullptr, *fit = nullptr, *bc = nullptr, *run = nullptr;

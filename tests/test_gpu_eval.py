@@ -163,7 +163,7 @@ def test_tile_shape_does_not_change_results(pm):
     outs = []
     old = os.environ.get("PMP_CLIENTS_PER_BLOCK")
     try:
-        for cpb in ("4", "12", "64", "900"):
+        for cpb in ("4", "12", "13", "64", "417", "900"):
             os.environ["PMP_CLIENTS_PER_BLOCK"] = cpb
             outs.append(inst.eval(masks).copy())
     finally:
