@@ -143,10 +143,9 @@ PMP_API pmp_status pmp_eval_population(pmp_instance *inst, const uint64_t *masks
  * merge is then checked exactly; a key collision (never expected) makes the
  * call fail with PMP_EUNSUPPORTED rather than merge different sets.
  *
- *  inst    a preprocessed instance (borrowed: it must outlive the handle);
- *          m <= 8128.
+ *  inst    a preprocessed instance (borrowed: it must outlive the handle).
  *  out     receives the handle (device tables, owned).
- * Errors: PMP_EINVAL (null), PMP_EUNSUPPORTED (m too large, key collision),
+ * Errors: PMP_EINVAL (null), PMP_EUNSUPPORTED (key collision),
  * PMP_ENOMEM.  Waits for its stream.
  * ------------------------------------------------------------------------- */
 typedef struct pmp_hbp pmp_hbp;

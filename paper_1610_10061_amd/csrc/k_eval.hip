@@ -96,7 +96,7 @@ int resident_wd()
 
 int eval_workgroups_per_cu(int W, bool reduced, bool paired)
 {
-    const int w2 = 2 * W + (reduced ? 1 : 0);
+    const int w2 = 2 * W;
 #define PMP_EVAL_WD(N)                                                           \
     if (w2 <= N)                                                                 \
         return reduced ? resident_wd<N, true, false>()                            \
@@ -122,9 +122,8 @@ hipError_t launch_eval(const EvalArgs &a, hipStream_t s, hipEvent_t e0, hipEvent
 {
     if (a.P <= 0 || a.tiles_c <= 0 || a.tiles_i <= 0)
         return hipSuccess;
-    // the reduced walk needs one spare staged word per chromosome
     const bool red = a.rlen != nullptr;
-    const int w2 = 2 * a.t.W + (red ? 1 : 0);
+    const int w2 = 2 * a.t.W;
 #define PMP_EVAL_WD(N)                                                         \
     if (w2 <= N)                                                               \
         return red ? launch_wd<N, true, false>(a, s, e0, e1)                     \

@@ -767,8 +767,6 @@ pmp_status pmp_hbp_reduce(pmp_instance *inst, void *stream, pmp_hbp **out)
     if (!inst || !out)
         return fail(PMP_EINVAL, "instance or out is NULL");
     *out = nullptr;
-    if (2 * inst->W + 1 > 256)
-        return fail(PMP_EUNSUPPORTED, "reduced polynomial: m = %d above 8128", inst->m);
     hipStream_t s = (hipStream_t)stream;
     const int n = inst->n, m = inst->m;
     const size_t cells = (size_t)n * inst->pitch;

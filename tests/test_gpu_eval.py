@@ -156,6 +156,20 @@ def _e5000():
     return _E5000["d"]
 
 
+@pytest.mark.parametrize("m,p", [(8192, 2000), (8191, 3), (8192, 8191)],
+                         ids=["m=8192 short scans", "m=8191 long scans", "p=m-1"])
+def test_eval_at_the_facility_limit(pm, m, p):
+    """m at PMP_MAX_FACILITIES (128 words per chromosome, the largest staging
+    and facility-major tile) and one below it, with two chromosome tiles (the
+    second ragged)."""
+    n, P = 24, 70
+    d = np.random.default_rng(m + p).integers(0, 10000, size=(n, m)).astype(np.int32)
+    masks = gi.random_population(P, m, p, seed=5)
+    print("case m", m, "p", p, "n", n, "P", P, flush=True)
+    inst = pm.Instance(d, p)
+    np.testing.assert_array_equal(inst.eval(masks), oracle.objective(d, masks, p))
+
+
 def test_tile_shape_does_not_change_results(pm):
     d, p = INSTANCES["g900"]()
     masks = gi.random_population(257, 900, p, seed=3)

@@ -157,7 +157,29 @@ def test_device_buffers_and_rejects(pm):
     pm.pmp_hbp_eval(h.handle, dm, fit, None, asynchronous=True)
     inst.check()
     np.testing.assert_array_equal(fit.cpu().numpy(), oracle.objective(d, masks, p))
-    wide = pm.Instance(np.random.default_rng(0).integers(0, 9, (2, 8150)).astype(np.int32), 5)
-    with pytest.raises(pm.PmpError) as e:
-        pm.Hbp(wide)
-    assert e.value.status == pm.PMP_EUNSUPPORTED
+    # m past 8128 (more than 127 words per chromosome) is served too
+    dw = np.random.default_rng(0).integers(0, 9, (2, 8150)).astype(np.int32)
+    wide = pm.Instance(dw, 5)
+    hw = pm.Hbp(wide)
+    mw = gi.random_population(3, 8150, 5, seed=1)
+    fw = np.zeros(3, np.int64)
+    pm.pmp_hbp_eval(hw.handle, mw, fw)
+    np.testing.assert_array_equal(fw, oracle.objective(dw, mw, 5))
+    with pytest.raises(pm.PmpError) as e:  # a chromosome with the wrong count
+        pm.pmp_hbp_eval(hw.handle, gi.random_population(1, 8150, 6, seed=1), fw[:1])
+    assert e.value.status == pm.PMP_EINFEASIBLE
+
+
+def test_reduced_eval_at_the_facility_limit(pm):
+    """m = PMP_MAX_FACILITIES: the reduced walk's stop needs no staged word
+    beyond the chromosome's 128, so the largest tile serves it too."""
+    n, m, p, P = 20, 8192, 1500, 70
+    d = np.random.default_rng(4).integers(0, 50, size=(n, m)).astype(np.int32)
+    print("case hbp m", m, "p", p, flush=True)
+    inst = pm.Instance(d, p)
+    h = pm.Hbp(inst)
+    masks = gi.random_population(P, m, p, seed=2)
+    fit = np.zeros(P, np.int64)
+    scan = np.zeros(P, np.int64)
+    pm.pmp_hbp_eval(h.handle, masks, fit, scan)
+    np.testing.assert_array_equal(fit, oracle.objective(d, masks, p))
