@@ -57,18 +57,24 @@ __device__ __forceinline__ uint32_t from_lane_xor(uint32_t v)
                                                      false);
 }
 
-// Per-lane operands of the transpose steps J = 16, 8, 4, 2, 1 (index 0-4):
-// the bits a lane keeps, and the rotation that brings its partner's bits
-// into the others.
+// Per-lane operands of the transpose steps J = 16, 8, 4, 2, 1 (index 0-4).
+// J = 16 and 8 move whole bytes: a v_perm_b32 byte selector per lane takes
+// the kept bytes from the lane's own word and the others from its
+// partner's.  J = 4, 2, 1: the bits a lane keeps, and the rotation that
+// brings its partner's bits into the others.
 struct TransposeLanes {
-    uint32_t keep[5], rot[5];
+    uint32_t sel[2], keep[5], rot[5];
 
     __device__ __forceinline__ explicit TransposeLanes(int lane)
     {
+        // v_perm_b32(own, partner, sel): selector byte 4-7 = own byte 0-3,
+        // 0-3 = partner byte 0-3
+        sel[0] = (lane & 16) ? 0x07060302u : 0x01000504u;  // [p2 p3 o2 o3] / [o0 o1 p0 p1]
+        sel[1] = (lane & 8) ? 0x07030501u : 0x02060004u;   // [p1 o1 p3 o3] / [o0 p0 o2 p2]
         constexpr uint32_t M[5] = {0x0000FFFFu, 0x00FF00FFu, 0x0F0F0F0Fu, 0x33333333u,
                                    0x55555555u};
 #pragma unroll
-        for (int s = 0; s < 5; ++s) {
+        for (int s = 2; s < 5; ++s) {
             const int J = 16 >> s;
             const bool up = (lane & J) != 0;
             keep[s] = up ? ~M[s] : M[s];
@@ -83,29 +89,43 @@ struct TransposeLanes {
 // clear and takes its partner's bits moved up by J; the partner keeps the
 // others and takes this lane's moved down by J.  Rotations stand in for the
 // shifts: the bits they wrap around land in positions that are not taken.
+// (a & mask) | (b & ~mask) in one instruction (written out, so that the
+// compiler does not split it into ands and ors shared with the next step)
+__device__ __forceinline__ uint32_t bit_select(uint32_t mask, uint32_t a, uint32_t b)
+{
+    uint32_t r;
+    asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "v"(mask), "v"(a), "v"(b));
+    return r;
+}
+
 template <int S>
 __device__ __forceinline__ void transpose_step(uint32_t &lo, uint32_t &hi,
                                                const TransposeLanes &tl)
 {
     constexpr int J = 16 >> S;
     const uint32_t ylo = from_lane_xor<J>(lo), yhi = from_lane_xor<J>(hi);
-    const uint32_t k = tl.keep[S], r = tl.rot[S];
-    lo = (lo & k) | (__builtin_amdgcn_alignbit(ylo, ylo, r) & ~k);
-    hi = (hi & k) | (__builtin_amdgcn_alignbit(yhi, yhi, r) & ~k);
+    if constexpr (S < 2) {
+        lo = __builtin_amdgcn_perm(lo, ylo, tl.sel[S]);
+        hi = __builtin_amdgcn_perm(hi, yhi, tl.sel[S]);
+    } else {
+        const uint32_t k = tl.keep[S], r = tl.rot[S];
+        lo = bit_select(k, lo, __builtin_amdgcn_alignbit(ylo, ylo, r));
+        hi = bit_select(k, hi, __builtin_amdgcn_alignbit(yhi, yhi, r));
+    }
 }
 
 // Transpose of the 64 x 64 bit matrix whose row l is lane l's (hi:lo): on
 // return lane c holds column c, bit l = bit c of row l.  Bit 5 of the row and
-// column index is exchanged first (lanes 32-63 give their low words for the
-// high words of lanes 0-31), then bits 4 to 0 within each half-wave.
+// column index is exchanged first: v_permlane32_swap of the low and high
+// words swaps the low words of lanes 32-63 with the high words of lanes
+// 0-31.  Then bits 4 to 0 within each half-wave.
 __device__ __forceinline__ void transpose64(uint32_t &lo, uint32_t &hi, int lane,
                                             const TransposeLanes &tl)
 {
-    const bool up = lane >= 32;
-    const uint32_t got =
-        (uint32_t)__builtin_amdgcn_ds_bpermute((lane ^ 32) << 2, (int)(up ? lo : hi));
-    lo = up ? got : lo;
-    hi = up ? hi : got;
+    (void)lane;
+    const auto sw = __builtin_amdgcn_permlane32_swap(lo, hi, false, false);
+    lo = (uint32_t)sw[0];
+    hi = (uint32_t)sw[1];
     transpose_step<0>(lo, hi, tl);
     transpose_step<1>(lo, hi, tl);
     transpose_step<2>(lo, hi, tl);
@@ -136,10 +156,11 @@ __device__ __forceinline__ void first_open2(uint64_t row, int lane, const Transp
 }
 
 // The rest of one client's walk from position `base` for the chromosomes in
-// `pend` (64-entry chunks, loaded here).  sT: the tile's facility-major masks.
+// `pend` (64-entry chunks, loaded here).  sT: the tile's facility-major masks,
+// with an all-zero word at index jz for positions past the row.
 __device__ __forceinline__ void walk_tail(const EvalArgs &a, const uint16_t *prow,
                                           const int32_t *drow, int base, uint64_t pend,
-                                          int lane, const uint64_t *sT,
+                                          int lane, const uint64_t *sT, uint32_t jz,
                                           const TransposeLanes &tl, unsigned long long &acc,
                                           uint32_t &scn)
 {
@@ -154,8 +175,7 @@ __device__ __forceinline__ void walk_tail(const EvalArgs &a, const uint16_t *pro
         const int kc = in ? k : a.t.K - 1;
         const uint32_t j = prow[kc];
         const int32_t dist = drow[kc];
-        const uint64_t t = sT[j];
-        const int hit = first_open(in ? t : 0ull, lane, tl);
+        const int hit = first_open(sT[in ? j : jz], lane, tl);
         const bool found = ((pend >> lane) & 1ull) && hit >= 0;
         const int32_t cost = __builtin_amdgcn_ds_bpermute((hit & 63) << 2, dist);
         if (found) {
@@ -168,8 +188,8 @@ __device__ __forceinline__ void walk_tail(const EvalArgs &a, const uint16_t *pro
 
 // LDS words (32-bit) eval_tile needs for its staged masks: rows of WD words
 // at an odd stride WD + 1, so that reading one word of every row (a lane per
-// row) hits 64 different banks.  The facility-major copy, 64 W 64-bit words,
-// reuses the same space.
+// row) hits 64 different banks.  The facility-major copy, 64 W 64-bit words
+// and two more (all zeros, all ones), reuses the same space.
 template <int WD>
 constexpr int eval_stage_words()
 {
@@ -312,6 +332,11 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
             sT[w * 64 + lane] = ((uint64_t)rhi[r] << 32) | rlo[r];
         }
     }
+    // T[64 W]: no chromosome open (positions that do not count); T[64 W + 1]:
+    // every chromosome open (the reduced walk's stop)
+    const uint32_t jz = (uint32_t)(64 * W), jone = jz + 1u;
+    if (wave == 0 && lane < 2)
+        sT[jz + lane] = lane ? ~0ull : 0ull;
     __syncthreads();
 
     unsigned long long acc = 0;
@@ -325,9 +350,8 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
             const uint32_t j_nxt = a.t.pi[(int64_t)rown * a.t.pitch + col];
             const int32_t d_nxt = a.t.ds[(int64_t)rown * a.t.pitch + col];
             const bool use = in_row && !(lane >= 32 && !has_b);
-            const uint64_t t = sT[j_cur];
             int ha, hb;
-            first_open2(use ? t : 0ull, lane, tl, ha, hb);
+            first_open2(sT[use ? j_cur : jz], lane, tl, ha, hb);
             const uint64_t pa = act, pb = has_b ? act : 0ull;
             const bool fa = ((pa >> lane) & 1ull) && ha >= 0;
             const bool fb = ((pb >> lane) & 1ull) && hb >= 0;
@@ -345,10 +369,10 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
             const uint64_t rb = pb & ~__builtin_amdgcn_ballot_w64(fb);
             if (ra)
                 walk_tail(a, a.t.pi + (int64_t)i * a.t.pitch, a.t.ds + (int64_t)i * a.t.pitch,
-                          32, ra, lane, sT, tl, acc, scn);
+                          32, ra, lane, sT, jz, tl, acc, scn);
             if (rb)
                 walk_tail(a, a.t.pi + (int64_t)ib * a.t.pitch, a.t.ds + (int64_t)ib * a.t.pitch,
-                          32, rb, lane, sT, tl, acc, scn);
+                          32, rb, lane, sT, jz, tl, acc, scn);
             j_cur = j_nxt;
             d_cur = d_nxt;
         }
@@ -395,11 +419,10 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
                 else
                     dist = drow[k];
             }
-            const uint64_t t0 = sT[j];
-            uint64_t t = use ? t0 : 0ull;
+            uint32_t jt = use ? j : jz;
             if (R && k == k_cur - 1)  // the row's last kept position
-                t = ~0ull;
-            const int hit = first_open(t, lane, tl);
+                jt = jone;
+            const int hit = first_open(sT[jt], lane, tl);
             const bool found = ((pend >> lane) & 1ull) && hit >= 0;
             if (R) {
                 const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(
