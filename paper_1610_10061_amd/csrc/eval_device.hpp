@@ -52,9 +52,8 @@ __device__ __forceinline__ uint32_t from_lane_xor(uint32_t v)
 {
     if constexpr (J >= 4)
         return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1F | (J << 10));
-    else
-        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, J == 2 ? 0x4E : 0xB1, 0xF, 0xF,
-                                                     false);
+    else  // every lane has a source, so no old value is needed
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, J == 2 ? 0x4E : 0xB1, 0xF, 0xF, true);
 }
 
 // Per-lane operands of the transpose steps J = 16, 8, 4, 2, 1 (index 0-4).

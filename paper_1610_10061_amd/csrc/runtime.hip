@@ -102,11 +102,20 @@ int clients_per_block(int n, int P, int m, int p, int W, bool reduced = false)
         cpb = std::min(64L, std::max(4L, cpb));
         return (int)(((cpb + 3) / 4) * 4);
     }
-    const long slots = 256L * eval_workgroups_per_cu(W, reduced, paired_scans(m, p) != 0);
+    const bool paired = paired_scans(m, p) != 0;
+    const long slots = 256L * eval_workgroups_per_cu(W, reduced, paired);
     const long want = std::min(slots, 896L);
     long ti = want >= slots ? std::max(1L, slots / tiles_c) : (want + tiles_c - 1) / tiles_c;
     ti = std::min(ti, std::max(1L, ((long)n + 3) / 4));
-    return (int)std::max(1L, ((long)n + ti - 1) / ti);
+    long cpb = std::max(1L, ((long)n + ti - 1) / ti);
+    // Small tiles: the same number of clients (of client pairs, when paired)
+    // for each of the 4 waves, or one wave's extra client sets the
+    // workgroup's time.  (When the slots are the limit, rounding down would
+    // add a client tile and a partial second round of workgroups.)
+    const long unit = paired ? 8 : 4;
+    if (cpb < 64 && want < slots && cpb >= unit)
+        cpb -= cpb % unit;
+    return (int)cpb;
 }
 
 // binom[a (p + 1) + b] = C(a, b) for a < m, b <= p, by Pascal's rule,
