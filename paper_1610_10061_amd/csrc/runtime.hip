@@ -87,9 +87,9 @@ int paired_scans(int m, int p)
 // (m+1)/(p+1) of 128 entries or more) the walks dominate: enough workgroups
 // to fill 256 CUs four times over, at most 64 clients each, so that uneven
 // scan lengths even out.  With short scans the staging counts: the fewest
-// client tiles that still give every CU about 3.5 workgroups, or that fill
-// every CU's resident slots once when it holds fewer, so that no workgroup
-// waits for a slot.
+// client tiles that still give every CU of the device about 3.5 workgroups,
+// or that fill every CU's resident slots once when it holds fewer, so that
+// no workgroup waits for a slot.
 int clients_per_block(int n, int P, int m, int p, int W, bool reduced = false)
 {
     const int forced = env_int("PMP_CLIENTS_PER_BLOCK", 0);
@@ -103,8 +103,14 @@ int clients_per_block(int n, int P, int m, int p, int W, bool reduced = false)
         return (int)(((cpb + 3) / 4) * 4);
     }
     const bool paired = paired_scans(m, p) != 0;
-    const long slots = 256L * eval_workgroups_per_cu(W, reduced, paired);
-    const long want = std::min(slots, 896L);
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1)
+        cus = 256;
+    const long slots = (long)cus * eval_workgroups_per_cu(W, reduced, paired);
+    const long busy = (long)cus * 7 / 2;  // about 3.5 workgroups per CU
+    const long want = std::min(slots, busy);
     long ti = want >= slots ? std::max(1L, slots / tiles_c) : (want + tiles_c - 1) / tiles_c;
     ti = std::min(ti, std::max(1L, ((long)n + 3) / 4));
     long cpb = std::max(1L, ((long)n + ti - 1) / ti);

@@ -135,3 +135,76 @@ def unrank(r, m, p):
 def test_unranking_follows_lexicographic_order(m, p):
     for r, s in enumerate(itertools.combinations(range(m), p)):
         assert unrank(r, m, p) == s
+
+
+# ------------------------------------------------ 64 x 64 bit transpose
+_U = 0xFFFFFFFF
+_M = {16: 0x0000FFFF, 8: 0x00FF00FF, 4: 0x0F0F0F0F, 2: 0x33333333, 1: 0x55555555}
+
+
+def _rotr(y, s):
+    s &= 31
+    return ((y >> s) | (y << (32 - s))) & _U
+
+
+def _byte_perm(own, partner, sel):
+    """A byte permute of (own : partner): selector byte 4-7 takes own byte
+    0-3, 0-3 takes partner byte 0-3."""
+    b = [(partner >> (8 * i)) & 255 for i in range(4)] + [(own >> (8 * i)) & 255 for i in range(4)]
+    return sum(b[(sel >> (8 * i)) & 255] << (8 * i) for i in range(4))
+
+
+def transpose_by_lanes(lo, hi):
+    """The evaluation's transpose as the lanes run it: lane l holds row l as
+    (hi:lo).  Step 32 swaps the low words of lanes 32-63 with the high words
+    of lanes 0-31; steps 16 and 8 merge own and partner (lane ^ J) bytes by
+    a byte permute; steps 4, 2, 1 keep the bits whose index has bit J equal
+    to the lane's and take the partner's rotated by J the other way."""
+    lo, hi = lo[:], hi[:]
+    for l in range(32):
+        lo[l + 32], hi[l] = hi[l], lo[l + 32]
+    sel = {16: (0x01000504, 0x07060302), 8: (0x02060004, 0x07030501)}
+    for J in (16, 8, 4, 2, 1):
+        ylo = [lo[l ^ J] for l in range(64)]
+        yhi = [hi[l ^ J] for l in range(64)]
+        for l in range(64):
+            up = (l & J) != 0
+            if J in sel:
+                s = sel[J][1 if up else 0]
+                lo[l] = _byte_perm(lo[l], ylo[l], s)
+                hi[l] = _byte_perm(hi[l], yhi[l], s)
+            else:
+                keep = (~_M[J] & _U) if up else _M[J]
+                r = J if up else 32 - J
+                lo[l] = (lo[l] & keep) | (_rotr(ylo[l], r) & ~keep & _U)
+                hi[l] = (hi[l] & keep) | (_rotr(yhi[l], r) & ~keep & _U)
+    return lo, hi
+
+
+def test_lane_transpose_is_the_bit_matrix_transpose():
+    rng = random.Random(5)
+    for _ in range(60):
+        rows = [rng.getrandbits(64) for _ in range(64)]
+        lo, hi = transpose_by_lanes([r & _U for r in rows], [r >> 32 for r in rows])
+        for c in range(64):
+            col = lo[c] | (hi[c] << 32)
+            assert col == sum(((rows[k] >> c) & 1) << k for k in range(64))
+
+
+def test_first_open_positions_from_the_transpose():
+    """Row k = the chromosomes in which the facility at position k is open;
+    after the transpose, chromosome c's lowest set bit is its first open
+    position (and, with two clients in the halves, each half's)."""
+    rng = random.Random(6)
+    for _ in range(40):
+        open_ = [[rng.random() < 0.1 for _ in range(64)] for _ in range(64)]  # [c][k]
+        rows = [sum(open_[c][k] << c for c in range(64)) for k in range(64)]
+        lo, hi = transpose_by_lanes([r & _U for r in rows], [r >> 32 for r in rows])
+        for c in range(64):
+            first = next((k for k in range(64) if open_[c][k]), -1)
+            col = lo[c] | (hi[c] << 32)
+            got = (col & -col).bit_length() - 1 if col else -1
+            assert got == first
+            first_b = next((k - 32 for k in range(32, 64) if open_[c][k]), -1)
+            got_b = (hi[c] & -hi[c]).bit_length() - 1 if hi[c] else -1
+            assert got_b == first_b
