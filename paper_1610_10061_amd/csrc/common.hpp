@@ -197,6 +197,7 @@ struct GaArgs {
     const unsigned long long *mpart;
     const uint32_t *mspart;
     int32_t TIm;                    // client tiles of the mutants' evaluation
+    int32_t mpw;                    // mutants made per wave (>= 1)
     uint64_t *cur[2];               // P x W population
     unsigned long long *fit[2];     // P fitness of cur
     uint64_t *off[2];               // P x W offspring

@@ -697,9 +697,10 @@ __device__ __forceinline__ bool mutate_wave(const WaveWords &A, uint64_t *F,
 // the lanes.
 // ---------------------------------------------------------------------------
 //
-// With op = OP_MUT_ALL the stage runs on Y waves per chromosome: wave `sub`
-// makes mutant `sub` of the parent, and only wave 0 writes the chromosome's
-// own state (every wave computes the same parent from the same loads).
+// With op = OP_MUT_ALL the stage runs on ceil(Y / mpw) waves per chromosome:
+// wave `sub` makes mutants sub mpw ... of the parent, and only wave 0 writes
+// the chromosome's own state (every wave computes the same parent from the
+// same loads).
 __device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
                                              int in, int prev, int op,
                                              int index, int sub = 0)
@@ -718,10 +719,6 @@ __device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
     int sj = 0, sk = 0;
     if (op == OP_SWAP) {
         const int32_t *sw = g.swaps + ((int64_t)c * g.L + index) * 2;
-        sj = sw[0];
-        sk = sw[1];
-    } else if (op == OP_MUT_ALL && sub < g.L) {  // a scored swap among the mutants
-        const int32_t *sw = g.swaps + ((int64_t)c * g.L + sub) * 2;
         sj = sw[0];
         sk = sw[1];
     }
@@ -853,30 +850,35 @@ __device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
     } else if (op == OP_MUT_ALL) {
         // every attempt mutates the same parent A (the cycle has not improved
         // it yet); ga_resolve_one takes the first strictly fitter mutant
-        const int64_t row = (int64_t)c * g.Y + sub;
-        bool ch = true;
-        if (sub < g.L) {  // scored swap: close sj, open sk
-            uint64_t *Fm = g.mut + row * W;
+        const int a1 = min(g.Y, (sub + 1) * g.mpw);
+        for (int a = sub * g.mpw; a < a1; ++a) {
+            const int64_t row = (int64_t)c * g.Y + a;
+            bool ch = true;
+            if (a < g.L) {  // scored swap: close its j, open its k
+                const int32_t *swp = g.swaps + ((int64_t)c * g.L + a) * 2;
+                const int aj = swp[0], ak = swp[1];
+                uint64_t *Fm = g.mut + row * W;
 #pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                const int w = lane + 64 * k;
-                if (w < W) {
-                    uint64_t v = A.v[k];
-                    if ((sj >> 6) == w)
-                        v ^= 1ull << (sj & 63);
-                    if ((sk >> 6) == w)
-                        v ^= 1ull << (sk & 63);
-                    Fm[w] = v;
+                for (int k = 0; k < 2; ++k) {
+                    const int w = lane + 64 * k;
+                    if (w < W) {
+                        uint64_t v = A.v[k];
+                        if ((aj >> 6) == w)
+                            v ^= 1ull << (aj & 63);
+                        if ((ak >> 6) == w)
+                            v ^= 1ull << (ak & 63);
+                        Fm[w] = v;
+                    }
                 }
+            } else {
+                const int lo_a = __builtin_amdgcn_readlane(dr.a, a);
+                const int hi_a = __builtin_amdgcn_readlane(dr.b, a);
+                const int mv_a = __builtin_amdgcn_readlane(dr.c, a);
+                ch = mutate_wave(A, g.mut + row * W, W, m, lo_a, hi_a, mv_a, lane);
             }
-        } else {
-            const int lo_a = __builtin_amdgcn_readlane(dr.a, sub);
-            const int hi_a = __builtin_amdgcn_readlane(dr.b, sub);
-            const int mv_a = __builtin_amdgcn_readlane(dr.c, sub);
-            ch = mutate_wave(A, g.mut + row * W, W, m, lo_a, hi_a, mv_a, lane);
+            if (lane == 0)
+                g.mut_ok[row] = ch ? 1 : 0;
         }
-        if (lane == 0)
-            g.mut_ok[row] = ch ? 1 : 0;
     } else if (op == OP_SWAP && !improved) {
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
@@ -1055,6 +1057,55 @@ __device__ __forceinline__ void ga_group_best(const GaArgs &g, int fb, int b,
         g.gcost[b] = sc[0];
 }
 
+// The run state after a generation: global best, saturation count, stop
+// test (Section 3.1 host steps 13-15), by one workgroup; the caller supplies
+// the least cost found and how to load word w of its mask.
+template <class LoadWord>
+__device__ __forceinline__ void ga_update_state(const GaArgs &g, unsigned long long cost,
+                                                LoadWord load)
+{
+    const bool better = cost < g.gs[GS_BEST];
+    const int W = g.t.W;
+    if (better)
+        for (int w = threadIdx.x; w < W; w += blockDim.x)
+            g.best_mask[w] = load(w);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (better) {
+            g.gs[GS_BEST] = cost;
+            g.gs[GS_SAT] = 0;
+        } else {
+            g.gs[GS_SAT] += 1;
+        }
+        const unsigned long long gen = g.gs[GS_GEN] + 1;
+        g.gs[GS_GEN] = gen;
+        if ((g.saturation > 0 && g.gs[GS_SAT] >= (unsigned long long)g.saturation) ||
+            gen >= (unsigned long long)g.generations)
+            g.gs[GS_DONE] = 1;
+    }
+}
+
+// Global best straight from the population: the least fitness over all P
+// slots, lowest slot on ties.  Groups are contiguous slot ranges, so this is
+// the least group best with the lowest group on ties, without waiting for
+// the other groups' results.
+__device__ __forceinline__ void ga_global_direct(const GaArgs &g, int fb,
+                                                 unsigned long long *sc, int *si)
+{
+    unsigned long long f = ~0ull;
+    int idx = 0x7FFFFFFF;
+    for (int t = threadIdx.x; t < g.P; t += blockDim.x) {
+        const unsigned long long v = buf(g.fit, fb)[t];
+        if (v < f) {  // t ascends per thread: keeps the lowest slot
+            f = v;
+            idx = t;
+        }
+    }
+    block_argmin(f, idx, sc, si);
+    const uint64_t *src = buf(g.cur, fb) + (int64_t)si[0] * g.t.W;
+    ga_update_state(g, sc[0], [src](int w) { return src[w]; });
+}
+
 // Global best, saturation count and stop test (Section 3.1 host steps
 // 13-15), by one workgroup once every group best is written and visible.
 __device__ __forceinline__ void ga_global(const GaArgs &g,
@@ -1071,27 +1122,10 @@ __device__ __forceinline__ void ga_global(const GaArgs &g,
         }
     }
     block_argmin(f, idx, sc, si);
-    const bool better = sc[0] < g.gs[GS_BEST];
-    const int W = g.t.W;
-    if (better)
-        for (int w = threadIdx.x; w < W; w += blockDim.x)
-            g.best_mask[w] = __hip_atomic_load(g.gmask + (int64_t)si[0] * W + w,
-                                               __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        if (better) {
-            g.gs[GS_BEST] = sc[0];
-            g.gs[GS_SAT] = 0;
-        } else {
-            g.gs[GS_SAT] += 1;
-        }
-        const unsigned long long gen = g.gs[GS_GEN] + 1;
-        g.gs[GS_GEN] = gen;
-        if ((g.saturation > 0 && g.gs[GS_SAT] >= (unsigned long long)g.saturation) ||
-            gen >= (unsigned long long)g.generations)
-            g.gs[GS_DONE] = 1;
-    }
+    const uint64_t *src = g.gmask + (int64_t)si[0] * g.t.W;
+    ga_update_state(g, sc[0], [src](int w) {
+        return __hip_atomic_load(src + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    });
 }
 
 }  // namespace pmp

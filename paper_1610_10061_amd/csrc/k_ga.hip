@@ -31,8 +31,8 @@ __global__ __launch_bounds__(64 * kGaWaves) void k_stage(GaArgs g, int in,
 {
     const int wave = wave_id(), lane = threadIdx.x & 63;
     const int gw = blockIdx.x * kGaWaves + wave;
-    // the whole mutation cycle at once: Y waves per chromosome
-    const int per = op == OP_MUT_ALL ? g.Y : 1;
+    // the whole mutation cycle at once: ceil(Y / mpw) waves per chromosome
+    const int per = op == OP_MUT_ALL ? (g.Y + g.mpw - 1) / g.mpw : 1;
     const int c = gw / per, sub = gw - c * per;
     if (c >= g.P)
         return;
@@ -49,27 +49,18 @@ __global__ __launch_bounds__(64 * kGaWaves) void k_resolve(GaArgs g, int YP, int
     ga_resolve_wave(g, gw, threadIdx.x & 63, YP, in, out);
 }
 
-// Group best per workgroup; the last workgroup to finish does the global
-// update (release fence before the arrival count, acquire fence after).
+// Group best per workgroup; workgroup 0 also takes the global best straight
+// from the population and updates the run state, so no workgroup waits for
+// another.  The others do not test the stop flag: workgroup 0 may set it in
+// this launch, and once a run has stopped its population no longer changes,
+// so rewriting a group best stores the same values.
 __global__ __launch_bounds__(1024) void k_best(GaArgs g, int fb)
 {
     __shared__ unsigned long long sc[16];
     __shared__ int si[16];
-    __shared__ int last;
-    if (ga_stopped(g))
-        return;
     ga_group_best(g, fb, blockIdx.x, sc, si);
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0)
-        last = atomicAdd(g.arrive, 1u) == (uint32_t)(g.NB - 1);
-    __syncthreads();
-    if (!last)
-        return;
-    __threadfence();
-    ga_global(g, sc, si);
-    if (threadIdx.x == 0)
-        *g.arrive = 0;
+    if (blockIdx.x == 0 && !ga_stopped(g))
+        ga_global_direct(g, fb, sc, si);
 }
 
 // ---------------------------------------------------------------------------
@@ -458,7 +449,7 @@ hipError_t launch_ga_init(const GaArgs &g, hipStream_t s)
 hipError_t launch_ga_stage(const GaArgs &g, int in, int prev, int op, int index,
                            hipStream_t s)
 {
-    const int waves = op == OP_MUT_ALL ? g.P * g.Y : g.P;
+    const int waves = op == OP_MUT_ALL ? g.P * ((g.Y + g.mpw - 1) / g.mpw) : g.P;
     hipLaunchKernelGGL(k_stage, per_wave(waves), dim3(64 * kGaWaves), 0, s, g, in,
                        prev, op, index);
     return hipGetLastError();

@@ -381,6 +381,8 @@ struct pmp_ga {
         g.mpart = mpart;
         g.mspart = mspart;
         g.TIm = spec_ti;
+        // two mutants per wave measured best at G900 (1, 2, 4, 8 tried)
+        g.mpw = std::max(1, env_int("PMP_MUTANTS_PER_WAVE", 2));
         g.part = part;
         g.spart = spart;
         g.TI = TI;

@@ -26,16 +26,19 @@ def pm():
 
 
 # launch schemes: per-step kernels replayed from a hipGraph of 2 generations
-# (the default scheme, with a chunk small enough to replay here), per-step
-# kernels launched one by one, the per-step kernels with the mutation cycle
-# run attempt by attempt instead of at once, one persistent cooperative
-# kernel, and the same with a grid of 8 workgroups (every phase loops)
+# (the default scheme, with a chunk small enough to replay here), the same
+# with every chromosome's mutants made by one wave, per-step kernels launched
+# one by one, the per-step kernels with the mutation cycle run attempt by
+# attempt instead of at once, one persistent cooperative kernel, and the same
+# with a grid of 8 workgroups (every phase loops)
 MODES = {"graph": {"PMP_GA_GRAPH_GENS": "2"},
+         "graph_mutants_1_wave": {"PMP_GA_GRAPH_GENS": "2", "PMP_MUTANTS_PER_WAVE": "64"},
          "kernels": {"PMP_GA_MODE": "kernels"},
          "sequential": {"PMP_GA_GRAPH_GENS": "2", "PMP_GA_SPEC": "0"},
          "persistent": {"PMP_GA_MODE": "persistent"},
          "persistent_8wg": {"PMP_GA_MODE": "persistent", "PMP_GA_BLOCKS": "8"}}
-_ENV = ("PMP_GA_MODE", "PMP_GA_BLOCKS", "PMP_GA_GRAPH_GENS", "PMP_GA_SPEC")
+_ENV = ("PMP_GA_MODE", "PMP_GA_BLOCKS", "PMP_GA_GRAPH_GENS", "PMP_GA_SPEC",
+        "PMP_MUTANTS_PER_WAVE")
 
 
 @pytest.fixture(params=list(MODES))
@@ -209,7 +212,7 @@ def test_mutation_cycle_at_once_counts(pm, mode):
     algorithm's own counters match the oracle either way (_compare)."""
     d = gi.graph_instance(100, 200, 3)
     s = _compare(pm, d, 5, 128, 32, 10, seed=2, steps=[3])
-    if mode in ("graph", "kernels"):
+    if mode in ("graph", "graph_mutants_1_wave", "kernels"):
         assert s["speculative_evals"] > 0
     else:
         assert s["speculative_evals"] == 0
