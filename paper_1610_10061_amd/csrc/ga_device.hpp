@@ -935,8 +935,8 @@ __device__ __forceinline__ void ga_resolve_wave(const GaArgs &g, int gw, int lan
     const unsigned long long c_se = cs[CS_SPEC_EVALS], c_ss = cs[CS_SPEC_SCAN];
     const unsigned long long c_st = cs[CS_SWAP_TRIED], c_sk = cs[CS_SWAP_TAKEN];
     unsigned long long f = 0, sc = 0;
-#pragma unroll 8
-    for (int t = 0; t < g.TIm; ++t) {
+#pragma unroll 16
+    for (int t = 0; t < g.TIm; ++t) {  // up to 16 tiles' loads in one round
         f += g.mpart[(int64_t)t * PY + row];
         sc += g.mspart[(int64_t)t * PY + row];
     }
