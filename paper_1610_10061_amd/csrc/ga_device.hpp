@@ -481,13 +481,19 @@ __device__ __forceinline__ void unrank_wave(const GaArgs &g, uint64_t r, int lan
 // second generation on the group bests migrate: group b's best to slot b*NT
 // (the same block) or to slot b (one block).  The population goes to off[0]
 // with fitness "infinite", so the first stage takes it as the current one.
-// The generation's operator draws are made here too (ga_draws_one).
+// The generation's operator draws are made here too (ga_draws_one): with
+// part -1 by the same wave, else part 0 makes the population slot and part 1
+// the draws, so that two waves share the work.
 // sw: 2 * W words of LDS owned by the wave.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void ga_init_one(const GaArgs &g, int c, int lane,
-                                            uint64_t *sw)
+                                            uint64_t *sw, int part = -1)
 {
     const uint64_t gen = g.gs[GS_GEN];
+    if (part == 1) {  // only the operator draws
+        ga_draws_one(g, gen, c, lane);
+        return;
+    }
     const int W = g.t.W, m = g.t.m, p = g.t.p;
     uint64_t *dst = g.off[0] + (int64_t)c * W;
     // migrant slots: b*NT for group b (same block) or b (one block)
@@ -526,7 +532,8 @@ __device__ __forceinline__ void ga_init_one(const GaArgs &g, int c, int lane,
         if (lane + 64 < W)
             dst[lane + 64] = word1;
     }
-    ga_draws_one(g, gen, c, lane);
+    if (part < 0)
+        ga_draws_one(g, gen, c, lane);
     if (lane == 0) {
         g.ok[0][c] = 1;
         g.fit[0][c] = ~0ull;

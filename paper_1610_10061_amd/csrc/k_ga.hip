@@ -15,14 +15,16 @@ namespace pmp {
 
 namespace {
 
+// Two waves per chromosome: the population slot, and the operator draws.
 __global__ __launch_bounds__(64 * kGaWaves) void k_init(GaArgs g)
 {
     __shared__ uint64_t sw[kGaWaves][2 * kMaxWords];
     const int wave = wave_id(), lane = threadIdx.x & 63;
-    const int c = blockIdx.x * kGaWaves + wave;
+    const int gw = blockIdx.x * kGaWaves + wave;
+    const int c = gw >> 1;
     if (c >= g.P || ga_stopped(g))
         return;
-    ga_init_one(g, c, lane, sw[wave]);
+    ga_init_one(g, c, lane, sw[wave], gw & 1);
 }
 
 __global__ __launch_bounds__(64 * kGaWaves) void k_stage(GaArgs g, int in,
@@ -442,7 +444,7 @@ hipError_t batch_wd(const BatchArgs &b, int generations, int max_blocks,
 
 hipError_t launch_ga_init(const GaArgs &g, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_init, per_wave(g.P), dim3(64 * kGaWaves), 0, s, g);
+    hipLaunchKernelGGL(k_init, per_wave(2 * g.P), dim3(64 * kGaWaves), 0, s, g);
     return hipGetLastError();
 }
 
