@@ -62,7 +62,7 @@ __device__ __forceinline__ uint32_t from_lane_xor(uint32_t v)
 // partner's.  J = 4, 2, 1: the bits a lane keeps, and the rotation that
 // brings its partner's bits into the others.
 struct TransposeLanes {
-    uint32_t sel[2], keep[5], rot[5];
+    uint32_t sel[2], keep[3], rot[3];  // sel: steps 16, 8; keep, rot: steps 4, 2, 1
 
     __device__ __forceinline__ explicit TransposeLanes(int lane)
     {
@@ -70,11 +70,10 @@ struct TransposeLanes {
         // 0-3 = partner byte 0-3
         sel[0] = (lane & 16) ? 0x07060302u : 0x01000504u;  // [p2 p3 o2 o3] / [o0 o1 p0 p1]
         sel[1] = (lane & 8) ? 0x07030501u : 0x02060004u;   // [p1 o1 p3 o3] / [o0 p0 o2 p2]
-        constexpr uint32_t M[5] = {0x0000FFFFu, 0x00FF00FFu, 0x0F0F0F0Fu, 0x33333333u,
-                                   0x55555555u};
+        constexpr uint32_t M[3] = {0x0F0F0F0Fu, 0x33333333u, 0x55555555u};
 #pragma unroll
-        for (int s = 2; s < 5; ++s) {
-            const int J = 16 >> s;
+        for (int s = 0; s < 3; ++s) {
+            const int J = 4 >> s;
             const bool up = (lane & J) != 0;
             keep[s] = up ? ~M[s] : M[s];
             rot[s] = up ? (uint32_t)J : (uint32_t)(32 - J);
@@ -107,7 +106,7 @@ __device__ __forceinline__ void transpose_step(uint32_t &lo, uint32_t &hi,
         lo = __builtin_amdgcn_perm(lo, ylo, tl.sel[S]);
         hi = __builtin_amdgcn_perm(hi, yhi, tl.sel[S]);
     } else {
-        const uint32_t k = tl.keep[S], r = tl.rot[S];
+        const uint32_t k = tl.keep[S - 2], r = tl.rot[S - 2];
         lo = bit_select(k, lo, __builtin_amdgcn_alignbit(ylo, ylo, r));
         hi = bit_select(k, hi, __builtin_amdgcn_alignbit(yhi, yhi, r));
     }

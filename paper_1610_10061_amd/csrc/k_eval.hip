@@ -2,6 +2,8 @@
 // (eval_device.hpp), a second adds the client-tile partial sums up.
 #include <hip/hip_ext.h>
 
+#include <atomic>
+
 #include "eval_device.hpp"
 
 namespace pmp {
@@ -79,17 +81,17 @@ namespace {
 template <int WD, bool R, bool H>
 int resident_wd()
 {
-    static int cached = 0;  // the same for every call: computed once
-    if (cached == 0) {
-        int per_cu = 0;
+    static std::atomic<int> cached{0};  // the same for every call: computed once
+    int per_cu = cached.load(std::memory_order_relaxed);
+    if (per_cu == 0) {
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
                 &per_cu, reinterpret_cast<const void *>(k_eval<WD, R, H>),
                 kEvalTile * kEvalWaves, 0) != hipSuccess ||
             per_cu < 1)
             per_cu = 1;
-        cached = per_cu;
+        cached.store(per_cu, std::memory_order_relaxed);
     }
-    return cached;
+    return per_cu;
 }
 
 }  // namespace

@@ -4,6 +4,7 @@
 #include "pmp.h"
 
 #include <algorithm>
+#include <atomic>
 #include <climits>
 #include <cstdarg>
 #include <cstdio>
@@ -103,10 +104,15 @@ int clients_per_block(int n, int P, int m, int p, int W, bool reduced = false)
         return (int)(((cpb + 3) / 4) * 4);
     }
     const bool paired = paired_scans(m, p) != 0;
+    static std::atomic<int> cus_of[64];  // per device, queried once
     int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        cus < 1)
+    if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64) {
+        cus = cus_of[dev].load(std::memory_order_relaxed);
+        if (cus == 0 &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+            cus_of[dev].store(cus, std::memory_order_relaxed);
+    }
+    if (cus < 1)
         cus = 256;
     const long slots = (long)cus * eval_workgroups_per_cu(W, reduced, paired);
     const long busy = (long)cus * 7 / 2;  // about 3.5 workgroups per CU
