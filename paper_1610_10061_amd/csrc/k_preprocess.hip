@@ -3,13 +3,15 @@
 // entries of the ordering Pi', the gap terms Delta' and the sorted distances
 // D'.
 //
-// One workgroup sorts one row in LDS.  A facility becomes the 64-bit key
+// One workgroup sorts one row in LDS.  A facility becomes the key
 // (d_ij << 16) | j; keys are distinct, so an ascending sort of keys is the
 // order by distance with ties broken by the lower index, the order the
-// paper's Example 1 prints.  The row is padded to a power of two with
-// all-ones keys and sorted by a bitonic network (Batcher, 1968).  The
-// epilogue splits the first K keys back into index and distance and takes
-// the first difference of the distances.
+// paper's Example 1 prints.  When every distance of the row is below 2^16
+// the key fits 32 bits, so the sort moves half the LDS bytes and twice as
+// many rows are sorted at once; otherwise it takes 64 bits.  The row is padded to a power of two with all-ones keys
+// and sorted by a bitonic network (Batcher, 1968).  The epilogue splits the
+// first K keys back into index and distance and takes the first difference
+// of the distances.
 #include "common.hpp"
 
 namespace pmp {
@@ -17,29 +19,16 @@ namespace pmp {
 namespace {
 
 constexpr int kSortThreads = 512;
+constexpr int kSortPerThread = PMP_MAX_FACILITIES / kSortThreads;  // 16
 
-__global__ __launch_bounds__(kSortThreads) void k_sort_rows(
-    const int32_t *__restrict__ d, int64_t ld, int32_t m, int32_t m2,
-    int32_t K, int32_t pitch, uint16_t *__restrict__ pi,
-    int32_t *__restrict__ delta, int32_t *__restrict__ ds,
-    uint32_t *__restrict__ err)
+// Compare-exchange t of a stage joins keys lo = 2t - (t mod stride) and
+// lo + stride.  With stride <= 32 the 64 threads of a wave (t in an aligned
+// block of 64) touch only their own aligned block of 128 keys, the same
+// block in every such stage, so consecutive stages of that kind need only
+// the wave's own ordering; a workgroup barrier is needed around the others.
+template <class Key>
+__device__ __forceinline__ void bitonic_sort(Key *key, int m2)
 {
-    extern __shared__ uint64_t key[];
-    const int32_t i = blockIdx.x;
-    const int32_t *row = d + (int64_t)i * ld;
-    int negative = 0;
-    for (int j = threadIdx.x; j < m2; j += kSortThreads) {
-        uint64_t k = ~0ull;
-        if (j < m) {
-            const int32_t v = row[j];
-            negative |= v < 0;
-            k = ((uint64_t)(uint32_t)v << 16) | (uint64_t)j;
-        }
-        key[j] = k;
-    }
-    if (__syncthreads_or(negative) && threadIdx.x == 0)
-        atomicOr(err, ERR_NEGATIVE_DISTANCE);
-
     const int half = m2 >> 1;
     for (int size = 2; size <= m2; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
@@ -47,22 +36,33 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_rows(
                 const int lo = 2 * t - (t & (stride - 1));
                 const int hi = lo + stride;
                 const bool ascending = (lo & size) == 0;
-                const uint64_t a = key[lo], b = key[hi];
+                const Key a = key[lo], b = key[hi];
                 if ((a > b) == ascending) {
                     key[lo] = b;
                     key[hi] = a;
                 }
             }
-            __syncthreads();
+            const int next = stride > 1 ? stride >> 1 : size;  // the next stage's stride
+            if (stride > 32 || next > 32) {
+                __syncthreads();
+            } else {
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+            }
         }
     }
+    __syncthreads();
+}
 
-    const int64_t base = (int64_t)i * pitch;
+template <class Key>
+__device__ __forceinline__ void emit_row(const Key *key, int K, int pitch, int64_t base,
+                                         uint16_t *pi, int32_t *delta, int32_t *ds)
+{
     for (int k = threadIdx.x; k < pitch; k += kSortThreads) {
         uint16_t f = 0;
         int32_t dist = 0, gap = 0;
         if (k < K) {
-            const uint64_t x = key[k];
+            const Key x = key[k];
             f = (uint16_t)(x & 0xFFFFu);
             dist = (int32_t)(x >> 16);
             gap = k == 0 ? dist : dist - (int32_t)(key[k - 1] >> 16);
@@ -71,6 +71,49 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_rows(
         ds[base + k] = dist;
         delta[base + k] = gap;
     }
+}
+
+// Two launches, one per key width: the 32-bit one (m2 x 4 bytes of LDS, so
+// twice as many workgroups stay resident) sorts the rows whose distances are
+// all below 2^16 and checks every row for negative distances; the 64-bit one
+// sorts the others.  Each reads the row and skips it when it belongs to the
+// other.  m2 <= PMP_MAX_FACILITIES; dynamic LDS holds m2 keys.
+template <class Key>
+__global__ __launch_bounds__(kSortThreads) void k_sort_rows(
+    const int32_t *__restrict__ d, int64_t ld, int32_t m, int32_t m2,
+    int32_t K, int32_t pitch, uint16_t *__restrict__ pi,
+    int32_t *__restrict__ delta, int32_t *__restrict__ ds,
+    uint32_t *__restrict__ err)
+{
+    constexpr bool k32 = sizeof(Key) == 4;
+    extern __shared__ uint64_t lds_keys[];
+    Key *key = reinterpret_cast<Key *>(lds_keys);
+    const int32_t i = blockIdx.x;
+    const int32_t *row = d + (int64_t)i * ld;
+    int32_t v[kSortPerThread];
+    int negative = 0, wide = 0;
+#pragma unroll
+    for (int r = 0; r < kSortPerThread; ++r) {
+        const int j = threadIdx.x + r * kSortThreads;
+        v[r] = row[j < m ? j : m - 1];  // every load at a valid address
+        if (j < m) {
+            negative |= v[r] < 0;
+            wide |= v[r] >= 65536;
+        }
+    }
+    if (k32 && __syncthreads_or(negative) && threadIdx.x == 0)
+        atomicOr(err, ERR_NEGATIVE_DISTANCE);
+    if ((__syncthreads_or(wide) != 0) == k32)
+        return;  // the other launch's row
+#pragma unroll
+    for (int r = 0; r < kSortPerThread; ++r) {
+        const int j = threadIdx.x + r * kSortThreads;
+        if (j < m2)
+            key[j] = j < m ? ((Key)(uint32_t)v[r] << 16) | (Key)j : ~(Key)0;
+    }
+    __syncthreads();
+    bitonic_sort(key, m2);
+    emit_row(key, K, pitch, (int64_t)i * pitch, pi, delta, ds);
 }
 
 __global__ void k_zero(uint32_t *p, size_t words)
@@ -91,9 +134,12 @@ hipError_t launch_sort_rows(const int32_t *d, int64_t ld, int32_t n, int32_t m,
     int32_t m2 = 2;
     while (m2 < m)
         m2 <<= 1;
-    const size_t lds = sizeof(uint64_t) * (size_t)m2;
-    hipLaunchKernelGGL(k_sort_rows, dim3(n), dim3(kSortThreads), lds, s, d, ld,
-                       m, m2, K, pitch, pi, delta, ds, err);
+    hipLaunchKernelGGL(k_sort_rows<uint32_t>, dim3(n), dim3(kSortThreads),
+                       sizeof(uint32_t) * (size_t)m2, s, d, ld, m, m2, K, pitch, pi, delta, ds,
+                       err);
+    hipLaunchKernelGGL(k_sort_rows<uint64_t>, dim3(n), dim3(kSortThreads),
+                       sizeof(uint64_t) * (size_t)m2, s, d, ld, m, m2, K, pitch, pi, delta, ds,
+                       err);
     return hipGetLastError();
 }
 

@@ -47,7 +47,20 @@ INSTANCES = {
     "euclid_129": lambda: (gi.euclid_instance(129, 5), 3),
     "wide_2x700": lambda: (_rand(2, 700, 50, 6), 350),
     "m2": lambda: (_rand(5, 2, 10, 7), 1),
+    # distances at and past 2^16: rows sort on 64-bit keys, the others on
+    # 32-bit keys, row by row
+    "wide_d": lambda: (_rand(40, 300, 2**31 - 1, 8), 30),
+    "mixed_rows": lambda: (_mixed_rows(), 10),
+    "edge_65535": lambda: (_rand(20, 100, 2, 10) + 65534, 5),
 }
+
+
+def _mixed_rows():
+    d = _rand(24, 200, 60000, 9)
+    d[3, 5] = 70000
+    d[17, 150] = 65536
+    d[20, :] = 65535
+    return d
 
 
 @pytest.mark.parametrize("name", list(INSTANCES))
@@ -65,7 +78,8 @@ def test_tables_bit_exact(pm, name):
 @pytest.mark.parametrize("name,P", [("example1", 6), ("g20", 200), ("g100", 64), ("g100", 1),
                                     ("g900", 1024), ("rect_37x150", 131), ("ties_p1", 70),
                                     ("ties_pm1", 65), ("euclid_64", 127), ("euclid_129", 64),
-                                    ("wide_2x700", 300), ("m2", 3)])
+                                    ("wide_2x700", 300), ("m2", 3), ("wide_d", 70),
+                                    ("mixed_rows", 65), ("edge_65535", 33)])
 def test_eval_bit_exact_host_path(pm, name, P):
     d, p = INSTANCES[name]()
     n, m = d.shape
