@@ -286,28 +286,6 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
         return;
     __syncthreads();
 
-    // Feasibility of each chromosome, checked once (first client tile).
-    // Lanes start at different words so the reads hit different banks.
-    if (ti == 0 && wave == 0 && my_act) {
-        int ones = 0;
-        uint32_t stray = 0;
-        const int full = a.t.m >> 5, rem = a.t.m & 31;
-        for (int k = 0; k < W2; ++k) {
-            int w = lane + k;
-            w = w >= W2 ? w - W2 * (w / W2) : w;
-            const uint32_t v = smask[lane * SD + w];
-            ones += __builtin_popcount(v);
-            if (w > full || (w == full && rem == 0))
-                stray |= v;
-            else if (w == full)
-                stray |= v & ~((1u << rem) - 1u);
-        }
-        if (ones != a.t.p)
-            atomicOr(a.err, ERR_POPCOUNT);
-        if (stray)
-            atomicOr(a.err, ERR_STRAY_BITS);
-    }
-
     // Facility-major copy: wave v turns the tile's 64-bit words v, v + 4, ...
     // (one row per lane) into T[64 w + f], f = 0..63, by one transpose each,
     // in place once every wave has read its rows.
@@ -318,6 +296,27 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
         const int w = min(wave + r * kEvalWaves, W - 1);
         rlo[r] = smask[lane * SD + 2 * w];
         rhi[r] = smask[lane * SD + 2 * w + 1];
+    }
+    // Feasibility of each chromosome (lane), checked once (first client
+    // tile) from the rows just read: each wave counts the open facilities in
+    // its words and looks for bits past m in the last word; wave 0 adds the
+    // waves' counts up once the copy's barrier has passed.
+    __shared__ uint32_t s_ones[kEvalWaves][kEvalTile];
+    __shared__ uint32_t s_stray[kEvalWaves][kEvalTile];
+    if (ti == 0) {
+        uint32_t ones = 0, stray = 0;
+        const uint64_t past = (a.t.m & 63) ? ~((1ull << (a.t.m & 63)) - 1ull) : 0ull;
+#pragma unroll
+        for (int r = 0; r < NW; ++r) {
+            const int w = wave + r * kEvalWaves;
+            if (w < W) {
+                ones += __builtin_popcount(rlo[r]) + __builtin_popcount(rhi[r]);
+                if (w == W - 1)
+                    stray |= (((uint64_t)rhi[r] << 32 | rlo[r]) & past) != 0ull ? 1u : 0u;
+            }
+        }
+        s_ones[wave][lane] = ones;
+        s_stray[wave][lane] = stray;
     }
     __syncthreads();
     uint64_t *sT = reinterpret_cast<uint64_t *>(smask);
@@ -336,6 +335,18 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
     if (wave == 0 && lane < 2)
         sT[jz + lane] = lane ? ~0ull : 0ull;
     __syncthreads();
+    if (ti == 0 && wave == 0 && my_act) {
+        uint32_t ones = 0, stray = 0;
+#pragma unroll
+        for (int v = 0; v < kEvalWaves; ++v) {
+            ones += s_ones[v][lane];
+            stray |= s_stray[v][lane];
+        }
+        if (ones != (uint32_t)a.t.p)
+            atomicOr(a.err, ERR_POPCOUNT);
+        if (stray)
+            atomicOr(a.err, ERR_STRAY_BITS);
+    }
 
     unsigned long long acc = 0;
     uint32_t scn = 0;
