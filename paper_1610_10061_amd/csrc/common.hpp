@@ -56,7 +56,7 @@ struct EvalArgs {
     const int32_t *rlen;
     const long long *e64;
     long long c0;
-    // short scans expected (m + 1 <= 12 (p + 1)): two clients per chunk
+    // very short scans expected (m + 1 <= 4 (p + 1)): two clients per chunk
     int32_t paired;
 };
 

@@ -71,15 +71,20 @@ int env_int(const char *name, int dflt)
     return atoi(v);
 }
 
-// Whether the evaluation walks two clients per chunk: when the expected scan
-// (m + 1) / (p + 1) of a random chromosome is short, almost every row finds
-// its first open facility within 32 entries.  PMP_EVAL_PAIRED=0/1 forces it.
+// Whether the evaluation walks two clients per chunk.  A pair's chunk holds
+// 32 entries of each row, and a row goes on to a tail chunk as soon as one
+// of the tile's 64 chromosomes has its first open facility past entry 31;
+// a tail chunk costs as much as a full one.  With mean scan (m+1)/(p+1) = 10
+// (G900, E5000 p = 500) most rows need the tail, and the single 64-entry
+// walk is faster (G900 80 -> 87 G evaluations/s, E5000 p = 500 85 -> 63 us),
+// so pairs are taken only for mean scans up to 4, where a row's 64
+// chromosomes rarely reach past 32.  PMP_EVAL_PAIRED=0/1 forces it.
 int paired_scans(int m, int p)
 {
     const int forced = env_int("PMP_EVAL_PAIRED", -1);
     if (forced >= 0)
         return forced ? 1 : 0;
-    return (int64_t)m + 1 <= 12LL * ((int64_t)p + 1) ? 1 : 0;
+    return (int64_t)m + 1 <= 4LL * ((int64_t)p + 1) ? 1 : 0;
 }
 
 // Clients per workgroup of the evaluation kernel.  A workgroup first stages
