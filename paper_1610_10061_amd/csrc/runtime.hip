@@ -93,9 +93,9 @@ int paired_scans(int m, int p)
 // (m+1)/(p+1) of 128 entries or more) the walks dominate: enough workgroups
 // to fill 256 CUs four times over, at most 64 clients each, so that uneven
 // scan lengths even out.  With short scans the staging counts: the fewest
-// client tiles that still give every CU of the device about 3.5 workgroups,
-// or that fill every CU's resident slots once when it holds fewer, so that
-// no workgroup waits for a slot.
+// client tiles that still give every CU of the device about 2.75
+// workgroups, or that fill every CU's resident slots once when it holds
+// fewer than 3.5, so that no workgroup waits for a slot.
 int clients_per_block(int n, int P, int m, int p, int W, bool reduced = false)
 {
     const int forced = env_int("PMP_CLIENTS_PER_BLOCK", 0);
@@ -120,7 +120,10 @@ int clients_per_block(int n, int P, int m, int p, int W, bool reduced = false)
     if (cus < 1)
         cus = 256;
     const long slots = (long)cus * eval_workgroups_per_cu(W, reduced, paired);
-    const long busy = (long)cus * 7 / 2;  // about 3.5 workgroups per CU
+    // When the CUs hold fewer than 3.5 workgroups each, fill the slots once;
+    // else aim at about 2.75 per CU (G900: 20 clients per workgroup measured
+    // 2 % faster than 16, 12 and 32 slower)
+    const long busy = slots < (long)cus * 7 / 2 ? slots : (long)cus * 11 / 4;
     const long want = std::min(slots, busy);
     long ti = want >= slots ? std::max(1L, slots / tiles_c) : (want + tiles_c - 1) / tiles_c;
     ti = std::min(ti, std::max(1L, ((long)n + 3) / 4));
@@ -336,7 +339,7 @@ struct pmp_ga {
         }
         const long tiles_c = (long)((PY + kEvalTile - 1) / kEvalTile);
         const int n = inst->n;
-        const long target = std::max(1, env_int("PMP_MUTANT_WORKGROUPS", 2048));
+        const long target = std::max(1, env_int("PMP_MUTANT_WORKGROUPS", 1024));
         int ti = (int)std::max(1L, std::min((long)n, target / std::max(1L, tiles_c)));
         ti = std::max(ti, (n + 127) / 128);  // at most 128 clients per workgroup
         int cpb = (n + ti - 1) / ti;
