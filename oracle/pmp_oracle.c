@@ -227,7 +227,7 @@ int orc_bc_eval(const int32_t *pi, const int32_t *delta, int32_t n, int32_t K,
     for (int32_t c = 0; c < P; ++c) {
         unpack(masks + (int64_t)c * W, m, open);
         int64_t fitness = 0, scanned = 0;
-        for (int32_t i = 0; i < n && cost[c] != -1; ++i) {
+        for (int32_t i = 0; i < n; ++i) {
             int32_t s = 0;
             int found = 0;
             while (s < K) {
@@ -663,11 +663,15 @@ int orc_mutate(uint64_t seed, uint64_t gen, uint64_t chrom, uint64_t attempt,
  *     count resets on a strict improvement and grows otherwise.  Stop when
  *     it reaches S (S > 0) or when EvolveLimit generations have run.
  *
- * Parity unpinned: the paper prints no trajectory (its Figures 1-3 are
- * missing), so the exact sequence of choices rests on the readings above;
- * the tests pin this function only by invariants (popcount p, fitness equal
- * to the objective, non-increasing best, saturation stop, optimum reached
- * on a small instance, checkpoint/resume equivalence).
+ * The paper prints no trajectory (its Figures 1-3 are missing), so the
+ * exact sequence of choices rests on the readings above.  The tests pin it
+ * by a worked derivation of whole generations kept apart from this file
+ * (every Philox word from numpy's generator, every operator parameter,
+ * offspring and accept decision, the state after each generation, on
+ * Example 1 and on an instance with many equal costs), and by invariants
+ * (popcount p, fitness equal to the objective, non-increasing best,
+ * saturation stop, optimum reached on a small instance, checkpoint/resume
+ * equivalence).
  * ---------------------------------------------------------------------- */
 typedef struct {
     uint64_t seed;
@@ -730,8 +734,12 @@ int orc_ga_run(const int32_t *d, int64_t ld, int32_t n, int32_t m, int32_t p,
     uint8_t *improved = (uint8_t *)malloc((size_t)P);
     int64_t *offfit = (int64_t *)malloc(sizeof(int64_t) * (size_t)P);
     uint64_t *tmp = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)P * W);
-    if (!bits || !snap || !offs || !ok || !improved || !offfit || !tmp)
-        return ORC_ENOMEM;
+    int32_t *which = (int32_t *)malloc(sizeof(int32_t) * (size_t)P);
+    int rc = ORC_OK;
+    if (!bits || !snap || !offs || !ok || !improved || !offfit || !tmp || !which) {
+        rc = ORC_ENOMEM;
+        goto out;
+    }
 
     /* the population carried over from the previous call (left unchanged
      * when this call runs no generation) */
@@ -761,8 +769,10 @@ int orc_ga_run(const int32_t *d, int64_t ld, int32_t n, int32_t m, int32_t p,
         /* 2. fitness */
         for (int32_t c = 0; c < P; ++c)
             pack(bits + (int64_t)c * m, m, W, tmp + (int64_t)c * W);
-        if (orc_objective(d, ld, n, m, p, tmp, P, fit, NULL, nt))
-            return ORC_EINFEASIBLE;
+        if (orc_objective(d, ld, n, m, p, tmp, P, fit, NULL, nt)) {
+            rc = ORC_EINFEASIBLE;
+            goto out;
+        }
         state[ORC_ST_CHROM_EVALS] += P;
 
         /* 3. crossover cycle */
@@ -785,14 +795,15 @@ int orc_ga_run(const int32_t *d, int64_t ld, int32_t n, int32_t m, int32_t p,
             }
             /* evaluate the offspring that exist */
             int32_t q = 0;
-            int32_t *which = (int32_t *)malloc(sizeof(int32_t) * (size_t)P);
             for (int32_t c = 0; c < P; ++c)
                 if (ok[c]) {
                     pack(offs + (int64_t)c * m, m, W, tmp + (int64_t)q * W);
                     which[q++] = c;
                 }
-            if (orc_objective(d, ld, n, m, p, tmp, q, offfit, NULL, nt))
-                return ORC_EINFEASIBLE;
+            if (orc_objective(d, ld, n, m, p, tmp, q, offfit, NULL, nt)) {
+                rc = ORC_EINFEASIBLE;
+                goto out;
+            }
             state[ORC_ST_CHROM_EVALS] += q;
             state[ORC_ST_XO_FAIL] += P - nok;
             for (int32_t r = 0; r < q; ++r) {
@@ -804,14 +815,12 @@ int orc_ga_run(const int32_t *d, int64_t ld, int32_t n, int32_t m, int32_t p,
                     state[ORC_ST_XO_TAKEN] += 1;
                 }
             }
-            free(which);
         }
 
         /* 4. mutation cycle */
         memset(improved, 0, (size_t)P);
         for (int32_t a = 0; a < Y; ++a) {
             int32_t q = 0;
-            int32_t *which = (int32_t *)malloc(sizeof(int32_t) * (size_t)P);
             for (int32_t c = 0; c < P; ++c) {
                 if (improved[c])
                     continue;
@@ -825,8 +834,10 @@ int orc_ga_run(const int32_t *d, int64_t ld, int32_t n, int32_t m, int32_t p,
                 pack(F, m, W, tmp + (int64_t)q * W);
                 which[q++] = c;
             }
-            if (orc_objective(d, ld, n, m, p, tmp, q, offfit, NULL, nt))
-                return ORC_EINFEASIBLE;
+            if (orc_objective(d, ld, n, m, p, tmp, q, offfit, NULL, nt)) {
+                rc = ORC_EINFEASIBLE;
+                goto out;
+            }
             state[ORC_ST_CHROM_EVALS] += q;
             for (int32_t r = 0; r < q; ++r) {
                 int32_t c = which[r];
@@ -838,7 +849,6 @@ int orc_ga_run(const int32_t *d, int64_t ld, int32_t n, int32_t m, int32_t p,
                     state[ORC_ST_MUT_TAKEN] += 1;
                 }
             }
-            free(which);
         }
 
         /* 5. group bests (Evolve steps 7-8) */
@@ -872,6 +882,7 @@ int orc_ga_run(const int32_t *d, int64_t ld, int32_t n, int32_t m, int32_t p,
     }
     for (int32_t c = 0; c < P; ++c)
         pack(bits + (int64_t)c * m, m, W, pop + (int64_t)c * W);
+out:
     free(bits);
     free(snap);
     free(offs);
@@ -879,7 +890,8 @@ int orc_ga_run(const int32_t *d, int64_t ld, int32_t n, int32_t m, int32_t p,
     free(improved);
     free(offfit);
     free(tmp);
-    return ORC_OK;
+    free(which);
+    return rc;
 }
 
 /* ------------------------------------------------------------------------
