@@ -125,6 +125,35 @@ PMP_API pmp_status pmp_eval_population(pmp_instance *inst, const uint64_t *masks
                                void *stream);
 
 /* ---------------------------------------------------------------------------
+ * pmp_eval_population_noalloc - pmp_eval_population (default tiled scheme)
+ * for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  It calls
+ * no hipMalloc, hipFree or allocating library routine.  The evaluation's
+ * client-tile partial sums go to a fixed workspace compiled into the
+ * library (a static device array of PMP_NOALLOC_CELLS 12-byte cells, 6 MiB,
+ * one copy on each GPU the library runs on, held until the process ends).
+ *
+ *  inst, masks, P, fitness, scan_total: as pmp_eval_population.
+ *  flags   must hold PMP_ON_DEVICE (masks, fitness, scan_total are device
+ *          pointers on `stream`); PMP_ASYNC as pmp_eval_population; no
+ *          scheme flag.
+ * Client tiles are widened when needed so that (client tiles) x P fits the
+ * workspace; the results do not depend on the tiling (exact integer sums).
+ * Errors: PMP_EINVAL for P > PMP_NOALLOC_CELLS, host pointers (no
+ * PMP_ON_DEVICE) or a scheme flag; PMP_EUNSUPPORTED when scan_total is asked
+ * for and a widened tile's scan sums could pass 2^32; otherwise as
+ * pmp_eval_population.  Every call on one GPU uses that GPU's workspace:
+ * calls that overlap on one GPU (two streams, two threads) race and give
+ * wrong results; the caller serialises them.  Nothing in the workspace
+ * needs clearing between calls (every cell read is written first).
+ * ------------------------------------------------------------------------- */
+#define PMP_NOALLOC_CELLS (1 << 19)
+PMP_API pmp_status pmp_eval_population_noalloc(pmp_instance *inst, const uint64_t *masks,
+                                               int32_t P, int64_t *fitness,
+                                               int64_t *scan_total, uint32_t flags,
+                                               void *stream);
+
+/* ---------------------------------------------------------------------------
  * The reduced Hammer-Beresnev polynomial (Section 2.1, after Eq. (6); Example
  * 1 reduces 15 terms to 7).  Term t >= 1 of client i has coefficient
  * Delta'_{i,t} and the monomial "the first t facilities of row i are all

@@ -19,7 +19,8 @@ import torch  # noqa: F401  (loads the HIP runtime libpmp.so binds to)
 
 __all__ = [
     "PmpError", "lib", "pmp_preprocess", "pmp_instance_info",
-    "pmp_instance_tables", "pmp_eval_population", "pmp_instance_check",
+    "pmp_instance_tables", "pmp_eval_population", "pmp_eval_population_noalloc",
+    "pmp_instance_check",
     "pmp_instance_destroy", "pmp_ga_create", "pmp_ga_step", "pmp_ga_best",
     "pmp_ga_state", "pmp_ga_destroy", "pmp_solve", "pmp_ga_profile",
     "pmp_ga_profile_read", "pmp_ga_autotune", "pmp_batch_create",
@@ -40,6 +41,7 @@ PMP_ON_DEVICE = 1
 PMP_ASYNC = 2
 PMP_EVAL_PER_CHROMOSOME = 4
 PMP_EVAL_PER_CLIENT = 8
+PMP_NOALLOC_CELLS = 1 << 19
 EVAL_SCHEMES = {"tiled": 0, "per_chromosome": PMP_EVAL_PER_CHROMOSOME,
                 "per_client": PMP_EVAL_PER_CLIENT}
 
@@ -54,6 +56,7 @@ EXPORTS = [
     "pmp_model_forward", "pmp_model_grad", "pmp_model_train", "pmp_model_destroy",
     "pmp_ga_set_model", "pmp_ga_replay", "pmp_exhaustive", "pmp_apsp",
     "pmp_hbp_reduce", "pmp_hbp_info", "pmp_hbp_terms", "pmp_hbp_eval", "pmp_hbp_destroy",
+    "pmp_eval_population_noalloc",
 ]
 
 FEATURES = 16
@@ -119,6 +122,7 @@ def lib():
     L.pmp_instance_info.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
     L.pmp_instance_tables.argtypes = [_vp, _vp, _vp, _vp, _u32, _vp]
     L.pmp_eval_population.argtypes = [_vp, _vp, _i32, _vp, _vp, _u32, _vp]
+    L.pmp_eval_population_noalloc.argtypes = [_vp, _vp, _i32, _vp, _vp, _u32, _vp]
     L.pmp_instance_check.argtypes = [_vp, _vp]
     L.pmp_instance_destroy.argtypes = [_vp]
     L.pmp_instance_destroy.restype = None
@@ -244,6 +248,22 @@ def pmp_eval_population(inst, masks, fitness, scan_total=None, stream=None,
     _check(lib().pmp_eval_population(inst, mp, P, fp, sp, flags,
                                      _stream(stream) if dev else None),
            "pmp_eval_population")
+
+
+def pmp_eval_population_noalloc(inst, masks, fitness, scan_total=None, stream=None,
+                                asynchronous=False):
+    """pmp_eval_population on CUDA tensors without any allocation: the
+    library's fixed workspace holds the partial sums (P up to
+    PMP_NOALLOC_CELLS; calls on one GPU must not overlap)."""
+    mp, dev = _buf(masks, np.uint64, torch.uint64)
+    fp, fdev = _buf(fitness, np.int64, torch.int64)
+    sp, sdev = _buf(scan_total, np.int64, torch.int64)
+    if not dev or not fdev or (sp is not None and not sdev):
+        raise ValueError("pmp_eval_population_noalloc takes CUDA tensors only")
+    flags = PMP_ON_DEVICE | (PMP_ASYNC if asynchronous else 0)
+    _check(lib().pmp_eval_population_noalloc(inst, mp, masks.shape[0], fp, sp, flags,
+                                             _stream(stream)),
+           "pmp_eval_population_noalloc")
 
 
 def pmp_apsp(w, d=None, stream=None):

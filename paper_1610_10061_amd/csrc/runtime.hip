@@ -558,6 +558,47 @@ hipError_t batch_enqueue(pmp_batch *bt, int generations, hipStream_t s, bool coo
                                    bh.max_w2, s);
 }
 
+// Workspace of pmp_eval_population_noalloc: the client-tile partial sums
+// (int64 costs, then uint32 scan lengths) of one evaluation, in memory the
+// library never allocates at run time.  Each GPU holds its own copy from the
+// moment the code object is loaded until the process ends.
+constexpr size_t kNoAllocCells = (size_t)PMP_NOALLOC_CELLS;
+static __device__ __align__(256) unsigned char scratch[kNoAllocCells * 12];
+
+// Device address of this GPU's copy of `scratch`, taken once per device
+// with that device current.  In host code the array's name is only a
+// host-side stand-in, never a device address: every kernel argument is
+// derived from the address returned here.
+constexpr int kMaxDevices = 64;
+std::atomic<void *> g_scratch_addr[kMaxDevices];
+std::mutex g_scratch_mu;
+
+hipError_t scratch_address(void **out)
+{
+    *out = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    if (dev < 0 || dev >= kMaxDevices)
+        return hipErrorInvalidDevice;
+    void *p = g_scratch_addr[dev].load(std::memory_order_acquire);
+    if (!p) {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        p = g_scratch_addr[dev].load(std::memory_order_acquire);
+        if (!p) {
+            e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess)
+                return e;
+            if (!p)
+                return hipErrorInvalidSymbol;
+            g_scratch_addr[dev].store(p, std::memory_order_release);
+        }
+    }
+    *out = p;
+    return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1186,6 +1227,69 @@ pmp_status pmp_eval_population(pmp_instance *inst, const uint64_t *masks,
             HIP_TRY(hipMemcpyAsync(scan_total, dscan, sizeof(int64_t) * P,
                                    hipMemcpyDeviceToHost, s));
     }
+    if (async)
+        return PMP_OK;
+    uint32_t herr = 0;
+    HIP_TRY(hipMemcpyAsync(&herr, inst->err, sizeof herr, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return status_from_err(herr);
+}
+
+pmp_status pmp_eval_population_noalloc(pmp_instance *inst, const uint64_t *masks,
+                                       int32_t P, int64_t *fitness,
+                                       int64_t *scan_total, uint32_t flags,
+                                       void *stream)
+{
+    if (!inst)
+        return fail(PMP_EINVAL, "instance is NULL");
+    if (!(flags & PMP_ON_DEVICE))
+        return fail(PMP_EINVAL, "pmp_eval_population_noalloc takes device pointers only "
+                                "(PMP_ON_DEVICE): host buffers would need staging memory");
+    if (flags & (PMP_EVAL_PER_CHROMOSOME | PMP_EVAL_PER_CLIENT))
+        return fail(PMP_EINVAL, "pmp_eval_population_noalloc runs the tiled scheme only");
+    if (P < 0)
+        return fail(PMP_EINVAL, "P < 0");
+    if ((size_t)P > kNoAllocCells)
+        return fail(PMP_EINVAL, "P = %d exceeds the no-allocation workspace (%zu chromosomes)",
+                    P, kNoAllocCells);
+    if (P == 0)
+        return PMP_OK;
+    if (!masks || !fitness)
+        return fail(PMP_EINVAL, "masks or fitness is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const bool async = flags & PMP_ASYNC;
+    void *ws = nullptr;
+    HIP_TRY(scratch_address(&ws));
+
+    EvalArgs a{};
+    a.t = inst->tables();
+    a.paired = paired_scans(inst->m, inst->p);
+    a.masks = masks;
+    a.P = P;
+    a.active = nullptr;
+    a.done = nullptr;
+    a.err = inst->err;
+    a.tiles_c = (P + kEvalTile - 1) / kEvalTile;
+    int64_t cpb = clients_per_block(inst->n, P, inst->m, inst->p, inst->W);
+    int64_t ti = ((int64_t)inst->n + cpb - 1) / cpb;
+    const int64_t ti_max = (int64_t)(kNoAllocCells / (size_t)P);  // >= 1
+    if (ti > ti_max) {  // wider client tiles, so that ti x P cells fit
+        cpb = ((int64_t)inst->n + ti_max - 1) / ti_max;
+        ti = ((int64_t)inst->n + cpb - 1) / cpb;
+    }
+    // a tile's summed scan lengths are kept in 32 bits
+    if (scan_total && cpb * (int64_t)inst->K >= (1ll << 32))
+        return fail(PMP_EUNSUPPORTED, "scan sums of %lld-client tiles may pass 2^32",
+                    (long long)cpb);
+    a.clients_per_block = (int32_t)cpb;
+    a.tiles_i = (int32_t)ti;
+    a.part = (unsigned long long *)ws;
+    a.spart = scan_total ? (uint32_t *)((unsigned char *)ws + kNoAllocCells * 8) : nullptr;
+    if (!async)
+        HIP_TRY(launch_zero(inst->err, sizeof(uint32_t), s));
+    HIP_TRY(launch_eval(a, s));
+    HIP_TRY(launch_reduce(a, (unsigned long long *)fitness, (unsigned long long *)scan_total,
+                          s));
     if (async)
         return PMP_OK;
     uint32_t herr = 0;
