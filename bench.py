@@ -13,10 +13,27 @@ peak (HIP events around each of its launches in the first generations of
 every timed step), and the CPU oracle's rate on the same workload, timed on
 this host's cores.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W]
+After the timed region the same run measures the other configurations
+(--legs, default all): the evaluation kernel alone on Euclidean n = m = 5000
+(p = 10, 100, 500; random and evolved populations of 4096), plain vs
+learned-proposal GA time-to-best on fresh Euclidean n = m = 2000 seeds, and
+256 ragged instances in one batched launch vs one launch sequence per
+instance.  Their numbers go into the same JSON line.
+
+The evaluation kernel's roofline is its VALU issue rate: the rocprofv3
+SQ_INSTS_VALU count per (client, chromosome) pair of the same workload (the
+committed counter summary, used while the kernel's sources match it) times
+the pairs the sampled launches evaluated, over their measured time, against
+1024 SIMDs x 2.4 GHz / 4 cycles per wave64 VALU instruction.  The bytes the
+paper's untiled walk would read (2 s* + 4 per pair) are reported beside it,
+labelled as such: the tiled kernel reads each row chunk once per 64
+chromosomes, so they are not HBM traffic; the measured HBM traffic is.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--legs e5000,learned,batch|none]
 python bench.py --workload batch     256 ragged instances, one launch vs many
 python bench.py --workload learned   plain vs learned-proposal GA at equal
                                      wall time (Euclidean n=m=2000, p=200)
+python bench.py --workload e5000     the evaluation kernel alone at E5000
 """
 from __future__ import annotations
 
@@ -30,6 +47,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+# VALU issue: 256 CUs x 4 SIMDs, one wave64 VALU instruction per SIMD every
+# 4 cycles (16 lanes per SIMD), 2.4 GHz peak engine clock
+SIMDS = 256 * 4
+CLOCK_HZ = 2.4e9
+VALU_PEAK_GIPS = SIMDS * CLOCK_HZ / 4 / 1e9  # 614.4 G wave-instructions/s
 
 WORKLOAD = {
     "workload": "G900 plain GA: random connected graph n=m=900, 16200 edges, "
@@ -47,10 +69,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-COUNTERS = os.path.join(ROOT, "profiles", "k_eval_g900_counters.json")
-# sources that decide what the evaluation dispatches of a GA step read and
-# write: the kernel, and the runtime that builds the schedule of dispatches
-EVAL_SOURCES = ("eval_device.hpp", "k_eval.hip", "runtime.hip")
+COUNTERS = os.path.join(ROOT, "profiles", "k_eval_counters.json")
+# sources of the evaluation kernel: a change to them voids its counters (the
+# summary also records the client tiles its dispatches used)
+EVAL_SOURCES = ("eval_device.hpp", "k_eval.hip")
 
 
 def eval_sources_digest():
@@ -63,10 +85,12 @@ def eval_sources_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per evaluation dispatch from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's readings),
-    or None when it is absent or the kernel's sources changed since."""
+def eval_counters(case):
+    """Per-dispatch counter averages of the evaluation kernel for one
+    workload case from the committed rocprofv3 summary (VALU and LDS
+    instructions, LDS bank-conflict cycles, HBM bytes scaled by a plain
+    copy's readings, pairs per dispatch), or None when the summary is absent
+    or the kernel's sources changed since it was taken."""
     try:
         with open(COUNTERS) as fh:
             c = json.load(fh)
@@ -74,33 +98,116 @@ def measured_traffic():
         return None
     if c.get("eval_sources_digest") != eval_sources_digest():
         return None
-    return c.get("hbm_bytes_per_dispatch")
+    return c.get("cases", {}).get(case)
+
+
+def valu_roofline(ctr, pairs, seconds, launches):
+    """VALU-issue roofline of the evaluation kernel from the counters'
+    instructions per pair, the pairs evaluated and their measured time."""
+    if not ctr or not seconds or not pairs:
+        return {"bound": "alu", "achieved": None, "peak": VALU_PEAK_GIPS,
+                "unit": "G wave64 VALU instructions/s", "frac": None, "traffic": None,
+                "note": "no counter summary matching the kernel's sources"}
+    per_pair = ctr["SQ_INSTS_VALU"] / ctr["pairs"]
+    achieved = per_pair * pairs / seconds / 1e9
+    out = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_GIPS,
+           "unit": "G wave64 VALU instructions/s", "frac": achieved / VALU_PEAK_GIPS,
+           "traffic": ctr.get("hbm_bytes")}
+    avg_s = seconds / max(launches, 1)
+    if ctr.get("hbm_bytes") is not None:
+        gbs = ctr["hbm_bytes"] / avg_s / 1e9
+        out["hbm_measured"] = {"GBps": gbs, "frac": gbs / HBM_PEAK_GBS}
+    if ctr.get("SQ_INSTS_LDS"):
+        out["lds"] = {"instructions_per_dispatch": ctr["SQ_INSTS_LDS"],
+                      "bank_conflict_cycles_per_lds_instruction":
+                          ctr.get("SQ_LDS_BANK_CONFLICT", 0) / ctr["SQ_INSTS_LDS"]}
+    return out
+
+
+def host_info():
+    """CPU model and core count of this host."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": usable, "os_cpu_count": os.cpu_count()}
 
 
 def cpu_baseline(d, p, P, NT, budget_s):
-    """The oracle GA on the same instance and parameters, a bounded number of
-    generations, on all host cores it is allowed."""
+    """The oracle on this host's cores, on the same G900 instance and GA
+    parameters: the oracle GA on all cores it is allowed (the reported
+    value) and on one thread, each for a bounded number of generations; the
+    paper's walk of Section 4.2 on the CPU (one thread) over the population
+    the GA left; and the preprocessing of Section 2.1 (the oracle's sort, and
+    numpy's stable argsort, one thread)."""
+    import numpy as np
     import oracle
-    n = d.shape[0]
-    st = oracle.GaState(n, d.shape[1], p, P, NT, 10_000, seed=12345)
+    n, m = d.shape
     threads = oracle.default_threads()
+
+    def ga_rate(nthreads, seconds, seed):
+        st = oracle.GaState(n, m, p, P, NT, 10_000, seed=seed)
+        t0 = time.perf_counter()
+        oracle.ga_run(d, st, 1, threads=nthreads)
+        one = time.perf_counter() - t0
+        more = max(0, min(400, int(seconds / max(one, 1e-3)) - 1))
+        if more:
+            oracle.ga_run(d, st, more, threads=nthreads)
+        dt = time.perf_counter() - t0
+        pairs = int(st.state[oracle.ST_CHROM_EVALS]) * n
+        return pairs / dt, 1 + more, pairs, dt, st
+
+    rate, gens, pairs, dt, st = ga_rate(0, budget_s, 12345)
+    rate1, gens1, pairs1, dt1, _ = ga_rate(1, budget_s / 3, 12345)
+    out = {"value": rate, "unit": "client×chromosome evals/s",
+           "cores": threads, "kind": "oracle",
+           "sample": f"{gens} generations of the oracle GA on the same G900 instance "
+                     f"(P={P}, NT={NT}), {pairs} client x chromosome evaluations "
+                     f"in {dt:.1f} s on {threads} threads",
+           "host": host_info(),
+           "one_thread": {"value": rate1, "unit": "client×chromosome evals/s", "cores": 1,
+                          "sample": f"{gens1} generations of the same oracle GA, "
+                                    f"{pairs1} evaluations in {dt1:.1f} s"}}
+    # the paper's walk on the CPU: Pi'/Delta' tables, scan to the first open
+    pi, de, _ = oracle.tables(d, p)
+    pop = st.pop
     t0 = time.perf_counter()
-    oracle.ga_run(d, st, 1)
-    one = time.perf_counter() - t0
-    more = max(0, min(400, int(budget_s / max(one, 1e-3)) - 1))
-    if more:
-        oracle.ga_run(d, st, more)
-    dt = time.perf_counter() - t0
-    gens = 1 + more
-    pairs = int(st.state[oracle.ST_CHROM_EVALS]) * n
-    return {"value": pairs / dt, "unit": "client×chromosome evals/s",
-            "cores": threads, "kind": "oracle",
-            "sample": f"{gens} generations of the oracle GA on the same G900 instance "
-                      f"(P={P}, NT={NT}), {pairs} client x chromosome evaluations "
-                      f"in {dt:.1f} s"}
+    reps = 0
+    while True:
+        oracle.bc_eval(pi, de, pop, m)
+        reps += 1
+        if time.perf_counter() - t0 > 1.0:
+            break
+    dts = time.perf_counter() - t0
+    out["pi_scan"] = {"value": reps * pop.shape[0] * n / dts,
+                      "unit": "client×chromosome evals/s", "cores": 1,
+                      "sample": f"{reps} walks of Section 4.2 over the {pop.shape[0]} "
+                                f"chromosomes the oracle GA left, in {dts:.2f} s"}
+    # preprocessing, one thread
+    t0 = time.perf_counter()
+    oracle.tables(d, p)
+    dtp = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.tables_numpy(d, p)
+    dtn = time.perf_counter() - t0
+    out["preprocess"] = {"oracle_rows_per_s": n / dtp, "numpy_argsort_rows_per_s": n / dtn,
+                         "cores": 1,
+                         "sample": f"tables of the {n} rows of the G900 instance: oracle "
+                                   f"sort {dtp * 1e3:.1f} ms, numpy stable argsort + diff "
+                                   f"{dtn * 1e3:.1f} ms"}
+    return out
 
 
-def bench_batch(args, specs, ds):
+def leg_batch(args, specs, ds):
     """256 ragged instances (population 256 each): all preprocessed, then
     `--batch-generations` generations of every GA run, (a) in one persistent
     launch per step replayed from a hipGraph, (b) instance by instance with
@@ -145,7 +252,7 @@ def bench_batch(args, specs, ds):
     log("one launch per instance ...")
     prep_s, evo_s, pairs_s, costs_s = run(False, 0)
     assert costs_b == costs_s, "batched and per-instance runs must agree"
-    out = {
+    return {
         "metric": "instances/s, 256 ragged instances x %d generations" % G,
         "value": 256 / (prep_b + evo_b),
         "unit": "instances/s",
@@ -162,7 +269,6 @@ def bench_batch(args, specs, ds):
         "speedup_evolve": evo_s / evo_b,
         "identical_results": costs_b == costs_s,
     }
-    print(json.dumps(out), flush=True)
 
 
 LEARNED = {
@@ -209,7 +315,7 @@ def _run_timed(pm, inst, seed, params, seconds, chunk, stream, learn_kw):
     return trace
 
 
-def bench_learned(args):
+def leg_learned(args):
     """Train the network online on `--train-seeds` instances, then on each
     fresh seed run the plain and the learned GA for the same wall time;
     report the time the learned GA needs to reach the plain GA's best."""
@@ -294,15 +400,18 @@ def bench_learned(args):
         out["cpu_baseline"] = {"value": Xc.shape[0] / dt, "unit": "network rows/s",
                                "cores": oracle_threads(), "kind": "oracle",
                                "sample": "oracle forward (numpy float64) of 8192 rows"}
-    print(json.dumps(out), flush=True)
+    return out
 
 
-def bench_e5000(args):
+def leg_e5000(args):
     """The evaluation kernel alone on the Euclidean n = m = 5000 instance,
-    p in {10, 100, 500}, population 4096: a uniform random population and
-    one evolved for --evolve-generations generations; median of 20 timed
-    launches (HIP events on the launch stream) after 3 warm-ups.  Also the
-    preprocessing time of each instance."""
+    p in {10, 100, 500}, population 4096: a uniform random population, then
+    the population a GA run (P = 4096, NT = 256) leaves after
+    --evolve-generations generations; median of 20 timed launches (HIP
+    events on the launch stream) after 3 warm-ups.  Also the preprocessing
+    time of each instance.  Per case: pairs/s, the VALU-issue roofline from
+    the committed counters of the same launches, the measured HBM traffic,
+    and the bytes the paper's untiled walk would read."""
     import numpy as np
     import torch
     import paper_1610_10061_amd as pm
@@ -314,6 +423,41 @@ def bench_e5000(args):
     dd = torch.from_numpy(d).cuda()
     W = gi.words_for(n)
     res = []
+
+    def timed(inst, masks, p, kind, prep_ms):
+        fit = torch.empty(P, dtype=torch.int64, device="cuda")
+        scan = torch.empty(P, dtype=torch.int64, device="cuda")
+        for _ in range(3):
+            inst.eval(masks, fit, scan, stream, asynchronous=True)
+        times = []
+        for _ in range(20):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            inst.eval(masks, fit, scan, stream, asynchronous=True)
+            b.record()
+            times.append((a, b))
+        inst.check(stream)
+        ms = float(np.median([a.elapsed_time(b) for a, b in times]))
+        s_tot = int(scan.sum().item())
+        pairs = P * n
+        byts = 2 * s_tot + 4 * pairs + P * (8 * W + 8)
+        case = f"e5000_p{p}_{kind}"
+        row = {"case": case, "p": p, "population": kind, "eval_ms": ms,
+               "pair_evals_per_s": pairs / (ms / 1e3),
+               "mean_scan": s_tot / pairs, "expected_scan_random": (n + 1) / (p + 1),
+               "roofline": valu_roofline(eval_counters(case), pairs, ms / 1e3, 1),
+               "paper_form_bytes": {"GBps": byts / (ms / 1e3) / 1e9,
+                                    "vs_hbm_peak": byts / (ms / 1e3) / 1e9 / HBM_PEAK_GBS},
+               "preprocess_ms": prep_ms, "preprocess_rows_per_s": n / (prep_ms / 1e3)}
+        if kind == "random":
+            import oracle
+            sub = masks[:8].cpu().numpy()
+            oc, os_ = oracle.objective(d, sub, p, scan=True)
+            assert np.array_equal(oc, fit[:8].cpu().numpy())
+            assert np.array_equal(os_, scan[:8].cpu().numpy())
+        log(json.dumps(row))
+        res.append(row)
+
     for p in (10, 100, 500):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         pm.Instance(dd, p, stream).close()  # first use outside the clock
@@ -323,44 +467,14 @@ def bench_e5000(args):
         e1.record()
         torch.cuda.synchronize()
         prep_ms = e0.elapsed_time(e1)
-        pops = {"random": torch.from_numpy(gi.random_population(P, n, p, 1)).cuda()}
+        rnd = torch.from_numpy(gi.random_population(P, n, p, 1)).cuda()
+        timed(inst, rnd, p, "random", prep_ms)
         ga = pm.GA(inst, P, 256, args.evolve_generations, 0)
         ga.step(args.evolve_generations, stream)
-        pops["evolved"] = torch.from_numpy(ga.state()[0]).cuda()
+        evolved = torch.from_numpy(ga.state()[0]).cuda()
         ga.close()
-        for kind, masks in pops.items():
-            fit = torch.empty(P, dtype=torch.int64, device="cuda")
-            scan = torch.empty(P, dtype=torch.int64, device="cuda")
-            for _ in range(3):
-                inst.eval(masks, fit, scan, stream, asynchronous=True)
-            times = []
-            for _ in range(20):
-                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                a.record()
-                inst.eval(masks, fit, scan, stream, asynchronous=True)
-                b.record()
-                times.append((a, b))
-            inst.check(stream)
-            ms = float(np.median([a.elapsed_time(b) for a, b in times]))
-            s_tot = int(scan.sum().item())
-            pairs = P * n
-            byts = 2 * s_tot + 4 * pairs + P * (8 * W + 8)
-            row = {"p": p, "population": kind, "eval_ms": ms,
-                   "pair_evals_per_s": pairs / (ms / 1e3),
-                   "mean_scan": s_tot / pairs, "expected_scan_random": (n + 1) / (p + 1),
-                   "algorithmic_GBps": byts / (ms / 1e3) / 1e9,
-                   "frac_of_hbm_peak": byts / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
-                   "preprocess_ms": prep_ms, "preprocess_rows_per_s": n / (prep_ms / 1e3)}
-            if kind == "random":
-                import oracle
-                sub = masks[:8].cpu().numpy()
-                oc, os_ = oracle.objective(d, sub, p, scan=True)
-                assert np.array_equal(oc, fit[:8].cpu().numpy())
-                assert np.array_equal(os_, scan[:8].cpu().numpy())
-            log(json.dumps(row))
-            res.append(row)
+        timed(inst, evolved, p, "evolved", prep_ms)
         inst.close()
-    best = max(res, key=lambda r: r["frac_of_hbm_peak"])
     out = {
         "metric": "client×chromosome fitness evals/s (evaluation kernel alone)",
         "value": float(np.median([r["pair_evals_per_s"] for r in res])),
@@ -369,22 +483,23 @@ def bench_e5000(args):
         "config": {"workload": "E5000: Euclidean n=m=5000 on the 10^4 x 10^4 integer grid, "
                                "p in {10,100,500}, population 4096, random and evolved "
                                "(%d generations) populations" % args.evolve_generations},
-        "roofline": {"bound": "hbm", "kernel": "k_eval", "achieved": best["algorithmic_GBps"],
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": best["frac_of_hbm_peak"], "traffic": None,
-                     "case": f"p={best['p']} {best['population']}"},
         "cases": res,
     }
     if not args.no_cpu_baseline:
         import oracle
-        sub = pops["random"][:256].cpu().numpy()
+        sub = rnd[:256].cpu().numpy()
         t0 = time.perf_counter()
         oracle.objective(d, sub, 500)
         dt = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.objective(d, sub[:32], 500, threads=1)
+        dt1 = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": 256 * n / dt, "unit": "client×chromosome evals/s",
                                "cores": oracle.default_threads(), "kind": "oracle",
-                               "sample": "oracle objective of 256 chromosomes (p=500)"}
-    print(json.dumps(out), flush=True)
+                               "sample": "oracle objective of 256 chromosomes (p=500)",
+                               "one_thread": {"value": 32 * n / dt1, "cores": 1,
+                                              "sample": "32 chromosomes (p=500)"}}
+    return out
 
 
 ALU_INT32_OPS = 256 * 64 * 2.4e9   # 256 CUs x 64 int32 VALU lanes x 2.4 GHz
@@ -714,9 +829,13 @@ def main():
     ap.add_argument("--workload", choices=["g900", "batch", "learned", "e5000", "g100",
                                            "ablation", "apsp", "hbp"],
                     default="g900",
-                    help="g900: the headline configuration; batch: 256 ragged "
-                         "instances in one launch vs one launch per instance; "
-                         "learned: plain vs learned-proposal GA at equal wall time")
+                    help="g900: the headline configuration (plus --legs); batch: 256 "
+                         "ragged instances in one launch vs one launch per instance; "
+                         "learned: plain vs learned-proposal GA at equal wall time; "
+                         "e5000: the evaluation kernel alone")
+    ap.add_argument("--legs", default="e5000,learned,batch",
+                    help="configurations measured after the headline's timed region "
+                         "(comma list of e5000, learned, batch; or none)")
     ap.add_argument("--train-seeds", type=int, default=20)
     ap.add_argument("--train-generations", type=int, default=100)
     ap.add_argument("--eval-seeds", type=int, default=10)
@@ -733,8 +852,13 @@ def main():
               "would shard by population across GPUs, which this build does not run.",
               file=sys.stderr)
         sys.exit(2)
+    legs = [x for x in args.legs.split(",") if x and x != "none"]
+    for x in legs:
+        if x not in ("e5000", "learned", "batch"):
+            ap.error(f"unknown leg {x}")
 
-    if args.workload == "batch":
+    batch_inputs = None
+    if args.workload == "batch" or (args.workload == "g900" and "batch" in legs):
         # instances are built before anything touches the GPU (worker
         # processes must not inherit a GPU context)
         import pmp_inputs as gi
@@ -743,12 +867,16 @@ def main():
         log("generating 256 instances ...")
         with ProcessPoolExecutor(max_workers=8) as ex:
             ds = list(ex.map(gi.batch_instance, specs))
-        return bench_batch(args, specs, ds)
-
+        batch_inputs = (specs, ds)
+    if args.workload == "batch":
+        print(json.dumps(leg_batch(args, *batch_inputs)), flush=True)
+        return
     if args.workload == "learned":
-        return bench_learned(args)
+        print(json.dumps(leg_learned(args)), flush=True)
+        return
     if args.workload == "e5000":
-        return bench_e5000(args)
+        print(json.dumps(leg_e5000(args)), flush=True)
+        return
     if args.workload == "g100":
         return bench_g100(args)
     if args.workload == "ablation":
@@ -813,7 +941,8 @@ def main():
     t0 = time.perf_counter()
     for k in range(args.steps):
         step(k, rec)
-        log(f"step {k} done: best {rec[-1][2]} (tile {rec[-1][3]} clients)")
+        log(f"step {k} done: best {rec[-1][2]} (tile {rec[-1][3][0]} clients, "
+            f"{rec[-1][3][1]} waves)")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
 
@@ -822,7 +951,27 @@ def main():
     ev_ms = sum(pr["eval_ms"] for pr in profs)
     ev_n = sum(pr["eval_launches"] for pr in profs)
     ev_bytes = sum(pr["eval_bytes"] for pr in profs)
-    achieved = ev_bytes / (ev_ms / 1e3) / 1e9 if ev_ms > 0 else 0.0
+    ev_pairs = sum(pr["eval_pairs"] for pr in profs)
+    roof = valu_roofline(eval_counters("g900_ga"), ev_pairs, ev_ms / 1e3, ev_n)
+    roof = dict({"bound": roof.pop("bound"), "kernel": "k_eval (population evaluation)"},
+                **roof)
+    paper_gbs = ev_bytes / (ev_ms / 1e3) / 1e9 if ev_ms > 0 else 0.0
+    roof.update({
+        "launches": ev_n,
+        "avg_launch_us": ev_ms * 1e3 / max(ev_n, 1),
+        "pairs_per_launch": ev_pairs / max(ev_n, 1),
+        "sampled": f"evaluation launches of the first {PROFILE_GENS} generations of each "
+                   "timed step (HIP events recorded by each dispatch)",
+        "counters": "profiles/k_eval_counters.json (case g900_ga; null fields when the "
+                    "evaluation kernel changed since)",
+        "paper_form_bytes": {
+            "bytes_per_launch": ev_bytes / max(ev_n, 1), "GBps": paper_gbs,
+            "vs_hbm_peak": paper_gbs / HBM_PEAK_GBS,
+            "note": "2 s* + 4 B per pair plus 8W + 8 per chromosome, what the untiled walk "
+                    "of Section 4.2 would read; the tiled kernel reads each row chunk once "
+                    "per 64 chromosomes, so this is not HBM traffic; s* from the kernel's "
+                    "own scan count (checked against the oracle by the parity tests)"},
+    })
     out = {
         "metric": METRIC,
         "value": pairs / dt,
@@ -837,27 +986,30 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": dict(WORKLOAD, generations=G),
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "k_eval (population evaluation)",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(),
-            "traffic_source": "profiles/k_eval_g900_counters.json (null if the "
-                              "evaluation kernel changed since)",
-            "launches": ev_n,
-            "avg_launch_us": ev_ms * 1e3 / max(ev_n, 1),
-            "bytes_per_launch": ev_bytes / max(ev_n, 1),
-            "sampled": f"evaluation launches of the first {PROFILE_GENS} generations of each timed step",
-        },
+        "roofline": roof,
         "best_costs": [int(r[2]) for r in rec],
-        "eval_tile_clients": rec[0][3] if rec else None,
+        "eval_tile": {"clients": rec[0][3][0], "waves": rec[0][3][1]} if rec else None,
     }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle ...")
         out["cpu_baseline"] = cpu_baseline(d, p, P, NT, args.cpu_seconds)
+    # the other configurations, outside the timed region
+    out["legs"] = {}
+    if "e5000" in legs:
+        log("E5000 evaluation leg ...")
+        out["legs"]["e5000"] = leg_e5000(argparse.Namespace(**dict(
+            vars(args), no_cpu_baseline=True)))
+    if "learned" in legs:
+        log("learned-proposal leg ...")
+        out["legs"]["learned"] = leg_learned(argparse.Namespace(**dict(
+            vars(args), train_seeds=4, train_generations=60, eval_seeds=5, seconds=1.0,
+            no_cpu_baseline=True)))
+        out["time_to_best"] = {k: out["legs"]["learned"].get(k) for k in
+                               ("metric", "value", "unit", "speedup_iqr", "reached",
+                                "relative_gap_at_equal_time_iqr")}
+    if "batch" in legs:
+        log("batch leg ...")
+        out["legs"]["batch"] = leg_batch(args, *batch_inputs)
     print(json.dumps(out), flush=True)
 
 

@@ -321,17 +321,20 @@ PMP_API pmp_status pmp_ga_state(pmp_ga *ga, uint64_t *population, int64_t *fitne
 PMP_API void pmp_ga_destroy(pmp_ga *ga);
 
 /* ---------------------------------------------------------------------------
- * pmp_ga_autotune (not in the paper) - choose the evaluation tile of a run:
- * how many clients one workgroup of the evaluation kernel takes (its 64
- * chromosomes are fixed, one per lane).  Candidates 4, 8, 12, ..., 128 are timed on a
- * generation-0 population of this run with HIP events; the fastest is kept
- * and remembered for runs of similar shape (n, m/p, W, P) in this process.
- * Results do not depend on the choice (integer sums).  Call it before the
- * first pmp_ga_step and before adding the run to a batch.  `chosen`
- * (optional) receives the clients per workgroup.  PMP_EINVAL after the first
+ * pmp_ga_autotune (not in the paper) - choose the evaluation tile of a run
+ * in two dimensions: how many clients one workgroup of the evaluation
+ * kernel takes (its 64 chromosomes are fixed, one per lane), and how many
+ * waves (4, 8 or 16) share that workgroup's staged chromosome tile.  The
+ * shape's default is timed first, then every pair of candidate clients (4,
+ * 8, 12, ..., 512) and waves, on a generation-0 population of this run with
+ * HIP events; a pair replaces the default only when at least 3 % faster.
+ * The choice is remembered for runs of similar shape (n, m/p, W, P) in this
+ * process.  Results do not depend on it (integer sums).  Call it before the
+ * first pmp_ga_step and before adding the run to a batch.  `clients` and
+ * `waves` (optional) receive the choice.  PMP_EINVAL after the first
  * generation.
  * ------------------------------------------------------------------------- */
-PMP_API pmp_status pmp_ga_autotune(pmp_ga *ga, int32_t *chosen, void *stream);
+PMP_API pmp_status pmp_ga_autotune(pmp_ga *ga, int32_t *clients, int32_t *waves, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Batching (not in the paper): advance many GA runs, typically on different

@@ -136,7 +136,7 @@ def lib():
                             C.POINTER(_i64), C.POINTER(GaStats)]
     L.pmp_ga_profile.argtypes = [_vp, _i32]
     L.pmp_ga_profile_read.argtypes = [_vp, C.POINTER(Profile), _vp]
-    L.pmp_ga_autotune.argtypes = [_vp, C.POINTER(_i32), _vp]
+    L.pmp_ga_autotune.argtypes = [_vp, C.POINTER(_i32), C.POINTER(_i32), _vp]
     L.pmp_batch_create.argtypes = [C.POINTER(_vp), _i32, C.POINTER(_vp)]
     L.pmp_batch_step.argtypes = [_vp, _i32, _vp]
     L.pmp_batch_check.argtypes = [_vp, C.POINTER(_i32), _vp]
@@ -403,9 +403,11 @@ def pmp_solve(d, p, population, group_size, generations, seed, saturation=0,
 
 
 def pmp_ga_autotune(ga, stream=None):
-    out = _i32()
-    _check(lib().pmp_ga_autotune(ga, C.byref(out), _stream(stream)), "pmp_ga_autotune")
-    return out.value
+    """Returns (clients per workgroup, waves per workgroup)."""
+    out, wv = _i32(), _i32()
+    _check(lib().pmp_ga_autotune(ga, C.byref(out), C.byref(wv), _stream(stream)),
+           "pmp_ga_autotune")
+    return out.value, wv.value
 
 
 def _handles(gas):

@@ -58,6 +58,8 @@ struct EvalArgs {
     long long c0;
     // very short scans expected (m + 1 <= 4 (p + 1)): two clients per chunk
     int32_t paired;
+    // waves per workgroup of k_eval: 4 (0 means 4), 8 or 16
+    int32_t waves;
 };
 
 // Reduced polynomial construction (k_hbp.hip).  t: the instance's tables.
@@ -112,7 +114,7 @@ hipError_t launch_sort_rows(const int32_t *d, int64_t ld, int32_t n, int32_t m,
 // e0/e1 (optional) are recorded at the kernel's start and end.
 // Workgroups of the evaluation kernel for W words per chromosome (reduced
 // or paired walk) that one CU holds at once.
-int eval_workgroups_per_cu(int W, bool reduced, bool paired);
+int eval_workgroups_per_cu(int W, bool reduced, bool paired, int waves = kEvalWaves);
 hipError_t launch_eval(const EvalArgs &a, hipStream_t s, hipEvent_t e0 = nullptr,
                        hipEvent_t e1 = nullptr);
 hipError_t launch_reduce(const EvalArgs &a, unsigned long long *fitness,

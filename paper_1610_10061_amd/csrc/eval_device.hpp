@@ -196,9 +196,11 @@ constexpr int eval_stage_words()
 }
 
 // Evaluate chromosome tile tc (64 chromosomes) on client tile ti and store
-// the tile's partial sums.  Called by a whole 256-thread workgroup;
+// the tile's partial sums.  Called by a whole workgroup of NV waves (each
+// walks every NV-th client of the tile; more waves share one staged tile,
+// so more of them are resident per CU and each walks fewer clients);
 // smask holds eval_stage_words<WD>() words (8-byte aligned), sred
-// 2 * kEvalWaves * 64 words.
+// 2 * NV * 64 words.
 //
 // R: the walk tables of the reduced polynomial (k_hbp.hip) instead of the
 // instance's: row i stops at position K_i - 1 at the latest (a.rlen) and
@@ -209,7 +211,7 @@ constexpr int eval_stage_words()
 // H (short scans, not with R): a wave walks its clients two at a time, the
 // first 32 entries of each row in one chunk (first_open2); the few rows
 // whose first open facility lies past entry 31 finish in walk_tail.
-template <int WD, bool R = false, bool H = false>
+template <int WD, bool R = false, bool H = false, int NV = kEvalWaves>
 __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
                                           uint32_t *smask,
                                           unsigned long long *sred)
@@ -238,7 +240,7 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
     const int col = pos < a.t.K ? pos : a.t.K - 1;
     const bool in_row = pos < a.t.K;
     const int last = i1 - 1;
-    const int row_first = (H && lane >= 32) ? min(i + kEvalWaves, last) : min(i, last);
+    const int row_first = (H && lane >= 32) ? min(i + NV, last) : min(i, last);
     uint32_t j_cur = a.t.pi[(int64_t)row_first * a.t.pitch + col];
     int32_t d_cur = 0;
     long long e_cur = 0;
@@ -254,7 +256,7 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
     // are replaced by 0 when stored.
     const uint32_t *g32 = reinterpret_cast<const uint32_t *>(a.masks);
     const int rows = min(kEvalTile, a.P - c0);
-    constexpr int kTot = kEvalTile * WD, kThreads = kEvalTile * kEvalWaves;
+    constexpr int kTot = kEvalTile * WD, kThreads = kEvalTile * NV;
     constexpr int kIt = (kTot + kThreads - 1) / kThreads;
     constexpr int kBatch = kIt < 16 ? kIt : 16;
     // active flag: also an unconditional load (of any valid byte when every
@@ -289,11 +291,11 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
     // Facility-major copy: wave v turns the tile's 64-bit words v, v + 4, ...
     // (one row per lane) into T[64 w + f], f = 0..63, by one transpose each,
     // in place once every wave has read its rows.
-    constexpr int NW = (WD / 2 + kEvalWaves - 1) / kEvalWaves;
+    constexpr int NW = (WD / 2 + NV - 1) / NV;
     uint32_t rlo[NW], rhi[NW];
 #pragma unroll
     for (int r = 0; r < NW; ++r) {
-        const int w = min(wave + r * kEvalWaves, W - 1);
+        const int w = min(wave + r * NV, W - 1);
         rlo[r] = smask[lane * SD + 2 * w];
         rhi[r] = smask[lane * SD + 2 * w + 1];
     }
@@ -301,14 +303,14 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
     // tile) from the rows just read: each wave counts the open facilities in
     // its words and looks for bits past m in the last word; wave 0 adds the
     // waves' counts up once the copy's barrier has passed.
-    __shared__ uint32_t s_ones[kEvalWaves][kEvalTile];
-    __shared__ uint32_t s_stray[kEvalWaves][kEvalTile];
+    __shared__ uint32_t s_ones[NV][kEvalTile];
+    __shared__ uint32_t s_stray[NV][kEvalTile];
     if (ti == 0) {
         uint32_t ones = 0, stray = 0;
         const uint64_t past = (a.t.m & 63) ? ~((1ull << (a.t.m & 63)) - 1ull) : 0ull;
 #pragma unroll
         for (int r = 0; r < NW; ++r) {
-            const int w = wave + r * kEvalWaves;
+            const int w = wave + r * NV;
             if (w < W) {
                 ones += __builtin_popcount(rlo[r]) + __builtin_popcount(rhi[r]);
                 if (w == W - 1)
@@ -323,7 +325,7 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
     const TransposeLanes tl(lane);
 #pragma unroll
     for (int r = 0; r < NW; ++r) {
-        const int w = wave + r * kEvalWaves;
+        const int w = wave + r * NV;
         if (w < W) {
             transpose64(rlo[r], rhi[r], lane, tl);
             sT[w * 64 + lane] = ((uint64_t)rhi[r] << 32) | rlo[r];
@@ -338,7 +340,7 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
     if (ti == 0 && wave == 0 && my_act) {
         uint32_t ones = 0, stray = 0;
 #pragma unroll
-        for (int v = 0; v < kEvalWaves; ++v) {
+        for (int v = 0; v < NV; ++v) {
             ones += s_ones[v][lane];
             stray |= s_stray[v][lane];
         }
@@ -351,10 +353,10 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
     unsigned long long acc = 0;
     uint32_t scn = 0;
     if constexpr (H) {
-        for (; i < i1; i += 2 * kEvalWaves) {
-            const int ib = i + kEvalWaves;
+        for (; i < i1; i += 2 * NV) {
+            const int ib = i + NV;
             const bool has_b = ib < i1;
-            const int na = min(i + 2 * kEvalWaves, last), nb = min(i + 3 * kEvalWaves, last);
+            const int na = min(i + 2 * NV, last), nb = min(i + 3 * NV, last);
             const int rown = lane >= 32 ? nb : na;
             const uint32_t j_nxt = a.t.pi[(int64_t)rown * a.t.pitch + col];
             const int32_t d_nxt = a.t.ds[(int64_t)rown * a.t.pitch + col];
@@ -386,8 +388,8 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
             d_cur = d_nxt;
         }
     }
-    for (; !H && i < i1; i += kEvalWaves) {
-        const int inext = min(i + kEvalWaves, last);
+    for (; !H && i < i1; i += NV) {
+        const int inext = min(i + NV, last);
         const uint32_t j_nxt = a.t.pi[(int64_t)inext * a.t.pitch + col];
         int32_t d_nxt = 0;
         long long e_nxt = 0;
@@ -460,14 +462,14 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
     }
 
     sred[wave * kEvalTile + lane] = acc;
-    sred[kEvalWaves * kEvalTile + wave * kEvalTile + lane] = scn;
+    sred[NV * kEvalTile + wave * kEvalTile + lane] = scn;
     __syncthreads();
     if (wave == 0 && my_act) {
         unsigned long long f = 0, s = 0;
 #pragma unroll
-        for (int w = 0; w < kEvalWaves; ++w) {
+        for (int w = 0; w < NV; ++w) {
             f += sred[w * kEvalTile + lane];
-            s += sred[kEvalWaves * kEvalTile + w * kEvalTile + lane];
+            s += sred[NV * kEvalTile + w * kEvalTile + lane];
         }
         const int64_t o = (int64_t)ti * a.P + my_c;
         a.part[o] = f;

@@ -10,11 +10,11 @@ namespace pmp {
 
 namespace {
 
-template <int WD, bool R, bool H>
-__global__ __launch_bounds__(kEvalTile *kEvalWaves) void k_eval(EvalArgs a)
+template <int WD, bool R, bool H, int NV>
+__global__ __launch_bounds__(kEvalTile *NV) void k_eval(EvalArgs a)
 {
     __shared__ __align__(16) uint32_t smask[eval_stage_words<WD>()];
-    __shared__ unsigned long long sred[2 * kEvalWaves * kEvalTile];
+    __shared__ unsigned long long sred[2 * NV * kEvalTile];
     // (A stopped GA run enqueues no-op generations: eval_tile checks the
     // stop flag once its loads are on their way.)
     // All chromosome tiles of one client tile on one XCD (workgroups are
@@ -25,7 +25,7 @@ __global__ __launch_bounds__(kEvalTile *kEvalWaves) void k_eval(EvalArgs a)
     if (logical >= ntiles)
         return;
     const int ti = logical / a.tiles_c;
-    eval_tile<WD, R, H>(a, ti, logical - ti * a.tiles_c, smask, sred);
+    eval_tile<WD, R, H, NV>(a, ti, logical - ti * a.tiles_c, smask, sred);
 }
 
 // fitness[c] (and scan[c]) = sum over client tiles of the partial sums.
@@ -48,22 +48,34 @@ __global__ __launch_bounds__(256) void k_reduce(
         scan[c] = s;
 }
 
-template <int WD, bool R, bool H>
-hipError_t launch_wd(const EvalArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
+template <int WD, bool R, bool H, int NV>
+hipError_t launch_nv(const EvalArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     const int tiles = a.tiles_c * a.tiles_i;
     const int grid = ((tiles + 7) / 8) * 8;
-    auto kernel = k_eval<WD, R, H>;
+    auto kernel = k_eval<WD, R, H, NV>;
     if (e0 && e1) {
         // events stamped by the dispatch itself: their interval is the
         // kernel's execution, without the gaps around it
-        hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(kEvalTile * kEvalWaves), 0,
-                              s, e0, e1, 0, a);
+        hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(kEvalTile * NV), 0, s, e0, e1, 0, a);
     } else {
-        hipLaunchKernelGGL(kernel, dim3(grid), dim3(kEvalTile * kEvalWaves), 0,
-                           s, a);
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(kEvalTile * NV), 0, s, a);
     }
     return hipGetLastError();
+}
+
+// Waves per workgroup: 4 (the default), 8 or 16; the reduced walk runs
+// with 4.
+template <int WD, bool R, bool H>
+hipError_t launch_wd(const EvalArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
+{
+    if constexpr (!R) {
+        if (a.waves == 8)
+            return launch_nv<WD, R, H, 8>(a, s, e0, e1);
+        if (a.waves == 16)
+            return launch_nv<WD, R, H, 16>(a, s, e0, e1);
+    }
+    return launch_nv<WD, R, H, kEvalWaves>(a, s, e0, e1);
 }
 
 }  // namespace
@@ -78,15 +90,15 @@ hipError_t launch_reduce(const EvalArgs &a, unsigned long long *fitness,
 
 namespace {
 
-template <int WD, bool R, bool H>
-int resident_wd()
+template <int WD, bool R, bool H, int NV>
+int resident_nv()
 {
     static std::atomic<int> cached{0};  // the same for every call: computed once
     int per_cu = cached.load(std::memory_order_relaxed);
     if (per_cu == 0) {
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, reinterpret_cast<const void *>(k_eval<WD, R, H>),
-                kEvalTile * kEvalWaves, 0) != hipSuccess ||
+                &per_cu, reinterpret_cast<const void *>(k_eval<WD, R, H, NV>),
+                kEvalTile * NV, 0) != hipSuccess ||
             per_cu < 1)
             per_cu = 1;
         cached.store(per_cu, std::memory_order_relaxed);
@@ -94,16 +106,28 @@ int resident_wd()
     return per_cu;
 }
 
+template <int WD, bool R, bool H>
+int resident_wd(int waves)
+{
+    if constexpr (!R) {
+        if (waves == 8)
+            return resident_nv<WD, R, H, 8>();
+        if (waves == 16)
+            return resident_nv<WD, R, H, 16>();
+    }
+    return resident_nv<WD, R, H, kEvalWaves>();
+}
+
 }  // namespace
 
-int eval_workgroups_per_cu(int W, bool reduced, bool paired)
+int eval_workgroups_per_cu(int W, bool reduced, bool paired, int waves)
 {
     const int w2 = 2 * W;
 #define PMP_EVAL_WD(N)                                                           \
     if (w2 <= N)                                                                 \
-        return reduced ? resident_wd<N, true, false>()                            \
-                       : (paired ? resident_wd<N, false, true>()                  \
-                                 : resident_wd<N, false, false>());
+        return reduced ? resident_wd<N, true, false>(waves)                       \
+                       : (paired ? resident_wd<N, false, true>(waves)             \
+                                 : resident_wd<N, false, false>(waves));
     PMP_EVAL_WD(2)
     PMP_EVAL_WD(4)
     PMP_EVAL_WD(8)

@@ -293,12 +293,17 @@ __global__ __launch_bounds__(64 * kGaWaves) void k_batch_init(BatchArgs B)
         ga_init_one(it.g, cg - B.chrom0[b], threadIdx.x & 63, sw[wave_id()]);
 }
 
+// The batch evaluation runs 16 waves per workgroup (one staged chromosome
+// tile shared by more resident waves, each walking fewer clients: the
+// fastest shape of the single-run evaluation too).
+constexpr int kBatchEvalWaves = 16;
+
 template <int WD>
-__global__ __launch_bounds__(kEvalTile *kEvalWaves) void k_batch_eval(BatchArgs B, int k,
-                                                                      int buf)
+__global__ __launch_bounds__(kEvalTile *kBatchEvalWaves) void k_batch_eval(BatchArgs B, int k,
+                                                                           int buf)
 {
     __shared__ __align__(16) uint32_t smask[eval_stage_words<WD>()];
-    __shared__ unsigned long long sred[2 * kEvalWaves * kEvalTile];
+    __shared__ unsigned long long sred[2 * kBatchEvalWaves * kEvalTile];
     const int ntiles = B.tile0[B.count];
     // blocks are dealt to the 8 XCDs round-robin: give XCD x a contiguous
     // eighth of the tile range
@@ -317,9 +322,9 @@ __global__ __launch_bounds__(kEvalTile *kEvalWaves) void k_batch_eval(BatchArgs 
     const int ti = local / e.tiles_c;
     // the walk each instance's scan lengths call for (uniform per workgroup)
     if (e.paired)
-        eval_tile<WD, false, true>(e, ti, local - ti * e.tiles_c, smask, sred);
+        eval_tile<WD, false, true, kBatchEvalWaves>(e, ti, local - ti * e.tiles_c, smask, sred);
     else
-        eval_tile<WD>(e, ti, local - ti * e.tiles_c, smask, sred);
+        eval_tile<WD, false, false, kBatchEvalWaves>(e, ti, local - ti * e.tiles_c, smask, sred);
 }
 
 __global__ __launch_bounds__(64 * kGaWaves) void k_batch_stage(BatchArgs B, int k)
@@ -370,12 +375,12 @@ hipError_t batch_kernels_wd(const BatchArgs &b, int nchrom, int ntiles, int ngro
     const dim3 tiles((unsigned)(((ntiles + 7) / 8) * 8));
     for (int gen = 0; gen < generations; ++gen) {
         hipLaunchKernelGGL(k_batch_init, waves, dim3(64 * kGaWaves), 0, s, b);
-        hipLaunchKernelGGL(k_batch_eval<WD>, tiles, dim3(kEvalTile * kEvalWaves), 0, s,
+        hipLaunchKernelGGL(k_batch_eval<WD>, tiles, dim3(kEvalTile * kBatchEvalWaves), 0, s,
                            b, -1, 0);
         for (int k = 0; k <= b.max_S; ++k) {
             hipLaunchKernelGGL(k_batch_stage, waves, dim3(64 * kGaWaves), 0, s, b, k);
             if (k < b.max_S)
-                hipLaunchKernelGGL(k_batch_eval<WD>, tiles, dim3(kEvalTile * kEvalWaves),
+                hipLaunchKernelGGL(k_batch_eval<WD>, tiles, dim3(kEvalTile * kBatchEvalWaves),
                                    0, s, b, k, (k & 1) ^ 1);
         }
         hipLaunchKernelGGL(k_batch_best, dim3((unsigned)ngroups), dim3(256), 0, s, b);

@@ -96,7 +96,27 @@ int paired_scans(int m, int p)
 // client tiles that still give every CU of the device about 2.75
 // workgroups, or that fill every CU's resident slots once when it holds
 // fewer than 3.5, so that no workgroup waits for a slot.
-int clients_per_block(int n, int P, int m, int p, int W, bool reduced = false)
+// Waves per workgroup of the evaluation kernel (4, 8 or 16 waves share one
+// staged chromosome tile).  PMP_EVAL_WAVES forces it.
+int eval_waves(int n, int P, int m, int p, int W)
+{
+    (void)n;
+    (void)P;
+    (void)m;
+    (void)p;
+    (void)W;
+    const int forced = env_int("PMP_EVAL_WAVES", 0);
+    if (forced == 4 || forced == 8 || forced == 16)
+        return forced;
+    // 16 waves were fastest on every measured shape: G900 88.7 -> 98.3 G
+    // evaluations/s against 4; E5000 p = 10 / 100 / 500 1.63 / 0.224 /
+    // 0.067 -> 0.95 / 0.154 / 0.050 ms (more waves resident per CU for the
+    // same staged tile, and fewer clients in each wave's chain)
+    return 16;
+}
+
+int clients_per_block(int n, int P, int m, int p, int W, bool reduced = false,
+                      int waves = kEvalWaves)
 {
     const int forced = env_int("PMP_CLIENTS_PER_BLOCK", 0);
     if (forced > 0)
@@ -106,7 +126,7 @@ int clients_per_block(int n, int P, int m, int p, int W, bool reduced = false)
     if (long_scans) {
         long cpb = (long)n * tiles_c / 1024;
         cpb = std::min(64L, std::max(4L, cpb));
-        return (int)(((cpb + 3) / 4) * 4);
+        return (int)(((cpb + waves - 1) / waves) * waves);
     }
     const bool paired = paired_scans(m, p) != 0;
     static std::atomic<int> cus_of[64];  // per device, queried once
@@ -119,7 +139,7 @@ int clients_per_block(int n, int P, int m, int p, int W, bool reduced = false)
     }
     if (cus < 1)
         cus = 256;
-    const long slots = (long)cus * eval_workgroups_per_cu(W, reduced, paired);
+    const long slots = (long)cus * eval_workgroups_per_cu(W, reduced, paired, waves);
     // When the CUs hold fewer than 3.5 workgroups each, fill the slots once;
     // else aim at about 2.75 per CU (G900: 20 clients per workgroup measured
     // 2 % faster than 16, 12 and 32 slower)
@@ -132,7 +152,7 @@ int clients_per_block(int n, int P, int m, int p, int W, bool reduced = false)
     // for each of the 4 waves, or one wave's extra client sets the
     // workgroup's time.  (When the slots are the limit, rounding down would
     // add a client tile and a partial second round of workgroups.)
-    const long unit = paired ? 8 : 4;
+    const long unit = (paired ? 2 : 1) * waves;
     if (cpb < 64 && want < slots && cpb >= unit)
         cpb -= cpb % unit;
     return (int)cpb;
@@ -260,6 +280,8 @@ struct pmp_ga {
     pmp_instance *inst = nullptr;
     pmp_ga_params prm{};
     int NB = 0, lg = 0, X = 0, Y = 0, TI = 0, cpb = 0;
+    int waves = kEvalWaves;       // waves per workgroup of the population's evaluation
+    int spec_waves = kEvalWaves;  // and of the mutants' evaluation
     uint64_t *cur[2] = {nullptr, nullptr}, *off[2] = {nullptr, nullptr};
     unsigned long long *fit[2] = {nullptr, nullptr};
     uint8_t *ok[2] = {nullptr, nullptr};
@@ -1196,7 +1218,8 @@ pmp_status pmp_eval_population(pmp_instance *inst, const uint64_t *masks,
     a.active = nullptr;
     a.done = nullptr;
     a.err = inst->err;
-    a.clients_per_block = clients_per_block(inst->n, P, inst->m, inst->p, inst->W);
+    a.waves = eval_waves(inst->n, P, inst->m, inst->p, inst->W);
+    a.clients_per_block = clients_per_block(inst->n, P, inst->m, inst->p, inst->W, false, a.waves);
     a.tiles_c = (P + kEvalTile - 1) / kEvalTile;
     a.tiles_i = (inst->n + a.clients_per_block - 1) / a.clients_per_block;
     if (scheme == PMP_EVAL_PER_CLIENT)
@@ -1270,7 +1293,8 @@ pmp_status pmp_eval_population_noalloc(pmp_instance *inst, const uint64_t *masks
     a.done = nullptr;
     a.err = inst->err;
     a.tiles_c = (P + kEvalTile - 1) / kEvalTile;
-    int64_t cpb = clients_per_block(inst->n, P, inst->m, inst->p, inst->W);
+    a.waves = eval_waves(inst->n, P, inst->m, inst->p, inst->W);
+    int64_t cpb = clients_per_block(inst->n, P, inst->m, inst->p, inst->W, false, a.waves);
     int64_t ti = ((int64_t)inst->n + cpb - 1) / cpb;
     const int64_t ti_max = (int64_t)(kNoAllocCells / (size_t)P);  // >= 1
     if (ti > ti_max) {  // wider client tiles, so that ti x P cells fit
@@ -1370,7 +1394,9 @@ pmp_status pmp_ga_create(pmp_instance *inst, const pmp_ga_params *prm,
     ga->lg = lg;
     ga->X = prm->crossover_iters > 0 ? prm->crossover_iters : lg;
     ga->Y = prm->mutation_iters > 0 ? prm->mutation_iters : lg;
-    ga->cpb = clients_per_block(inst->n, P, inst->m, inst->p, inst->W);
+    ga->waves = eval_waves(inst->n, P, inst->m, inst->p, inst->W);
+    ga->spec_waves = ga->waves;
+    ga->cpb = clients_per_block(inst->n, P, inst->m, inst->p, inst->W, false, ga->waves);
     ga->TI = (inst->n + ga->cpb - 1) / ga->cpb;
     const size_t W = inst->W, PW = (size_t)P * W;
     bool bad = false;
@@ -1459,6 +1485,7 @@ EvalArgs ga_eval_args(const pmp_ga *ga, const GaArgs &g, int buf)
     a.clients_per_block = ga->cpb;
     a.tiles_c = (g.P + kEvalTile - 1) / kEvalTile;
     a.tiles_i = ga->TI;
+    a.waves = ga->waves;
     return a;
 }
 
@@ -1495,6 +1522,7 @@ hipError_t ga_eval(pmp_ga *ga, const GaArgs &g, int buf, hipStream_t s, bool mut
         a.tiles_c = (a.P + kEvalTile - 1) / kEvalTile;
         a.clients_per_block = ga->spec_cpb;
         a.tiles_i = ga->spec_ti;
+        a.waves = ga->spec_waves;
     }
     return launch_eval(a, s, e0, e1);
 }
@@ -1785,7 +1813,7 @@ pmp_status pmp_ga_profile_read(pmp_ga *ga, pmp_profile *out, void *stream)
     return PMP_OK;
 }
 
-pmp_status pmp_ga_autotune(pmp_ga *ga, int32_t *chosen, void *stream)
+pmp_status pmp_ga_autotune(pmp_ga *ga, int32_t *clients, int32_t *waves, void *stream)
 {
     if (!ga)
         return fail(PMP_EINVAL, "ga is NULL");
@@ -1797,11 +1825,12 @@ pmp_status pmp_ga_autotune(pmp_ga *ga, int32_t *chosen, void *stream)
         return fail(PMP_EINVAL, "autotune a GA before its first generation");
     const pmp_instance *inst = ga->inst;
     const int P = ga->prm.population, n = inst->n;
-    int best = clients_per_block(n, P, inst->m, inst->p, inst->W);
-    const bool forced = env_int("PMP_CLIENTS_PER_BLOCK", 0) > 0;
+    // the shape's default: the rule's waves and clients per workgroup
+    int best = ga->cpb, best_w = ga->waves;
+    const bool forced = env_int("PMP_CLIENTS_PER_BLOCK", 0) > 0 || env_int("PMP_EVAL_WAVES", 0) > 0;
     // measured choices are shared by runs of similar shape
     static std::mutex mu;
-    static std::map<std::tuple<int, int, int, int>, int> cache;
+    static std::map<std::tuple<int, int, int, int>, std::pair<int, int>> cache;
     const auto key = std::make_tuple((int)std::lround(std::log((double)n) / std::log(1.15)),
                                      2 * inst->W,
                                      (int)std::lround(std::log((inst->m + 1.0) / (inst->p + 1.0)) /
@@ -1812,7 +1841,8 @@ pmp_status pmp_ga_autotune(pmp_ga *ga, int32_t *chosen, void *stream)
         std::lock_guard<std::mutex> lock(mu);
         auto it = cache.find(key);
         if (it != cache.end()) {
-            best = it->second;
+            best = it->second.first;
+            best_w = it->second.second;
             cached = true;
         }
     }
@@ -1821,6 +1851,7 @@ pmp_status pmp_ga_autotune(pmp_ga *ga, int32_t *chosen, void *stream)
         GaArgs g = ga->args();
         HIP_TRY(launch_ga_init(g, s));
         const int cands[] = {4, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512};
+        const int wcands[] = {16, 8, 4};
         const int max_ti = (n + 3) / 4;
         unsigned long long *part = nullptr;
         uint32_t *spart = nullptr;
@@ -1835,24 +1866,16 @@ pmp_status pmp_ga_autotune(pmp_ga *ga, int32_t *chosen, void *stream)
         // the shape's default is timed first and is only replaced by a
         // candidate at least 3 % faster: back-to-back launches of the
         // evaluation alone are a noisy proxy for a whole generation
-        const int dflt = best;
+        const int dflt = best, dflt_w = best_w;
         float best_ms = 1e30f;
-        int last_ti = -1;
-        for (int k = -1; k < (int)(sizeof cands / sizeof cands[0]); ++k) {
-            const int cpb = k < 0 ? dflt : cands[k];
-            if (e != hipSuccess)
-                break;
-            if (k >= 0 && cpb > ((n + 3) / 4) * 4 && last_ti == 1)
-                break;
+        auto time_it = [&](int cpb, int wv) -> float {
             EvalArgs a = ga_eval_args(ga, g, 0);
             a.done = nullptr;
             a.part = part;
             a.spart = spart;
             a.clients_per_block = cpb;
             a.tiles_i = (n + cpb - 1) / cpb;
-            if (k >= 0 && (a.tiles_i == last_ti || a.tiles_i == (n + dflt - 1) / dflt))
-                continue;
-            last_ti = a.tiles_i;
+            a.waves = wv;
             e = launch_eval(a, s);  // warm-up
             if (e == hipSuccess)
                 e = hipEventRecord(e0, s);
@@ -1865,9 +1888,26 @@ pmp_status pmp_ga_autotune(pmp_ga *ga, int32_t *chosen, void *stream)
             float ms = 0;
             if (e == hipSuccess)
                 e = hipEventElapsedTime(&ms, e0, e1);
-            if (e == hipSuccess && (k < 0 || ms < 0.97f * best_ms)) {
-                best_ms = ms;
-                best = cpb;
+            return e == hipSuccess ? ms : 1e30f;
+        };
+        best_ms = time_it(dflt, dflt_w);
+        for (int wv : wcands) {
+            int last_ti = -1;
+            for (int cpb : cands) {
+                if (e != hipSuccess)
+                    break;
+                const int ti = (n + cpb - 1) / cpb;
+                if (ti == last_ti || cpb > max_ti * 4 || (wv == dflt_w && ti == (n + dflt - 1) / dflt))
+                    continue;
+                last_ti = ti;
+                const float ms = time_it(cpb, wv);
+                if (ms < 0.97f * best_ms) {
+                    best_ms = ms;
+                    best = cpb;
+                    best_w = wv;
+                }
+                if (ti == 1)
+                    break;
             }
         }
         if (e0)
@@ -1879,8 +1919,10 @@ pmp_status pmp_ga_autotune(pmp_ga *ga, int32_t *chosen, void *stream)
         if (e != hipSuccess)
             return fail(PMP_EDEVICE, "autotune: %s", hipGetErrorString(e));
         std::lock_guard<std::mutex> lock(mu);
-        cache[key] = best;
+        cache[key] = std::make_pair(best, best_w);
     }
+    ga->waves = best_w;
+    ga->spec_waves = best_w;
     if (best != ga->cpb) {
         const int ti = (n + best - 1) / best;
         dfree(ga->part);
@@ -1889,18 +1931,20 @@ pmp_status pmp_ga_autotune(pmp_ga *ga, int32_t *chosen, void *stream)
             return fail(PMP_ENOMEM, "GA partial sums for %d client tiles", ti);
         ga->cpb = best;
         ga->TI = ti;
-        if (ga->gexec) {
-            (void)hipGraphExecDestroy(ga->gexec);
-            ga->gexec = nullptr;
-        }
         if (ga->self) {
             ga->self->release();
             delete ga->self;
             ga->self = nullptr;
         }
     }
-    if (chosen)
-        *chosen = best;
+    if (ga->gexec) {  // captured with the old tile
+        (void)hipGraphExecDestroy(ga->gexec);
+        ga->gexec = nullptr;
+    }
+    if (clients)
+        *clients = best;
+    if (waves)
+        *waves = best_w;
     return PMP_OK;
 }
 
@@ -2457,7 +2501,8 @@ pmp_status pmp_exhaustive(pmp_instance *inst, uint64_t *best_mask, int64_t *best
     a.active = nullptr;
     a.done = nullptr;
     a.err = inst->err;
-    a.clients_per_block = clients_per_block(n, B, m, p, W);
+    a.waves = eval_waves(n, B, m, p, W);
+    a.clients_per_block = clients_per_block(n, B, m, p, W, false, a.waves);
     a.tiles_c = (B + kEvalTile - 1) / kEvalTile;
     a.tiles_i = (n + a.clients_per_block - 1) / a.clients_per_block;
     unsigned long long *d_binom = nullptr, *fit = nullptr, *bc = nullptr, *run = nullptr;

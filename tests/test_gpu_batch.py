@@ -150,9 +150,9 @@ def test_autotune_keeps_results(pm):
     d = gi.euclid_instance(700, 5)
     inst = pm.Instance(d, 40)
     a = pm.GA(inst, 512, 128, 3, seed=1)
-    chosen = a.autotune()
+    chosen, waves = a.autotune()
     # the shape's default tile, or one of the timed candidates
-    assert 1 <= chosen <= 700
+    assert 1 <= chosen <= 700 and waves in (4, 8, 16)
     b = pm.GA(inst, 512, 128, 3, seed=1)
     os.environ["PMP_CLIENTS_PER_BLOCK"] = "4"
     try:
@@ -166,12 +166,12 @@ def test_autotune_keeps_results(pm):
         a.autotune()  # after the first generation
 
 
-def test_full_batch_config_sampled(pm):
+def test_full_batch_config(pm):
     """The ragged 256-instance configuration (n = m log-uniform in
     [100, 2000], p uniform in [5, n/4], half graphs with 4n edges, half
     Euclidean, population 256) stepped in one launch per call, as the
-    benchmark runs it; sampled runs are compared with the same runs stepped
-    alone and two with the oracle."""
+    benchmark runs it.  Every run is compared with the same run stepped
+    alone, and 16 runs spread over the range of n with the oracle GA."""
     specs = gi.batch_specs(256)
     _say("generating 256 instances")
     ds = [gi.batch_instance(s) for s in specs]
@@ -187,18 +187,24 @@ def test_full_batch_config_sampled(pm):
     batch = pm.Batch(gas)
     batch.step(G)
     batch.check()
-    pick = [0, 1, 2, 3, 100, 101, 254, 255]
-    small = sorted(range(256), key=lambda b: specs[b]["n"])[:2]
-    for b in pick + small:
+    by_n = sorted(range(256), key=lambda b: specs[b]["n"])
+    # 16 runs at evenly spaced ranks of n, smallest and largest included
+    with_oracle = {by_n[round(k * 255 / 15)] for k in range(16)}
+    for b in range(256):
         s = specs[b]
         ref_inst = pm.Instance(ds[b], s["p"])
         ref = pm.GA(ref_inst, 256, 256, 100, seed=b)
         ref.step(G)
         a = _state(gas[b])
         _assert_same(a, _state(ref))
-        if b in small:
+        ref.close()
+        ref_inst.close()
+        if b in with_oracle:
+            _say("oracle run", b, "n", s["n"], "p", s["p"], s["kind"])
             st = oracle.GaState(s["n"], s["n"], s["p"], 256, 256, 100, b)
             oracle.ga_run(ds[b], st, G)
             np.testing.assert_array_equal(a[0], st.pop)
+            np.testing.assert_array_equal(a[1], st.fit)
             assert a[5] == st.best_cost
+            assert a[6]["chromosome_evals"] == st.state[oracle.ST_CHROM_EVALS]
     batch.close()

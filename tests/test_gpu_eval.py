@@ -132,9 +132,11 @@ def test_example1_all_pairs_match_printed_costs(pm):
 
 
 @pytest.mark.parametrize("p", [10, 100, 500])
-def test_e5000_full_size_sampled(pm, p):
-    """Full E5000 shape (P = 4096) in the benchmark's launch configuration;
-    a sample of chromosomes and of table rows is recomputed by the oracle."""
+def test_e5000_full_size(pm, p):
+    """Full E5000 shape (P = 4096) in the benchmark's launch configuration:
+    every chromosome's fitness against the oracle's direct minimum, scan
+    lengths of a sample (the oracle counts them in O(m) per client), and a
+    sample of table rows."""
     import torch
     d = _e5000()
     _say("case e5000 p", p)
@@ -145,8 +147,9 @@ def test_e5000_full_size_sampled(pm, p):
     scan = torch.empty(4096, dtype=torch.int64, device="cuda")
     pm.pmp_eval_population(inst.handle, dm, fit, scan)
     fit, scan = fit.cpu().numpy(), scan.cpu().numpy()
+    np.testing.assert_array_equal(fit, oracle.objective(d, masks, p))
     rng = np.random.default_rng(p)
-    pick = np.concatenate([[0, 4095], rng.choice(4096, 30, replace=False)])
+    pick = np.concatenate([[0, 4095], rng.choice(4096, 46, replace=False)])
     want, wscan = oracle.objective(d, masks[pick], p, scan=True)
     np.testing.assert_array_equal(fit[pick], want)
     np.testing.assert_array_equal(scan[pick], wscan)
@@ -159,6 +162,41 @@ def test_e5000_full_size_sampled(pm, p):
     np.testing.assert_array_equal(pi[rows].astype(np.int32), opi)
     np.testing.assert_array_equal(de[rows], ode)
     np.testing.assert_array_equal(ds[rows], ods)
+
+
+@pytest.mark.parametrize("p", [10, 500])
+def test_e5000_evolved_population(pm, p):
+    """The population the E5000 benchmark times after evolving it (GA with
+    P = 4096, NT = 256 for 20 generations): the evaluation of all 4096
+    chromosomes against the oracle, and against the GA's own fitness."""
+    import torch
+    d = _e5000()
+    _say("case e5000 evolved p", p)
+    inst = pm.Instance(torch.from_numpy(d).cuda(), p)
+    ga = pm.GA(inst, 4096, 256, 20, 0)
+    ga.step(20)
+    pop, gfit, _, _ = ga.state()
+    dm = torch.from_numpy(pop.view(np.int64)).cuda().view(torch.uint64)
+    fit = torch.empty(4096, dtype=torch.int64, device="cuda")
+    scan = torch.empty(4096, dtype=torch.int64, device="cuda")
+    pm.pmp_eval_population(inst.handle, dm, fit, scan)
+    fit, scan = fit.cpu().numpy(), scan.cpu().numpy()
+    want = oracle.objective(d, pop, p)
+    np.testing.assert_array_equal(fit, want)
+    np.testing.assert_array_equal(gfit, want)
+    pick = np.random.default_rng(p + 1).choice(4096, 24, replace=False)
+    _, wscan = oracle.objective(d, pop[pick], p, scan=True)
+    np.testing.assert_array_equal(scan[pick], wscan)
+
+
+def test_e5000_ga_generation_bitwise(pm):
+    """One generation of the E5000 GA configuration (p = 10, the long-scan
+    walk; P = 4096, NT = 256, NB = 16) against the oracle GA, bit for bit:
+    population, fitness, group bests, global best and counters."""
+    d = _e5000()
+    _say("case e5000 GA generation p 10")
+    from test_gpu_ga import _compare
+    _compare(pm, d, 10, 4096, 256, 200, seed=0, steps=[1])
 
 
 _E5000 = {}
@@ -182,6 +220,41 @@ def test_eval_at_the_facility_limit(pm, m, p):
     print("case m", m, "p", p, "n", n, "P", P, flush=True)
     inst = pm.Instance(d, p)
     np.testing.assert_array_equal(inst.eval(masks), oracle.objective(d, masks, p))
+
+
+@pytest.mark.parametrize("waves", ["4", "8", "16"])
+@pytest.mark.parametrize("name,P", [("g900", 300), ("euclid_129", 130), ("wide_2x700", 70),
+                                    ("ties_p1", 65), ("mixed_rows", 129)])
+def test_waves_per_workgroup(pm, name, P, waves):
+    """4, 8 or 16 waves sharing one staged chromosome tile: same results,
+    for the single and paired walks and several tile sizes."""
+    d, p = INSTANCES[name]()
+    n, m = d.shape
+    masks = gi.random_population(P, m, p, seed=P + 7)
+    want, wscan = oracle.objective(d, masks, p, scan=True)
+    old = {k: os.environ.get(k) for k in ("PMP_EVAL_WAVES", "PMP_CLIENTS_PER_BLOCK",
+                                          "PMP_EVAL_PAIRED")}
+    try:
+        os.environ["PMP_EVAL_WAVES"] = waves
+        for cpb, paired in (("0", "0"), ("0", "1"), ("5", "0"), ("37", "1"), ("900", "0")):
+            _say("case", name, "P", P, "waves", waves, "clients", cpb, "paired", paired)
+            if cpb == "0":
+                os.environ.pop("PMP_CLIENTS_PER_BLOCK", None)
+            else:
+                os.environ["PMP_CLIENTS_PER_BLOCK"] = cpb
+            os.environ["PMP_EVAL_PAIRED"] = paired
+            inst = pm.Instance(d, p)
+            fit = np.zeros(P, np.int64)
+            scan = np.zeros(P, np.int64)
+            pm.pmp_eval_population(inst.handle, masks, fit, scan)
+            np.testing.assert_array_equal(fit, want)
+            np.testing.assert_array_equal(scan, wscan)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
 
 
 def test_tile_shape_does_not_change_results(pm):

@@ -32,13 +32,15 @@ def pm():
 # attempt instead of at once, one persistent cooperative kernel, and the same
 # with a grid of 8 workgroups (every phase loops)
 MODES = {"graph": {"PMP_GA_GRAPH_GENS": "2"},
+         "graph_16_waves": {"PMP_GA_GRAPH_GENS": "2", "PMP_EVAL_WAVES": "16"},
+         "kernels_8_waves": {"PMP_GA_MODE": "kernels", "PMP_EVAL_WAVES": "8"},
          "graph_mutants_1_wave": {"PMP_GA_GRAPH_GENS": "2", "PMP_MUTANTS_PER_WAVE": "64"},
          "kernels": {"PMP_GA_MODE": "kernels"},
          "sequential": {"PMP_GA_GRAPH_GENS": "2", "PMP_GA_SPEC": "0"},
          "persistent": {"PMP_GA_MODE": "persistent"},
          "persistent_8wg": {"PMP_GA_MODE": "persistent", "PMP_GA_BLOCKS": "8"}}
 _ENV = ("PMP_GA_MODE", "PMP_GA_BLOCKS", "PMP_GA_GRAPH_GENS", "PMP_GA_SPEC",
-        "PMP_MUTANTS_PER_WAVE")
+        "PMP_MUTANTS_PER_WAVE", "PMP_EVAL_WAVES")
 
 
 @pytest.fixture(params=list(MODES))
@@ -212,7 +214,7 @@ def test_mutation_cycle_at_once_counts(pm, mode):
     algorithm's own counters match the oracle either way (_compare)."""
     d = gi.graph_instance(100, 200, 3)
     s = _compare(pm, d, 5, 128, 32, 10, seed=2, steps=[3])
-    if mode in ("graph", "graph_mutants_1_wave", "kernels"):
+    if mode in ("graph", "graph_mutants_1_wave", "kernels", "graph_16_waves", "kernels_8_waves"):
         assert s["speculative_evals"] > 0
     else:
         assert s["speculative_evals"] == 0

@@ -85,10 +85,17 @@ def test_model_init_matches_oracle(pm):
         np.testing.assert_array_equal(model.params(), OL.init_params(seed))
 
 
-def _rel_ok(got, ref, tol=2e-2):
-    """|got - ref| <= tol (|ref| + mean |ref|) elementwise."""
-    scale = np.abs(ref).mean() + 1e-30
-    return np.abs(got - ref) <= tol * (np.abs(ref) + scale)
+def _rel_ok(got, ref, tol=2e-2, floor_frac=0.1):
+    """Relative tolerance tol where |ref| >= floor = floor_frac * mean |ref|,
+    and |got - ref| <= tol * floor below it.  A score near zero is a
+    difference of large terms: one first-layer activation whose FP32 sum
+    rounds to the other neighbouring BF16 value than its float64 sum moves
+    the score by about |w3_k| 2^-8 |h_k|, however small the score is, so
+    a pure relative bound cannot hold there."""
+    floor = floor_frac * np.abs(ref).mean() + 1e-30
+    err = np.abs(got - ref)
+    big = np.abs(ref) >= floor
+    return np.where(big, err <= tol * np.abs(ref), err <= tol * floor)
 
 
 @pytest.mark.parametrize("rows", [1, 17, 1000, 4099])
@@ -174,12 +181,20 @@ def _learned_ga(pm, d, p, P, NT, G, seed, model, **kw):
     return inst, ga
 
 
-@pytest.mark.parametrize("case", ["graph120", "euclid260"])
+@pytest.mark.parametrize("case", ["graph120", "euclid260", "euclid2000_config"])
 def test_learned_generation0_against_oracle(pm, case):
+    sample = None
     if case == "graph120":
         d, p, P, NT, C, L, expl = gi.graph_instance(120, 240, 3), 9, 64, 16, 16, 4, 300
-    else:
+    elif case == "euclid260":
         d, p, P, NT, C, L, expl = gi.euclid_instance(260, 4), 26, 32, 32, 24, 3, 0
+    else:
+        # the learned workload's configuration: Euclidean n = m = 2000, p =
+        # 200, population 1024 (NT 256), 64 candidates, 4 scored swaps, 5 %
+        # exploration; 24 chromosomes checked swap by swap
+        d, p, P, NT, C, L, expl = gi.euclid_instance(2000, 100), 200, 1024, 256, 64, 4, 50
+        sample = np.concatenate([[0, P - 1], np.random.default_rng(5).choice(
+            np.arange(1, P - 1), 22, replace=False)])
     n, m = d.shape
     seed, G = 21, 50
     _say("learned generation 0", case)
@@ -194,7 +209,7 @@ def test_learned_generation0_against_oracle(pm, case):
     pbits = gi.unpack_masks(parent, m)
     static = OL.static_sums(d, p)
     checked = 0
-    for c in range(P):
+    for c in (range(P) if sample is None else sample):
         feats = OL.features(d, pbits[c], p, 0.0, static)
         cands = OL.candidates(seed, 0, c, pbits[c], p, C)
         rows = np.stack([np.concatenate([feats[j], feats[k]]) for j, k in cands])
@@ -224,6 +239,9 @@ def test_learned_generation0_against_oracle(pm, case):
             assert rep["target"][r] == OL.target(cf - pfit[c], pfit[c], p)
             improved = cf < pfit[c]
             checked += 1
+    if sample is not None:
+        assert checked >= len(sample)
+        return
     assert checked >= P
     _, cost, stats = ga.best()
     assert stats["swap_tried"] == checked
