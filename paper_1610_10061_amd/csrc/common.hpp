@@ -236,6 +236,13 @@ hipError_t launch_fold(const unsigned long long *bc, const int *bi, int nblk,
                        unsigned long long r0, unsigned long long *run, hipStream_t s);
 
 hipError_t launch_ga_init(const GaArgs &g, hipStream_t s);
+// A crossover stage fused with the evaluation of its offspring (a: the
+// evaluation's arguments; e0/e1 optional events stamped by the dispatch),
+// for chromosomes of W <= 16 words (ga_stage_eval_fits).
+bool ga_stage_eval_fits(int W);
+hipError_t launch_ga_stage_eval(const GaArgs &g, const EvalArgs &a, int in, int prev,
+                                int index, hipStream_t s, hipEvent_t e0 = nullptr,
+                                hipEvent_t e1 = nullptr);
 hipError_t launch_ga_stage(const GaArgs &g, int in, int prev, int op,
                            int index, hipStream_t s);
 hipError_t launch_ga_best(const GaArgs &g, int fb, hipStream_t s);

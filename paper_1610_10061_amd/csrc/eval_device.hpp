@@ -211,10 +211,50 @@ constexpr int eval_stage_words()
 // H (short scans, not with R): a wave walks its clients two at a time, the
 // first 32 entries of each row in one chunk (first_open2); the few rows
 // whose first open facility lies past entry 31 finish in walk_tail.
-template <int WD, bool R = false, bool H = false, int NV = kEvalWaves>
+//
+// PRE: the caller has already staged the tile's masks in smask (rows at
+// stride WD + 1, zero past 2W words) and the chromosomes' active flags in
+// sact, and synchronised the workgroup (the stage steps fused with the
+// evaluation make the offspring right there).
+// Clients whose first 64-entry chunk a wave of the single-client walk has
+// in flight (loaded up to this many clients ahead, so that the wait for a
+// client's chunk falls several clients' work after its load).
+constexpr int kPrefetch = 4;
+
+// The first chunks (Pi' entry and D' value of this lane's position) of the
+// first clients a lane's wave walks in client tile ti: kPrefetch clients for
+// the single-client walk, one pair for the paired walk (H: lanes 32-63 hold
+// the pair's second client).  Always in bounds: rows clamped into the tile,
+// columns below K.
+struct FirstChunks {
+    uint32_t j[kPrefetch];
+    int32_t d[kPrefetch];
+};
+
+template <bool H, int NV>
+__device__ __forceinline__ void eval_first_chunks(const EvalArgs &a, int ti, int lane, int wave,
+                                                  FirstChunks &fc)
+{
+    const int i0 = ti * a.clients_per_block;
+    const int i1 = min(a.t.n, i0 + a.clients_per_block);
+    const int i = i0 + wave, last = i1 - 1;
+    const int pos = H ? (lane & 31) : lane;
+    const int col = pos < a.t.K ? pos : a.t.K - 1;
+    constexpr int Q = H ? 1 : kPrefetch;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int row = (H && lane >= 32) ? min(i + NV, last) : min(i + NV * q, last);
+        fc.j[q] = a.t.pi[(int64_t)row * a.t.pitch + col];
+        fc.d[q] = a.t.ds[(int64_t)row * a.t.pitch + col];
+    }
+}
+
+template <int WD, bool R = false, bool H = false, int NV = kEvalWaves, bool PRE = false>
 __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
                                           uint32_t *smask,
-                                          unsigned long long *sred)
+                                          unsigned long long *sred,
+                                          const uint8_t *sact = nullptr,
+                                          const FirstChunks *pre = nullptr)
 {
     constexpr int SD = WD + 1;  // staged row stride
     const int c0 = tc * kEvalTile;
@@ -241,16 +281,35 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
     const bool in_row = pos < a.t.K;
     const int last = i1 - 1;
     const int row_first = (H && lane >= 32) ? min(i + NV, last) : min(i, last);
-    uint32_t j_cur = a.t.pi[(int64_t)row_first * a.t.pitch + col];
-    int32_t d_cur = 0;
+    // queue of the next clients' first chunks (the single-client walk keeps
+    // kPrefetch in flight; the reduced and paired walks one)
+    constexpr int PF = (!H && !R) ? kPrefetch : 1;
+    uint32_t jq[PF];
+    int32_t dq[PF];
     long long e_cur = 0;
     int k_cur = 0;  // R: the row's length K_i
-    if (R) {
+    if constexpr (PRE) {  // loaded by the caller (eval_first_chunks)
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            jq[q] = pre->j[q];
+            dq[q] = pre->d[q];
+        }
+    } else if constexpr (R) {
+        jq[0] = a.t.pi[(int64_t)row_first * a.t.pitch + col];
+        dq[0] = 0;
         e_cur = a.e64[(int64_t)min(i, last) * a.t.pitch + col];
         k_cur = a.rlen[min(i, last)];
     } else {
-        d_cur = a.t.ds[(int64_t)row_first * a.t.pitch + col];
+        FirstChunks fc;
+        eval_first_chunks<H, NV>(a, ti, lane, wave, fc);
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            jq[q] = fc.j[q];
+            dq[q] = fc.d[q];
+        }
     }
+    uint32_t j_cur = jq[0];
+    int32_t d_cur = dq[0];
     // Masks: every load unconditional at a clamped (always valid) address,
     // in batches, so that a batch costs one round trip; out-of-range words
     // are replaced by 0 when stored.
@@ -261,10 +320,15 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
     constexpr int kBatch = kIt < 16 ? kIt : 16;
     // active flag: also an unconditional load (of any valid byte when every
     // chromosome is active)
-    const uint8_t *ap = a.active ? a.active + min(my_c, a.P - 1) : (const uint8_t *)a.masks;
-    const uint8_t actv = *ap;
+    uint8_t actv = 0;
+    if constexpr (PRE) {
+        actv = sact[lane];
+    } else {
+        const uint8_t *ap = a.active ? a.active + min(my_c, a.P - 1) : (const uint8_t *)a.masks;
+        actv = *ap;
+    }
 #pragma unroll
-    for (int r0 = 0; r0 < kIt; r0 += kBatch) {
+    for (int r0 = 0; !PRE && r0 < kIt; r0 += kBatch) {
         uint32_t v[kBatch];
 #pragma unroll
         for (int r = 0; r < kBatch; ++r) {
@@ -280,7 +344,7 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
                 smask[c * SD + w] = (w < W2 && c < rows) ? v[r] : 0u;
         }
     }
-    const bool my_act = my_c < a.P && (a.active == nullptr || actv != 0);
+    const bool my_act = my_c < a.P && ((!PRE && a.active == nullptr) || actv != 0);
     const uint64_t act = __builtin_amdgcn_ballot_w64(my_act);
     // nothing to do (same in every wave: the whole workgroup leaves), or a
     // stopped GA run, whose later generations are no-ops
@@ -389,16 +453,23 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
         }
     }
     for (; !H && i < i1; i += NV) {
-        const int inext = min(i + NV, last);
-        const uint32_t j_nxt = a.t.pi[(int64_t)inext * a.t.pitch + col];
-        int32_t d_nxt = 0;
+        j_cur = jq[0];
+        d_cur = dq[0];
+        // refill the queue: the client PF places ahead
+#pragma unroll
+        for (int q = 0; q + 1 < PF; ++q) {
+            jq[q] = jq[q + 1];
+            dq[q] = dq[q + 1];
+        }
+        const int inext = min(i + NV * PF, last);
+        jq[PF - 1] = a.t.pi[(int64_t)inext * a.t.pitch + col];
         long long e_nxt = 0;
         int k_nxt = 0;
         if (R) {
             e_nxt = a.e64[(int64_t)inext * a.t.pitch + col];
             k_nxt = a.rlen[inext];
         } else {
-            d_nxt = a.t.ds[(int64_t)inext * a.t.pitch + col];
+            dq[PF - 1] = a.t.ds[(int64_t)inext * a.t.pitch + col];
         }
         const uint16_t *prow = a.t.pi + (int64_t)i * a.t.pitch;
         const int32_t *drow = a.t.ds + (int64_t)i * a.t.pitch;
@@ -453,10 +524,6 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
             }
             pend &= ~__builtin_amdgcn_ballot_w64(found);
         }
-        // the next client's operands, computed here so that the wait for
-        // its loads falls after this client's work
-        j_cur = j_nxt;
-        d_cur = d_nxt;
         e_cur = e_nxt;
         k_cur = k_nxt;
     }

@@ -585,6 +585,28 @@ __device__ __forceinline__ uint64_t cyclic_bits(const WaveWords &A, int W,
     return second > 0 ? (v1 | (v2 << first)) : v1;
 }
 
+// Where an operator's result words go: a row of device memory, or (in the
+// stage steps fused with the evaluation) a chromosome's row of the
+// evaluation's LDS staging area as two 32-bit halves, plus the device row
+// when the workgroup keeps the run's state (null otherwise).
+__device__ __forceinline__ void store_word(uint64_t *F, int w, uint64_t v)
+{
+    F[w] = v;
+}
+
+struct StagedRow {
+    uint64_t *global;  // may be null
+    uint32_t *lds;     // 2 W words
+};
+
+__device__ __forceinline__ void store_word(const StagedRow &F, int w, uint64_t v)
+{
+    if (F.global)
+        F.global[w] = v;
+    F.lds[2 * w] = (uint32_t)v;
+    F.lds[2 * w + 1] = (uint32_t)(v >> 32);
+}
+
 // ---------------------------------------------------------------------------
 // Crossover (Section 4.3) of own parent A with partner B, both as the
 // previous stage left them.  Walking from r1 and wrapping past the end,
@@ -596,8 +618,9 @@ __device__ __forceinline__ uint64_t cyclic_bits(const WaveWords &A, int W,
 // hence how many of its own to take (its lowest ones).  Returns false when
 // the parents differ in fewer than 2*quota genes (no offspring).
 // ---------------------------------------------------------------------------
+template <class Out>
 __device__ __forceinline__ bool crossover_wave(const WaveWords &A,
-                                               const WaveWords &B, uint64_t *F,
+                                               const WaveWords &B, const Out &F,
                                                int W, int r1, int quota,
                                                int lane)
 {
@@ -646,7 +669,7 @@ __device__ __forceinline__ bool crossover_wave(const WaveWords &A,
             take_x |= lowest_bits(xl, quota - main_x);
             take_y |= lowest_bits(yl, quota - main_y);
         }
-        F[wd[h]] = (av[h] & ~take_x) | take_y;
+        store_word(F, wd[h], (av[h] & ~take_x) | take_y);
     }
     return true;
 }
@@ -657,7 +680,8 @@ __device__ __forceinline__ bool crossover_wave(const WaveWords &A,
 // L, and source bit q outside it.  Each lane builds its destination words
 // from at most two runs of source bits.  Returns whether F differs from A.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool mutate_wave(const WaveWords &A, uint64_t *F,
+template <class Out>
+__device__ __forceinline__ bool mutate_wave(const WaveWords &A, const Out &F,
                                             int W, int m, int lo, int hi,
                                             int move, int lane)
 {
@@ -682,7 +706,7 @@ __device__ __forceinline__ bool mutate_wave(const WaveWords &A, uint64_t *F,
                 val = (val & ~mask) | (part << (qa - q0));
             }
             changed |= val != A.v[h];
-            F[w] = val;
+            store_word(F, w, val);
         }
     }
     return __builtin_amdgcn_ballot_w64(changed) != 0ull;
@@ -708,52 +732,67 @@ __device__ __forceinline__ bool mutate_wave(const WaveWords &A, uint64_t *F,
 // wave `sub` makes mutants sub mpw ... of the parent, and only wave 0 writes
 // the chromosome's own state (every wave computes the same parent from the
 // same loads).
-__device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
-                                             int in, int prev, int op,
-                                             int index, int sub = 0)
-{
-    const bool primary = sub == 0;
-    const int out = in ^ 1;
-    const int W = g.t.W, m = g.t.m;
-    const bool xo = op == OP_XOVER;
-    const int pc = xo ? (c ^ (g.NT >> (1 + index % g.lg))) : c;
+// Everything one stage step of chromosome c reads, loaded in one round:
+// every load is unconditional at an address that is always valid (clamped
+// index; the partner is c itself when no crossover runs) and values outside
+// the range are masked afterwards.
+struct StageLoad {
+    uint64_t gen;
+    int32_t sj, sk;
+    uint8_t okc_b, okp_b, imp_b;
+    unsigned long long fin, fpin, cs_old;
+    unsigned long long pf0, ph0, pf1, ph1;  // partial sums of client tiles 0-127
+    uint32_t ps0, ps1;
+    WaveWords cc, oc, cp, opw;  // own and partner's chromosome and offspring
+    OpDraw dr;
+};
 
-    // One round of independent loads, all issued before anything waits:
-    // every load is unconditional at an address that is always valid
-    // (clamped index; the partner is c itself when no crossover runs) and
-    // values outside the range are masked afterwards.
-    const uint64_t gen = g.gs[GS_GEN];
-    int sj = 0, sk = 0;
+__device__ __forceinline__ int stage_partner(const GaArgs &g, int c, int op, int index)
+{
+    return op == OP_XOVER ? (c ^ (g.NT >> (1 + index % g.lg))) : c;
+}
+
+__device__ __forceinline__ void stage_load(const GaArgs &g, int c, int lane, int in, int op,
+                                           int index, StageLoad &L)
+{
+    const int W = g.t.W;
+    const bool xo = op == OP_XOVER;
+    const int pc = stage_partner(g, c, op, index);
+    L.gen = g.gs[GS_GEN];
+    L.sj = 0;
+    L.sk = 0;
     if (op == OP_SWAP) {
         const int32_t *sw = g.swaps + ((int64_t)c * g.L + index) * 2;
-        sj = sw[0];
-        sk = sw[1];
+        L.sj = sw[0];
+        L.sk = sw[1];
     }
-    const uint8_t okc_b = buf(g.ok, in)[c];
-    const uint8_t okp_b = buf(g.ok, in)[pc];
-    const unsigned long long fin = buf(g.fit, in)[c];
-    const unsigned long long fpin = buf(g.fit, in)[pc];
-    const uint8_t imp_b = g.improved[c];
+    L.okc_b = buf(g.ok, in)[c];
+    L.okp_b = buf(g.ok, in)[pc];
+    L.fin = buf(g.fit, in)[c];
+    L.fpin = buf(g.fit, in)[pc];
+    L.imp_b = g.improved[c];
     // lane k < CS_COUNT holds counter k of chromosome c
-    unsigned long long *cs = g.cstat + (int64_t)c * CS_COUNT;
-    const unsigned long long cs_old = cs[lane < CS_COUNT ? lane : 0];
+    L.cs_old = g.cstat[(int64_t)c * CS_COUNT + (lane < CS_COUNT ? lane : 0)];
     // partial sums of the first 128 client tiles (straight-line; more tiles
-    // are added below)
-    const bool use0 = lane < g.TI;
+    // are added when the step finishes)
     const int64_t row0 = (int64_t)min(lane, g.TI - 1) * g.P;
-    const unsigned long long pf0 = g.part[row0 + c], ph0 = g.part[row0 + pc];
-    const uint32_t ps0 = g.spart[row0 + c];
+    L.pf0 = g.part[row0 + c];
+    L.ph0 = g.part[row0 + pc];
+    L.ps0 = g.spart[row0 + c];
     // tiles 64..127 in the same round (the branch is uniform)
-    const bool use1 = lane + 64 < g.TI;
-    unsigned long long pf1 = 0, ph1 = 0;
-    uint32_t ps1 = 0;
+    L.pf1 = 0;
+    L.ph1 = 0;
+    L.ps1 = 0;
     if (g.TI > 64) {
         const int64_t row1 = (int64_t)min(lane + 64, g.TI - 1) * g.P;
-        pf1 = g.part[row1 + c];
-        ph1 = g.part[row1 + pc];
-        ps1 = g.spart[row1 + c];
+        L.pf1 = g.part[row1 + c];
+        L.ph1 = g.part[row1 + pc];
+        L.ps1 = g.spart[row1 + c];
     }
-    WaveWords cc{}, oc{}, cp{}, opw{};
+    L.cc = WaveWords{};
+    L.oc = WaveWords{};
+    L.cp = WaveWords{};
+    L.opw = WaveWords{};
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
         if (k == 1 && W <= 64)
@@ -764,25 +803,40 @@ __device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
         const uint64_t a1 = buf(g.off, in)[(int64_t)c * W + wl];
         const uint64_t a2 = buf(g.cur, in)[(int64_t)pc * W + wl];
         const uint64_t a3 = buf(g.off, in)[(int64_t)pc * W + wl];
-        cc.v[k] = w < W ? a0 : 0ull;
-        oc.v[k] = w < W ? a1 : 0ull;
-        cp.v[k] = w < W ? a2 : 0ull;
-        opw.v[k] = w < W ? a3 : 0ull;
+        L.cc.v[k] = w < W ? a0 : 0ull;
+        L.oc.v[k] = w < W ? a1 : 0ull;
+        L.cp.v[k] = w < W ? a2 : 0ull;
+        L.opw.v[k] = w < W ? a3 : 0ull;
     }
     // the operator's draws (the branch is uniform); for the whole mutation
     // cycle, lane a loads attempt a's
-    OpDraw dr{0, 0, 0, 0};
+    L.dr = OpDraw{0, 0, 0, 0};
     if (xo || op == OP_MUT) {
         const int leader = c < pc ? c : pc;
-        dr = g.draws[(int64_t)(xo ? leader : c) * (g.X + g.Y) + (xo ? index : g.X + index)];
+        L.dr = g.draws[(int64_t)(xo ? leader : c) * (g.X + g.Y) + (xo ? index : g.X + index)];
     } else if (op == OP_MUT_ALL) {
-        dr = g.draws[(int64_t)c * (g.X + g.Y) + g.X + min(lane, g.Y - 1)];
+        L.dr = g.draws[(int64_t)c * (g.X + g.Y) + g.X + min(lane, g.Y - 1)];
     }
-    if (ga_stopped(g))  // checked once the loads are on their way
-        return;
-    unsigned long long f = (use0 ? pf0 : 0ull) + (use1 ? pf1 : 0ull);
-    unsigned long long h = (use0 ? ph0 : 0ull) + (use1 ? ph1 : 0ull);
-    unsigned long long s = (unsigned long long)(use0 ? ps0 : 0u) + (use1 ? ps1 : 0u);
+}
+
+// The rest of the stage step from its loads.  `primary`: this wave writes
+// the chromosome's state (population, fitness, flags, counters); F receives
+// the new offspring's words.  Returns whether an offspring was made.
+template <class Out>
+__device__ __forceinline__ bool stage_finish(const GaArgs &g, int c, int lane, int in,
+                                             int prev, int op, int index, int sub,
+                                             bool primary, const StageLoad &L, const Out &F)
+{
+    const int out = in ^ 1;
+    const int W = g.t.W, m = g.t.m;
+    const bool xo = op == OP_XOVER;
+    const int pc = stage_partner(g, c, op, index);
+    const uint64_t gen = L.gen;
+    const OpDraw dr = L.dr;
+    const bool use0 = lane < g.TI, use1 = lane + 64 < g.TI;
+    unsigned long long f = (use0 ? L.pf0 : 0ull) + (use1 ? L.pf1 : 0ull);
+    unsigned long long h = (use0 ? L.ph0 : 0ull) + (use1 ? L.ph1 : 0ull);
+    unsigned long long s = (unsigned long long)(use0 ? L.ps0 : 0u) + (use1 ? L.ps1 : 0u);
     for (int t0 = 128; t0 < g.TI; t0 += 64) {
         const bool use = t0 + lane < g.TI;
         const int64_t row = (int64_t)min(t0 + lane, g.TI - 1) * g.P;
@@ -794,9 +848,10 @@ __device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
     }
     // prev == OP_NONE: the previous operator was already finished (the
     // learned proposal ran in between), so there is nothing to take
-    const bool okc = okc_b != 0 && prev != OP_NONE;
-    const bool okp = xo && okp_b != 0;
-    const bool was_improved = imp_b != 0;
+    const bool okc = L.okc_b != 0 && prev != OP_NONE;
+    const bool okp = xo && L.okp_b != 0;
+    const bool was_improved = L.imp_b != 0;
+    const unsigned long long fin = L.fin, fpin = L.fpin;
 
     const int r1 = dr.a, quota = dr.b;
     const int lo = op == OP_MUT ? dr.a : 0, hi = op == OP_MUT ? dr.b : m - 1;
@@ -806,7 +861,7 @@ __device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
     const unsigned long long fo = wave_sum(f), scan = wave_sum(s), fop = wave_sum(h);
     const bool take = okc && fo < fin;
     const bool ptake = okp && fop < fpin;
-    const WaveWords A = take ? oc : cc;
+    const WaveWords A = take ? L.oc : L.cc;
     uint64_t *cur = buf(g.cur, out) + (int64_t)c * W;
 #pragma unroll
     for (int k = 0; k < 2; ++k)
@@ -845,10 +900,9 @@ __device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
     }
 
     // start the next operator
-    uint64_t *F = buf(g.off, out) + (int64_t)c * W;
     bool ok = false;
     if (xo) {
-        const WaveWords B = ptake ? opw : cp;
+        const WaveWords B = ptake ? L.opw : L.cp;
         ok = crossover_wave(A, B, F, W, r1, quota, lane);
         if (!ok)
             cs_inc += lane == CS_XO_FAIL ? 1ull : 0ull;
@@ -892,11 +946,11 @@ __device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
             const int w = lane + 64 * k;
             if (w < W) {
                 uint64_t v = A.v[k];
-                if ((sj >> 6) == w)
-                    v ^= 1ull << (sj & 63);
-                if ((sk >> 6) == w)
-                    v ^= 1ull << (sk & 63);
-                F[w] = v;
+                if ((L.sj >> 6) == w)
+                    v ^= 1ull << (L.sj & 63);
+                if ((L.sk >> 6) == w)
+                    v ^= 1ull << (L.sk & 63);
+                store_word(F, w, v);
             }
         }
         ok = true;
@@ -904,7 +958,20 @@ __device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
     if (primary && lane == 0)
         buf(g.ok, out)[c] = ok ? 1 : 0;
     if (primary && lane < CS_COUNT && cs_inc != 0ull)
-        cs[lane] = cs_old + cs_inc;
+        g.cstat[(int64_t)c * CS_COUNT + lane] = L.cs_old + cs_inc;
+    return ok;
+}
+
+__device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
+                                             int in, int prev, int op,
+                                             int index, int sub = 0)
+{
+    StageLoad L;
+    stage_load(g, c, lane, in, op, index, L);
+    if (ga_stopped(g))  // checked once the loads are on their way
+        return;
+    stage_finish(g, c, lane, in, prev, op, index, sub, sub == 0, L,
+                 buf(g.off, in ^ 1) + (int64_t)c * g.t.W);
 }
 
 // ---------------------------------------------------------------------------

@@ -8,6 +8,7 @@
 //    off when a phase holds much work (a batch of instances); for a single
 //    small instance the per-step kernels are faster, because every barrier
 //    costs each workgroup an L2 write-back and invalidate.
+#include <hip/hip_ext.h>
 #include "eval_device.hpp"
 #include "ga_device.hpp"
 
@@ -39,6 +40,166 @@ __global__ __launch_bounds__(64 * kGaWaves) void k_stage(GaArgs g, int in,
     if (c >= g.P)
         return;
     ga_stage_one(g, c, lane, in, prev, op, index, sub);  // checks the stop flag itself
+}
+
+// ---------------------------------------------------------------------------
+// A crossover stage fused with the evaluation of its offspring (chromosomes
+// of at most 16 words).  The workgroup of chromosome tile tc and client tile
+// ti first runs the stage step for the tile's 64 chromosomes: each of its 16
+// waves takes 4 chromosomes, a row of 16 lanes per chromosome and a word per
+// lane.  A row adds up the previous evaluation's partial sums, takes the
+// offspring if strictly fitter (for the chromosome and its partner), and
+// runs the crossover of Section 4.3 on its words: row prefix sums of the
+// qualifying genes per word (A = 1, B = 0 and A = 0, B = 1), rearranged into
+// the cyclic walk order from r1, tell each lane how many genes of each kind
+// come before its word, hence which of its own to take.  The new offspring
+// goes straight into the evaluation's staging rows, and the tile is then
+// evaluated on the workgroup's clients.  Every client tile's workgroup
+// computes the same offspring from the same inputs (what the previous
+// launch left); only client tile 0's writes the run's state (population,
+// fitness, offspring, flags, counters).  The partial sums it reads and the
+// ones it writes are different buffers (launches alternate them).
+// ---------------------------------------------------------------------------
+constexpr int kFusedWaves = 16;
+constexpr int kFusedMaxW = 16;
+
+// Inclusive prefix sums within each 16-lane row (DPP row shifts; lanes
+// without a source add 0).
+__device__ __forceinline__ uint32_t row_scan_incl(uint32_t v)
+{
+    v += dpp_from<0x111, 0xF>(v);  // row_shr:1
+    v += dpp_from<0x112, 0xF>(v);  // row_shr:2
+    v += dpp_from<0x114, 0xF>(v);  // row_shr:4
+    v += dpp_from<0x118, 0xF>(v);  // row_shr:8
+    return v;
+}
+
+// Sum over the 16 lanes of each row (xor butterflies stay inside a row).
+__device__ __forceinline__ unsigned long long row_sum(unsigned long long v)
+{
+    v += __shfl_xor(v, 8);
+    v += __shfl_xor(v, 4);
+    v += __shfl_xor(v, 2);
+    v += __shfl_xor(v, 1);
+    return v;
+}
+
+template <int WD, bool H>
+__global__ __launch_bounds__(kEvalTile *kFusedWaves) void k_stage_eval(GaArgs g, EvalArgs a,
+                                                                      int in, int prev,
+                                                                      int index)
+{
+    constexpr int SD = WD + 1;
+    __shared__ __align__(16) uint32_t smask[eval_stage_words<WD>()];
+    __shared__ unsigned long long sred[2 * kFusedWaves * kEvalTile];
+    __shared__ uint8_t sact[kEvalTile];
+    const int ntiles = a.tiles_c * a.tiles_i;
+    const int per_xcd = (int)gridDim.x >> 3;
+    const int logical = ((int)blockIdx.x & 7) * per_xcd + ((int)blockIdx.x >> 3);
+    if (logical >= ntiles)
+        return;
+    const int ti = logical / a.tiles_c, tc = logical - ti * a.tiles_c;
+    const int c0 = tc * kEvalTile, rows = min(kEvalTile, g.P - c0);
+    const int lane = threadIdx.x & 63, wave = wave_id();
+    const int W = g.t.W, out = in ^ 1;
+    const int stride = g.NT >> (1 + index % g.lg);
+    const int q = lane >> 4, w = lane & 15, rb = lane & ~15;  // row, word, row's first lane
+    const int cl = 4 * wave + q;                               // chromosome of the tile
+    const bool valid = cl < rows, inw = w < W;
+    const int c = c0 + min(cl, rows - 1), pc = c ^ stride;
+    const int wl = min(w, W - 1);
+    // one round of loads
+    const uint64_t *cin = buf(g.cur, in), *oin = buf(g.off, in);
+    const uint64_t cc = cin[(int64_t)c * W + wl], oc = oin[(int64_t)c * W + wl];
+    const uint64_t cp = cin[(int64_t)pc * W + wl], op = oin[(int64_t)pc * W + wl];
+    const unsigned long long fin = buf(g.fit, in)[c], fpin = buf(g.fit, in)[pc];
+    const uint8_t okc_b = buf(g.ok, in)[c], okp_b = buf(g.ok, in)[pc];
+    const OpDraw dr = g.draws[(int64_t)min(c, pc) * (g.X + g.Y) + index];
+    // lanes 0-3 of a row: the counters this stage may change
+    const int cs_k = w == 0 ? CS_EVALS : (w == 1 ? CS_SCAN : (w == 2 ? CS_XO_TAKEN : CS_XO_FAIL));
+    unsigned long long *cs = g.cstat + (int64_t)c * CS_COUNT;
+    const unsigned long long cs_old = cs[cs_k];
+    unsigned long long f = 0, h = 0, sc = 0;
+    for (int t = w; t < g.TI; t += 16) {
+        f += g.part[(int64_t)t * g.P + c];
+        h += g.part[(int64_t)t * g.P + pc];
+        sc += g.spart[(int64_t)t * g.P + c];
+    }
+    // the evaluation's first chunks, in the same round
+    FirstChunks fc;
+    eval_first_chunks<H, kFusedWaves>(a, ti, lane, wave, fc);
+    if (ga_stopped(g))  // the same flag for every wave
+        return;
+    f = row_sum(f);
+    h = row_sum(h);
+    sc = row_sum(sc);
+    // finish the previous stage for the chromosome and its partner
+    const bool okc = okc_b != 0 && prev != OP_NONE;
+    const bool take = okc && f < fin;
+    const bool ptake = okp_b != 0 && h < fpin;
+    const uint64_t A = inw ? (take ? oc : cc) : 0ull;
+    const uint64_t B = inw ? (ptake ? op : cp) : 0ull;
+    // crossover: from r1 on, cyclically, turn off the first `quota` genes
+    // with A = 1, B = 0 and turn on the first `quota` with A = 0, B = 1
+    const int r1 = dr.a, quota = dr.b;
+    const int w0 = r1 >> 6, b0 = r1 & 63;
+    const uint64_t hi_m = ~0ull << b0, lo_m = b0 ? ((1ull << b0) - 1ull) : 0ull;
+    const uint64_t x = A & ~B, y = ~A & B;
+    // counts packed as (x | y << 16): at most 1024 genes of each kind
+    const uint32_t v = (uint32_t)__builtin_popcountll(x) | ((uint32_t)__builtin_popcountll(y) << 16);
+    const uint32_t vlo = (uint32_t)__builtin_popcountll(x & lo_m) |
+                         ((uint32_t)__builtin_popcountll(y & lo_m) << 16);
+    const uint32_t incl = row_scan_incl(v), excl = incl - v;
+    const uint32_t total = (uint32_t)__shfl((int)incl, rb + 15);
+    const uint32_t excl0 = (uint32_t)__shfl((int)excl, rb + w0);
+    const uint32_t lo0 = (uint32_t)__shfl((int)vlo, rb + w0);
+    // genes of each kind before this lane's word in the walk order: word w0
+    // from bit b0 up, words w0 + 1 ... W - 1, 0 ... w0 - 1, word w0 below b0
+    const uint32_t before = w > w0 ? excl - excl0 - lo0 : (w < w0 ? total - excl0 - lo0 + excl : 0u);
+    const int tot_x = (int)(total & 0xFFFFu);
+    const bool ok = valid && tot_x >= quota;
+    uint64_t tx, ty;
+    if (w == w0) {
+        const uint32_t main_ = total - lo0;  // everything before the last segment
+        tx = lowest_bits(x & hi_m, quota) |
+             lowest_bits(x & lo_m, quota - (int)(main_ & 0xFFFFu));
+        ty = lowest_bits(y & hi_m, quota) |
+             lowest_bits(y & lo_m, quota - (int)(main_ >> 16));
+    } else {
+        tx = lowest_bits(x, quota - (int)(before & 0xFFFFu));
+        ty = lowest_bits(y, quota - (int)(before >> 16));
+    }
+    const uint64_t F = (A & ~tx) | ty;
+    if (ok && inw) {
+        smask[cl * SD + 2 * w] = (uint32_t)F;
+        smask[cl * SD + 2 * w + 1] = (uint32_t)(F >> 32);
+    }
+    if (w == 0)
+        sact[cl] = ok ? 1 : 0;
+    if (ti == 0 && valid) {  // the run's state
+        if (inw) {
+            buf(g.cur, out)[(int64_t)c * W + w] = A;
+            if (ok)
+                buf(g.off, out)[(int64_t)c * W + w] = F;
+        }
+        if (w == 0) {
+            buf(g.fit, out)[c] = take ? f : fin;
+            buf(g.ok, out)[c] = ok ? 1 : 0;
+        }
+        unsigned long long inc = 0;
+        if (w == 0 && okc)
+            inc = 1;
+        if (w == 1 && okc)
+            inc = sc;
+        if (w == 2 && take && prev == OP_XOVER)
+            inc = 1;
+        if (w == 3 && !ok)
+            inc = 1;
+        if (w < 4 && inc)
+            cs[cs_k] = cs_old + inc;
+    }
+    __syncthreads();
+    eval_tile<WD, false, H, kFusedWaves, true>(a, ti, tc, smask, sred, sact, &fc);
 }
 
 // The mutation cycle resolved at once (ga_resolve_wave): 64 / YP
@@ -460,6 +621,35 @@ hipError_t launch_ga_stage(const GaArgs &g, int in, int prev, int op, int index,
     hipLaunchKernelGGL(k_stage, per_wave(waves), dim3(64 * kGaWaves), 0, s, g, in,
                        prev, op, index);
     return hipGetLastError();
+}
+
+bool ga_stage_eval_fits(int W)
+{
+    return W <= kFusedMaxW;
+}
+
+hipError_t launch_ga_stage_eval(const GaArgs &g, const EvalArgs &a, int in, int prev,
+                                int index, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
+{
+    const int tiles = a.tiles_c * a.tiles_i;
+    const dim3 grid((unsigned)(((tiles + 7) / 8) * 8)), block(kEvalTile * kFusedWaves);
+    const int w2 = 2 * g.t.W;
+#define PMP_FUSED_WD(N)                                                                 \
+    if (w2 <= N) {                                                                      \
+        auto fn = a.paired ? k_stage_eval<N, true> : k_stage_eval<N, false>;            \
+        if (e0 && e1)                                                                   \
+            hipExtLaunchKernelGGL(fn, grid, block, 0, s, e0, e1, 0, g, a, in, prev, index); \
+        else                                                                            \
+            hipLaunchKernelGGL(fn, grid, block, 0, s, g, a, in, prev, index);           \
+        return hipGetLastError();                                                       \
+    }
+    PMP_FUSED_WD(2)
+    PMP_FUSED_WD(4)
+    PMP_FUSED_WD(8)
+    PMP_FUSED_WD(16)
+    PMP_FUSED_WD(32)
+#undef PMP_FUSED_WD
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_ga_resolve(const GaArgs &g, int in, int out, hipStream_t s)

@@ -115,6 +115,22 @@ int eval_waves(int n, int P, int m, int p, int W)
     return 16;
 }
 
+// Clients per workgroup of the fused stage-and-evaluation launches.  Each
+// client tile's workgroup repeats the stage step of its 64 chromosomes, so
+// these tiles are larger than the plain evaluation's: about 512 workgroups,
+// 64 clients at least.  PMP_FUSED_CLIENTS forces it.
+int fused_clients_per_block(int n, int P)
+{
+    const int forced = env_int("PMP_FUSED_CLIENTS", 0);
+    if (forced > 0)
+        return forced;
+    const long tiles_c = (P + kEvalTile - 1) / kEvalTile;
+    const long ti = std::max(1L, 512 / std::max(1L, tiles_c));
+    long f = ((long)n + ti - 1) / ti;
+    f = std::max(f, 64L);
+    return (int)std::min<long>(f, n);
+}
+
 int clients_per_block(int n, int P, int m, int p, int W, bool reduced = false,
                       int waves = kEvalWaves)
 {
@@ -280,6 +296,8 @@ struct pmp_ga {
     pmp_instance *inst = nullptr;
     pmp_ga_params prm{};
     int NB = 0, lg = 0, X = 0, Y = 0, TI = 0, cpb = 0;
+    bool fused = true;            // crossover stages fused with their evaluations
+    int fcpb = 0, fTI = 0;        // client tiles of the fused launches
     int waves = kEvalWaves;       // waves per workgroup of the population's evaluation
     int spec_waves = kEvalWaves;  // and of the mutants' evaluation
     uint64_t *cur[2] = {nullptr, nullptr}, *off[2] = {nullptr, nullptr};
@@ -297,6 +315,10 @@ struct pmp_ga {
     bool spec_on = true;
     unsigned long long *part = nullptr;
     uint32_t *spart = nullptr;
+    // second set of partial sums: fused stage launches alternate between the
+    // two (one reads the previous stage's sums while it writes its own)
+    unsigned long long *part2 = nullptr;
+    uint32_t *spart2 = nullptr;
     uint64_t *gmask = nullptr, *best = nullptr;
     unsigned long long *binom = nullptr;  // PMP_INIT_RANK: binomial table
     uint64_t nsets = 0;                   // PMP_INIT_RANK: C(m, p)
@@ -1341,6 +1363,8 @@ void pmp_ga_destroy(pmp_ga *ga)
     dfree(ga->mspart);
     dfree(ga->part);
     dfree(ga->spart);
+    dfree(ga->part2);
+    dfree(ga->spart2);
     dfree(ga->gmask);
     dfree(ga->best);
     dfree(ga->gcost);
@@ -1396,8 +1420,11 @@ pmp_status pmp_ga_create(pmp_instance *inst, const pmp_ga_params *prm,
     ga->Y = prm->mutation_iters > 0 ? prm->mutation_iters : lg;
     ga->waves = eval_waves(inst->n, P, inst->m, inst->p, inst->W);
     ga->spec_waves = ga->waves;
+    ga->fused = env_int("PMP_GA_FUSED", 1) != 0 && ga_stage_eval_fits(inst->W);
     ga->cpb = clients_per_block(inst->n, P, inst->m, inst->p, inst->W, false, ga->waves);
     ga->TI = (inst->n + ga->cpb - 1) / ga->cpb;
+    ga->fcpb = fused_clients_per_block(inst->n, P);
+    ga->fTI = (inst->n + ga->fcpb - 1) / ga->fcpb;
     const size_t W = inst->W, PW = (size_t)P * W;
     bool bad = false;
     for (int k = 0; k < 2; ++k)
@@ -1405,7 +1432,10 @@ pmp_status pmp_ga_create(pmp_instance *inst, const pmp_ga_params *prm,
               dalloc(&ga->fit[k], (size_t)P) || dalloc(&ga->ok[k], (size_t)P);
     bad = bad || dalloc(&ga->improved, (size_t)P) ||
           dalloc(&ga->draws, (size_t)P * std::max(1, ga->X + ga->Y)) ||
-          dalloc(&ga->part, (size_t)ga->TI * P) || dalloc(&ga->spart, (size_t)ga->TI * P) ||
+          dalloc(&ga->part, (size_t)std::max(ga->TI, ga->fTI) * P) ||
+          dalloc(&ga->spart, (size_t)std::max(ga->TI, ga->fTI) * P) ||
+          dalloc(&ga->part2, (size_t)std::max(ga->TI, ga->fTI) * P) ||
+          dalloc(&ga->spart2, (size_t)std::max(ga->TI, ga->fTI) * P) ||
           dalloc(&ga->gmask, (size_t)ga->NB * W) || dalloc(&ga->best, W) ||
           dalloc(&ga->gcost, (size_t)ga->NB) || dalloc(&ga->gs, GS_COUNT) ||
           dalloc(&ga->cstat, (size_t)P * CS_COUNT) || dalloc(&ga->arrive, 1) ||
@@ -1527,6 +1557,33 @@ hipError_t ga_eval(pmp_ga *ga, const GaArgs &g, int buf, hipStream_t s, bool mut
     return launch_eval(a, s, e0, e1);
 }
 
+// A crossover stage fused with the evaluation of its offspring (buffer
+// in ^ 1); when profiling, with a pair of events stamped by the launch.
+hipError_t ga_stage_eval(pmp_ga *ga, const GaArgs &g, int in, int prev, int index,
+                         hipStream_t s)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (ga->prof) {
+        e0 = next_event(ga);
+        e1 = next_event(ga);
+        if (!e0 || !e1)
+            return hipErrorOutOfMemory;
+    }
+    // launch k reads the partial sums launch k - 1 wrote (the population's
+    // evaluation wrote `part` before launch 0) and writes the other set
+    GaArgs gk = g;
+    EvalArgs a = ga_eval_args(ga, g, in ^ 1);
+    const bool odd = (index & 1) != 0;
+    gk.part = odd ? ga->part2 : ga->part;
+    gk.spart = odd ? ga->spart2 : ga->spart;
+    gk.TI = index == 0 ? ga->TI : ga->fTI;  // the tiling of the sums it reads
+    a.part = odd ? ga->part : ga->part2;
+    a.spart = odd ? ga->spart : ga->spart2;
+    a.clients_per_block = ga->fcpb;
+    a.tiles_i = ga->fTI;
+    return launch_ga_stage_eval(gk, a, in, prev, index, s, e0, e1);
+}
+
 // Host-side totals of the per-chromosome counters.
 hipError_t ga_counters(pmp_ga *ga, unsigned long long tot[CS_COUNT])
 {
@@ -1577,24 +1634,38 @@ hipError_t enqueue_generations(pmp_ga *ga, const GaArgs &g, int generations,
             for (int k = 0; k < X && e == hipSuccess; ++k) {
                 int prev, op, index;
                 ga_stage_ops(k, X, S, &prev, &op, &index, 0);
-                e = launch_ga_stage(g, k & 1, prev, op, index, s);
-                if (e == hipSuccess)
-                    e = ga_eval(ga, g, (k & 1) ^ 1, s);
+                if (ga->fused) {
+                    e = ga_stage_eval(ga, g, k & 1, prev, index, s);
+                } else {
+                    e = launch_ga_stage(g, k & 1, prev, op, index, s);
+                    if (e == hipSuccess)
+                        e = ga_eval(ga, g, (k & 1) ^ 1, s);
+                }
             }
             int in = X & 1;  // the buffer holding the last crossover's results
             const int prev = X == 0 ? OP_INIT : OP_XOVER;
+            // the partial sums of the last evaluation (fused launches
+            // alternate the two sets: launch k writes set (k + 1) mod 2)
+            GaArgs gl = g;
+            if (ga->fused && X > 0) {
+                gl.TI = ga->fTI;
+                if (X & 1) {
+                    gl.part = ga->part2;
+                    gl.spart = ga->spart2;
+                }
+            }
             if (L > 0) {
                 // finish the crossovers, score the swaps of the chromosomes as
                 // they stand, then make every mutant (the swaps among them)
                 if (e == hipSuccess)
-                    e = launch_ga_stage(g, in, prev, OP_NONE, 0, s);
+                    e = launch_ga_stage(gl, in, prev, OP_NONE, 0, s);
                 if (e == hipSuccess)
                     e = launch_propose(ga->learn_args(g), in, s);
                 in ^= 1;
                 if (e == hipSuccess)
                     e = launch_ga_stage(g, in, OP_NONE, OP_MUT_ALL, 0, s);
             } else if (e == hipSuccess) {
-                e = launch_ga_stage(g, in, prev, OP_MUT_ALL, 0, s);
+                e = launch_ga_stage(gl, in, prev, OP_MUT_ALL, 0, s);
             }
             if (e == hipSuccess)
                 e = ga_eval(ga, g, 0, s, true);
@@ -1927,7 +1998,11 @@ pmp_status pmp_ga_autotune(pmp_ga *ga, int32_t *clients, int32_t *waves, void *s
         const int ti = (n + best - 1) / best;
         dfree(ga->part);
         dfree(ga->spart);
-        if (dalloc(&ga->part, (size_t)ti * P) || dalloc(&ga->spart, (size_t)ti * P))
+        dfree(ga->part2);
+        dfree(ga->spart2);
+        const size_t cells = (size_t)std::max(ti, ga->fTI) * P;
+        if (dalloc(&ga->part, cells) || dalloc(&ga->spart, cells) ||
+            dalloc(&ga->part2, cells) || dalloc(&ga->spart2, cells))
             return fail(PMP_ENOMEM, "GA partial sums for %d client tiles", ti);
         ga->cpb = best;
         ga->TI = ti;
