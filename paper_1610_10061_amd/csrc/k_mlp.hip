@@ -172,17 +172,17 @@ __global__ __launch_bounds__(64 * kWaves) void k_mlp_grad(MlpDev P, const uint16
         wave_lds_sync();
         // dz1 = (dz2 W2) relu'(z1); db1 += dz1
         {
-            bf16x4 a[kHidden / 16];
+            bf16x8 a[kHidden / 32];
 #pragma unroll
-            for (int kb = 0; kb < kHidden / 16; ++kb)
-                a[kb] = load_bf16x4(L.hr + (wr + r) * kHStride + kb * 16 + 4 * g);
+            for (int kb = 0; kb < kHidden / 32; ++kb)
+                a[kb] = load_bf16x8(L.hr + (wr + r) * kHStride + kb * 32 + 8 * g);
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
                 f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int kb = 0; kb < kHidden / 16; ++kb)
+                for (int kb = 0; kb < kHidden / 32; ++kb)
                     acc = mfma_bf16(a[kb],
-                                    load_bf16x4(P.W2T + (t * 16 + r) * kHidden + kb * 16 + 4 * g),
+                                    load_bf16x8(P.W2T + (t * 16 + r) * kHidden + kb * 32 + 8 * g),
                                     acc);
                 uint16_t h[4];
 #pragma unroll
@@ -199,24 +199,24 @@ __global__ __launch_bounds__(64 * kWaves) void k_mlp_grad(MlpDev P, const uint16
         // weight gradients over the chunk's rows: this wave owns output rows
         // (hidden units) 32 wave .. 32 wave + 31 of dW2 and dW1
 #pragma unroll
-        for (int kk = 0; kk < kChunk / 16; ++kk) {
-            bf16x4 a2[2], a1[2];
+        for (int kk = 0; kk < kChunk / 32; ++kk) {
+            bf16x8 a2[2], a1[2];
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
                 const int n = (2 * wave + q) * 16 + r;
-                a2[q] = load_bf16x4(L.z2t + n * kTStride + kk * 16 + 4 * g);
-                a1[q] = load_bf16x4(L.z1t + n * kTStride + kk * 16 + 4 * g);
+                a2[q] = load_bf16x8(L.z2t + n * kTStride + kk * 32 + 8 * g);
+                a1[q] = load_bf16x8(L.z1t + n * kTStride + kk * 32 + 8 * g);
             }
 #pragma unroll
             for (int kt = 0; kt < 8; ++kt) {
-                const bf16x4 b = load_bf16x4(L.ht + (kt * 16 + r) * kTStride + kk * 16 + 4 * g);
+                const bf16x8 b = load_bf16x8(L.ht + (kt * 16 + r) * kTStride + kk * 32 + 8 * g);
 #pragma unroll
                 for (int q = 0; q < 2; ++q)
                     acc2[q * 8 + kt] = mfma_bf16(a2[q], b, acc2[q * 8 + kt]);
             }
 #pragma unroll
             for (int kt = 0; kt < 2; ++kt) {
-                const bf16x4 b = load_bf16x4(L.xt + (kt * 16 + r) * kTStride + kk * 16 + 4 * g);
+                const bf16x8 b = load_bf16x8(L.xt + (kt * 16 + r) * kTStride + kk * 32 + 8 * g);
 #pragma unroll
                 for (int q = 0; q < 2; ++q)
                     acc1[q * 2 + kt] = mfma_bf16(a1[q], b, acc1[q * 2 + kt]);

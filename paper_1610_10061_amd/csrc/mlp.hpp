@@ -1,11 +1,12 @@
 // Swap-scoring network shared by the proposal kernel and the training
 // kernels: 32 inputs -> 128 -> 128 -> 1 with ReLU, BF16 weights and inputs,
-// FP32 accumulation on the MFMA units (v_mfma_f32_16x16x16bf16_1k).
+// FP32 accumulation on the MFMA units (gfx950's v_mfma_f32_16x16x32_bf16:
+// a 16 x 16 product over 32 values of k per instruction).
 //
-// MFMA 16x16x16 BF16 operand layout (wave64, lane l, g = l / 16, i = 0..3):
-//   A fragment: A[row l%16][k 4g + i]
-//   B fragment: B[k 4g + i][col l%16]
-//   C/D:        D[row 4g + i][col l%16]
+// MFMA 16x16x32 BF16 operand layout (wave64, lane l, g = l / 16):
+//   A fragment: A[row l%16][k 8g + i], i = 0..7
+//   B fragment: B[k 8g + i][col l%16], i = 0..7
+//   C/D:        D[row 4g + i][col l%16], i = 0..3
 //
 // Parameter vector (FP32 master copy, kParams values):
 //   W1 [128][32] | b1 [128] | W2 [128][128] | b2 [128] | w3 [128] | b3 [1]
@@ -84,24 +85,21 @@ struct TrainGate {
     int32_t every;
 };
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ f32x4 mfma_bf16(bf16x4 a, bf16x4 b, f32x4 c)
+__device__ __forceinline__ f32x4 mfma_bf16(bf16x8 a, bf16x8 b, f32x4 c)
 {
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-// Four consecutive BF16 values at an 8-byte aligned address.
-__device__ __forceinline__ bf16x4 load_bf16x4(const uint16_t *p)
+// Eight consecutive BF16 values at an 8-byte aligned address.
+__device__ __forceinline__ bf16x8 load_bf16x8(const uint16_t *p)
 {
-    const uint2 v = *reinterpret_cast<const uint2 *>(p);
-    bf16x4 r;
-    r[0] = (short)(v.x & 0xFFFFu);
-    r[1] = (short)(v.x >> 16);
-    r[2] = (short)(v.y & 0xFFFFu);
-    r[3] = (short)(v.y >> 16);
-    return r;
+    const uint2 lo = *reinterpret_cast<const uint2 *>(p);
+    const uint2 hi = *reinterpret_cast<const uint2 *>(p + 4);
+    const uint4 v = {lo.x, lo.y, hi.x, hi.y};
+    return __builtin_bit_cast(bf16x8, v);
 }
 
 // Order this wave's earlier LDS accesses before its later ones.
@@ -124,16 +122,16 @@ __device__ __forceinline__ void mlp_forward16(const MlpDev &P, const uint16_t *x
                                               f32x4 z2[8], float y[4])
 {
     const int r = lane & 15, g = lane >> 4;
-    bf16x4 ax[kIn / 16];
+    bf16x8 ax[kIn / 32];
 #pragma unroll
-    for (int kb = 0; kb < kIn / 16; ++kb)
-        ax[kb] = load_bf16x4(x + r * kXStride + kb * 16 + 4 * g);
+    for (int kb = 0; kb < kIn / 32; ++kb)
+        ax[kb] = load_bf16x8(x + r * kXStride + kb * 32 + 8 * g);
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kb = 0; kb < kIn / 16; ++kb)
-            acc = mfma_bf16(ax[kb], load_bf16x4(P.W1 + (t * 16 + r) * kIn + kb * 16 + 4 * g),
+        for (int kb = 0; kb < kIn / 32; ++kb)
+            acc = mfma_bf16(ax[kb], load_bf16x8(P.W1 + (t * 16 + r) * kIn + kb * 32 + 8 * g),
                             acc);
         const float bias = P.b1[t * 16 + r];
 #pragma unroll
@@ -147,17 +145,17 @@ __device__ __forceinline__ void mlp_forward16(const MlpDev &P, const uint16_t *x
         for (int i = 0; i < 4; ++i)
             h1[(4 * g + i) * kHStride + t * 16 + r] = f32_to_bf16(fmaxf(z1[t][i], 0.f));
     wave_lds_sync();
-    bf16x4 ah[kHidden / 16];
+    bf16x8 ah[kHidden / 32];
 #pragma unroll
-    for (int kb = 0; kb < kHidden / 16; ++kb)
-        ah[kb] = load_bf16x4(h1 + r * kHStride + kb * 16 + 4 * g);
+    for (int kb = 0; kb < kHidden / 32; ++kb)
+        ah[kb] = load_bf16x8(h1 + r * kHStride + kb * 32 + 8 * g);
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kb = 0; kb < kHidden / 16; ++kb)
+        for (int kb = 0; kb < kHidden / 32; ++kb)
             acc = mfma_bf16(ah[kb],
-                            load_bf16x4(P.W2 + (t * 16 + r) * kHidden + kb * 16 + 4 * g),
+                            load_bf16x8(P.W2 + (t * 16 + r) * kHidden + kb * 32 + 8 * g),
                             acc);
         const float bias = P.b2[t * 16 + r];
 #pragma unroll
