@@ -70,9 +70,10 @@ def log(*a):
 
 
 COUNTERS = os.path.join(ROOT, "profiles", "k_eval_counters.json")
-# sources of the evaluation kernel: a change to them voids its counters (the
-# summary also records the client tiles its dispatches used)
-EVAL_SOURCES = ("eval_device.hpp", "k_eval.hip")
+# sources of the evaluation kernels (k_eval, and k_stage_eval: a crossover
+# stage fused with its evaluation): a change to them voids their counters
+# (the summary also records the client tiles the dispatches used)
+EVAL_SOURCES = ("eval_device.hpp", "k_eval.hip", "k_ga.hip", "ga_device.hpp")
 
 
 def eval_sources_digest():
@@ -953,7 +954,9 @@ def main():
     ev_bytes = sum(pr["eval_bytes"] for pr in profs)
     ev_pairs = sum(pr["eval_pairs"] for pr in profs)
     roof = valu_roofline(eval_counters("g900_ga"), ev_pairs, ev_ms / 1e3, ev_n)
-    roof = dict({"bound": roof.pop("bound"), "kernel": "k_eval (population evaluation)"},
+    roof = dict({"bound": roof.pop("bound"),
+                 "kernel": "k_stage_eval + k_eval (the crossover stages fused with their "
+                           "evaluations, the population's and the mutants' evaluations)"},
                 **roof)
     paper_gbs = ev_bytes / (ev_ms / 1e3) / 1e9 if ev_ms > 0 else 0.0
     roof.update({
