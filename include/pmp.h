@@ -46,7 +46,7 @@ typedef enum {
     PMP_ENOMEM = 2,       /* device or host allocation failed */
     PMP_EDEVICE = 3,      /* a HIP call failed; see pmp_last_error() */
     PMP_EINFEASIBLE = 4,  /* a chromosome without exactly p open facilities */
-    PMP_EUNSUPPORTED = 5  /* a size this build does not handle (m > 8192) */
+    PMP_EUNSUPPORTED = 5  /* a size this build does not handle for that call */
 } pmp_status;
 
 #define PMP_ON_DEVICE 1u
@@ -59,8 +59,14 @@ typedef enum {
 #define PMP_EVAL_PER_CHROMOSOME 4u
 #define PMP_EVAL_PER_CLIENT 8u
 
-/* Largest m handled: chromosome masks of a tile of 64 chromosomes are held in
- * LDS (64 x 1 KiB at m = 8192). */
+/* Largest m of an instance: facility indices of Pi' are 16-bit. */
+#define PMP_MAX_EVAL_FACILITIES 65535
+/* Largest m of the GA, the reduced polynomial, the enumeration and the other
+ * evaluation schemes (their kernels hold a tile of 64 chromosomes, or a
+ * chromosome per wave, on chip: 64 x 1 KiB at m = 8192).  Preprocessing and
+ * the tiled evaluation take wider instances: rows are then sorted in device
+ * memory and the chromosome tiles are turned facility-major in device
+ * memory (L2-resident) instead of LDS. */
 #define PMP_MAX_FACILITIES 8192
 
 typedef struct pmp_instance pmp_instance;
@@ -77,10 +83,12 @@ typedef struct pmp_ga pmp_ga;
  *
  *  d       n x m int32, row stride ld >= m elements; host pointer, or device
  *          pointer with PMP_ON_DEVICE.  Copied; not kept.
- *  n, m, p 1 <= n, 2 <= m <= PMP_MAX_FACILITIES, 1 <= p <= m - 1.
+ *  n, m, p 1 <= n, 2 <= m <= PMP_MAX_EVAL_FACILITIES, 1 <= p <= m - 1.
  *  out     receives a new instance handle (device tables, owned).
- * Errors: PMP_EINVAL for sizes, null pointers or any d_ij < 0 (the paper
- * assumes non-negative distances); PMP_EUNSUPPORTED for m above the limit.
+ * Errors: PMP_EINVAL for sizes (m above PMP_MAX_EVAL_FACILITIES included),
+ * null pointers or any d_ij < 0 (the paper assumes non-negative distances).
+ * Rows wider than PMP_MAX_FACILITIES are sorted in device memory (a scratch
+ * of up to 256 MB of keys, freed before returning).
  * Always waits for its stream before returning (one-time step).
  * ------------------------------------------------------------------------- */
 PMP_API pmp_status pmp_preprocess(const int32_t *d, int64_t ld, int32_t n, int32_t m,
@@ -117,7 +125,9 @@ PMP_API pmp_status pmp_instance_tables(const pmp_instance *inst, uint16_t *pi,
  * at positions >= m (the truncated walk is defined only for exactly p open
  * facilities); its fitness is then unspecified.  With PMP_ASYNC the error is
  * only recorded in the instance (see pmp_instance_check).  PMP_EINVAL for
- * both scheme flags at once.
+ * both scheme flags at once; PMP_EUNSUPPORTED for a scheme flag when m >
+ * PMP_MAX_FACILITIES.  For m > PMP_MAX_FACILITIES the instance keeps a device
+ * buffer of the tiles' facility-major copies (P x W words, grown on demand).
  * ------------------------------------------------------------------------- */
 PMP_API pmp_status pmp_eval_population(pmp_instance *inst, const uint64_t *masks,
                                int32_t P, int64_t *fitness,
@@ -141,8 +151,8 @@ PMP_API pmp_status pmp_eval_population(pmp_instance *inst, const uint64_t *masks
  * workspace; the results do not depend on the tiling (exact integer sums).
  * Errors: PMP_EINVAL for P > PMP_NOALLOC_CELLS, host pointers (no
  * PMP_ON_DEVICE) or a scheme flag; PMP_EUNSUPPORTED when scan_total is asked
- * for and a widened tile's scan sums could pass 2^32; otherwise as
- * pmp_eval_population.  Every call on one GPU uses that GPU's workspace:
+ * for and a widened tile's scan sums could pass 2^32, or for m >
+ * PMP_MAX_FACILITIES; otherwise as pmp_eval_population.  Every call on one GPU uses that GPU's workspace:
  * calls that overlap on one GPU (two streams, two threads) race and give
  * wrong results; the caller serialises them.  Nothing in the workspace
  * needs clearing between calls (every cell read is written first).
@@ -298,7 +308,8 @@ typedef struct {
 /* Create a GA run on an instance (the instance must outlive it).
  * PMP_EINVAL: P < 1, NT not a power of two, NT > 1024, P % NT != 0,
  * generations < 1, negative counts, unknown migration or init.
- * PMP_EUNSUPPORTED: PMP_INIT_RANK with C(m, p) >= 2^63. */
+ * PMP_EUNSUPPORTED: PMP_INIT_RANK with C(m, p) >= 2^63, or m >
+ * PMP_MAX_FACILITIES. */
 PMP_API pmp_status pmp_ga_create(pmp_instance *inst, const pmp_ga_params *params,
                          pmp_ga **out);
 

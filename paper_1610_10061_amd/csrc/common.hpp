@@ -60,7 +60,17 @@ struct EvalArgs {
     int32_t paired;
     // waves per workgroup of k_eval: 4 (0 means 4), 8 or 16
     int32_t waves;
+    // chromosomes wider than LDS staging allows (W > kMaxStagedWords): the
+    // tiles' facility-major copies in device memory (tile tc at
+    // tg + tc * tg_stride: 64 W words, then an all-zero and an all-ones word),
+    // made and checked beforehand (launch_tile_major)
+    const uint64_t *tg;
+    int64_t tg_stride;
 };
+
+// Widest chromosome the evaluation stages in LDS (words); wider ones use a
+// facility-major copy in device memory.
+constexpr int kMaxStagedWords = PMP_MAX_FACILITIES / 64;  // 128
 
 // Reduced polynomial construction (k_hbp.hip).  t: the instance's tables.
 struct HbpArgs {
@@ -119,6 +129,18 @@ hipError_t launch_eval(const EvalArgs &a, hipStream_t s, hipEvent_t e0 = nullptr
                        hipEvent_t e1 = nullptr);
 hipError_t launch_reduce(const EvalArgs &a, unsigned long long *fitness,
                          unsigned long long *scan, hipStream_t s);
+// Facility-major copies of the chromosome tiles of a.masks into tg (a.P
+// chromosomes, a.t.W words each) and the feasibility check of every
+// chromosome (error bits into a.err).
+hipError_t launch_tile_major(const EvalArgs &a, uint64_t *tg, hipStream_t s);
+// Rows wider than PMP_MAX_FACILITIES: the sort in device memory, `batch`
+// rows at a time in `scratch` (batch x m2 keys, m2 = m rounded up to a power
+// of two).
+int wide_sort_rows_per_batch(int32_t m);
+hipError_t launch_sort_rows_wide(const int32_t *d, int64_t ld, int32_t n, int32_t m,
+                                 int32_t K, int32_t pitch, uint16_t *pi, int32_t *delta,
+                                 int32_t *ds, uint32_t *err, uint64_t *scratch, int32_t batch,
+                                 hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
 // The other thread mappings of the evaluation (k_eval_schemes.hip).
 hipError_t launch_eval_per_chromosome(const EvalArgs &a, unsigned long long *fitness,

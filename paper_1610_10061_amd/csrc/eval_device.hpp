@@ -249,7 +249,12 @@ __device__ __forceinline__ void eval_first_chunks(const EvalArgs &a, int ti, int
     }
 }
 
-template <int WD, bool R = false, bool H = false, int NV = kEvalWaves, bool PRE = false>
+//
+// GT: the tile's facility-major copy is in device memory (a.tg; chromosomes
+// wider than the LDS staging allows), made and checked by launch_tile_major;
+// nothing is staged in LDS.
+template <int WD, bool R = false, bool H = false, int NV = kEvalWaves, bool PRE = false,
+          bool GT = false>
 __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
                                           uint32_t *smask,
                                           unsigned long long *sred,
@@ -328,7 +333,7 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
         actv = *ap;
     }
 #pragma unroll
-    for (int r0 = 0; !PRE && r0 < kIt; r0 += kBatch) {
+    for (int r0 = 0; !PRE && !GT && r0 < kIt; r0 += kBatch) {
         uint32_t v[kBatch];
 #pragma unroll
         for (int r = 0; r < kBatch; ++r) {
@@ -350,70 +355,76 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
     // stopped GA run, whose later generations are no-ops
     if (act == 0ull || (a.done && *a.done))
         return;
-    __syncthreads();
+    if constexpr (!GT)
+        __syncthreads();
 
     // Facility-major copy: wave v turns the tile's 64-bit words v, v + 4, ...
     // (one row per lane) into T[64 w + f], f = 0..63, by one transpose each,
     // in place once every wave has read its rows.
-    constexpr int NW = (WD / 2 + NV - 1) / NV;
-    uint32_t rlo[NW], rhi[NW];
+    const uint64_t *sT = nullptr;
+    const uint32_t jz = (uint32_t)(64 * W), jone = jz + 1u;
+    const TransposeLanes tl(lane);
+    if constexpr (GT) {
+        sT = a.tg + (int64_t)tc * a.tg_stride;
+    } else {
+        constexpr int NW = (WD / 2 + NV - 1) / NV;
+        uint32_t rlo[NW], rhi[NW];
 #pragma unroll
-    for (int r = 0; r < NW; ++r) {
-        const int w = min(wave + r * NV, W - 1);
-        rlo[r] = smask[lane * SD + 2 * w];
-        rhi[r] = smask[lane * SD + 2 * w + 1];
-    }
-    // Feasibility of each chromosome (lane), checked once (first client
-    // tile) from the rows just read: each wave counts the open facilities in
-    // its words and looks for bits past m in the last word; wave 0 adds the
-    // waves' counts up once the copy's barrier has passed.
-    __shared__ uint32_t s_ones[NV][kEvalTile];
-    __shared__ uint32_t s_stray[NV][kEvalTile];
-    if (ti == 0) {
-        uint32_t ones = 0, stray = 0;
-        const uint64_t past = (a.t.m & 63) ? ~((1ull << (a.t.m & 63)) - 1ull) : 0ull;
+        for (int r = 0; r < NW; ++r) {
+            const int w = min(wave + r * NV, W - 1);
+            rlo[r] = smask[lane * SD + 2 * w];
+            rhi[r] = smask[lane * SD + 2 * w + 1];
+        }
+        // Feasibility of each chromosome (lane), checked once (first client
+        // tile) from the rows just read: each wave counts the open facilities in
+        // its words and looks for bits past m in the last word; wave 0 adds the
+        // waves' counts up once the copy's barrier has passed.
+        __shared__ uint32_t s_ones[NV][kEvalTile];
+        __shared__ uint32_t s_stray[NV][kEvalTile];
+        if (ti == 0) {
+            uint32_t ones = 0, stray = 0;
+            const uint64_t past = (a.t.m & 63) ? ~((1ull << (a.t.m & 63)) - 1ull) : 0ull;
+#pragma unroll
+            for (int r = 0; r < NW; ++r) {
+                const int w = wave + r * NV;
+                if (w < W) {
+                    ones += __builtin_popcount(rlo[r]) + __builtin_popcount(rhi[r]);
+                    if (w == W - 1)
+                        stray |= (((uint64_t)rhi[r] << 32 | rlo[r]) & past) != 0ull ? 1u : 0u;
+                }
+            }
+            s_ones[wave][lane] = ones;
+            s_stray[wave][lane] = stray;
+        }
+        __syncthreads();
+        uint64_t *sTw = reinterpret_cast<uint64_t *>(smask);
+        sT = sTw;
 #pragma unroll
         for (int r = 0; r < NW; ++r) {
             const int w = wave + r * NV;
             if (w < W) {
-                ones += __builtin_popcount(rlo[r]) + __builtin_popcount(rhi[r]);
-                if (w == W - 1)
-                    stray |= (((uint64_t)rhi[r] << 32 | rlo[r]) & past) != 0ull ? 1u : 0u;
+                transpose64(rlo[r], rhi[r], lane, tl);
+                sTw[w * 64 + lane] = ((uint64_t)rhi[r] << 32) | rlo[r];
             }
         }
-        s_ones[wave][lane] = ones;
-        s_stray[wave][lane] = stray;
-    }
-    __syncthreads();
-    uint64_t *sT = reinterpret_cast<uint64_t *>(smask);
-    const TransposeLanes tl(lane);
+        // T[64 W]: no chromosome open (positions that do not count); T[64 W + 1]:
+        // every chromosome open (the reduced walk's stop)
+        if (wave == 0 && lane < 2)
+            sTw[jz + lane] = lane ? ~0ull : 0ull;
+        __syncthreads();
+        if (ti == 0 && wave == 0 && my_act) {
+            uint32_t ones = 0, stray = 0;
 #pragma unroll
-    for (int r = 0; r < NW; ++r) {
-        const int w = wave + r * NV;
-        if (w < W) {
-            transpose64(rlo[r], rhi[r], lane, tl);
-            sT[w * 64 + lane] = ((uint64_t)rhi[r] << 32) | rlo[r];
+            for (int v = 0; v < NV; ++v) {
+                ones += s_ones[v][lane];
+                stray |= s_stray[v][lane];
+            }
+            if (ones != (uint32_t)a.t.p)
+                atomicOr(a.err, ERR_POPCOUNT);
+            if (stray)
+                atomicOr(a.err, ERR_STRAY_BITS);
         }
     }
-    // T[64 W]: no chromosome open (positions that do not count); T[64 W + 1]:
-    // every chromosome open (the reduced walk's stop)
-    const uint32_t jz = (uint32_t)(64 * W), jone = jz + 1u;
-    if (wave == 0 && lane < 2)
-        sT[jz + lane] = lane ? ~0ull : 0ull;
-    __syncthreads();
-    if (ti == 0 && wave == 0 && my_act) {
-        uint32_t ones = 0, stray = 0;
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            ones += s_ones[v][lane];
-            stray |= s_stray[v][lane];
-        }
-        if (ones != (uint32_t)a.t.p)
-            atomicOr(a.err, ERR_POPCOUNT);
-        if (stray)
-            atomicOr(a.err, ERR_STRAY_BITS);
-    }
-
     unsigned long long acc = 0;
     uint32_t scn = 0;
     if constexpr (H) {

@@ -226,6 +226,9 @@ struct pmp_instance {
     unsigned long long *part = nullptr;
     uint32_t *spart = nullptr;
     size_t part_cap = 0;
+    // facility-major tiles of chromosomes wider than the LDS staging
+    uint64_t *tg = nullptr;
+    size_t tg_cap = 0;
     // static sums of the learned proposal's features
     unsigned long long *colsum = nullptr;  // m column sums of d
     uint32_t *nearc = nullptr;             // m near counts
@@ -675,6 +678,7 @@ void pmp_instance_destroy(pmp_instance *inst)
     dfree(inst->h_scan);
     dfree(inst->part);
     dfree(inst->spart);
+    dfree(inst->tg);
     dfree(inst->colsum);
     dfree(inst->nearc);
     delete inst;
@@ -692,8 +696,9 @@ pmp_status pmp_preprocess(const int32_t *d, int64_t ld, int32_t n, int32_t m,
     if (n < 1 || m < 2 || p < 1 || p > m - 1)
         return fail(PMP_EINVAL, "need n >= 1, m >= 2, 1 <= p <= m-1 (n=%d m=%d p=%d)",
                     n, m, p);
-    if (m > PMP_MAX_FACILITIES)
-        return fail(PMP_EUNSUPPORTED, "m=%d above %d", m, PMP_MAX_FACILITIES);
+    if (m > PMP_MAX_EVAL_FACILITIES)
+        return fail(PMP_EINVAL, "m=%d above %d (facility indices are 16-bit)", m,
+                    PMP_MAX_EVAL_FACILITIES);
     if (ld < m)
         return fail(PMP_EINVAL, "row stride %lld < m", (long long)ld);
     hipStream_t s = (hipStream_t)stream;
@@ -722,6 +727,7 @@ pmp_status pmp_preprocess(const int32_t *d, int64_t ld, int32_t n, int32_t m,
         return fail(PMP_ENOMEM, "device allocation of tables (%zu cells)", cells);
     }
     int32_t *dd = nullptr;
+    uint64_t *wide = nullptr;  // sort scratch of rows wider than PMP_MAX_FACILITIES
     const int32_t *src = d;
     int64_t src_ld = ld;
     pmp_status st = PMP_OK;
@@ -745,8 +751,21 @@ pmp_status pmp_preprocess(const int32_t *d, int64_t ld, int32_t n, int32_t m,
             src = dd;
             src_ld = m;
         }
-        e = launch_sort_rows(src, src_ld, n, m, inst->K, inst->pitch, inst->pi,
-                             inst->delta, inst->ds, inst->err, s);
+        if (m <= PMP_MAX_FACILITIES) {
+            e = launch_sort_rows(src, src_ld, n, m, inst->K, inst->pitch, inst->pi,
+                                 inst->delta, inst->ds, inst->err, s);
+        } else {  // rows wider than one workgroup's LDS: the sort in device memory
+            int32_t m2 = 2;
+            while (m2 < m)
+                m2 <<= 1;
+            const int batch = std::min(n, wide_sort_rows_per_batch(m));
+            if (dalloc(&wide, (size_t)batch * m2) != hipSuccess) {
+                st = fail(PMP_ENOMEM, "sort scratch (%d rows x %d keys)", batch, m2);
+                break;
+            }
+            e = launch_sort_rows_wide(src, src_ld, n, m, inst->K, inst->pitch, inst->pi,
+                                      inst->delta, inst->ds, inst->err, wide, batch, s);
+        }
         if (e != hipSuccess) {
             st = fail(PMP_EDEVICE, "sort kernel launch: %s", hipGetErrorString(e));
             break;
@@ -776,6 +795,7 @@ pmp_status pmp_preprocess(const int32_t *d, int64_t ld, int32_t n, int32_t m,
         st = status_from_err(herr);
     } while (0);
     dfree(dd);
+    dfree(wide);
     if (st != PMP_OK) {
         pmp_instance_destroy(inst);
         return st;
@@ -880,6 +900,8 @@ struct HbpScratch {
 
 pmp_status pmp_hbp_reduce(pmp_instance *inst, void *stream, pmp_hbp **out)
 {
+    if (inst && inst->m > PMP_MAX_FACILITIES)
+        return fail(PMP_EUNSUPPORTED, "the reduced polynomial takes m <= %d", PMP_MAX_FACILITIES);
     if (!inst || !out)
         return fail(PMP_EINVAL, "instance or out is NULL");
     *out = nullptr;
@@ -1203,6 +1225,10 @@ pmp_status pmp_eval_population(pmp_instance *inst, const uint64_t *masks,
     const uint32_t scheme = flags & (PMP_EVAL_PER_CHROMOSOME | PMP_EVAL_PER_CLIENT);
     if (scheme == (PMP_EVAL_PER_CHROMOSOME | PMP_EVAL_PER_CLIENT))
         return fail(PMP_EINVAL, "at most one evaluation scheme flag");
+    const bool wide = inst->W > kMaxStagedWords;
+    if (scheme && wide)
+        return fail(PMP_EUNSUPPORTED, "the per-chromosome and per-client schemes take m <= %d",
+                    PMP_MAX_FACILITIES);
     hipStream_t s = (hipStream_t)stream;
     const bool on_dev = flags & PMP_ON_DEVICE;
     const bool async = on_dev && (flags & PMP_ASYNC);
@@ -1240,8 +1266,13 @@ pmp_status pmp_eval_population(pmp_instance *inst, const uint64_t *masks,
     a.active = nullptr;
     a.done = nullptr;
     a.err = inst->err;
-    a.waves = eval_waves(inst->n, P, inst->m, inst->p, inst->W);
+    // (wide chromosomes take the device-memory tile walk, 16 waves only)
+    a.waves = wide ? 16 : eval_waves(inst->n, P, inst->m, inst->p, inst->W);
     a.clients_per_block = clients_per_block(inst->n, P, inst->m, inst->p, inst->W, false, a.waves);
+    // a tile's summed scan lengths are kept in 32 bits
+    const int64_t cpb_scan = ((1ll << 32) - 1) / inst->K;
+    if (dscan && (int64_t)a.clients_per_block > cpb_scan)
+        a.clients_per_block = (int32_t)cpb_scan;
     a.tiles_c = (P + kEvalTile - 1) / kEvalTile;
     a.tiles_i = (inst->n + a.clients_per_block - 1) / a.clients_per_block;
     if (scheme == PMP_EVAL_PER_CLIENT)
@@ -1258,6 +1289,22 @@ pmp_status pmp_eval_population(pmp_instance *inst, const uint64_t *masks,
     }
     a.part = inst->part;
     a.spart = dscan ? inst->spart : nullptr;
+    if (wide) {
+        // chromosomes too wide to stage in LDS: their tiles' facility-major
+        // copies in device memory (made and checked first), the single walk
+        a.paired = 0;
+        a.tg_stride = 64 * (int64_t)inst->W + 2;
+        const size_t tg_words = (size_t)a.tiles_c * (size_t)a.tg_stride;
+        if (inst->tg_cap < tg_words) {
+            dfree(inst->tg);
+            inst->tg_cap = 0;
+            if (dalloc(&inst->tg, tg_words) != hipSuccess)
+                return fail(PMP_ENOMEM, "facility-major tiles (%zu words)", tg_words);
+            inst->tg_cap = tg_words;
+        }
+        a.tg = inst->tg;
+        HIP_TRY(launch_tile_major(a, inst->tg, s));
+    }
     if (scheme == PMP_EVAL_PER_CHROMOSOME) {
         HIP_TRY(launch_eval_per_chromosome(a, dfit, dscan, s));
     } else {
@@ -1292,6 +1339,9 @@ pmp_status pmp_eval_population_noalloc(pmp_instance *inst, const uint64_t *masks
                                 "(PMP_ON_DEVICE): host buffers would need staging memory");
     if (flags & (PMP_EVAL_PER_CHROMOSOME | PMP_EVAL_PER_CLIENT))
         return fail(PMP_EINVAL, "pmp_eval_population_noalloc runs the tiled scheme only");
+    if (inst->W > kMaxStagedWords)
+        return fail(PMP_EUNSUPPORTED, "pmp_eval_population_noalloc takes m <= %d",
+                    PMP_MAX_FACILITIES);
     if (P < 0)
         return fail(PMP_EINVAL, "P < 0");
     if ((size_t)P > kNoAllocCells)
@@ -1402,6 +1452,9 @@ pmp_status pmp_ga_create(pmp_instance *inst, const pmp_ga_params *prm,
         (prm->migration != PMP_MIG_SAME_BLOCK && prm->migration != PMP_MIG_ONE_BLOCK) ||
         (prm->init != PMP_INIT_SUBSET && prm->init != PMP_INIT_RANK))
         return fail(PMP_EINVAL, "bad GA parameters");
+    if (inst->m > PMP_MAX_FACILITIES)
+        return fail(PMP_EUNSUPPORTED, "GA runs take m <= %d (the instance has m = %d)",
+                    PMP_MAX_FACILITIES, inst->m);
     std::vector<unsigned long long> binom;
     const unsigned long long nsets =
         prm->init == PMP_INIT_RANK ? binomial_table(inst->m, inst->p, binom) : 0ull;
@@ -2559,6 +2612,8 @@ pmp_status pmp_exhaustive(pmp_instance *inst, uint64_t *best_mask, int64_t *best
 {
     if (!inst)
         return fail(PMP_EINVAL, "instance is NULL");
+    if (inst->m > PMP_MAX_FACILITIES)
+        return fail(PMP_EUNSUPPORTED, "enumeration takes m <= %d", PMP_MAX_FACILITIES);
     const int m = inst->m, p = inst->p, n = inst->n, W = inst->W;
     std::vector<unsigned long long> binom;
     const unsigned long long total = binomial_table(m, p, binom);

@@ -41,15 +41,15 @@ def test_status_strings():
 
 
 @pytest.mark.parametrize("shape,p", [((3, 1), 1), ((4, 5), 0), ((4, 5), 5), ((0, 5), 2),
-                                     ((2, 9000), 3)])
+                                     ((2, 65536), 3)])
 def test_preprocess_rejects_bad_sizes(shape, p):
+    """Sizes rejected before any device call (m above 65535 included: the
+    facility indices of Pi' are 16-bit)."""
     import paper_1610_10061_amd as pm
     d = np.zeros(shape, np.int32)
     with pytest.raises(pm.PmpError) as e:
         pm.pmp_preprocess(d, p)
-    assert e.value.status in (pm.PMP_EINVAL, pm.PMP_EUNSUPPORTED)
-    if shape[1] > 8192:
-        assert e.value.status == pm.PMP_EUNSUPPORTED
+    assert e.value.status == pm.PMP_EINVAL
 
 
 def test_preprocess_rejects_negative_distance_on_host():
