@@ -66,6 +66,10 @@ struct EvalArgs {
     // made and checked beforehand (launch_tile_major)
     const uint64_t *tg;
     int64_t tg_stride;
+    // partial sums chromosome-major (part[c * tiles_i + ti]) instead of
+    // tile-major (part[ti * P + c]): the fused crossover stages, whose
+    // readers add up one chromosome's tiles at a time
+    int32_t pcm;
 };
 
 // Widest chromosome the evaluation stages in LDS (words); wider ones use a
@@ -230,6 +234,7 @@ struct GaArgs {
     const unsigned long long *part; // TI x P partial costs of the last evaluation
     const uint32_t *spart;          // TI x P partial scan lengths
     int32_t TI;                     // client tiles of the evaluation
+    int32_t pcm;                    // part/spart chromosome-major (P x TI)
     uint64_t *gmask;                // NB x W group bests (migrants)
     unsigned long long *gcost;      // NB
     uint64_t *best_mask;            // W

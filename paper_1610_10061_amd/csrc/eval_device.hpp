@@ -253,13 +253,20 @@ __device__ __forceinline__ void eval_first_chunks(const EvalArgs &a, int ti, int
 // GT: the tile's facility-major copy is in device memory (a.tg; chromosomes
 // wider than the LDS staging allows), made and checked by launch_tile_major;
 // nothing is staged in LDS.
+// live = false: a workgroup past the last tile (called with tile 0), which
+// issues the loads and leaves with the stop test, so that no branch comes
+// before the loads (the compiler then issues them, and the kernel arguments
+// they need, in one round each).
+static __device__ const unsigned long long kNoStopFlag = 0ull;
+
 template <int WD, bool R = false, bool H = false, int NV = kEvalWaves, bool PRE = false,
           bool GT = false>
 __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
                                           uint32_t *smask,
                                           unsigned long long *sred,
                                           const uint8_t *sact = nullptr,
-                                          const FirstChunks *pre = nullptr)
+                                          const FirstChunks *pre = nullptr,
+                                          bool live = true)
 {
     constexpr int SD = WD + 1;  // staged row stride
     const int c0 = tc * kEvalTile;
@@ -326,6 +333,11 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
     // active flag: also an unconditional load (of any valid byte when every
     // chromosome is active)
     uint8_t actv = 0;
+    // the stop flag of a GA run (a no-op generation), loaded in the same
+    // round (PRE: the caller has tested it)
+    unsigned long long stop = 0ull;
+    if constexpr (!PRE)
+        stop = *(a.done ? a.done : &kNoStopFlag);
     if constexpr (PRE) {
         actv = sact[lane];
     } else {
@@ -353,7 +365,7 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
     const uint64_t act = __builtin_amdgcn_ballot_w64(my_act);
     // nothing to do (same in every wave: the whole workgroup leaves), or a
     // stopped GA run, whose later generations are no-ops
-    if (act == 0ull || (a.done && *a.done))
+    if (!live || act == 0ull || stop != 0ull)
         return;
     if constexpr (!GT)
         __syncthreads();
@@ -549,7 +561,7 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
             f += sred[w * kEvalTile + lane];
             s += sred[NV * kEvalTile + w * kEvalTile + lane];
         }
-        const int64_t o = (int64_t)ti * a.P + my_c;
+        const int64_t o = a.pcm ? (int64_t)my_c * a.tiles_i + ti : (int64_t)ti * a.P + my_c;
         a.part[o] = f;
         if (a.spart)
             a.spart[o] = (uint32_t)s;

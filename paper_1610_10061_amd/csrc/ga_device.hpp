@@ -111,13 +111,10 @@ __device__ __forceinline__ void wave_lds_fence()
     __builtin_amdgcn_wave_barrier();
 }
 
-// The k lowest set bits of x (all of x when it has no more than k).
+// The k lowest set bits of x (all of x when it has no more than k, none
+// when k <= 0).  No branches: lanes of a wave seldom agree on the cases.
 __device__ __forceinline__ uint64_t lowest_bits(uint64_t x, int k)
 {
-    if (k <= 0)
-        return 0;
-    if (__builtin_popcountll(x) <= k)
-        return x;
     // largest q with popcount(x below bit q) < k; the k-th set bit is at q
     int q = 0;
 #pragma unroll
@@ -126,7 +123,8 @@ __device__ __forceinline__ uint64_t lowest_bits(uint64_t x, int k)
         if (__builtin_popcountll(x & ((1ull << t) - 1ull)) < k)
             q = t;
     }
-    return q >= 63 ? x : (x & ((1ull << (q + 1)) - 1ull));
+    const uint64_t cut = q >= 63 ? x : (x & ((1ull << (q + 1)) - 1ull));
+    return k <= 0 ? 0ull : (__builtin_popcountll(x) <= k ? x : cut);
 }
 
 // Philox4x64-10 block (philox.hpp) for counter (c0, c1, c2, c3).
@@ -663,12 +661,18 @@ __device__ __forceinline__ bool crossover_wave(const WaveWords &A,
         if (wd[h] < 0)
             continue;
         const uint32_t ex = inc[h] - v[h];
-        uint64_t take_x = lowest_bits(x[h], quota - (int)(ex & 0xFFFFu));
-        uint64_t take_y = lowest_bits(y[h], quota - (int)(ex >> 16));
-        if (lane + 64 * h == 0) {  // word r1/64 also holds the last segment
-            take_x |= lowest_bits(xl, quota - main_x);
-            take_y |= lowest_bits(yl, quota - main_y);
-        }
+        // Word r1/64 (lane 0, h = 0) also holds the last segment, below bit
+        // r1 mod 64, which the walk reaches only once every other gene of
+        // the kind is taken (its first segment included): one lowest_bits
+        // per kind on every lane, no divergent extra calls.
+        const bool first = lane + 64 * h == 0;
+        const int kx = quota - (int)(ex & 0xFFFFu), ky = quota - (int)(ex >> 16);
+        const bool x_in = !first || kx <= __builtin_popcountll(x[h]);
+        const bool y_in = !first || ky <= __builtin_popcountll(y[h]);
+        const uint64_t take_x = lowest_bits(x_in ? x[h] : xl, x_in ? kx : quota - main_x) |
+                                (x_in ? 0ull : x[h]);
+        const uint64_t take_y = lowest_bits(y_in ? y[h] : yl, y_in ? ky : quota - main_y) |
+                                (y_in ? 0ull : y[h]);
         store_word(F, wd[h], (av[h] & ~take_x) | take_y);
     }
     return true;
@@ -774,20 +778,22 @@ __device__ __forceinline__ void stage_load(const GaArgs &g, int c, int lane, int
     // lane k < CS_COUNT holds counter k of chromosome c
     L.cs_old = g.cstat[(int64_t)c * CS_COUNT + (lane < CS_COUNT ? lane : 0)];
     // partial sums of the first 128 client tiles (straight-line; more tiles
-    // are added when the step finishes)
-    const int64_t row0 = (int64_t)min(lane, g.TI - 1) * g.P;
-    L.pf0 = g.part[row0 + c];
-    L.ph0 = g.part[row0 + pc];
-    L.ps0 = g.spart[row0 + c];
+    // are added when the step finishes); tile t of chromosome x at
+    // t * ts + x * xs
+    const int64_t ts = g.pcm ? 1 : g.P, xs = g.pcm ? g.TI : 1;
+    const int64_t row0 = (int64_t)min(lane, g.TI - 1) * ts;
+    L.pf0 = g.part[row0 + c * xs];
+    L.ph0 = g.part[row0 + pc * xs];
+    L.ps0 = g.spart[row0 + c * xs];
     // tiles 64..127 in the same round (the branch is uniform)
     L.pf1 = 0;
     L.ph1 = 0;
     L.ps1 = 0;
     if (g.TI > 64) {
-        const int64_t row1 = (int64_t)min(lane + 64, g.TI - 1) * g.P;
-        L.pf1 = g.part[row1 + c];
-        L.ph1 = g.part[row1 + pc];
-        L.ps1 = g.spart[row1 + c];
+        const int64_t row1 = (int64_t)min(lane + 64, g.TI - 1) * ts;
+        L.pf1 = g.part[row1 + c * xs];
+        L.ph1 = g.part[row1 + pc * xs];
+        L.ps1 = g.spart[row1 + c * xs];
     }
     L.cc = WaveWords{};
     L.oc = WaveWords{};
@@ -837,11 +843,12 @@ __device__ __forceinline__ bool stage_finish(const GaArgs &g, int c, int lane, i
     unsigned long long f = (use0 ? L.pf0 : 0ull) + (use1 ? L.pf1 : 0ull);
     unsigned long long h = (use0 ? L.ph0 : 0ull) + (use1 ? L.ph1 : 0ull);
     unsigned long long s = (unsigned long long)(use0 ? L.ps0 : 0u) + (use1 ? L.ps1 : 0u);
+    const int64_t ts = g.pcm ? 1 : g.P, xs = g.pcm ? g.TI : 1;
     for (int t0 = 128; t0 < g.TI; t0 += 64) {
         const bool use = t0 + lane < g.TI;
-        const int64_t row = (int64_t)min(t0 + lane, g.TI - 1) * g.P;
-        const unsigned long long pf = g.part[row + c], ph = g.part[row + pc];
-        const uint32_t ps = g.spart[row + c];
+        const int64_t row = (int64_t)min(t0 + lane, g.TI - 1) * ts;
+        const unsigned long long pf = g.part[row + c * xs], ph = g.part[row + pc * xs];
+        const uint32_t ps = g.spart[row + c * xs];
         f += use ? pf : 0ull;
         s += use ? ps : 0u;
         h += use ? ph : 0ull;

@@ -22,10 +22,11 @@ __global__ __launch_bounds__(kEvalTile *NV) void k_eval(EvalArgs a)
     const int ntiles = a.tiles_c * a.tiles_i;
     const int per_xcd = (int)gridDim.x >> 3;
     const int logical = ((int)blockIdx.x & 7) * per_xcd + ((int)blockIdx.x >> 3);
-    if (logical >= ntiles)
-        return;
-    const int ti = logical / a.tiles_c;
-    eval_tile<WD, R, H, NV, false, GT>(a, ti, logical - ti * a.tiles_c, smask, sred);
+    const bool live = logical < ntiles;  // (tested inside, once the loads are out)
+    const int lt = live ? logical : 0;
+    const int ti = lt / a.tiles_c;
+    eval_tile<WD, R, H, NV, false, GT>(a, ti, lt - ti * a.tiles_c, smask, sred, nullptr, nullptr,
+                                       live);
 }
 
 // Facility-major copy of chromosome tile tc's word w by one wave: lane c

@@ -96,9 +96,12 @@ __global__ __launch_bounds__(kEvalTile *kFusedWaves) void k_stage_eval(GaArgs g,
     const int ntiles = a.tiles_c * a.tiles_i;
     const int per_xcd = (int)gridDim.x >> 3;
     const int logical = ((int)blockIdx.x & 7) * per_xcd + ((int)blockIdx.x >> 3);
-    if (logical >= ntiles)
-        return;
-    const int ti = logical / a.tiles_c, tc = logical - ti * a.tiles_c;
+    // Nothing branches before the loads below, so the arguments they need
+    // and the loads themselves go out in one round each (a workgroup past
+    // the last tile loads tile 0's inputs and leaves with the stop test).
+    const bool live = logical < ntiles;
+    const int lt = live ? logical : 0;
+    const int ti = lt / a.tiles_c, tc = lt - ti * a.tiles_c;
     const int c0 = tc * kEvalTile, rows = min(kEvalTile, g.P - c0);
     const int lane = threadIdx.x & 63, wave = wave_id();
     const int W = g.t.W, out = in ^ 1;
@@ -119,20 +122,49 @@ __global__ __launch_bounds__(kEvalTile *kFusedWaves) void k_stage_eval(GaArgs g,
     const int cs_k = w == 0 ? CS_EVALS : (w == 1 ? CS_SCAN : (w == 2 ? CS_XO_TAKEN : CS_XO_FAIL));
     unsigned long long *cs = g.cstat + (int64_t)c * CS_COUNT;
     const unsigned long long cs_old = cs[cs_k];
+    // partial sums of client tile w (a clamped load, always issued; tile t
+    // of chromosome x at t * ts + x * xs: the previous fused stage leaves
+    // them chromosome-major, one or two cache lines per chromosome), tile
+    // w + 16 when there are more than 16, and the evaluation's first chunks,
+    // in the same round
+    const int64_t ts = g.pcm ? 1 : g.P, xs = g.pcm ? g.TI : 1;
     unsigned long long f = 0, h = 0, sc = 0;
-    for (int t = w; t < g.TI; t += 16) {
-        f += g.part[(int64_t)t * g.P + c];
-        h += g.part[(int64_t)t * g.P + pc];
-        sc += g.spart[(int64_t)t * g.P + c];
+    {
+        const int64_t t = min(w, g.TI - 1) * ts;
+        const unsigned long long pf = g.part[t + c * xs];
+        const unsigned long long ph = g.part[t + pc * xs];
+        const uint32_t ps = g.spart[t + c * xs];
+        // masked, not branched: a branch would let the compiler move the
+        // loads behind it
+        const unsigned long long keep = w < g.TI ? ~0ull : 0ull;
+        f = pf & keep;
+        h = ph & keep;
+        sc = ps & keep;
     }
-    // the evaluation's first chunks, in the same round
+    unsigned long long f2 = 0, h2 = 0, sc2 = 0;
+    if (g.TI > 16) {  // uniform
+        const int64_t t = min(w + 16, g.TI - 1) * ts;
+        const unsigned long long pf = g.part[t + c * xs];
+        const unsigned long long ph = g.part[t + pc * xs];
+        const uint32_t ps = g.spart[t + c * xs];
+        const unsigned long long keep = w + 16 < g.TI ? ~0ull : 0ull;
+        f2 = pf & keep;
+        h2 = ph & keep;
+        sc2 = ps & keep;
+    }
     FirstChunks fc;
     eval_first_chunks<H, kFusedWaves>(a, ti, lane, wave, fc);
-    if (ga_stopped(g))  // the same flag for every wave
+    // client tiles past 32 (small populations of many clients)
+    for (int t = w + 32; t < g.TI; t += 16) {
+        f2 += g.part[t * ts + c * xs];
+        h2 += g.part[t * ts + pc * xs];
+        sc2 += g.spart[t * ts + c * xs];
+    }
+    if (!live || ga_stopped(g))  // the same for every wave of the workgroup
         return;
-    f = row_sum(f);
-    h = row_sum(h);
-    sc = row_sum(sc);
+    f = row_sum(f + f2);
+    h = row_sum(h + h2);
+    sc = row_sum(sc + sc2);
     // finish the previous stage for the chromosome and its partner
     const bool okc = okc_b != 0 && prev != OP_NONE;
     const bool take = okc && f < fin;
@@ -158,17 +190,23 @@ __global__ __launch_bounds__(kEvalTile *kFusedWaves) void k_stage_eval(GaArgs g,
     const uint32_t before = w > w0 ? excl - excl0 - lo0 : (w < w0 ? total - excl0 - lo0 + excl : 0u);
     const int tot_x = (int)(total & 0xFFFFu);
     const bool ok = valid && tot_x >= quota;
-    uint64_t tx, ty;
-    if (w == w0) {
-        const uint32_t main_ = total - lo0;  // everything before the last segment
-        tx = lowest_bits(x & hi_m, quota) |
-             lowest_bits(x & lo_m, quota - (int)(main_ & 0xFFFFu));
-        ty = lowest_bits(y & hi_m, quota) |
-             lowest_bits(y & lo_m, quota - (int)(main_ >> 16));
-    } else {
-        tx = lowest_bits(x, quota - (int)(before & 0xFFFFu));
-        ty = lowest_bits(y, quota - (int)(before >> 16));
-    }
+    // One lowest_bits per kind and lane, the same code for every lane: word
+    // w0 is walked in two segments, from bit b0 up first and below b0 last;
+    // the walk reaches the low segment only after every other gene of the
+    // kind, the whole high segment included.
+    const bool first = w == w0;
+    const uint32_t main_ = total - lo0;  // genes before the low segment of word w0
+    const uint32_t hi_n = v - vlo;       // (lane w0) genes in its high segment
+    const int hx = (int)(hi_n & 0xFFFFu), hy = (int)(hi_n >> 16);
+    const bool x_hi = quota <= hx, y_hi = quota <= hy;
+    const uint64_t sx = first ? (x_hi ? x & hi_m : x & lo_m) : x;
+    const uint64_t sy = first ? (y_hi ? y & hi_m : y & lo_m) : y;
+    const int kx = first ? (x_hi ? quota : quota - (int)(main_ & 0xFFFFu))
+                         : quota - (int)(before & 0xFFFFu);
+    const int ky = first ? (y_hi ? quota : quota - (int)(main_ >> 16))
+                         : quota - (int)(before >> 16);
+    const uint64_t tx = lowest_bits(sx, kx) | (first && !x_hi ? x & hi_m : 0ull);
+    const uint64_t ty = lowest_bits(sy, ky) | (first && !y_hi ? y & hi_m : 0ull);
     const uint64_t F = (A & ~tx) | ty;
     if (ok && inw) {
         smask[cl * SD + 2 * w] = (uint32_t)F;

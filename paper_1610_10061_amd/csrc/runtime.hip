@@ -1630,6 +1630,8 @@ hipError_t ga_stage_eval(pmp_ga *ga, const GaArgs &g, int in, int prev, int inde
     gk.part = odd ? ga->part2 : ga->part;
     gk.spart = odd ? ga->spart2 : ga->spart;
     gk.TI = index == 0 ? ga->TI : ga->fTI;  // the tiling of the sums it reads
+    gk.pcm = index != 0;  // fused launches write chromosome-major sums
+    a.pcm = 1;
     a.part = odd ? ga->part : ga->part2;
     a.spart = odd ? ga->spart : ga->spart2;
     a.clients_per_block = ga->fcpb;
@@ -1702,6 +1704,7 @@ hipError_t enqueue_generations(pmp_ga *ga, const GaArgs &g, int generations,
             GaArgs gl = g;
             if (ga->fused && X > 0) {
                 gl.TI = ga->fTI;
+                gl.pcm = 1;
                 if (X & 1) {
                     gl.part = ga->part2;
                     gl.spart = ga->spart2;
