@@ -18,7 +18,9 @@
 // selects, about 35 instructions) gives lane c its column, and the column's
 // lowest set bit is chromosome c's first open position in this chunk.  One
 // ds_bpermute then fetches each chromosome's D' entry from the lane that
-// holds it, so a chunk costs the same for all 64 chromosomes whatever their
+// holds it (the lane is bits 7:2 of its address, so position -1 needs no
+// mask: lanes without a hit discard the value), so a chunk costs the same for
+// all 64 chromosomes whatever their
 // scan lengths up to 64.  Chromosomes still unmatched go on to the next 64
 // entries.  This replaces the paper's one-thread-per-chromosome loop: lanes
 // never diverge and Pi' rows are read once per 64 chromosomes.
@@ -140,8 +142,12 @@ __device__ __forceinline__ int first_open(uint64_t row, int lane, const Transpos
 {
     uint32_t lo = (uint32_t)row, hi = (uint32_t)(row >> 32);
     transpose64(lo, hi, lane, tl);
-    const int a = lowest_bit(lo), b = lowest_bit(hi);
-    return a >= 0 ? a : (b >= 0 ? 32 + b : -1);
+    // v_ffbl gives 0xFFFFFFFF for a zero word: the unsigned minimum of the
+    // low word's position and 32 plus the high word's (saturating, so that
+    // "none" stays 0xFFFFFFFF) is the first open position, or -1
+    const uint32_t a = (uint32_t)lowest_bit(lo);
+    const uint32_t b = __builtin_elementwise_add_sat((uint32_t)lowest_bit(hi), 32u);
+    return (int)(a < b ? a : b);
 }
 
 __device__ __forceinline__ void first_open2(uint64_t row, int lane, const TransposeLanes &tl,
@@ -175,12 +181,13 @@ __device__ __forceinline__ void walk_tail(const EvalArgs &a, const uint16_t *pro
         const int32_t dist = drow[kc];
         const int hit = first_open(sT[in ? j : jz], lane, tl);
         const bool found = ((pend >> lane) & 1ull) && hit >= 0;
-        const int32_t cost = __builtin_amdgcn_ds_bpermute((hit & 63) << 2, dist);
+        const int32_t cost = __builtin_amdgcn_ds_bpermute(hit << 2, dist);
         if (found) {
             acc += (uint32_t)cost;
             scn += (uint32_t)(base + hit + 1);
         }
-        pend &= ~__builtin_amdgcn_ballot_w64(found);
+        // (= pend & ~ballot(found): found is hit >= 0 on pend's lanes)
+        pend &= ~__builtin_amdgcn_ballot_w64(hit >= 0);
     }
 }
 
@@ -453,8 +460,8 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
             const uint64_t pa = act, pb = has_b ? act : 0ull;
             const bool fa = ((pa >> lane) & 1ull) && ha >= 0;
             const bool fb = ((pb >> lane) & 1ull) && hb >= 0;
-            const int32_t ca = __builtin_amdgcn_ds_bpermute((ha & 31) << 2, d_cur);
-            const int32_t cb = __builtin_amdgcn_ds_bpermute((32 + (hb & 31)) << 2, d_cur);
+            const int32_t ca = __builtin_amdgcn_ds_bpermute(ha << 2, d_cur);
+            const int32_t cb = __builtin_amdgcn_ds_bpermute((hb << 2) + 128, d_cur);
             if (fa) {
                 acc += (uint32_t)ca;
                 scn += (uint32_t)(ha + 1);
@@ -463,8 +470,8 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
                 acc += (uint32_t)cb;
                 scn += (uint32_t)(hb + 1);
             }
-            const uint64_t ra = pa & ~__builtin_amdgcn_ballot_w64(fa);
-            const uint64_t rb = pb & ~__builtin_amdgcn_ballot_w64(fb);
+            const uint64_t ra = pa & ~__builtin_amdgcn_ballot_w64(ha >= 0);
+            const uint64_t rb = pb & ~__builtin_amdgcn_ballot_w64(hb >= 0);
             if (ra)
                 walk_tail(a, a.t.pi + (int64_t)i * a.t.pitch, a.t.ds + (int64_t)i * a.t.pitch,
                           32, ra, lane, sT, jz, tl, acc, scn);
@@ -531,21 +538,21 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int ti, int tc,
             const bool found = ((pend >> lane) & 1ull) && hit >= 0;
             if (R) {
                 const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(
-                    (hit & 63) << 2, (int)(uint32_t)(unsigned long long)ev);
+                    hit << 2, (int)(uint32_t)(unsigned long long)ev);
                 const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(
-                    (hit & 63) << 2, (int)(uint32_t)((unsigned long long)ev >> 32));
+                    hit << 2, (int)(uint32_t)((unsigned long long)ev >> 32));
                 if (found) {
                     acc += ((unsigned long long)hi << 32) | lo;
                     scn += (uint32_t)(base + hit + 1);
                 }
             } else {
-                const int32_t cost = __builtin_amdgcn_ds_bpermute((hit & 63) << 2, dist);
+                const int32_t cost = __builtin_amdgcn_ds_bpermute(hit << 2, dist);
                 if (found) {
                     acc += (uint32_t)cost;
                     scn += (uint32_t)(base + hit + 1);
                 }
             }
-            pend &= ~__builtin_amdgcn_ballot_w64(found);
+            pend &= ~__builtin_amdgcn_ballot_w64(hit >= 0);  // as in walk_tail
         }
         e_cur = e_nxt;
         k_cur = k_nxt;
