@@ -272,8 +272,12 @@ hipError_t launch_ga_stage_eval(const GaArgs &g, const EvalArgs &a, int in, int 
                                 hipEvent_t e1 = nullptr);
 hipError_t launch_ga_stage(const GaArgs &g, int in, int prev, int op,
                            int index, hipStream_t s);
-hipError_t launch_ga_best(const GaArgs &g, int fb, hipStream_t s);
+hipError_t launch_ga_best(const GaArgs &g, int fb, hipStream_t s, bool place_migrants = false);
 hipError_t launch_ga_resolve(const GaArgs &g, int in, int out, hipStream_t s);
+// launch_ga_resolve plus the next generation's population and draws
+// (k_init's work) in the same launch; launch_ga_best must then place the
+// migrants.  Only when the resolve reads and writes buffer 1.
+hipError_t launch_ga_resolve_init(const GaArgs &g, int in, int out, hipStream_t s);
 // One instance of a batched (persistent) GA launch: its GA state and its
 // evaluation tiling, with its offsets in the batch's global item ranges.
 struct BatchItem {

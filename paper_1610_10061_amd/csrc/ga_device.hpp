@@ -485,9 +485,11 @@ __device__ __forceinline__ void unrank_wave(const GaArgs &g, uint64_t r, int lan
 // sw: 2 * W words of LDS owned by the wave.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void ga_init_one(const GaArgs &g, int c, int lane,
-                                            uint64_t *sw, int part = -1)
+                                            uint64_t *sw, int part = -1, bool ahead = false)
 {
-    const uint64_t gen = g.gs[GS_GEN];
+    // ahead: the next generation's population, made while this one's last
+    // steps run (its migrants are placed by the group-best step)
+    const uint64_t gen = g.gs[GS_GEN] + (ahead ? 1u : 0u);
     if (part == 1) {  // only the operator draws
         ga_draws_one(g, gen, c, lane);
         return;
@@ -498,9 +500,11 @@ __device__ __forceinline__ void ga_init_one(const GaArgs &g, int c, int lane,
     const bool one = g.migration == PMP_MIG_ONE_BLOCK;
     const bool migrant = gen > 0 && (one ? c < g.NB : (c % g.NT) == 0);
     if (migrant) {
-        const uint64_t *src = g.gmask + (int64_t)(one ? c : c / g.NT) * W;
-        for (int w = lane; w < W; w += 64)
-            dst[w] = src[w];
+        if (!ahead) {
+            const uint64_t *src = g.gmask + (int64_t)(one ? c : c / g.NT) * W;
+            for (int w = lane; w < W; w += 64)
+                dst[w] = src[w];
+        }
     } else {
         // the subset's words live in the lanes: word w in lane w (w < 64)
         // or in the second register of lane w - 64
@@ -999,7 +1003,7 @@ __device__ __forceinline__ void ga_stage_one(const GaArgs &g, int c, int lane,
 // it then writes).  Y <= 64.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void ga_resolve_wave(const GaArgs &g, int gw, int lane, int YP,
-                                                int in, int out)
+                                                int in, int out, bool mark_improved = true)
 {
     const int W = g.t.W, Y = g.Y;
     const int64_t PY = (int64_t)g.P * Y;
@@ -1064,7 +1068,7 @@ __device__ __forceinline__ void ga_resolve_wave(const GaArgs &g, int gw, int lan
     if (valid_c && a == 0) {
         buf(g.fit, out)[cc] = taken >= 0 ? f_taken : fin;
         buf(g.ok, out)[cc] = 0;
-        if (taken >= 0)
+        if (taken >= 0 && mark_improved)
             g.improved[cc] = 1;
         if (n_cnt) {
             cs[CS_EVALS] = c_ev + (unsigned long long)n_cnt;
@@ -1118,7 +1122,8 @@ __device__ __forceinline__ void block_argmin(unsigned long long f, int idx,
 // Group best of group b (Evolve steps 7-8: least fitness, lowest slot on
 // ties) from population buffer fb, by a whole workgroup.
 __device__ __forceinline__ void ga_group_best(const GaArgs &g, int fb, int b,
-                                              unsigned long long *sc, int *si)
+                                              unsigned long long *sc, int *si,
+                                              uint64_t *next_pop = nullptr)
 {
     unsigned long long f = ~0ull;
     int idx = 0x7FFFFFFF;
@@ -1132,8 +1137,15 @@ __device__ __forceinline__ void ga_group_best(const GaArgs &g, int fb, int b,
     block_argmin(f, idx, sc, si);
     const int W = g.t.W;
     const uint64_t *src = buf(g.cur, fb) + ((int64_t)b * g.NT + si[0]) * W;
-    for (int w = threadIdx.x; w < W; w += blockDim.x)
-        g.gmask[(int64_t)b * W + w] = src[w];
+    // next_pop: the next generation's population, made ahead; the group
+    // best is its migrant (slot b * NT, or b with the one-block variant)
+    const int64_t slot = g.migration == PMP_MIG_ONE_BLOCK ? b : (int64_t)b * g.NT;
+    for (int w = threadIdx.x; w < W; w += blockDim.x) {
+        const uint64_t v = src[w];
+        g.gmask[(int64_t)b * W + w] = v;
+        if (next_pop)
+            next_pop[slot * W + w] = v;
+    }
     if (threadIdx.x == 0)
         g.gcost[b] = sc[0];
 }

@@ -250,16 +250,43 @@ __global__ __launch_bounds__(64 * kGaWaves) void k_resolve(GaArgs g, int YP, int
     ga_resolve_wave(g, gw, threadIdx.x & 63, YP, in, out);
 }
 
+// The mutation cycle resolved (as k_resolve) by workgroups [0, nres), and the
+// next generation's population and operator draws (as k_init) by the
+// others.  The two share no data: the new population goes to off[0] with
+// its flags, which this generation no longer reads, while the resolve reads
+// and writes buffer 1 (the launch is used only when that holds); the
+// `improved` flags the resolve would set are dead in this schedule and the
+// sampling resets them.  So the sampling runs beside the latency-bound
+// resolve instead of in a launch of its own; k_best places the migrants.
+__global__ __launch_bounds__(64 * kGaWaves) void k_resolve_init(GaArgs g, int YP, int in,
+                                                                int out, int nres)
+{
+    __shared__ uint64_t sw[kGaWaves][2 * kMaxWords];
+    const int wave = wave_id(), lane = threadIdx.x & 63;
+    if ((int)blockIdx.x < nres) {
+        const int gw = blockIdx.x * kGaWaves + wave;
+        if (gw * (64 / YP) >= g.P)
+            return;
+        ga_resolve_wave(g, gw, lane, YP, in, out, false);
+        return;
+    }
+    const int gw = ((int)blockIdx.x - nres) * kGaWaves + wave;
+    const int c = gw >> 1;
+    if (c >= g.P || ga_stopped(g))
+        return;
+    ga_init_one(g, c, lane, sw[wave], gw & 1, true);
+}
+
 // Group best per workgroup; workgroup 0 also takes the global best straight
 // from the population and updates the run state, so no workgroup waits for
 // another.  The others do not test the stop flag: workgroup 0 may set it in
 // this launch, and once a run has stopped its population no longer changes,
 // so rewriting a group best stores the same values.
-__global__ __launch_bounds__(1024) void k_best(GaArgs g, int fb)
+__global__ __launch_bounds__(1024) void k_best(GaArgs g, int fb, int place)
 {
     __shared__ unsigned long long sc[16];
     __shared__ int si[16];
-    ga_group_best(g, fb, blockIdx.x, sc, si);
+    ga_group_best(g, fb, blockIdx.x, sc, si, place ? g.off[0] : nullptr);
     if (blockIdx.x == 0 && !ga_stopped(g))
         ga_global_direct(g, fb, sc, si);
 }
@@ -701,11 +728,24 @@ hipError_t launch_ga_resolve(const GaArgs &g, int in, int out, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_ga_best(const GaArgs &g, int fb, hipStream_t s)
+hipError_t launch_ga_best(const GaArgs &g, int fb, hipStream_t s, bool place_migrants)
 {
     const int threads = ((g.NT + 63) / 64) * 64;
     hipLaunchKernelGGL(k_best, dim3(g.NB), dim3(threads < 64 ? 64 : threads), 0, s,
-                       g, fb);
+                       g, fb, place_migrants ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_ga_resolve_init(const GaArgs &g, int in, int out, hipStream_t s)
+{
+    int YP = 1;
+    while (YP < g.Y)
+        YP <<= 1;
+    const int per = 64 / YP;
+    const int nres = ((g.P + per - 1) / per + kGaWaves - 1) / kGaWaves;
+    const int ninit = (2 * g.P + kGaWaves - 1) / kGaWaves;
+    hipLaunchKernelGGL(k_resolve_init, dim3(nres + ninit), dim3(64 * kGaWaves), 0, s, g, YP, in,
+                       out, nres);
     return hipGetLastError();
 }
 

@@ -363,6 +363,17 @@ struct pmp_ga {
     int xstages() const { return (inst->p >= 2 && lg > 0) ? X : 0; }
     // buffer holding the population after a generation's last stage
     int final_buf() const { return ((xstages() + Y) % 2) ^ 1; }
+    // The next generation's population is made in the launch of this
+    // generation's resolve step (launch_ga_resolve_init) when nothing of this
+    // generation reads buffer 0 after the mutants are made: the whole cycle
+    // at once, no learned proposal, the resolve reading and writing buffer 1.
+    bool merge_init(const GaArgs &g) const
+    {
+        return spec() && g.L == 0 && xstages() % 2 == 0 && final_buf() == 1;
+    }
+    // the device already holds the population and draws of the generation
+    // the run is at (made ahead by the previous one's resolve launch)
+    bool init_ahead = false;
     // the per-step schedule evaluates the whole mutation cycle at once (one
     // evaluation of P x Y mutants instead of Y dependent ones); the batched
     // and persistent schedules, and the learned proposal, run it attempt by
@@ -1674,16 +1685,22 @@ hipError_t launch_train(pmp_ga *ga, const GaArgs &g, hipStream_t s)
 }
 
 // Enqueue `generations` generations of the per-step launch sequence.
+// capture: the sequence goes into a graph, which assumes that the first
+// generation's population has been made ahead whenever the schedule makes
+// populations ahead (pmp_ga_step ensures it before each replay).
 hipError_t enqueue_generations(pmp_ga *ga, const GaArgs &g, int generations,
-                               hipStream_t s)
+                               hipStream_t s, bool capture = false)
 {
     const int X = ga->xstages(), S = X + ga->Y, L = g.L;
     const bool train = L > 0 && ga->Levery > 0;
     if (ga->spec()) {
         // crossover stages as usual; stage X finishes the last crossover and
-        // makes all Y mutants; one evaluation; the cycle is resolved
+        // makes all Y mutants; one evaluation; the cycle is resolved (with
+        // the next generation's sampling in the same launch when merge)
+        const bool merge = ga->merge_init(g);
+        bool ahead = capture ? merge : (merge && ga->init_ahead);
         for (int gen = 0; gen < generations; ++gen) {
-            hipError_t e = launch_ga_init(g, s);
+            hipError_t e = ahead ? hipSuccess : launch_ga_init(g, s);
             if (e == hipSuccess)
                 e = ga_eval(ga, g, 0, s);
             for (int k = 0; k < X && e == hipSuccess; ++k) {
@@ -1726,16 +1743,22 @@ hipError_t enqueue_generations(pmp_ga *ga, const GaArgs &g, int generations,
             if (e == hipSuccess)
                 e = ga_eval(ga, g, 0, s, true);
             if (e == hipSuccess)
-                e = launch_ga_resolve(g, in ^ 1, ga->final_buf(), s);
+                e = merge ? launch_ga_resolve_init(g, in ^ 1, ga->final_buf(), s)
+                          : launch_ga_resolve(g, in ^ 1, ga->final_buf(), s);
             if (e == hipSuccess)
-                e = launch_ga_best(g, ga->final_buf(), s);
+                e = launch_ga_best(g, ga->final_buf(), s, merge);
             if (e == hipSuccess && train)
                 e = launch_train(ga, g, s);
+            if (!capture)
+                ga->init_ahead = merge && e == hipSuccess;
             if (e != hipSuccess)
                 return e;
+            ahead = merge;
         }
         return hipSuccess;
     }
+    if (!capture)
+        ga->init_ahead = false;
     for (int gen = 0; gen < generations; ++gen) {
         hipError_t e = launch_ga_init(g, s);
         if (e == hipSuccess)
@@ -1779,7 +1802,7 @@ hipError_t ensure_graph(pmp_ga *ga, const GaArgs &g)
     if (e == hipSuccess) {
         const bool prof = ga->prof;
         ga->prof = false;  // no events inside the graph
-        hipError_t ee = enqueue_generations(ga, g, ga->graph_gens, cs);
+        hipError_t ee = enqueue_generations(ga, g, ga->graph_gens, cs, true);
         ga->prof = prof;
         e = hipStreamEndCapture(cs, &graph);
         if (ee != hipSuccess)
@@ -1817,6 +1840,7 @@ pmp_status pmp_ga_step(pmp_ga *ga, int32_t generations, void *stream)
             if (batch_build(*ga->self, &one, 1) != hipSuccess)
                 return fail(PMP_ENOMEM, "persistent launch set-up");
         }
+        ga->init_ahead = false;
         HIP_TRY(mark(ga, s));
         HIP_TRY(batch_launch(*ga->self, generations, ga->max_blocks, s, true));
         HIP_TRY(mark(ga, s));
@@ -1825,6 +1849,11 @@ pmp_status pmp_ga_step(pmp_ga *ga, int32_t generations, void *stream)
     int left = generations;
     if (ga->graph_gens > 0 && !ga->prof && left >= ga->graph_gens) {
         HIP_TRY(ensure_graph(ga, g));
+        if (ga->spec() && ga->merge_init(g) && !ga->init_ahead) {
+            // the graph starts from a population made ahead
+            HIP_TRY(launch_ga_init(g, s));
+            ga->init_ahead = true;
+        }
         for (; left >= ga->graph_gens; left -= ga->graph_gens)
             HIP_TRY(hipGraphLaunch(ga->gexec, s));
     }
@@ -2121,6 +2150,8 @@ pmp_status pmp_batch_step(pmp_batch *bt, int32_t generations, void *stream)
         return PMP_OK;
     hipStream_t s = (hipStream_t)stream;
     BatchHost &bh = bt->bh;
+    for (pmp_ga *ga : bh.gas)  // the batch kernels make each generation's population
+        ga->init_ahead = false;
     if (!bt->graphs) {
         HIP_TRY(batch_enqueue(bt, generations, s, true));
         return PMP_OK;

@@ -241,3 +241,43 @@ def test_ga_paired_walk_with_long_scans(pm):
             os.environ.pop("PMP_EVAL_PAIRED", None)
         else:
             os.environ["PMP_EVAL_PAIRED"] = old
+
+
+def test_ga_population_made_ahead_across_launch_schemes(pm):
+    """The per-step schedule makes each next generation's population in the
+    launch of the current one's resolve step (the cycle at once, even X and
+    X + Y).  Runs that switch to the batch kernels, re-tune the evaluation
+    tile or replay graphs in between must still match the oracle bit for bit
+    (the batch kernels make their own populations; the autotuner samples
+    generation 0 before the run)."""
+    old = os.environ.get("PMP_GA_GRAPH_GENS")
+    os.environ["PMP_GA_GRAPH_GENS"] = "2"
+    try:
+        d = gi.graph_instance(100, 200, 7)
+        n, m = d.shape
+        p, P, NT, G, seed = 5, 256, 64, 50, 23  # X = Y = lg 64 = 6
+        print("case G100 p", p, "P", P, "NT", NT, "seed", seed, flush=True)
+        inst = pm.Instance(d, p)
+        ga = pm.GA(inst, P, NT, G, seed)
+        st = oracle.GaState(n, m, p, P, NT, G, seed, 0, 0, 0, 0, 0)
+        ga.autotune()                            # samples generation 0
+        ga.step(3)                               # graph replay + one generation
+        pm.pmp_ga_step_batch([ga.handle], 2)     # the batch kernels
+        ga.step(1)
+        ga.step(4)                               # graphs again
+        oracle.ga_run(d, st, 10)
+        pop, fit, gm, gc = ga.state()
+        np.testing.assert_array_equal(pop, st.pop)
+        np.testing.assert_array_equal(fit, st.fit)
+        np.testing.assert_array_equal(gm, st.gbest_mask)
+        np.testing.assert_array_equal(gc, st.gbest_cost)
+        mask, cost, stats = ga.best()
+        np.testing.assert_array_equal(mask, st.best_mask)
+        assert cost == st.best_cost
+        assert stats["generations"] == st.state[oracle.ST_GEN] == 10
+        assert stats["chromosome_evals"] == st.state[oracle.ST_CHROM_EVALS]
+    finally:
+        if old is None:
+            os.environ.pop("PMP_GA_GRAPH_GENS", None)
+        else:
+            os.environ["PMP_GA_GRAPH_GENS"] = old
