@@ -2003,9 +2003,21 @@ pmp_status pmp_ga_autotune(pmp_ga *ga, int32_t *clients, int32_t *waves, void *s
         }
     }
     if (!forced && !cached) {
-        // a generation-0 population to time the evaluation on
+        // a generation-0 population to time the evaluation on, and (when the
+        // mutation cycle is evaluated at once) Y copies of it standing in for
+        // the mutants, whose evaluation runs with the same waves
         GaArgs g = ga->args();
         HIP_TRY(launch_ga_init(g, s));
+        const bool spec = ga->spec();
+        const size_t PY = (size_t)P * ga->Y, W = inst->W;
+        uint64_t *stand_in = nullptr;
+        if (spec) {
+            if (ga->ensure_spec() != hipSuccess || dalloc(&stand_in, PY * W) != hipSuccess)
+                return fail(PMP_ENOMEM, "autotune mutant stand-ins");
+            for (int y = 0; y < ga->Y; ++y)
+                HIP_TRY(hipMemcpyAsync(stand_in + (size_t)y * P * W, g.off[0],
+                                       sizeof(uint64_t) * P * W, hipMemcpyDeviceToDevice, s));
+        }
         const int cands[] = {4, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512};
         const int wcands[] = {16, 8, 4};
         const int max_ti = (n + 3) / 4;
@@ -2013,15 +2025,18 @@ pmp_status pmp_ga_autotune(pmp_ga *ga, int32_t *clients, int32_t *waves, void *s
         uint32_t *spart = nullptr;
         if (dalloc(&part, (size_t)max_ti * P) || dalloc(&spart, (size_t)max_ti * P)) {
             dfree(part);
+            dfree(stand_in);
             return fail(PMP_ENOMEM, "autotune workspace");
         }
         hipEvent_t e0 = nullptr, e1 = nullptr;
         hipError_t e = hipEventCreate(&e0);
         if (e == hipSuccess)
             e = hipEventCreate(&e1);
-        // the shape's default is timed first and is only replaced by a
-        // candidate at least 3 % faster: back-to-back launches of the
-        // evaluation alone are a noisy proxy for a whole generation
+        // The shape's default is timed first and is only replaced by a
+        // candidate at least 3 % faster.  A candidate's time is the least of
+        // three trials of four back-to-back pairs (the population's
+        // evaluation, then the mutants'), so that one disturbed trial does
+        // not decide.
         const int dflt = best, dflt_w = best_w;
         float best_ms = 1e30f;
         auto time_it = [&](int cpb, int wv) -> float {
@@ -2032,19 +2047,40 @@ pmp_status pmp_ga_autotune(pmp_ga *ga, int32_t *clients, int32_t *waves, void *s
             a.clients_per_block = cpb;
             a.tiles_i = (n + cpb - 1) / cpb;
             a.waves = wv;
-            e = launch_eval(a, s);  // warm-up
-            if (e == hipSuccess)
+            EvalArgs am = a;
+            if (spec) {
+                am.masks = stand_in;
+                am.P = (int32_t)PY;
+                am.active = nullptr;
+                am.part = ga->mpart;
+                am.spart = ga->mspart;
+                am.clients_per_block = ga->spec_cpb;
+                am.tiles_c = (int32_t)((PY + kEvalTile - 1) / kEvalTile);
+                am.tiles_i = ga->spec_ti;
+            }
+            auto pair = [&]() {
+                hipError_t r = launch_eval(a, s);
+                if (r == hipSuccess && spec)
+                    r = launch_eval(am, s);
+                return r;
+            };
+            e = pair();  // warm-up
+            float least = 1e30f;
+            for (int trial = 0; trial < 3 && e == hipSuccess; ++trial) {
                 e = hipEventRecord(e0, s);
-            for (int rep = 0; rep < 5 && e == hipSuccess; ++rep)
-                e = launch_eval(a, s);
-            if (e == hipSuccess)
-                e = hipEventRecord(e1, s);
-            if (e == hipSuccess)
-                e = hipEventSynchronize(e1);
-            float ms = 0;
-            if (e == hipSuccess)
-                e = hipEventElapsedTime(&ms, e0, e1);
-            return e == hipSuccess ? ms : 1e30f;
+                for (int rep = 0; rep < 4 && e == hipSuccess; ++rep)
+                    e = pair();
+                if (e == hipSuccess)
+                    e = hipEventRecord(e1, s);
+                if (e == hipSuccess)
+                    e = hipEventSynchronize(e1);
+                float ms = 0;
+                if (e == hipSuccess)
+                    e = hipEventElapsedTime(&ms, e0, e1);
+                if (e == hipSuccess && ms < least)
+                    least = ms;
+            }
+            return e == hipSuccess ? least : 1e30f;
         };
         best_ms = time_it(dflt, dflt_w);
         for (int wv : wcands) {
@@ -2072,6 +2108,7 @@ pmp_status pmp_ga_autotune(pmp_ga *ga, int32_t *clients, int32_t *waves, void *s
             (void)hipEventDestroy(e1);
         dfree(part);
         dfree(spart);
+        dfree(stand_in);
         if (e != hipSuccess)
             return fail(PMP_EDEVICE, "autotune: %s", hipGetErrorString(e));
         std::lock_guard<std::mutex> lock(mu);
