@@ -636,6 +636,8 @@ __device__ __forceinline__ bool crossover_wave(const WaveWords &A,
     uint32_t v[2] = {0, 0};
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
+        if (h == 1 && W <= 64)  // uniform: no second register
+            break;
         const int r = lane + 64 * h;
         int w = w0 + r;
         if (w >= W)
@@ -653,8 +655,8 @@ __device__ __forceinline__ bool crossover_wave(const WaveWords &A,
     }
     const uint32_t inc0 = wave_scan_incl(v[0], lane);
     const uint32_t tot0 = (uint32_t)__builtin_amdgcn_readlane((int)inc0, 63);
-    const uint32_t inc1 = wave_scan_incl(v[1], lane) + tot0;
-    const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)inc1, 63);
+    const uint32_t inc1 = W > 64 ? wave_scan_incl(v[1], lane) + tot0 : tot0;
+    const uint32_t tot = W > 64 ? (uint32_t)__builtin_amdgcn_readlane((int)inc1, 63) : tot0;
     const int main_x = (int)(tot & 0xFFFFu), main_y = (int)(tot >> 16);
     const int differ = main_x + __builtin_popcountll(xl);
     if (differ < quota)
@@ -697,6 +699,8 @@ __device__ __forceinline__ bool mutate_wave(const WaveWords &A, const Out &F,
     bool changed = false;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
+        if (h == 1 && W <= 64)  // uniform: no second register
+            break;
         const int w = lane + 64 * h;
         const int q0 = w * 64;
         const int q1 = min(m, q0 + 64);
@@ -704,7 +708,11 @@ __device__ __forceinline__ bool mutate_wave(const WaveWords &A, const Out &F,
         // every lane takes part in the shuffles; only words < W are kept
         const bool inside = w < W && qa < qb;
         const int nin = inside ? qb - qa : 1;
-        const int s0 = inside ? lo + (((qa - lo - move) % L) + L) % L : lo;
+        // source of bit qa: lo + (qa - lo - move) mod L; with qa - lo in
+        // [0, L) and the drawn move in [1, L) one conditional add reduces it
+        int t = qa - lo - move;
+        t += t < 0 ? L : 0;
+        const int s0 = inside ? lo + t : lo;
         const uint64_t part = cyclic_bits(A, W, lo, hi, s0, nin);
         if (w < W) {
             uint64_t val = A.v[h];
