@@ -113,17 +113,26 @@ __device__ __forceinline__ void wave_lds_fence()
 
 // The k lowest set bits of x (all of x when it has no more than k, none
 // when k <= 0).  No branches: lanes of a wave seldom agree on the cases.
+// The half holding the k-th set bit is found from the low half's count,
+// then the bit within that half by a 5-step search on 32-bit popcounts.
 __device__ __forceinline__ uint64_t lowest_bits(uint64_t x, int k)
 {
-    // largest q with popcount(x below bit q) < k; the k-th set bit is at q
+    const uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+    const int nlo = __builtin_popcount(lo);
+    const bool in_lo = k <= nlo;
+    const uint32_t v = in_lo ? lo : hi;
+    const int kk = in_lo ? k : k - nlo;
+    // largest q with popcount(v below bit q) < kk; the kk-th set bit of v
+    // is at q
     int q = 0;
 #pragma unroll
-    for (int step = 32; step > 0; step >>= 1) {
+    for (int step = 16; step > 0; step >>= 1) {
         const int t = q + step;
-        if (__builtin_popcountll(x & ((1ull << t) - 1ull)) < k)
+        if (__builtin_popcount(v & ((1u << t) - 1u)) < kk)
             q = t;
     }
-    const uint64_t cut = q >= 63 ? x : (x & ((1ull << (q + 1)) - 1ull));
+    const uint32_t keep = q >= 31 ? ~0u : ((2u << q) - 1u);  // bits 0..q
+    const uint64_t cut = in_lo ? (uint64_t)(lo & keep) : (((uint64_t)(hi & keep) << 32) | lo);
     return k <= 0 ? 0ull : (__builtin_popcountll(x) <= k ? x : cut);
 }
 
