@@ -60,7 +60,7 @@ WORKLOAD = {
     "n": 900, "m": 900, "p": 90, "edges": 16200, "population": 1024,
     "group_size": 256, "generations": 500,
 }
-PROFILE_GENS = 10
+PROFILE_GENS = 4
 METRIC = ("client×chromosome fitness evals/s; time-to-best, plain vs "
           "learned-proposal GA")
 

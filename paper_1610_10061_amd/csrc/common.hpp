@@ -171,6 +171,16 @@ enum GaStat : int {
     CS_COUNT = 9
 };
 
+// A run's report, gathered on the device so that the host reads it in one
+// copy: the run state, the counters summed over the population, the error
+// words (OR-ed), the best mask.
+enum GaReport : int {
+    RP_GS = 0,
+    RP_TOT = RP_GS + GS_COUNT,
+    RP_ERR = RP_TOT + CS_COUNT,
+    RP_MASK = RP_ERR + 1  // then W words
+};
+
 // Kinds of the operator a stage kernel finishes (prev) and starts (op).
 // OP_MUT_ALL: every attempt of the mutation cycle at once (the mutants of
 // one parent; see ga_resolve_one).
@@ -278,6 +288,9 @@ hipError_t launch_ga_resolve(const GaArgs &g, int in, int out, hipStream_t s);
 // (k_init's work) in the same launch; launch_ga_best must then place the
 // migrants.  Only when the resolve reads and writes buffer 1.
 hipError_t launch_ga_resolve_init(const GaArgs &g, int in, int out, hipStream_t s);
+// The report (GaReport layout) into out; err1 may be null.
+hipError_t launch_ga_report(const GaArgs &g, const uint32_t *err0, const uint32_t *err1,
+                            unsigned long long *out, hipStream_t s);
 // One instance of a batched (persistent) GA launch: its GA state and its
 // evaluation tiling, with its offsets in the batch's global item ranges.
 struct BatchItem {

@@ -736,6 +736,54 @@ hipError_t launch_ga_best(const GaArgs &g, int fb, hipStream_t s, bool place_mig
     return hipGetLastError();
 }
 
+namespace {
+
+// One workgroup: counter totals by a strided sum and an LDS reduction per
+// counter, then the run state, the error words and the best mask.
+__global__ __launch_bounds__(256) void k_report(GaArgs g, const uint32_t *err0,
+                                                const uint32_t *err1, unsigned long long *out)
+{
+    __shared__ unsigned long long sum[CS_COUNT][256];
+    unsigned long long t[CS_COUNT];
+#pragma unroll
+    for (int k = 0; k < CS_COUNT; ++k)
+        t[k] = 0;
+    for (int c = threadIdx.x; c < g.P; c += 256) {
+#pragma unroll
+        for (int k = 0; k < CS_COUNT; ++k)
+            t[k] += g.cstat[(int64_t)c * CS_COUNT + k];
+    }
+#pragma unroll
+    for (int k = 0; k < CS_COUNT; ++k)
+        sum[k][threadIdx.x] = t[k];
+    __syncthreads();
+    for (int half = 128; half > 0; half >>= 1) {
+        if (threadIdx.x < half) {
+#pragma unroll
+            for (int k = 0; k < CS_COUNT; ++k)
+                sum[k][threadIdx.x] += sum[k][threadIdx.x + half];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < CS_COUNT)
+        out[RP_TOT + threadIdx.x] = sum[threadIdx.x][0];
+    if (threadIdx.x < GS_COUNT)
+        out[RP_GS + threadIdx.x] = g.gs[threadIdx.x];
+    if (threadIdx.x == 0)
+        out[RP_ERR] = (unsigned long long)(*err0 | (err1 ? *err1 : 0u));
+    for (int w = threadIdx.x; w < g.t.W; w += 256)
+        out[RP_MASK + w] = g.best_mask[w];
+}
+
+}  // namespace
+
+hipError_t launch_ga_report(const GaArgs &g, const uint32_t *err0, const uint32_t *err1,
+                            unsigned long long *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_report, dim3(1), dim3(256), 0, s, g, err0, err1, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_ga_resolve_init(const GaArgs &g, int in, int out, hipStream_t s)
 {
     int YP = 1;

@@ -328,6 +328,7 @@ struct pmp_ga {
     unsigned long long *gcost = nullptr, *gs = nullptr, *cstat = nullptr;
     uint32_t *arrive = nullptr;
     uint32_t *bar = nullptr;
+    unsigned long long *report = nullptr;  // GaReport layout, RP_MASK + W words
     bool persistent = false;  // one persistent launch per pmp_ga_step call
     BatchHost *self = nullptr;  // this run as a batch of one
     // graph of `graph_gens` generations of the per-step launch sequence
@@ -1433,6 +1434,7 @@ void pmp_ga_destroy(pmp_ga *ga)
     dfree(ga->cstat);
     dfree(ga->arrive);
     dfree(ga->bar);
+    dfree(ga->report);
     ga->free_learned();
     if (ga->self) {
         ga->self->release();
@@ -1503,7 +1505,7 @@ pmp_status pmp_ga_create(pmp_instance *inst, const pmp_ga_params *prm,
           dalloc(&ga->gmask, (size_t)ga->NB * W) || dalloc(&ga->best, W) ||
           dalloc(&ga->gcost, (size_t)ga->NB) || dalloc(&ga->gs, GS_COUNT) ||
           dalloc(&ga->cstat, (size_t)P * CS_COUNT) || dalloc(&ga->arrive, 1) ||
-          dalloc(&ga->bar, kBarrierWords) ||
+          dalloc(&ga->bar, kBarrierWords) || dalloc(&ga->report, (size_t)RP_MASK + W) ||
           (!binom.empty() && dalloc(&ga->binom, binom.size()));
     if (bad) {
         pmp_ga_destroy(ga);
@@ -1650,18 +1652,46 @@ hipError_t ga_stage_eval(pmp_ga *ga, const GaArgs &g, int in, int prev, int inde
     return launch_ga_stage_eval(gk, a, in, prev, index, s, e0, e1);
 }
 
-// Host-side totals of the per-chromosome counters.
-hipError_t ga_counters(pmp_ga *ga, unsigned long long tot[CS_COUNT])
+// The run's report (GaReport layout) read into `out` with one copy after the
+// work on stream s: gathered by a kernel, copied through pinned staging
+// memory shared by the process (a few hundred bytes; calls serialize on it).
+hipError_t ga_report(pmp_ga *ga, hipStream_t s, std::vector<unsigned long long> &out)
 {
-    const size_t P = ga->prm.population;
-    std::vector<unsigned long long> cs(P * CS_COUNT);
-    hipError_t e = hipMemcpy(cs.data(), ga->cstat, sizeof(unsigned long long) * cs.size(),
-                             hipMemcpyDeviceToHost);
+    static std::mutex mu;
+    static unsigned long long *staging = nullptr;
+    static size_t cap = 0;
+    const size_t words = (size_t)RP_MASK + ga->inst->W;
+    std::lock_guard<std::mutex> lock(mu);
+    if (cap < words) {
+        if (staging)
+            (void)hipHostFree(staging);
+        staging = nullptr;
+        cap = 0;
+        hipError_t e = hipHostMalloc((void **)&staging, sizeof(unsigned long long) * words,
+                                     hipHostMallocDefault);
+        if (e != hipSuccess)
+            return e;
+        cap = words;
+    }
+    hipError_t e = launch_ga_report(ga->args(), ga->inst->err,
+                                    ga->self ? ga->self->d_err : nullptr, ga->report, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(staging, ga->report, sizeof(unsigned long long) * words,
+                           hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e == hipSuccess)
+        out.assign(staging, staging + words);
+    return e;
+}
+
+// Totals of the per-chromosome counters.
+hipError_t ga_counters(pmp_ga *ga, unsigned long long tot[CS_COUNT], hipStream_t s = nullptr)
+{
+    std::vector<unsigned long long> r;
+    const hipError_t e = ga_report(ga, s, r);
     for (int k = 0; k < CS_COUNT; ++k)
-        tot[k] = 0;
-    for (size_t c = 0; c < P; ++c)
-        for (int k = 0; k < CS_COUNT; ++k)
-            tot[k] += cs[c * CS_COUNT + k];
+        tot[k] = e == hipSuccess ? r[RP_TOT + k] : 0ull;
     return e;
 }
 
@@ -1858,6 +1888,10 @@ pmp_status pmp_ga_step(pmp_ga *ga, int32_t generations, void *stream)
             HIP_TRY(hipGraphLaunch(ga->gexec, s));
     }
     HIP_TRY(enqueue_generations(ga, g, left, s));
+    // Profiled generations are launched one by one; build the graph of the
+    // later ones now, on the host, while these run on the device.
+    if (ga->prof && ga->graph_gens > 0)
+        HIP_TRY(ensure_graph(ga, g));
     return PMP_OK;
 }
 
@@ -1867,17 +1901,16 @@ pmp_status pmp_ga_best(pmp_ga *ga, uint64_t *mask, int64_t *cost,
     if (!ga)
         return fail(PMP_EINVAL, "ga is NULL");
     hipStream_t s = (hipStream_t)stream;
-    HIP_TRY(hipStreamSynchronize(s));
-    unsigned long long gs[GS_COUNT];
-    HIP_TRY(hipMemcpy(gs, ga->gs, sizeof gs, hipMemcpyDeviceToHost));
+    std::vector<unsigned long long> r;
+    HIP_TRY(ga_report(ga, s, r));
+    const unsigned long long *gs = r.data() + RP_GS;
     if (mask)
-        HIP_TRY(hipMemcpy(mask, ga->best, sizeof(uint64_t) * ga->inst->W,
-                          hipMemcpyDeviceToHost));
+        for (int w = 0; w < ga->inst->W; ++w)
+            mask[w] = r[RP_MASK + w];
     if (cost)
         *cost = (int64_t)gs[GS_BEST];
     if (stats) {
-        unsigned long long tot[CS_COUNT];
-        HIP_TRY(ga_counters(ga, tot));
+        const unsigned long long *tot = r.data() + RP_TOT;
         stats->generations = (int64_t)gs[GS_GEN];
         stats->saturation_count = (int64_t)gs[GS_SAT];
         stats->done = (int64_t)gs[GS_DONE];
@@ -1892,14 +1925,7 @@ pmp_status pmp_ga_best(pmp_ga *ga, uint64_t *mask, int64_t *cost,
         stats->swap_taken = (int64_t)tot[CS_SWAP_TAKEN];
         stats->speculative_evals = (int64_t)tot[CS_SPEC_EVALS];
     }
-    uint32_t herr = 0;
-    HIP_TRY(hipMemcpy(&herr, ga->inst->err, sizeof herr, hipMemcpyDeviceToHost));
-    if (ga->self) {
-        uint32_t berr = 0;
-        HIP_TRY(hipMemcpy(&berr, ga->self->d_err, sizeof berr, hipMemcpyDeviceToHost));
-        herr |= berr;
-    }
-    return status_from_err(herr);
+    return status_from_err((uint32_t)r[RP_ERR]);
 }
 
 pmp_status pmp_ga_state(pmp_ga *ga, uint64_t *population, int64_t *fitness,
@@ -1945,15 +1971,14 @@ pmp_status pmp_ga_profile_read(pmp_ga *ga, pmp_profile *out, void *stream)
     if (!ga || !out)
         return fail(PMP_EINVAL, "ga or out is NULL");
     hipStream_t s = (hipStream_t)stream;
-    HIP_TRY(hipStreamSynchronize(s));
+    unsigned long long tot[CS_COUNT];
+    HIP_TRY(ga_counters(ga, tot, s));  // (waits for the stream)
     double ms = 0;
     for (size_t k = 0; k + 1 < ga->ev_used; k += 2) {
         float t = 0;
         HIP_TRY(hipEventElapsedTime(&t, ga->ev[k], ga->ev[k + 1]));
         ms += t;
     }
-    unsigned long long tot[CS_COUNT];
-    HIP_TRY(ga_counters(ga, tot));
     // every evaluation the kernel ran, the mutation cycle's speculative ones
     // included
     const int64_t evals = (int64_t)(tot[CS_EVALS] + tot[CS_SPEC_EVALS] - ga->base_evals);
