@@ -1172,9 +1172,9 @@ __device__ __forceinline__ void ga_group_best(const GaArgs &g, int fb, int b,
 // the least cost found and how to load word w of its mask.
 template <class LoadWord>
 __device__ __forceinline__ void ga_update_state(const GaArgs &g, unsigned long long cost,
-                                                LoadWord load)
+                                                LoadWord load, unsigned long long prev_best)
 {
-    const bool better = cost < g.gs[GS_BEST];
+    const bool better = cost < prev_best;
     const int W = g.t.W;
     if (better)
         for (int w = threadIdx.x; w < W; w += blockDim.x)
@@ -1202,6 +1202,7 @@ __device__ __forceinline__ void ga_update_state(const GaArgs &g, unsigned long l
 __device__ __forceinline__ void ga_global_direct(const GaArgs &g, int fb,
                                                  unsigned long long *sc, int *si)
 {
+    const unsigned long long prev_best = g.gs[GS_BEST];  // loaded with the fitness
     unsigned long long f = ~0ull;
     int idx = 0x7FFFFFFF;
     for (int t = threadIdx.x; t < g.P; t += blockDim.x) {
@@ -1213,7 +1214,7 @@ __device__ __forceinline__ void ga_global_direct(const GaArgs &g, int fb,
     }
     block_argmin(f, idx, sc, si);
     const uint64_t *src = buf(g.cur, fb) + (int64_t)si[0] * g.t.W;
-    ga_update_state(g, sc[0], [src](int w) { return src[w]; });
+    ga_update_state(g, sc[0], [src](int w) { return src[w]; }, prev_best);
 }
 
 // Global best, saturation count and stop test (Section 3.1 host steps
@@ -1221,6 +1222,7 @@ __device__ __forceinline__ void ga_global_direct(const GaArgs &g, int fb,
 __device__ __forceinline__ void ga_global(const GaArgs &g,
                                           unsigned long long *sc, int *si)
 {
+    const unsigned long long prev_best = g.gs[GS_BEST];
     unsigned long long f = ~0ull;
     int idx = 0x7FFFFFFF;
     for (int k = threadIdx.x; k < g.NB; k += blockDim.x) {
@@ -1235,7 +1237,7 @@ __device__ __forceinline__ void ga_global(const GaArgs &g,
     const uint64_t *src = g.gmask + (int64_t)si[0] * g.t.W;
     ga_update_state(g, sc[0], [src](int w) {
         return __hip_atomic_load(src + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    });
+    }, prev_best);
 }
 
 }  // namespace pmp

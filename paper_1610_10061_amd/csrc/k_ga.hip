@@ -277,17 +277,19 @@ __global__ __launch_bounds__(64 * kGaWaves) void k_resolve_init(GaArgs g, int YP
     ga_init_one(g, c, lane, sw[wave], gw & 1, true);
 }
 
-// Group best per workgroup; workgroup 0 also takes the global best straight
-// from the population and updates the run state, so no workgroup waits for
-// another.  The others do not test the stop flag: workgroup 0 may set it in
-// this launch, and once a run has stopped its population no longer changes,
-// so rewriting a group best stores the same values.
+// Group best per workgroup b < NB; workgroup NB takes the global best
+// straight from the population and updates the run state at the same time,
+// so no workgroup waits for another.  The group-best workgroups do not test
+// the stop flag: workgroup NB may set it in this launch, and once a run has
+// stopped its population no longer changes, so rewriting a group best
+// stores the same values.
 __global__ __launch_bounds__(1024) void k_best(GaArgs g, int fb, int place)
 {
     __shared__ unsigned long long sc[16];
     __shared__ int si[16];
-    ga_group_best(g, fb, blockIdx.x, sc, si, place ? g.off[0] : nullptr);
-    if (blockIdx.x == 0 && !ga_stopped(g))
+    if ((int)blockIdx.x < g.NB)
+        ga_group_best(g, fb, blockIdx.x, sc, si, place ? g.off[0] : nullptr);
+    else if (!ga_stopped(g))
         ga_global_direct(g, fb, sc, si);
 }
 
@@ -731,7 +733,7 @@ hipError_t launch_ga_resolve(const GaArgs &g, int in, int out, hipStream_t s)
 hipError_t launch_ga_best(const GaArgs &g, int fb, hipStream_t s, bool place_migrants)
 {
     const int threads = ((g.NT + 63) / 64) * 64;
-    hipLaunchKernelGGL(k_best, dim3(g.NB), dim3(threads < 64 ? 64 : threads), 0, s,
+    hipLaunchKernelGGL(k_best, dim3(g.NB + 1), dim3(threads < 64 ? 64 : threads), 0, s,
                        g, fb, place_migrants ? 1 : 0);
     return hipGetLastError();
 }
