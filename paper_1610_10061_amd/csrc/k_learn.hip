@@ -593,6 +593,28 @@ __global__ void k_near(const uint16_t *pi, int pitch, int n, int L, uint32_t *ne
     atomicAdd(nearc + pi[i * pitch + s], 1u);
 }
 
+// report[0] = sum of the column sums, report[1] = the error word (one
+// workgroup).
+__global__ __launch_bounds__(256) void k_total(const unsigned long long *colsum, int m,
+                                               const uint32_t *err, unsigned long long *report)
+{
+    __shared__ unsigned long long part[256];
+    unsigned long long t = 0;
+    for (int j = threadIdx.x; j < m; j += 256)
+        t += colsum[j];
+    part[threadIdx.x] = t;
+    __syncthreads();
+    for (int half = 128; half > 0; half >>= 1) {
+        if (threadIdx.x < half)
+            part[threadIdx.x] += part[threadIdx.x + half];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        report[0] = part[0];
+        report[1] = *err;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_features(const Tables &t, const uint64_t *masks, int P, const FeatCtx &ctx,
@@ -641,7 +663,7 @@ hipError_t launch_propose(const LearnArgs &a, int in, hipStream_t s)
 
 hipError_t launch_static_sums(const int32_t *d, int64_t ld, int n, int m, const uint16_t *pi,
                               int pitch, int L, unsigned long long *colsum, uint32_t *nearc,
-                              hipStream_t s)
+                              const uint32_t *err, unsigned long long *report, hipStream_t s)
 {
     const int slices = n < 64 ? n : 64;
     hipLaunchKernelGGL(k_colsum, dim3((m + 255) / 256, slices), dim3(256), 0, s, d, ld, n, m,
@@ -652,6 +674,7 @@ hipError_t launch_static_sums(const int32_t *d, int64_t ld, int n, int m, const 
     const int64_t cells = (int64_t)n * L;
     hipLaunchKernelGGL(k_near, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, s, pi,
                        pitch, n, L, nearc);
+    hipLaunchKernelGGL(k_total, dim3(1), dim3(256), 0, s, colsum, m, err, report);
     return hipGetLastError();
 }
 

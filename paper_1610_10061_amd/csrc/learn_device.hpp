@@ -234,10 +234,11 @@ hipError_t launch_features(const Tables &t, const uint64_t *masks, int P, const 
 // The proposal of one generation (candidates, walk, scoring and picks);
 // `in` is the buffer the finished crossover stages read.
 hipError_t launch_propose(const LearnArgs &a, int in, hipStream_t s);
-// Column sums of d and near counts (first L entries of the Pi' rows).
+// Column sums of d and near counts (first L entries of the Pi' rows); then
+// report[0] = the sum of d, report[1] = the error word err (one read-back).
 hipError_t launch_static_sums(const int32_t *d, int64_t ld, int n, int m, const uint16_t *pi,
                               int pitch, int L, unsigned long long *colsum, uint32_t *nearc,
-                              hipStream_t s);
+                              const uint32_t *err, unsigned long long *report, hipStream_t s);
 
 // Load a chromosome into LDS (as 32-bit words) and check it: exactly p
 // open facilities, no bits at positions >= m.  Block-wide; returns the

@@ -63,6 +63,95 @@ void dfree(T *&p)
     p = nullptr;
 }
 
+// Pinned host memory shared by the process for small read-backs (a few
+// hundred bytes), used under its lock: one asynchronous copy on the
+// caller's stream, then a wait for that stream.
+struct Staging {
+    std::mutex mu;
+    unsigned long long *host = nullptr;
+    size_t cap = 0;
+
+    // (called with mu held)
+    hipError_t reserve(size_t words)
+    {
+        if (cap >= words)
+            return hipSuccess;
+        if (host)
+            (void)hipHostFree(host);
+        host = nullptr;
+        cap = 0;
+        const hipError_t e =
+            hipHostMalloc((void **)&host, sizeof(unsigned long long) * words, hipHostMallocDefault);
+        if (e == hipSuccess)
+            cap = words;
+        return e;
+    }
+    // words device words after the work on s, into out
+    hipError_t read(const unsigned long long *dev, size_t words, hipStream_t s,
+                    std::vector<unsigned long long> &out)
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        hipError_t e = reserve(words);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(host, dev, sizeof(unsigned long long) * words,
+                               hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(s);
+        if (e == hipSuccess)
+            out.assign(host, host + words);
+        return e;
+    }
+};
+
+Staging &staging()
+{
+    static Staging st;
+    return st;
+}
+
+// Fixed-size buffers of one object carved out of a single device
+// allocation (one hipMalloc and one hipFree instead of one per buffer).
+// Members are listed with add(), then carve() allocates and assigns them;
+// release() frees the block and clears the members.  Buffers that are
+// reallocated later keep allocations of their own.
+struct Arena {
+    void *base = nullptr;
+    std::vector<std::pair<void **, size_t>> members;
+
+    template <class T>
+    void add(T **p, size_t count)
+    {
+        members.emplace_back(reinterpret_cast<void **>(p),
+                             sizeof(T) * (count == 0 ? 1 : count));
+    }
+    hipError_t carve()
+    {
+        size_t total = 0;
+        for (const auto &m : members)
+            total += (m.second + 255) & ~size_t(255);
+        hipError_t e = hipMalloc(&base, total);
+        if (e != hipSuccess) {
+            base = nullptr;
+            return e;
+        }
+        char *q = static_cast<char *>(base);
+        for (const auto &m : members) {
+            *m.first = q;
+            q += (m.second + 255) & ~size_t(255);
+        }
+        return hipSuccess;
+    }
+    void release()
+    {
+        for (const auto &m : members)
+            *m.first = nullptr;
+        if (base)
+            (void)hipFree(base);
+        base = nullptr;
+        members.clear();
+    }
+};
+
 int env_int(const char *name, int dflt)
 {
     const char *v = getenv(name);
@@ -234,6 +323,8 @@ struct pmp_instance {
     uint32_t *nearc = nullptr;             // m near counts
     int64_t total = 0;                     // sum of d
     int32_t near_len = 1;                  // ceil(m / p)
+    unsigned long long *dtotal = nullptr;  // the sum and the error word, read back together
+    Arena arena;                           // pi, ds, delta, err, colsum, nearc, dtotal
 
     Tables tables() const
     {
@@ -329,6 +420,7 @@ struct pmp_ga {
     uint32_t *arrive = nullptr;
     uint32_t *bar = nullptr;
     unsigned long long *report = nullptr;  // GaReport layout, RP_MASK + W words
+    Arena arena;  // the fixed-size buffers above (not part/spart, mut, mpart)
     bool persistent = false;  // one persistent launch per pmp_ga_step call
     BatchHost *self = nullptr;  // this run as a batch of one
     // graph of `graph_gens` generations of the per-step launch sequence
@@ -681,18 +773,13 @@ void pmp_instance_destroy(pmp_instance *inst)
 {
     if (!inst)
         return;
-    dfree(inst->pi);
-    dfree(inst->ds);
-    dfree(inst->delta);
-    dfree(inst->err);
+    inst->arena.release();
     dfree(inst->h_masks);
     dfree(inst->h_fit);
     dfree(inst->h_scan);
     dfree(inst->part);
     dfree(inst->spart);
     dfree(inst->tg);
-    dfree(inst->colsum);
-    dfree(inst->nearc);
     delete inst;
 }
 
@@ -731,10 +818,14 @@ pmp_status pmp_preprocess(const int32_t *d, int64_t ld, int32_t n, int32_t m,
     inst->pitch = ((inst->K + 63) / 64) * 64;
     const size_t cells = (size_t)n * inst->pitch;
     inst->near_len = (m + p - 1) / p;
-    if (dalloc(&inst->pi, cells) != hipSuccess || dalloc(&inst->ds, cells) != hipSuccess ||
-        dalloc(&inst->delta, cells) != hipSuccess || dalloc(&inst->err, 1) != hipSuccess ||
-        dalloc(&inst->colsum, (size_t)m) != hipSuccess ||
-        dalloc(&inst->nearc, (size_t)m) != hipSuccess) {
+    inst->arena.add(&inst->pi, cells);
+    inst->arena.add(&inst->ds, cells);
+    inst->arena.add(&inst->delta, cells);
+    inst->arena.add(&inst->err, 1);
+    inst->arena.add(&inst->colsum, (size_t)m);
+    inst->arena.add(&inst->nearc, (size_t)m);
+    inst->arena.add(&inst->dtotal, 2);
+    if (inst->arena.carve() != hipSuccess) {
         pmp_instance_destroy(inst);
         return fail(PMP_ENOMEM, "device allocation of tables (%zu cells)", cells);
     }
@@ -782,29 +873,23 @@ pmp_status pmp_preprocess(const int32_t *d, int64_t ld, int32_t n, int32_t m,
             st = fail(PMP_EDEVICE, "sort kernel launch: %s", hipGetErrorString(e));
             break;
         }
-        // static sums of the learned proposal's features
-        std::vector<unsigned long long> cs((size_t)m);
+        // static sums of the learned proposal's features; the sum of d and
+        // the error word come back in one copy
         e = hipMemsetAsync(inst->colsum, 0, sizeof(unsigned long long) * m, s);
         if (e == hipSuccess)
             e = hipMemsetAsync(inst->nearc, 0, sizeof(uint32_t) * m, s);
         if (e == hipSuccess)
             e = launch_static_sums(src, src_ld, n, m, inst->pi, inst->pitch, inst->near_len,
-                                   inst->colsum, inst->nearc, s);
+                                   inst->colsum, inst->nearc, inst->err, inst->dtotal, s);
+        std::vector<unsigned long long> rb;
         if (e == hipSuccess)
-            e = hipMemcpyAsync(cs.data(), inst->colsum, sizeof(unsigned long long) * m,
-                               hipMemcpyDeviceToHost, s);
-        uint32_t herr = 0;
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(&herr, inst->err, sizeof herr, hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess)
-            e = hipStreamSynchronize(s);
+            e = staging().read(inst->dtotal, 2, s, rb);
         if (e != hipSuccess) {
             st = fail(PMP_EDEVICE, "preprocess: %s", hipGetErrorString(e));
             break;
         }
-        for (unsigned long long v : cs)
-            inst->total += (int64_t)v;
-        st = status_from_err(herr);
+        inst->total = (int64_t)rb[0];
+        st = status_from_err((uint32_t)rb[1]);
     } while (0);
     dfree(dd);
     dfree(wide);
@@ -1410,6 +1495,7 @@ void pmp_ga_destroy(pmp_ga *ga)
 {
     if (!ga)
         return;
+    ga->arena.release();  // (clears its members: the frees below skip them)
     for (int k = 0; k < 2; ++k) {
         dfree(ga->cur[k]);
         dfree(ga->off[k]);
@@ -1492,21 +1578,29 @@ pmp_status pmp_ga_create(pmp_instance *inst, const pmp_ga_params *prm,
     ga->fcpb = fused_clients_per_block(inst->n, P);
     ga->fTI = (inst->n + ga->fcpb - 1) / ga->fcpb;
     const size_t W = inst->W, PW = (size_t)P * W;
-    bool bad = false;
-    for (int k = 0; k < 2; ++k)
-        bad = bad || dalloc(&ga->cur[k], PW) || dalloc(&ga->off[k], PW) ||
-              dalloc(&ga->fit[k], (size_t)P) || dalloc(&ga->ok[k], (size_t)P);
-    bad = bad || dalloc(&ga->improved, (size_t)P) ||
-          dalloc(&ga->draws, (size_t)P * std::max(1, ga->X + ga->Y)) ||
-          dalloc(&ga->part, (size_t)std::max(ga->TI, ga->fTI) * P) ||
+    for (int k = 0; k < 2; ++k) {
+        ga->arena.add(&ga->cur[k], PW);
+        ga->arena.add(&ga->off[k], PW);
+        ga->arena.add(&ga->fit[k], (size_t)P);
+        ga->arena.add(&ga->ok[k], (size_t)P);
+    }
+    ga->arena.add(&ga->improved, (size_t)P);
+    ga->arena.add(&ga->draws, (size_t)P * std::max(1, ga->X + ga->Y));
+    ga->arena.add(&ga->gmask, (size_t)ga->NB * W);
+    ga->arena.add(&ga->best, W);
+    ga->arena.add(&ga->gcost, (size_t)ga->NB);
+    ga->arena.add(&ga->gs, GS_COUNT);
+    ga->arena.add(&ga->cstat, (size_t)P * CS_COUNT);
+    ga->arena.add(&ga->arrive, 1);
+    ga->arena.add(&ga->bar, kBarrierWords);
+    ga->arena.add(&ga->report, (size_t)RP_MASK + W);
+    if (!binom.empty())
+        ga->arena.add(&ga->binom, binom.size());
+    bool bad = ga->arena.carve() != hipSuccess;
+    bad = bad || dalloc(&ga->part, (size_t)std::max(ga->TI, ga->fTI) * P) ||
           dalloc(&ga->spart, (size_t)std::max(ga->TI, ga->fTI) * P) ||
           dalloc(&ga->part2, (size_t)std::max(ga->TI, ga->fTI) * P) ||
-          dalloc(&ga->spart2, (size_t)std::max(ga->TI, ga->fTI) * P) ||
-          dalloc(&ga->gmask, (size_t)ga->NB * W) || dalloc(&ga->best, W) ||
-          dalloc(&ga->gcost, (size_t)ga->NB) || dalloc(&ga->gs, GS_COUNT) ||
-          dalloc(&ga->cstat, (size_t)P * CS_COUNT) || dalloc(&ga->arrive, 1) ||
-          dalloc(&ga->bar, kBarrierWords) || dalloc(&ga->report, (size_t)RP_MASK + W) ||
-          (!binom.empty() && dalloc(&ga->binom, binom.size()));
+          dalloc(&ga->spart2, (size_t)std::max(ga->TI, ga->fTI) * P);
     if (bad) {
         pmp_ga_destroy(ga);
         return fail(PMP_ENOMEM, "GA buffers for P=%d", P);
@@ -1653,35 +1747,15 @@ hipError_t ga_stage_eval(pmp_ga *ga, const GaArgs &g, int in, int prev, int inde
 }
 
 // The run's report (GaReport layout) read into `out` with one copy after the
-// work on stream s: gathered by a kernel, copied through pinned staging
-// memory shared by the process (a few hundred bytes; calls serialize on it).
+// work on stream s: gathered by a kernel, copied through the pinned staging
+// memory.
 hipError_t ga_report(pmp_ga *ga, hipStream_t s, std::vector<unsigned long long> &out)
 {
-    static std::mutex mu;
-    static unsigned long long *staging = nullptr;
-    static size_t cap = 0;
     const size_t words = (size_t)RP_MASK + ga->inst->W;
-    std::lock_guard<std::mutex> lock(mu);
-    if (cap < words) {
-        if (staging)
-            (void)hipHostFree(staging);
-        staging = nullptr;
-        cap = 0;
-        hipError_t e = hipHostMalloc((void **)&staging, sizeof(unsigned long long) * words,
-                                     hipHostMallocDefault);
-        if (e != hipSuccess)
-            return e;
-        cap = words;
-    }
     hipError_t e = launch_ga_report(ga->args(), ga->inst->err,
                                     ga->self ? ga->self->d_err : nullptr, ga->report, s);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(staging, ga->report, sizeof(unsigned long long) * words,
-                           hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess)
-        e = hipStreamSynchronize(s);
-    if (e == hipSuccess)
-        out.assign(staging, staging + words);
+        e = staging().read(ga->report, words, s, out);
     return e;
 }
 
