@@ -61,6 +61,7 @@ WORKLOAD = {
     "group_size": 256, "generations": 500,
 }
 PROFILE_GENS = 4
+BATCH_PROFILE_GENS = 2  # batch generations whose evaluation launches are timed
 METRIC = ("client×chromosome fitness evals/s; time-to-best, plain vs "
           "learned-proposal GA")
 
@@ -210,9 +211,13 @@ def cpu_baseline(d, p, P, NT, budget_s):
 
 def leg_batch(args, specs, ds):
     """256 ragged instances (population 256 each): all preprocessed, then
-    `--batch-generations` generations of every GA run, (a) in one persistent
-    launch per step replayed from a hipGraph, (b) instance by instance with
-    pmp_ga_step.  Reports instances per second of (a) and (b)."""
+    `--batch-generations` generations of every GA run, (a) batched (one
+    batch-wide kernel per phase, a step replayed from a hipGraph), (b)
+    instance by instance with pmp_ga_step.  Reports instances per second of
+    (a) and (b), and the roofline of the batch evaluation kernel from the
+    first BATCH_PROFILE_GENS generations of (a), whose evaluation launches
+    are timed with HIP events.  --batch-only runs (a) alone, without the
+    warm-up (the command the counter runs profile)."""
     import torch
     import paper_1610_10061_amd as pm
     torch.cuda.set_device(0)
@@ -220,16 +225,24 @@ def leg_batch(args, specs, ds):
     G = args.batch_generations
     dd = [torch.from_numpy(d).cuda() for d in ds]
 
-    def run(batched, seed0):
+    def run(batched, seed0, profile=False):
         t0 = time.perf_counter()
         insts = [pm.Instance(d, s["p"], stream) for s, d in zip(specs, dd)]
         gas = [pm.GA(i, 256, 256, G, seed0 + s["index"]) for i, s in zip(insts, specs)]
         for g in gas:
             g.autotune(stream)
         t1 = time.perf_counter()
+        prof = None
         if batched:
             bt = pm.Batch(gas)
-            bt.step(G, stream)
+            pg = min(BATCH_PROFILE_GENS, G) if profile else 0
+            if pg:
+                bt.profile(True)
+                bt.step(pg, stream)
+                prof = bt.profile_read(stream)
+                bt.profile(False)
+            if G > pg:
+                bt.step(G - pg, stream)
             bt.check(stream)
         else:
             for g in gas:
@@ -244,14 +257,19 @@ def leg_batch(args, specs, ds):
             costs.append(c)
         if batched:
             bt.close()
-        return t1 - t0, t2 - t1, pairs, costs
+        return t1 - t0, t2 - t1, pairs, costs, prof
 
+    if args.batch_only:
+        log("batched (alone) ...")
+        prep_b, evo_b, pairs_b, costs_b, prof_b = run(True, 0, profile=True)
+        return {"batch_only": True, "evolve_s": evo_b, "eval_ms": prof_b[0],
+                "eval_launches": prof_b[1]}
     log("warm-up ...")
     run(True, 10_000)
     log("batched ...")
-    prep_b, evo_b, pairs_b, costs_b = run(True, 0)
+    prep_b, evo_b, pairs_b, costs_b, prof_b = run(True, 0, profile=True)
     log("one launch per instance ...")
-    prep_s, evo_s, pairs_s, costs_s = run(False, 0)
+    prep_s, evo_s, pairs_s, costs_s, _ = run(False, 0)
     assert costs_b == costs_s, "batched and per-instance runs must agree"
     return {
         "metric": "instances/s, 256 ragged instances x %d generations" % G,
@@ -269,7 +287,35 @@ def leg_batch(args, specs, ds):
                                   "pair_evals_per_s": pairs_s / evo_s},
         "speedup_evolve": evo_s / evo_b,
         "identical_results": costs_b == costs_s,
+        "roofline": batch_eval_roofline(prof_b),
     }
+
+
+def batch_eval_roofline(prof):
+    """VALU-issue roofline of the batch evaluation kernel (k_batch_eval): the
+    VALU instructions per launch that rocprofv3 counted for the same launches
+    (the first BATCH_PROFILE_GENS generations of the same batched run, case
+    batch_eval of the committed counter summary) over the launches' time
+    measured here."""
+    ms, launches = prof if prof else (0.0, 0)
+    ctr = eval_counters("batch_eval")
+    out = {"kernel": "k_batch_eval", "bound": "alu", "peak": VALU_PEAK_GIPS,
+           "unit": "G wave64 VALU instructions/s", "launches": launches,
+           "avg_launch_us": ms * 1e3 / max(launches, 1),
+           "sampled": f"evaluation launches of the first {BATCH_PROFILE_GENS} generations of "
+                      "the timed batched run (HIP events recorded by each dispatch)"}
+    if not ctr or not ms or not launches or ctr.get("dispatches") != launches:
+        out.update({"achieved": None, "frac": None, "traffic": None,
+                    "note": "no counter summary matching the kernel's sources and launches"})
+        return out
+    achieved = ctr["SQ_INSTS_VALU"] * launches / (ms / 1e3) / 1e9
+    out.update({"achieved": achieved, "frac": achieved / VALU_PEAK_GIPS,
+                "traffic": ctr.get("hbm_bytes"),
+                "counters": "profiles/k_eval_counters.json (case batch_eval)"})
+    if ctr.get("hbm_bytes") is not None:
+        gbs = ctr["hbm_bytes"] / (ms / 1e3 / launches) / 1e9
+        out["hbm_measured"] = {"GBps": gbs, "frac": gbs / HBM_PEAK_GBS}
+    return out
 
 
 LEARNED = {
@@ -844,6 +890,9 @@ def main():
     ap.add_argument("--seconds", type=float, default=2.0,
                     help="wall time of each plain / learned run (learned workload)")
     ap.add_argument("--batch-generations", type=int, default=100)
+    ap.add_argument("--batch-only", action="store_true",
+                    help="batch workload: the batched run alone, no warm-up or "
+                         "per-instance run (what the counter runs profile)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (scales the "
                          "FETCH_SIZE / WRITE_SIZE counters)")

@@ -430,6 +430,16 @@ typedef struct {
 PMP_API pmp_status pmp_ga_profile(pmp_ga *ga, int32_t enable);
 PMP_API pmp_status pmp_ga_profile_read(pmp_ga *ga, pmp_profile *out, void *stream);
 
+/* The same for a batch (per-phase kernels only): while enabled,
+ * pmp_batch_step launches its phases directly (no graph) and brackets every
+ * launch of the batch-wide evaluation kernel with HIP events.
+ * pmp_batch_profile_read waits for `stream` and returns the summed
+ * milliseconds of those launches and their number; both reset the totals.
+ * PMP_EUNSUPPORTED for a batch in persistent-kernel mode. */
+PMP_API pmp_status pmp_batch_profile(pmp_batch *batch, int32_t enable);
+PMP_API pmp_status pmp_batch_profile_read(pmp_batch *batch, double *eval_ms,
+                                          int64_t *eval_launches, void *stream);
+
 /* ===========================================================================
  * Learned swap proposal (not in the paper).  A small network scores swap
  * moves of a chromosome (close open facility j, open closed facility k) from

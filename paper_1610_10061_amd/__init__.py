@@ -25,6 +25,7 @@ __all__ = [
     "pmp_ga_state", "pmp_ga_destroy", "pmp_solve", "pmp_ga_profile",
     "pmp_ga_profile_read", "pmp_ga_autotune", "pmp_batch_create",
     "pmp_batch_step", "pmp_batch_check", "pmp_batch_destroy",
+    "pmp_batch_profile", "pmp_batch_profile_read",
     "pmp_ga_step_batch", "pmp_features", "pmp_model_create", "pmp_model_get",
     "pmp_model_set", "pmp_model_forward", "pmp_model_grad", "pmp_model_train",
     "pmp_model_destroy", "pmp_ga_set_model", "pmp_ga_replay", "pmp_exhaustive",
@@ -56,7 +57,7 @@ EXPORTS = [
     "pmp_model_forward", "pmp_model_grad", "pmp_model_train", "pmp_model_destroy",
     "pmp_ga_set_model", "pmp_ga_replay", "pmp_exhaustive", "pmp_apsp",
     "pmp_hbp_reduce", "pmp_hbp_info", "pmp_hbp_terms", "pmp_hbp_eval", "pmp_hbp_destroy",
-    "pmp_eval_population_noalloc",
+    "pmp_eval_population_noalloc", "pmp_batch_profile", "pmp_batch_profile_read",
 ]
 
 FEATURES = 16
@@ -142,6 +143,8 @@ def lib():
     L.pmp_batch_check.argtypes = [_vp, C.POINTER(_i32), _vp]
     L.pmp_batch_destroy.argtypes = [_vp]
     L.pmp_batch_destroy.restype = None
+    L.pmp_batch_profile.argtypes = [_vp, _i32]
+    L.pmp_batch_profile_read.argtypes = [_vp, C.POINTER(C.c_double), C.POINTER(_i64), _vp]
     L.pmp_ga_step_batch.argtypes = [C.POINTER(_vp), _i32, _i32, _vp]
     L.pmp_features.argtypes = [_vp, _vp, _i32, C.c_float, _vp, _u32, _vp]
     L.pmp_model_create.argtypes = [C.c_uint64, C.POINTER(_vp)]
@@ -436,6 +439,20 @@ def pmp_batch_destroy(batch):
     lib().pmp_batch_destroy(batch)
 
 
+def pmp_batch_profile(batch, enable: bool):
+    _check(lib().pmp_batch_profile(batch, 1 if enable else 0), "pmp_batch_profile")
+
+
+def pmp_batch_profile_read(batch, stream=None):
+    """(milliseconds, launches) of the batch evaluation launches since the
+    last enable or read."""
+    ms = C.c_double()
+    n = _i64()
+    _check(lib().pmp_batch_profile_read(batch, C.byref(ms), C.byref(n), _stream(stream)),
+           "pmp_batch_profile_read")
+    return ms.value, n.value
+
+
 def pmp_ga_step_batch(gas, generations, stream=None):
     _check(lib().pmp_ga_step_batch(_handles(gas), len(gas), generations, _stream(stream)),
            "pmp_ga_step_batch")
@@ -705,6 +722,12 @@ class Batch:
 
     def check(self, stream=None):
         return pmp_batch_check(self.handle, stream)
+
+    def profile(self, enable=True):
+        pmp_batch_profile(self.handle, enable)
+
+    def profile_read(self, stream=None):
+        return pmp_batch_profile_read(self.handle, stream)
 
     def close(self):
         if self.handle:

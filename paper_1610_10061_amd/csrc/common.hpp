@@ -317,9 +317,16 @@ struct BatchArgs {
 hipError_t launch_ga_batch(const BatchArgs &b, int generations, int max_w2,
                            int max_blocks, int want_blocks, hipStream_t s,
                            int *grid, bool cooperative);
+// Events that bracket the batch-wide evaluation launches (profiling): pairs
+// events[*used], events[*used + 1] while *used + 2 <= cap; none when null.
+struct BatchEvents {
+    hipEvent_t *events = nullptr;
+    int cap = 0;
+    int *used = nullptr;
+};
 // The same generations as a sequence of batch-wide kernels (one per phase).
 hipError_t launch_ga_batch_kernels(const BatchArgs &b, int nchrom, int ntiles,
                                    int ngroups, int generations, int max_w2,
-                                   hipStream_t s);
+                                   hipStream_t s, const BatchEvents &ev = BatchEvents{});
 
 }  // namespace pmp

@@ -597,19 +597,29 @@ __global__ __launch_bounds__(256) void k_batch_best(BatchArgs B)
 
 template <int WD>
 hipError_t batch_kernels_wd(const BatchArgs &b, int nchrom, int ntiles, int ngroups,
-                            int generations, hipStream_t s)
+                            int generations, hipStream_t s, const BatchEvents &ev)
 {
     const dim3 waves((unsigned)((nchrom + kGaWaves - 1) / kGaWaves));
     const dim3 tiles((unsigned)(((ntiles + 7) / 8) * 8));
+    // the evaluation launch, bracketed by the next pair of events if any
+    auto eval = [&](int k, int buf) {
+        if (ev.events && *ev.used + 2 <= ev.cap) {
+            hipExtLaunchKernelGGL(k_batch_eval<WD>, tiles, dim3(kEvalTile * kBatchEvalWaves), 0,
+                                  s, ev.events[*ev.used], ev.events[*ev.used + 1], 0, b, k,
+                                  buf);
+            *ev.used += 2;
+        } else {
+            hipLaunchKernelGGL(k_batch_eval<WD>, tiles, dim3(kEvalTile * kBatchEvalWaves), 0, s,
+                               b, k, buf);
+        }
+    };
     for (int gen = 0; gen < generations; ++gen) {
         hipLaunchKernelGGL(k_batch_init, waves, dim3(64 * kGaWaves), 0, s, b);
-        hipLaunchKernelGGL(k_batch_eval<WD>, tiles, dim3(kEvalTile * kBatchEvalWaves), 0, s,
-                           b, -1, 0);
+        eval(-1, 0);
         for (int k = 0; k <= b.max_S; ++k) {
             hipLaunchKernelGGL(k_batch_stage, waves, dim3(64 * kGaWaves), 0, s, b, k);
             if (k < b.max_S)
-                hipLaunchKernelGGL(k_batch_eval<WD>, tiles, dim3(kEvalTile * kBatchEvalWaves),
-                                   0, s, b, k, (k & 1) ^ 1);
+                eval(k, (k & 1) ^ 1);
         }
         hipLaunchKernelGGL(k_batch_best, dim3((unsigned)ngroups), dim3(256), 0, s, b);
         hipError_t e = hipGetLastError();
@@ -801,12 +811,12 @@ hipError_t launch_ga_resolve_init(const GaArgs &g, int in, int out, hipStream_t 
 
 hipError_t launch_ga_batch_kernels(const BatchArgs &b, int nchrom, int ntiles,
                                    int ngroups, int generations, int max_w2,
-                                   hipStream_t s)
+                                   hipStream_t s, const BatchEvents &ev)
 {
     const int w2 = max_w2;
 #define PMP_BATCH_KWD(N)                                                       \
     if (w2 <= N)                                                               \
-        return batch_kernels_wd<N>(b, nchrom, ntiles, ngroups, generations, s);
+        return batch_kernels_wd<N>(b, nchrom, ntiles, ngroups, generations, s, ev);
     PMP_BATCH_KWD(2)
     PMP_BATCH_KWD(4)
     PMP_BATCH_KWD(8)

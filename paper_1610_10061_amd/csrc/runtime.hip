@@ -694,6 +694,10 @@ struct pmp_batch {
     bool graphs = true;
     bool persistent = false;  // one persistent kernel instead of per-phase kernels
     int max_blocks = 0;
+    // profiling of the evaluation launches (pmp_batch_profile)
+    bool prof = false;
+    std::vector<hipEvent_t> ev;
+    int ev_used = 0;
 };
 
 namespace {
@@ -705,8 +709,23 @@ hipError_t batch_enqueue(pmp_batch *bt, int generations, hipStream_t s, bool coo
     BatchHost &bh = bt->bh;
     if (bt->persistent)
         return batch_launch(bh, generations, bt->max_blocks, s, cooperative);
+    BatchEvents ev;
+    if (bt->prof) {
+        // one pair per evaluation launch: max_S + 1 per generation
+        const size_t need = (size_t)bt->ev_used + 2 * (size_t)generations * (bh.args.max_S + 1);
+        while (bt->ev.size() < need) {
+            hipEvent_t e = nullptr;
+            const hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess)
+                return r;
+            bt->ev.push_back(e);
+        }
+        ev.events = bt->ev.data();
+        ev.cap = (int)bt->ev.size();
+        ev.used = &bt->ev_used;
+    }
     return launch_ga_batch_kernels(bh.args, bh.nchrom, bh.ntiles, bh.ngroups, generations,
-                                   bh.max_w2, s);
+                                   bh.max_w2, s, ev);
 }
 
 // Workspace of pmp_eval_population_noalloc: the client-tile partial sums
@@ -2288,7 +2307,7 @@ pmp_status pmp_batch_step(pmp_batch *bt, int32_t generations, void *stream)
     BatchHost &bh = bt->bh;
     for (pmp_ga *ga : bh.gas)  // the batch kernels make each generation's population
         ga->init_ahead = false;
-    if (!bt->graphs) {
+    if (!bt->graphs || bt->prof) {
         HIP_TRY(batch_enqueue(bt, generations, s, true));
         return PMP_OK;
     }
@@ -2336,7 +2355,41 @@ void pmp_batch_destroy(pmp_batch *bt)
     if (!bt)
         return;
     bt->bh.release();
+    for (hipEvent_t e : bt->ev)
+        (void)hipEventDestroy(e);
     delete bt;
+}
+
+pmp_status pmp_batch_profile(pmp_batch *bt, int32_t enable)
+{
+    if (!bt)
+        return fail(PMP_EINVAL, "batch is NULL");
+    if (bt->persistent)
+        return fail(PMP_EUNSUPPORTED, "profiling the persistent batch kernel");
+    HIP_TRY(hipDeviceSynchronize());
+    bt->prof = enable != 0;
+    bt->ev_used = 0;
+    return PMP_OK;
+}
+
+pmp_status pmp_batch_profile_read(pmp_batch *bt, double *eval_ms, int64_t *eval_launches,
+                                  void *stream)
+{
+    if (!bt)
+        return fail(PMP_EINVAL, "batch is NULL");
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    double ms = 0;
+    for (int k = 0; k + 1 < bt->ev_used; k += 2) {
+        float t = 0;
+        HIP_TRY(hipEventElapsedTime(&t, bt->ev[k], bt->ev[k + 1]));
+        ms += t;
+    }
+    if (eval_ms)
+        *eval_ms = ms;
+    if (eval_launches)
+        *eval_launches = bt->ev_used / 2;
+    bt->ev_used = 0;
+    return PMP_OK;
 }
 
 pmp_status pmp_ga_step_batch(pmp_ga *const *gas, int32_t count, int32_t generations,

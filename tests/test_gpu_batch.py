@@ -208,3 +208,34 @@ def test_full_batch_config(pm):
             assert a[5] == st.best_cost
             assert a[6]["chromosome_evals"] == st.state[oracle.ST_CHROM_EVALS]
     batch.close()
+
+
+def test_batch_profiled_steps_keep_results(pm):
+    """Profiled batch steps (launched directly, the evaluation launches
+    bracketed by events) evolve every run as the unprofiled ones, and count
+    one evaluation launch per stage and generation."""
+    old = os.environ.get("PMP_BATCH_MODE")
+    os.environ.pop("PMP_BATCH_MODE", None)
+    try:
+        cases = _mini_batch()
+        G = 5
+        _say("profiled mini batch of", len(cases))
+        insts, gas = _make(pm, cases, G)
+        batch = pm.Batch(gas)
+        batch.profile(True)
+        batch.step(2)
+        ms, launches = batch.profile_read()
+        batch.profile(False)
+        batch.step(3)
+        batch.check()
+        # every generation launches the same number of evaluations
+        assert ms > 0 and launches >= 2 and launches % 2 == 0
+        rinsts, refs = _make(pm, cases, G)
+        for r in refs:
+            r.step(G)
+        for ga, ref in zip(gas, refs):
+            _assert_same(_state(ga), _state(ref))
+        batch.close()
+    finally:
+        if old is not None:
+            os.environ["PMP_BATCH_MODE"] = old
