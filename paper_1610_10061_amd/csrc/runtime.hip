@@ -640,6 +640,14 @@ hipError_t batch_build(BatchHost &bh, pmp_ga *const *gas, int count)
         it.g = ga->args();
         it.e = ga_eval_args(ga, it.g, 0);
         it.e.done = nullptr;
+        // The batch evaluation runs 16 waves per workgroup: a tile tuned for
+        // fewer waves keeps its clients per wave with proportionally more
+        // clients per workgroup (fewer client tiles, so the partial sums
+        // still fit); the stage steps read the sums with the same tiling.
+        const int scale = 16 / std::max(1, std::min(16, ga->waves));
+        it.e.clients_per_block = ga->cpb * scale;
+        it.e.tiles_i = (ga->inst->n + it.e.clients_per_block - 1) / it.e.clients_per_block;
+        it.g.TI = it.e.tiles_i;
         it.X = ga->xstages();
         it.S = it.X + ga->Y;
         it.fb = ga->final_buf();
