@@ -615,7 +615,290 @@ __global__ __launch_bounds__(256) void k_total(const unsigned long long *colsum,
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Two-pass walk (the default).  Pass 1 (k_prop_s12) uses the evaluation's
+// tiling: the workgroup of a chromosome tile (64 chromosomes) and a client
+// tile stages the tile's masks facility-major in LDS; a wave takes a client,
+// its lanes hold the row's positions, one transpose gives lane c the open
+// positions of chromosome c in the chunk, and two lowest-bit steps give s1
+// and s2 (chunk after chunk until every chromosome has both or the row ends),
+// their costs from the lanes holding them.  Pass 2 (k_prop_slots), a
+// workgroup per chromosome: a candidate facility f's slot sums come from the
+// index entries (i, k) with Pi'_i[k] = f, k < kNearL, tested against (s1, s2)
+// of the chromosome and client i; positions at or past kNearL (rows whose
+// second open facility lies further) are walked directly.  The sums are the
+// one-pass walk's (the same integer terms, added in another order).
+// ---------------------------------------------------------------------------
+constexpr int kS12Waves = 16;
+constexpr int kS12Clients = 64;  // clients per workgroup
+constexpr int kMaxLearnWords = PMP_MAX_LEARNED_FACILITIES / 64;
+constexpr int kSlotWaves = 4;
+
+// Lowest set bit of the 64-bit (hi:lo), -1 if none.
+__device__ __forceinline__ int lowest64(uint32_t lo, uint32_t hi)
+{
+    const uint32_t a = (uint32_t)lowest_bit(lo);
+    const uint32_t b = __builtin_elementwise_add_sat((uint32_t)lowest_bit(hi), 32u);
+    return (int)(a < b ? a : b);
+}
+
+__global__ __launch_bounds__(64 * kS12Waves) void k_prop_s12(LearnArgs A, int out, int tiles_c)
+{
+    // the rows staged at a padded stride (32-bit words), then in place the
+    // facility-major words T[64 w + lane] and T[64 W] = 0
+    __shared__ __align__(16) uint32_t sm[kEvalTile * (2 * kMaxLearnWords + 1)];
+    const GaArgs &g = A.g;
+    const Tables &t = g.t;
+    const int W = t.W, SD = 2 * W + 1;
+    const int ntiles = tiles_c * ((t.n + kS12Clients - 1) / kS12Clients);
+    const int per_xcd = (int)gridDim.x >> 3;
+    const int logical = ((int)blockIdx.x & 7) * per_xcd + ((int)blockIdx.x >> 3);
+    if (logical >= ntiles)  // (the whole workgroup, before any barrier)
+        return;
+    const int ti = logical / tiles_c, tc = logical - ti * tiles_c;
+    const int c0 = tc * kEvalTile, rows = min(kEvalTile, g.P - c0);
+    const int lane = threadIdx.x & 63, wave = wave_id();
+    const uint32_t *g32 = reinterpret_cast<const uint32_t *>(buf(g.cur, out));
+    for (int e = threadIdx.x; e < kEvalTile * 2 * W; e += 64 * kS12Waves) {
+        const int c = e / (2 * W), w = e - c * (2 * W);
+        const uint32_t v = g32[(int64_t)(c0 + min(c, rows - 1)) * 2 * W + w];
+        sm[c * SD + w] = c < rows ? v : 0u;
+    }
+    if (ga_stopped(g))
+        return;
+    __syncthreads();
+    constexpr int NW = (kMaxLearnWords + kS12Waves - 1) / kS12Waves;
+    uint32_t rlo[NW], rhi[NW];
+#pragma unroll
+    for (int r = 0; r < NW; ++r) {
+        const int w = min(wave + r * kS12Waves, W - 1);
+        rlo[r] = sm[lane * SD + 2 * w];
+        rhi[r] = sm[lane * SD + 2 * w + 1];
+    }
+    __syncthreads();
+    uint64_t *sT = reinterpret_cast<uint64_t *>(sm);
+    const TransposeLanes tl(lane);
+#pragma unroll
+    for (int r = 0; r < NW; ++r) {
+        const int w = wave + r * kS12Waves;
+        if (w < W) {
+            transpose64(rlo[r], rhi[r], lane, tl);
+            sT[w * 64 + lane] = ((uint64_t)rhi[r] << 32) | rlo[r];
+        }
+    }
+    if (threadIdx.x == 0)
+        sT[64 * W] = 0ull;
+    __syncthreads();
+    const uint32_t jz = (uint32_t)(64 * W);
+    const bool mine = lane < rows;  // lane c: chromosome c0 + c
+    const int i1 = min(t.n, ti * kS12Clients + kS12Clients);
+    for (int i = ti * kS12Clients + wave; i < i1; i += kS12Waves) {
+        const uint16_t *prow = t.pi + (int64_t)i * t.pitch;
+        const int32_t *drow = t.ds + (int64_t)i * t.pitch;
+        int s1 = -1, s2 = -1;
+        int32_t c1 = 0, c2 = 0;
+        for (int base = 0; base < t.K; base += 64) {
+            const int k = base + lane;
+            const bool in = k < t.K;
+            const int kc = in ? k : t.K - 1;
+            const uint32_t j = in ? (uint32_t)prow[kc] : jz;
+            const int32_t d = drow[kc];
+            const uint64_t row = sT[j];
+            uint32_t lo = (uint32_t)row, hi = (uint32_t)(row >> 32);
+            transpose64(lo, hi, lane, tl);
+            const int a = lowest64(lo, hi);
+            const int32_t da = __builtin_amdgcn_ds_bpermute(a << 2, d);
+            if (s1 < 0 && a >= 0) {  // the chunk's first open position is s1
+                s1 = base + a;
+                c1 = da;
+                if (a < 32)
+                    lo &= lo - 1u;
+                else
+                    hi &= hi - 1u;
+            }
+            const int b = lowest64(lo, hi);
+            const int32_t db = __builtin_amdgcn_ds_bpermute(b << 2, d);
+            if (s1 >= 0 && s2 < 0 && b >= 0) {
+                s2 = base + b;
+                c2 = db;
+            }
+            if (__builtin_amdgcn_ballot_w64(mine && s2 < 0) == 0ull)
+                break;
+        }
+        if (__builtin_amdgcn_ballot_w64(mine && s1 < 0) != 0ull && lane == 0)
+            atomicOr(g.err, ERR_SCAN_OVERRUN);  // a row without an open facility
+        if (mine) {
+            const bool none2 = s2 < 0;
+            if (none2)
+                c2 = drow[t.K - 1];
+            const int64_t o = (int64_t)(c0 + lane) * t.n + i;
+            A.s12[o] = (uint32_t)max(s1, 0) | ((uint32_t)(none2 ? 0xFFFF : s2) << 16);
+            A.c12[2 * o] = c1;
+            A.c12[2 * o + 1] = c2;
+        }
+    }
+}
+
+// Slot of facility f among the chromosome's candidates (bitmap cb, prefix
+// counts cp), -1 if f is not one.
+__device__ __forceinline__ int cand_slot(const uint64_t *cb, const uint8_t *cp, int f)
+{
+    const uint64_t w = cb[f >> 6];
+    const uint64_t bit = 1ull << (f & 63);
+    return (w & bit) ? (int)cp[f >> 6] + __builtin_popcountll(w & (bit - 1ull)) : -1;
+}
+
+__global__ __launch_bounds__(64 * kSlotWaves) void k_prop_slots(LearnArgs A)
+{
+    __shared__ SlotBins B;
+    __shared__ int32_t fac[kSlots];
+    __shared__ int32_t nslots;
+    const GaArgs &g = A.g;
+    const Tables &t = g.t;
+    const int c = blockIdx.x;
+    if (c >= g.P || ga_stopped(g))  // (the whole workgroup)
+        return;
+    const int lane = threadIdx.x & 63, wave = wave_id(), W = t.W;
+    const uint64_t *cb = A.cbits + (int64_t)c * W;
+    const uint8_t *cp = A.cpre + (int64_t)c * W;
+    bins_clear(B);
+    // slot -> facility (slots in facility order)
+    for (int w = threadIdx.x; w < W; w += blockDim.x) {
+        uint64_t bits = cb[w];
+        int sl = cp[w];
+        while (bits) {
+            fac[sl++] = w * 64 + __builtin_ctzll(bits);
+            bits &= bits - 1ull;
+        }
+        if (w == W - 1)
+            nslots = sl;
+    }
+    __syncthreads();
+    const uint32_t *s12 = A.s12 + (int64_t)c * t.n;
+    const int32_t *c12 = A.c12 + 2 * (int64_t)c * t.n;
+    const int nearL = min(kNearL, t.K);
+    // rows whose walk reaches position nearL: those positions directly
+    for (int ib = wave * 64; ib < t.n; ib += kSlotWaves * 64) {
+        const int i = ib + lane;
+        const uint32_t sv = s12[min(i, t.n - 1)];
+        const int s2r = (int)(sv >> 16);
+        const int end = s2r == 0xFFFF ? t.K : s2r + 1;
+        uint64_t far = __builtin_amdgcn_ballot_w64(i < t.n && end > nearL);
+        while (far) {
+            const int l = (int)__builtin_ctzll(far);
+            far &= far - 1ull;
+            const int ii = ib + l;
+            const uint32_t v = (uint32_t)__builtin_amdgcn_readlane((int)sv, l);
+            const int s1 = (int)(v & 0xFFFFu), s2x = (int)(v >> 16);
+            const int s2 = s2x == 0xFFFF ? -1 : s2x;
+            const int e2 = s2 < 0 ? t.K : s2 + 1;
+            const int32_t c1 = c12[2 * (int64_t)ii], c2 = c12[2 * (int64_t)ii + 1];
+            const uint16_t *prow = t.pi + (int64_t)ii * t.pitch;
+            const int32_t *drow = t.ds + (int64_t)ii * t.pitch;
+            for (int p0 = nearL; p0 < e2; p0 += 64) {
+                const int pos = p0 + lane;
+                if (pos < e2) {
+                    const int sl = cand_slot(cb, cp, prow[pos]);
+                    if (sl >= 0)
+                        add_terms(B, sl, pos, s1, s2, c1, c2, drow[pos]);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // the index: a wave per slot, its facility's entries over the lanes
+    const int ns = nslots;
+    for (int s = wave; s < ns; s += kSlotWaves) {
+        const int f = fac[s];
+        const int e0 = A.near_off[f], e1 = A.near_off[f + 1];
+        unsigned long long ad = 0, sb = 0, scc = 0, se = 0;  // ad: a | dd << 32
+        for (int e = e0 + lane; e < e1; e += 64) {
+            const uint32_t ik = A.near_ik[e];
+            const int i = (int)(ik >> 6), k = (int)(ik & 63u);
+            const int32_t dist = A.near_d[e];
+            const uint32_t sv = s12[i];
+            const int s1 = (int)(sv & 0xFFFFu), s2x = (int)(sv >> 16);
+            const int s2 = s2x == 0xFFFF ? -1 : s2x;
+            const int end = s2 < 0 ? t.K : s2 + 1;
+            if (k < end) {
+                const int32_t c1 = c12[2 * (int64_t)i], c2 = c12[2 * (int64_t)i + 1];
+                const bool upto1 = k <= s1, first = k == s1, second = k == s2;
+                ad += upto1 ? 1ull : (1ull << 32);
+                const int32_t v = k < s1 ? c1 - dist : (first ? c1 : (second ? c2 - c1 : c2 - dist));
+                const unsigned long long uv = (unsigned long long)v;
+                sb += upto1 ? uv : 0ull;
+                se += !upto1 && second ? uv : 0ull;
+                scc += !upto1 && !second ? uv : 0ull;
+                scc += first ? (unsigned long long)(c2 - c1) : 0ull;
+            }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            ad += __shfl_xor(ad, o);
+            sb += __shfl_xor(sb, o);
+            scc += __shfl_xor(scc, o);
+            se += __shfl_xor(se, o);
+        }
+        if (lane == 0) {  // (the slot's own wave; the direct walk finished)
+            B.a[s] += (uint32_t)ad;
+            B.dd[s] += (uint32_t)(ad >> 32);
+            B.b[s] += sb;
+            B.cc[s] += scc;
+            B.e[s] += se;
+        }
+    }
+    __syncthreads();
+    for (int sl = threadIdx.x; sl < kSlots; sl += blockDim.x) {
+        const int64_t o = (int64_t)c * kSlots + sl;
+        A.sums.a[o] = B.a[sl];
+        A.sums.dd[o] = B.dd[sl];
+        A.sums.b[o] = B.b[sl];
+        A.sums.cc[o] = B.cc[sl];
+        A.sums.e[o] = B.e[sl];
+    }
+}
+
+__global__ void k_near_count(Tables t, int L, int32_t *count)
+{
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= (int64_t)t.n * L)
+        return;
+    const int64_t i = x / L, k = x - i * L;
+    atomicAdd(count + t.pi[i * t.pitch + k], 1);
+}
+
+__global__ void k_near_fill(Tables t, int L, int32_t *cursor, uint32_t *ik, int32_t *d)
+{
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= (int64_t)t.n * L)
+        return;
+    const int64_t i = x / L, k = x - i * L;
+    const int e = atomicAdd(cursor + t.pi[i * t.pitch + k], 1);
+    ik[e] = ((uint32_t)i << 6) | (uint32_t)k;
+    d[e] = t.ds[i * t.pitch + k];
+}
+
 }  // namespace
+
+hipError_t launch_near_count(const Tables &t, int32_t *count, hipStream_t s)
+{
+    const int L = min(kNearL, t.K);
+    const int64_t cells = (int64_t)t.n * L;
+    hipLaunchKernelGGL(k_near_count, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, s, t,
+                       L, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_near_fill(const Tables &t, int32_t *cursor, uint32_t *ik, int32_t *d,
+                            hipStream_t s)
+{
+    const int L = min(kNearL, t.K);
+    const int64_t cells = (int64_t)t.n * L;
+    hipLaunchKernelGGL(k_near_fill, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, s, t, L,
+                       cursor, ik, d);
+    return hipGetLastError();
+}
 
 hipError_t launch_features(const Tables &t, const uint64_t *masks, int P, const FeatCtx &ctx,
                            float *out, uint32_t *err, hipStream_t s)
@@ -639,6 +922,17 @@ hipError_t launch_walk_t(const LearnArgs &a, int out, hipStream_t s)
 // waves per SIMD resident at P = 1024).
 hipError_t launch_walk(const LearnArgs &a, int out, hipStream_t s)
 {
+    if (a.walk == 0) {  // the two-pass walk
+        const int tiles_c = (a.g.P + kEvalTile - 1) / kEvalTile;
+        const int tiles = tiles_c * ((a.g.t.n + kS12Clients - 1) / kS12Clients);
+        hipLaunchKernelGGL(k_prop_s12, dim3(((tiles + 7) / 8) * 8), dim3(64 * kS12Waves), 0, s,
+                           a, out, tiles_c);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(k_prop_slots, dim3(a.g.P), dim3(64 * kSlotWaves), 0, s, a);
+        return hipGetLastError();
+    }
     switch (a.walk) {
     case 1: return launch_walk_t<1, 8>(a, out, s);
     case 4: return launch_walk_t<4, 16>(a, out, s);

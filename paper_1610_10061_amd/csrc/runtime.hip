@@ -448,7 +448,14 @@ struct pmp_ga {
     uint8_t *cpre = nullptr;
     void *sums = nullptr;  // P x kSlots: a, dd (uint32), b, cc, e (uint64)
     unsigned long long *last_trained = nullptr;
-    int walk_shape = 2;  // chromosomes per workgroup of the proposal walk
+    int walk_shape = 0;  // proposal walk: 0 two passes, else chromosomes per workgroup
+    // two-pass walk: first two open positions and costs per (chromosome,
+    // client), and the facility index of every row's first positions
+    uint32_t *s12 = nullptr;
+    int32_t *c12 = nullptr;
+    int32_t *near_off = nullptr;
+    uint32_t *near_ik = nullptr;
+    int32_t *near_d = nullptr;
 
     int64_t ring_rows() const { return (int64_t)LH * LL * prm.population; }
 
@@ -600,6 +607,11 @@ struct pmp_ga {
         a.clients_per_block = cpb;
         a.tiles_i = TI;
         a.walk = walk_shape;
+        a.s12 = s12;
+        a.c12 = c12;
+        a.near_off = near_off;
+        a.near_ik = near_ik;
+        a.near_d = near_d;
         return a;
     }
 
@@ -619,6 +631,11 @@ struct pmp_ga {
             (void)hipFree(sums);
         sums = nullptr;
         dfree(last_trained);
+        dfree(s12);
+        dfree(c12);
+        dfree(near_off);
+        dfree(near_ik);
+        dfree(near_d);
     }
 };
 
@@ -2798,8 +2815,46 @@ pmp_status pmp_ga_set_model(pmp_ga *ga, pmp_model *model, const pmp_learn_params
         ga->free_learned();
         return fail(PMP_EDEVICE, "learned proposal init: %s", hipGetErrorString(e));
     }
+    ga->walk_shape = env_int("PMP_WALK", 0);
+    if (ga->walk_shape == 0) {
+        // the two-pass walk's buffers and the facility index of the rows'
+        // first positions (built once per run)
+        const Tables t = ga->inst->tables();
+        const size_t PN = P * (size_t)t.n;
+        const int L = std::min(kNearL, t.K);
+        const size_t E = (size_t)t.n * L;
+        int32_t *cursor = nullptr;
+        std::vector<int32_t> off((size_t)t.m + 1, 0);
+        if (dalloc(&ga->s12, PN) || dalloc(&ga->c12, 2 * PN) ||
+            dalloc(&ga->near_off, (size_t)t.m + 1) || dalloc(&ga->near_ik, E) ||
+            dalloc(&ga->near_d, E) || dalloc(&cursor, (size_t)t.m)) {
+            dfree(cursor);
+            ga->free_learned();
+            return fail(PMP_ENOMEM, "two-pass walk buffers (%zu pairs)", PN);
+        }
+        e = hipMemset(cursor, 0, sizeof(int32_t) * t.m);
+        if (e == hipSuccess)
+            e = launch_near_count(t, cursor, nullptr);
+        if (e == hipSuccess)
+            e = hipMemcpy(off.data() + 1, cursor, sizeof(int32_t) * t.m, hipMemcpyDeviceToHost);
+        for (int f = 0; f < t.m; ++f)
+            off[f + 1] += off[f];
+        if (e == hipSuccess)
+            e = hipMemcpy(ga->near_off, off.data(), sizeof(int32_t) * off.size(),
+                          hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(cursor, off.data(), sizeof(int32_t) * t.m, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = launch_near_fill(t, cursor, ga->near_ik, ga->near_d, nullptr);
+        if (e == hipSuccess)
+            e = hipDeviceSynchronize();
+        dfree(cursor);
+        if (e != hipSuccess) {
+            ga->free_learned();
+            return fail(PMP_EDEVICE, "facility index: %s", hipGetErrorString(e));
+        }
+    }
     ga->model = model;
-    ga->walk_shape = env_int("PMP_WALK", 2);
     ga->LC = C;
     ga->LL = L;
     ga->Lexp = q.explore_permille;

@@ -366,3 +366,46 @@ def test_trained_network_gains(pm):
     assert lbest < pbest
     mask, cost, _ = lga.best()
     assert cost == oracle.objective(fresh, mask[None], p)[0]
+
+
+@pytest.mark.parametrize("case", ["euclid300", "rand_p3", "short_rows"])
+def test_two_pass_walk_equals_one_pass(pm, case):
+    """The two-pass proposal walk (first two open positions per chromosome
+    and client, then each candidate facility's index entries; positions past
+    the index walked directly) gives the one-pass walk's slot sums: the same
+    features, scores, swaps, training and runs, bit for bit.  Cases: common
+    rows, rows whose second open facility often lies past the index (p = 3),
+    rows shorter than the index (K < 64)."""
+    if case == "euclid300":
+        d, p = gi.euclid_instance(300, 7), 30
+    elif case == "rand_p3":
+        d, p = np.random.default_rng(3).integers(1, 500, size=(40, 150)).astype(np.int32), 3
+    else:
+        d, p = gi.euclid_instance(70, 2), 30
+    P, NT, G = 128, 32, 20
+    runs = []
+    old = os.environ.get("PMP_WALK")
+    try:
+        for walk in ("0", "2"):
+            os.environ["PMP_WALK"] = walk
+            _say("walk", walk, case)
+            model = pm.Model(11)
+            inst, ga = _learned_ga(pm, d, p, P, NT, G, 3, model, candidates=32,
+                                   learned_iters=2, explore_permille=50, train_every=1,
+                                   lr=2e-3)
+            ga.step(6)
+            rep = ga.replay()
+            pop, fit, gm, gc = ga.state()
+            runs.append((pop, fit, gm, gc, model.params(), rep["x"], rep["delta"],
+                         rep["scores"], ga.best()[2]))
+    finally:
+        if old is None:
+            os.environ.pop("PMP_WALK", None)
+        else:
+            os.environ["PMP_WALK"] = old
+    a, b = runs
+    for x, y in zip(a[:8], b[:8]):
+        np.testing.assert_array_equal(x, y)
+    for k in ("swap_tried", "swap_taken", "chromosome_evals"):
+        assert a[8][k] == b[8][k], k
+    assert a[8]["swap_tried"] > 0
