@@ -633,7 +633,10 @@ __global__ __launch_bounds__(256) void k_total(const unsigned long long *colsum,
 constexpr int kS12Waves = 16;
 constexpr int kS12Clients = 64;  // clients per workgroup
 constexpr int kMaxLearnWords = PMP_MAX_LEARNED_FACILITIES / 64;
-constexpr int kSlotWaves = 4;
+constexpr int kSlotWaves = 8;
+constexpr int kSlotRows = 4 * kSlotWaves;  // 16-lane rows per workgroup
+constexpr int kFarCap = 256;               // listed far clients per chromosome
+constexpr int kStageClients = 4096;        // (12 bytes of LDS each)
 
 // Lowest set bit of the 64-bit (hi:lo), -1 if none.
 __device__ __forceinline__ int lowest64(uint32_t lo, uint32_t hi)
@@ -749,24 +752,97 @@ __device__ __forceinline__ int cand_slot(const uint64_t *cb, const uint8_t *cp, 
     return (w & bit) ? (int)cp[f >> 6] + __builtin_popcountll(w & (bit - 1ull)) : -1;
 }
 
+// Sum over each 16-lane row; lane 15 of the row ends with the total.
+__device__ __forceinline__ unsigned long long row_sum64(unsigned long long v)
+{
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+    dpp_add64<0x111, 0xF>(lo, hi);  // row_shr:1
+    dpp_add64<0x112, 0xF>(lo, hi);  // row_shr:2
+    dpp_add64<0x114, 0xF>(lo, hi);  // row_shr:4
+    dpp_add64<0x118, 0xF>(lo, hi);  // row_shr:8
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// Client i's (s1 | s2 << 16) and (c1, c2): from LDS when staged, else from
+// device memory.
+template <bool Stage>
+struct RowState {
+    const uint32_t *S;  // LDS when staged
+    const uint2 *C;
+    const uint32_t *gs;
+    const uint2 *gc;
+    __device__ __forceinline__ uint32_t s(int i) const
+    {
+        if constexpr (Stage)
+            return S[i];
+        else
+            return gs[i];
+    }
+    __device__ __forceinline__ uint2 c(int i) const
+    {
+        if constexpr (Stage)
+            return C[i];
+        else
+            return gc[i];
+    }
+};
+
+// Positions nearL .. e2 - 1 of client ii's row (one beyond the index) walked
+// by `width` lanes starting at lane `first` of the group (a 16-lane row or
+// the whole wave).
+__device__ __forceinline__ void walk_far(const Tables &t, SlotBins &B, const uint64_t *cb,
+                                         const uint8_t *cp, int ii, uint32_t v, uint2 cc,
+                                         int nearL, int sub, int width)
+{
+    const int s1 = (int)(v & 0xFFFFu), s2x = (int)(v >> 16);
+    const int s2 = s2x == 0xFFFF ? -1 : s2x;
+    const int e2 = s2 < 0 ? t.K : s2 + 1;
+    const uint16_t *prow = t.pi + (int64_t)ii * t.pitch;
+    const int32_t *drow = t.ds + (int64_t)ii * t.pitch;
+    for (int p0 = nearL; p0 < e2; p0 += width) {
+        const int pos = p0 + sub;
+        if (pos < e2) {
+            const int f = prow[pos];
+            const int32_t d = drow[pos];
+            const int sl = cand_slot(cb, cp, f);
+            if (sl >= 0)
+                add_terms(B, sl, pos, s1, s2, (int32_t)cc.x, (int32_t)cc.y, d);
+        }
+    }
+}
+
+// Pass 2, a workgroup per chromosome.  Its clients' (s1, s2, c1, c2) are
+// staged in LDS (n <= kStageClients) with one coalesced sweep that also lists
+// the clients whose walk reaches past the index.  Then each 16-lane row takes
+// tasks: a candidate slot (its facility's index entries, 16 at a time, four
+// loads in flight, summed over the row) or a listed client (its positions
+// from kNearL on).  Clients past the list's capacity are walked by the wave
+// that finds them.
+template <bool Stage>
 __global__ __launch_bounds__(64 * kSlotWaves) void k_prop_slots(LearnArgs A)
 {
+    extern __shared__ __align__(16) uint32_t dyn[];  // staged: (c1, c2) x n, then s12 x n
     __shared__ SlotBins B;
-    __shared__ int32_t fac[kSlots];
-    __shared__ int32_t nslots;
+    __shared__ uint64_t cb[kMaxLearnWords];
+    __shared__ uint8_t cp[kMaxLearnWords];
+    __shared__ int32_t fac[kSlots], soff[kSlots], scnt[kSlots];
+    __shared__ int32_t farl[kFarCap];
+    __shared__ int32_t nslots, nfar;
     const GaArgs &g = A.g;
     const Tables &t = g.t;
     const int c = blockIdx.x;
     if (c >= g.P || ga_stopped(g))  // (the whole workgroup)
         return;
-    const int lane = threadIdx.x & 63, wave = wave_id(), W = t.W;
-    const uint64_t *cb = A.cbits + (int64_t)c * W;
-    const uint8_t *cp = A.cpre + (int64_t)c * W;
-    bins_clear(B);
+    const int lane = threadIdx.x & 63, W = t.W, n = t.n;
+    const int nearL = min(kNearL, t.K);
+    const uint64_t *gcb = A.cbits + (int64_t)c * W;
+    const uint8_t *gcp = A.cpre + (int64_t)c * W;
     // slot -> facility (slots in facility order)
     for (int w = threadIdx.x; w < W; w += blockDim.x) {
-        uint64_t bits = cb[w];
-        int sl = cp[w];
+        uint64_t bits = gcb[w];
+        int sl = gcp[w];
+        cb[w] = bits;
+        cp[w] = (uint8_t)sl;
         while (bits) {
             fac[sl++] = w * 64 + __builtin_ctzll(bits);
             bits &= bits - 1ull;
@@ -774,78 +850,125 @@ __global__ __launch_bounds__(64 * kSlotWaves) void k_prop_slots(LearnArgs A)
         if (w == W - 1)
             nslots = sl;
     }
+    bins_clear(B);
+    if (threadIdx.x == 0)
+        nfar = 0;
     __syncthreads();
-    const uint32_t *s12 = A.s12 + (int64_t)c * t.n;
-    const int32_t *c12 = A.c12 + 2 * (int64_t)c * t.n;
-    const int nearL = min(kNearL, t.K);
-    // rows whose walk reaches position nearL: those positions directly
-    for (int ib = wave * 64; ib < t.n; ib += kSlotWaves * 64) {
-        const int i = ib + lane;
-        const uint32_t sv = s12[min(i, t.n - 1)];
-        const int s2r = (int)(sv >> 16);
-        const int end = s2r == 0xFFFF ? t.K : s2r + 1;
-        uint64_t far = __builtin_amdgcn_ballot_w64(i < t.n && end > nearL);
-        while (far) {
-            const int l = (int)__builtin_ctzll(far);
-            far &= far - 1ull;
-            const int ii = ib + l;
-            const uint32_t v = (uint32_t)__builtin_amdgcn_readlane((int)sv, l);
-            const int s1 = (int)(v & 0xFFFFu), s2x = (int)(v >> 16);
-            const int s2 = s2x == 0xFFFF ? -1 : s2x;
-            const int e2 = s2 < 0 ? t.K : s2 + 1;
-            const int32_t c1 = c12[2 * (int64_t)ii], c2 = c12[2 * (int64_t)ii + 1];
-            const uint16_t *prow = t.pi + (int64_t)ii * t.pitch;
-            const int32_t *drow = t.ds + (int64_t)ii * t.pitch;
-            for (int p0 = nearL; p0 < e2; p0 += 64) {
-                const int pos = p0 + lane;
-                if (pos < e2) {
-                    const int sl = cand_slot(cb, cp, prow[pos]);
-                    if (sl >= 0)
-                        add_terms(B, sl, pos, s1, s2, c1, c2, drow[pos]);
+    RowState<Stage> rs;
+    rs.C = reinterpret_cast<const uint2 *>(dyn);
+    rs.S = dyn + 2 * n;
+    rs.gs = A.s12 + (int64_t)c * n;
+    rs.gc = reinterpret_cast<const uint2 *>(A.c12) + (int64_t)c * n;
+    const int ns = nslots;
+    if ((int)threadIdx.x < ns) {
+        const int f = fac[threadIdx.x];
+        const int e0 = A.near_off[f];
+        soff[threadIdx.x] = e0;
+        scnt[threadIdx.x] = A.near_off[f + 1] - e0;
+    }
+    // the sweep: U clients per thread in flight
+    constexpr int U = 8;
+    constexpr int NT = 64 * kSlotWaves;
+    for (int x0 = 0; x0 < n; x0 += U * NT) {
+        uint32_t sv[U];
+        uint2 cv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int x = x0 + u * NT + (int)threadIdx.x;
+            sv[u] = x < n ? rs.gs[x] : 0u;
+            cv[u] = x < n ? rs.gc[x] : uint2{0u, 0u};
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int x = x0 + u * NT + (int)threadIdx.x;
+            if (x0 + u * NT >= n)  // (uniform)
+                break;
+            if constexpr (Stage) {
+                if (x < n) {
+                    uint2 *C = reinterpret_cast<uint2 *>(dyn);
+                    C[x] = cv[u];
+                    dyn[2 * n + x] = sv[u];
                 }
+            }
+            const int s2x = (int)(sv[u] >> 16);
+            const int end = s2x == 0xFFFF ? t.K : s2x + 1;
+            const bool far = x < n && end > nearL;
+            const uint64_t fb = __builtin_amdgcn_ballot_w64(far);
+            if (fb == 0ull)
+                continue;
+            int base = 0;
+            if (lane == 0)
+                base = atomicAdd(&nfar, __builtin_popcountll(fb));
+            base = __shfl(base, 0);
+            const int idx = base + (int)__builtin_amdgcn_mbcnt_hi(
+                                       (uint32_t)(fb >> 32),
+                                       __builtin_amdgcn_mbcnt_lo((uint32_t)fb, 0u));
+            if (far && idx < kFarCap)
+                farl[idx] = x;
+            uint64_t over = __builtin_amdgcn_ballot_w64(far && idx >= kFarCap);
+            while (over) {  // the list is full: this wave walks the row itself
+                const int l = (int)__builtin_ctzll(over);
+                over &= over - 1ull;
+                const int ii = x0 + u * NT + (int)(threadIdx.x & ~63u) + l;
+                const uint32_t v = (uint32_t)__builtin_amdgcn_readlane((int)sv[u], l);
+                const uint2 cc = {(uint32_t)__builtin_amdgcn_readlane((int)cv[u].x, l),
+                                  (uint32_t)__builtin_amdgcn_readlane((int)cv[u].y, l)};
+                walk_far(t, B, cb, cp, ii, v, cc, nearL, lane, 64);
             }
         }
     }
     __syncthreads();
-    // the index: a wave per slot, its facility's entries over the lanes
-    const int ns = nslots;
-    for (int s = wave; s < ns; s += kSlotWaves) {
-        const int f = fac[s];
-        const int e0 = A.near_off[f], e1 = A.near_off[f + 1];
-        unsigned long long ad = 0, sb = 0, scc = 0, se = 0;  // ad: a | dd << 32
-        for (int e = e0 + lane; e < e1; e += 64) {
-            const uint32_t ik = A.near_ik[e];
-            const int i = (int)(ik >> 6), k = (int)(ik & 63u);
-            const int32_t dist = A.near_d[e];
-            const uint32_t sv = s12[i];
-            const int s1 = (int)(sv & 0xFFFFu), s2x = (int)(sv >> 16);
-            const int s2 = s2x == 0xFFFF ? -1 : s2x;
-            const int end = s2 < 0 ? t.K : s2 + 1;
-            if (k < end) {
-                const int32_t c1 = c12[2 * (int64_t)i], c2 = c12[2 * (int64_t)i + 1];
-                const bool upto1 = k <= s1, first = k == s1, second = k == s2;
-                ad += upto1 ? 1ull : (1ull << 32);
-                const int32_t v = k < s1 ? c1 - dist : (first ? c1 : (second ? c2 - c1 : c2 - dist));
-                const unsigned long long uv = (unsigned long long)v;
-                sb += upto1 ? uv : 0ull;
-                se += !upto1 && second ? uv : 0ull;
-                scc += !upto1 && !second ? uv : 0ull;
-                scc += first ? (unsigned long long)(c2 - c1) : 0ull;
-            }
-        }
+    const int nf = min(nfar, kFarCap);
+    const int row = (int)threadIdx.x >> 4, sub = lane & 15;
+    for (int task = row; task < ns + nf; task += kSlotRows) {  // (uniform in the row)
+        if (task < ns) {
+            const uint2 *ent = A.near_q + soff[task];
+            const int cnt = scnt[task];
+            unsigned long long ad = 0, sb = 0, scc = 0, se = 0;  // ad: a | dd << 32
+            for (int q0 = 0; q0 < cnt; q0 += 64) {
+                uint2 en[4];
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            ad += __shfl_xor(ad, o);
-            sb += __shfl_xor(sb, o);
-            scc += __shfl_xor(scc, o);
-            se += __shfl_xor(se, o);
-        }
-        if (lane == 0) {  // (the slot's own wave; the direct walk finished)
-            B.a[s] += (uint32_t)ad;
-            B.dd[s] += (uint32_t)(ad >> 32);
-            B.b[s] += sb;
-            B.cc[s] += scc;
-            B.e[s] += se;
+                for (int u = 0; u < 4; ++u) {
+                    const int q = q0 + 16 * u + sub;
+                    en[u] = q < cnt ? ent[q] : uint2{0xFFFFFFFFu, 0u};
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (en[u].x == 0xFFFFFFFFu)
+                        continue;
+                    const int i = (int)(en[u].x >> 6), k = (int)(en[u].x & 63u);
+                    const int32_t dist = (int32_t)en[u].y;
+                    const uint32_t sv = rs.s(i);
+                    const int s1 = (int)(sv & 0xFFFFu), s2x = (int)(sv >> 16);
+                    if (k <= s2x) {  // (s2x = 0xFFFF, no second: every k < nearL)
+                        const uint2 cc = rs.c(i);
+                        const int32_t c1 = (int32_t)cc.x, c2 = (int32_t)cc.y;
+                        const bool upto1 = k <= s1, first = k == s1, second = k == s2x;
+                        ad += upto1 ? 1ull : (1ull << 32);
+                        const int32_t v =
+                            k < s1 ? c1 - dist : (first ? c1 : (second ? c2 - c1 : c2 - dist));
+                        const unsigned long long uv = (unsigned long long)v;
+                        sb += upto1 ? uv : 0ull;
+                        se += !upto1 && second ? uv : 0ull;
+                        scc += !upto1 && !second ? uv : 0ull;
+                        scc += first ? (unsigned long long)(c2 - c1) : 0ull;
+                    }
+                }
+            }
+            ad = row_sum64(ad);
+            sb = row_sum64(sb);
+            scc = row_sum64(scc);
+            se = row_sum64(se);
+            if (sub == 15) {  // (rows that list far clients add to the same bins)
+                atomicAdd(&B.a[task], (uint32_t)ad);
+                atomicAdd(&B.dd[task], (uint32_t)(ad >> 32));
+                atomicAdd(&B.b[task], sb);
+                atomicAdd(&B.cc[task], scc);
+                atomicAdd(&B.e[task], se);
+            }
+        } else {
+            const int ii = farl[task - ns];
+            walk_far(t, B, cb, cp, ii, rs.s(ii), rs.c(ii), nearL, sub, 16);
         }
     }
     __syncthreads();
@@ -868,15 +991,14 @@ __global__ void k_near_count(Tables t, int L, int32_t *count)
     atomicAdd(count + t.pi[i * t.pitch + k], 1);
 }
 
-__global__ void k_near_fill(Tables t, int L, int32_t *cursor, uint32_t *ik, int32_t *d)
+__global__ void k_near_fill(Tables t, int L, int32_t *cursor, uint2 *q)
 {
     const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= (int64_t)t.n * L)
         return;
     const int64_t i = x / L, k = x - i * L;
     const int e = atomicAdd(cursor + t.pi[i * t.pitch + k], 1);
-    ik[e] = ((uint32_t)i << 6) | (uint32_t)k;
-    d[e] = t.ds[i * t.pitch + k];
+    q[e] = uint2{((uint32_t)i << 6) | (uint32_t)k, (uint32_t)t.ds[i * t.pitch + k]};
 }
 
 }  // namespace
@@ -890,13 +1012,12 @@ hipError_t launch_near_count(const Tables &t, int32_t *count, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_near_fill(const Tables &t, int32_t *cursor, uint32_t *ik, int32_t *d,
-                            hipStream_t s)
+hipError_t launch_near_fill(const Tables &t, int32_t *cursor, uint2 *q, hipStream_t s)
 {
     const int L = min(kNearL, t.K);
     const int64_t cells = (int64_t)t.n * L;
     hipLaunchKernelGGL(k_near_fill, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, s, t, L,
-                       cursor, ik, d);
+                       cursor, q);
     return hipGetLastError();
 }
 
@@ -930,7 +1051,11 @@ hipError_t launch_walk(const LearnArgs &a, int out, hipStream_t s)
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;
-        hipLaunchKernelGGL(k_prop_slots, dim3(a.g.P), dim3(64 * kSlotWaves), 0, s, a);
+        if (a.g.t.n <= kStageClients)
+            hipLaunchKernelGGL(k_prop_slots<true>, dim3(a.g.P), dim3(64 * kSlotWaves),
+                               (size_t)a.g.t.n * 12, s, a);
+        else
+            hipLaunchKernelGGL(k_prop_slots<false>, dim3(a.g.P), dim3(64 * kSlotWaves), 0, s, a);
         return hipGetLastError();
     }
     switch (a.walk) {

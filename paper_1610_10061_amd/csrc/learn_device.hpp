@@ -233,8 +233,7 @@ struct LearnArgs {
     uint32_t *s12;            // P x n: s1 | s2 << 16 (s2 = 0xFFFF: no second in the row)
     int32_t *c12;             // P x n x 2: c1, c2 (c2 = D'_{i,K-1} without a second)
     const int32_t *near_off;  // m + 1: facility f's entries at [near_off[f], near_off[f + 1])
-    const uint32_t *near_ik;  // entries: client i << 6 | position k
-    const int32_t *near_d;    // entries: D'_{i,k}
+    const uint2 *near_q;      // entries: (client i << 6 | position k, D'_{i,k})
 };
 
 // Positions per row in the facility index of the two-pass walk.
@@ -243,8 +242,7 @@ constexpr int kNearL = 64;
 // per-facility counts, then (offsets from the host's prefix sums) the
 // entries, in any order within a facility.
 hipError_t launch_near_count(const Tables &t, int32_t *count, hipStream_t s);
-hipError_t launch_near_fill(const Tables &t, int32_t *cursor, uint32_t *ik, int32_t *d,
-                            hipStream_t s);
+hipError_t launch_near_fill(const Tables &t, int32_t *cursor, uint2 *q, hipStream_t s);
 
 hipError_t launch_features(const Tables &t, const uint64_t *masks, int P, const FeatCtx &ctx,
                            float *out, uint32_t *err, hipStream_t s);

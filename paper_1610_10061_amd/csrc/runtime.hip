@@ -454,8 +454,7 @@ struct pmp_ga {
     uint32_t *s12 = nullptr;
     int32_t *c12 = nullptr;
     int32_t *near_off = nullptr;
-    uint32_t *near_ik = nullptr;
-    int32_t *near_d = nullptr;
+    uint2 *near_q = nullptr;
 
     int64_t ring_rows() const { return (int64_t)LH * LL * prm.population; }
 
@@ -610,8 +609,7 @@ struct pmp_ga {
         a.s12 = s12;
         a.c12 = c12;
         a.near_off = near_off;
-        a.near_ik = near_ik;
-        a.near_d = near_d;
+        a.near_q = near_q;
         return a;
     }
 
@@ -634,8 +632,7 @@ struct pmp_ga {
         dfree(s12);
         dfree(c12);
         dfree(near_off);
-        dfree(near_ik);
-        dfree(near_d);
+        dfree(near_q);
     }
 };
 
@@ -2826,8 +2823,8 @@ pmp_status pmp_ga_set_model(pmp_ga *ga, pmp_model *model, const pmp_learn_params
         int32_t *cursor = nullptr;
         std::vector<int32_t> off((size_t)t.m + 1, 0);
         if (dalloc(&ga->s12, PN) || dalloc(&ga->c12, 2 * PN) ||
-            dalloc(&ga->near_off, (size_t)t.m + 1) || dalloc(&ga->near_ik, E) ||
-            dalloc(&ga->near_d, E) || dalloc(&cursor, (size_t)t.m)) {
+            dalloc(&ga->near_off, (size_t)t.m + 1) || dalloc(&ga->near_q, E) ||
+            dalloc(&cursor, (size_t)t.m)) {
             dfree(cursor);
             ga->free_learned();
             return fail(PMP_ENOMEM, "two-pass walk buffers (%zu pairs)", PN);
@@ -2845,7 +2842,7 @@ pmp_status pmp_ga_set_model(pmp_ga *ga, pmp_model *model, const pmp_learn_params
         if (e == hipSuccess)
             e = hipMemcpy(cursor, off.data(), sizeof(int32_t) * t.m, hipMemcpyHostToDevice);
         if (e == hipSuccess)
-            e = launch_near_fill(t, cursor, ga->near_ik, ga->near_d, nullptr);
+            e = launch_near_fill(t, cursor, ga->near_q, nullptr);
         if (e == hipSuccess)
             e = hipDeviceSynchronize();
         dfree(cursor);

@@ -368,18 +368,26 @@ def test_trained_network_gains(pm):
     assert cost == oracle.objective(fresh, mask[None], p)[0]
 
 
-@pytest.mark.parametrize("case", ["euclid300", "rand_p3", "short_rows"])
+@pytest.mark.parametrize("case", ["euclid300", "rand_p3", "short_rows", "far_overflow",
+                                  "unstaged"])
 def test_two_pass_walk_equals_one_pass(pm, case):
     """The two-pass proposal walk (first two open positions per chromosome
     and client, then each candidate facility's index entries; positions past
     the index walked directly) gives the one-pass walk's slot sums: the same
     features, scores, swaps, training and runs, bit for bit.  Cases: common
     rows, rows whose second open facility often lies past the index (p = 3),
-    rows shorter than the index (K < 64)."""
+    rows shorter than the index (K < 64), more rows past the index than a
+    chromosome's list holds (256: the rest walked by the wave that finds
+    them), more clients than the per-chromosome LDS staging takes (4096:
+    client data read from device memory)."""
     if case == "euclid300":
         d, p = gi.euclid_instance(300, 7), 30
     elif case == "rand_p3":
         d, p = np.random.default_rng(3).integers(1, 500, size=(40, 150)).astype(np.int32), 3
+    elif case == "far_overflow":
+        d, p = np.random.default_rng(4).integers(1, 900, size=(700, 300)).astype(np.int32), 3
+    elif case == "unstaged":
+        d, p = np.random.default_rng(5).integers(1, 3000, size=(4200, 120)).astype(np.int32), 12
     else:
         d, p = gi.euclid_instance(70, 2), 30
     P, NT, G = 128, 32, 20
