@@ -631,7 +631,7 @@ __global__ __launch_bounds__(256) void k_total(const unsigned long long *colsum,
 // one-pass walk's (the same integer terms, added in another order).
 // ---------------------------------------------------------------------------
 constexpr int kS12Waves = 16;
-constexpr int kS12Clients = 64;  // clients per workgroup
+constexpr int kS12Clients = 32;  // clients per workgroup
 constexpr int kMaxLearnWords = PMP_MAX_LEARNED_FACILITIES / 64;
 constexpr int kSlotWaves = 8;
 constexpr int kSlotRows = 4 * kSlotWaves;  // 16-lane rows per workgroup
@@ -651,6 +651,9 @@ __global__ __launch_bounds__(64 * kS12Waves) void k_prop_s12(LearnArgs A, int ou
     // the rows staged at a padded stride (32-bit words), then in place the
     // facility-major words T[64 w + lane] and T[64 W] = 0
     __shared__ __align__(16) uint32_t sm[kEvalTile * (2 * kMaxLearnWords + 1)];
+    // results by chromosome and client (padded rows), written out row by row
+    __shared__ uint32_t o_s[kEvalTile][kS12Clients + 1];
+    __shared__ int32_t o_c1[kEvalTile][kS12Clients + 1], o_c2[kEvalTile][kS12Clients + 1];
     const GaArgs &g = A.g;
     const Tables &t = g.t;
     const int W = t.W, SD = 2 * W + 1;
@@ -661,12 +664,26 @@ __global__ __launch_bounds__(64 * kS12Waves) void k_prop_s12(LearnArgs A, int ou
         return;
     const int ti = logical / tiles_c, tc = logical - ti * tiles_c;
     const int c0 = tc * kEvalTile, rows = min(kEvalTile, g.P - c0);
+    const int i0 = ti * kS12Clients, ni = min(kS12Clients, t.n - i0);
     const int lane = threadIdx.x & 63, wave = wave_id();
     const uint32_t *g32 = reinterpret_cast<const uint32_t *>(buf(g.cur, out));
     for (int e = threadIdx.x; e < kEvalTile * 2 * W; e += 64 * kS12Waves) {
         const int c = e / (2 * W), w = e - c * (2 * W);
         const uint32_t v = g32[(int64_t)(c0 + min(c, rows - 1)) * 2 * W + w];
         sm[c * SD + w] = c < rows ? v : 0u;
+    }
+    // each wave's clients: their first chunks in flight with the staging
+    constexpr int R = kS12Clients / kS12Waves;
+    const uint32_t jz = (uint32_t)(64 * W);
+    uint32_t j0[R];
+    int32_t d0[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int il = wave + r * kS12Waves;
+        const int i = i0 + min(il, ni - 1);
+        const int kc = min(lane, t.K - 1);
+        j0[r] = lane < t.K ? (uint32_t)t.pi[(int64_t)i * t.pitch + kc] : jz;
+        d0[r] = t.ds[(int64_t)i * t.pitch + kc];
     }
     if (ga_stopped(g))
         return;
@@ -693,20 +710,20 @@ __global__ __launch_bounds__(64 * kS12Waves) void k_prop_s12(LearnArgs A, int ou
     if (threadIdx.x == 0)
         sT[64 * W] = 0ull;
     __syncthreads();
-    const uint32_t jz = (uint32_t)(64 * W);
     const bool mine = lane < rows;  // lane c: chromosome c0 + c
-    const int i1 = min(t.n, ti * kS12Clients + kS12Clients);
-    for (int i = ti * kS12Clients + wave; i < i1; i += kS12Waves) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int il = wave + r * kS12Waves;
+        if (il >= ni)  // (uniform)
+            break;
+        const int i = i0 + il;
         const uint16_t *prow = t.pi + (int64_t)i * t.pitch;
         const int32_t *drow = t.ds + (int64_t)i * t.pitch;
         int s1 = -1, s2 = -1;
         int32_t c1 = 0, c2 = 0;
-        for (int base = 0; base < t.K; base += 64) {
-            const int k = base + lane;
-            const bool in = k < t.K;
-            const int kc = in ? k : t.K - 1;
-            const uint32_t j = in ? (uint32_t)prow[kc] : jz;
-            const int32_t d = drow[kc];
+        uint32_t j = j0[r];
+        int32_t d = d0[r];
+        for (int base = 0;;) {
             const uint64_t row = sT[j];
             uint32_t lo = (uint32_t)row, hi = (uint32_t)(row >> 32);
             transpose64(lo, hi, lane, tl);
@@ -726,19 +743,31 @@ __global__ __launch_bounds__(64 * kS12Waves) void k_prop_s12(LearnArgs A, int ou
                 s2 = base + b;
                 c2 = db;
             }
-            if (__builtin_amdgcn_ballot_w64(mine && s2 < 0) == 0ull)
+            base += 64;
+            if (base >= t.K || __builtin_amdgcn_ballot_w64(mine && s2 < 0) == 0ull)
                 break;
+            const int k = base + lane;
+            const int kc = min(k, t.K - 1);
+            j = k < t.K ? (uint32_t)prow[kc] : jz;
+            d = drow[kc];
         }
         if (__builtin_amdgcn_ballot_w64(mine && s1 < 0) != 0ull && lane == 0)
             atomicOr(g.err, ERR_SCAN_OVERRUN);  // a row without an open facility
-        if (mine) {
-            const bool none2 = s2 < 0;
-            if (none2)
-                c2 = drow[t.K - 1];
-            const int64_t o = (int64_t)(c0 + lane) * t.n + i;
-            A.s12[o] = (uint32_t)max(s1, 0) | ((uint32_t)(none2 ? 0xFFFF : s2) << 16);
-            A.c12[2 * o] = c1;
-            A.c12[2 * o + 1] = c2;
+        const bool none2 = s2 < 0;
+        if (mine && none2)
+            c2 = drow[t.K - 1];
+        o_s[lane][il] = (uint32_t)max(s1, 0) | ((uint32_t)(none2 ? 0xFFFF : s2) << 16);
+        o_c1[lane][il] = c1;
+        o_c2[lane][il] = c2;
+    }
+    __syncthreads();
+    uint2 *c12 = reinterpret_cast<uint2 *>(A.c12);
+    for (int e = threadIdx.x; e < kEvalTile * kS12Clients; e += 64 * kS12Waves) {
+        const int c = e / kS12Clients, il = e - c * kS12Clients;
+        if (c < rows && il < ni) {
+            const int64_t o = (int64_t)(c0 + c) * t.n + i0 + il;
+            A.s12[o] = o_s[c][il];
+            c12[o] = uint2{(uint32_t)o_c1[c][il], (uint32_t)o_c2[c][il]};
         }
     }
 }
