@@ -212,8 +212,10 @@ def cpu_baseline(d, p, P, NT, budget_s):
 def leg_batch(args, specs, ds):
     """256 ragged instances (population 256 each): all preprocessed, then
     `--batch-generations` generations of every GA run, (a) batched (one
-    batch-wide kernel per phase, a step replayed from a hipGraph), (b)
-    instance by instance with pmp_ga_step.  Reports instances per second of
+    batch-wide kernel per phase, a step replayed from a hipGraph; the batch
+    evaluation's client tiling timed by the batch autotuner, counted with the
+    per-run tuning in the set-up time), (b) instance by instance with
+    pmp_ga_step.  Reports instances per second of
     (a) and (b), and the roofline of the batch evaluation kernel from the
     first BATCH_PROFILE_GENS generations of (a), whose evaluation launches
     are timed with HIP events.  --batch-only runs (a) alone, without the
@@ -231,10 +233,13 @@ def leg_batch(args, specs, ds):
         gas = [pm.GA(i, 256, 256, G, seed0 + s["index"]) for i, s in zip(insts, specs)]
         for g in gas:
             g.autotune(stream)
+        floor = None
+        if batched:
+            bt = pm.Batch(gas)
+            floor = bt.autotune(stream)
         t1 = time.perf_counter()
         prof = None
         if batched:
-            bt = pm.Batch(gas)
             pg = min(BATCH_PROFILE_GENS, G) if profile else 0
             if pg:
                 bt.profile(True)
@@ -257,19 +262,19 @@ def leg_batch(args, specs, ds):
             costs.append(c)
         if batched:
             bt.close()
-        return t1 - t0, t2 - t1, pairs, costs, prof
+        return t1 - t0, t2 - t1, pairs, costs, prof, floor
 
     if args.batch_only:
         log("batched (alone) ...")
-        prep_b, evo_b, pairs_b, costs_b, prof_b = run(True, 0, profile=True)
+        prep_b, evo_b, pairs_b, costs_b, prof_b, floor_b = run(True, 0, profile=True)
         return {"batch_only": True, "evolve_s": evo_b, "eval_ms": prof_b[0],
-                "eval_launches": prof_b[1]}
+                "eval_launches": prof_b[1], "client_floor": floor_b}
     log("warm-up ...")
     run(True, 10_000)
     log("batched ...")
-    prep_b, evo_b, pairs_b, costs_b, prof_b = run(True, 0, profile=True)
+    prep_b, evo_b, pairs_b, costs_b, prof_b, floor_b = run(True, 0, profile=True)
     log("one launch per instance ...")
-    prep_s, evo_s, pairs_s, costs_s, _ = run(False, 0)
+    prep_s, evo_s, pairs_s, costs_s, _, _ = run(False, 0)
     assert costs_b == costs_s, "batched and per-instance runs must agree"
     return {
         "metric": "instances/s, 256 ragged instances x %d generations" % G,
@@ -280,6 +285,7 @@ def leg_batch(args, specs, ds):
                                "half graphs (4n edges, weights 1..100), half Euclidean; "
                                "population 256 (NT=256), %d generations" % G},
         "batched": {"preprocess_s": prep_b, "evolve_s": evo_b,
+                    "client_floor": floor_b,
                     "instances_per_s_evolve": 256 / evo_b,
                     "pair_evals_per_s": pairs_b / evo_b},
         "per_instance_launches": {"preprocess_s": prep_s, "evolve_s": evo_s,

@@ -25,7 +25,7 @@ __all__ = [
     "pmp_ga_state", "pmp_ga_destroy", "pmp_solve", "pmp_ga_profile",
     "pmp_ga_profile_read", "pmp_ga_autotune", "pmp_batch_create",
     "pmp_batch_step", "pmp_batch_check", "pmp_batch_destroy",
-    "pmp_batch_profile", "pmp_batch_profile_read",
+    "pmp_batch_profile", "pmp_batch_profile_read", "pmp_batch_autotune",
     "pmp_ga_step_batch", "pmp_features", "pmp_model_create", "pmp_model_get",
     "pmp_model_set", "pmp_model_forward", "pmp_model_grad", "pmp_model_train",
     "pmp_model_destroy", "pmp_ga_set_model", "pmp_ga_replay", "pmp_exhaustive",
@@ -58,6 +58,7 @@ EXPORTS = [
     "pmp_ga_set_model", "pmp_ga_replay", "pmp_exhaustive", "pmp_apsp",
     "pmp_hbp_reduce", "pmp_hbp_info", "pmp_hbp_terms", "pmp_hbp_eval", "pmp_hbp_destroy",
     "pmp_eval_population_noalloc", "pmp_batch_profile", "pmp_batch_profile_read",
+    "pmp_batch_autotune",
 ]
 
 FEATURES = 16
@@ -141,6 +142,7 @@ def lib():
     L.pmp_batch_create.argtypes = [C.POINTER(_vp), _i32, C.POINTER(_vp)]
     L.pmp_batch_step.argtypes = [_vp, _i32, _vp]
     L.pmp_batch_check.argtypes = [_vp, C.POINTER(_i32), _vp]
+    L.pmp_batch_autotune.argtypes = [_vp, C.POINTER(_i32), _vp]
     L.pmp_batch_destroy.argtypes = [_vp]
     L.pmp_batch_destroy.restype = None
     L.pmp_batch_profile.argtypes = [_vp, _i32]
@@ -435,6 +437,15 @@ def pmp_batch_check(batch, stream=None):
     return grid.value
 
 
+def pmp_batch_autotune(batch, stream=None):
+    """Time the batch evaluation's client tilings; returns the chosen floor of
+    clients per workgroup (0: every run keeps its own tuning)."""
+    floor = _i32()
+    _check(lib().pmp_batch_autotune(batch, C.byref(floor), _stream(stream)),
+           "pmp_batch_autotune")
+    return floor.value
+
+
 def pmp_batch_destroy(batch):
     lib().pmp_batch_destroy(batch)
 
@@ -722,6 +733,9 @@ class Batch:
 
     def check(self, stream=None):
         return pmp_batch_check(self.handle, stream)
+
+    def autotune(self, stream=None):
+        return pmp_batch_autotune(self.handle, stream)
 
     def profile(self, enable=True):
         pmp_batch_profile(self.handle, enable)

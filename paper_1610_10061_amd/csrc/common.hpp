@@ -328,5 +328,8 @@ struct BatchEvents {
 hipError_t launch_ga_batch_kernels(const BatchArgs &b, int nchrom, int ntiles,
                                    int ngroups, int generations, int max_w2,
                                    hipStream_t s, const BatchEvents &ev = BatchEvents{});
+// One batch-wide evaluation of every run's current population (buffer 0),
+// as the first evaluation of a generation does (the batch autotuner's probe).
+hipError_t launch_ga_batch_eval(const BatchArgs &b, int ntiles, int max_w2, hipStream_t s);
 
 }  // namespace pmp

@@ -833,6 +833,36 @@ hipError_t launch_ga_batch_kernels(const BatchArgs &b, int nchrom, int ntiles,
     return hipErrorInvalidValue;
 }
 
+template <int WD>
+hipError_t batch_eval_wd(const BatchArgs &b, int ntiles, hipStream_t s)
+{
+    const dim3 tiles((unsigned)(((ntiles + 7) / 8) * 8));
+    hipLaunchKernelGGL(k_batch_eval<WD>, tiles, dim3(kEvalTile * kBatchEvalWaves), 0, s, b, -1,
+                       0);
+    return hipGetLastError();
+}
+
+hipError_t launch_ga_batch_eval(const BatchArgs &b, int ntiles, int max_w2, hipStream_t s)
+{
+#define PMP_BATCH_EWD(N)                                                       \
+    if (max_w2 <= N)                                                           \
+        return batch_eval_wd<N>(b, ntiles, s);
+    PMP_BATCH_EWD(2)
+    PMP_BATCH_EWD(4)
+    PMP_BATCH_EWD(8)
+    PMP_BATCH_EWD(16)
+    PMP_BATCH_EWD(32)
+    PMP_BATCH_EWD(48)
+    PMP_BATCH_EWD(64)
+    PMP_BATCH_EWD(96)
+    PMP_BATCH_EWD(128)
+    PMP_BATCH_EWD(160)
+    PMP_BATCH_EWD(192)
+    PMP_BATCH_EWD(256)
+#undef PMP_BATCH_EWD
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_ga_batch(const BatchArgs &b, int generations, int max_w2,
                            int max_blocks, int want_blocks, hipStream_t s,
                            int *grid, bool cooperative)

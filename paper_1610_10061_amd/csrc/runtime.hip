@@ -355,12 +355,24 @@ struct BatchHost {
     int max_w2 = 2, want = 8, last_grid = 0;
     int nchrom = 0, ntiles = 0, ngroups = 0;
     std::map<int, hipGraphExec_t> graphs;  // by generations per launch
+    // host copies of the run table and prefix offsets; each run's clients
+    // per workgroup from its own tuning (scaled to the batch kernel's
+    // waves), raised to min_cpb
+    std::vector<BatchItem> items;
+    std::vector<int32_t> prefix;
+    std::vector<int32_t> base_cpb;
+    int min_cpb = 0;
 
-    void release()
+    void drop_graphs()
     {
         for (auto &kv : graphs)
             (void)hipGraphExecDestroy(kv.second);
         graphs.clear();
+    }
+
+    void release()
+    {
+        drop_graphs();
         dfree(d_items);
         dfree(d_prefix);
         dfree(d_bar);
@@ -641,46 +653,69 @@ namespace {
 
 EvalArgs ga_eval_args(const pmp_ga *ga, const GaArgs &g, int buf);
 
+// The batch's client tiling: run b takes max(base_cpb[b], min_cpb) clients
+// per evaluation workgroup (never fewer than its own tuning, so its tiles
+// fit the partial-sum buffers sized for that); the stage steps read the
+// partial sums with the same tiling.  Uploads the run table and prefix
+// offsets; graphs captured for another tiling are dropped.
+hipError_t batch_tiles(BatchHost &bh, int min_cpb)
+{
+    const int count = (int)bh.gas.size();
+    int32_t *c0 = bh.prefix.data(), *t0 = c0 + count + 1, *g0 = t0 + count + 1;
+    for (int b = 0; b < count; ++b) {
+        BatchItem &it = bh.items[b];
+        it.e.clients_per_block = std::max(bh.base_cpb[b], min_cpb);
+        it.e.tiles_i = (bh.gas[b]->inst->n + it.e.clients_per_block - 1) / it.e.clients_per_block;
+        it.g.TI = it.e.tiles_i;
+        t0[b + 1] = t0[b] + it.e.tiles_c * it.e.tiles_i;
+    }
+    bh.drop_graphs();
+    hipError_t e = hipMemcpy(bh.d_items, bh.items.data(), sizeof(BatchItem) * count,
+                             hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(bh.d_prefix, bh.prefix.data(), sizeof(int32_t) * bh.prefix.size(),
+                      hipMemcpyHostToDevice);
+    bh.min_cpb = min_cpb;
+    bh.nchrom = c0[count];
+    bh.ntiles = t0[count];
+    bh.ngroups = g0[count];
+    const int waves = (c0[count] + 3) / 4;  // one wave per chromosome, 4 per workgroup
+    bh.want = std::max(std::max(t0[count], waves), g0[count]);
+    return e;
+}
+
 hipError_t batch_build(BatchHost &bh, pmp_ga *const *gas, int count)
 {
     bh.gas.assign(gas, gas + count);
-    std::vector<BatchItem> items((size_t)count);
-    std::vector<int32_t> prefix(3 * ((size_t)count + 1), 0);
-    int32_t *c0 = prefix.data(), *t0 = c0 + count + 1, *g0 = t0 + count + 1;
+    bh.items.assign((size_t)count, BatchItem{});
+    bh.prefix.assign(3 * ((size_t)count + 1), 0);
+    bh.base_cpb.assign((size_t)count, 0);
+    int32_t *c0 = bh.prefix.data(), *g0 = c0 + 2 * (count + 1);
     int max_S = 0, max_w2 = 2;
     for (int b = 0; b < count; ++b) {
         pmp_ga *ga = gas[b];
-        BatchItem &it = items[b];
+        BatchItem &it = bh.items[b];
         it.g = ga->args();
         it.e = ga_eval_args(ga, it.g, 0);
         it.e.done = nullptr;
         // The batch evaluation runs 16 waves per workgroup: a tile tuned for
         // fewer waves keeps its clients per wave with proportionally more
         // clients per workgroup (fewer client tiles, so the partial sums
-        // still fit); the stage steps read the sums with the same tiling.
+        // still fit).
         const int scale = 16 / std::max(1, std::min(16, ga->waves));
-        it.e.clients_per_block = ga->cpb * scale;
-        it.e.tiles_i = (ga->inst->n + it.e.clients_per_block - 1) / it.e.clients_per_block;
-        it.g.TI = it.e.tiles_i;
+        bh.base_cpb[b] = ga->cpb * scale;
         it.X = ga->xstages();
         it.S = it.X + ga->Y;
         it.fb = ga->final_buf();
         c0[b + 1] = c0[b] + ga->prm.population;
-        t0[b + 1] = t0[b] + it.e.tiles_c * it.e.tiles_i;
         g0[b + 1] = g0[b] + ga->NB;
         max_S = max_S > it.S ? max_S : it.S;
         max_w2 = max_w2 > 2 * ga->inst->W ? max_w2 : 2 * ga->inst->W;
     }
-    hipError_t e = hipSuccess;
-    if (dalloc(&bh.d_items, (size_t)count) || dalloc(&bh.d_prefix, prefix.size()) ||
+    if (dalloc(&bh.d_items, (size_t)count) || dalloc(&bh.d_prefix, bh.prefix.size()) ||
         dalloc(&bh.d_bar, kBarrierWords) || dalloc(&bh.d_err, 1))
         return hipErrorOutOfMemory;
-    e = hipMemcpy(bh.d_items, items.data(), sizeof(BatchItem) * count, hipMemcpyHostToDevice);
-    if (e == hipSuccess)
-        e = hipMemcpy(bh.d_prefix, prefix.data(), sizeof(int32_t) * prefix.size(),
-                      hipMemcpyHostToDevice);
-    if (e == hipSuccess)
-        e = hipMemset(bh.d_bar, 0, sizeof(uint32_t) * kBarrierWords);
+    hipError_t e = hipMemset(bh.d_bar, 0, sizeof(uint32_t) * kBarrierWords);
     if (e == hipSuccess)
         e = hipMemset(bh.d_err, 0, sizeof(uint32_t));
     bh.args.items = bh.d_items;
@@ -692,13 +727,8 @@ hipError_t batch_build(BatchHost &bh, pmp_ga *const *gas, int count)
     bh.args.bar = bh.d_bar;
     bh.args.err = bh.d_err;
     bh.max_w2 = max_w2;
-    bh.nchrom = c0[count];
-    bh.ntiles = t0[count];
-    bh.ngroups = g0[count];
-    const int waves = (c0[count] + 3) / 4;  // one wave per chromosome, 4 per workgroup
-    bh.want = t0[count] > waves ? t0[count] : waves;
-    if (g0[count] > bh.want)
-        bh.want = g0[count];
+    if (e == hipSuccess)
+        e = batch_tiles(bh, env_int("PMP_BATCH_CLIENTS", 0));
     return e;
 }
 
@@ -2314,6 +2344,118 @@ pmp_status pmp_batch_create(pmp_ga *const *gas, int32_t count, pmp_batch **out)
     bt->persistent = mode && strcmp(mode, "persistent") == 0;
     bt->max_blocks = env_int("PMP_GA_BLOCKS", 0);
     *out = bt;
+    return PMP_OK;
+}
+
+pmp_status pmp_batch_autotune(pmp_batch *bt, int32_t *min_clients, void *stream)
+{
+    if (!bt)
+        return fail(PMP_EINVAL, "batch is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    BatchHost &bh = bt->bh;
+    HIP_TRY(hipStreamSynchronize(s));
+    if (env_int("PMP_BATCH_CLIENTS", 0) > 0) {  // set by hand: no timing
+        if (min_clients)
+            *min_clients = bh.min_cpb;
+        return PMP_OK;
+    }
+    for (size_t b = 0; b < bh.gas.size(); ++b) {
+        unsigned long long gen = 0;
+        HIP_TRY(hipMemcpy(&gen, bh.gas[b]->gs + GS_GEN, sizeof gen, hipMemcpyDeviceToHost));
+        if (gen != 0)
+            return fail(PMP_EINVAL, "autotune a batch before its first step (run %zu)", b);
+    }
+    // measured choices are shared by batches of the same run shapes
+    static std::mutex mu;
+    static std::map<std::vector<int32_t>, int> cache;
+    std::vector<int32_t> key;
+    key.reserve(5 * bh.gas.size());
+    for (size_t b = 0; b < bh.gas.size(); ++b) {
+        const pmp_ga *ga = bh.gas[b];
+        key.insert(key.end(), {ga->inst->n, ga->inst->m, ga->inst->p, ga->prm.population,
+                               bh.base_cpb[b]});
+    }
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            if (batch_tiles(bh, it->second) != hipSuccess)
+                return fail(PMP_EDEVICE, "batch tiling upload");
+            if (min_clients)
+                *min_clients = it->second;
+            return PMP_OK;
+        }
+    }
+    // the probe's inputs: every run's generation-0 population (buffer 0)
+    for (pmp_ga *ga : bh.gas)
+        HIP_TRY(launch_ga_init(ga->args(), s));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess)
+        e = hipEventCreate(&e1);
+    // A floor's time is the least of three trials of four back-to-back
+    // evaluations; the runs' own tiling (floor 0) is timed first and is only
+    // replaced by a floor at least 3 % faster.
+    auto time_it = [&](int floor) -> float {
+        if (e == hipSuccess)
+            e = batch_tiles(bh, floor);
+        if (e == hipSuccess)
+            e = launch_ga_batch_eval(bh.args, bh.ntiles, bh.max_w2, s);  // warm-up
+        float least = 1e30f;
+        for (int trial = 0; trial < 3 && e == hipSuccess; ++trial) {
+            e = hipEventRecord(e0, s);
+            for (int rep = 0; rep < 4 && e == hipSuccess; ++rep)
+                e = launch_ga_batch_eval(bh.args, bh.ntiles, bh.max_w2, s);
+            if (e == hipSuccess)
+                e = hipEventRecord(e1, s);
+            if (e == hipSuccess)
+                e = hipEventSynchronize(e1);
+            float ms = 0;
+            if (e == hipSuccess)
+                e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess && ms < least)
+                least = ms;
+        }
+        return least;
+    };
+    int best = 0;
+    float best_ms = time_it(0);
+    const int floors[] = {64, 96, 128, 192, 256, 384, 512};
+    int last_tiles = bh.ntiles;
+    for (int f : floors) {
+        if (e != hipSuccess)
+            break;
+        // a floor that changes no run's tiling is not timed
+        int tiles = 0;
+        for (size_t b = 0; b < bh.gas.size(); ++b) {
+            const int cpb = std::max(bh.base_cpb[b], f);
+            tiles += bh.items[b].e.tiles_c * ((bh.gas[b]->inst->n + cpb - 1) / cpb);
+        }
+        if (tiles == last_tiles)
+            continue;
+        last_tiles = tiles;
+        const float ms = time_it(f);
+        if (ms < 0.97f * best_ms) {
+            best_ms = ms;
+            best = f;
+        }
+    }
+    if (e0)
+        (void)hipEventDestroy(e0);
+    if (e1)
+        (void)hipEventDestroy(e1);
+    if (e == hipSuccess)
+        e = batch_tiles(bh, best);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return fail(PMP_EDEVICE, "batch autotune: %s", hipGetErrorString(e));
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        cache[key] = best;
+    }
+    if (min_clients)
+        *min_clients = best;
     return PMP_OK;
 }
 

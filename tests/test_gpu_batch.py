@@ -183,8 +183,10 @@ def test_full_batch_config(pm):
         ga = pm.GA(inst, 256, 256, 100, seed=s["index"])
         ga.autotune()
         gas.append(ga)
-    _say("batch step")
+    _say("batch autotune")
     batch = pm.Batch(gas)
+    floor = batch.autotune()
+    _say("batch step, client floor", floor)
     batch.step(G)
     batch.check()
     by_n = sorted(range(256), key=lambda b: specs[b]["n"])
@@ -208,6 +210,55 @@ def test_full_batch_config(pm):
             assert a[5] == st.best_cost
             assert a[6]["chromosome_evals"] == st.state[oracle.ST_CHROM_EVALS]
     batch.close()
+
+
+@pytest.mark.parametrize("how", ["autotuned", "floor512", "floor96_persistent"])
+def test_batch_client_tiling_keeps_results(pm, how):
+    """The batch evaluation's client tiling (each run's own tuning, or a
+    common floor of clients per workgroup, timed by the batch autotuner or
+    set by hand) changes no run: every batched run equals the run stepped
+    alone.  The autotuner refuses a batch past its first step."""
+    keys = ("PMP_BATCH_CLIENTS", "PMP_BATCH_MODE")
+    old = {k: os.environ.get(k) for k in keys}
+    for k in keys:
+        os.environ.pop(k, None)
+    if how == "floor512":
+        os.environ["PMP_BATCH_CLIENTS"] = "512"
+    elif how == "floor96_persistent":
+        os.environ["PMP_BATCH_CLIENTS"] = "96"
+        os.environ["PMP_BATCH_MODE"] = "persistent"
+    try:
+        cases = _mini_batch()
+        G = 5
+        insts, gas = _make(pm, cases, G)
+        for g in gas:
+            g.autotune()
+        batch = pm.Batch(gas)
+        floor = batch.autotune()
+        _say(how, "floor", floor)
+        if how == "autotuned":
+            assert floor in (0, 64, 96, 128, 192, 256, 384, 512)
+        else:
+            assert floor == int(os.environ["PMP_BATCH_CLIENTS"])
+        batch.step(2)
+        batch.step(3)
+        batch.check()
+        if how == "autotuned":
+            with pytest.raises(pm.PmpError) as e:
+                batch.autotune()
+            assert e.value.status == pm.PMP_EINVAL
+        rinsts, refs = _make(pm, cases, G)
+        for r in refs:
+            r.step(G)
+        for ga, ref in zip(gas, refs):
+            _assert_same(_state(ga), _state(ref))
+        batch.close()
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
 
 
 def test_batch_profiled_steps_keep_results(pm):
