@@ -305,6 +305,8 @@ struct BatchArgs {
     const int32_t *chrom0;  // count + 1 prefix offsets of chromosomes
     const int32_t *tile0;   // ... of evaluation tiles
     const int32_t *group0;  // ... of groups
+    // the run of every chromosome, evaluation tile and group of the batch
+    const int32_t *chrom_run, *tile_run, *group_run;
     int32_t count, max_S;
     uint32_t *bar;          // grid barrier: epoch word, then one flag per
                             // workgroup (32 words apart)

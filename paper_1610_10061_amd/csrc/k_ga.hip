@@ -376,21 +376,6 @@ struct GridBarrier {
     }
 };
 
-// Instance owning global item `x` of a range with prefix offsets `start`
-// (count + 1 entries): the last b with start[b] <= x.
-__device__ __forceinline__ int owner(const int32_t *start, int count, int x)
-{
-    int lo = 0, hi = count - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (start[mid] <= x)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    return lo;
-}
-
 // Evaluation phase: evaluation tiles of every instance whose generation has
 // a stage k (k < 0: the population's first evaluation), evaluating offspring
 // buffer `buf`.  The global tile range (instance-major, client-tile major
@@ -407,7 +392,7 @@ __device__ __forceinline__ void eval_phase(const BatchArgs &B, int k, int buf,
     const int x = blockIdx.x & 7, per = (int)gridDim.x >> 3;
     const int end = min(ntiles, (x + 1) * chunk);
     for (int item = x * chunk + ((int)blockIdx.x >> 3); item < end; item += per) {
-        const int b = owner(B.tile0, B.count, item);
+        const int b = B.tile_run[item];
         const BatchItem &it = B.items[b];
         if (ga_stopped(it.g) || k >= it.S)
             continue;
@@ -457,7 +442,7 @@ __global__ __launch_bounds__(64 * kGaWaves) void k_ga_batch(BatchArgs B,
         if (all_stopped(B))
             return;
         for (int cg = gw; cg < nchrom; cg += nw) {
-            const int b = owner(B.chrom0, B.count, cg);
+            const int b = B.chrom_run[cg];
             const BatchItem &it = B.items[b];
             // the sampler's 2 W words per wave fit in WD (>= 2 W) words of
             // the evaluation's LDS, which is idle in this phase
@@ -471,7 +456,7 @@ __global__ __launch_bounds__(64 * kGaWaves) void k_ga_batch(BatchArgs B,
             return;
         for (int k = 0; k <= B.max_S; ++k) {
             for (int cg = gw; cg < nchrom; cg += nw) {
-                const int b = owner(B.chrom0, B.count, cg);
+                const int b = B.chrom_run[cg];
                 const BatchItem &it = B.items[b];
                 if (ga_stopped(it.g) || k > it.S)
                     continue;
@@ -488,7 +473,7 @@ __global__ __launch_bounds__(64 * kGaWaves) void k_ga_batch(BatchArgs B,
             }
         }
         for (int xg = blockIdx.x; xg < ngroups; xg += gridDim.x) {
-            const int b = owner(B.group0, B.count, xg);
+            const int b = B.group_run[xg];
             const BatchItem &it = B.items[b];
             if (!ga_stopped(it.g))
                 ga_group_best(it.g, it.fb, xg - B.group0[b], sc, si);
@@ -515,7 +500,7 @@ __global__ __launch_bounds__(64 * kGaWaves) void k_batch_init(BatchArgs B)
     const int cg = blockIdx.x * kGaWaves + wave_id();
     if (cg >= B.chrom0[B.count])
         return;
-    const int b = owner(B.chrom0, B.count, cg);
+    const int b = B.chrom_run[cg];
     const BatchItem &it = B.items[b];
     if (!ga_stopped(it.g))
         ga_init_one(it.g, cg - B.chrom0[b], threadIdx.x & 63, sw[wave_id()]);
@@ -539,7 +524,7 @@ __global__ __launch_bounds__(kEvalTile *kBatchEvalWaves) void k_batch_eval(Batch
     const int item = ((int)blockIdx.x & 7) * per_xcd + ((int)blockIdx.x >> 3);
     if (item >= ntiles)
         return;
-    const int b = owner(B.tile0, B.count, item);
+    const int b = B.tile_run[item];
     const BatchItem &it = B.items[b];
     if (ga_stopped(it.g) || k >= it.S)
         return;
@@ -560,7 +545,7 @@ __global__ __launch_bounds__(64 * kGaWaves) void k_batch_stage(BatchArgs B, int 
     const int cg = blockIdx.x * kGaWaves + wave_id();
     if (cg >= B.chrom0[B.count])
         return;
-    const int b = owner(B.chrom0, B.count, cg);
+    const int b = B.chrom_run[cg];
     const BatchItem &it = B.items[b];
     if (ga_stopped(it.g) || k > it.S)
         return;
@@ -577,7 +562,7 @@ __global__ __launch_bounds__(256) void k_batch_best(BatchArgs B)
     __shared__ int si[16];
     __shared__ int last;
     const int xg = blockIdx.x;
-    const int b = owner(B.group0, B.count, xg);
+    const int b = B.group_run[xg];
     const BatchItem &it = B.items[b];
     if (ga_stopped(it.g))
         return;

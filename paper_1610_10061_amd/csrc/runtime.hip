@@ -362,6 +362,11 @@ struct BatchHost {
     std::vector<int32_t> prefix;
     std::vector<int32_t> base_cpb;
     int min_cpb = 0;
+    // run of every chromosome, group and evaluation tile (host copy and
+    // device table; tiles sized for the finest tiling, min_cpb = 0)
+    std::vector<int32_t> runs;
+    int32_t *d_runs = nullptr;
+    int max_tiles = 0;
 
     void drop_graphs()
     {
@@ -375,6 +380,7 @@ struct BatchHost {
         drop_graphs();
         dfree(d_items);
         dfree(d_prefix);
+        dfree(d_runs);
         dfree(d_bar);
         dfree(d_err);
     }
@@ -669,11 +675,18 @@ hipError_t batch_tiles(BatchHost &bh, int min_cpb)
         it.g.TI = it.e.tiles_i;
         t0[b + 1] = t0[b] + it.e.tiles_c * it.e.tiles_i;
     }
+    int32_t *tile_run = bh.runs.data() + c0[count] + g0[count];
+    for (int b = 0; b < count; ++b)
+        for (int x = t0[b]; x < t0[b + 1]; ++x)
+            tile_run[x] = b;
     bh.drop_graphs();
     hipError_t e = hipMemcpy(bh.d_items, bh.items.data(), sizeof(BatchItem) * count,
                              hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(bh.d_prefix, bh.prefix.data(), sizeof(int32_t) * bh.prefix.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(bh.d_runs, bh.runs.data(), sizeof(int32_t) * bh.runs.size(),
                       hipMemcpyHostToDevice);
     bh.min_cpb = min_cpb;
     bh.nchrom = c0[count];
@@ -712,8 +725,21 @@ hipError_t batch_build(BatchHost &bh, pmp_ga *const *gas, int count)
         max_S = max_S > it.S ? max_S : it.S;
         max_w2 = max_w2 > 2 * ga->inst->W ? max_w2 : 2 * ga->inst->W;
     }
+    // the finest tiling's tile count bounds every tiling's
+    bh.max_tiles = 0;
+    for (int b = 0; b < count; ++b)
+        bh.max_tiles += bh.items[b].e.tiles_c *
+                        ((gas[b]->inst->n + bh.base_cpb[b] - 1) / bh.base_cpb[b]);
+    bh.runs.assign((size_t)c0[count] + g0[count] + bh.max_tiles, 0);
+    for (int b = 0; b < count; ++b) {
+        for (int x = c0[b]; x < c0[b + 1]; ++x)
+            bh.runs[x] = b;
+        for (int x = g0[b]; x < g0[b + 1]; ++x)
+            bh.runs[c0[count] + x] = b;
+    }
     if (dalloc(&bh.d_items, (size_t)count) || dalloc(&bh.d_prefix, bh.prefix.size()) ||
-        dalloc(&bh.d_bar, kBarrierWords) || dalloc(&bh.d_err, 1))
+        dalloc(&bh.d_runs, bh.runs.size()) || dalloc(&bh.d_bar, kBarrierWords) ||
+        dalloc(&bh.d_err, 1))
         return hipErrorOutOfMemory;
     hipError_t e = hipMemset(bh.d_bar, 0, sizeof(uint32_t) * kBarrierWords);
     if (e == hipSuccess)
@@ -722,6 +748,9 @@ hipError_t batch_build(BatchHost &bh, pmp_ga *const *gas, int count)
     bh.args.chrom0 = bh.d_prefix;
     bh.args.tile0 = bh.d_prefix + count + 1;
     bh.args.group0 = bh.d_prefix + 2 * (count + 1);
+    bh.args.chrom_run = bh.d_runs;
+    bh.args.group_run = bh.d_runs + c0[count];
+    bh.args.tile_run = bh.d_runs + c0[count] + g0[count];
     bh.args.count = count;
     bh.args.max_S = max_S;
     bh.args.bar = bh.d_bar;
