@@ -109,7 +109,7 @@ def valu_roofline(ctr, pairs, seconds, launches):
     if not ctr or not seconds or not pairs:
         return {"bound": "alu", "achieved": None, "peak": VALU_PEAK_GIPS,
                 "unit": "G wave64 VALU instructions/s", "frac": None, "traffic": None,
-                "note": "no counter summary matching the kernel's sources"}
+                "note": "no counter summary matching the kernel's sources and tile"}
     per_pair = ctr["SQ_INSTS_VALU"] / ctr["pairs"]
     achieved = per_pair * pairs / seconds / 1e9
     out = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_GIPS,
@@ -233,10 +233,10 @@ def leg_batch(args, specs, ds):
         gas = [pm.GA(i, 256, 256, G, seed0 + s["index"]) for i, s in zip(insts, specs)]
         for g in gas:
             g.autotune(stream)
-        floor = None
+        common = None
         if batched:
             bt = pm.Batch(gas)
-            floor = bt.autotune(stream)
+            common = bt.autotune(stream)
         t1 = time.perf_counter()
         prof = None
         if batched:
@@ -262,17 +262,17 @@ def leg_batch(args, specs, ds):
             costs.append(c)
         if batched:
             bt.close()
-        return t1 - t0, t2 - t1, pairs, costs, prof, floor
+        return t1 - t0, t2 - t1, pairs, costs, prof, common
 
     if args.batch_only:
         log("batched (alone) ...")
-        prep_b, evo_b, pairs_b, costs_b, prof_b, floor_b = run(True, 0, profile=True)
+        prep_b, evo_b, pairs_b, costs_b, prof_b, common_b = run(True, 0, profile=True)
         return {"batch_only": True, "evolve_s": evo_b, "eval_ms": prof_b[0],
-                "eval_launches": prof_b[1], "client_floor": floor_b}
+                "eval_launches": prof_b[1], "batch_clients": common_b}
     log("warm-up ...")
     run(True, 10_000)
     log("batched ...")
-    prep_b, evo_b, pairs_b, costs_b, prof_b, floor_b = run(True, 0, profile=True)
+    prep_b, evo_b, pairs_b, costs_b, prof_b, common_b = run(True, 0, profile=True)
     log("one launch per instance ...")
     prep_s, evo_s, pairs_s, costs_s, _, _ = run(False, 0)
     assert costs_b == costs_s, "batched and per-instance runs must agree"
@@ -285,7 +285,7 @@ def leg_batch(args, specs, ds):
                                "half graphs (4n edges, weights 1..100), half Euclidean; "
                                "population 256 (NT=256), %d generations" % G},
         "batched": {"preprocess_s": prep_b, "evolve_s": evo_b,
-                    "client_floor": floor_b,
+                    "batch_clients": common_b,
                     "instances_per_s_evolve": 256 / evo_b,
                     "pair_evals_per_s": pairs_b / evo_b},
         "per_instance_launches": {"preprocess_s": prep_s, "evolve_s": evo_s,
@@ -293,18 +293,21 @@ def leg_batch(args, specs, ds):
                                   "pair_evals_per_s": pairs_s / evo_s},
         "speedup_evolve": evo_s / evo_b,
         "identical_results": costs_b == costs_s,
-        "roofline": batch_eval_roofline(prof_b),
+        "roofline": batch_eval_roofline(prof_b, common_b),
     }
 
 
-def batch_eval_roofline(prof):
+def batch_eval_roofline(prof, clients):
     """VALU-issue roofline of the batch evaluation kernel (k_batch_eval): the
     VALU instructions per launch that rocprofv3 counted for the same launches
-    (the first BATCH_PROFILE_GENS generations of the same batched run, case
-    batch_eval of the committed counter summary) over the launches' time
+    (the first BATCH_PROFILE_GENS generations of the same batched run with the
+    same client tiling, case batch_eval@<clients> of the committed counter
+    summary) over the launches' time
     measured here."""
     ms, launches = prof if prof else (0.0, 0)
-    ctr = eval_counters("batch_eval")
+    # counters are taken per common client tiling (a run's own tuning varies
+    # from process to process, so a batch tiled by it has none)
+    ctr = eval_counters(f"batch_eval@{clients}") if clients else None
     out = {"kernel": "k_batch_eval", "bound": "alu", "peak": VALU_PEAK_GIPS,
            "unit": "G wave64 VALU instructions/s", "launches": launches,
            "avg_launch_us": ms * 1e3 / max(launches, 1),
@@ -312,12 +315,13 @@ def batch_eval_roofline(prof):
                       "the timed batched run (HIP events recorded by each dispatch)"}
     if not ctr or not ms or not launches or ctr.get("dispatches") != launches:
         out.update({"achieved": None, "frac": None, "traffic": None,
-                    "note": "no counter summary matching the kernel's sources and launches"})
+                    "note": "no counter summary matching the kernel's sources, the batch's "
+                            f"client tiling ({clients} clients per workgroup) and launches"})
         return out
     achieved = ctr["SQ_INSTS_VALU"] * launches / (ms / 1e3) / 1e9
     out.update({"achieved": achieved, "frac": achieved / VALU_PEAK_GIPS,
                 "traffic": ctr.get("hbm_bytes"),
-                "counters": "profiles/k_eval_counters.json (case batch_eval)"})
+                "counters": f"profiles/k_eval_counters.json (case batch_eval@{clients})"})
     if ctr.get("hbm_bytes") is not None:
         gbs = ctr["hbm_bytes"] / (ms / 1e3 / launches) / 1e9
         out["hbm_measured"] = {"GBps": gbs, "frac": gbs / HBM_PEAK_GBS}
@@ -1008,7 +1012,11 @@ def main():
     ev_n = sum(pr["eval_launches"] for pr in profs)
     ev_bytes = sum(pr["eval_bytes"] for pr in profs)
     ev_pairs = sum(pr["eval_pairs"] for pr in profs)
-    roof = valu_roofline(eval_counters("g900_ga"), ev_pairs, ev_ms / 1e3, ev_n)
+    # counters are taken per client tile of the plain evaluation (the
+    # autotuner's choice; the fused launches' tile follows from the shape)
+    tile = rec[0][3] if rec else (0, 0)
+    roof = valu_roofline(eval_counters(f"g900_ga@{tile[0]}x{tile[1]}"), ev_pairs, ev_ms / 1e3,
+                         ev_n)
     roof = dict({"bound": roof.pop("bound"),
                  "kernel": "k_stage_eval + k_eval (the crossover stages fused with their "
                            "evaluations, the population's and the mutants' evaluations)"},
@@ -1020,8 +1028,9 @@ def main():
         "pairs_per_launch": ev_pairs / max(ev_n, 1),
         "sampled": f"evaluation launches of the first {PROFILE_GENS} generations of each "
                    "timed step (HIP events recorded by each dispatch)",
-        "counters": "profiles/k_eval_counters.json (case g900_ga; null fields when the "
-                    "evaluation kernel changed since)",
+        "counters": f"profiles/k_eval_counters.json (case g900_ga@{tile[0]}x{tile[1]}: this "
+                    "run's tile; null fields when the evaluation kernels changed since or the "
+                    "tile has no counters)",
         "paper_form_bytes": {
             "bytes_per_launch": ev_bytes / max(ev_n, 1), "GBps": paper_gbs,
             "vs_hbm_peak": paper_gbs / HBM_PEAK_GBS,

@@ -369,16 +369,19 @@ PMP_API pmp_status pmp_ga_autotune(pmp_ga *ga, int32_t *clients, int32_t *waves,
  *                   Asynchronous.
  * pmp_batch_autotune  choose the batch evaluation's client tiling by
  *                   timing it: every run keeps its own tuned clients per
- *                   workgroup (scaled to the batch kernel's 16 waves) unless a
- *                   common floor (64 ... 512 clients) is faster over the whole
- *                   batch; the chosen floor goes to `*min_clients` (optional;
- *                   0 = none).  The probe evaluates each run's generation-0
+ *                   workgroup (scaled to the batch kernel's 16 waves) unless
+ *                   one common count of clients per workgroup (64 ... 512;
+ *                   more for a run whose partial sums would not fit) is
+ *                   faster over the whole batch; the choice goes to
+ *                   `*clients` (optional; 0 = each run's own).  The probe
+ *                   evaluates each run's generation-0
  *                   population (made again by the first step, identically),
  *                   so every run must be before its first generation
  *                   (PMP_EINVAL otherwise).  Choices are cached per process by
  *                   the runs' shapes.  Results of the runs do not depend on
  *                   the tiling.  Synchronous on `stream`.  PMP_BATCH_CLIENTS
- *                   sets the floor without timing.
+ *                   sets the common count without timing (also at
+ *                   pmp_batch_create).
  * pmp_batch_check   wait for `stream`; PMP_EDEVICE if a grid barrier timed
  *                   out (the kernel then drains without finishing); `grid`
  *                   (optional) receives the workgroups of the last launch.
@@ -391,7 +394,7 @@ PMP_API pmp_status pmp_batch_create(pmp_ga *const *gas, int32_t count,
                                     pmp_batch **out);
 PMP_API pmp_status pmp_batch_step(pmp_batch *batch, int32_t generations,
                                   void *stream);
-PMP_API pmp_status pmp_batch_autotune(pmp_batch *batch, int32_t *min_clients,
+PMP_API pmp_status pmp_batch_autotune(pmp_batch *batch, int32_t *clients,
                                       void *stream);
 PMP_API pmp_status pmp_batch_check(pmp_batch *batch, int32_t *grid, void *stream);
 PMP_API void pmp_batch_destroy(pmp_batch *batch);

@@ -438,12 +438,12 @@ def pmp_batch_check(batch, stream=None):
 
 
 def pmp_batch_autotune(batch, stream=None):
-    """Time the batch evaluation's client tilings; returns the chosen floor of
-    clients per workgroup (0: every run keeps its own tuning)."""
-    floor = _i32()
-    _check(lib().pmp_batch_autotune(batch, C.byref(floor), _stream(stream)),
+    """Time the batch evaluation's client tilings; returns the chosen common
+    count of clients per workgroup (0: every run keeps its own tuning)."""
+    clients = _i32()
+    _check(lib().pmp_batch_autotune(batch, C.byref(clients), _stream(stream)),
            "pmp_batch_autotune")
-    return floor.value
+    return clients.value
 
 
 def pmp_batch_destroy(batch):

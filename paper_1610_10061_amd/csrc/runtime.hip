@@ -357,13 +357,13 @@ struct BatchHost {
     std::map<int, hipGraphExec_t> graphs;  // by generations per launch
     // host copies of the run table and prefix offsets; each run's clients
     // per workgroup from its own tuning (scaled to the batch kernel's
-    // waves), raised to min_cpb
+    // waves), or `clients` for every run (0: none)
     std::vector<BatchItem> items;
     std::vector<int32_t> prefix;
     std::vector<int32_t> base_cpb;
-    int min_cpb = 0;
+    int clients = 0;
     // run of every chromosome, group and evaluation tile (host copy and
-    // device table; tiles sized for the finest tiling, min_cpb = 0)
+    // device table; tiles sized for the most any tiling can give)
     std::vector<int32_t> runs;
     int32_t *d_runs = nullptr;
     int max_tiles = 0;
@@ -659,18 +659,23 @@ namespace {
 
 EvalArgs ga_eval_args(const pmp_ga *ga, const GaArgs &g, int buf);
 
-// The batch's client tiling: run b takes max(base_cpb[b], min_cpb) clients
-// per evaluation workgroup (never fewer than its own tuning, so its tiles
-// fit the partial-sum buffers sized for that); the stage steps read the
-// partial sums with the same tiling.  Uploads the run table and prefix
-// offsets; graphs captured for another tiling are dropped.
-hipError_t batch_tiles(BatchHost &bh, int min_cpb)
+// The batch's client tiling: with clients = 0 every run keeps its own
+// tuning (base_cpb), else every run takes `clients` clients per evaluation
+// workgroup, or more where its partial-sum buffers (sized for the larger of
+// its own and its fused launches' tile counts) hold fewer tiles than that
+// gives; the stage steps read the partial sums with the same tiling.
+// Uploads the run table and prefix offsets; graphs captured for another
+// tiling are dropped.
+hipError_t batch_tiles(BatchHost &bh, int clients)
 {
     const int count = (int)bh.gas.size();
     int32_t *c0 = bh.prefix.data(), *t0 = c0 + count + 1, *g0 = t0 + count + 1;
     for (int b = 0; b < count; ++b) {
         BatchItem &it = bh.items[b];
-        it.e.clients_per_block = std::max(bh.base_cpb[b], min_cpb);
+        const pmp_ga *ga = bh.gas[b];
+        const int n = ga->inst->n, cap = std::max(ga->TI, ga->fTI);
+        it.e.clients_per_block =
+            clients > 0 ? std::max(clients, (n + cap - 1) / cap) : bh.base_cpb[b];
         it.e.tiles_i = (bh.gas[b]->inst->n + it.e.clients_per_block - 1) / it.e.clients_per_block;
         it.g.TI = it.e.tiles_i;
         t0[b + 1] = t0[b] + it.e.tiles_c * it.e.tiles_i;
@@ -688,7 +693,7 @@ hipError_t batch_tiles(BatchHost &bh, int min_cpb)
     if (e == hipSuccess)
         e = hipMemcpy(bh.d_runs, bh.runs.data(), sizeof(int32_t) * bh.runs.size(),
                       hipMemcpyHostToDevice);
-    bh.min_cpb = min_cpb;
+    bh.clients = clients;
     bh.nchrom = c0[count];
     bh.ntiles = t0[count];
     bh.ngroups = g0[count];
@@ -725,11 +730,10 @@ hipError_t batch_build(BatchHost &bh, pmp_ga *const *gas, int count)
         max_S = max_S > it.S ? max_S : it.S;
         max_w2 = max_w2 > 2 * ga->inst->W ? max_w2 : 2 * ga->inst->W;
     }
-    // the finest tiling's tile count bounds every tiling's
+    // a run's tile count is at most its partial-sum capacity in any tiling
     bh.max_tiles = 0;
     for (int b = 0; b < count; ++b)
-        bh.max_tiles += bh.items[b].e.tiles_c *
-                        ((gas[b]->inst->n + bh.base_cpb[b] - 1) / bh.base_cpb[b]);
+        bh.max_tiles += bh.items[b].e.tiles_c * std::max(gas[b]->TI, gas[b]->fTI);
     bh.runs.assign((size_t)c0[count] + g0[count] + bh.max_tiles, 0);
     for (int b = 0; b < count; ++b) {
         for (int x = c0[b]; x < c0[b + 1]; ++x)
@@ -2376,7 +2380,7 @@ pmp_status pmp_batch_create(pmp_ga *const *gas, int32_t count, pmp_batch **out)
     return PMP_OK;
 }
 
-pmp_status pmp_batch_autotune(pmp_batch *bt, int32_t *min_clients, void *stream)
+pmp_status pmp_batch_autotune(pmp_batch *bt, int32_t *clients, void *stream)
 {
     if (!bt)
         return fail(PMP_EINVAL, "batch is NULL");
@@ -2384,8 +2388,8 @@ pmp_status pmp_batch_autotune(pmp_batch *bt, int32_t *min_clients, void *stream)
     BatchHost &bh = bt->bh;
     HIP_TRY(hipStreamSynchronize(s));
     if (env_int("PMP_BATCH_CLIENTS", 0) > 0) {  // set by hand: no timing
-        if (min_clients)
-            *min_clients = bh.min_cpb;
+        if (clients)
+            *clients = bh.clients;
         return PMP_OK;
     }
     for (size_t b = 0; b < bh.gas.size(); ++b) {
@@ -2410,8 +2414,8 @@ pmp_status pmp_batch_autotune(pmp_batch *bt, int32_t *min_clients, void *stream)
         if (it != cache.end()) {
             if (batch_tiles(bh, it->second) != hipSuccess)
                 return fail(PMP_EDEVICE, "batch tiling upload");
-            if (min_clients)
-                *min_clients = it->second;
+            if (clients)
+                *clients = it->second;
             return PMP_OK;
         }
     }
@@ -2422,12 +2426,12 @@ pmp_status pmp_batch_autotune(pmp_batch *bt, int32_t *min_clients, void *stream)
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess)
         e = hipEventCreate(&e1);
-    // A floor's time is the least of three trials of four back-to-back
-    // evaluations; the runs' own tiling (floor 0) is timed first and is only
-    // replaced by a floor at least 3 % faster.
-    auto time_it = [&](int floor) -> float {
+    // A tiling's time is the least of three trials of four back-to-back
+    // evaluations; the runs' own tiling (0) is timed first and is only
+    // replaced by a common one at least 3 % faster.
+    auto time_it = [&](int common) -> float {
         if (e == hipSuccess)
-            e = batch_tiles(bh, floor);
+            e = batch_tiles(bh, common);
         if (e == hipSuccess)
             e = launch_ga_batch_eval(bh.args, bh.ntiles, bh.max_w2, s);  // warm-up
         float least = 1e30f;
@@ -2449,20 +2453,10 @@ pmp_status pmp_batch_autotune(pmp_batch *bt, int32_t *min_clients, void *stream)
     };
     int best = 0;
     float best_ms = time_it(0);
-    const int floors[] = {64, 96, 128, 192, 256, 384, 512};
-    int last_tiles = bh.ntiles;
-    for (int f : floors) {
+    const int commons[] = {64, 96, 128, 192, 256, 384, 512};
+    for (int f : commons) {
         if (e != hipSuccess)
             break;
-        // a floor that changes no run's tiling is not timed
-        int tiles = 0;
-        for (size_t b = 0; b < bh.gas.size(); ++b) {
-            const int cpb = std::max(bh.base_cpb[b], f);
-            tiles += bh.items[b].e.tiles_c * ((bh.gas[b]->inst->n + cpb - 1) / cpb);
-        }
-        if (tiles == last_tiles)
-            continue;
-        last_tiles = tiles;
         const float ms = time_it(f);
         if (ms < 0.97f * best_ms) {
             best_ms = ms;
@@ -2483,8 +2477,8 @@ pmp_status pmp_batch_autotune(pmp_batch *bt, int32_t *min_clients, void *stream)
         std::lock_guard<std::mutex> lock(mu);
         cache[key] = best;
     }
-    if (min_clients)
-        *min_clients = best;
+    if (clients)
+        *clients = best;
     return PMP_OK;
 }
 

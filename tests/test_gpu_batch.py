@@ -185,8 +185,8 @@ def test_full_batch_config(pm):
         gas.append(ga)
     _say("batch autotune")
     batch = pm.Batch(gas)
-    floor = batch.autotune()
-    _say("batch step, client floor", floor)
+    clients = batch.autotune()
+    _say("batch step, clients per workgroup", clients)
     batch.step(G)
     batch.check()
     by_n = sorted(range(256), key=lambda b: specs[b]["n"])
@@ -212,19 +212,19 @@ def test_full_batch_config(pm):
     batch.close()
 
 
-@pytest.mark.parametrize("how", ["autotuned", "floor512", "floor96_persistent"])
+@pytest.mark.parametrize("how", ["autotuned", "common512", "common96_persistent"])
 def test_batch_client_tiling_keeps_results(pm, how):
     """The batch evaluation's client tiling (each run's own tuning, or a
-    common floor of clients per workgroup, timed by the batch autotuner or
+    common count of clients per workgroup, timed by the batch autotuner or
     set by hand) changes no run: every batched run equals the run stepped
     alone.  The autotuner refuses a batch past its first step."""
     keys = ("PMP_BATCH_CLIENTS", "PMP_BATCH_MODE")
     old = {k: os.environ.get(k) for k in keys}
     for k in keys:
         os.environ.pop(k, None)
-    if how == "floor512":
+    if how == "common512":
         os.environ["PMP_BATCH_CLIENTS"] = "512"
-    elif how == "floor96_persistent":
+    elif how == "common96_persistent":
         os.environ["PMP_BATCH_CLIENTS"] = "96"
         os.environ["PMP_BATCH_MODE"] = "persistent"
     try:
@@ -234,12 +234,12 @@ def test_batch_client_tiling_keeps_results(pm, how):
         for g in gas:
             g.autotune()
         batch = pm.Batch(gas)
-        floor = batch.autotune()
-        _say(how, "floor", floor)
+        clients = batch.autotune()
+        _say(how, "clients per workgroup", clients)
         if how == "autotuned":
-            assert floor in (0, 64, 96, 128, 192, 256, 384, 512)
+            assert clients in (0, 64, 96, 128, 192, 256, 384, 512)
         else:
-            assert floor == int(os.environ["PMP_BATCH_CLIENTS"])
+            assert clients == int(os.environ["PMP_BATCH_CLIENTS"])
         batch.step(2)
         batch.step(3)
         batch.check()
