@@ -191,6 +191,46 @@ __device__ __forceinline__ void features16_sums(const FeatCtx &x, double A, doub
     out[15] = 1.f;
 }
 
+// Half `half` (features 8 half .. 8 half + 7) of features16_sums, with six
+// divisions whatever the half and the open flag (the operands are selected,
+// the results the same bit for bit): the lanes of a wave that split a row's
+// features this way all run the same instructions.
+__device__ __forceinline__ void features8_sums(const FeatCtx &x, double A, double D, double Bv,
+                                               double Cv, double E, int j, bool open, int half,
+                                               float out[8])
+{
+    const double n = x.n, m = x.m, p = x.p;
+    const double F = x.f > 0 ? (double)x.f : 1.0;
+    const double T = x.total > 0 ? (double)x.total : 1.0;
+    const bool h = half != 0;
+    const float s0 = fdiv3(h ? D : A, p, n);
+    const float s1 = fdiv3(h ? Cv : Bv, p, F);
+    const double cs = (double)x.colsum[j], nc = (double)x.nearc[j];
+    const float s2 = fdiv3(h ? cs : Cv, h ? m : p, h ? T : F);
+    const float s3 = fdiv3(h ? nc : D, h ? m : p, h ? n * (double)x.near_len : n);
+    const float s4 = fdiv3(h ? p : E, h ? 1.0 : p, h ? m : F);  // (p * 1 / m = p / m)
+    const float s5 = fdiv3(h ? (double)x.f : 0.0, h ? m : 1.0, h ? T : 1.0);
+    if (!h) {
+        out[0] = open ? 1.f : 0.f;
+        out[1] = open ? s0 : 0.f;
+        out[2] = open ? s1 : 0.f;
+        out[3] = open ? s2 : 0.f;
+        out[4] = open ? s3 : 0.f;
+        out[5] = open ? s4 : 0.f;
+        out[6] = open ? 0.f : s0;
+        out[7] = open ? 0.f : s1;
+    } else {
+        out[0] = open ? 0.f : s0;
+        out[1] = open ? 0.f : s1;
+        out[2] = s2;
+        out[3] = s3;
+        out[4] = s4;
+        out[5] = s5;
+        out[6] = x.gen_frac;
+        out[7] = 1.f;
+    }
+}
+
 // The 16 features of facility j (slot s of B, or -1 for none gathered).
 __device__ __forceinline__ void features16(const FeatCtx &x, const SlotBins &B, int s,
                                            int j, bool open, float out[kFeatures])

@@ -112,6 +112,28 @@ __device__ __forceinline__ void wave_lds_sync()
 constexpr int kXStride = kIn + 4;       // padded LDS row of inputs (BF16)
 constexpr int kHStride = kHidden + 4;   // padded LDS row of activations
 
+// The output layer's terms of hidden tiles 2q and 2q + 1 for one row (this
+// lane's unit of each tile, z: pre-activations, w: output weights), summed
+// over the 16 lanes of the row's group (every lane ends with the sum).
+__device__ __forceinline__ float out_pair(float z_a, float z_b, float w_a, float w_b)
+{
+    float v = fmaxf(z_a, 0.f) * w_a;
+    v += fmaxf(z_b, 0.f) * w_b;
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    v += __shfl_xor(v, 4);
+    v += __shfl_xor(v, 8);
+    return v;
+}
+
+// The output from the four tile pairs' sums; every kernel adds them in this
+// order, so that a row's output is the same bits whichever kernel computes
+// it (one wave over all tiles, or a wave per tile pair).
+__device__ __forceinline__ float out_sum(const float s[4], float b3)
+{
+    return ((s[0] + s[1]) + (s[2] + s[3])) + b3;
+}
+
 // Forward pass of 16 rows by one wave.  x: the rows' inputs in LDS (row r at
 // x + r * kXStride); h1: 16 x kHStride BF16 of LDS scratch.  Leaves the
 // pre-activations z1 = W1 x + b1 and z2 = W2 h1 + b2 in D layout (tile t =
@@ -163,23 +185,15 @@ __device__ __forceinline__ void mlp_forward16(const MlpDev &P, const uint16_t *x
             acc[i] += bias;
         z2[t] = acc;
     }
-    float part[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        const float w = bf16_to_f32(P.w3[t * 16 + r]);
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            part[i] += fmaxf(z2[t][i], 0.f) * w;
-    }
     const float b3 = P.b3[0];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        float v = part[i];
-        v += __shfl_xor(v, 1);
-        v += __shfl_xor(v, 2);
-        v += __shfl_xor(v, 4);
-        v += __shfl_xor(v, 8);
-        y[i] = v + b3;
+        float s[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            s[q] = out_pair(z2[2 * q][i], z2[2 * q + 1][i], bf16_to_f32(P.w3[2 * q * 16 + r]),
+                            bf16_to_f32(P.w3[(2 * q + 1) * 16 + r]));
+        y[i] = out_sum(s, b3);
     }
     wave_lds_sync();  // h1 may be reused by the caller
 }
