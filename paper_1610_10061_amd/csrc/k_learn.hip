@@ -890,9 +890,9 @@ struct RowState {
     }
 };
 
-// Positions nearL .. e2 - 1 of client ii's row (one beyond the index) walked
-// by `width` lanes starting at lane `first` of the group (a 16-lane row or
-// the whole wave).
+// Positions nearL .. e2 - 1 of client ii's row (those beyond the index)
+// walked by a group of `width` lanes (a 16-lane row or the whole wave; this
+// lane is number `sub` of it), four steps of loads in flight per round.
 __device__ __forceinline__ void walk_far(const Tables &t, SlotBins &B, const uint64_t *cb,
                                          const uint8_t *cp, int ii, uint32_t v, uint2 cc,
                                          int nearL, int sub, int width)
@@ -902,19 +902,74 @@ __device__ __forceinline__ void walk_far(const Tables &t, SlotBins &B, const uin
     const int e2 = s2 < 0 ? t.K : s2 + 1;
     const uint16_t *prow = t.pi + (int64_t)ii * t.pitch;
     const int32_t *drow = t.ds + (int64_t)ii * t.pitch;
-    for (int p0 = nearL; p0 < e2; p0 += width) {
-        const int pos = p0 + sub;
-        if (pos < e2) {
-            const int f = prow[pos];
-            const int32_t d = drow[pos];
-            const int sl = cand_slot(cb, cp, f);
-            if (sl >= 0)
-                add_terms(B, sl, pos, s1, s2, (int32_t)cc.x, (int32_t)cc.y, d);
+    // four steps' loads in flight per round (clamped into the row)
+    for (int p0 = nearL; p0 < e2; p0 += 4 * width) {
+        int f[4];
+        int32_t d[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int pos = min(p0 + u * width + sub, e2 - 1);
+            f[u] = prow[pos];
+            d[u] = drow[pos];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int pos = p0 + u * width + sub;
+            if (pos < e2) {
+                const int sl = cand_slot(cb, cp, f[u]);
+                if (sl >= 0)
+                    add_terms(B, sl, pos, s1, s2, (int32_t)cc.x, (int32_t)cc.y, d[u]);
+            }
         }
     }
 }
 
-// Pass 2, a workgroup per chromosome.  Its clients' (s1, s2, c1, c2) are
+// One 16-lane row's sums of a slot's index entries: an entry (client i,
+// position k, D'_{i,k}) adds the terms of position k of client i's walk (the
+// one-pass walk's terms) when k lies up to the client's second open
+// position.
+struct SlotAcc {
+    unsigned long long ad = 0, sb = 0, scc = 0, se = 0;  // ad: a | dd << 32
+    template <bool Stage>
+    __device__ __forceinline__ void add(uint2 en, const RowState<Stage> &rs)
+    {
+        if (en.x == 0xFFFFFFFFu)
+            return;
+        const int i = (int)(en.x >> 6), k = (int)(en.x & 63u);
+        const int32_t dist = (int32_t)en.y;
+        const uint32_t sv = rs.s(i);
+        const int s1 = (int)(sv & 0xFFFFu), s2x = (int)(sv >> 16);
+        if (k <= s2x) {  // (s2x = 0xFFFF, no second: every k < nearL)
+            const uint2 cc = rs.c(i);
+            const int32_t c1 = (int32_t)cc.x, c2 = (int32_t)cc.y;
+            const bool upto1 = k <= s1, first = k == s1, second = k == s2x;
+            ad += upto1 ? 1ull : (1ull << 32);
+            const int32_t v = k < s1 ? c1 - dist : (first ? c1 : (second ? c2 - c1 : c2 - dist));
+            const unsigned long long uv = (unsigned long long)v;
+            sb += upto1 ? uv : 0ull;
+            se += !upto1 && second ? uv : 0ull;
+            scc += !upto1 && !second ? uv : 0ull;
+            scc += first ? (unsigned long long)(c2 - c1) : 0ull;
+        }
+    }
+    // the row's totals into slot `slot` (lane 15 of the row adds them; rows
+    // walking listed clients add to the same bins)
+    __device__ __forceinline__ void flush(SlotBins &B, int slot, int sub)
+    {
+        const unsigned long long a = row_sum64(ad), b = row_sum64(sb), c = row_sum64(scc),
+                                 e = row_sum64(se);
+        if (sub == 15) {
+            atomicAdd(&B.a[slot], (uint32_t)a);
+            atomicAdd(&B.dd[slot], (uint32_t)(a >> 32));
+            atomicAdd(&B.b[slot], b);
+            atomicAdd(&B.cc[slot], c);
+            atomicAdd(&B.e[slot], e);
+        }
+    }
+};
+
+// Pass 2, a workgroup per chromosome (eight waves per SIMD: four workgroups
+// per CU, so that a population of 1024 is resident at once).  Its clients' (s1, s2, c1, c2) are
 // staged in LDS (n <= kStageClients) with one coalesced sweep that also lists
 // the clients whose walk reaches past the index.  Then each 16-lane row takes
 // tasks: a candidate slot (its facility's index entries, 16 at a time, four
@@ -922,7 +977,8 @@ __device__ __forceinline__ void walk_far(const Tables &t, SlotBins &B, const uin
 // from kNearL on).  Clients past the list's capacity are walked by the wave
 // that finds them.
 template <bool Stage>
-__global__ __launch_bounds__(64 * kSlotWaves) void k_prop_slots(LearnArgs A)
+__global__ __launch_bounds__(64 * kSlotWaves) __attribute__((amdgpu_waves_per_eu(8)))
+void k_prop_slots(LearnArgs A)
 {
     extern __shared__ __align__(16) uint32_t dyn[];  // staged: (c1, c2) x n, then s12 x n
     __shared__ SlotBins B;
@@ -970,7 +1026,7 @@ __global__ __launch_bounds__(64 * kSlotWaves) void k_prop_slots(LearnArgs A)
         scnt[threadIdx.x] = A.near_off[f + 1] - e0;
     }
     // the sweep: U clients per thread in flight
-    constexpr int U = 8;
+    constexpr int U = 4;
     constexpr int NT = 64 * kSlotWaves;
     for (int x0 = 0; x0 < n; x0 += U * NT) {
         uint32_t sv[U];
@@ -1023,56 +1079,45 @@ __global__ __launch_bounds__(64 * kSlotWaves) void k_prop_slots(LearnArgs A)
     __syncthreads();
     const int nf = min(nfar, kFarCap);
     const int row = (int)threadIdx.x >> 4, sub = lane & 15;
-    for (int task = row; task < ns + nf; task += kSlotRows) {  // (uniform in the row)
-        if (task < ns) {
-            const uint2 *ent = A.near_q + soff[task];
-            const int cnt = scnt[task];
-            unsigned long long ad = 0, sb = 0, scc = 0, se = 0;  // ad: a | dd << 32
-            for (int q0 = 0; q0 < cnt; q0 += 64) {
-                uint2 en[4];
+    // slot tasks two at a time per row: both slots' first 64 entries are
+    // loaded in one round (further entries, rare, one chunk at a time)
+    for (int t0 = row; t0 < ns; t0 += 2 * kSlotRows) {  // (uniform in the row)
+        const int t1 = t0 + kSlotRows;
+        const bool two = t1 < ns;
+        const uint2 *ent[2] = {A.near_q + soff[t0], A.near_q + soff[two ? t1 : t0]};
+        const int cnt[2] = {scnt[t0], two ? scnt[t1] : 0};
+        uint2 en[2][4];
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int q = 16 * u + sub;
+                en[v][u] = q < cnt[v] ? ent[v][q] : uint2{0xFFFFFFFFu, 0u};
+            }
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            SlotAcc acc;
+            for (int q0 = 0;;) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    acc.add(en[v][u], rs);
+                q0 += 64;
+                if (q0 >= cnt[v])
+                    break;
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const int q = q0 + 16 * u + sub;
-                    en[u] = q < cnt ? ent[q] : uint2{0xFFFFFFFFu, 0u};
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    if (en[u].x == 0xFFFFFFFFu)
-                        continue;
-                    const int i = (int)(en[u].x >> 6), k = (int)(en[u].x & 63u);
-                    const int32_t dist = (int32_t)en[u].y;
-                    const uint32_t sv = rs.s(i);
-                    const int s1 = (int)(sv & 0xFFFFu), s2x = (int)(sv >> 16);
-                    if (k <= s2x) {  // (s2x = 0xFFFF, no second: every k < nearL)
-                        const uint2 cc = rs.c(i);
-                        const int32_t c1 = (int32_t)cc.x, c2 = (int32_t)cc.y;
-                        const bool upto1 = k <= s1, first = k == s1, second = k == s2x;
-                        ad += upto1 ? 1ull : (1ull << 32);
-                        const int32_t v =
-                            k < s1 ? c1 - dist : (first ? c1 : (second ? c2 - c1 : c2 - dist));
-                        const unsigned long long uv = (unsigned long long)v;
-                        sb += upto1 ? uv : 0ull;
-                        se += !upto1 && second ? uv : 0ull;
-                        scc += !upto1 && !second ? uv : 0ull;
-                        scc += first ? (unsigned long long)(c2 - c1) : 0ull;
-                    }
+                    en[v][u] = q < cnt[v] ? ent[v][q] : uint2{0xFFFFFFFFu, 0u};
                 }
             }
-            ad = row_sum64(ad);
-            sb = row_sum64(sb);
-            scc = row_sum64(scc);
-            se = row_sum64(se);
-            if (sub == 15) {  // (rows that list far clients add to the same bins)
-                atomicAdd(&B.a[task], (uint32_t)ad);
-                atomicAdd(&B.dd[task], (uint32_t)(ad >> 32));
-                atomicAdd(&B.b[task], sb);
-                atomicAdd(&B.cc[task], scc);
-                atomicAdd(&B.e[task], se);
-            }
-        } else {
-            const int ii = farl[task - ns];
-            walk_far(t, B, cb, cp, ii, rs.s(ii), rs.c(ii), nearL, sub, 16);
+            if (v == 0 || two)
+                acc.flush(B, v == 0 ? t0 : t1, sub);
         }
+    }
+    // listed clients whose walk reaches past the index
+    for (int f = row; f < nf; f += kSlotRows) {
+        const int ii = farl[f];
+        walk_far(t, B, cb, cp, ii, rs.s(ii), rs.c(ii), nearL, sub, 16);
     }
     __syncthreads();
     for (int sl = threadIdx.x; sl < kSlots; sl += blockDim.x) {
