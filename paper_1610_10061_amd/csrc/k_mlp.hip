@@ -14,6 +14,7 @@ namespace {
 
 constexpr int kWaves = 4;
 constexpr int kChunk = 16 * kWaves;   // rows per workgroup step
+static_assert(kWaves == 4, "training splits the hidden layer into four tile pairs");
 constexpr int kTStride = kChunk + 4;  // padded LDS row of a transposed tile
 
 // Copy 16 input rows (row0..row0+15, zero past `rows`) into LDS x.
@@ -59,7 +60,8 @@ struct GradLds {
     uint16_t ht[kHidden * kTStride];     // h1 transposed
     uint16_t z2t[kHidden * kTStride];    // dz2 transposed
     uint16_t z1t[kHidden * kTStride];    // dz1 transposed
-    float vec[kWaves][3 * kHidden + 4];  // per-wave vector partials
+    float ys[kChunk * 4];                // per row, the tile pairs' output sums
+    float dy[kChunk];                    // per row, weight x output error
     int train;
 };
 
@@ -95,11 +97,13 @@ __global__ __launch_bounds__(64 * kWaves) void k_mlp_grad(MlpDev P, const uint16
 #pragma unroll
     for (int k = 0; k < 4; ++k)
         acc1[k] = f32x4{0.f, 0.f, 0.f, 0.f};
-    float db1[8], db2[8], dw3[8];
+    // this wave's hidden tiles 2 wave and 2 wave + 1: bias and output-weight
+    // gradients (per lane: unit r of each tile, over its rows)
+    float db1[2], db2[2], dw3[2];
 #pragma unroll
-    for (int t = 0; t < 8; ++t)
-        db1[t] = db2[t] = dw3[t] = 0.f;
-    float db3 = 0.f, lsum = 0.f, wsum = 0.f;
+    for (int j = 0; j < 2; ++j)
+        db1[j] = db2[j] = dw3[j] = 0.f;
+    float db3 = 0.f, lsum = 0.f, wsum = 0.f;  // (threads of the chunk's rows)
 
     const int nchunks = (rows + kChunk - 1) / kChunk;
     for (int ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
@@ -121,78 +125,155 @@ __global__ __launch_bounds__(64 * kWaves) void k_mlp_grad(MlpDev P, const uint16
         }
         __syncthreads();
 
-        const int wr = wave * 16;  // this wave's first row in the chunk
-        f32x4 z1[8], z2[8];
-        float y[4];
-        mlp_forward16(P, L.xr + wr * kXStride, L.hr + wr * kHStride, lane, z1, z2, y);
-        // h1 transposed (the D layout holds four consecutive rows per lane)
+        // Forward and backward by hidden tile pairs: wave qp computes hidden
+        // tiles 2 qp and 2 qp + 1 of every product for all 64 rows of the chunk
+        // (a quarter of the weights per wave, each fragment used for four
+        // row tiles), with the same operations per element as mlp_forward16.
+        const int qp = wave;
+        f32x4 z1[4][2], z2[4][2];
+        {
+            bf16x8 bw[2];
+            float bias[2];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            const uint32_t lo = f32_to_bf16(fmaxf(z1[t][0], 0.f)) |
-                                ((uint32_t)f32_to_bf16(fmaxf(z1[t][1], 0.f)) << 16);
-            const uint32_t hi = f32_to_bf16(fmaxf(z1[t][2], 0.f)) |
-                                ((uint32_t)f32_to_bf16(fmaxf(z1[t][3], 0.f)) << 16);
-            *reinterpret_cast<uint2 *>(L.ht + (t * 16 + r) * kTStride + wr + 4 * g) =
-                uint2{lo, hi};
+            for (int j = 0; j < 2; ++j) {
+                const int t = 2 * qp + j;
+                bw[j] = load_bf16x8(P.W1 + (t * 16 + r) * kIn + 8 * g);
+                bias[j] = P.b1[t * 16 + r];
+            }
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                const bf16x8 ax = load_bf16x8(L.xr + (mt * 16 + r) * kXStride + 8 * g);
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int t = 2 * qp + j;
+                    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+                    acc = mfma_bf16(ax, bw[j], acc);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        acc[i] += bias[j];
+                    z1[mt][j] = acc;
+                    uint16_t h[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        h[i] = f32_to_bf16(fmaxf(acc[i], 0.f));
+                        L.hr[(mt * 16 + 4 * g + i) * kHStride + t * 16 + r] = h[i];
+                    }
+                    // h1 transposed (the D layout holds four consecutive rows)
+                    *reinterpret_cast<uint2 *>(L.ht + (t * 16 + r) * kTStride + mt * 16 + 4 * g) =
+                        uint2{h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16)};
+                }
+            }
         }
-        // output error and row weights
-        float dy[4];
+        __syncthreads();
+        float w3[2];
+        {
+            bf16x8 bw[2][kHidden / 32];
+            float bias[2];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int64_t row = row0 + wr + 4 * g + i;
+            for (int j = 0; j < 2; ++j) {
+                const int t = 2 * qp + j;
+#pragma unroll
+                for (int kb = 0; kb < kHidden / 32; ++kb)
+                    bw[j][kb] = load_bf16x8(P.W2 + (t * 16 + r) * kHidden + kb * 32 + 8 * g);
+                bias[j] = P.b2[t * 16 + r];
+                w3[j] = bf16_to_f32(P.w3[t * 16 + r]);
+            }
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                bf16x8 ah[kHidden / 32];
+#pragma unroll
+                for (int kb = 0; kb < kHidden / 32; ++kb)
+                    ah[kb] = load_bf16x8(L.hr + (mt * 16 + r) * kHStride + kb * 32 + 8 * g);
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int kb = 0; kb < kHidden / 32; ++kb)
+                        acc = mfma_bf16(ah[kb], bw[j][kb], acc);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        acc[i] += bias[j];
+                    z2[mt][j] = acc;
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float v = out_pair(z2[mt][0][i], z2[mt][1][i], w3[0], w3[1]);
+                    if (r == 0)
+                        L.ys[(mt * 16 + 4 * g + i) * 4 + qp] = v;
+                }
+            }
+        }
+        __syncthreads();
+        // output error and row weight of row `threadIdx.x`
+        if (threadIdx.x < kChunk) {
+            const int64_t row = row0 + threadIdx.x;
             float e = 0.f, w = 0.f;
             if (row < rows) {
                 w = Wt ? Wt[row] : 1.f;
-                e = y[i] - T[row];
+                e = out_sum(L.ys + threadIdx.x * 4, P.b3[0]) - T[row];
             }
-            dy[i] = w * e;
-            if (r == 0) {
-                lsum += w * e * e;
-                wsum += w;
-                db3 += w * e;
-            }
+            L.dy[threadIdx.x] = w * e;
+            lsum += w * e * e;
+            wsum += w;
+            db3 += w * e;
         }
-        // dz2 = dy w3 relu'(z2); dw3 += dy h2; db2 += dz2
+        __syncthreads();
+        // dz2 = dy w3 relu'(z2); dw3 += dy h2; db2 += dz2 (dz2 row-major over
+        // h1, whose last reader passed the barrier above, and transposed)
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            const float w = bf16_to_f32(P.w3[t * 16 + r]);
-            uint16_t h[4];
+        for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float z = z2[t][i];
-                dw3[t] += dy[i] * fmaxf(z, 0.f);
-                const float dz = z > 0.f ? dy[i] * w : 0.f;
-                db2[t] += dz;
-                h[i] = f32_to_bf16(dz);
-                L.hr[(wr + 4 * g + i) * kHStride + t * 16 + r] = h[i];
-            }
-            *reinterpret_cast<uint2 *>(L.z2t + (t * 16 + r) * kTStride + wr + 4 * g) =
-                uint2{h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16)};
-        }
-        wave_lds_sync();
-        // dz1 = (dz2 W2) relu'(z1); db1 += dz1
-        {
-            bf16x8 a[kHidden / 32];
-#pragma unroll
-            for (int kb = 0; kb < kHidden / 32; ++kb)
-                a[kb] = load_bf16x8(L.hr + (wr + r) * kHStride + kb * 32 + 8 * g);
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int kb = 0; kb < kHidden / 32; ++kb)
-                    acc = mfma_bf16(a[kb],
-                                    load_bf16x8(P.W2T + (t * 16 + r) * kHidden + kb * 32 + 8 * g),
-                                    acc);
+            for (int j = 0; j < 2; ++j) {
+                const int t = 2 * qp + j;
                 uint16_t h[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const float dz = z1[t][i] > 0.f ? acc[i] : 0.f;
-                    db1[t] += dz;
+                    const int rw = mt * 16 + 4 * g + i;
+                    const float dyv = L.dy[rw];
+                    const float z = z2[mt][j][i];
+                    dw3[j] += dyv * fmaxf(z, 0.f);
+                    const float dz = z > 0.f ? dyv * w3[j] : 0.f;
+                    db2[j] += dz;
                     h[i] = f32_to_bf16(dz);
+                    L.hr[rw * kHStride + t * 16 + r] = h[i];
                 }
-                *reinterpret_cast<uint2 *>(L.z1t + (t * 16 + r) * kTStride + wr + 4 * g) =
+                *reinterpret_cast<uint2 *>(L.z2t + (t * 16 + r) * kTStride + mt * 16 + 4 * g) =
                     uint2{h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16)};
+            }
+        __syncthreads();
+        // dz1 = (dz2 W2) relu'(z1); db1 += dz1
+        {
+            bf16x8 bw[2][kHidden / 32];
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int kb = 0; kb < kHidden / 32; ++kb)
+                    bw[j][kb] =
+                        load_bf16x8(P.W2T + ((2 * qp + j) * 16 + r) * kHidden + kb * 32 + 8 * g);
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                bf16x8 a[kHidden / 32];
+#pragma unroll
+                for (int kb = 0; kb < kHidden / 32; ++kb)
+                    a[kb] = load_bf16x8(L.hr + (mt * 16 + r) * kHStride + kb * 32 + 8 * g);
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int t = 2 * qp + j;
+                    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int kb = 0; kb < kHidden / 32; ++kb)
+                        acc = mfma_bf16(a[kb], bw[j][kb], acc);
+                    uint16_t h[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const float dz = z1[mt][j][i] > 0.f ? acc[i] : 0.f;
+                        db1[j] += dz;
+                        h[i] = f32_to_bf16(dz);
+                    }
+                    *reinterpret_cast<uint2 *>(L.z1t + (t * 16 + r) * kTStride + mt * 16 +
+                                               4 * g) =
+                        uint2{h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16)};
+                }
             }
         }
         __syncthreads();
@@ -240,10 +321,10 @@ __global__ __launch_bounds__(64 * kWaves) void k_mlp_grad(MlpDev P, const uint16
             for (int i = 0; i < 4; ++i)
                 part[kOffW1 + (n0 + i) * kIn + kt * 16 + r] = acc1[q * 2 + kt][i];
     }
-    // vectors: sum the four row groups of the wave, then the waves in order
+    // vectors: the wave's own tiles, summed over the four row groups
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        float a = db1[t], b = db2[t], c = dw3[t];
+    for (int j = 0; j < 2; ++j) {
+        float a = db1[j], b = db2[j], c = dw3[j];
         a += __shfl_xor(a, 16);
         a += __shfl_xor(a, 32);
         b += __shfl_xor(b, 16);
@@ -251,39 +332,25 @@ __global__ __launch_bounds__(64 * kWaves) void k_mlp_grad(MlpDev P, const uint16
         c += __shfl_xor(c, 16);
         c += __shfl_xor(c, 32);
         if (g == 0) {
-            L.vec[wave][t * 16 + r] = a;
-            L.vec[wave][kHidden + t * 16 + r] = b;
-            L.vec[wave][2 * kHidden + t * 16 + r] = c;
+            const int u = (2 * wave + j) * 16 + r;
+            part[kOffB1 + u] = a;
+            part[kOffB2 + u] = b;
+            part[kOffW3 + u] = c;
         }
     }
-    db3 += __shfl_xor(db3, 16);
-    db3 += __shfl_xor(db3, 32);
-    lsum += __shfl_xor(lsum, 16);
-    lsum += __shfl_xor(lsum, 32);
-    wsum += __shfl_xor(wsum, 16);
-    wsum += __shfl_xor(wsum, 32);
-    if (lane == 0) {
-        L.vec[wave][3 * kHidden] = db3;
-        L.vec[wave][3 * kHidden + 1] = lsum;
-        L.vec[wave][3 * kHidden + 2] = wsum;
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k < 3 * kHidden + 3; k += blockDim.x) {
-        float v = 0.f;
-        for (int w = 0; w < kWaves; ++w)
-            v += L.vec[w][k];
-        if (k < kHidden)
-            part[kOffB1 + k] = v;
-        else if (k < 2 * kHidden)
-            part[kOffB2 + k - kHidden] = v;
-        else if (k < 3 * kHidden)
-            part[kOffW3 + k - 2 * kHidden] = v;
-        else if (k == 3 * kHidden)
-            part[kOffB3] = v;
-        else if (k == 3 * kHidden + 1)
-            part[kParams + 1] = v;
-        else
-            part[kParams] = v;
+    // the output bias, loss and row-weight sums over the rows (wave 0)
+    if (wave == 0) {
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            db3 += __shfl_xor(db3, o);
+            lsum += __shfl_xor(lsum, o);
+            wsum += __shfl_xor(wsum, o);
+        }
+        if (lane == 0) {
+            part[kOffB3] = db3;
+            part[kParams + 1] = lsum;
+            part[kParams] = wsum;
+        }
     }
     if (threadIdx.x == 0)
         part[kParams + 2] = __uint_as_float(*step + 1u);
