@@ -448,84 +448,6 @@ struct ScoreLds {
     float ys[PMP_MAX_CANDIDATES * 4];  // per row, the four tile pairs' output sums
 };
 
-// The network on the workgroup's 64 input rows x (LDS), by hidden tile
-// pairs: wave q computes hidden tiles 2q and 2q + 1 of both layers for all 64
-// rows, so each wave loads a quarter of the weights once and uses each
-// weight fragment for four row tiles (the layers' weights are read once per
-// workgroup, not once per wave).  h1: the first layer's BF16 activations of
-// all rows (LDS); ys: per row the output sums of the four tile pairs, which
-// out_sum adds.  The same operations as mlp_forward16, so the same bits.
-// Block-wide (kMlpWaves = 4 waves; one barrier inside).
-static_assert(kMlpWaves == 4 && kIn == 32, "tile pairs of the scoring network");
-__device__ __forceinline__ void mlp_score64(const MlpDev &P, const uint16_t *x, uint16_t *h1,
-                                            float *ys, int q, int lane)
-{
-    const int r = lane & 15, g = lane >> 4;
-    {
-        bf16x8 bw[2];
-        float bias[2];
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int t = 2 * q + j;
-            bw[j] = load_bf16x8(P.W1 + (t * 16 + r) * kIn + 8 * g);
-            bias[j] = P.b1[t * 16 + r];
-        }
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
-            const bf16x8 ax = load_bf16x8(x + (mt * 16 + r) * kXStride + 8 * g);
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-                acc = mfma_bf16(ax, bw[j], acc);
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    acc[i] += bias[j];
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    h1[(mt * 16 + 4 * g + i) * kHStride + (2 * q + j) * 16 + r] =
-                        f32_to_bf16(fmaxf(acc[i], 0.f));
-            }
-        }
-    }
-    __syncthreads();
-    bf16x8 bw[2][kHidden / 32];
-    float bias[2], w3[2];
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const int t = 2 * q + j;
-#pragma unroll
-        for (int kb = 0; kb < kHidden / 32; ++kb)
-            bw[j][kb] = load_bf16x8(P.W2 + (t * 16 + r) * kHidden + kb * 32 + 8 * g);
-        bias[j] = P.b2[t * 16 + r];
-        w3[j] = bf16_to_f32(P.w3[t * 16 + r]);
-    }
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-        bf16x8 ah[kHidden / 32];
-#pragma unroll
-        for (int kb = 0; kb < kHidden / 32; ++kb)
-            ah[kb] = load_bf16x8(h1 + (mt * 16 + r) * kHStride + kb * 32 + 8 * g);
-        f32x4 z[2];
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int kb = 0; kb < kHidden / 32; ++kb)
-                acc = mfma_bf16(ah[kb], bw[j][kb], acc);
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                acc[i] += bias[j];
-            z[j] = acc;
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const float v = out_pair(z[0][i], z[1][i], w3[0], w3[1]);
-            if (r == 0)
-                ys[(mt * 16 + 4 * g + i) * 4 + q] = v;
-        }
-    }
-}
-
 __global__ __launch_bounds__(64 * kMlpWaves) void k_prop_score(LearnArgs A, int out)
 {
     __shared__ ScoreLds L;
@@ -578,7 +500,7 @@ __global__ __launch_bounds__(64 * kMlpWaves) void k_prop_score(LearnArgs A, int 
         d[1] = uint2{v8[4] | ((uint32_t)v8[5] << 16), v8[6] | ((uint32_t)v8[7] << 16)};
     }
     __syncthreads();
-    mlp_score64(A.net, L.x, L.h, L.ys, wave, lane);
+    mlp_forward64(A.net, L.x, L.h, L.ys, wave, lane);
     __syncthreads();
     if (threadIdx.x < PMP_MAX_CANDIDATES)
         L.score[threadIdx.x] = out_sum(L.ys + threadIdx.x * 4, A.net.b3[0]);

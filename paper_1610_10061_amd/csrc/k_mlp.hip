@@ -30,27 +30,23 @@ __device__ __forceinline__ void stage_rows16(const uint16_t *X, int64_t row0, in
     d[1] = uint2{v.z, v.w};
 }
 
+// Forward of 64 rows per workgroup, split by hidden tile pairs over the
+// four waves (mlp_forward64).
 __global__ __launch_bounds__(64 * kWaves) void k_mlp_forward(MlpDev P, const uint16_t *X,
                                                             int rows, float *y)
 {
-    __shared__ __align__(16) uint16_t xs[kWaves][16 * kXStride];
-    __shared__ __align__(16) uint16_t hs[kWaves][16 * kHStride];
+    __shared__ __align__(16) uint16_t xs[kChunk * kXStride];
+    __shared__ __align__(16) uint16_t hs[kChunk * kHStride];
+    __shared__ float ys[kChunk * 4];
     const int wave = wave_id(), lane = threadIdx.x & 63;
-    const int64_t row0 = ((int64_t)blockIdx.x * kWaves + wave) * 16;
-    if (row0 >= rows)
-        return;
-    stage_rows16(X, row0, rows, xs[wave], lane);
-    wave_lds_sync();
-    f32x4 z1[8], z2[8];
-    float out[4];
-    mlp_forward16(P, xs[wave], hs[wave], lane, z1, z2, out);
-    if ((lane & 15) == 0)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int64_t row = row0 + 4 * (lane >> 4) + i;
-            if (row < rows)
-                y[row] = out[i];
-        }
+    const int64_t row0 = (int64_t)blockIdx.x * kChunk;
+    stage_rows16(X, row0 + wave * 16, rows, xs + wave * 16 * kXStride, lane);
+    __syncthreads();
+    mlp_forward64(P, xs, hs, ys, wave, lane);
+    __syncthreads();
+    const int64_t row = row0 + threadIdx.x;
+    if (threadIdx.x < kChunk && row < rows)
+        y[row] = out_sum(ys + threadIdx.x * 4, P.b3[0]);
 }
 
 struct GradLds {
@@ -128,7 +124,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_mlp_grad(MlpDev P, const uint16
         // Forward and backward by hidden tile pairs: wave qp computes hidden
         // tiles 2 qp and 2 qp + 1 of every product for all 64 rows of the chunk
         // (a quarter of the weights per wave, each fragment used for four
-        // row tiles), with the same operations per element as mlp_forward16.
+        // row tiles), with the same operations per element as mlp_forward64.
         const int qp = wave;
         f32x4 z1[4][2], z2[4][2];
         {

@@ -126,76 +126,90 @@ __device__ __forceinline__ float out_pair(float z_a, float z_b, float w_a, float
     return v;
 }
 
-// The output from the four tile pairs' sums; every kernel adds them in this
-// order, so that a row's output is the same bits whichever kernel computes
-// it (one wave over all tiles, or a wave per tile pair).
+// The output from the four tile pairs' sums, added in this order by every
+// kernel.
 __device__ __forceinline__ float out_sum(const float s[4], float b3)
 {
     return ((s[0] + s[1]) + (s[2] + s[3])) + b3;
 }
 
-// Forward pass of 16 rows by one wave.  x: the rows' inputs in LDS (row r at
-// x + r * kXStride); h1: 16 x kHStride BF16 of LDS scratch.  Leaves the
-// pre-activations z1 = W1 x + b1 and z2 = W2 h1 + b2 in D layout (tile t =
-// hidden units 16t..16t+15) and y for rows 4g..4g+3 in y[0..3] (all lanes of
-// the group of 16 hold them).
-__device__ __forceinline__ void mlp_forward16(const MlpDev &P, const uint16_t *x,
-                                              uint16_t *h1, int lane, f32x4 z1[8],
-                                              f32x4 z2[8], float y[4])
+// The network on the workgroup's 64 input rows x (LDS), by hidden tile
+// pairs: wave q computes hidden tiles 2q and 2q + 1 of both layers for all 64
+// rows, so each wave loads a quarter of the weights once and uses each
+// weight fragment for four row tiles (the layers' weights are read once per
+// workgroup, not once per wave).  h1: the first layer's BF16 activations of
+// all rows (LDS); ys: per row the output sums of the four tile pairs, which
+// out_sum adds.  The training kernel computes its forward with the same
+// operations, so a row's output is the same bits in every kernel.
+// Block-wide (four waves, q = the wave's number; one barrier inside).
+static_assert(kIn == 32 && kHidden == 128, "four tile pairs, one K-step in layer 1");
+__device__ __forceinline__ void mlp_forward64(const MlpDev &P, const uint16_t *x, uint16_t *h1,
+                                            float *ys, int q, int lane)
 {
     const int r = lane & 15, g = lane >> 4;
-    bf16x8 ax[kIn / 32];
+    {
+        bf16x8 bw[2];
+        float bias[2];
 #pragma unroll
-    for (int kb = 0; kb < kIn / 32; ++kb)
-        ax[kb] = load_bf16x8(x + r * kXStride + kb * 32 + 8 * g);
+        for (int j = 0; j < 2; ++j) {
+            const int t = 2 * q + j;
+            bw[j] = load_bf16x8(P.W1 + (t * 16 + r) * kIn + 8 * g);
+            bias[j] = P.b1[t * 16 + r];
+        }
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        for (int mt = 0; mt < 4; ++mt) {
+            const bf16x8 ax = load_bf16x8(x + (mt * 16 + r) * kXStride + 8 * g);
 #pragma unroll
-        for (int kb = 0; kb < kIn / 32; ++kb)
-            acc = mfma_bf16(ax[kb], load_bf16x8(P.W1 + (t * 16 + r) * kIn + kb * 32 + 8 * g),
-                            acc);
-        const float bias = P.b1[t * 16 + r];
+            for (int j = 0; j < 2; ++j) {
+                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+                acc = mfma_bf16(ax, bw[j], acc);
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            acc[i] += bias;
-        z1[t] = acc;
+                for (int i = 0; i < 4; ++i)
+                    acc[i] += bias[j];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    h1[(mt * 16 + 4 * g + i) * kHStride + (2 * q + j) * 16 + r] =
+                        f32_to_bf16(fmaxf(acc[i], 0.f));
+            }
+        }
     }
+    __syncthreads();
+    bf16x8 bw[2][kHidden / 32];
+    float bias[2], w3[2];
 #pragma unroll
-    for (int t = 0; t < 8; ++t)
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            h1[(4 * g + i) * kHStride + t * 16 + r] = f32_to_bf16(fmaxf(z1[t][i], 0.f));
-    wave_lds_sync();
-    bf16x8 ah[kHidden / 32];
-#pragma unroll
-    for (int kb = 0; kb < kHidden / 32; ++kb)
-        ah[kb] = load_bf16x8(h1 + r * kHStride + kb * 32 + 8 * g);
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < 2; ++j) {
+        const int t = 2 * q + j;
 #pragma unroll
         for (int kb = 0; kb < kHidden / 32; ++kb)
-            acc = mfma_bf16(ah[kb],
-                            load_bf16x8(P.W2 + (t * 16 + r) * kHidden + kb * 32 + 8 * g),
-                            acc);
-        const float bias = P.b2[t * 16 + r];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            acc[i] += bias;
-        z2[t] = acc;
+            bw[j][kb] = load_bf16x8(P.W2 + (t * 16 + r) * kHidden + kb * 32 + 8 * g);
+        bias[j] = P.b2[t * 16 + r];
+        w3[j] = bf16_to_f32(P.w3[t * 16 + r]);
     }
-    const float b3 = P.b3[0];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        float s[4];
+    for (int mt = 0; mt < 4; ++mt) {
+        bf16x8 ah[kHidden / 32];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-            s[q] = out_pair(z2[2 * q][i], z2[2 * q + 1][i], bf16_to_f32(P.w3[2 * q * 16 + r]),
-                            bf16_to_f32(P.w3[(2 * q + 1) * 16 + r]));
-        y[i] = out_sum(s, b3);
+        for (int kb = 0; kb < kHidden / 32; ++kb)
+            ah[kb] = load_bf16x8(h1 + (mt * 16 + r) * kHStride + kb * 32 + 8 * g);
+        f32x4 z[2];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kb = 0; kb < kHidden / 32; ++kb)
+                acc = mfma_bf16(ah[kb], bw[j][kb], acc);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                acc[i] += bias[j];
+            z[j] = acc;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float v = out_pair(z[0][i], z[1][i], w3[0], w3[1]);
+            if (r == 0)
+                ys[(mt * 16 + 4 * g + i) * 4 + q] = v;
+        }
     }
-    wave_lds_sync();  // h1 may be reused by the caller
 }
 
 // Launchers (k_mlp.hip).
