@@ -446,6 +446,9 @@ struct ScoreLds {
     __align__(16) uint16_t x[PMP_MAX_CANDIDATES * kXStride];
     __align__(16) uint16_t h[PMP_MAX_CANDIDATES * kHStride];
     float ys[PMP_MAX_CANDIDATES * 4];  // per row, the four tile pairs' output sums
+    int32_t prank[kMlpWaves][PMP_MAX_CANDIDATES];  // partial ranks by quarter
+    int32_t pe[PMP_MAX_CANDIDATES], pu[PMP_MAX_CANDIDATES];  // exploration draws
+    int32_t swap0[2];                                     // attempt 0's (j, k)
 };
 
 __global__ __launch_bounds__(64 * kMlpWaves) void k_prop_score(LearnArgs A, int out)
@@ -505,31 +508,49 @@ __global__ __launch_bounds__(64 * kMlpWaves) void k_prop_score(LearnArgs A, int 
     if (threadIdx.x < PMP_MAX_CANDIDATES)
         L.score[threadIdx.x] = out_sum(L.ys + threadIdx.x * 4, A.net.b3[0]);
     __syncthreads();
-    // rank (wave 0): rank of t = #{u : (y_u, u) < (y_t, t)}, NaN as +inf
-    if (wave == 0) {
+    static_assert(kMlpWaves * 16 == PMP_MAX_CANDIDATES, "a quarter of the candidates per wave");
+    // rank of t = #{u : (y_u, u) < (y_t, t)}, NaN as +inf: wave v counts
+    // the u of the quarter 16 v .. 16 v + 15 for every t; wave 1 also makes
+    // the attempts' exploration draws
+    {
         float y = lane < C ? L.score[lane] : __builtin_inff();
-        if (lane < C)
-            A.scores[(int64_t)c * C + lane] = y;
         if (y != y)
             y = __builtin_inff();
-        int rank = 0;
-        for (int u = 0; u < 64; ++u) {
-            const float yu = __shfl(y, u);
-            rank += (yu < y || (yu == y && u < lane)) ? 1 : 0;
+        int cnt = 0;
+#pragma unroll
+        for (int uu = 0; uu < 16; ++uu) {
+            const int u = wave * 16 + uu;
+            float yu = u < C ? L.score[u] : __builtin_inff();
+            if (yu != yu)
+                yu = __builtin_inff();
+            cnt += (yu < y || (yu == y && u < lane)) ? 1 : 0;
         }
+        L.prank[wave][lane] = cnt;
+        if (wave == 1 && lane < A.L) {
+            PhiloxStream st(g.seed, ROLE_EVOLVE, gen, (uint64_t)c, TAG_EXPLORE, (uint64_t)lane);
+            L.pe[lane] = (int)st.below(1000);
+            L.pu[lane] = (int)st.below((uint64_t)C);
+        }
+    }
+    __syncthreads();
+    if (wave == 0) {
+        if (lane < C)
+            A.scores[(int64_t)c * C + lane] = L.score[lane];
+        const int rank = L.prank[0][lane] + L.prank[1][lane] + L.prank[2][lane] + L.prank[3][lane];
         if (lane < C)
             L.order[rank] = lane;
         wave_lds_sync();
         // the attempts' picks, swaps and ring rows
         if (lane < A.L) {
-            PhiloxStream st(g.seed, ROLE_EVOLVE, gen, (uint64_t)c, TAG_EXPLORE, (uint64_t)lane);
-            const int e = (int)st.below(1000);
-            const int u = (int)st.below((uint64_t)C);
-            const int pick = e < A.explore ? u : L.order[lane];
+            const int pick = L.pe[lane] < A.explore ? L.pu[lane] : L.order[lane];
             const int j = L.cj[pick], k = L.ck[pick];
             int32_t *sw = A.swaps + ((int64_t)c * A.L + lane) * 2;
             sw[0] = j;
             sw[1] = k;
+            if (lane == 0) {
+                L.swap0[0] = j;
+                L.swap0[1] = k;
+            }
             const int64_t slot = ((int64_t)(gen % (uint64_t)A.H) * A.L + lane) * g.P + c;
             const uint2 *src = reinterpret_cast<const uint2 *>(L.x + pick * kXStride);
             uint2 *dst = reinterpret_cast<uint2 *>(A.rep_x + slot * kIn);
@@ -546,8 +567,7 @@ __global__ __launch_bounds__(64 * kMlpWaves) void k_prop_score(LearnArgs A, int 
     }
     __syncthreads();
     // attempt 0's offspring
-    const int32_t *sw0 = A.swaps + (int64_t)c * A.L * 2;
-    const int j0 = sw0[0], k0 = sw0[1];
+    const int j0 = L.swap0[0], k0 = L.swap0[1];
     const uint64_t *mask = buf(g.cur, out) + (int64_t)c * W;
     uint64_t *F = buf(g.off, out) + (int64_t)c * W;
     for (int w = threadIdx.x; w < W; w += blockDim.x) {
