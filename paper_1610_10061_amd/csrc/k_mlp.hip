@@ -71,7 +71,9 @@ __global__ __launch_bounds__(64 * kWaves) void k_mlp_grad(MlpDev P, const uint16
     __shared__ __align__(16) GradLds L;
     const int wave = wave_id(), lane = threadIdx.x & 63;
     const int r = lane & 15, g = lane >> 4;
-    float *part = partials + (int64_t)blockIdx.x * kPartStride;
+    // value k of this workgroup's partial vector
+    const int blk = (int)blockIdx.x;
+    auto part = [partials, blk](int k) -> float & { return partials[part_index(blk, k)]; };
     if (threadIdx.x == 0) {
         int train = 1;
         if (gate.gen) {
@@ -80,7 +82,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_mlp_grad(MlpDev P, const uint16
         }
         L.train = train;
         if (!train)
-            part[kParams] = 0.f;  // no rows: the update kernel skips
+            part(kParams) = 0.f;  // no rows: the update kernel skips
     }
     __syncthreads();
     if (!L.train)
@@ -310,12 +312,12 @@ __global__ __launch_bounds__(64 * kWaves) void k_mlp_grad(MlpDev P, const uint16
         for (int kt = 0; kt < 8; ++kt)
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                part[kOffW2 + (n0 + i) * kHidden + kt * 16 + r] = acc2[q * 8 + kt][i];
+                part(kOffW2 + (n0 + i) * kHidden + kt * 16 + r) = acc2[q * 8 + kt][i];
 #pragma unroll
         for (int kt = 0; kt < 2; ++kt)
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                part[kOffW1 + (n0 + i) * kIn + kt * 16 + r] = acc1[q * 2 + kt][i];
+                part(kOffW1 + (n0 + i) * kIn + kt * 16 + r) = acc1[q * 2 + kt][i];
     }
     // vectors: the wave's own tiles, summed over the four row groups
 #pragma unroll
@@ -329,9 +331,9 @@ __global__ __launch_bounds__(64 * kWaves) void k_mlp_grad(MlpDev P, const uint16
         c += __shfl_xor(c, 32);
         if (g == 0) {
             const int u = (2 * wave + j) * 16 + r;
-            part[kOffB1 + u] = a;
-            part[kOffB2 + u] = b;
-            part[kOffW3 + u] = c;
+            part(kOffB1 + u) = a;
+            part(kOffB2 + u) = b;
+            part(kOffW3 + u) = c;
         }
     }
     // the output bias, loss and row-weight sums over the rows (wave 0)
@@ -343,13 +345,13 @@ __global__ __launch_bounds__(64 * kWaves) void k_mlp_grad(MlpDev P, const uint16
             wsum += __shfl_xor(wsum, o);
         }
         if (lane == 0) {
-            part[kOffB3] = db3;
-            part[kParams + 1] = lsum;
-            part[kParams] = wsum;
+            part(kOffB3) = db3;
+            part(kParams + 1) = lsum;
+            part(kParams) = wsum;
         }
     }
     if (threadIdx.x == 0)
-        part[kParams + 2] = __uint_as_float(*step + 1u);
+        part(kParams + 2) = __uint_as_float(*step + 1u);
 }
 
 // BF16 copies of parameter k from its master value.
@@ -374,7 +376,7 @@ __device__ __forceinline__ void publish(const MlpModelDev &M, int k, float v)
 // partials of workgroups q, q + 8, ... in order, then the 8 group sums are
 // added in order, so the result does not depend on scheduling.
 constexpr int kUpdGroups = 8;
-constexpr int kUpdMaxBlocks = 256;
+constexpr int kUpdMaxBlocks = kMaxTrainBlocks;
 
 __global__ __launch_bounds__(64 * kUpdGroups) void k_mlp_update(MlpModelDev M,
                                                                  const float *partials,
@@ -388,8 +390,8 @@ __global__ __launch_bounds__(64 * kUpdGroups) void k_mlp_update(MlpModelDev M,
     __shared__ float tot[2];
     const int tx = threadIdx.x & 63, q = threadIdx.x >> 6;
     if (threadIdx.x < blocks) {
-        hn[threadIdx.x] = partials[(int64_t)threadIdx.x * kPartStride + kParams];
-        hl[threadIdx.x] = partials[(int64_t)threadIdx.x * kPartStride + kParams + 1];
+        hn[threadIdx.x] = partials[part_index(threadIdx.x, kParams)];
+        hl[threadIdx.x] = partials[part_index(threadIdx.x, kParams + 1)];
     }
     const int k = blockIdx.x * 64 + tx;
     float s = 0.f;
@@ -398,7 +400,7 @@ __global__ __launch_bounds__(64 * kUpdGroups) void k_mlp_update(MlpModelDev M,
 #pragma unroll
         for (int r = 0; r < kUpdMaxBlocks / kUpdGroups; ++r) {
             const int b = q + kUpdGroups * r;
-            v[r] = b < blocks ? partials[(int64_t)b * kPartStride + k] : 0.f;
+            v[r] = b < blocks ? partials[part_index(b, k)] : 0.f;
         }
 #pragma unroll
         for (int r = 0; r < kUpdMaxBlocks / kUpdGroups; ++r)
@@ -406,14 +408,24 @@ __global__ __launch_bounds__(64 * kUpdGroups) void k_mlp_update(MlpModelDev M,
     }
     red[q][tx] = s;
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < 64) {  // row-weight and loss sums: lane l adds 4 l .. 4 l + 3, then a
+                             // butterfly (the same order in every workgroup)
         float n = 0.f, l = 0.f;
-        for (int b = 0; b < blocks; ++b) {
-            n += hn[b];
-            l += hl[b];
+#pragma unroll
+        for (int i = 0; i < kUpdMaxBlocks / 64; ++i) {
+            const int b = (int)threadIdx.x * (kUpdMaxBlocks / 64) + i;
+            n += b < blocks ? hn[b] : 0.f;
+            l += b < blocks ? hl[b] : 0.f;
         }
-        tot[0] = n;
-        tot[1] = l;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            n += __shfl_xor(n, o);
+            l += __shfl_xor(l, o);
+        }
+        if (threadIdx.x == 0) {
+            tot[0] = n;
+            tot[1] = l;
+        }
     }
     __syncthreads();
     const float n = tot[0];
@@ -423,7 +435,7 @@ __global__ __launch_bounds__(64 * kUpdGroups) void k_mlp_update(MlpModelDev M,
         if (loss_out)
             *loss_out = tot[1] / (2.f * n);
         if (lr > 0.f) {
-            *M.step = __float_as_uint(partials[kParams + 2]);
+            *M.step = __float_as_uint(partials[part_index(0, kParams + 2)]);
             if (gate.last)
                 *gate.last = *gate.gen;
         }
@@ -439,7 +451,7 @@ __global__ __launch_bounds__(64 * kUpdGroups) void k_mlp_update(MlpModelDev M,
         grad_out[k] = gk;
     if (!(lr > 0.f))
         return;
-    const float t = (float)__float_as_uint(partials[kParams + 2]);
+    const float t = (float)__float_as_uint(partials[part_index(0, kParams + 2)]);
     const float beta1 = 0.9f, beta2 = 0.999f, eps = 1e-8f;
     const float m = beta1 * M.m1[k] + (1.f - beta1) * gk;
     const float v = beta2 * M.m2[k] + (1.f - beta2) * gk * gk;
@@ -522,6 +534,8 @@ hipError_t launch_mlp_grad(const MlpDev &P, const uint16_t *X, const float *T,
     int nb = (int)grid_for(rows > 0 ? rows : 1, kChunk);
     if (nb > max_blocks)
         nb = max_blocks;
+    if (nb > kMaxTrainBlocks)
+        nb = kMaxTrainBlocks;
     *blocks = nb;
     hipLaunchKernelGGL(k_mlp_grad, dim3(nb), dim3(64 * kWaves), 0, s, P, X, T, Wt, rows,
                        partials, (const uint32_t *)M.step, gate);

@@ -33,6 +33,17 @@ static_assert(kParams == PMP_MLP_PARAMS, "parameter count");
 // Header words of one training block's partial sums (after kParams values).
 constexpr int kPartHead = 4;            // count, loss, step, unused
 constexpr int kPartStride = kParams + kPartHead + 3;  // 20872, 16-byte multiple
+// Partial vectors of at most kMaxTrainBlocks workgroups, stored by 64-value
+// chunks: chunk k / 64 of workgroup b at (k / 64 * kMaxTrainBlocks + b) * 64,
+// so a workgroup writes 64 consecutive values at a time and the update
+// reads one chunk of every workgroup as one contiguous block.
+constexpr int kMaxTrainBlocks = 256;
+constexpr int kPartChunks = (kPartStride + 63) / 64;
+constexpr size_t kPartFloats = (size_t)kPartChunks * kMaxTrainBlocks * 64;
+__device__ __forceinline__ int64_t part_index(int b, int k)
+{
+    return ((int64_t)(k >> 6) * kMaxTrainBlocks + b) * 64 + (k & 63);
+}
 
 // Round-to-nearest-even FP32 -> BF16 (finite inputs).
 __device__ __host__ __forceinline__ uint16_t f32_to_bf16(float x)
@@ -216,7 +227,8 @@ __device__ __forceinline__ void mlp_forward64(const MlpDev &P, const uint16_t *x
 hipError_t launch_mlp_forward(const MlpDev &P, const uint16_t *X, int rows, float *y,
                               hipStream_t s);
 // Partial gradient sums of L = sum_r w_r (y_r - t_r)^2 / (2 sum_r w_r) into
-// `partials` (blocks x kPartStride); returns the block count used.
+// `partials` (kPartFloats, by part_index; at most kMaxTrainBlocks blocks);
+// returns the block count used.
 hipError_t launch_mlp_grad(const MlpDev &P, const uint16_t *X, const float *T,
                            const float *Wt, int rows, float *partials, int max_blocks,
                            const MlpModelDev &M, TrainGate gate, int *blocks,

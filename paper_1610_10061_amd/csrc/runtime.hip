@@ -391,7 +391,7 @@ struct BatchHost {
 // A scoring network: device parameters, Adam state and staging buffers.
 struct pmp_model {
     MlpModelDev d{};
-    float *partials = nullptr;   // training partial sums, kTrainBlocks rows
+    float *partials = nullptr;   // training partial sums (kPartFloats, by part_index)
     float *grad = nullptr;       // staging of a host gradient output
     float *loss = nullptr;       // one float
     float *xf = nullptr;         // staging of host inputs (rows x 32)
@@ -401,7 +401,7 @@ struct pmp_model {
 };
 
 namespace {
-constexpr int kTrainBlocks = 256;  // workgroups of a training gradient launch
+constexpr int kTrainBlocks = kMaxTrainBlocks;  // workgroups of a training gradient launch
 }
 
 struct pmp_ga {
@@ -2732,7 +2732,7 @@ pmp_status pmp_model_create(uint64_t seed, pmp_model **out)
     if (dalloc(&d.master, kParams) || dalloc(&d.m1, kParams) || dalloc(&d.m2, kParams) ||
         dalloc(&d.W1, (size_t)kHidden * kIn) || dalloc(&d.W2, (size_t)kHidden * kHidden) ||
         dalloc(&d.W2T, (size_t)kHidden * kHidden) || dalloc(&d.w3, kHidden) ||
-        dalloc(&d.step, 1) || dalloc(&md->partials, (size_t)kTrainBlocks * kPartStride) ||
+        dalloc(&d.step, 1) || dalloc(&md->partials, kPartFloats) ||
         dalloc(&md->grad, kParams) || dalloc(&md->loss, 1)) {
         pmp_model_destroy(md);
         return fail(PMP_ENOMEM, "model buffers");
