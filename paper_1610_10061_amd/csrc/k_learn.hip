@@ -647,7 +647,7 @@ __global__ __launch_bounds__(256) void k_total(const unsigned long long *colsum,
 // one-pass walk's (the same integer terms, added in another order).
 // ---------------------------------------------------------------------------
 constexpr int kS12Waves = 16;
-constexpr int kS12Clients = 32;  // clients per workgroup
+constexpr int kS12Clients = 64;  // clients per workgroup
 constexpr int kMaxLearnWords = PMP_MAX_LEARNED_FACILITIES / 64;
 constexpr int kSlotWaves = 8;
 constexpr int kSlotRows = 4 * kSlotWaves;  // 16-lane rows per workgroup
@@ -665,8 +665,9 @@ __device__ __forceinline__ int lowest64(uint32_t lo, uint32_t hi)
 __global__ __launch_bounds__(64 * kS12Waves) void k_prop_s12(LearnArgs A, int out, int tiles_c)
 {
     // the rows staged at a padded stride (32-bit words), then in place the
-    // facility-major words T[64 w + lane] and T[64 W] = 0
-    __shared__ __align__(16) uint32_t sm[kEvalTile * (2 * kMaxLearnWords + 1)];
+    // facility-major words T[64 w + lane] and T[64 W] = 0: 64 (2W + 1) words
+    // of dynamic LDS (s12_lds_bytes)
+    extern __shared__ __align__(16) uint32_t sm[];
     // results by chromosome and client (padded rows), written out row by row
     __shared__ uint32_t o_s[kEvalTile][kS12Clients + 1];
     __shared__ int32_t o_c1[kEvalTile][kS12Clients + 1], o_c2[kEvalTile][kS12Clients + 1];
@@ -1136,7 +1137,8 @@ hipError_t launch_walk(const LearnArgs &a, int out, hipStream_t s)
     if (a.walk == 0) {  // the two-pass walk
         const int tiles_c = (a.g.P + kEvalTile - 1) / kEvalTile;
         const int tiles = tiles_c * ((a.g.t.n + kS12Clients - 1) / kS12Clients);
-        hipLaunchKernelGGL(k_prop_s12, dim3(((tiles + 7) / 8) * 8), dim3(64 * kS12Waves), 0, s,
+        const size_t lds = sizeof(uint32_t) * kEvalTile * (2 * (size_t)a.g.t.W + 1);
+        hipLaunchKernelGGL(k_prop_s12, dim3(((tiles + 7) / 8) * 8), dim3(64 * kS12Waves), lds, s,
                            a, out, tiles_c);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
