@@ -369,7 +369,7 @@ def test_trained_network_gains(pm):
 
 
 @pytest.mark.parametrize("case", ["euclid300", "rand_p3", "short_rows", "far_overflow",
-                                  "unstaged", "wide_m4000"])
+                                  "unstaged", "wide_m4000", "ragged_P96"])
 def test_two_pass_walk_equals_one_pass(pm, case):
     """The two-pass proposal walk (first two open positions per chromosome
     and client, then each candidate facility's index entries; positions past
@@ -379,8 +379,8 @@ def test_two_pass_walk_equals_one_pass(pm, case):
     rows shorter than the index (K < 64), more rows past the index than a
     chromosome's list holds (256: the rest walked by the wave that finds
     them), more clients than the per-chromosome LDS staging takes (4096:
-    client data read from device memory), and m = 4000 (the first pass's
-    widest mask staging)."""
+    client data read from device memory), m = 4000 (the first pass's widest
+    mask staging), and a population of 96 (a last chromosome tile of 32)."""
     if case == "euclid300":
         d, p = gi.euclid_instance(300, 7), 30
     elif case == "rand_p3":
@@ -391,9 +391,11 @@ def test_two_pass_walk_equals_one_pass(pm, case):
         d, p = np.random.default_rng(5).integers(1, 3000, size=(4200, 120)).astype(np.int32), 12
     elif case == "wide_m4000":  # 63 mask words: the widest staging of the first pass
         d, p = np.random.default_rng(6).integers(1, 5000, size=(300, 4000)).astype(np.int32), 40
+    elif case == "ragged_P96":  # a last chromosome tile of 32
+        d, p = gi.euclid_instance(210, 8), 20
     else:
         d, p = gi.euclid_instance(70, 2), 30
-    P, NT, G = 128, 32, 20
+    P, NT, G = (96 if case == "ragged_P96" else 128), 32, 20
     runs = []
     old = os.environ.get("PMP_WALK")
     try:
