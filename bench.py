@@ -908,8 +908,8 @@ def main():
                          "FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the path "
-              "would shard by population across GPUs, which this build does not run.",
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); runs on several "
+              "GPUs are not implemented (the path would shard by population).",
               file=sys.stderr)
         sys.exit(2)
     legs = [x for x in args.legs.split(",") if x and x != "none"]

@@ -46,7 +46,7 @@ typedef enum {
     PMP_ENOMEM = 2,       /* device or host allocation failed */
     PMP_EDEVICE = 3,      /* a HIP call failed; see pmp_last_error() */
     PMP_EINFEASIBLE = 4,  /* a chromosome without exactly p open facilities */
-    PMP_EUNSUPPORTED = 5  /* a size this build does not handle for that call */
+    PMP_EUNSUPPORTED = 5  /* a size or mode the library does not handle for that call */
 } pmp_status;
 
 #define PMP_ON_DEVICE 1u
