@@ -68,8 +68,12 @@ def test_null_handles_rejected():
     assert L.pmp_eval_population(None, None, 1, None, None, 0, None) == pm.PMP_EINVAL
     assert L.pmp_ga_step(None, 1, None) == pm.PMP_EINVAL
     assert L.pmp_instance_info(None, None, None, None, None, None) == pm.PMP_EINVAL
+    assert L.pmp_batch_step(None, 1, None) == pm.PMP_EINVAL
+    assert L.pmp_batch_autotune(None, None, None) == pm.PMP_EINVAL
+    assert L.pmp_batch_profile(None, 1) == pm.PMP_EINVAL
     L.pmp_instance_destroy(None)
     L.pmp_ga_destroy(None)
+    L.pmp_batch_destroy(None)
 
 
 def test_ga_params_rejected_before_allocation():
