@@ -492,9 +492,10 @@ struct pmp_ga {
     // the run is at (made ahead by the previous one's resolve launch)
     bool init_ahead = false;
     // the per-step schedule evaluates the whole mutation cycle at once (one
-    // evaluation of P x Y mutants instead of Y dependent ones); the batched
-    // and persistent schedules, and the learned proposal, run it attempt by
-    // attempt.  Both give the same results.
+    // evaluation of P x Y mutants instead of Y dependent ones; with the
+    // learned proposal the scored swaps are among them); the batched and
+    // persistent schedules run it attempt by attempt.  Both give the same
+    // results.
     bool spec() const
     {
         return spec_on && Y >= 2 && Y <= kMaxSpec;
