@@ -124,11 +124,16 @@ struct Arena {
         members.emplace_back(reinterpret_cast<void **>(p),
                              sizeof(T) * (count == 0 ? 1 : count));
     }
-    hipError_t carve()
+    size_t bytes() const
     {
         size_t total = 0;
         for (const auto &m : members)
             total += (m.second + 255) & ~size_t(255);
+        return total;
+    }
+    hipError_t carve()
+    {
+        const size_t total = bytes();
         hipError_t e = hipMalloc(&base, total);
         if (e != hipSuccess) {
             base = nullptr;
@@ -141,6 +146,8 @@ struct Arena {
         }
         return hipSuccess;
     }
+    // every member zeroed (one memset over the allocation)
+    hipError_t zero() const { return hipMemset(base, 0, bytes()); }
     void release()
     {
         for (const auto &m : members)
@@ -439,6 +446,19 @@ struct pmp_ga {
     uint32_t *bar = nullptr;
     unsigned long long *report = nullptr;  // GaReport layout, RP_MASK + W words
     Arena arena;  // the fixed-size buffers above (not part/spart, mut, mpart)
+    Arena parts;  // part, spart, part2, spart2 (sized by the client tiling)
+
+    // the client-tile partial sums for `tiles` tiles (both sets)
+    hipError_t carve_parts(int tiles)
+    {
+        parts.release();
+        const size_t cells = (size_t)tiles * prm.population;
+        parts.add(&part, cells);
+        parts.add(&spart, cells);
+        parts.add(&part2, cells);
+        parts.add(&spart2, cells);
+        return parts.carve();
+    }
     bool persistent = false;  // one persistent launch per pmp_ga_step call
     BatchHost *self = nullptr;  // this run as a batch of one
     // graph of `graph_gens` generations of the per-step launch sequence
@@ -1601,6 +1621,7 @@ void pmp_ga_destroy(pmp_ga *ga)
     if (!ga)
         return;
     ga->arena.release();  // (clears its members: the frees below skip them)
+    ga->parts.release();
     for (int k = 0; k < 2; ++k) {
         dfree(ga->cur[k]);
         dfree(ga->off[k]);
@@ -1614,10 +1635,6 @@ void pmp_ga_destroy(pmp_ga *ga)
     dfree(ga->mut_ok);
     dfree(ga->mpart);
     dfree(ga->mspart);
-    dfree(ga->part);
-    dfree(ga->spart);
-    dfree(ga->part2);
-    dfree(ga->spart2);
     dfree(ga->gmask);
     dfree(ga->best);
     dfree(ga->gcost);
@@ -1701,35 +1718,19 @@ pmp_status pmp_ga_create(pmp_instance *inst, const pmp_ga_params *prm,
     ga->arena.add(&ga->report, (size_t)RP_MASK + W);
     if (!binom.empty())
         ga->arena.add(&ga->binom, binom.size());
-    bool bad = ga->arena.carve() != hipSuccess;
-    bad = bad || dalloc(&ga->part, (size_t)std::max(ga->TI, ga->fTI) * P) ||
-          dalloc(&ga->spart, (size_t)std::max(ga->TI, ga->fTI) * P) ||
-          dalloc(&ga->part2, (size_t)std::max(ga->TI, ga->fTI) * P) ||
-          dalloc(&ga->spart2, (size_t)std::max(ga->TI, ga->fTI) * P);
+    const bool bad = ga->arena.carve() != hipSuccess ||
+                     ga->carve_parts(std::max(ga->TI, ga->fTI)) != hipSuccess;
     if (bad) {
         pmp_ga_destroy(ga);
         return fail(PMP_ENOMEM, "GA buffers for P=%d", P);
     }
+    // every buffer of the arena starts at zero (populations, fitness, bests,
+    // counters, barrier and arrival words), then the run state
+    hipError_t e = ga->arena.zero();
     unsigned long long init[GS_COUNT] = {0};
     init[GS_BEST] = (unsigned long long)INT64_MAX;
-    hipError_t e = hipMemcpy(ga->gs, init, sizeof init, hipMemcpyHostToDevice);
-    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
-        e = hipMemset(ga->cur[k], 0, sizeof(uint64_t) * PW);
-        if (e == hipSuccess)
-            e = hipMemset(ga->fit[k], 0, sizeof(unsigned long long) * P);
-    }
     if (e == hipSuccess)
-        e = hipMemset(ga->best, 0, sizeof(uint64_t) * W);
-    if (e == hipSuccess)
-        e = hipMemset(ga->gmask, 0, sizeof(uint64_t) * W * ga->NB);
-    if (e == hipSuccess)
-        e = hipMemset(ga->gcost, 0, sizeof(unsigned long long) * ga->NB);
-    if (e == hipSuccess)
-        e = hipMemset(ga->cstat, 0, sizeof(unsigned long long) * P * CS_COUNT);
-    if (e == hipSuccess)
-        e = hipMemset(ga->arrive, 0, sizeof(uint32_t));
-    if (e == hipSuccess)
-        e = hipMemset(ga->bar, 0, sizeof(uint32_t) * kBarrierWords);
+        e = hipMemcpy(ga->gs, init, sizeof init, hipMemcpyHostToDevice);
     if (e == hipSuccess && ga->binom)
         e = hipMemcpy(ga->binom, binom.data(), sizeof(unsigned long long) * binom.size(),
                       hipMemcpyHostToDevice);
@@ -2322,13 +2323,7 @@ pmp_status pmp_ga_autotune(pmp_ga *ga, int32_t *clients, int32_t *waves, void *s
     ga->spec_waves = best_w;
     if (best != ga->cpb) {
         const int ti = (n + best - 1) / best;
-        dfree(ga->part);
-        dfree(ga->spart);
-        dfree(ga->part2);
-        dfree(ga->spart2);
-        const size_t cells = (size_t)std::max(ti, ga->fTI) * P;
-        if (dalloc(&ga->part, cells) || dalloc(&ga->spart, cells) ||
-            dalloc(&ga->part2, cells) || dalloc(&ga->spart2, cells))
+        if (ga->carve_parts(std::max(ti, ga->fTI)) != hipSuccess)
             return fail(PMP_ENOMEM, "GA partial sums for %d client tiles", ti);
         ga->cpb = best;
         ga->TI = ti;
