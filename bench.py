@@ -229,8 +229,11 @@ def leg_batch(args, specs, ds):
 
     def run(batched, seed0, profile=False):
         t0 = time.perf_counter()
-        insts = [pm.Instance(d, s["p"], stream) for s, d in zip(specs, dd)]
+        # preprocessing back to back on the device, checked once it is done
+        insts = [pm.Instance(d, s["p"], stream, asynchronous=True) for s, d in zip(specs, dd)]
         gas = [pm.GA(i, 256, 256, G, seed0 + s["index"]) for i, s in zip(insts, specs)]
+        for i in insts:
+            i.check(stream)
         for g in gas:
             g.autotune(stream)
         common = None

@@ -84,12 +84,19 @@ typedef struct pmp_ga pmp_ga;
  *  d       n x m int32, row stride ld >= m elements; host pointer, or device
  *          pointer with PMP_ON_DEVICE.  Copied; not kept.
  *  n, m, p 1 <= n, 2 <= m <= PMP_MAX_EVAL_FACILITIES, 1 <= p <= m - 1.
+ *  flags   PMP_ON_DEVICE; with it, PMP_ASYNC (see below).
  *  out     receives a new instance handle (device tables, owned).
  * Errors: PMP_EINVAL for sizes (m above PMP_MAX_EVAL_FACILITIES included),
- * null pointers or any d_ij < 0 (the paper assumes non-negative distances).
+ * null pointers, PMP_ASYNC without PMP_ON_DEVICE, or any d_ij < 0 (the paper
+ * assumes non-negative distances).
  * Rows wider than PMP_MAX_FACILITIES are sorted in device memory (a scratch
  * of up to 256 MB of keys, freed before returning).
- * Always waits for its stream before returning (one-time step).
+ * Waits for its stream before returning, except with PMP_ASYNC: the tables
+ * are then made on `stream` after the call returns (d must stay valid until
+ * they are), negative distances are recorded in the instance's error word
+ * for pmp_instance_check, and the sum of d (a learned-proposal feature) is
+ * read back when first needed.  Many instances then preprocess back to
+ * back on the device.
  * ------------------------------------------------------------------------- */
 PMP_API pmp_status pmp_preprocess(const int32_t *d, int64_t ld, int32_t n, int32_t m,
                           int32_t p, uint32_t flags, void *stream,

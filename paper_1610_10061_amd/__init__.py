@@ -209,12 +209,16 @@ def _buf(x, dtype_np, dtype_t):
 
 
 # --------------------------------------------------------------- C names
-def pmp_preprocess(d, p: int, stream=None):
-    """Section 2.1 tables of d (n x m int32, numpy or CUDA tensor)."""
+def pmp_preprocess(d, p: int, stream=None, asynchronous=False):
+    """Section 2.1 tables of d (n x m int32, numpy or CUDA tensor);
+    asynchronous (CUDA tensors only): returns before the tables are made, its
+    errors reported by pmp_instance_check."""
     ptr, dev = _buf(d, np.int32, torch.int32)
     n, m = d.shape
     out = _vp()
     flags = PMP_ON_DEVICE if dev else 0
+    if asynchronous:
+        flags |= PMP_ASYNC
     _check(lib().pmp_preprocess(ptr, m, n, m, p, flags,
                                 _stream(stream) if dev else None, C.byref(out)),
            "pmp_preprocess")
@@ -598,8 +602,8 @@ def pmp_exhaustive(inst, stream=None):
 class Instance:
     """Owning wrapper of a pmp_instance handle."""
 
-    def __init__(self, d, p: int, stream=None):
-        self.handle = pmp_preprocess(d, p, stream)
+    def __init__(self, d, p: int, stream=None, asynchronous=False):
+        self.handle = pmp_preprocess(d, p, stream, asynchronous)
         self.n, self.m, self.p, self.K, self.W = pmp_instance_info(self.handle)
 
     def tables(self):

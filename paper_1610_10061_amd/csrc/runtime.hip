@@ -328,10 +328,28 @@ struct pmp_instance {
     // static sums of the learned proposal's features
     unsigned long long *colsum = nullptr;  // m column sums of d
     uint32_t *nearc = nullptr;             // m near counts
-    int64_t total = 0;                     // sum of d
+    mutable int64_t total = 0;             // sum of d
+    mutable bool total_pending = false;    // not read back yet (asynchronous preprocessing)
     int32_t near_len = 1;                  // ceil(m / p)
     unsigned long long *dtotal = nullptr;  // the sum and the error word, read back together
     Arena arena;                           // pi, ds, delta, err, colsum, nearc, dtotal
+
+    // the sum of d, read back on its first use after an asynchronous
+    // preprocessing (which may still be running on its stream)
+    hipError_t resolve_total() const
+    {
+        if (!total_pending)
+            return hipSuccess;
+        unsigned long long t = 0;
+        hipError_t e = hipDeviceSynchronize();
+        if (e == hipSuccess)
+            e = hipMemcpy(&t, dtotal, sizeof t, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) {
+            total = (int64_t)t;
+            total_pending = false;
+        }
+        return e;
+    }
 
     Tables tables() const
     {
@@ -927,6 +945,9 @@ pmp_status pmp_preprocess(const int32_t *d, int64_t ld, int32_t n, int32_t m,
         return fail(PMP_EINVAL, "row stride %lld < m", (long long)ld);
     hipStream_t s = (hipStream_t)stream;
     const bool on_dev = flags & PMP_ON_DEVICE;
+    const bool async = flags & PMP_ASYNC;
+    if (async && !on_dev)
+        return fail(PMP_EINVAL, "PMP_ASYNC needs device input (PMP_ON_DEVICE)");
     if (!on_dev) {
         for (int64_t i = 0; i < n; ++i)
             for (int64_t j = 0; j < m; ++j)
@@ -1006,6 +1027,10 @@ pmp_status pmp_preprocess(const int32_t *d, int64_t ld, int32_t n, int32_t m,
         if (e == hipSuccess)
             e = launch_static_sums(src, src_ld, n, m, inst->pi, inst->pitch, inst->near_len,
                                    inst->colsum, inst->nearc, inst->err, inst->dtotal, s);
+        if (e == hipSuccess && async) {  // the error word stays for pmp_instance_check
+            inst->total_pending = true;
+            break;
+        }
         std::vector<unsigned long long> rb;
         if (e == hipSuccess)
             e = staging().read(inst->dtotal, 2, s, rb);
@@ -2643,6 +2668,8 @@ pmp_status pmp_features(pmp_instance *inst, const uint64_t *masks, int32_t P,
         return PMP_OK;
     if (!masks || !out)
         return fail(PMP_EINVAL, "masks or out is NULL");
+    if (inst->resolve_total() != hipSuccess)
+        return fail(PMP_EDEVICE, "sum of d of the instance");
     hipStream_t s = (hipStream_t)stream;
     const bool on_dev = flags & PMP_ON_DEVICE;
     const size_t W = inst->W, cells = (size_t)P * inst->m * kFeatures;
@@ -2919,6 +2946,8 @@ pmp_status pmp_ga_set_model(pmp_ga *ga, pmp_model *model, const pmp_learn_params
         return fail(PMP_EUNSUPPORTED, "learned proposal in persistent-kernel mode");
     if (ga->inst->m > PMP_MAX_LEARNED_FACILITIES)
         return fail(PMP_EUNSUPPORTED, "m=%d above %d", ga->inst->m, PMP_MAX_LEARNED_FACILITIES);
+    if (ga->inst->resolve_total() != hipSuccess)  // (a feature's denominator)
+        return fail(PMP_EDEVICE, "sum of d of the instance");
     pmp_learn_params q{};
     if (lp)
         q = *lp;

@@ -52,6 +52,18 @@ def test_preprocess_rejects_bad_sizes(shape, p):
     assert e.value.status == pm.PMP_EINVAL
 
 
+def test_preprocess_async_needs_device_input():
+    """PMP_ASYNC leaves the work on a stream after the call returns, so a
+    host matrix (copied by the call) is refused before any device work."""
+    import ctypes as C
+    import paper_1610_10061_amd as pm
+    d = np.arange(12, dtype=np.int32).reshape(3, 4)
+    out = C.c_void_p()
+    st = pm.lib().pmp_preprocess(d.ctypes.data_as(C.c_void_p), 4, 3, 4, 2, pm.PMP_ASYNC, None,
+                                 C.byref(out))
+    assert st == pm.PMP_EINVAL and not out.value
+
+
 def test_preprocess_rejects_negative_distance_on_host():
     import paper_1610_10061_amd as pm
     d = np.ones((4, 6), np.int32)

@@ -314,6 +314,36 @@ def test_negative_distance_rejected_on_device(pm):
     with pytest.raises(pm.PmpError) as e:
         pm.Instance(torch.from_numpy(d).cuda(), 3)
     assert e.value.status == pm.PMP_EINVAL
+    # asynchronous preprocessing: the same error, from the instance check
+    inst = pm.Instance(torch.from_numpy(d).cuda(), 3, asynchronous=True)
+    with pytest.raises(pm.PmpError) as e:
+        inst.check()
+    assert e.value.status == pm.PMP_EINVAL
+
+
+@pytest.mark.parametrize("name", ["g100", "g900", "euclid_129", "wide_2x700", "ties_p1"])
+def test_asynchronous_preprocessing_same_tables(pm, name):
+    """Instances preprocessed back to back without waiting (PMP_ASYNC) hold
+    the oracle's tables and evaluate like synchronously made ones; the
+    learned features, which read the sum of d back on first use, agree."""
+    import torch
+    d, p = INSTANCES[name]()
+    dd = torch.from_numpy(d).cuda()
+    insts = [pm.Instance(dd, p, asynchronous=True) for _ in range(3)]
+    for inst in insts:
+        inst.check()
+    opi, ode, ods = oracle.tables(d, p)
+    masks = gi.random_population(70, d.shape[1], p, seed=4)
+    want = oracle.objective(d, masks, p)
+    for inst in insts:
+        pi, de, ds = inst.tables()
+        np.testing.assert_array_equal(pi.astype(np.int32), opi)
+        np.testing.assert_array_equal(de, ode)
+        np.testing.assert_array_equal(ds, ods)
+        np.testing.assert_array_equal(inst.eval(masks), want)
+    sync = pm.Instance(d, p)
+    np.testing.assert_array_equal(pm.pmp_features(insts[0].handle, masks[:5], 0.25),
+                                  pm.pmp_features(sync.handle, masks[:5], 0.25))
 
 
 SCHEME_CASES = [("example1", 6), ("g20", 200), ("g100", 64), ("g900", 257),
