@@ -384,8 +384,8 @@ PMP_API pmp_status pmp_ga_autotune(pmp_ga *ga, int32_t *clients, int32_t *waves,
  *                   evaluates each run's generation-0
  *                   population (made again by the first step, identically),
  *                   so every run must be before its first generation
- *                   (PMP_EINVAL otherwise).  Choices are cached per process by
- *                   the runs' shapes.  Results of the runs do not depend on
+ *                   (PMP_EINVAL otherwise, when the choice is timed).
+ *                   Choices are cached per process by the runs' shapes.  Results of the runs do not depend on
  *                   the tiling.  Synchronous on `stream`.  PMP_BATCH_CLIENTS
  *                   sets the common count without timing (also at
  *                   pmp_batch_create).

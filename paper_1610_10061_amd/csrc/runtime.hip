@@ -2413,12 +2413,6 @@ pmp_status pmp_batch_autotune(pmp_batch *bt, int32_t *clients, void *stream)
             *clients = bh.clients;
         return PMP_OK;
     }
-    for (size_t b = 0; b < bh.gas.size(); ++b) {
-        unsigned long long gen = 0;
-        HIP_TRY(hipMemcpy(&gen, bh.gas[b]->gs + GS_GEN, sizeof gen, hipMemcpyDeviceToHost));
-        if (gen != 0)
-            return fail(PMP_EINVAL, "autotune a batch before its first step (run %zu)", b);
-    }
     // measured choices are shared by batches of the same run shapes
     static std::mutex mu;
     static std::map<std::vector<int32_t>, int> cache;
@@ -2440,7 +2434,14 @@ pmp_status pmp_batch_autotune(pmp_batch *bt, int32_t *clients, void *stream)
             return PMP_OK;
         }
     }
-    // the probe's inputs: every run's generation-0 population (buffer 0)
+    // the probe's inputs: every run's generation-0 population (buffer 0),
+    // made again by the first step; a run past it would lose its population
+    for (size_t b = 0; b < bh.gas.size(); ++b) {
+        unsigned long long gen = 0;
+        HIP_TRY(hipMemcpy(&gen, bh.gas[b]->gs + GS_GEN, sizeof gen, hipMemcpyDeviceToHost));
+        if (gen != 0)
+            return fail(PMP_EINVAL, "autotune a batch before its first step (run %zu)", b);
+    }
     for (pmp_ga *ga : bh.gas)
         HIP_TRY(launch_ga_init(ga->args(), s));
     hipEvent_t e0 = nullptr, e1 = nullptr;

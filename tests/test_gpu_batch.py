@@ -217,7 +217,8 @@ def test_batch_client_tiling_keeps_results(pm, how):
     """The batch evaluation's client tiling (each run's own tuning, or a
     common count of clients per workgroup, timed by the batch autotuner or
     set by hand) changes no run: every batched run equals the run stepped
-    alone.  The autotuner refuses a batch past its first step."""
+    alone.  The autotuner applies a cached choice at any time and refuses to
+    time a batch past its first step."""
     keys = ("PMP_BATCH_CLIENTS", "PMP_BATCH_MODE")
     old = {k: os.environ.get(k) for k in keys}
     for k in keys:
@@ -244,9 +245,16 @@ def test_batch_client_tiling_keeps_results(pm, how):
         batch.step(3)
         batch.check()
         if how == "autotuned":
+            # a cached choice applies between steps; a choice to be timed
+            # needs runs before their first generation
+            assert batch.autotune() == clients
+            sub_insts, sub = _make(pm, cases[:3], G)
+            sb = pm.Batch(sub)
+            sb.step(1)
             with pytest.raises(pm.PmpError) as e:
-                batch.autotune()
+                sb.autotune()
             assert e.value.status == pm.PMP_EINVAL
+            sb.close()
         rinsts, refs = _make(pm, cases, G)
         for r in refs:
             r.step(G)
